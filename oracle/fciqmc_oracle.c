@@ -1,0 +1,1361 @@
+/*
+ * CPU oracle: a plain FCIQMC iteration written from Booth, Smart & Alavi,
+ * arXiv:1305.6981.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the benchmark's
+ * CPU-baseline leg. The product library neither links nor calls it, and the
+ * two share no source.
+ *
+ * What is followed, and where:
+ *   - walker dynamics: spawning, death/cloning, same-iteration isolation
+ *     (Sec. 2, Eqs. master, pspawn, pdeath);
+ *   - determinant representation and byte-table decoding (Sec. 3, 3.1);
+ *   - Algorithm 1 hash with a random orbital map, a main-list hash table with
+ *     chaining and a circular list of vacant slots (Sec. 4, 4.2);
+ *   - sorting and compression of the spawned list (Sec. 4.1, footnote on
+ *     sorting), annihilation and the initiator test at that stage (Sec. 4.2);
+ *   - excitation generation with renormalisation over electrons/orbitals that
+ *     have no allowed partner, and the generation probabilities of Eq. p_sing
+ *     and of the double-excitation formula (Sec. 5, 5.1, 5.2);
+ *   - Slater-Condon matrix elements ("standard rules", Sec. 2);
+ *   - projected energy (Eq. ProjE) and the shift (Sec. 2);
+ *   - blocking analysis of the correlated ratio (Sec. 7, Flyvbjerg-Petersen).
+ *
+ * Readings where the paper is silent (each listed in the design notes):
+ *   RNG = Philox4x32-10 (Salmon et al., SC'11) keyed by the seed, with a
+ *   counter built from (determinant, walker ordinal, iteration, block);
+ *   the a/b orbitals are picked by enumerating the allowed set (the paper's
+ *   stated alternative to drawing with rejection; same pgen); initiator =
+ *   |C| > n_a or the reference; the merged spawn flag is the OR of parents'
+ *   flags; occupancy for the initiator test is judged after death; the shift
+ *   is S <- S - zeta/(A tau) ln(N_w/N_prev), tested every A iterations; death
+ *   is one stochastic rounding per determinant.
+ *
+ * Built with -ffp-contract=off: every floating-point decision uses the
+ * operation order written here.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+static char g_err[512];
+
+static int fail(const char *msg)
+{
+    snprintf(g_err, sizeof g_err, "%s", msg);
+    return -1;
+}
+
+const char *orc_last_error(void) { return g_err; }
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).                       */
+/* Each round: two 32x32->64 products of counter words 0 and 2 with the      */
+/* round multipliers; the new counter is (hi1^c1^k0, lo1, hi0^c3^k1, lo0).   */
+/* The two key words are bumped by the Weyl constants between rounds.        */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Random-number contract (a reading: the paper uses a Mersenne Twister).
+ * key = (lo32(seed), hi32(seed)); counter = (lo32(D), hi32(D), k, ((n mod 2^24) << 8) | block).
+ * Spawn attempt k on D at iteration n:
+ *   block 0 -> x0 (excitation type), x1 (electron or electron pair)
+ *   block 1 -> x2 (orbital a), x3 (orbital b)
+ *   block 2 -> x4 (acceptance)
+ * Death on D: k = 0xFFFFFFFF, block 0x80 -> x0.
+ * A 64-bit draw is (w[2j+1] << 32) | w[2j]. */
+static void draw_block(uint64_t seed, uint64_t det, uint32_t k, int64_t iter, uint32_t block,
+                       uint64_t x[2])
+{
+    uint32_t ctr[4], key[2], w[4];
+    ctr[0] = (uint32_t)det;
+    ctr[1] = (uint32_t)(det >> 32);
+    ctr[2] = k;
+    ctr[3] = ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block;
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    orc_philox4x32_10(ctr, key, w);
+    x[0] = ((uint64_t)w[1] << 32) | (uint64_t)w[0];
+    x[1] = ((uint64_t)w[3] << 32) | (uint64_t)w[2];
+}
+
+/* Uniform double in [0, 1) from the top 53 bits. */
+static double unit_uniform(uint64_t x)
+{
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Natural logarithm used by the shift update. Method: write x = m 2^e with
+ * m in (1/sqrt2, sqrt2], then ln x = e ln2 + 2 atanh(z), z = (m-1)/(m+1),
+ * with the odd series of atanh summed by Horner's rule up to z^25
+ * (|z| <= 0.1716, so the first omitted term is below 1e-20). The operation
+ * order is fixed so that the same method gives the same bits on any IEEE
+ * double machine without fused multiply-adds. */
+double orc_log(double x)
+{
+    uint64_t bits;
+    memcpy(&bits, &x, sizeof bits);
+    int e = (int)((bits >> 52) & 0x7FFu) - 1023;
+    uint64_t mb = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+    double m;
+    memcpy(&m, &mb, sizeof m);
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double z = (m - 1.0) / (m + 1.0);
+    double z2 = z * z;
+    double sum = 1.0 / 27.0;
+    for (int k = 25; k >= 1; k -= 2)
+        sum = sum * z2 + 1.0 / (double)k;
+    return (double)e * 0.6931471805599453 + 2.0 * z * sum;
+}
+
+/* Uniform index in [0, n): floor(x * n / 2^64). */
+static uint64_t uniform_index(uint64_t x, uint64_t n)
+{
+    return (uint64_t)(((unsigned __int128)x * (unsigned __int128)n) >> 64);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Decoding through a 256-entry byte table (Sec. 3.1): each entry holds the  */
+/* number of set bits of the byte and their positions.                      */
+/* ------------------------------------------------------------------------ */
+static int g_lut_ready;
+static uint8_t g_lut_count[256];
+static uint8_t g_lut_orb[256][8];
+
+static void build_lut(void)
+{
+    if (g_lut_ready)
+        return;
+    for (int v = 0; v < 256; v++) {
+        int c = 0;
+        for (int b = 0; b < 8; b++)
+            if (v & (1 << b))
+                g_lut_orb[v][c++] = (uint8_t)b;
+        g_lut_count[v] = (uint8_t)c;
+    }
+    g_lut_ready = 1;
+}
+
+int orc_decode(uint64_t det, int32_t *occ)
+{
+    build_lut();
+    int n = 0;
+    for (int byte = 0; byte < 8; byte++) {
+        unsigned v = (unsigned)((det >> (8 * byte)) & 0xFFu);
+        if (!v)
+            continue;
+        for (int j = 0; j < g_lut_count[v]; j++)
+            occ[n++] = 8 * byte + g_lut_orb[v][j];
+    }
+    return n;
+}
+
+static int popcount64(uint64_t x)
+{
+    int c = 0;
+    while (x) {
+        x &= x - 1;
+        c++;
+    }
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hamiltonian.                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int M, N, n_alpha, n_beta, n_so;
+    double e_core;
+    double *h1, *eri;
+    int irrep[32];
+    int n_class;
+    int class_of[64];
+    double p_double, p_single;
+    uint64_t d0;
+    double e0;
+} sys_t;
+
+static int64_t pair_index(int i, int j)
+{
+    if (i < j) {
+        int t = i;
+        i = j;
+        j = t;
+    }
+    return (int64_t)i * (i + 1) / 2 + j;
+}
+
+static double eri_spatial(const sys_t *s, int i, int j, int k, int l)
+{
+    int64_t a = pair_index(i, j), b = pair_index(k, l);
+    if (a < b) {
+        int64_t t = a;
+        a = b;
+        b = t;
+    }
+    return s->eri[a * (a + 1) / 2 + b];
+}
+
+/* (pq|rs) over spin orbitals: zero unless p,q share a spin and r,s share a spin. */
+static double eri_so(const sys_t *s, int p, int q, int r, int t)
+{
+    if ((p & 1) != (q & 1) || (r & 1) != (t & 1))
+        return 0.0;
+    return eri_spatial(s, p >> 1, q >> 1, r >> 1, t >> 1);
+}
+
+static double h_so(const sys_t *s, int p, int q)
+{
+    if ((p & 1) != (q & 1))
+        return 0.0;
+    return s->h1[(p >> 1) * s->M + (q >> 1)];
+}
+
+/* Number of occupied orbitals strictly between p and a. */
+static int n_between(uint64_t det, int p, int a)
+{
+    int lo = p < a ? p : a, hi = p < a ? a : p;
+    int c = 0;
+    for (int r = lo + 1; r < hi; r++)
+        if ((det >> r) & 1u)
+            c++;
+    return c;
+}
+
+/* Diagonal element: E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)]. */
+static double hdiag_of(const sys_t *s, uint64_t det)
+{
+    int32_t occ[64];
+    int n = orc_decode(det, occ);
+    double acc = s->e_core;
+    for (int i = 0; i < n; i++)
+        acc = acc + h_so(s, occ[i], occ[i]);
+    for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++)
+            acc = acc + (eri_so(s, occ[i], occ[i], occ[j], occ[j]) -
+                         eri_so(s, occ[i], occ[j], occ[j], occ[i]));
+    return acc;
+}
+
+/* Single excitation p -> a from det: sign * (h_pa + sum_{q occ, q != p} [(pa|qq) - (pq|qa)]). */
+static double hel_single(const sys_t *s, uint64_t det, int p, int a)
+{
+    int32_t occ[64];
+    int n = orc_decode(det, occ);
+    double acc = h_so(s, p, a);
+    for (int i = 0; i < n; i++) {
+        int q = occ[i];
+        if (q == p)
+            continue;
+        acc = acc + (eri_so(s, p, a, q, q) - eri_so(s, p, q, q, a));
+    }
+    if (n_between(det, p, a) & 1)
+        acc = -acc;
+    return acc;
+}
+
+/* Double excitation p,q -> a,b (p<q occupied; a,b empty).
+ * Pairing: for unlike spins a' carries the spin of p; for like spins a' = min(a, b).
+ * Sign: parity of q -> b' on det, times parity of p -> a' on the result. */
+static double hel_double(const sys_t *s, uint64_t det, int p, int q, int a, int b)
+{
+    int ap, bp;
+    if ((p & 1) != (q & 1)) {
+        if ((a & 1) == (p & 1)) {
+            ap = a;
+            bp = b;
+        } else {
+            ap = b;
+            bp = a;
+        }
+    } else {
+        ap = a < b ? a : b;
+        bp = a < b ? b : a;
+    }
+    int nsw = n_between(det, q, bp);
+    uint64_t d1 = (det & ~(1ull << q)) | (1ull << bp);
+    nsw += n_between(d1, p, ap);
+    double v = eri_so(s, p, ap, q, bp) - eri_so(s, p, bp, q, ap);
+    return (nsw & 1) ? -v : v;
+}
+
+/* <bra|H|ket>, ket taken as the source of the excitation. */
+static double hel_general(const sys_t *s, uint64_t bra, uint64_t ket)
+{
+    if (popcount64(bra) != popcount64(ket))
+        return 0.0;
+    uint64_t diff = bra ^ ket;
+    int nd = popcount64(diff);
+    if (nd == 0)
+        return hdiag_of(s, ket);
+    int from[2], to[2], nf = 0, nt = 0;
+    if (nd > 4)
+        return 0.0;
+    for (int r = 0; r < s->n_so; r++) {
+        if (!((diff >> r) & 1u))
+            continue;
+        if ((ket >> r) & 1u)
+            from[nf++] = r;
+        else
+            to[nt++] = r;
+    }
+    if (nd == 2)
+        return hel_single(s, ket, from[0], to[0]);
+    return hel_double(s, ket, from[0], from[1], to[0], to[1]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Excitation generation (Sec. 5).                                           */
+/* Symmetry classes: (irrep, spin); class id = 2*irrep + spin.               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t det;
+    int n;
+    int32_t occ[64];
+    int n_unocc[16];
+} detinfo_t;
+
+static void det_setup(const sys_t *s, uint64_t det, detinfo_t *di)
+{
+    di->det = det;
+    di->n = orc_decode(det, di->occ);
+    for (int c = 0; c < 16; c++)
+        di->n_unocc[c] = 0;
+    for (int r = 0; r < s->n_so; r++)
+        if (!((det >> r) & 1u))
+            di->n_unocc[s->class_of[r]]++;
+}
+
+static int class_id(int irrep, int spin) { return 2 * irrep + spin; }
+
+/* Number of empty orbitals that can pair with x as the second orbital of a
+ * double excitation from the pair (p, q) (Eq. sym1 plus spin), excluding x. */
+static int n_partner(const sys_t *s, const detinfo_t *di, int p, int q, int x)
+{
+    int spin_b = ((p & 1) == (q & 1)) ? (p & 1) : 1 - (x & 1);
+    int irrep_b = s->irrep[p >> 1] ^ s->irrep[q >> 1] ^ s->irrep[x >> 1];
+    int cb = class_id(irrep_b, spin_b);
+    int n = di->n_unocc[cb];
+    if (cb == s->class_of[x])
+        n -= 1;
+    return n;
+}
+
+static int partner_ok(const sys_t *s, int p, int q, int x, int y)
+{
+    int spin_b = ((p & 1) == (q & 1)) ? (p & 1) : 1 - (x & 1);
+    int irrep_b = s->irrep[p >> 1] ^ s->irrep[q >> 1] ^ s->irrep[x >> 1];
+    return s->class_of[y] == class_id(irrep_b, spin_b) && y != x;
+}
+
+typedef struct {
+    uint64_t det;   /* 0 = null excitation */
+    double pgen;
+    double hel;
+} excit_t;
+
+/* One excitation from the three choice draws x[1..3] and the type draw x[0]. */
+static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], excit_t *out)
+{
+    const int N = di->n;
+    const uint64_t det = di->det;
+    out->det = 0;
+    out->pgen = 0.0;
+    out->hel = 0.0;
+    int is_double = unit_uniform(x[0]) < s->p_double;
+    if (!is_double) {
+        /* Sec. 5.1: renormalise over the electrons that have an allowed a. */
+        int n_allow[64], delta_s = 0;
+        for (int e = 0; e < N; e++) {
+            n_allow[e] = di->n_unocc[s->class_of[di->occ[e]]];
+            if (n_allow[e] == 0)
+                delta_s++;
+        }
+        if (N - delta_s == 0)
+            return;
+        uint64_t ke = uniform_index(x[1], (uint64_t)(N - delta_s));
+        int esel = -1;
+        for (int e = 0; e < N; e++) {
+            if (n_allow[e] == 0)
+                continue;
+            if (ke == 0) {
+                esel = e;
+                break;
+            }
+            ke--;
+        }
+        int p = di->occ[esel];
+        int cls = s->class_of[p];
+        uint64_t ka = uniform_index(x[2], (uint64_t)n_allow[esel]);
+        int a = -1;
+        for (int r = 0; r < s->n_so; r++) {
+            if (((det >> r) & 1u) || s->class_of[r] != cls)
+                continue;
+            if (ka == 0) {
+                a = r;
+                break;
+            }
+            ka--;
+        }
+        out->det = det ^ (1ull << p) ^ (1ull << a);
+        out->pgen = s->p_single / (double)((int64_t)n_allow[esel] * (int64_t)(N - delta_s));
+        out->hel = hel_single(s, det, p, a);
+        return;
+    }
+    /* Sec. 5.2: a unique pair by inverse triangular indexing. */
+    if (N < 2)
+        return;
+    int64_t n_pairs = (int64_t)N * (N - 1) / 2;
+    int64_t K = (int64_t)uniform_index(x[1], (uint64_t)n_pairs);
+    int j = 1;
+    while ((int64_t)(j + 1) * j / 2 <= K)
+        j++;
+    int i = (int)(K - (int64_t)j * (j - 1) / 2);
+    int p = di->occ[i], q = di->occ[j];
+    int same = (p & 1) == (q & 1);
+    /* Count the allowed a orbitals and those with no partner b (delta_d). */
+    int n_a_set = 0, delta_d = 0;
+    for (int r = 0; r < s->n_so; r++) {
+        if ((det >> r) & 1u)
+            continue;
+        if (same && (r & 1) != (p & 1))
+            continue;
+        n_a_set++;
+        if (n_partner(s, di, p, q, r) == 0)
+            delta_d++;
+    }
+    if (n_a_set - delta_d == 0)
+        return;
+    uint64_t ka = uniform_index(x[2], (uint64_t)(n_a_set - delta_d));
+    int a = -1;
+    for (int r = 0; r < s->n_so; r++) {
+        if ((det >> r) & 1u)
+            continue;
+        if (same && (r & 1) != (p & 1))
+            continue;
+        if (n_partner(s, di, p, q, r) == 0)
+            continue;
+        if (ka == 0) {
+            a = r;
+            break;
+        }
+        ka--;
+    }
+    int nba = n_partner(s, di, p, q, a);
+    uint64_t kb = uniform_index(x[3], (uint64_t)nba);
+    int b = -1;
+    for (int r = 0; r < s->n_so; r++) {
+        if ((det >> r) & 1u)
+            continue;
+        if (!partner_ok(s, p, q, a, r))
+            continue;
+        if (kb == 0) {
+            b = r;
+            break;
+        }
+        kb--;
+    }
+    int nbb = n_partner(s, di, p, q, b);
+    out->det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
+    out->pgen = (2.0 * s->p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
+                (double)((int64_t)N * (N - 1) * (int64_t)(n_a_set - delta_d));
+    out->hel = hel_double(s, det, p, q, a, b);
+}
+
+/* Counts of symmetry-allowed single and double excitations from a determinant,
+ * by enumeration (used to fix P_double from the reference, Sec. 5). */
+static void count_excitations(const sys_t *s, uint64_t det, int64_t *n_single, int64_t *n_double)
+{
+    int32_t occ[64];
+    int n = orc_decode(det, occ);
+    int64_t ns = 0, nd = 0;
+    for (int e = 0; e < n; e++)
+        for (int r = 0; r < s->n_so; r++)
+            if (!((det >> r) & 1u) && s->class_of[r] == s->class_of[occ[e]])
+                ns++;
+    for (int i = 0; i < n; i++)
+        for (int j = i + 1; j < n; j++) {
+            int p = occ[i], q = occ[j];
+            int sym = s->irrep[p >> 1] ^ s->irrep[q >> 1];
+            for (int a = 0; a < s->n_so; a++) {
+                if ((det >> a) & 1u)
+                    continue;
+                for (int b = a + 1; b < s->n_so; b++) {
+                    if ((det >> b) & 1u)
+                        continue;
+                    if ((a & 1) + (b & 1) != (p & 1) + (q & 1))
+                        continue;
+                    if ((s->irrep[a >> 1] ^ s->irrep[b >> 1]) != sym)
+                        continue;
+                    nd++;
+                }
+            }
+        }
+    *n_single = ns;
+    *n_double = nd;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Main walker list: hash table with chaining + circular list of vacancies   */
+/* (Sec. 4.2), hashed with Algorithm 1.                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t cap, high;        /* storage size; one past the highest slot ever used */
+    uint64_t *det;            /* 0 = vacant */
+    int32_t *pop;
+    double *hdiag;
+    int64_t *next;            /* chain link */
+    int64_t *head;            /* hash table: first slot of each chain, -1 if none */
+    int64_t range;            /* hash-table size */
+    int64_t *ring;            /* circular list of vacant slots */
+    int64_t ring_head, ring_count;
+    int64_t n_entries;
+    int64_t map[64];          /* Algorithm 1 random orbital map */
+} mainlist_t;
+
+static int64_t hash_alg1(const int64_t *map, const int32_t *occ, int n, int64_t range)
+{
+    uint64_t h = 0;
+    for (int i = 1; i <= n; i++)
+        h = 1099511628211ull * h + (uint64_t)map[occ[i - 1]] * (uint64_t)i;
+    int64_t r = (int64_t)h % range;
+    return r < 0 ? -r : r;
+}
+
+static int64_t ml_hash(const mainlist_t *ml, uint64_t det)
+{
+    int32_t occ[64];
+    int n = orc_decode(det, occ);
+    return hash_alg1(ml->map, occ, n, ml->range);
+}
+
+static uint64_t splitmix64(uint64_t *state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static int ml_init(mainlist_t *ml, int64_t cap, int64_t range, uint64_t hash_seed)
+{
+    memset(ml, 0, sizeof *ml);
+    ml->cap = cap;
+    ml->range = range;
+    ml->det = calloc((size_t)cap, sizeof(uint64_t));
+    ml->pop = calloc((size_t)cap, sizeof(int32_t));
+    ml->hdiag = calloc((size_t)cap, sizeof(double));
+    ml->next = malloc((size_t)cap * sizeof(int64_t));
+    ml->ring = malloc((size_t)cap * sizeof(int64_t));
+    ml->head = malloc((size_t)range * sizeof(int64_t));
+    if (!ml->det || !ml->pop || !ml->hdiag || !ml->next || !ml->ring || !ml->head)
+        return fail("oracle: out of host memory");
+    for (int64_t i = 0; i < range; i++)
+        ml->head[i] = -1;
+    /* A 1-to-1 map from spin orbitals to distinct random integers. */
+    uint64_t st = hash_seed;
+    for (int r = 0; r < 64; r++) {
+        for (;;) {
+            int64_t v = (int64_t)(splitmix64(&st) >> 2);
+            int dup = 0;
+            for (int t = 0; t < r; t++)
+                if (ml->map[t] == v)
+                    dup = 1;
+            if (!dup && v != 0) {
+                ml->map[r] = v;
+                break;
+            }
+        }
+    }
+    return 0;
+}
+
+static void ml_free(mainlist_t *ml)
+{
+    free(ml->det);
+    free(ml->pop);
+    free(ml->hdiag);
+    free(ml->next);
+    free(ml->ring);
+    free(ml->head);
+    memset(ml, 0, sizeof *ml);
+}
+
+static int64_t ml_find(const mainlist_t *ml, uint64_t det)
+{
+    int64_t h = ml_hash(ml, det);
+    for (int64_t i = ml->head[h]; i >= 0; i = ml->next[i])
+        if (ml->det[i] == det)
+            return i;
+    return -1;
+}
+
+static void ml_link(mainlist_t *ml, int64_t slot)
+{
+    int64_t h = ml_hash(ml, ml->det[slot]);
+    ml->next[slot] = ml->head[h];
+    ml->head[h] = slot;
+}
+
+static int ml_rehash(mainlist_t *ml, int64_t new_range)
+{
+    int64_t *nh = malloc((size_t)new_range * sizeof(int64_t));
+    if (!nh)
+        return fail("oracle: out of host memory");
+    free(ml->head);
+    ml->head = nh;
+    ml->range = new_range;
+    for (int64_t i = 0; i < new_range; i++)
+        nh[i] = -1;
+    for (int64_t i = 0; i < ml->high; i++)
+        if (ml->det[i])
+            ml_link(ml, i);
+    return 0;
+}
+
+static int ml_grow(mainlist_t *ml)
+{
+    int64_t nc = ml->cap * 2;
+    uint64_t *d = realloc(ml->det, (size_t)nc * sizeof(uint64_t));
+    if (!d)
+        return fail("oracle: out of host memory");
+    ml->det = d;
+    int32_t *p = realloc(ml->pop, (size_t)nc * sizeof(int32_t));
+    if (!p)
+        return fail("oracle: out of host memory");
+    ml->pop = p;
+    double *h = realloc(ml->hdiag, (size_t)nc * sizeof(double));
+    if (!h)
+        return fail("oracle: out of host memory");
+    ml->hdiag = h;
+    int64_t *n = realloc(ml->next, (size_t)nc * sizeof(int64_t));
+    if (!n)
+        return fail("oracle: out of host memory");
+    ml->next = n;
+    /* The ring is rebuilt in the larger buffer, keeping its order. */
+    int64_t *r = malloc((size_t)nc * sizeof(int64_t));
+    if (!r)
+        return fail("oracle: out of host memory");
+    for (int64_t i = 0; i < ml->ring_count; i++)
+        r[i] = ml->ring[(ml->ring_head + i) % ml->cap];
+    free(ml->ring);
+    ml->ring = r;
+    ml->ring_head = 0;
+    for (int64_t i = ml->cap; i < nc; i++) {
+        ml->det[i] = 0;
+        ml->pop[i] = 0;
+        ml->hdiag[i] = 0.0;
+    }
+    ml->cap = nc;
+    return 0;
+}
+
+/* Insert into the earliest vacancy recorded in the circular list, else past the end. */
+static int64_t ml_insert(mainlist_t *ml, uint64_t det, int32_t pop, double hd)
+{
+    int64_t slot;
+    if (ml->ring_count > 0) {
+        slot = ml->ring[ml->ring_head];
+        ml->ring_head = (ml->ring_head + 1) % ml->cap;
+        ml->ring_count--;
+    } else {
+        if (ml->high == ml->cap && ml_grow(ml) != 0)
+            return -1;
+        slot = ml->high++;
+    }
+    ml->det[slot] = det;
+    ml->pop[slot] = pop;
+    ml->hdiag[slot] = hd;
+    ml_link(ml, slot);
+    ml->n_entries++;
+    if (ml->n_entries > 2 * ml->range && ml_rehash(ml, ml->range * 2) != 0)
+        return -1;
+    return slot;
+}
+
+static void ml_remove(mainlist_t *ml, int64_t slot)
+{
+    int64_t h = ml_hash(ml, ml->det[slot]);
+    int64_t *link = &ml->head[h];
+    while (*link != slot)
+        link = &ml->next[*link];
+    *link = ml->next[slot];
+    ml->det[slot] = 0;
+    ml->pop[slot] = 0;
+    ml->ring[(ml->ring_head + ml->ring_count) % ml->cap] = slot;
+    ml->ring_count++;
+    ml->n_entries--;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole state.                                                              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t det;
+    int64_t pop;
+    uint32_t flag;
+} spawn_t;
+
+struct orc_state {
+    sys_t sys;
+    orc_params prm;
+    mainlist_t ml;
+    spawn_t *spawn;
+    int64_t n_spawn, cap_spawn;
+    /* dynamics */
+    int64_t iter;
+    double shift;
+    int varying;
+    int64_t n_prev, n_var;
+    /* last iteration's statistics */
+    int64_t nw, nd, c0, attempts, spawns, merged, aborted, tot_attempts, tot_spawns;
+    double num;
+    /* series for the averages */
+    double *s_num, *s_den, *s_shift;
+    int64_t n_series, cap_series;
+};
+
+static int cmp_spawn(const void *a, const void *b)
+{
+    uint64_t x = ((const spawn_t *)a)->det, y = ((const spawn_t *)b)->det;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int push_spawn(orc_state *st, uint64_t det, int64_t pop, uint32_t flag)
+{
+    if (st->n_spawn == st->cap_spawn) {
+        int64_t nc = st->cap_spawn ? st->cap_spawn * 2 : 1024;
+        spawn_t *p = realloc(st->spawn, (size_t)nc * sizeof(spawn_t));
+        if (!p)
+            return fail("oracle: out of host memory");
+        st->spawn = p;
+        st->cap_spawn = nc;
+    }
+    st->spawn[st->n_spawn].det = det;
+    st->spawn[st->n_spawn].pop = pop;
+    st->spawn[st->n_spawn].flag = flag;
+    st->n_spawn++;
+    return 0;
+}
+
+static int push_series(orc_state *st, double num, double den, double shift)
+{
+    if (st->n_series == st->cap_series) {
+        int64_t nc = st->cap_series ? st->cap_series * 2 : 1024;
+        double *a = realloc(st->s_num, (size_t)nc * sizeof(double));
+        double *b = a ? realloc(st->s_den, (size_t)nc * sizeof(double)) : NULL;
+        double *c = b ? realloc(st->s_shift, (size_t)nc * sizeof(double)) : NULL;
+        if (a)
+            st->s_num = a;
+        if (b)
+            st->s_den = b;
+        if (c)
+            st->s_shift = c;
+        if (!a || !b || !c)
+            return fail("oracle: out of host memory");
+        st->cap_series = nc;
+    }
+    st->s_num[st->n_series] = num;
+    st->s_den[st->n_series] = den;
+    st->s_shift[st->n_series] = shift;
+    st->n_series++;
+    return 0;
+}
+
+static int sys_init(sys_t *s, const orc_ham *h)
+{
+    memset(s, 0, sizeof *s);
+    if (h->n_orb <= 0 || 2 * h->n_orb > 64)
+        return fail("oracle: need 1 <= n_orb <= 32");
+    if (h->n_alpha < 0 || h->n_beta < 0 || h->n_alpha > h->n_orb || h->n_beta > h->n_orb ||
+        h->n_alpha + h->n_beta == 0)
+        return fail("oracle: bad electron counts");
+    if (!h->h1 || !h->eri)
+        return fail("oracle: missing integrals");
+    s->M = h->n_orb;
+    s->n_alpha = h->n_alpha;
+    s->n_beta = h->n_beta;
+    s->N = h->n_alpha + h->n_beta;
+    s->n_so = 2 * h->n_orb;
+    s->e_core = h->e_core;
+    int64_t np = (int64_t)s->M * (s->M + 1) / 2;
+    int64_t ne = np * (np + 1) / 2;
+    s->h1 = malloc((size_t)s->M * s->M * sizeof(double));
+    s->eri = malloc((size_t)ne * sizeof(double));
+    if (!s->h1 || !s->eri)
+        return fail("oracle: out of host memory");
+    memcpy(s->h1, h->h1, (size_t)s->M * s->M * sizeof(double));
+    memcpy(s->eri, h->eri, (size_t)ne * sizeof(double));
+    int max_irrep = 0;
+    for (int r = 0; r < s->M; r++) {
+        s->irrep[r] = h->orb_irrep ? h->orb_irrep[r] : 0;
+        if (s->irrep[r] > 7)
+            return fail("oracle: irrep labels must be 0..7");
+        if (s->irrep[r] > max_irrep)
+            max_irrep = s->irrep[r];
+    }
+    s->n_class = 2 * (max_irrep + 1);
+    for (int r = 0; r < s->n_so; r++)
+        s->class_of[r] = class_id(s->irrep[r >> 1], r & 1);
+    /* Reference determinant. */
+    if (h->ref_det) {
+        s->d0 = *h->ref_det;
+        uint64_t a = 0, b = 0;
+        for (int r = 0; r < s->n_so; r++)
+            if ((s->d0 >> r) & 1u) {
+                if (r & 1)
+                    b++;
+                else
+                    a++;
+            }
+        if ((s->n_so < 64 && (s->d0 >> s->n_so) != 0) || (int)a != s->n_alpha ||
+            (int)b != s->n_beta)
+            return fail("oracle: reference determinant does not match the electron counts");
+    } else {
+        int order[32];
+        for (int r = 0; r < s->M; r++)
+            order[r] = r;
+        for (int r = 1; r < s->M; r++) {          /* insertion sort by (h_pp, index) */
+            int v = order[r], t = r;
+            while (t > 0 && s->h1[order[t - 1] * s->M + order[t - 1]] > s->h1[v * s->M + v]) {
+                order[t] = order[t - 1];
+                t--;
+            }
+            order[t] = v;
+        }
+        s->d0 = 0;
+        for (int r = 0; r < s->n_alpha; r++)
+            s->d0 |= 1ull << (2 * order[r]);
+        for (int r = 0; r < s->n_beta; r++)
+            s->d0 |= 1ull << (2 * order[r] + 1);
+    }
+    s->e0 = hdiag_of(s, s->d0);
+    if (h->p_double >= 0.0) {
+        if (h->p_double > 1.0)
+            return fail("oracle: p_double > 1");
+        s->p_double = h->p_double;
+    } else {
+        int64_t ns, nd;
+        count_excitations(s, s->d0, &ns, &nd);
+        s->p_double = (ns + nd) > 0 ? (double)nd / (double)(ns + nd) : 0.0;
+    }
+    s->p_single = 1.0 - s->p_double;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Blocking analysis (Flyvbjerg & Petersen) of <num>/<den>, or of <num> when */
+/* den is NULL. At each level neighbouring samples are averaged in pairs (a  */
+/* trailing odd sample is dropped). The reported level is the first one     */
+/* (with at least 16 blocks) whose error is not exceeded by the next two     */
+/* levels by more than its own statistical uncertainty e/sqrt(2(n-1)).       */
+/* ------------------------------------------------------------------------ */
+int orc_blocking(const double *num, const double *den, int64_t n, double *mean_ratio,
+                 double *err, int32_t *level)
+{
+    *mean_ratio = NAN;
+    *err = NAN;
+    *level = -1;
+    if (n < 1)
+        return 0;
+    double sx = 0.0, sy = 0.0;
+    for (int64_t t = 0; t < n; t++) {
+        sx = sx + num[t];
+        sy = sy + (den ? den[t] : 1.0);
+    }
+    *mean_ratio = den ? (sx / (double)n) / (sy / (double)n) : sx / (double)n;
+    double *x = malloc((size_t)n * sizeof(double));
+    double *y = malloc((size_t)n * sizeof(double));
+    if (!x || !y) {
+        free(x);
+        free(y);
+        return fail("oracle: out of host memory");
+    }
+    for (int64_t t = 0; t < n; t++) {
+        x[t] = num[t];
+        y[t] = den ? den[t] : 1.0;
+    }
+    double e_lv[64];
+    int64_t n_lv[64];
+    int nlev = 0;
+    int64_t m = n;
+    while (m >= 2 && nlev < 64) {
+        double xm = 0.0, ym = 0.0;
+        for (int64_t t = 0; t < m; t++) {
+            xm = xm + x[t];
+            ym = ym + y[t];
+        }
+        xm = xm / (double)m;
+        ym = ym / (double)m;
+        double vx = 0.0, vy = 0.0, cxy = 0.0;
+        for (int64_t t = 0; t < m; t++) {
+            vx = vx + (x[t] - xm) * (x[t] - xm);
+            vy = vy + (y[t] - ym) * (y[t] - ym);
+            cxy = cxy + (x[t] - xm) * (y[t] - ym);
+        }
+        double norm = (double)m * (double)(m - 1);
+        vx = vx / norm;
+        vy = vy / norm;
+        cxy = cxy / norm;
+        double var;
+        if (den) {
+            double r = xm / ym;
+            var = r * r * (vx / (xm * xm) + vy / (ym * ym) - 2.0 * cxy / (xm * ym));
+        } else {
+            var = vx;
+        }
+        e_lv[nlev] = sqrt(var > 0.0 ? var : 0.0);
+        n_lv[nlev] = m;
+        nlev++;
+        int64_t h = m / 2;
+        for (int64_t t = 0; t < h; t++) {
+            x[t] = (x[2 * t] + x[2 * t + 1]) * 0.5;
+            y[t] = (y[2 * t] + y[2 * t + 1]) * 0.5;
+        }
+        m = h;
+    }
+    free(x);
+    free(y);
+    int chosen = -1, last_ok = -1;
+    for (int l = 0; l < nlev; l++) {
+        if (n_lv[l] < 16)
+            break;
+        last_ok = l;
+        double tol = e_lv[l] + e_lv[l] / sqrt(2.0 * (double)(n_lv[l] - 1));
+        int ok = 1;
+        for (int k = 1; k <= 2; k++)
+            if (l + k < nlev && n_lv[l + k] >= 16 && e_lv[l + k] > tol)
+                ok = 0;
+        if (ok) {
+            chosen = l;
+            break;
+        }
+    }
+    if (chosen < 0)
+        chosen = last_ok;
+    if (chosen >= 0) {
+        *err = e_lv[chosen];
+        *level = chosen;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Run interface.                                                            */
+/* ------------------------------------------------------------------------ */
+int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
+{
+    *out = NULL;
+    if (!ham || !prm)
+        return fail("oracle: null argument");
+    if (!(prm->tau > 0.0))
+        return fail("oracle: tau must be positive");
+    if (prm->shift_every <= 0)
+        return fail("oracle: shift_every must be positive");
+    orc_state *st = calloc(1, sizeof *st);
+    if (!st)
+        return fail("oracle: out of host memory");
+    if (sys_init(&st->sys, ham) != 0) {
+        free(st->sys.h1);
+        free(st->sys.eri);
+        free(st);
+        return -1;
+    }
+    st->prm = *prm;
+    int64_t range = prm->hash_range > 0 ? prm->hash_range : 1024;
+    if (ml_init(&st->ml, 1024, range, prm->hash_seed ? prm->hash_seed : 0x5EED5EEDull) != 0) {
+        orc_free(st);
+        return -1;
+    }
+    int64_t n0 = prm->n_init > 0 ? prm->n_init : 10;
+    if (n0 > 2147483647)
+        return fail("oracle: initial population exceeds int32");
+    ml_insert(&st->ml, st->sys.d0, (int32_t)n0, st->sys.e0);
+    st->shift = prm->shift0;
+    st->nw = n0;
+    st->nd = 1;
+    st->c0 = n0;
+    *out = st;
+    return 0;
+}
+
+void orc_free(orc_state *st)
+{
+    if (!st)
+        return;
+    ml_free(&st->ml);
+    free(st->spawn);
+    free(st->sys.h1);
+    free(st->sys.eri);
+    free(st->s_num);
+    free(st->s_den);
+    free(st->s_shift);
+    free(st);
+}
+
+static int is_initiator(const orc_state *st, uint64_t det, int32_t pop)
+{
+    int64_t a = pop < 0 ? -(int64_t)pop : pop;
+    return a > st->prm.n_a || det == st->sys.d0;
+}
+
+/* One iteration in the paper's order: spawning from every walker, death on
+ * each determinant, then compression and annihilation of the spawned list
+ * against the main list with the initiator test, then the estimators. */
+static int one_iteration(orc_state *st)
+{
+    const sys_t *s = &st->sys;
+    const double tau = st->prm.tau;
+    const int64_t it = st->iter;
+    mainlist_t *ml = &st->ml;
+    st->n_spawn = 0;
+    int64_t attempts = 0;
+    detinfo_t di;
+
+    /* Spawning and death, one occupied determinant at a time (Sec. 2). */
+    int64_t high = ml->high;
+    for (int64_t slot = 0; slot < high; slot++) {
+        uint64_t D = ml->det[slot];
+        if (!D)
+            continue;
+        int32_t C = ml->pop[slot];
+        int64_t absC = C < 0 ? -(int64_t)C : C;
+        if (absC == 0)
+            continue;          /* only the reference can sit at zero */
+        uint32_t flag = (uint32_t)is_initiator(st, D, C);
+        det_setup(s, D, &di);
+        for (int64_t k = 0; k < absC; k++) {
+            uint64_t x[5], b[2];
+            draw_block(st->prm.seed, D, (uint32_t)k, it, 0, b);
+            x[0] = b[0];
+            x[1] = b[1];
+            draw_block(st->prm.seed, D, (uint32_t)k, it, 1, b);
+            x[2] = b[0];
+            x[3] = b[1];
+            excit_t ex;
+            gen_excit(s, &di, x, &ex);
+            attempts++;
+            if (!ex.det || ex.hel == 0.0)
+                continue;
+            draw_block(st->prm.seed, D, (uint32_t)k, it, 2, b);
+            x[4] = b[0];
+            /* Eq. pspawn: integer part created deterministically, fraction stochastically. */
+            double pr = (tau * fabs(ex.hel)) / ex.pgen;
+            double fl = floor(pr);
+            if (fl > 1073741824.0)
+                return fail("oracle: spawn count overflow");
+            int64_t m = (int64_t)fl + (unit_uniform(x[4]) < pr - fl ? 1 : 0);
+            if (m == 0)
+                continue;
+            int64_t sgn = ((C > 0) ? 1 : -1) * (ex.hel > 0.0 ? 1 : -1);
+            if (push_spawn(st, ex.det, -sgn * m, flag) != 0)
+                return -1;
+        }
+        /* Eq. pdeath, all walkers on the determinant at once. */
+        uint64_t xd[2];
+        draw_block(st->prm.seed, D, 0xFFFFFFFFu, it, 0x80, xd);
+        double d = ((ml->hdiag[slot] - s->e0) - st->shift) * tau * (double)absC;
+        double ad = fabs(d);
+        double fl = floor(ad);
+        if (fl > 1073741824.0)
+            return fail("oracle: death count overflow");
+        int64_t m = (int64_t)fl + (unit_uniform(xd[0]) < ad - fl ? 1 : 0);
+        int64_t cnew = (int64_t)C - (C > 0 ? 1 : -1) * (d > 0.0 ? 1 : -1) * m;
+        if (cnew > 2147483647 || cnew < -2147483647)
+            return fail("oracle: population overflow");
+        if (cnew == 0 && D != s->d0)
+            ml_remove(ml, slot);
+        else
+            ml->pop[slot] = (int32_t)cnew;
+    }
+
+    /* Sort and compress the spawned list (Sec. 4.1): sum signed walkers on each
+     * determinant, OR the initiator flags, drop entries that cancel to zero. */
+    qsort(st->spawn, (size_t)st->n_spawn, sizeof(spawn_t), cmp_spawn);
+    int64_t merged = 0, aborted = 0;
+    int64_t i = 0;
+    while (i < st->n_spawn) {
+        uint64_t D = st->spawn[i].det;
+        int64_t c = 0;
+        uint32_t f = 0;
+        while (i < st->n_spawn && st->spawn[i].det == D) {
+            c += st->spawn[i].pop;
+            f |= st->spawn[i].flag;
+            i++;
+        }
+        if (c == 0)
+            continue;
+        merged++;
+        /* Annihilation against the main list (Sec. 4.2). */
+        int64_t slot = ml_find(ml, D);
+        if (slot >= 0) {
+            int64_t nv = (int64_t)ml->pop[slot] + c;
+            if (nv > 2147483647 || nv < -2147483647)
+                return fail("oracle: population overflow");
+            if (nv == 0 && D != s->d0)
+                ml_remove(ml, slot);
+            else
+                ml->pop[slot] = (int32_t)nv;
+        } else if (f) {
+            if (c > 2147483647 || c < -2147483647)
+                return fail("oracle: population overflow");
+            if (ml_insert(ml, D, (int32_t)c, hdiag_of(s, D)) < 0)
+                return -1;
+        } else {
+            aborted += c < 0 ? -c : c;
+        }
+    }
+
+    /* Estimators on the new list (Eq. ProjE). */
+    int64_t nw = 0, nd = 0, c0 = 0;
+    double num = 0.0;
+    for (int64_t slot = 0; slot < ml->high; slot++) {
+        uint64_t D = ml->det[slot];
+        if (!D)
+            continue;
+        int32_t C = ml->pop[slot];
+        if (D == s->d0)
+            c0 = C;
+        if (C == 0)
+            continue;
+        nw += C < 0 ? -(int64_t)C : C;
+        nd++;
+        if (D != s->d0 && popcount64(D ^ s->d0) <= 4)
+            num = num + hel_general(s, D, s->d0) * (double)C;
+    }
+    st->nw = nw;
+    st->nd = nd;
+    st->c0 = c0;
+    st->num = num;
+    st->attempts = attempts;
+    st->spawns = st->n_spawn;
+    st->merged = merged;
+    st->aborted = aborted;
+    st->tot_attempts += attempts;
+    st->tot_spawns += st->n_spawn;
+    st->iter++;
+
+    /* Shift: held until the walker target is reached, then
+     * S <- S - zeta/(A tau) ln(N_w / N_prev), both tested every A iterations. */
+    const int A = st->prm.shift_every;
+    if (st->iter % A == 0) {
+        if (!st->varying) {
+            if (nw >= st->prm.target) {
+                st->varying = 1;
+                st->n_prev = nw;
+                st->n_var = st->iter;
+            }
+        } else {
+            st->shift = st->shift - (st->prm.zeta / ((double)A * tau)) *
+                                        orc_log((double)nw / (double)st->n_prev);
+            st->n_prev = nw;
+        }
+    }
+    if (st->varying && st->iter - st->n_var >= st->prm.avg_start)
+        if (push_series(st, num, (double)c0, st->shift) != 0)
+            return -1;
+    return 0;
+}
+
+int orc_iterate(orc_state *st, int32_t n_iter)
+{
+    if (!st)
+        return fail("oracle: null state");
+    for (int32_t t = 0; t < n_iter; t++)
+        if (one_iteration(st) != 0)
+            return -1;
+    return 0;
+}
+
+int orc_estimates(orc_state *st, orc_est *out)
+{
+    if (!st || !out)
+        return fail("oracle: null argument");
+    memset(out, 0, sizeof *out);
+    out->iteration = st->iter;
+    out->n_walkers = st->nw;
+    out->n_dets = st->nd;
+    out->ref_pop = st->c0;
+    out->attempts = st->attempts;
+    out->spawns = st->spawns;
+    out->merged = st->merged;
+    out->aborted = st->aborted;
+    out->total_attempts = st->tot_attempts;
+    out->total_spawns = st->tot_spawns;
+    out->n_samples = st->n_series;
+    out->n_var = st->n_var;
+    out->n_prev = st->n_prev;
+    out->shift = st->shift;
+    out->e_ref = st->sys.e0;
+    out->p_double = st->sys.p_double;
+    out->proj_num = st->num;
+    out->e_proj_inst = st->c0 != 0 ? st->sys.e0 + st->num / (double)st->c0 : NAN;
+    out->shift_varying = st->varying;
+    int32_t lvl;
+    double r, e;
+    orc_blocking(st->s_num, st->s_den, st->n_series, &r, &e, &lvl);
+    out->e_proj_mean = st->sys.e0 + r;
+    out->e_proj_err = e;
+    orc_blocking(st->s_shift, NULL, st->n_series, &r, &e, &lvl);
+    out->shift_mean = st->sys.e0 + r;
+    out->shift_err = e;
+    return 0;
+}
+
+int64_t orc_walkers(orc_state *st, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap)
+{
+    if (!st)
+        return fail("oracle: null state");
+    int64_t n = 0;
+    for (int64_t slot = 0; slot < st->ml.high; slot++)
+        if (st->ml.det[slot] && st->ml.pop[slot] != 0)
+            n++;
+    if (!det)
+        return n;
+    spawn_t *tmp = malloc((size_t)(n ? n : 1) * sizeof(spawn_t));
+    if (!tmp)
+        return fail("oracle: out of host memory");
+    int64_t k = 0;
+    for (int64_t slot = 0; slot < st->ml.high; slot++)
+        if (st->ml.det[slot] && st->ml.pop[slot] != 0) {
+            tmp[k].det = st->ml.det[slot];
+            tmp[k].pop = st->ml.pop[slot];
+            tmp[k].flag = (uint32_t)is_initiator(st, st->ml.det[slot], st->ml.pop[slot]);
+            k++;
+        }
+    qsort(tmp, (size_t)n, sizeof(spawn_t), cmp_spawn);
+    for (int64_t t = 0; t < n && t < cap; t++) {
+        det[t] = tmp[t].det;
+        if (pop)
+            pop[t] = (int32_t)tmp[t].pop;
+        if (flags)
+            flags[t] = tmp[t].flag;
+    }
+    free(tmp);
+    return n;
+}
+
+int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int64_t n,
+                     int64_t iteration, double shift, int64_t n_prev, int32_t varying,
+                     int64_t n_var)
+{
+    if (!st)
+        return fail("oracle: null state");
+    uint64_t hs = st->prm.hash_seed ? st->prm.hash_seed : 0x5EED5EEDull;
+    int64_t range = st->ml.range;
+    ml_free(&st->ml);
+    if (ml_init(&st->ml, 1024, range, hs) != 0)
+        return -1;
+    int have_ref = 0;
+    for (int64_t t = 0; t < n; t++) {
+        if (pop[t] == 0)
+            continue;
+        if (ml_find(&st->ml, det[t]) >= 0)
+            return fail("oracle: duplicate determinant in walker list");
+        if (det[t] == st->sys.d0)
+            have_ref = 1;
+        if (ml_insert(&st->ml, det[t], pop[t], hdiag_of(&st->sys, det[t])) < 0)
+            return -1;
+    }
+    if (!have_ref && ml_insert(&st->ml, st->sys.d0, 0, st->sys.e0) < 0)
+        return -1;
+    st->iter = iteration;
+    st->shift = shift;
+    st->n_prev = n_prev;
+    st->varying = varying;
+    st->n_var = n_var;
+    st->n_series = 0;
+    st->nw = st->nd = st->c0 = 0;
+    st->num = 0.0;
+    for (int64_t slot = 0; slot < st->ml.high; slot++) {
+        uint64_t D = st->ml.det[slot];
+        int32_t C = st->ml.pop[slot];
+        if (!D)
+            continue;
+        if (D == st->sys.d0)
+            st->c0 = C;
+        if (C == 0)
+            continue;
+        st->nw += C < 0 ? -(int64_t)C : C;
+        st->nd++;
+        if (D != st->sys.d0 && popcount64(D ^ st->sys.d0) <= 4)
+            st->num = st->num + hel_general(&st->sys, D, st->sys.d0) * (double)C;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Unit-level entry points.                                                  */
+/* ------------------------------------------------------------------------ */
+int64_t orc_hash(const orc_state *st, uint64_t det, int64_t range)
+{
+    int32_t occ[64];
+    int n = orc_decode(det, occ);
+    return hash_alg1(st->ml.map, occ, n, range);
+}
+
+double orc_hel(const orc_state *st, uint64_t bra, uint64_t ket)
+{
+    return hel_general(&st->sys, bra, ket);
+}
+
+double orc_hdiag(const orc_state *st, uint64_t det) { return hdiag_of(&st->sys, det); }
+
+double orc_proj_num(const orc_state *st, const uint64_t *det, const double *c, int64_t n)
+{
+    double num = 0.0;
+    for (int64_t t = 0; t < n; t++)
+        if (det[t] != st->sys.d0 && popcount64(det[t] ^ st->sys.d0) <= 4)
+            num = num + hel_general(&st->sys, det[t], st->sys.d0) * c[t];
+    return num;
+}
+
+int orc_sample_excitations(const orc_state *st, uint64_t det, int64_t iteration, int64_t n_samples,
+                           uint64_t *out_det, double *out_pgen, double *out_hel)
+{
+    detinfo_t di;
+    det_setup(&st->sys, det, &di);
+    for (int64_t k = 0; k < n_samples; k++) {
+        uint64_t x[4], b[2];
+        draw_block(st->prm.seed, det, (uint32_t)k, iteration, 0, b);
+        x[0] = b[0];
+        x[1] = b[1];
+        draw_block(st->prm.seed, det, (uint32_t)k, iteration, 1, b);
+        x[2] = b[0];
+        x[3] = b[1];
+        excit_t ex;
+        gen_excit(&st->sys, &di, x, &ex);
+        out_det[k] = ex.det;
+        out_pgen[k] = ex.pgen;
+        out_hel[k] = ex.hel;
+    }
+    return 0;
+}

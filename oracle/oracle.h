@@ -1,0 +1,85 @@
+/*
+ * CPU oracle for the FCIQMC iteration of Booth, Smart & Alavi,
+ * "Linear-scaling and parallelizable algorithms for stochastic quantum
+ * chemistry" (arXiv:1305.6981).
+ *
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow, single-threaded reference
+ * implementation used by the test-suite, the smoke check and the CPU baseline
+ * leg of the benchmark. The product library never links, loads or calls it,
+ * and it shares no source with the HIP path.
+ *
+ * Conventions (shared only as a *data format* with the product ABI):
+ *   spin orbital p = 2*s + sigma (s spatial, sigma 0 = alpha, 1 = beta);
+ *   a determinant is a uint64 with bit p set when p is occupied;
+ *   h1 is M*M row-major; eri is the eight-fold packed (pq|rs) array with pair
+ *   index ij = i(i+1)/2 + j (i >= j) and element IJ(IJ+1)/2 + KL (IJ >= KL).
+ */
+#ifndef FCIQMC_ORACLE_H
+#define FCIQMC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t n_orb, n_alpha, n_beta, pad0;
+    double e_core;
+    const double *h1;
+    const double *eri;
+    const uint8_t *orb_irrep;   /* NULL: every orbital in the totally symmetric irrep */
+    double p_double;            /* < 0: ratio of double to all excitations from D0 */
+    const uint64_t *ref_det;    /* NULL: aufbau by h_pp */
+} orc_ham;
+
+typedef struct {
+    double tau, zeta, shift0;
+    int32_t shift_every, n_a;
+    int64_t target, n_init;
+    uint64_t seed;
+    int32_t avg_start, pad0;
+    uint64_t hash_seed;         /* seeds the random orbital map of Algorithm 1 */
+    int64_t hash_range;         /* initial size of the main-list hash table; 0 = auto */
+} orc_params;
+
+typedef struct {
+    int64_t iteration, n_walkers, n_dets, ref_pop;
+    int64_t attempts, spawns, merged, aborted;
+    int64_t total_attempts, total_spawns, n_samples, n_var;
+    double shift, e_ref, p_double, proj_num, e_proj_inst;
+    double e_proj_mean, e_proj_err, shift_mean, shift_err;
+    int32_t shift_varying, pad0;
+    int64_t n_prev;
+} orc_est;
+
+typedef struct orc_state orc_state;
+
+/* Whole-run interface (same meaning as the product's fciqmc_* calls). */
+int     orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out);
+int     orc_iterate(orc_state *st, int32_t n_iter);
+int     orc_estimates(orc_state *st, orc_est *out);
+int64_t orc_walkers(orc_state *st, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap);
+int     orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int64_t n,
+                         int64_t iteration, double shift, int64_t n_prev, int32_t varying,
+                         int64_t n_var);
+void    orc_free(orc_state *st);
+const char *orc_last_error(void);
+
+/* Unit-level entry points used by the pins. */
+void    orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+int     orc_decode(uint64_t det, int32_t *occ);          /* byte-table decode; returns count */
+int64_t orc_hash(const orc_state *st, uint64_t det, int64_t range);   /* Algorithm 1 */
+double  orc_hel(const orc_state *st, uint64_t bra, uint64_t ket);      /* <bra|H|ket> */
+double  orc_hdiag(const orc_state *st, uint64_t det);
+double  orc_proj_num(const orc_state *st, const uint64_t *det, const double *c, int64_t n);
+int     orc_sample_excitations(const orc_state *st, uint64_t det, int64_t iteration,
+                               int64_t n_samples, uint64_t *out_det, double *out_pgen,
+                               double *out_hel);
+double  orc_log(double x);                              /* shift-update logarithm */
+int     orc_blocking(const double *num, const double *den, int64_t n,
+                     double *mean_ratio, double *err, int32_t *level);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
