@@ -1,0 +1,211 @@
+/*
+ * fciqmc.h -- C ABI of the MI355X FCIQMC library (libfciqmc.so).
+ *
+ * The library runs the FCIQMC iteration of Booth, Smart & Alavi,
+ * "Linear-scaling and parallelizable algorithms for stochastic quantum
+ * chemistry" (arXiv:1305.6981), on one AMD Instinct MI355X (gfx950), with the
+ * whole signed-walker list resident in device memory:
+ *   - spawning: one attempt per walker, a random single or double excitation
+ *     with its generation probability (Sec. 5, Eq. p_sing and the double
+ *     excitation formula), the Slater-Condon element, and acceptance with
+ *     probability tau |H_ij| / P_gen, the integer part deterministic
+ *     (Sec. 2, Eq. pspawn);
+ *   - death/cloning of all walkers on a determinant at once (Eq. pdeath);
+ *   - annihilation of the spawned walkers against the main list with the
+ *     initiator rule applied to spawns onto unoccupied determinants, and the
+ *     diagonal element computed when a determinant becomes occupied (Sec. 4.2);
+ *   - the projected energy (Eq. ProjE) and the population-control shift
+ *     (Sec. 2), with blocking error bars (Sec. 7).
+ *
+ * Conventions
+ *   - spin orbital p = 2*s + sigma (s spatial orbital, sigma 0 = alpha,
+ *     1 = beta); a determinant is a uint64 with bit p set when p is occupied
+ *     (the bit-string representation of Sec. 3). 2*n_orb <= 64.
+ *   - all pointers in this header are HOST pointers; the library copies what
+ *     it needs at the call and never keeps a caller's pointer.
+ *   - return value: 0 on success, a negative FCIQMC_E* code on failure; the
+ *     message of the last failure on the calling thread is returned by
+ *     fciqmc_last_error(). No C++ exception crosses this boundary.
+ *   - a handle is used by one host thread at a time; its device work runs on
+ *     the HIP stream given at creation (NULL: the library's own stream).
+ *   - results do not depend on memory layout, table sizes, launch shapes or
+ *     on which other systems share a batch: every random decision is drawn
+ *     from a Philox4x32-10 stream keyed by (seed, iteration, determinant,
+ *     walker ordinal), and every merge is an integer sum.
+ */
+#ifndef FCIQMC_H
+#define FCIQMC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCIQMC_OK            0
+#define FCIQMC_EINVAL       -1   /* bad argument: sizes, tau <= 0, 2*n_orb > 64, ... */
+#define FCIQMC_ENOMEM       -2   /* device or host allocation failed / does not fit */
+#define FCIQMC_EDEVICE      -3   /* a HIP call failed (message kept) */
+#define FCIQMC_ECAPACITY    -4   /* a table could not be grown */
+#define FCIQMC_EOVERFLOW    -5   /* a population left the int32 range, or died out */
+#define FCIQMC_ESTATE       -6   /* call not valid for this handle or slot */
+
+typedef struct fciqmc_t fciqmc_t;   /* opaque; owned by the library */
+
+/* The Hamiltonian in an M-orbital determinant basis with N = n_alpha + n_beta
+ * electrons (Sec. 2). */
+typedef struct {
+    int32_t n_orb;              /* M spatial orbitals, 1 <= M <= 32 */
+    int32_t n_alpha, n_beta;    /* electrons per spin */
+    int32_t reserved0;
+    double e_core;              /* constant energy */
+    const double *h1;           /* M*M row-major one-electron integrals, symmetric */
+    const double *eri;          /* eight-fold packed (pq|rs): pair ij = i(i+1)/2 + j (i >= j),
+                                   element IJ(IJ+1)/2 + KL (IJ >= KL); M(M+1)/2*(M(M+1)/2+1)/2 doubles */
+    const uint8_t *orb_irrep;   /* NULL: no point group; else an abelian irrep label 0..7 per
+                                   spatial orbital, direct product = XOR (Sec. 5) */
+    double p_double;            /* >= 0: probability of drawing a double excitation; < 0: the
+                                   ratio of double to all symmetry-allowed excitations of the
+                                   reference (Sec. 5) */
+    const uint64_t *ref_det;    /* NULL: aufbau (lowest n_alpha / n_beta orbitals by h_pp) */
+} fciqmc_hamiltonian;
+
+/* Run parameters. */
+typedef struct {
+    double tau;                 /* time step, > 0 */
+    double shift_damping;       /* zeta in S <- S - zeta/(A tau) ln(N_w/N_prev) */
+    double initial_shift;       /* S before the target is reached, relative to E0 = H_00 */
+    int32_t shift_update_every; /* A >= 1: the target test and the shift update happen when
+                                   the number of completed iterations is a multiple of A */
+    int32_t initiator_threshold;/* n_a: a determinant is an initiator when |C| > n_a (the
+                                   reference always is); 0 gives plain FCIQMC */
+    int64_t target_walkers;     /* the shift starts to vary once N_w >= target */
+    int64_t initial_walkers;    /* walkers placed on the reference at start (0: 10) */
+    int64_t det_capacity;       /* initial main-table slots per buffer (0: automatic); the
+                                   table grows by itself, results do not depend on it */
+    int64_t spawn_capacity;     /* reserved (spawns accumulate in the main table) */
+    uint64_t seed;              /* Philox key */
+    int32_t avg_start;          /* iterations after the shift starts varying before samples
+                                   enter the averages */
+    int32_t reserved0;
+} fciqmc_params;
+
+/* Estimators and counters of one system. Counts refer to the last completed
+ * iteration unless marked total. */
+typedef struct {
+    int64_t iteration;          /* completed iterations */
+    int64_t n_walkers;          /* N_w = sum |C| */
+    int64_t n_dets;             /* occupied determinants */
+    int64_t ref_pop;            /* C_0 */
+    int64_t attempts;           /* spawn attempts (= N_w at the start of the iteration) */
+    int64_t spawns;             /* accepted spawning events (records entering annihilation) */
+    int64_t merged;             /* distinct determinants receiving a nonzero spawned sum */
+    int64_t aborted;            /* walkers discarded by the initiator rule */
+    int64_t total_attempts, total_spawns;
+    int64_t n_samples;          /* iterations in the averages */
+    int64_t n_var;              /* iteration at which the shift started to vary */
+    int64_t n_prev;             /* N_w at the last shift update */
+    double shift;               /* S, relative to E0 */
+    double e_ref;               /* E0 = H_00 */
+    double p_double;
+    double proj_num;            /* sum over D != D0 of <D|H|D0> C_D */
+    double e_proj_inst;         /* E0 + proj_num / C_0 (NaN when C_0 = 0) */
+    double e_proj_mean, e_proj_err;   /* E0 + <num>/<C_0> and its blocking error */
+    double shift_mean, shift_err;     /* E0 + <S> and its blocking error */
+    double ms_last_call;        /* wall time of the last fciqmc_iterate on this handle */
+    int32_t shift_varying;
+    int32_t status;             /* 0, or the FCIQMC_E* code that stopped this system */
+} fciqmc_estimates;
+
+/* Create a handle holding one system, place initial_walkers on the reference.
+ * hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream),
+ * or NULL. Errors: EINVAL, ENOMEM, EDEVICE. */
+int fciqmc_init(const fciqmc_hamiltonian *ham, const fciqmc_params *prm, void *hip_stream,
+                fciqmc_t **out);
+
+/* Advance every active system of the handle by n_iterations (>= 0) full
+ * iterations (spawn, death, annihilation, estimators, shift), in graph-captured
+ * launches of up to 64 iterations. Tables grow as needed; an iteration that
+ * overflows a table is re-executed bit-exactly after the growth.
+ * Errors: EINVAL, EDEVICE, ECAPACITY, EOVERFLOW. */
+int fciqmc_iterate(fciqmc_t *h, int32_t n_iterations);
+
+/* Estimators of system 0 of the handle. */
+int fciqmc_estimators(fciqmc_t *h, fciqmc_estimates *out);
+
+/* Release everything. NULL-safe. */
+int fciqmc_free(fciqmc_t *h);
+
+/* Copy the occupied determinants of system 0, sorted by determinant, into the
+ * caller's host arrays (each of length cap; any may be NULL). flags[i] is 1
+ * when the determinant is an initiator for the next iteration. Returns the
+ * number of occupied determinants (which may exceed cap: then only cap are
+ * written), or a negative error code. */
+int64_t fciqmc_walkers(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap);
+
+/* Replace the walker list of system 0 (checkpoint restart). Entries with
+ * pop == 0 are ignored; the reference is kept in the list even when absent.
+ * iteration is the number of completed iterations, shift is S relative to E0,
+ * varying / n_var / n_prev restore the shift-update state. The averages are
+ * cleared. Errors: EINVAL (duplicates, electron-count mismatch), ENOMEM. */
+int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, int64_t n,
+                        int64_t iteration, double shift, int64_t n_prev, int32_t varying,
+                        int64_t n_var);
+
+/* Set the shift of system 0 and start (varying = 1) or stop its variation;
+ * when started, N_prev is set to the current N_w and n_var to the current
+ * iteration. Used to end a growth stage run at a raised shift. */
+int fciqmc_set_shift(fciqmc_t *h, double shift, int32_t varying);
+
+/* Thread-local message of the last failure ("" when none). */
+const char *fciqmc_last_error(void);
+
+/* ---- batching and serving: many independent systems in one handle -------
+ * The systems of a batch advance together: every iteration of every system
+ * is one pass of the same kernels over a descriptor table, so one launch
+ * serves all of them, and each system's walker list is bit-identical to the
+ * list it would have alone. Slots are numbered 0 .. max_slots-1. */
+
+/* Create a handle with room for max_slots systems and admit n of them
+ * (hams[i], prms[i] -> slot i). Errors: EINVAL, ENOMEM, EDEVICE. */
+int fciqmc_batch_create(int32_t max_slots, int32_t n, const fciqmc_hamiltonian *hams,
+                        const fciqmc_params *prms, void *hip_stream, fciqmc_t **out);
+
+/* Advance every active system by n_iterations (same as fciqmc_iterate). */
+int fciqmc_batch_iterate(fciqmc_t *h, int32_t n_iterations);
+
+/* Advance each active slot i by n_iter[i] iterations (n_iter has max_slots
+ * entries; inactive slots are ignored). Systems that reach their count idle
+ * while the others run. */
+int fciqmc_batch_iterate_each(fciqmc_t *h, const int32_t *n_iter);
+
+/* Admit one system into a free slot while others may be mid-run. Fails with
+ * ENOMEM when its tables (32 B per walker slot) do not fit in the free device
+ * memory left after the reserve, with ESTATE when no slot is free. */
+int fciqmc_batch_admit(fciqmc_t *h, const fciqmc_hamiltonian *ham, const fciqmc_params *prm,
+                       int32_t *slot);
+
+/* Retire a slot and free its device memory. */
+int fciqmc_batch_retire(fciqmc_t *h, int32_t slot);
+
+int fciqmc_batch_slot_estimators(fciqmc_t *h, int32_t slot, fciqmc_estimates *out);
+int64_t fciqmc_batch_slot_walkers(fciqmc_t *h, int32_t slot, uint64_t *det, int32_t *pop,
+                                  uint32_t *flags, int64_t cap);
+
+/* Device bytes a system with the given walker target would reserve, and the
+ * number of active slots. */
+int64_t fciqmc_footprint_bytes(const fciqmc_hamiltonian *ham, const fciqmc_params *prm);
+int32_t fciqmc_batch_active(fciqmc_t *h);
+
+/* ---- instrumentation -------------------------------------------------------
+ * Per-kernel device time (ms) accumulated since the last reset, measured with
+ * HIP events on the handle's stream around each kernel of non-graph launches
+ * (enable with fciqmc_set_profiling(h, 1); graph launches are then disabled).
+ * Kernel order: 0 chunk sums, 1 chunk scan, 2 spawn, 3 death+annihilation,
+ * 4 estimators/shift. counts[k] is the number of launches measured. */
+int fciqmc_set_profiling(fciqmc_t *h, int32_t on);
+int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

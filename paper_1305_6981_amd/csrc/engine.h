@@ -1,0 +1,95 @@
+// Internal layout shared by the kernels and the host engine of libfciqmc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fq {
+
+constexpr int CHUNK = 1024;          // main-table slots per chunk (one workgroup's unit)
+constexpr int NCLASS = 16;           // symmetry classes: 2 spins x up to 8 abelian irreps
+constexpr int REC_CAP = 256;         // per-system ring of per-iteration records
+constexpr int MAX_GRAPH_ITERS = 64;  // iterations captured in one graph launch
+
+// Status bits set on the device.
+constexpr uint32_t ST_TABLE_FULL = 1u;     // a spawn found no free slot: grow and redo
+constexpr uint32_t ST_POP_OVERFLOW = 2u;   // a population left int32
+constexpr uint32_t ST_DIED = 4u;           // N_w reached zero
+constexpr uint32_t ST_SPAWN_OVERFLOW = 8u; // one spawning event would create > 2^30 walkers
+
+// One main-table slot: the determinant key and the spawned walkers that
+// arrive on it during the current iteration (signed sum, OR of initiator flags).
+struct alignas(16) Slot {
+    uint64_t det;      // 0 = empty
+    int32_t spop;
+    uint32_t sflag;
+};
+
+struct IterRecord {
+    int64_t iter;      // completed iterations after this one
+    int64_t nw, nd, c0, attempts, spawns, merged, aborted;
+    int64_t n_var, n_prev;
+    double num, shift;
+    int32_t varying, status;
+};
+
+struct ChunkStat {
+    int64_t nw, nd, c0, merged, aborted;
+    double num;
+};
+
+// Per-system descriptor, resident in device memory. The first block is
+// written by the host at admission / growth; the second block is updated by
+// the finalize kernel every iteration.
+struct SysDesc {
+    // --- set by the host
+    int32_t active, M, N, n_so;
+    int32_t A, n_a, pad0, pad1;
+    double tau, zeta, e0, e_core, p_double, p_single;
+    int64_t target;
+    uint64_t seed, d0, valid;
+    uint64_t cmask[NCLASS];
+    uint64_t irr_packed[2];          // 4 bits per spatial orbital
+    const double *h1, *eri;
+    Slot *kv[2];
+    int32_t *pop[2];
+    double *hdiag[2];
+    uint64_t cap_mask;               // capacity - 1 (capacity a power of two >= CHUNK)
+    int64_t nchunks, gchunk0;        // chunks of this system and the first global chunk
+    int64_t stop_at;                 // iterate while iter < stop_at
+    // --- updated on the device
+    int64_t iter;
+    double shift;
+    int32_t varying, parity;
+    int64_t n_prev, n_var;
+    uint32_t status, pad2;
+    unsigned long long spawns;       // spawning events of the running iteration
+};
+
+struct EngineArgs {
+    SysDesc *desc;
+    int32_t max_sys;
+    int32_t pad;
+    const int32_t *chunk_sys;        // system of each global chunk (-1: unused)
+    const int32_t *chunk_local;      // chunk index inside its system's table
+    unsigned long long *chunk_nw;    // sum |C| per chunk (this iteration's attempts)
+    unsigned long long *chunk_off;   // exclusive scan of chunk_nw
+    ChunkStat *chunk_stat;
+    unsigned long long *total;       // total attempts of the iteration
+    const int64_t *nchunks;          // global chunks in use
+    IterRecord *rec;                 // [max_sys][REC_CAP]
+};
+
+// Kernel launchers (kernels.hip).
+void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int spawn_grid,
+                      hipStream_t s, hipEvent_t *ev /* 6 events or nullptr */);
+hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
+                       int64_t n, int32_t parity, uint32_t *d_err, hipStream_t s);
+hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const Slot *src_kv, const int32_t *src_pop,
+                         const double *src_hd, int64_t src_cap, Slot *dst_kv, int32_t *dst_pop,
+                         double *dst_hd, uint32_t *d_err, hipStream_t s);
+hipError_t launch_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint64_t *out_det,
+                          int32_t *out_pop, unsigned long long *count, hipStream_t s);
+hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s);
+int spawn_grid_size();
+
+}  // namespace fq

@@ -1,0 +1,1113 @@
+// Host engine of libfciqmc: the C ABI declared in include/fciqmc.h.
+//
+// A handle holds up to max_slots independent systems. Each system owns a
+// double-buffered open-addressing main table in device memory (Slot key +
+// spawned sum, population, stored diagonal element), its integrals, and a row
+// of the device descriptor table. One iteration of every system is one pass
+// of five kernels over the descriptor table; up to 64 iterations are captured
+// in one HIP graph. The host reads the per-iteration records after each
+// launch, keeps the estimator series for blocking, and grows tables between
+// launches (re-running an iteration whose spawns overflowed a table; the
+// counter-based random numbers make the re-run identical).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fciqmc.h"
+#include "engine.h"
+
+using namespace fq;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return set_err(FCIQMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t next_pow2(int64_t x) {
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Blocking analysis (Flyvbjerg & Petersen) of <num>/<den> (den == nullptr:
+// of <num>). Pairwise averaging per level, trailing odd sample dropped; the
+// error is taken at the first level with >= 16 blocks whose value the next two
+// levels do not exceed by more than its own uncertainty e/sqrt(2(n-1)).
+// ---------------------------------------------------------------------------
+void blocking(const std::vector<double> &num, const std::vector<double> *den, double &mean,
+              double &err) {
+    const size_t n = num.size();
+    mean = NAN;
+    err = NAN;
+    if (n == 0) return;
+    double sx = 0.0, sy = 0.0;
+    for (size_t t = 0; t < n; ++t) {
+        sx = sx + num[t];
+        sy = sy + (den ? (*den)[t] : 1.0);
+    }
+    mean = den ? (sx / (double)n) / (sy / (double)n) : sx / (double)n;
+    std::vector<double> x(num), y(n, 1.0);
+    if (den) y = *den;
+    std::vector<double> ev;
+    std::vector<size_t> nv;
+    size_t m = n;
+    while (m >= 2) {
+        double xm = 0.0, ym = 0.0;
+        for (size_t t = 0; t < m; ++t) {
+            xm = xm + x[t];
+            ym = ym + y[t];
+        }
+        xm = xm / (double)m;
+        ym = ym / (double)m;
+        double vx = 0.0, vy = 0.0, c = 0.0;
+        for (size_t t = 0; t < m; ++t) {
+            vx = vx + (x[t] - xm) * (x[t] - xm);
+            vy = vy + (y[t] - ym) * (y[t] - ym);
+            c = c + (x[t] - xm) * (y[t] - ym);
+        }
+        const double nn = (double)m * (double)(m - 1);
+        vx = vx / nn;
+        vy = vy / nn;
+        c = c / nn;
+        double var;
+        if (den) {
+            const double r = xm / ym;
+            var = r * r * (vx / (xm * xm) + vy / (ym * ym) - 2.0 * c / (xm * ym));
+        } else {
+            var = vx;
+        }
+        ev.push_back(std::sqrt(var > 0.0 ? var : 0.0));
+        nv.push_back(m);
+        const size_t h = m / 2;
+        for (size_t t = 0; t < h; ++t) {
+            x[t] = (x[2 * t] + x[2 * t + 1]) * 0.5;
+            y[t] = (y[2 * t] + y[2 * t + 1]) * 0.5;
+        }
+        m = h;
+    }
+    int chosen = -1, last_ok = -1;
+    for (size_t l = 0; l < ev.size(); ++l) {
+        if (nv[l] < 16) break;
+        last_ok = (int)l;
+        const double tol = ev[l] + ev[l] / std::sqrt(2.0 * (double)(nv[l] - 1));
+        bool ok = true;
+        for (size_t k = 1; k <= 2; ++k)
+            if (l + k < ev.size() && nv[l + k] >= 16 && ev[l + k] > tol) ok = false;
+        if (ok) {
+            chosen = (int)l;
+            break;
+        }
+    }
+    if (chosen < 0) chosen = last_ok;
+    if (chosen >= 0) err = ev[chosen];
+}
+
+struct SysHost {
+    bool active = false;
+    fciqmc_params prm{};
+    int M = 0, N = 0, na = 0, nb = 0;
+    std::vector<double> h1, eri;
+    std::vector<uint8_t> irrep;
+    double e_core = 0.0, p_double = 0.0, e0 = 0.0;
+    uint64_t d0 = 0;
+    int64_t cap = 0;           // slots per buffer
+    void *block = nullptr;     // one device allocation for tables + integrals
+    Slot *kv[2] = {nullptr, nullptr};
+    int32_t *pop[2] = {nullptr, nullptr};
+    double *hd[2] = {nullptr, nullptr};
+    double *d_h1 = nullptr, *d_eri = nullptr;
+    int64_t reserve_bytes = 0; // admission accounting (target footprint)
+    // mirrored dynamics and statistics
+    IterRecord last{};
+    int64_t tot_att = 0, tot_sp = 0;
+    std::vector<double> s_num, s_den, s_shift;
+    int fatal = 0;
+};
+
+}  // namespace
+
+struct fciqmc_t {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int max_sys = 0;
+    std::vector<SysHost> sys;
+    std::vector<SysDesc> hdesc;
+    SysDesc *d_desc = nullptr;
+    IterRecord *d_rec = nullptr;
+    std::vector<IterRecord> hrec;
+    // global chunk layout
+    int64_t chunk_alloc = 0, n_chunks = 0;
+    int32_t *d_chunk_sys = nullptr, *d_chunk_local = nullptr;
+    unsigned long long *d_chunk_nw = nullptr, *d_chunk_off = nullptr, *d_total = nullptr;
+    ChunkStat *d_chunk_stat = nullptr;
+    int64_t *d_nchunks = nullptr;
+    uint32_t *d_err = nullptr;
+    int spawn_grid = 2048;
+    std::map<int, hipGraphExec_t> graphs;
+    bool use_graph = true;
+    bool profiling = false;
+    hipEvent_t ev[6] = {};
+    double kms[5] = {0, 0, 0, 0, 0};
+    int64_t kcount[5] = {0, 0, 0, 0, 0};
+    double ms_last = 0.0;
+};
+
+namespace {
+
+EngineArgs make_args(fciqmc_t *h) {
+    EngineArgs a{};
+    a.desc = h->d_desc;
+    a.max_sys = h->max_sys;
+    a.chunk_sys = h->d_chunk_sys;
+    a.chunk_local = h->d_chunk_local;
+    a.chunk_nw = h->d_chunk_nw;
+    a.chunk_off = h->d_chunk_off;
+    a.chunk_stat = h->d_chunk_stat;
+    a.total = h->d_total;
+    a.nchunks = h->d_nchunks;
+    a.rec = h->d_rec;
+    return a;
+}
+
+void drop_graphs(fciqmc_t *h) {
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
+
+int upload_desc(fciqmc_t *h) {
+    HIP_TRY(hipMemcpyAsync(h->d_desc, h->hdesc.data(), sizeof(SysDesc) * h->max_sys,
+                           hipMemcpyHostToDevice, h->stream));
+    return 0;
+}
+
+int download_desc(fciqmc_t *h) {
+    HIP_TRY(hipMemcpyAsync(h->hdesc.data(), h->d_desc, sizeof(SysDesc) * h->max_sys,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+// Lay the chunks of all active systems out contiguously.
+int relayout(fciqmc_t *h) {
+    int64_t total = 0;
+    for (int s = 0; s < h->max_sys; ++s)
+        if (h->sys[s].active) total += h->sys[s].cap / CHUNK;
+    if (total > h->chunk_alloc) {
+        int64_t na = next_pow2(std::max<int64_t>(total, 64));
+        hipFree(h->d_chunk_sys);
+        hipFree(h->d_chunk_local);
+        hipFree(h->d_chunk_nw);
+        hipFree(h->d_chunk_off);
+        hipFree(h->d_chunk_stat);
+        h->d_chunk_sys = nullptr;
+        h->chunk_alloc = 0;
+        HIP_TRY(hipMalloc(&h->d_chunk_sys, na * sizeof(int32_t)));
+        HIP_TRY(hipMalloc(&h->d_chunk_local, na * sizeof(int32_t)));
+        HIP_TRY(hipMalloc(&h->d_chunk_nw, na * sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc(&h->d_chunk_off, na * sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc(&h->d_chunk_stat, na * sizeof(ChunkStat)));
+        h->chunk_alloc = na;
+        drop_graphs(h);
+    }
+    std::vector<int32_t> cs(total), cl(total);
+    int64_t g = 0;
+    for (int s = 0; s < h->max_sys; ++s) {
+        SysDesc &d = h->hdesc[s];
+        if (!h->sys[s].active) {
+            d.gchunk0 = 0;
+            d.nchunks = 0;
+            continue;
+        }
+        const int64_t nc = h->sys[s].cap / CHUNK;
+        d.gchunk0 = g;
+        d.nchunks = nc;
+        for (int64_t c = 0; c < nc; ++c) {
+            cs[g + c] = s;
+            cl[g + c] = (int32_t)c;
+        }
+        g += nc;
+    }
+    h->n_chunks = total;
+    if (total > 0) {
+        HIP_TRY(hipMemcpyAsync(h->d_chunk_sys, cs.data(), total * sizeof(int32_t),
+                               hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->d_chunk_local, cl.data(), total * sizeof(int32_t),
+                               hipMemcpyHostToDevice, h->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(h->d_nchunks, &h->n_chunks, sizeof(int64_t), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int64_t table_bytes(int64_t cap) {
+    return 2 * cap * (int64_t)(sizeof(Slot) + sizeof(int32_t) + sizeof(double));
+}
+
+int64_t integral_bytes(int M) {
+    const int64_t np = (int64_t)M * (M + 1) / 2;
+    return (int64_t)(M * M + np * (np + 1) / 2) * 8 + 256;
+}
+
+// Allocate (and zero) the tables of a system at capacity cap; integrals are
+// copied in as well. Old storage is released by the caller.
+int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
+    const int64_t tb = table_bytes(cap), ib = integral_bytes(S.M);
+    void *blk = nullptr;
+    hipError_t e = hipMalloc(&blk, (size_t)(tb + ib));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(FCIQMC_ENOMEM, "device allocation of " + std::to_string(tb + ib) +
+                                          " bytes failed: " + hipGetErrorString(e));
+    }
+    HIP_TRY(hipMemsetAsync(blk, 0, (size_t)tb, h->stream));
+    *block_out = blk;
+    return 0;
+}
+
+void carve(SysHost &S, void *blk, int64_t cap) {
+    char *p = (char *)blk;
+    for (int b = 0; b < 2; ++b) {
+        S.kv[b] = (Slot *)p;
+        p += cap * sizeof(Slot);
+    }
+    for (int b = 0; b < 2; ++b) {
+        S.hd[b] = (double *)p;
+        p += cap * sizeof(double);
+    }
+    for (int b = 0; b < 2; ++b) {
+        S.pop[b] = (int32_t *)p;
+        p += cap * sizeof(int32_t);
+    }
+    p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+    S.d_h1 = (double *)p;
+    p += (size_t)S.M * S.M * sizeof(double);
+    S.d_eri = (double *)p;
+    S.block = blk;
+    S.cap = cap;
+}
+
+void fill_desc_tables(fciqmc_t *h, int s) {
+    SysHost &S = h->sys[s];
+    SysDesc &d = h->hdesc[s];
+    for (int b = 0; b < 2; ++b) {
+        d.kv[b] = S.kv[b];
+        d.pop[b] = S.pop[b];
+        d.hdiag[b] = S.hd[b];
+    }
+    d.h1 = S.d_h1;
+    d.eri = S.d_eri;
+    d.cap_mask = (uint64_t)(S.cap - 1);
+}
+
+// Grow system s to new_cap, rehashing the live entries of its current buffer.
+int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
+    SysHost &S = h->sys[s];
+    SysDesc &d = h->hdesc[s];
+    void *blk = nullptr;
+    int rc = alloc_tables(h, S, new_cap, &blk);
+    if (rc) return rc == FCIQMC_ENOMEM ? FCIQMC_ECAPACITY : rc;
+    SysHost T = S;   // new pointers
+    carve(T, blk, new_cap);
+    HIP_TRY(hipMemcpyAsync(T.d_h1, S.d_h1, (size_t)integral_bytes(S.M) - 256,
+                           hipMemcpyDeviceToDevice, h->stream));
+    const int cur = d.parity;
+    // the descriptor on the device needs the new mask/d0 for the rehash kernel
+    SysDesc dd = d;
+    dd.cap_mask = (uint64_t)(new_cap - 1);
+    h->hdesc[s] = dd;
+    int r2 = upload_desc(h);
+    if (r2) return r2;
+    HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
+    HIP_TRY(launch_rehash(h->d_desc, s, S.kv[cur], S.pop[cur], S.hd[cur], S.cap, T.kv[0], T.pop[0],
+                          T.hd[0], h->d_err, h->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (err) return set_err(FCIQMC_ECAPACITY, "rehash into the grown table failed");
+    HIP_TRY(hipFree(S.block));
+    carve(S, blk, new_cap);
+    h->hdesc[s].parity = 0;
+    fill_desc_tables(h, s);
+    int r3 = relayout(h);
+    if (r3) return r3;
+    return upload_desc(h);
+}
+
+uint64_t aufbau(const std::vector<double> &h1, int M, int na, int nb) {
+    std::vector<int> order(M);
+    for (int i = 0; i < M; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return h1[a * M + a] < h1[b * M + b]; });
+    uint64_t d = 0;
+    for (int i = 0; i < na; ++i) d |= 1ull << (2 * order[i]);
+    for (int i = 0; i < nb; ++i) d |= 1ull << (2 * order[i] + 1);
+    return d;
+}
+
+// Numbers of symmetry-allowed singles and doubles from det, counted per class.
+void excitation_counts(const SysHost &S, uint64_t det, int64_t &ns, int64_t &nd) {
+    const int nso = 2 * S.M;
+    int n_occ[NCLASS] = {0}, n_emp[NCLASS] = {0};
+    auto cls = [&](int p) { return 2 * (int)S.irrep[p >> 1] + (p & 1); };
+    for (int p = 0; p < nso; ++p) ((det >> p) & 1 ? n_occ : n_emp)[cls(p)]++;
+    ns = 0;
+    for (int c = 0; c < NCLASS; ++c) ns += (int64_t)n_occ[c] * n_emp[c];
+    nd = 0;
+    std::vector<int> occ;
+    for (int p = 0; p < nso; ++p)
+        if ((det >> p) & 1) occ.push_back(p);
+    for (size_t i = 0; i < occ.size(); ++i)
+        for (size_t j = i + 1; j < occ.size(); ++j) {
+            const int p = occ[i], q = occ[j];
+            const int g = S.irrep[p >> 1] ^ S.irrep[q >> 1];
+            if ((p & 1) == (q & 1)) {
+                const int sp = p & 1;
+                for (int ga = 0; ga < 8; ++ga) {
+                    const int gb = ga ^ g;
+                    if (gb < ga) continue;
+                    const int na_ = n_emp[2 * ga + sp], nb_ = n_emp[2 * gb + sp];
+                    nd += (ga == gb) ? (int64_t)na_ * (na_ - 1) / 2 : (int64_t)na_ * nb_;
+                }
+            } else {
+                for (int ga = 0; ga < 8; ++ga)
+                    nd += (int64_t)n_emp[2 * ga + 0] * n_emp[2 * (ga ^ g) + 1];
+            }
+        }
+}
+
+int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
+    if (!ham || !prm) return set_err(FCIQMC_EINVAL, "null hamiltonian or params");
+    if (ham->n_orb < 1 || ham->n_orb > 32)
+        return set_err(FCIQMC_EINVAL, "n_orb must be in 1..32 (2*n_orb <= 64)");
+    if (ham->n_alpha < 0 || ham->n_beta < 0 || ham->n_alpha > ham->n_orb ||
+        ham->n_beta > ham->n_orb || ham->n_alpha + ham->n_beta == 0)
+        return set_err(FCIQMC_EINVAL, "bad electron counts");
+    if (!ham->h1 || !ham->eri) return set_err(FCIQMC_EINVAL, "missing integrals");
+    if (!(prm->tau > 0.0)) return set_err(FCIQMC_EINVAL, "tau must be positive");
+    if (prm->shift_update_every < 1) return set_err(FCIQMC_EINVAL, "shift_update_every must be >= 1");
+    if (ham->p_double > 1.0) return set_err(FCIQMC_EINVAL, "p_double > 1");
+    if (prm->initial_walkers < 0 || prm->initial_walkers > 2147483647)
+        return set_err(FCIQMC_EINVAL, "initial_walkers out of range");
+    if (ham->orb_irrep)
+        for (int i = 0; i < ham->n_orb; ++i)
+            if (ham->orb_irrep[i] > 7) return set_err(FCIQMC_EINVAL, "irrep labels must be 0..7");
+    return 0;
+}
+
+int64_t initial_capacity(const fciqmc_params *prm) {
+    int64_t want = prm->det_capacity > 0 ? prm->det_capacity : 4 * std::max<int64_t>(prm->initial_walkers, 1024);
+    return next_pow2(std::max<int64_t>(want, 4 * CHUNK));
+}
+
+int64_t target_footprint(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
+    const int64_t cap = next_pow2(std::max<int64_t>(2 * std::max<int64_t>(prm->target_walkers, 1), 4 * CHUNK));
+    return table_bytes(cap) + integral_bytes(ham->n_orb);
+}
+
+int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop);
+
+// Admit a system into slot s (slot must be free).
+int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
+    int rc = validate(ham, prm);
+    if (rc) return rc;
+    SysHost &S = h->sys[s];
+    S = SysHost();
+    S.prm = *prm;
+    S.M = ham->n_orb;
+    S.na = ham->n_alpha;
+    S.nb = ham->n_beta;
+    S.N = S.na + S.nb;
+    S.e_core = ham->e_core;
+    S.h1.assign(ham->h1, ham->h1 + (size_t)S.M * S.M);
+    const int64_t np = (int64_t)S.M * (S.M + 1) / 2;
+    S.eri.assign(ham->eri, ham->eri + np * (np + 1) / 2);
+    S.irrep.assign(S.M, 0);
+    if (ham->orb_irrep) S.irrep.assign(ham->orb_irrep, ham->orb_irrep + S.M);
+    const int nso = 2 * S.M;
+    const uint64_t valid = nso == 64 ? ~0ull : ((1ull << nso) - 1ull);
+    if (ham->ref_det) {
+        S.d0 = *ham->ref_det;
+        int a = 0, b = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((S.d0 >> p) & 1) (p & 1 ? b : a)++;
+        if ((S.d0 & ~valid) || a != S.na || b != S.nb)
+            return set_err(FCIQMC_EINVAL, "reference determinant does not match the electron counts");
+    } else {
+        S.d0 = aufbau(S.h1, S.M, S.na, S.nb);
+    }
+    if (ham->p_double >= 0.0) {
+        S.p_double = ham->p_double;
+    } else {
+        int64_t ns, nd;
+        excitation_counts(S, S.d0, ns, nd);
+        S.p_double = (ns + nd) > 0 ? (double)nd / (double)(ns + nd) : 0.0;
+    }
+    S.reserve_bytes = target_footprint(ham, prm);
+    // free-memory admission
+    size_t fr = 0, tot = 0;
+    HIP_TRY(hipMemGetInfo(&fr, &tot));
+    int64_t reserved = 0;
+    for (int t = 0; t < h->max_sys; ++t)
+        if (t != s && h->sys[t].active) reserved += std::max<int64_t>(0, h->sys[t].reserve_bytes - table_bytes(h->sys[t].cap));
+    const int64_t need = S.reserve_bytes;
+    if ((int64_t)fr - reserved < need + (int64_t)(1ull << 30))
+        return set_err(FCIQMC_ENOMEM, "system footprint " + std::to_string(need) +
+                                          " B does not fit in free device memory");
+    const int64_t cap = initial_capacity(prm);
+    void *blk = nullptr;
+    rc = alloc_tables(h, S, cap, &blk);
+    if (rc) return rc;
+    carve(S, blk, cap);
+    HIP_TRY(hipMemcpyAsync(S.d_h1, S.h1.data(), S.h1.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(S.d_eri, S.eri.data(), S.eri.size() * 8, hipMemcpyHostToDevice, h->stream));
+    S.active = true;
+    SysDesc &d = h->hdesc[s];
+    std::memset(&d, 0, sizeof d);
+    d.active = 1;
+    d.M = S.M;
+    d.N = S.N;
+    d.n_so = nso;
+    d.A = prm->shift_update_every;
+    d.n_a = prm->initiator_threshold;
+    d.tau = prm->tau;
+    d.zeta = prm->shift_damping;
+    d.e_core = S.e_core;
+    d.p_double = S.p_double;
+    d.p_single = 1.0 - S.p_double;
+    d.target = prm->target_walkers;
+    d.seed = prm->seed;
+    d.d0 = S.d0;
+    d.valid = valid;
+    for (int p = 0; p < nso; ++p) d.cmask[2 * S.irrep[p >> 1] + (p & 1)] |= 1ull << p;
+    for (int i = 0; i < S.M; ++i) d.irr_packed[i >> 4] |= (uint64_t)S.irrep[i] << (4 * (i & 15));
+    d.shift = prm->initial_shift;
+    fill_desc_tables(h, s);
+    rc = relayout(h);
+    if (rc) return rc;
+    const int64_t n0 = prm->initial_walkers > 0 ? prm->initial_walkers : 10;
+    rc = load_list(h, s, {S.d0}, {(int32_t)n0});
+    if (rc) return rc;
+    S.last.shift = prm->initial_shift;
+    return 0;
+}
+
+// Replace the list of system s by (det, pop); computes E0 on the device.
+int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop) {
+    SysHost &S = h->sys[s];
+    SysDesc &d = h->hdesc[s];
+    const int64_t n = (int64_t)det.size();
+    int64_t need = next_pow2(std::max<int64_t>(4 * CHUNK, 3 * n));
+    if (need > S.cap) {
+        void *blk = nullptr;
+        int rc = alloc_tables(h, S, need, &blk);
+        if (rc) return rc;
+        SysHost T = S;
+        carve(T, blk, need);
+        HIP_TRY(hipMemcpyAsync(T.d_h1, S.h1.data(), S.h1.size() * 8, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(T.d_eri, S.eri.data(), S.eri.size() * 8, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(hipFree(S.block));
+        carve(S, blk, need);
+        fill_desc_tables(h, s);
+        int r = relayout(h);
+        if (r) return r;
+    } else {
+        HIP_TRY(hipMemsetAsync(S.block, 0, (size_t)table_bytes(S.cap), h->stream));
+    }
+    d.parity = 0;
+    d.status = 0;
+    d.spawns = 0;
+    int rc = upload_desc(h);
+    if (rc) return rc;
+    uint64_t *dd = nullptr;
+    int32_t *dp = nullptr;
+    HIP_TRY(hipMalloc(&dd, std::max<int64_t>(n, 1) * 8));
+    HIP_TRY(hipMalloc(&dp, std::max<int64_t>(n, 1) * 4));
+    HIP_TRY(hipMemcpyAsync(dd, det.data(), n * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(dp, pop.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
+    HIP_TRY(launch_load(h->d_desc, s, dd, dp, n, 0, h->d_err, h->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->d_err, 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hipFree(dd);
+    hipFree(dp);
+    if (err) return set_err(FCIQMC_ECAPACITY, "walker list does not fit the table");
+    return 0;
+}
+
+int compute_e0(fciqmc_t *h, int s);
+
+struct Walkers {
+    std::vector<uint64_t> det;
+    std::vector<int32_t> pop;
+};
+
+int export_walkers(fciqmc_t *h, int s, Walkers &w) {
+    SysHost &S = h->sys[s];
+    const int par = h->hdesc[s].parity;
+    uint64_t *od = nullptr;
+    int32_t *op = nullptr;
+    unsigned long long *cnt = nullptr;
+    HIP_TRY(hipMalloc(&od, S.cap * 8));
+    HIP_TRY(hipMalloc(&op, S.cap * 4));
+    HIP_TRY(hipMalloc(&cnt, 8));
+    HIP_TRY(hipMemsetAsync(cnt, 0, 8, h->stream));
+    HIP_TRY(launch_compact(S.kv[par], S.pop[par], S.cap, od, op, cnt, h->stream));
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    std::vector<uint64_t> dv(n);
+    std::vector<int32_t> pv(n);
+    if (n) {
+        HIP_TRY(hipMemcpyAsync(dv.data(), od, n * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(pv.data(), op, n * 4, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    hipFree(od);
+    hipFree(op);
+    hipFree(cnt);
+    std::vector<size_t> idx(n);
+    for (size_t i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return dv[a] < dv[b]; });
+    w.det.resize(n);
+    w.pop.resize(n);
+    for (size_t i = 0; i < n; ++i) {
+        w.det[i] = dv[idx[i]];
+        w.pop[i] = pv[idx[i]];
+    }
+    return 0;
+}
+
+int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
+    SysHost &S = h->sys[s];
+    if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
+    const IterRecord &r = S.last;
+    std::memset(o, 0, sizeof *o);
+    o->iteration = h->hdesc[s].iter;
+    o->n_walkers = r.nw;
+    o->n_dets = r.nd;
+    o->ref_pop = r.c0;
+    o->attempts = r.attempts;
+    o->spawns = r.spawns;
+    o->merged = r.merged;
+    o->aborted = r.aborted;
+    o->total_attempts = S.tot_att;
+    o->total_spawns = S.tot_sp;
+    o->n_samples = (int64_t)S.s_num.size();
+    o->n_var = h->hdesc[s].n_var;
+    o->n_prev = h->hdesc[s].n_prev;
+    o->shift = h->hdesc[s].shift;
+    o->e_ref = S.e0;
+    o->p_double = S.p_double;
+    o->proj_num = r.num;
+    o->e_proj_inst = r.c0 != 0 ? S.e0 + r.num / (double)r.c0 : NAN;
+    double m, e;
+    blocking(S.s_num, &S.s_den, m, e);
+    o->e_proj_mean = S.e0 + m;
+    o->e_proj_err = e;
+    blocking(S.s_shift, nullptr, m, e);
+    o->shift_mean = S.e0 + m;
+    o->shift_err = e;
+    o->ms_last_call = h->ms_last;
+    o->shift_varying = h->hdesc[s].varying;
+    o->status = S.fatal;
+    return 0;
+}
+
+// Statistics of the list as loaded (before any iteration): N_w, N_d, C_0, num.
+int refresh_stats_after_load(fciqmc_t *h, int s, const std::vector<uint64_t> &det,
+                             const std::vector<int32_t> &pop, double num) {
+    SysHost &S = h->sys[s];
+    IterRecord r{};
+    for (size_t i = 0; i < det.size(); ++i) {
+        if (det[i] == S.d0) r.c0 = pop[i];
+        if (pop[i] == 0) continue;
+        r.nw += pop[i] < 0 ? -(int64_t)pop[i] : pop[i];
+        r.nd++;
+    }
+    r.num = num;
+    r.shift = h->hdesc[s].shift;
+    S.last = r;
+    return 0;
+}
+
+int run_iterations(fciqmc_t *h, int L);
+
+int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
+    auto it = h->graphs.find(L);
+    if (it != h->graphs.end()) {
+        *out = it->second;
+        return 0;
+    }
+    EngineArgs a = make_args(h);
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
+    for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->spawn_grid, h->stream, nullptr);
+    HIP_TRY(hipStreamEndCapture(h->stream, &g));
+    hipGraphExec_t ex = nullptr;
+    HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    HIP_TRY(hipGraphDestroy(g));
+    h->graphs[L] = ex;
+    *out = ex;
+    return 0;
+}
+
+// Grow systems whose last iterations came close to filling their table.
+int growth_check(fciqmc_t *h) {
+    for (int s = 0; s < h->max_sys; ++s) {
+        SysHost &S = h->sys[s];
+        if (!S.active || S.fatal) continue;
+        const int64_t occ = S.last.nd + std::max<int64_t>(S.last.spawns, S.last.merged);
+        if (occ * 5 > S.cap * 2) {   // above 40 % load
+            int64_t nc = S.cap;
+            while (occ * 5 > nc * 2) nc <<= 1;
+            int rc = grow_system(h, s, nc);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
+// Launch L iterations (graph or direct), then read records and statuses.
+int run_iterations(fciqmc_t *h, int L) {
+    std::vector<int64_t> before(h->max_sys);
+    for (int s = 0; s < h->max_sys; ++s) before[s] = h->hdesc[s].iter;
+    int rc = upload_desc(h);
+    if (rc) return rc;
+    EngineArgs a = make_args(h);
+    if (h->profiling) {
+        for (int i = 0; i < L; ++i) {
+            launch_iteration(a, h->chunk_alloc, h->spawn_grid, h->stream, h->ev);
+            HIP_TRY(hipEventSynchronize(h->ev[5]));
+            for (int k = 0; k < 5; ++k) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+                h->kms[k] += ms;
+                h->kcount[k]++;
+            }
+        }
+        HIP_TRY(hipGetLastError());
+    } else if (h->use_graph) {
+        hipGraphExec_t ex = nullptr;
+        rc = capture_or_get(h, L, &ex);
+        if (rc) return rc;
+        HIP_TRY(hipGraphLaunch(ex, h->stream));
+    } else {
+        for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->spawn_grid, h->stream, nullptr);
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    rc = download_desc(h);
+    if (rc) return rc;
+    for (int s = 0; s < h->max_sys; ++s) {
+        SysHost &S = h->sys[s];
+        if (!S.active) continue;
+        SysDesc &d = h->hdesc[s];
+        const int64_t n_new = d.iter - before[s];
+        if (n_new > 0) {
+            std::vector<IterRecord> rr(REC_CAP);
+            HIP_TRY(hipMemcpyAsync(rr.data(), h->d_rec + (int64_t)s * REC_CAP,
+                                   sizeof(IterRecord) * REC_CAP, hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            for (int64_t it = before[s] + 1; it <= d.iter; ++it) {
+                const IterRecord &r = rr[it % REC_CAP];
+                S.tot_att += r.attempts;
+                S.tot_sp += r.spawns;
+                if (r.varying && r.iter - r.n_var >= S.prm.avg_start) {
+                    S.s_num.push_back(r.num);
+                    S.s_den.push_back((double)r.c0);
+                    S.s_shift.push_back(r.shift);
+                }
+                S.last = r;
+            }
+        }
+        if (d.status & ST_TABLE_FULL) {
+            d.status &= ~ST_TABLE_FULL;
+            d.spawns = 0;
+            rc = grow_system(h, s, S.cap * 2);
+            if (rc) return rc;
+        }
+        if (d.status) {
+            S.fatal = FCIQMC_EOVERFLOW;
+            return set_err(FCIQMC_EOVERFLOW,
+                           "system " + std::to_string(s) + ": status " + std::to_string(d.status) +
+                               ((d.status & ST_DIED) ? " (walkers died out)" : " (population overflow)"));
+        }
+    }
+    return 0;
+}
+
+int iterate_each(fciqmc_t *h, const std::vector<int64_t> &n) {
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, h->stream));
+    for (int s = 0; s < h->max_sys; ++s)
+        if (h->sys[s].active) h->hdesc[s].stop_at = h->hdesc[s].iter + std::max<int64_t>(n[s], 0);
+    for (;;) {
+        int64_t rem = 0;
+        for (int s = 0; s < h->max_sys; ++s)
+            if (h->sys[s].active && !h->sys[s].fatal)
+                rem = std::max<int64_t>(rem, h->hdesc[s].stop_at - h->hdesc[s].iter);
+        if (rem <= 0) break;
+        int rc = growth_check(h);
+        if (rc) return rc;
+        const int L = (int)std::min<int64_t>(rem, MAX_GRAPH_ITERS);
+        rc = run_iterations(h, L);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipEventRecord(t1, h->stream));
+    HIP_TRY(hipEventSynchronize(t1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+    h->ms_last = ms;
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    return 0;
+}
+
+int create_handle(int max_slots, void *stream, fciqmc_t **out) {
+    fciqmc_t *h = new (std::nothrow) fciqmc_t();
+    if (!h) return set_err(FCIQMC_ENOMEM, "host allocation failed");
+    HIP_TRY(hipGetDevice(&h->dev));
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        HIP_TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+        h->own_stream = true;
+    }
+    h->max_sys = max_slots;
+    h->sys.resize(max_slots);
+    h->hdesc.assign(max_slots, SysDesc{});
+    HIP_TRY(hipMalloc(&h->d_desc, sizeof(SysDesc) * max_slots));
+    HIP_TRY(hipMalloc(&h->d_rec, sizeof(IterRecord) * REC_CAP * max_slots));
+    HIP_TRY(hipMalloc(&h->d_total, sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
+    HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
+    HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
+    for (int k = 0; k < 6; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
+    h->spawn_grid = spawn_grid_size();
+    int rc = upload_desc(h);
+    if (rc) return rc;
+    rc = relayout(h);
+    if (rc) return rc;
+    *out = h;
+    return 0;
+}
+
+}  // namespace
+
+namespace {
+int compute_e0(fciqmc_t *h, int s) {
+    double *d_out = nullptr;
+    HIP_TRY(hipMalloc(&d_out, 8));
+    int rc = upload_desc(h);
+    if (rc) return rc;
+    HIP_TRY(launch_e0(h->d_desc, s, h->sys[s].d0, d_out, h->stream));
+    double e0 = 0;
+    HIP_TRY(hipMemcpyAsync(&e0, d_out, 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hipFree(d_out);
+    h->sys[s].e0 = e0;
+    h->hdesc[s].e0 = e0;
+    return 0;
+}
+
+int admit_full(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
+    int rc = admit(h, s, ham, prm);
+    if (rc) {
+        SysHost &S = h->sys[s];
+        if (S.block) hipFree(S.block);
+        S = SysHost();
+        h->hdesc[s] = SysDesc{};
+        relayout(h);
+        upload_desc(h);
+        return rc;
+    }
+    rc = compute_e0(h, s);
+    if (rc) return rc;
+    const int64_t n0 = prm->initial_walkers > 0 ? prm->initial_walkers : 10;
+    h->sys[s].last = IterRecord{};
+    h->sys[s].last.nw = n0;
+    h->sys[s].last.nd = 1;
+    h->sys[s].last.c0 = n0;
+    h->sys[s].last.shift = prm->initial_shift;
+    return upload_desc(h);
+}
+
+void release(fciqmc_t *h) {
+    if (!h) return;
+    hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    for (auto &S : h->sys)
+        if (S.block) hipFree(S.block);
+    hipFree(h->d_desc);
+    hipFree(h->d_rec);
+    hipFree(h->d_total);
+    hipFree(h->d_nchunks);
+    hipFree(h->d_err);
+    hipFree(h->d_chunk_sys);
+    hipFree(h->d_chunk_local);
+    hipFree(h->d_chunk_nw);
+    hipFree(h->d_chunk_off);
+    hipFree(h->d_chunk_stat);
+    for (auto &e : h->ev)
+        if (e) hipEventDestroy(e);
+    if (h->own_stream) hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int64_t walkers_out(fciqmc_t *h, int s, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap) {
+    if (!h || s < 0 || s >= h->max_sys || !h->sys[s].active)
+        return set_err(FCIQMC_ESTATE, "slot is not active");
+    Walkers w;
+    int rc = export_walkers(h, s, w);
+    if (rc) return rc;
+    const SysHost &S = h->sys[s];
+    const int64_t n = (int64_t)w.det.size();
+    for (int64_t i = 0; i < n && i < cap; ++i) {
+        if (det) det[i] = w.det[i];
+        if (pop) pop[i] = w.pop[i];
+        if (flags) {
+            const int64_t a = w.pop[i] < 0 ? -(int64_t)w.pop[i] : w.pop[i];
+            flags[i] = (a > S.prm.initiator_threshold || w.det[i] == S.d0) ? 1u : 0u;
+        }
+    }
+    return n;
+}
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *fciqmc_last_error(void) { return g_err.c_str(); }
+
+int fciqmc_batch_create(int32_t max_slots, int32_t n, const fciqmc_hamiltonian *hams,
+                        const fciqmc_params *prms, void *hip_stream, fciqmc_t **out) {
+    if (!out) return set_err(FCIQMC_EINVAL, "null output handle");
+    *out = nullptr;
+    if (max_slots < 1 || n < 0 || n > max_slots) return set_err(FCIQMC_EINVAL, "bad slot counts");
+    if (n > 0 && (!hams || !prms)) return set_err(FCIQMC_EINVAL, "null hamiltonians or params");
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(&hams[i], &prms[i]);
+        if (rc) return rc;
+    }
+    fciqmc_t *h = nullptr;
+    int rc = create_handle(max_slots, hip_stream, &h);
+    if (rc) {
+        release(h);
+        return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        rc = admit_full(h, i, &hams[i], &prms[i]);
+        if (rc) {
+            std::string keep = g_err;
+            release(h);
+            g_err = keep;
+            return rc;
+        }
+    }
+    *out = h;
+    return 0;
+}
+
+int fciqmc_init(const fciqmc_hamiltonian *ham, const fciqmc_params *prm, void *hip_stream,
+                fciqmc_t **out) {
+    return fciqmc_batch_create(1, 1, ham, prm, hip_stream, out);
+}
+
+int fciqmc_free(fciqmc_t *h) {
+    release(h);
+    return 0;
+}
+
+int fciqmc_iterate(fciqmc_t *h, int32_t n_iterations) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    if (n_iterations < 0) return set_err(FCIQMC_EINVAL, "negative iteration count");
+    std::vector<int64_t> n(h->max_sys, n_iterations);
+    return iterate_each(h, n);
+}
+
+int fciqmc_batch_iterate(fciqmc_t *h, int32_t n_iterations) { return fciqmc_iterate(h, n_iterations); }
+
+int fciqmc_batch_iterate_each(fciqmc_t *h, const int32_t *n_iter) {
+    if (!h || !n_iter) return set_err(FCIQMC_EINVAL, "null argument");
+    std::vector<int64_t> n(h->max_sys);
+    for (int s = 0; s < h->max_sys; ++s) n[s] = n_iter[s];
+    return iterate_each(h, n);
+}
+
+int fciqmc_estimators(fciqmc_t *h, fciqmc_estimates *out) {
+    if (!h || !out) return set_err(FCIQMC_EINVAL, "null argument");
+    return fill_estimates(h, 0, out);
+}
+
+int fciqmc_batch_slot_estimators(fciqmc_t *h, int32_t slot, fciqmc_estimates *out) {
+    if (!h || !out || slot < 0 || slot >= h->max_sys) return set_err(FCIQMC_EINVAL, "bad argument");
+    return fill_estimates(h, slot, out);
+}
+
+int64_t fciqmc_walkers(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    return walkers_out(h, 0, det, pop, flags, cap);
+}
+
+int64_t fciqmc_batch_slot_walkers(fciqmc_t *h, int32_t slot, uint64_t *det, int32_t *pop,
+                                  uint32_t *flags, int64_t cap) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    return walkers_out(h, slot, det, pop, flags, cap);
+}
+
+int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, int64_t n,
+                        int64_t iteration, double shift, int64_t n_prev, int32_t varying,
+                        int64_t n_var) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    if (n < 0 || (n > 0 && (!det || !pop)) || iteration < 0)
+        return set_err(FCIQMC_EINVAL, "bad walker list");
+    const int s = 0;
+    SysHost &S = h->sys[s];
+    if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
+    const uint64_t valid = 2 * S.M == 64 ? ~0ull : ((1ull << (2 * S.M)) - 1ull);
+    std::vector<std::pair<uint64_t, int32_t>> v;
+    v.reserve(n + 1);
+    bool have_ref = false;
+    for (int64_t i = 0; i < n; ++i) {
+        if (pop[i] == 0) continue;
+        const uint64_t d = det[i];
+        int a = 0, b = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((d >> p) & 1) (p & 1 ? b : a)++;
+        if ((d & ~valid) || a != S.na || b != S.nb)
+            return set_err(FCIQMC_EINVAL, "determinant with wrong electron counts in walker list");
+        if (pop[i] == INT32_MIN) return set_err(FCIQMC_EINVAL, "population out of range");
+        if (d == S.d0) have_ref = true;
+        v.emplace_back(d, pop[i]);
+    }
+    if (!have_ref) v.emplace_back(S.d0, 0);
+    std::sort(v.begin(), v.end());
+    for (size_t i = 1; i < v.size(); ++i)
+        if (v[i].first == v[i - 1].first)
+            return set_err(FCIQMC_EINVAL, "duplicate determinant in walker list");
+    std::vector<uint64_t> dv(v.size());
+    std::vector<int32_t> pv(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        dv[i] = v[i].first;
+        pv[i] = v[i].second;
+    }
+    SysDesc &d = h->hdesc[s];
+    d.iter = iteration;
+    d.shift = shift;
+    d.n_prev = n_prev;
+    d.varying = varying ? 1 : 0;
+    d.n_var = n_var;
+    d.spawns = 0;
+    int rc = load_list(h, s, dv, pv);
+    if (rc) return rc;
+    S.s_num.clear();
+    S.s_den.clear();
+    S.s_shift.clear();
+    S.fatal = 0;
+    refresh_stats_after_load(h, s, dv, pv, NAN);
+    return upload_desc(h);
+}
+
+int fciqmc_set_shift(fciqmc_t *h, double shift, int32_t varying) {
+    if (!h || !h->sys[0].active) return set_err(FCIQMC_EINVAL, "null handle");
+    SysDesc &d = h->hdesc[0];
+    d.shift = shift;
+    d.varying = varying ? 1 : 0;
+    if (varying) {
+        d.n_prev = h->sys[0].last.nw;
+        d.n_var = d.iter;
+    }
+    h->sys[0].s_num.clear();
+    h->sys[0].s_den.clear();
+    h->sys[0].s_shift.clear();
+    return upload_desc(h);
+}
+
+int fciqmc_batch_admit(fciqmc_t *h, const fciqmc_hamiltonian *ham, const fciqmc_params *prm,
+                       int32_t *slot) {
+    if (!h || !slot) return set_err(FCIQMC_EINVAL, "null argument");
+    int s = -1;
+    for (int i = 0; i < h->max_sys; ++i)
+        if (!h->sys[i].active) {
+            s = i;
+            break;
+        }
+    if (s < 0) return set_err(FCIQMC_ESTATE, "no free slot");
+    int rc = admit_full(h, s, ham, prm);
+    if (rc) return rc;
+    *slot = s;
+    return 0;
+}
+
+int fciqmc_batch_retire(fciqmc_t *h, int32_t slot) {
+    if (!h || slot < 0 || slot >= h->max_sys || !h->sys[slot].active)
+        return set_err(FCIQMC_ESTATE, "slot is not active");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    SysHost &S = h->sys[slot];
+    if (S.block) HIP_TRY(hipFree(S.block));
+    S = SysHost();
+    h->hdesc[slot] = SysDesc{};
+    int rc = relayout(h);
+    if (rc) return rc;
+    return upload_desc(h);
+}
+
+int32_t fciqmc_batch_active(fciqmc_t *h) {
+    if (!h) return 0;
+    int32_t n = 0;
+    for (auto &S : h->sys) n += S.active ? 1 : 0;
+    return n;
+}
+
+int64_t fciqmc_footprint_bytes(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
+    if (!ham || !prm) return set_err(FCIQMC_EINVAL, "null argument");
+    return target_footprint(ham, prm);
+}
+
+int fciqmc_set_profiling(fciqmc_t *h, int32_t on) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    h->profiling = on != 0;
+    for (int k = 0; k < 5; ++k) {
+        h->kms[k] = 0.0;
+        h->kcount[k] = 0;
+    }
+    return 0;
+}
+
+int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]) {
+    if (!h || !ms || !counts) return set_err(FCIQMC_EINVAL, "null argument");
+    for (int k = 0; k < 5; ++k) {
+        ms[k] = h->kms[k];
+        counts[k] = h->kcount[k];
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,769 @@
+// HIP kernels of the FCIQMC iteration (Booth, Smart & Alavi, arXiv:1305.6981)
+// for gfx950. One iteration of every active system is five launches:
+//
+//   k_chunk_sum   sum |C| over each 1024-slot chunk of the current main tables
+//   k_scan        exclusive scan of the chunk sums -> global attempt offsets
+//   k_spawn       one spawning attempt per walker (Sec. 2, Eq. pspawn): random
+//                 excitation with its pgen (Sec. 5), Slater-Condon element,
+//                 acceptance; accepted walkers are summed straight into the
+//                 target determinant's slot of the main table (the merge of
+//                 equal spawned determinants of Sec. 4.1, done by atomics)
+//   k_post        per slot: death/cloning (Eq. pdeath), annihilation of the
+//                 arrived walkers with the initiator test for determinants that
+//                 are empty after death, diagonal element for new determinants
+//                 (Sec. 4.2); survivors are rehashed into the other buffer;
+//                 estimator partial sums (Eq. ProjE)
+//   k_finalize    per system: fixed-order reduction of the partial sums, the
+//                 shift update, the per-iteration record
+//
+// All floating-point decisions follow the same operation order as the CPU
+// oracle and are compiled with -ffp-contract=off.
+#include "engine.h"
+
+namespace fq {
+
+// ---------------------------------------------------------------------------
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// Counter (lo32(D), hi32(D), k, ((iter mod 2^24) << 8) | block), key = seed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ void draw2(uint64_t seed, uint64_t det, uint32_t k, int64_t iter,
+                                      uint32_t block, uint64_t &x0, uint64_t &x1) {
+    const uint4 ctr = make_uint4((uint32_t)det, (uint32_t)(det >> 32), k,
+                                 ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block);
+    const uint4 w = philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    x0 = ((uint64_t)w.y << 32) | (uint64_t)w.x;
+    x1 = ((uint64_t)w.w << 32) | (uint64_t)w.z;
+}
+
+__device__ __forceinline__ double u01(uint64_t x) {
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ uint32_t pick(uint64_t x, uint32_t n) {
+    return (uint32_t)__umul64hi(x, (uint64_t)n);
+}
+
+// Position of the k-th (0-based) set bit of x, by halving with popcounts.
+__device__ __forceinline__ int select_bit(uint64_t x, uint32_t k) {
+    int pos = 0;
+    uint32_t c = (uint32_t)__popc((uint32_t)x);
+    if (k >= c) {
+        k -= c;
+        x >>= 32;
+        pos = 32;
+    }
+    uint32_t w = (uint32_t)x;
+    c = (uint32_t)__popc(w & 0xFFFFu);
+    if (k >= c) { k -= c; w >>= 16; pos += 16; }
+    c = (uint32_t)__popc(w & 0xFFu);
+    if (k >= c) { k -= c; w >>= 8; pos += 8; }
+    c = (uint32_t)__popc(w & 0xFu);
+    if (k >= c) { k -= c; w >>= 4; pos += 4; }
+    c = (uint32_t)__popc(w & 0x3u);
+    if (k >= c) { k -= c; w >>= 2; pos += 2; }
+    c = w & 1u;
+    if (k >= c) pos += 1;
+    return pos;
+}
+
+// 64-bit finaliser of MurmurHash3 (public domain): table placement only.
+__device__ __forceinline__ uint64_t mix64(uint64_t h) {
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// Hamiltonian (spin orbital p = 2 s + sigma).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int tri(int i, int j) {
+    return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+__device__ __forceinline__ double eri_so(const SysDesc &d, int p, int q, int r, int s) {
+    if (((p ^ q) | (r ^ s)) & 1) return 0.0;
+    const int a = tri(p >> 1, q >> 1), b = tri(r >> 1, s >> 1);
+    return d.eri[a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a];
+}
+
+__device__ __forceinline__ double h_so(const SysDesc &d, int p, int q) {
+    if ((p ^ q) & 1) return 0.0;
+    return d.h1[(p >> 1) * d.M + (q >> 1)];
+}
+
+__device__ __forceinline__ int irrep_of(const SysDesc &d, int s) {
+    return (int)((d.irr_packed[s >> 4] >> (4 * (s & 15))) & 0xFull);
+}
+
+__device__ __forceinline__ int class_of(const SysDesc &d, int p) {
+    return 2 * irrep_of(d, p >> 1) + (p & 1);
+}
+
+// Parity of the number of occupied orbitals strictly between p and a.
+__device__ __forceinline__ int between_parity(uint64_t det, int p, int a) {
+    const int lo = p < a ? p : a, hi = p < a ? a : p;
+    const uint64_t m = ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+    return __popcll(det & m) & 1;
+}
+
+__device__ double hdiag_of(const SysDesc &d, uint64_t det) {
+    double acc = d.e_core;
+    for (uint64_t m = det; m; m &= m - 1) {
+        const int p = __builtin_ctzll(m);
+        acc = acc + h_so(d, p, p);
+    }
+    for (uint64_t m1 = det; m1; m1 &= m1 - 1) {
+        const int p = __builtin_ctzll(m1);
+        for (uint64_t m2 = m1 & (m1 - 1); m2; m2 &= m2 - 1) {
+            const int q = __builtin_ctzll(m2);
+            acc = acc + (eri_so(d, p, p, q, q) - eri_so(d, p, q, q, p));
+        }
+    }
+    return acc;
+}
+
+__device__ double hel_single(const SysDesc &d, uint64_t det, int p, int a) {
+    double acc = h_so(d, p, a);
+    for (uint64_t m = det & ~(1ull << p); m; m &= m - 1) {
+        const int q = __builtin_ctzll(m);
+        acc = acc + (eri_so(d, p, a, q, q) - eri_so(d, p, q, q, a));
+    }
+    return between_parity(det, p, a) ? -acc : acc;
+}
+
+// p < q occupied, a, b empty. Pairing: unlike spins -> a' carries p's spin;
+// like spins -> a' = min(a, b). Sign: q -> b' on det, then p -> a'.
+__device__ double hel_double(const SysDesc &d, uint64_t det, int p, int q, int a, int b) {
+    int ap, bp;
+    if ((p ^ q) & 1) {
+        const bool a_with_p = ((a ^ p) & 1) == 0;
+        ap = a_with_p ? a : b;
+        bp = a_with_p ? b : a;
+    } else {
+        ap = a < b ? a : b;
+        bp = a < b ? b : a;
+    }
+    int par = between_parity(det, q, bp);
+    const uint64_t d1 = (det & ~(1ull << q)) | (1ull << bp);
+    par ^= between_parity(d1, p, ap);
+    const double v = eri_so(d, p, ap, q, bp) - eri_so(d, p, bp, q, ap);
+    return par ? -v : v;
+}
+
+// <det|H|d0> for det != d0 within two excitations of d0 (d0 is the source).
+__device__ double hel_to_ref(const SysDesc &d, uint64_t det) {
+    const uint64_t from = d.d0 & ~det, to = det & ~d.d0;
+    const int nd = __popcll(from);
+    if (nd == 1) return hel_single(d, d.d0, __builtin_ctzll(from), __builtin_ctzll(to));
+    const int p = __builtin_ctzll(from), q = 63 - __builtin_clzll(from);
+    const int a = __builtin_ctzll(to), b = 63 - __builtin_clzll(to);
+    return hel_double(d, d.d0, p, q, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// Excitation generation (Sec. 5). Symmetry classes are (irrep, spin) with
+// class id 2*irrep + spin; cmask[c] holds the spin orbitals of class c.
+// Returns false for a null excitation.
+// ---------------------------------------------------------------------------
+struct Excit {
+    uint64_t det;
+    double pgen;
+    double hel;
+};
+
+constexpr uint64_t EVEN_BITS = 0x5555555555555555ull;
+constexpr uint64_t ODD_BITS = 0xAAAAAAAAAAAAAAAAull;
+
+__device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1, uint64_t x2,
+                       uint64_t x3, Excit &ex) {
+    const uint64_t emp = ~det & d.valid;
+    const int N = d.N;
+    if (!(u01(x0) < d.p_double)) {
+        // Single (Sec. 5.1): renormalise over electrons that have an allowed target.
+        uint64_t movable = 0;
+#pragma unroll
+        for (int c = 0; c < NCLASS; ++c) {
+            const uint64_t cm = d.cmask[c];
+            if (emp & cm) movable |= det & cm;
+        }
+        const uint32_t nmov = (uint32_t)__popcll(movable);
+        if (nmov == 0) return false;
+        const int p = select_bit(movable, pick(x1, nmov));
+        const uint64_t tg = emp & d.cmask[class_of(d, p)];
+        const uint32_t nal = (uint32_t)__popcll(tg);
+        const int a = select_bit(tg, pick(x2, nal));
+        ex.det = det ^ (1ull << p) ^ (1ull << a);
+        ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
+        ex.hel = hel_single(d, det, p, a);
+        return true;
+    }
+    // Double (Sec. 5.2): a unique pair by inverse triangular indexing.
+    if (N < 2) return false;
+    const uint64_t npairs = (uint64_t)N * (uint64_t)(N - 1) / 2;
+    const int64_t K = (int64_t)__umul64hi(x1, npairs);
+    int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)K)) * 0.5);
+    while ((int64_t)j * (j - 1) / 2 > K) --j;
+    while ((int64_t)(j + 1) * j / 2 <= K) ++j;
+    const int i = (int)(K - (int64_t)j * (j - 1) / 2);
+    const int p = select_bit(det, (uint32_t)i), q = select_bit(det, (uint32_t)j);
+    const bool same = ((p ^ q) & 1) == 0;
+    const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
+    const int gpq = irrep_of(d, p >> 1) ^ irrep_of(d, q >> 1);
+    // a orbitals whose partner class (Eq. sym1 plus spin) has an empty orbital besides a.
+    uint64_t allowed = 0;
+#pragma unroll
+    for (int c = 0; c < NCLASS; ++c) {
+        const uint64_t memb = A & d.cmask[c];
+        if (!memb) continue;
+        const int sb = same ? (p & 1) : 1 - (c & 1);
+        const int pc = 2 * (gpq ^ (c >> 1)) + sb;
+        const int nb = __popcll(emp & d.cmask[pc]) - (pc == c ? 1 : 0);
+        if (nb > 0) allowed |= memb;
+    }
+    const uint32_t nal = (uint32_t)__popcll(allowed);
+    if (nal == 0) return false;
+    const int a = select_bit(allowed, pick(x2, nal));
+    const int ca = class_of(d, a);
+    const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
+    const uint64_t bset = emp & d.cmask[pca] & ~(1ull << a);
+    const uint32_t nba = (uint32_t)__popcll(bset);
+    const int b = select_bit(bset, pick(x3, nba));
+    const int cb = class_of(d, b);
+    const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
+    const int nbb = __popcll(emp & d.cmask[pcb]) - (pcb == cb ? 1 : 0);
+    ex.det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
+    ex.pgen = (2.0 * d.p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
+              (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
+    ex.hel = hel_double(d, det, p, q, a, b);
+    return true;
+}
+
+// Natural log for the shift update: x = m 2^e with m in (1/sqrt2, sqrt2],
+// ln x = e ln2 + 2 atanh((m-1)/(m+1)), the atanh series summed by Horner's
+// rule through the z^25 term. Fixed operation order (no contraction), so any
+// IEEE-double implementation of the same method returns the same bits.
+__device__ double shift_log(double x) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7FFull) - 1023;
+    double m = __longlong_as_double((long long)((bits & 0x000FFFFFFFFFFFFFull) |
+                                                0x3FF0000000000000ull));
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double z = (m - 1.0) / (m + 1.0);
+    const double z2 = z * z;
+    double sum = 1.0 / 27.0;
+    for (int k = 25; k >= 1; k -= 2) sum = sum * z2 + 1.0 / (double)k;
+    return (double)e * 0.6931471805599453 + 2.0 * z * sum;
+}
+
+__device__ __forceinline__ bool participating(const SysDesc &d) {
+    return d.active && d.status == 0 && d.iter < d.stop_at;
+}
+
+// ---------------------------------------------------------------------------
+// Block reductions (256 threads, fixed order -> deterministic).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) sh[t] = sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    const T r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// K1: chunk sums of |C| on the current buffer.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a) {
+    __shared__ unsigned long long sh[256];
+    const int64_t nch = *a.nchunks;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int s = a.chunk_sys[c];
+        unsigned long long sum = 0;
+        if (s >= 0) {
+            const SysDesc &d = a.desc[s];
+            if (participating(d)) {
+                const int32_t *pop = d.pop[d.parity] + (int64_t)a.chunk_local[c] * CHUNK;
+                for (int i = threadIdx.x; i < CHUNK; i += 256) {
+                    const int32_t v = pop[i];
+                    sum += (unsigned long long)(v < 0 ? -(int64_t)v : (int64_t)v);
+                }
+            }
+        }
+        sum = block_sum(sum, sh);
+        if (threadIdx.x == 0) a.chunk_nw[c] = sum;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: exclusive scan of the chunk sums (one workgroup).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
+    __shared__ unsigned long long part[1024];
+    const int64_t n = *a.nchunks;
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b = t * per, e = (b + per < n) ? b + per : n;
+    unsigned long long s = 0;
+    for (int64_t i = b; i < e; ++i) s += a.chunk_nw[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = part[t] - s;  // exclusive
+    for (int64_t i = b; i < e; ++i) {
+        const unsigned long long v = a.chunk_nw[i];
+        a.chunk_off[i] = run;
+        run += v;
+    }
+    if (t == 1023) *a.total = part[1023];
+}
+
+// ---------------------------------------------------------------------------
+// K3: spawning. Attempts are numbered globally; a workgroup takes a tile of
+// consecutive attempts, scans the pops of the chunk(s) covering it in LDS and
+// maps attempt t to (slot, walker ordinal k).
+// ---------------------------------------------------------------------------
+constexpr int SPAWN_TILE = 1024;
+
+__device__ __forceinline__ bool table_add(Slot *kv, uint64_t mask, uint64_t key, int32_t v,
+                                          bool init) {
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t n = 0; n <= mask; ++n) {
+        uint64_t cur = __hip_atomic_load(&kv[h].det, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == 0) {
+            cur = atomicCAS((unsigned long long *)&kv[h].det, 0ull, (unsigned long long)key);
+            if (cur == 0) cur = key;
+        }
+        if (cur == key) {
+            atomicAdd(&kv[h].spop, v);
+            if (init && __hip_atomic_load(&kv[h].sflag, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                atomicOr(&kv[h].sflag, 1u);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
+    __shared__ unsigned long long s_incl[CHUNK];
+    __shared__ int32_t s_pop[CHUNK];
+    __shared__ unsigned long long s_part[256];
+    __shared__ long long s_c;
+    const unsigned long long total = *a.total;
+    const int64_t nch = *a.nchunks;
+    const int t = threadIdx.x;
+    for (unsigned long long t0 = (unsigned long long)blockIdx.x * SPAWN_TILE; t0 < total;
+         t0 += (unsigned long long)gridDim.x * SPAWN_TILE) {
+        const unsigned long long t1 = (t0 + SPAWN_TILE < total) ? t0 + SPAWN_TILE : total;
+        if (t == 0) {
+            int64_t lo = 0, hi = nch;  // first chunk with offset > t0
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (a.chunk_off[mid] <= t0) lo = mid + 1;
+                else hi = mid;
+            }
+            s_c = lo - 1;
+        }
+        __syncthreads();
+        int64_t c = s_c;
+        __syncthreads();
+        while (c < nch) {
+            const unsigned long long off_c = a.chunk_off[c];
+            if (off_c >= t1) break;
+            const unsigned long long nw_c = a.chunk_nw[c];
+            if (nw_c == 0) {
+                ++c;
+                continue;
+            }
+            const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
+            const SysDesc &d = a.desc[s];
+            const int par = d.parity;
+            const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
+            const Slot *kvc = d.kv[par] + base;
+            const int32_t *popc = d.pop[par] + base;
+            // LDS scan of |C| over the chunk: 4 consecutive slots per thread.
+            unsigned long long loc[4], run = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t v = popc[4 * t + u];
+                s_pop[4 * t + u] = v;
+                run += (unsigned long long)(v < 0 ? -(int64_t)v : (int64_t)v);
+                loc[u] = run;
+            }
+            s_part[t] = run;
+            __syncthreads();
+            for (int o = 1; o < 256; o <<= 1) {
+                const unsigned long long v = t >= o ? s_part[t - o] : 0ull;
+                __syncthreads();
+                s_part[t] += v;
+                __syncthreads();
+            }
+            const unsigned long long before = s_part[t] - run;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s_incl[4 * t + u] = before + loc[u];
+            __syncthreads();
+            const unsigned long long lo_t = t0 > off_c ? t0 : off_c;
+            const unsigned long long hi_t = (t1 < off_c + nw_c) ? t1 : off_c + nw_c;
+            const Slot *kvn = d.kv[par];
+            unsigned long long spawned = 0;
+            for (unsigned long long at = lo_t + t; at < hi_t; at += 256) {
+                const unsigned long long local = at - off_c;
+                int lo = 0, hi = CHUNK - 1;  // first slot with inclusive sum > local
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_incl[mid] > local) hi = mid;
+                    else lo = mid + 1;
+                }
+                const int32_t C = s_pop[lo];
+                const unsigned long long excl = lo ? s_incl[lo - 1] : 0ull;
+                const uint32_t k = (uint32_t)(local - excl);
+                const uint64_t D = kvc[lo].det;
+                const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
+                const bool init = absC > d.n_a || D == d.d0;
+                uint64_t x0, x1, x2, x3;
+                draw2(d.seed, D, k, d.iter, 0u, x0, x1);
+                draw2(d.seed, D, k, d.iter, 1u, x2, x3);
+                Excit ex;
+                if (!excite(d, D, x0, x1, x2, x3, ex)) continue;
+                if (ex.hel == 0.0) continue;
+                uint64_t x4, x5;
+                draw2(d.seed, D, k, d.iter, 2u, x4, x5);
+                const double pr = (d.tau * fabs(ex.hel)) / ex.pgen;
+                const double fl = floor(pr);
+                if (fl > 1073741824.0) {
+                    atomicOr(&a.desc[s].status, ST_SPAWN_OVERFLOW);
+                    continue;
+                }
+                const int32_t m = (int32_t)fl + (u01(x4) < pr - fl ? 1 : 0);
+                if (m == 0) continue;
+                const int32_t v = ((C > 0) == (ex.hel > 0.0)) ? -m : m;
+                if (!table_add(const_cast<Slot *>(kvn), d.cap_mask, ex.det, v, init))
+                    atomicOr(&a.desc[s].status, ST_TABLE_FULL);
+                ++spawned;
+            }
+            // one atomic per wavefront for the spawn counter
+            unsigned long long ws = spawned;
+            for (int o = 32; o > 0; o >>= 1) ws += __shfl_down(ws, o, 64);
+            if ((t & 63) == 0 && ws) atomicAdd(&a.desc[s].spawns, ws);
+            __syncthreads();
+            ++c;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4: death, annihilation and initiator test per slot; survivors are inserted
+// into the other buffer; the current slot is cleared; estimator partials.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t insert_unique(Slot *kv, uint64_t mask, uint64_t key) {
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t n = 0; n <= mask; ++n) {
+        const unsigned long long old =
+            atomicCAS((unsigned long long *)&kv[h].det, 0ull, (unsigned long long)key);
+        if (old == 0ull) return (int64_t)h;
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
+__global__ __launch_bounds__(256) void k_post(EngineArgs a) {
+    __shared__ long long shi[256];
+    __shared__ double shd[256];
+    const int64_t nch = *a.nchunks;
+    const int t = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int s = a.chunk_sys[c];
+        int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0;
+        double num = 0.0;
+        bool live = false;
+        if (s >= 0) live = participating(a.desc[s]);
+        if (live) {
+            const SysDesc &d = a.desc[s];
+            const int cur = d.parity, nxt = cur ^ 1;
+            const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
+            Slot *kv = d.kv[cur] + base;
+            int32_t *pp = d.pop[cur] + base;
+            const double *hh = d.hdiag[cur] + base;
+            for (int i = t; i < CHUNK; i += 256) {
+                const Slot sl = kv[i];
+                if (sl.det == 0) continue;
+                const uint64_t D = sl.det;
+                const int32_t p = pp[i];
+                double hd = hh[i];
+                int64_t pd = p;
+                if (p != 0) {
+                    // Eq. pdeath, one stochastic rounding for the whole determinant.
+                    uint64_t xd, xu;
+                    draw2(d.seed, D, 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
+                    const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
+                    const double dv = ((hd - d.e0) - d.shift) * d.tau * (double)absC;
+                    const double ad = fabs(dv);
+                    const double fl = floor(ad);
+                    if (fl > 1073741824.0) {
+                        atomicOr(&a.desc[s].status, ST_POP_OVERFLOW);
+                        continue;
+                    }
+                    const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
+                    pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
+                }
+                const bool present = pd != 0 || D == d.d0;
+                const int64_t sp = sl.spop;
+                int64_t np;
+                if (present) {
+                    np = pd + sp;
+                } else if (sp != 0 && sl.sflag) {
+                    np = sp;
+                } else {
+                    np = 0;
+                    if (sp != 0) aborted += sp < 0 ? -sp : sp;
+                }
+                if (sp != 0) ++merged;
+                if (np > 2147483647ll || np < -2147483647ll) {
+                    atomicOr(&a.desc[s].status, ST_POP_OVERFLOW);
+                    np = 0;
+                }
+                if (np != 0 || D == d.d0) {
+                    if (p == 0 && D != d.d0) hd = hdiag_of(d, D);  // newly occupied
+                    const int64_t j = insert_unique(d.kv[nxt], d.cap_mask, D);
+                    if (j >= 0) {
+                        d.pop[nxt][j] = (int32_t)np;
+                        d.hdiag[nxt][j] = hd;
+                    } else {
+                        atomicOr(&a.desc[s].status, ST_TABLE_FULL);
+                    }
+                }
+                kv[i] = Slot{0ull, 0, 0u};
+                pp[i] = 0;
+                if (D == d.d0) c0 = np;
+                if (np != 0) {
+                    nw += np < 0 ? -np : np;
+                    ++nd;
+                    if (D != d.d0 && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
+                }
+            }
+        }
+        nw = block_sum((long long)nw, shi);
+        nd = block_sum((long long)nd, shi);
+        c0 = block_sum((long long)c0, shi);
+        merged = block_sum((long long)merged, shi);
+        aborted = block_sum((long long)aborted, shi);
+        num = block_sum(num, shd);
+        if (t == 0) a.chunk_stat[c] = ChunkStat{nw, nd, c0, merged, aborted, num};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K5: per-system reduction, record, shift update (one workgroup per system).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
+    __shared__ long long shi[256];
+    __shared__ double shd[256];
+    const int s = blockIdx.x;
+    if (s >= a.max_sys) return;
+    SysDesc &d = a.desc[s];
+    if (!participating(d)) return;   // uniform across the workgroup
+    const int t = threadIdx.x;
+    int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0;
+    double num = 0.0;
+    for (int64_t i = t; i < d.nchunks; i += 256) {
+        const ChunkStat cs = a.chunk_stat[d.gchunk0 + i];
+        nw += cs.nw;
+        nd += cs.nd;
+        c0 += cs.c0;
+        merged += cs.merged;
+        aborted += cs.aborted;
+        num = num + cs.num;
+        att += (int64_t)a.chunk_nw[d.gchunk0 + i];
+    }
+    nw = block_sum((long long)nw, shi);
+    nd = block_sum((long long)nd, shi);
+    c0 = block_sum((long long)c0, shi);
+    merged = block_sum((long long)merged, shi);
+    aborted = block_sum((long long)aborted, shi);
+    att = block_sum((long long)att, shi);
+    num = block_sum(num, shd);
+    if (t == 0) {
+        const int64_t done = d.iter + 1;
+        if (d.status == 0) {
+            if (done % d.A == 0) {
+                if (!d.varying) {
+                    if (nw >= d.target) {
+                        d.varying = 1;
+                        d.n_prev = nw;
+                        d.n_var = done;
+                    }
+                } else {
+                    d.shift = d.shift - (d.zeta / ((double)d.A * d.tau)) *
+                                            shift_log((double)nw / (double)d.n_prev);
+                    d.n_prev = nw;
+                }
+            }
+            if (nw == 0) d.status |= ST_DIED;
+        }
+        IterRecord r;
+        r.iter = done;
+        r.nw = nw;
+        r.nd = nd;
+        r.c0 = c0;
+        r.attempts = att;
+        r.spawns = (int64_t)d.spawns;
+        r.merged = merged;
+        r.aborted = aborted;
+        r.n_var = d.n_var;
+        r.n_prev = d.n_prev;
+        r.num = num;
+        r.shift = d.shift;
+        r.varying = d.varying;
+        r.status = (int32_t)d.status;
+        a.rec[(int64_t)s * REC_CAP + (done % REC_CAP)] = r;
+        d.spawns = 0ull;
+        d.iter = done;
+        d.parity ^= 1;
+    }
+}
+
+void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int spawn_grid, hipStream_t s,
+                      hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)chunk_grid), dim3(256), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[3], s);
+    hipLaunchKernelGGL(k_post, dim3((unsigned)chunk_grid), dim3(256), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[4], s);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(256), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[5], s);
+}
+
+// ---------------------------------------------------------------------------
+// Loading a walker list, rehashing into a grown table, exporting.
+// ---------------------------------------------------------------------------
+__global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const int32_t *pop,
+                       int64_t n, int32_t par, uint32_t *err) {
+    const SysDesc &d = desc[sys];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t D = det[i];
+        const int64_t j = insert_unique(d.kv[par], d.cap_mask, D);
+        if (j < 0) {
+            atomicOr(err, 1u);
+            continue;
+        }
+        d.pop[par][j] = pop[i];
+        d.hdiag[par][j] = hdiag_of(d, D);
+    }
+}
+
+__global__ void k_rehash(SysDesc *desc, int32_t sys, const Slot *skv, const int32_t *spop,
+                         const double *shd, int64_t scap, Slot *dkv, int32_t *dpop, double *dhd,
+                         uint32_t *err) {
+    const SysDesc &d = desc[sys];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < scap;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t D = skv[i].det;
+        if (D == 0) continue;
+        const int32_t p = spop[i];
+        if (p == 0 && D != d.d0) continue;
+        const int64_t j = insert_unique(dkv, d.cap_mask, D);
+        if (j < 0) {
+            atomicOr(err, 1u);
+            continue;
+        }
+        dpop[j] = p;
+        dhd[j] = shd[i];
+    }
+}
+
+__global__ void k_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint64_t *odet,
+                          int32_t *opop, unsigned long long *count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t D = kv[i].det;
+        const int32_t p = pop[i];
+        if (D == 0 || p == 0) continue;
+        const unsigned long long j = atomicAdd(count, 1ull);
+        odet[j] = D;
+        opop[j] = p;
+    }
+}
+
+hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
+                       int64_t n, int32_t parity, uint32_t *d_err, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_load, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, d_desc,
+                       sys, det, pop, n, parity, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const Slot *src_kv, const int32_t *src_pop,
+                         const double *src_hd, int64_t src_cap, Slot *dst_kv, int32_t *dst_pop,
+                         double *dst_hd, uint32_t *d_err, hipStream_t s) {
+    const int64_t g = (src_cap + 255) / 256;
+    hipLaunchKernelGGL(k_rehash, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, d_desc,
+                       sys, src_kv, src_pop, src_hd, src_cap, dst_kv, dst_pop, dst_hd, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint64_t *out_det,
+                          int32_t *out_pop, unsigned long long *count, hipStream_t s) {
+    const int64_t g = (cap + 255) / 256;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, kv,
+                       pop, cap, out_det, out_pop, count);
+    return hipGetLastError();
+}
+
+__global__ void k_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = hdiag_of(desc[sys], det);
+}
+
+hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_e0, dim3(1), dim3(64), 0, s, desc, sys, det, out);
+    return hipGetLastError();
+}
+
+int spawn_grid_size() {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+    }
+    return cus * 8;
+}
+
+}  // namespace fq
