@@ -1,0 +1,297 @@
+"""Throughput benchmark of the FCIQMC iteration on one MI355X.
+
+Workload (one step = one full iteration: spawning, death, annihilation,
+estimators, shift): the 24-electron / 30-orbital synthetic system with a
+12-orbital near-degenerate band (60 spin orbitals, one 64-bit word per
+determinant), initiator threshold 3, tau = 5e-4, at >= 1e8 walkers.
+
+Input preparation (untimed): a growth stage from walkers on the reference at a
+raised constant shift (cloning everywhere) until N_w reaches the walker target;
+the shift is then set to the instantaneous projected-energy estimate and
+allowed to vary, W warm-up iterations run, and K iterations are timed with the
+walker list resident in device memory. Per-kernel times in the timed region
+come from HIP events recorded on the library's stream around every launch.
+
+Also reported: annihilated determinants/s (spawn records entering
+annihilation), the HBM roofline of the dominant kernel, the CPU oracle on a
+bounded sample of the same walker list, and batched (64 systems in one launch
+sequence) vs plain (the same systems solved one after another) throughput.
+"""
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+KERNELS = ["k_chunk_sum", "k_scan", "k_spawn", "k_post", "k_finalize"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Roctx:
+    """roctxProfilerResume/Pause, so rocprofv3 --selected-regions covers the timed region."""
+
+    def __init__(self):
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(os.path.join("/opt/rocm/lib", name))
+                break
+            except OSError:
+                continue
+
+    def resume(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerResume(ctypes.c_uint64(0))
+
+    def pause(self):
+        if self.lib is not None:
+            self.lib.roctxProfilerPause(ctypes.c_uint64(0))
+
+
+def grow(F, solver, target, log_every=40):
+    it = 0
+    while True:
+        e = solver.estimates()
+        if e["n_walkers"] >= target:
+            return e
+        step = 20 if e["n_walkers"] * 4 < target else 2
+        solver.iterate(step)
+        it += step
+        if it % log_every == 0 or step == 2:
+            e = solver.estimates()
+            log(f"[grow] iter {e['iteration']} N_w {e['n_walkers']} N_d {e['n_dets']} "
+                f"C0 {e['ref_pop']} spawns {e['spawns']} {e['ms_last_call']:.1f} ms/20it")
+        if it > 20000:
+            raise RuntimeError("growth stage did not reach the walker target")
+
+
+def bytes_per_kernel(rec, n_slots):
+    """Algorithmic HBM bytes of one launch of each kernel (per-unit figures in the design notes)."""
+    nd, spawns, merged = rec["n_dets"], rec["spawns"], rec["merged"]
+    return {
+        # read the population of every slot of the table
+        "k_chunk_sum": 4.0 * n_slots,
+        # read key+spawned sum, population, diagonal element of every slot; clear key+spawned
+        # sum and population; write key, population, diagonal element of every survivor
+        "k_post": (16 + 4 + 8) * n_slots + (16 + 4) * n_slots + (8 + 4 + 8) * nd,
+        # per attempt: key + population of its source slot; per spawn: one 16-byte slot update
+        "k_spawn": 12.0 * rec["attempts"] + 16.0 * spawns,
+    }
+
+
+def cpu_baseline(ham, prm, det, pop, e, budget_attempts):
+    from oracle import oracle as O
+    rng = np.random.default_rng(7)
+    order = rng.permutation(len(det))
+    take, acc = [], 0
+    for i in order:
+        take.append(i)
+        acc += abs(int(pop[i]))
+        if acc >= budget_attempts:
+            break
+    take = np.sort(np.asarray(take))
+    o = O.Oracle(ham, prm)
+    o.load_walkers(det[take], pop[take], iteration=e["iteration"], shift=e["shift"],
+                   n_prev=e["n_prev"], varying=1, n_var=e["n_var"])
+    t0 = time.perf_counter()
+    o.iterate(1)
+    dt = time.perf_counter() - t0
+    eo = o.estimates()
+    o.close()
+    return {"value": eo["attempts"] / dt, "unit": "spawn attempts/s", "cores": 1,
+            "kind": "oracle",
+            "annihilated_dets_per_s": eo["spawns"] / dt,
+            "sample": f"one iteration of the single-threaded oracle on {len(take)} determinants "
+                      f"({eo['attempts']} walkers) drawn at random from the timed walker list; "
+                      f"{dt:.1f} s"}
+
+
+def batched_vs_plain(F, S, iters, scale):
+    systems = S.batch_workload(scale=scale)
+    hams = [h for h, _ in systems]
+    prms = [p for _, p in systems]
+    for p in prms:
+        p.initial_walkers = max(10, p.target_walkers // 4)
+    stream = F.current_stream()
+    h = F.fciqmc_batch_create(len(systems), hams, prms, stream)
+    F.fciqmc_batch_iterate(h, 30)                      # warm-up (untimed)
+    log("[batched] created and warmed up")
+    a0 = sum(F.fciqmc_batch_slot_estimators(h, s)["total_attempts"] for s in range(len(systems)))
+    t0 = time.perf_counter()
+    F.fciqmc_batch_iterate(h, iters)
+    tb = time.perf_counter() - t0
+    a1 = sum(F.fciqmc_batch_slot_estimators(h, s)["total_attempts"] for s in range(len(systems)))
+    F.fciqmc_free(h)
+    log(f"[batched] {iters} iterations of {len(systems)} systems in {tb:.3f} s")
+    att_plain, t_plain = 0, 0.0
+    for i, (hm, pr) in enumerate(systems):
+        if i % 16 == 0:
+            log(f"[plain] system {i}")
+        sv = F.Solver(hm, pr, stream)
+        sv.iterate(30)
+        b0 = sv.estimates()["total_attempts"]
+        t0 = time.perf_counter()
+        sv.iterate(iters)
+        t_plain += time.perf_counter() - t0
+        att_plain += sv.estimates()["total_attempts"] - b0
+        sv.close()
+    return {"systems": len(systems), "iterations": iters,
+            "batched_attempts_per_s": (a1 - a0) / tb, "plain_attempts_per_s": att_plain / t_plain,
+            "batched_s": tb, "plain_s": t_plain,
+            "speedup": ((a1 - a0) / tb) / (att_plain / t_plain)}
+
+
+def copy_calibration(roctx, nbytes=1 << 30):
+    """One plain device copy of nbytes inside a profiled region: the HBM counters of this
+    kernel calibrate FETCH_SIZE / WRITE_SIZE against a known traffic."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    roctx.resume()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    roctx.pause()
+    del x, y
+
+
+def pmc_summary(path):
+    """Average of each counter per dispatch, per kernel, from a rocprofv3 --pmc output tree."""
+    import csv
+    import glob
+    rows = {}
+    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                name = r.get("Kernel_Name", r.get("Kernel-Name", "?")).split("(")[0]
+                key = (name, r.get("Counter_Name", "?"))
+                v = float(r.get("Counter_Value", "nan"))
+                disp = r.get("Dispatch_Id", r.get("Dispatch-Id", "0"))
+                rows.setdefault(key, {}).setdefault(disp, 0.0)
+                rows[key][disp] += v
+    for (name, ctr), d in sorted(rows.items()):
+        vals = list(d.values())
+        print(f"{name:40s} {ctr:12s} dispatches {len(vals):5d} mean/dispatch {sum(vals) / len(vals):.6g}")
+
+
+def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--pmc-summary":
+        pmc_summary(sys.argv[2])
+        return
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--walkers", type=float, default=1e8)
+    ap.add_argument("--growth-shift", type=float, default=40.0)
+    ap.add_argument("--initial-walkers", type=int, default=20000)
+    ap.add_argument("--cpu-attempts", type=float, default=4e6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-scale", type=float, default=0.2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="add a 1 GiB device copy in its own profiled region")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1305_6981_amd import fciqmc as F
+    from paper_1305_6981_amd import systems as S
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    roctx = Roctx()
+
+    ham, prm, _ = S.workload("synth24e30o")
+    target = int(args.walkers)
+    prm.target_walkers = target
+    prm.initial_walkers = args.initial_walkers
+    prm.initial_shift = args.growth_shift
+    log(f"[bench] growth stage to {target} walkers at shift +{args.growth_shift}")
+    t_g = time.perf_counter()
+    sv = F.Solver(ham, prm, F.current_stream())
+    e = grow(F, sv, target)
+    s_est = e["proj_num"] / e["ref_pop"] if e["ref_pop"] else 0.0
+    sv.set_shift(s_est, 1)
+    log(f"[bench] grown in {time.perf_counter() - t_g:.1f} s: N_w {e['n_walkers']} N_d "
+        f"{e['n_dets']} C0 {e['ref_pop']}; shift set to E_proj - E0 = {s_est:.4f}")
+    sv.iterate(args.warmup)
+    log("[bench] warm-up done")
+
+    F.fciqmc_set_profiling(sv.h, 1)
+    e0 = sv.estimates()
+    torch.cuda.synchronize()
+    roctx.resume()
+    t0 = time.perf_counter()
+    sv.iterate(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    roctx.pause()
+    e1 = sv.estimates()
+    kms, kcnt = F.fciqmc_kernel_times(sv.h)
+    if args.calibrate_copy:
+        copy_calibration(roctx)
+    F.fciqmc_set_profiling(sv.h, 0)
+    dt = t1 - t0
+    attempts = e1["total_attempts"] - e0["total_attempts"]
+    spawns = e1["total_spawns"] - e0["total_spawns"]
+    log(f"[bench] timed {args.steps} iterations in {dt:.3f} s: N_w {e1['n_walkers']} N_d "
+        f"{e1['n_dets']} attempts {attempts} spawns {spawns}")
+
+    avg_ms = {k: float(kms[i] / max(kcnt[i], 1)) for i, k in enumerate(KERNELS)}
+    dominant = max(("k_spawn", "k_post", "k_chunk_sum"), key=lambda k: avg_ms[k])
+    n_slots = e1["table_slots"]
+    det, pop, _ = sv.walkers()
+    rec = {"n_dets": e1["n_dets"], "spawns": spawns / args.steps, "merged": e1["merged"],
+           "attempts": attempts / args.steps}
+    bpk = bytes_per_kernel(rec, n_slots)
+    if dominant in bpk:
+        achieved = bpk[dominant] / (avg_ms[dominant] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": None, "avg_ms": avg_ms[dominant]}
+    else:
+        roofline = None
+
+    out = {
+        "metric": "spawn attempts/s + annihilated dets/s at 1e8 walkers; batched vs plain",
+        "value": attempts / dt,
+        "unit": "spawn attempts/s",
+        "annihilated_dets_per_s": spawns / dt,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "synthetic 24e/30o with a 12-orbital band at +-0.2 Ha, initiator n_a=3, "
+                               f"tau=5e-4, {e1['n_walkers']} walkers on {e1['n_dets']} dets",
+                   "walkers": e1["n_walkers"], "dets": e1["n_dets"], "table_slots": n_slots,
+                   "parallelism": "1 GPU"},
+        "kernel_avg_ms": avg_ms,
+        "roofline": roofline,
+    }
+    sv_e = e1
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(ham, prm, det, pop, sv_e, args.cpu_attempts)
+        out["gpu_over_oracle"] = out["value"] / out["cpu_baseline"]["value"]
+    sv.close()
+    if not args.no_batched:
+        log("[bench] batched vs plain (64 systems)")
+        out["batched"] = batched_vs_plain(F, S, 100, args.batched_scale)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

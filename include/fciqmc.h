@@ -104,6 +104,7 @@ typedef struct {
     int64_t n_samples;          /* iterations in the averages */
     int64_t n_var;              /* iteration at which the shift started to vary */
     int64_t n_prev;             /* N_w at the last shift update */
+    int64_t table_slots;        /* slots per main-table buffer (layout only) */
     double shift;               /* S, relative to E0 */
     double e_ref;               /* E0 = H_00 */
     double p_double;

@@ -27,13 +27,14 @@ struct alignas(16) Slot {
 struct IterRecord {
     int64_t iter;      // completed iterations after this one
     int64_t nw, nd, c0, attempts, spawns, merged, aborted;
+    int64_t used;      // table slots holding a key (occupied + vacated) after the iteration
     int64_t n_var, n_prev;
     double num, shift;
     int32_t varying, status;
 };
 
 struct ChunkStat {
-    int64_t nw, nd, c0, merged, aborted;
+    int64_t nw, nd, c0, merged, aborted, used;
     double num;
 };
 
@@ -50,16 +51,17 @@ struct SysDesc {
     uint64_t cmask[NCLASS];
     uint64_t irr_packed[2];          // 4 bits per spatial orbital
     const double *h1, *eri;
-    Slot *kv[2];
-    int32_t *pop[2];
-    double *hdiag[2];
+    const double *jk;                // [n_so][64]: (pp|qq) - (pq|qp) for p < q, spin orbitals
+    Slot *kv;                        // main table: key + spawned walkers of this iteration
+    int32_t *pop;                    // signed walker count (0: vacated or not yet occupied)
+    double *hdiag;                   // stored H_DD; NaN until the determinant is first occupied
     uint64_t cap_mask;               // capacity - 1 (capacity a power of two >= CHUNK)
     int64_t nchunks, gchunk0;        // chunks of this system and the first global chunk
     int64_t stop_at;                 // iterate while iter < stop_at
     // --- updated on the device
     int64_t iter;
     double shift;
-    int32_t varying, parity;
+    int32_t varying, pad3;
     int64_t n_prev, n_var;
     uint32_t status, pad2;
     unsigned long long spawns;       // spawning events of the running iteration
@@ -80,10 +82,10 @@ struct EngineArgs {
 };
 
 // Kernel launchers (kernels.hip).
-void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int spawn_grid,
+void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, int spawn_grid,
                       hipStream_t s, hipEvent_t *ev /* 6 events or nullptr */);
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
-                       int64_t n, int32_t parity, uint32_t *d_err, hipStream_t s);
+                       int64_t n, uint32_t *d_err, hipStream_t s);
 hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const Slot *src_kv, const int32_t *src_pop,
                          const double *src_hd, int64_t src_cap, Slot *dst_kv, int32_t *dst_pop,
                          double *dst_hd, uint32_t *d_err, hipStream_t s);
@@ -91,5 +93,6 @@ hipError_t launch_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint6
                           int32_t *out_pop, unsigned long long *count, hipStream_t s);
 hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s);
 int spawn_grid_size();
+int post_grid_size();
 
 }  // namespace fq

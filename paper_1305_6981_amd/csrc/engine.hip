@@ -1,14 +1,16 @@
 // Host engine of libfciqmc: the C ABI declared in include/fciqmc.h.
 //
-// A handle holds up to max_slots independent systems. Each system owns a
-// double-buffered open-addressing main table in device memory (Slot key +
-// spawned sum, population, stored diagonal element), its integrals, and a row
-// of the device descriptor table. One iteration of every system is one pass
-// of five kernels over the descriptor table; up to 64 iterations are captured
-// in one HIP graph. The host reads the per-iteration records after each
-// launch, keeps the estimator series for blocking, and grows tables between
-// launches (re-running an iteration whose spawns overflowed a table; the
-// counter-based random numbers make the re-run identical).
+// A handle holds up to max_slots independent systems. Each system owns an
+// open-addressing main table in device memory (Slot key + spawned sum,
+// population, stored diagonal element), its integrals, and a row of the device
+// descriptor table. One iteration of every system is one pass of five kernels
+// over the descriptor table; up to 64 iterations are captured in one HIP
+// graph. Slots are updated in place; a vacated slot keeps its key until the
+// table is compacted. Between launches the host reads the per-iteration
+// records, keeps the estimator series for blocking, and compacts or grows a
+// table whose headroom would not last the next launch (an iteration whose
+// spawns overflowed a table is re-run after growth; the counter-based random
+// numbers make the re-run identical).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -129,12 +131,14 @@ struct SysHost {
     std::vector<uint8_t> irrep;
     double e_core = 0.0, p_double = 0.0, e0 = 0.0;
     uint64_t d0 = 0;
-    int64_t cap = 0;           // slots per buffer
-    void *block = nullptr;     // one device allocation for tables + integrals
-    Slot *kv[2] = {nullptr, nullptr};
-    int32_t *pop[2] = {nullptr, nullptr};
-    double *hd[2] = {nullptr, nullptr};
-    double *d_h1 = nullptr, *d_eri = nullptr;
+    int64_t cap = 0;           // table slots
+    void *block = nullptr;     // one device allocation for the table + integrals
+    Slot *kv = nullptr;
+    int32_t *pop = nullptr;
+    double *hd = nullptr;
+    double *d_h1 = nullptr, *d_eri = nullptr, *d_jk = nullptr;
+    std::vector<double> jk;    // [n_so][64] pair table
+    int64_t growth = 0;        // expected per-iteration increase of used slots
     int64_t reserve_bytes = 0; // admission accounting (target footprint)
     // mirrored dynamics and statistics
     IterRecord last{};
@@ -163,6 +167,7 @@ struct fciqmc_t {
     int64_t *d_nchunks = nullptr;
     uint32_t *d_err = nullptr;
     int spawn_grid = 2048;
+    int post_grid = 1024;
     std::map<int, hipGraphExec_t> graphs;
     bool use_graph = true;
     bool profiling = false;
@@ -261,12 +266,24 @@ int relayout(fciqmc_t *h) {
 }
 
 int64_t table_bytes(int64_t cap) {
-    return 2 * cap * (int64_t)(sizeof(Slot) + sizeof(int32_t) + sizeof(double));
+    return cap * (int64_t)(sizeof(Slot) + sizeof(int32_t) + sizeof(double));
 }
 
-int64_t integral_bytes(int M) {
+int64_t integral_doubles(int M) {
     const int64_t np = (int64_t)M * (M + 1) / 2;
-    return (int64_t)(M * M + np * (np + 1) / 2) * 8 + 256;
+    return (int64_t)M * M + np * (np + 1) / 2 + 64 * 64;
+}
+
+int64_t integral_bytes(int M) { return integral_doubles(M) * 8 + 256; }
+
+// Empty table: keys and populations zero, diagonal elements NaN ("not computed").
+int clear_table(fciqmc_t *h, void *blk, int64_t cap) {
+    char *p = (char *)blk;
+    HIP_TRY(hipMemsetAsync(p, 0, (size_t)cap * sizeof(Slot), h->stream));
+    HIP_TRY(hipMemsetAsync(p + cap * sizeof(Slot), 0xFF, (size_t)cap * sizeof(double), h->stream));
+    HIP_TRY(hipMemsetAsync(p + cap * (sizeof(Slot) + sizeof(double)), 0,
+                           (size_t)cap * sizeof(int32_t), h->stream));
+    return 0;
 }
 
 // Allocate (and zero) the tables of a system at capacity cap; integrals are
@@ -280,77 +297,79 @@ int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
         return set_err(FCIQMC_ENOMEM, "device allocation of " + std::to_string(tb + ib) +
                                           " bytes failed: " + hipGetErrorString(e));
     }
-    HIP_TRY(hipMemsetAsync(blk, 0, (size_t)tb, h->stream));
+    int rc = clear_table(h, blk, cap);
+    if (rc) return rc;
     *block_out = blk;
     return 0;
 }
 
 void carve(SysHost &S, void *blk, int64_t cap) {
     char *p = (char *)blk;
-    for (int b = 0; b < 2; ++b) {
-        S.kv[b] = (Slot *)p;
-        p += cap * sizeof(Slot);
-    }
-    for (int b = 0; b < 2; ++b) {
-        S.hd[b] = (double *)p;
-        p += cap * sizeof(double);
-    }
-    for (int b = 0; b < 2; ++b) {
-        S.pop[b] = (int32_t *)p;
-        p += cap * sizeof(int32_t);
-    }
+    S.kv = (Slot *)p;
+    p += cap * sizeof(Slot);
+    S.hd = (double *)p;
+    p += cap * sizeof(double);
+    S.pop = (int32_t *)p;
+    p += cap * sizeof(int32_t);
     p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
     S.d_h1 = (double *)p;
     p += (size_t)S.M * S.M * sizeof(double);
     S.d_eri = (double *)p;
+    p += (size_t)S.eri.size() * sizeof(double);
+    S.d_jk = (double *)p;
     S.block = blk;
     S.cap = cap;
+}
+
+int upload_integrals(fciqmc_t *h, SysHost &S) {
+    HIP_TRY(hipMemcpyAsync(S.d_h1, S.h1.data(), S.h1.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(S.d_eri, S.eri.data(), S.eri.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(S.d_jk, S.jk.data(), S.jk.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return 0;
 }
 
 void fill_desc_tables(fciqmc_t *h, int s) {
     SysHost &S = h->sys[s];
     SysDesc &d = h->hdesc[s];
-    for (int b = 0; b < 2; ++b) {
-        d.kv[b] = S.kv[b];
-        d.pop[b] = S.pop[b];
-        d.hdiag[b] = S.hd[b];
-    }
+    d.kv = S.kv;
+    d.pop = S.pop;
+    d.hdiag = S.hd;
     d.h1 = S.d_h1;
     d.eri = S.d_eri;
+    d.jk = S.d_jk;
     d.cap_mask = (uint64_t)(S.cap - 1);
 }
 
-// Grow system s to new_cap, rehashing the live entries of its current buffer.
+// Compact (and possibly grow) the table of system s into new_cap slots: only
+// occupied determinants (and the reference) are carried over, vacated keys are
+// dropped, the spawned-walker fields start at zero.
 int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
     SysHost &S = h->sys[s];
-    SysDesc &d = h->hdesc[s];
     void *blk = nullptr;
     int rc = alloc_tables(h, S, new_cap, &blk);
     if (rc) return rc == FCIQMC_ENOMEM ? FCIQMC_ECAPACITY : rc;
-    SysHost T = S;   // new pointers
+    SysHost T = S;
     carve(T, blk, new_cap);
-    HIP_TRY(hipMemcpyAsync(T.d_h1, S.d_h1, (size_t)integral_bytes(S.M) - 256,
-                           hipMemcpyDeviceToDevice, h->stream));
-    const int cur = d.parity;
-    // the descriptor on the device needs the new mask/d0 for the rehash kernel
-    SysDesc dd = d;
-    dd.cap_mask = (uint64_t)(new_cap - 1);
-    h->hdesc[s] = dd;
-    int r2 = upload_desc(h);
-    if (r2) return r2;
+    rc = upload_integrals(h, T);
+    if (rc) return rc;
+    // the rehash kernel reads the new mask from the descriptor
+    h->hdesc[s].cap_mask = (uint64_t)(new_cap - 1);
+    rc = upload_desc(h);
+    if (rc) return rc;
     HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_rehash(h->d_desc, s, S.kv[cur], S.pop[cur], S.hd[cur], S.cap, T.kv[0], T.pop[0],
-                          T.hd[0], h->d_err, h->stream));
+    HIP_TRY(launch_rehash(h->d_desc, s, S.kv, S.pop, S.hd, S.cap, T.kv, T.pop, T.hd, h->d_err,
+                          h->stream));
     uint32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (err) return set_err(FCIQMC_ECAPACITY, "rehash into the grown table failed");
     HIP_TRY(hipFree(S.block));
     carve(S, blk, new_cap);
-    h->hdesc[s].parity = 0;
     fill_desc_tables(h, s);
-    int r3 = relayout(h);
-    if (r3) return r3;
+    S.last.used = S.last.nd + 1;
+    rc = relayout(h);
+    if (rc) return rc;
     return upload_desc(h);
 }
 
@@ -474,13 +493,27 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     if ((int64_t)fr - reserved < need + (int64_t)(1ull << 30))
         return set_err(FCIQMC_ENOMEM, "system footprint " + std::to_string(need) +
                                           " B does not fit in free device memory");
+    // Pair table for the diagonal elements: (pp|qq) - (pq|qp) over spin orbitals p < q.
+    S.jk.assign(64 * 64, 0.0);
+    auto eri_sp = [&](int i, int j, int k, int l) {
+        auto tri = [](int x, int y) { return x >= y ? (int64_t)x * (x + 1) / 2 + y : (int64_t)y * (y + 1) / 2 + x; };
+        const int64_t a = tri(i, j), b = tri(k, l);
+        return S.eri[a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a];
+    };
+    for (int p = 0; p < nso; ++p)
+        for (int q = p + 1; q < nso; ++q) {
+            const double coul = eri_sp(p >> 1, p >> 1, q >> 1, q >> 1);
+            const double exch = ((p ^ q) & 1) ? 0.0 : eri_sp(p >> 1, q >> 1, q >> 1, p >> 1);
+            S.jk[p * 64 + q] = coul - exch;
+        }
     const int64_t cap = initial_capacity(prm);
     void *blk = nullptr;
     rc = alloc_tables(h, S, cap, &blk);
     if (rc) return rc;
     carve(S, blk, cap);
-    HIP_TRY(hipMemcpyAsync(S.d_h1, S.h1.data(), S.h1.size() * 8, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(S.d_eri, S.eri.data(), S.eri.size() * 8, hipMemcpyHostToDevice, h->stream));
+    rc = upload_integrals(h, S);
+    if (rc) return rc;
+    S.growth = cap / 16;
     S.active = true;
     SysDesc &d = h->hdesc[s];
     std::memset(&d, 0, sizeof d);
@@ -524,18 +557,18 @@ int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::v
         if (rc) return rc;
         SysHost T = S;
         carve(T, blk, need);
-        HIP_TRY(hipMemcpyAsync(T.d_h1, S.h1.data(), S.h1.size() * 8, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(hipMemcpyAsync(T.d_eri, S.eri.data(), S.eri.size() * 8, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
+        rc = upload_integrals(h, T);
+        if (rc) return rc;
         HIP_TRY(hipFree(S.block));
         carve(S, blk, need);
         fill_desc_tables(h, s);
         int r = relayout(h);
         if (r) return r;
     } else {
-        HIP_TRY(hipMemsetAsync(S.block, 0, (size_t)table_bytes(S.cap), h->stream));
+        int rc = clear_table(h, S.block, S.cap);
+        if (rc) return rc;
     }
-    d.parity = 0;
+    S.growth = std::max<int64_t>(S.cap / 16, 2 * n);
     d.status = 0;
     d.spawns = 0;
     int rc = upload_desc(h);
@@ -547,7 +580,7 @@ int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::v
     HIP_TRY(hipMemcpyAsync(dd, det.data(), n * 8, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(dp, pop.data(), n * 4, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_load(h->d_desc, s, dd, dp, n, 0, h->d_err, h->stream));
+    HIP_TRY(launch_load(h->d_desc, s, dd, dp, n, h->d_err, h->stream));
     uint32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, h->d_err, 4, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -566,7 +599,6 @@ struct Walkers {
 
 int export_walkers(fciqmc_t *h, int s, Walkers &w) {
     SysHost &S = h->sys[s];
-    const int par = h->hdesc[s].parity;
     uint64_t *od = nullptr;
     int32_t *op = nullptr;
     unsigned long long *cnt = nullptr;
@@ -574,7 +606,7 @@ int export_walkers(fciqmc_t *h, int s, Walkers &w) {
     HIP_TRY(hipMalloc(&op, S.cap * 4));
     HIP_TRY(hipMalloc(&cnt, 8));
     HIP_TRY(hipMemsetAsync(cnt, 0, 8, h->stream));
-    HIP_TRY(launch_compact(S.kv[par], S.pop[par], S.cap, od, op, cnt, h->stream));
+    HIP_TRY(launch_compact(S.kv, S.pop, S.cap, od, op, cnt, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -618,6 +650,7 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
     o->n_samples = (int64_t)S.s_num.size();
     o->n_var = h->hdesc[s].n_var;
     o->n_prev = h->hdesc[s].n_prev;
+    o->table_slots = S.cap;
     o->shift = h->hdesc[s].shift;
     o->e_ref = S.e0;
     o->p_double = S.p_double;
@@ -664,7 +697,7 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     EngineArgs a = make_args(h);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
-    for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->spawn_grid, h->stream, nullptr);
+    for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->post_grid, h->spawn_grid, h->stream, nullptr);
     HIP_TRY(hipStreamEndCapture(h->stream, &g));
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
@@ -674,19 +707,32 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     return 0;
 }
 
-// Grow systems whose last iterations came close to filling their table.
-int growth_check(fciqmc_t *h) {
+// Before a launch of up to L iterations: compact or grow any table whose
+// free slots would not last, and return how many iterations the headroom of
+// every table allows (each iteration can add at most `growth` keys, the
+// largest increase seen so far; the overflow path catches the rest).
+int plan_launch(fciqmc_t *h, int L, int *L_out) {
+    int allowed = L;
     for (int s = 0; s < h->max_sys; ++s) {
         SysHost &S = h->sys[s];
         if (!S.active || S.fatal) continue;
-        const int64_t occ = S.last.nd + std::max<int64_t>(S.last.spawns, S.last.merged);
-        if (occ * 5 > S.cap * 2) {   // above 40 % load
+        const SysDesc &d = h->hdesc[s];
+        if (d.iter >= d.stop_at) continue;
+        const int64_t g = std::max<int64_t>(S.growth, 256);
+        const int64_t limit = S.cap * 7 / 10;
+        int64_t used = std::max<int64_t>(S.last.used, S.last.nd);
+        if (used + 4 * g > limit) {
+            const int64_t live = S.last.nd + 1;
             int64_t nc = S.cap;
-            while (occ * 5 > nc * 2) nc <<= 1;
+            while (live + 16 * g > nc * 45 / 100) nc <<= 1;
             int rc = grow_system(h, s, nc);
             if (rc) return rc;
+            used = live;
         }
+        const int64_t room = (S.cap * 7 / 10 - used) / g;
+        allowed = (int)std::max<int64_t>(1, std::min<int64_t>(allowed, room));
     }
+    *L_out = allowed;
     return 0;
 }
 
@@ -699,7 +745,7 @@ int run_iterations(fciqmc_t *h, int L) {
     EngineArgs a = make_args(h);
     if (h->profiling) {
         for (int i = 0; i < L; ++i) {
-            launch_iteration(a, h->chunk_alloc, h->spawn_grid, h->stream, h->ev);
+            launch_iteration(a, h->chunk_alloc, h->post_grid, h->spawn_grid, h->stream, h->ev);
             HIP_TRY(hipEventSynchronize(h->ev[5]));
             for (int k = 0; k < 5; ++k) {
                 float ms = 0.f;
@@ -715,7 +761,7 @@ int run_iterations(fciqmc_t *h, int L) {
         if (rc) return rc;
         HIP_TRY(hipGraphLaunch(ex, h->stream));
     } else {
-        for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->spawn_grid, h->stream, nullptr);
+        for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->post_grid, h->spawn_grid, h->stream, nullptr);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -731,8 +777,11 @@ int run_iterations(fciqmc_t *h, int L) {
             HIP_TRY(hipMemcpyAsync(rr.data(), h->d_rec + (int64_t)s * REC_CAP,
                                    sizeof(IterRecord) * REC_CAP, hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
+            int64_t prev_used = S.last.used, seen = 0;
             for (int64_t it = before[s] + 1; it <= d.iter; ++it) {
                 const IterRecord &r = rr[it % REC_CAP];
+                seen = std::max<int64_t>(seen, r.used - prev_used);
+                prev_used = r.used;
                 S.tot_att += r.attempts;
                 S.tot_sp += r.spawns;
                 if (r.varying && r.iter - r.n_var >= S.prm.avg_start) {
@@ -742,6 +791,9 @@ int run_iterations(fciqmc_t *h, int L) {
                 }
                 S.last = r;
             }
+            // headroom estimate for the next launch: the largest growth of the last
+            // one, with 25 % slack
+            S.growth = std::max<int64_t>(256, seen + seen / 4);
         }
         if (d.status & ST_TABLE_FULL) {
             d.status &= ~ST_TABLE_FULL;
@@ -772,9 +824,9 @@ int iterate_each(fciqmc_t *h, const std::vector<int64_t> &n) {
             if (h->sys[s].active && !h->sys[s].fatal)
                 rem = std::max<int64_t>(rem, h->hdesc[s].stop_at - h->hdesc[s].iter);
         if (rem <= 0) break;
-        int rc = growth_check(h);
+        int L = 0;
+        int rc = plan_launch(h, (int)std::min<int64_t>(rem, MAX_GRAPH_ITERS), &L);
         if (rc) return rc;
-        const int L = (int)std::min<int64_t>(rem, MAX_GRAPH_ITERS);
         rc = run_iterations(h, L);
         if (rc) return rc;
     }
@@ -809,6 +861,7 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
     for (int k = 0; k < 6; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
     h->spawn_grid = spawn_grid_size();
+    h->post_grid = post_grid_size();
     int rc = upload_desc(h);
     if (rc) return rc;
     rc = relayout(h);

@@ -8,11 +8,13 @@
 //                 acceptance; accepted walkers are summed straight into the
 //                 target determinant's slot of the main table (the merge of
 //                 equal spawned determinants of Sec. 4.1, done by atomics)
-//   k_post        per slot: death/cloning (Eq. pdeath), annihilation of the
-//                 arrived walkers with the initiator test for determinants that
-//                 are empty after death, diagonal element for new determinants
-//                 (Sec. 4.2); survivors are rehashed into the other buffer;
-//                 estimator partial sums (Eq. ProjE)
+//   k_post        per slot, in place: death/cloning (Eq. pdeath), annihilation
+//                 of the arrived walkers with the initiator test for
+//                 determinants that are empty after death, the stored diagonal
+//                 element for newly occupied determinants (Sec. 4.2) from a
+//                 pair table staged in LDS; estimator partial sums (Eq. ProjE).
+//                 A vacated slot keeps its key (and H_DD) until the table is
+//                 compacted, so no slot ever moves during an iteration.
 //   k_finalize    per system: fixed-order reduction of the partial sums, the
 //                 shift update, the per-iteration record
 //
@@ -308,7 +310,7 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a) {
         if (s >= 0) {
             const SysDesc &d = a.desc[s];
             if (participating(d)) {
-                const int32_t *pop = d.pop[d.parity] + (int64_t)a.chunk_local[c] * CHUNK;
+                const int32_t *pop = d.pop + (int64_t)a.chunk_local[c] * CHUNK;
                 for (int i = threadIdx.x; i < CHUNK; i += 256) {
                     const int32_t v = pop[i];
                     sum += (unsigned long long)(v < 0 ? -(int64_t)v : (int64_t)v);
@@ -409,10 +411,9 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
             }
             const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
             const SysDesc &d = a.desc[s];
-            const int par = d.parity;
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-            const Slot *kvc = d.kv[par] + base;
-            const int32_t *popc = d.pop[par] + base;
+            const Slot *kvc = d.kv + base;
+            const int32_t *popc = d.pop + base;
             // LDS scan of |C| over the chunk: 4 consecutive slots per thread.
             unsigned long long loc[4], run = 0;
 #pragma unroll
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
             __syncthreads();
             const unsigned long long lo_t = t0 > off_c ? t0 : off_c;
             const unsigned long long hi_t = (t1 < off_c + nw_c) ? t1 : off_c + nw_c;
-            const Slot *kvn = d.kv[par];
+            Slot *kvn = d.kv;
             unsigned long long spawned = 0;
             for (unsigned long long at = lo_t + t; at < hi_t; at += 256) {
                 const unsigned long long local = at - off_c;
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
                 const int32_t m = (int32_t)fl + (u01(x4) < pr - fl ? 1 : 0);
                 if (m == 0) continue;
                 const int32_t v = ((C > 0) == (ex.hel > 0.0)) ? -m : m;
-                if (!table_add(const_cast<Slot *>(kvn), d.cap_mask, ex.det, v, init))
+                if (!table_add(kvn, d.cap_mask, ex.det, v, init))
                     atomicOr(&a.desc[s].status, ST_TABLE_FULL);
                 ++spawned;
             }
@@ -484,8 +485,8 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K4: death, annihilation and initiator test per slot; survivors are inserted
-// into the other buffer; the current slot is cleared; estimator partials.
+// K4: death, annihilation and initiator test per slot, in place; the
+// diagonal element of newly occupied determinants; estimator partials.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t insert_unique(Slot *kv, uint64_t mask, uint64_t key) {
     uint64_t h = mix64(key) & mask;
@@ -498,37 +499,63 @@ __device__ __forceinline__ int64_t insert_unique(Slot *kv, uint64_t mask, uint64
     return -1;
 }
 
+constexpr int POST_QUEUE = 512;
+
+// H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
+// ascending (p, q) order from the LDS copies of h_pp and of the pair table.
+__device__ __forceinline__ double hdiag_lds(double e_core, uint64_t det, const double *hpp,
+                                            const double *jk) {
+    double acc = e_core;
+    for (uint64_t m = det; m; m &= m - 1) acc = acc + hpp[__builtin_ctzll(m)];
+    for (uint64_t m1 = det; m1; m1 &= m1 - 1) {
+        const double *row = jk + 64 * __builtin_ctzll(m1);
+        for (uint64_t m2 = m1 & (m1 - 1); m2; m2 &= m2 - 1) acc = acc + row[__builtin_ctzll(m2)];
+    }
+    return acc;
+}
+
 __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
+    __shared__ double s_jk[64 * 64];
+    __shared__ double s_hpp[64];
+    __shared__ int s_queue[POST_QUEUE];
+    __shared__ int s_qn;
     __shared__ long long shi[256];
     __shared__ double shd[256];
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x;
+    int loaded = -1;
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const int s = a.chunk_sys[c];
-        int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0;
+        int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, used = 0;
         double num = 0.0;
-        bool live = false;
-        if (s >= 0) live = participating(a.desc[s]);
+        const bool live = s >= 0 && participating(a.desc[s]);   // uniform
         if (live) {
             const SysDesc &d = a.desc[s];
-            const int cur = d.parity, nxt = cur ^ 1;
+            if (loaded != s) {
+                __syncthreads();
+                for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = d.jk[i];
+                for (int i = t; i < d.n_so; i += 256) s_hpp[i] = h_so(d, i, i);
+                loaded = s;
+            }
+            if (t == 0) s_qn = 0;
+            __syncthreads();
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-            Slot *kv = d.kv[cur] + base;
-            int32_t *pp = d.pop[cur] + base;
-            const double *hh = d.hdiag[cur] + base;
+            Slot *kv = d.kv + base;
+            int32_t *pp = d.pop + base;
+            double *hh = d.hdiag + base;
             for (int i = t; i < CHUNK; i += 256) {
                 const Slot sl = kv[i];
                 if (sl.det == 0) continue;
+                ++used;
                 const uint64_t D = sl.det;
                 const int32_t p = pp[i];
-                double hd = hh[i];
                 int64_t pd = p;
                 if (p != 0) {
                     // Eq. pdeath, one stochastic rounding for the whole determinant.
                     uint64_t xd, xu;
                     draw2(d.seed, D, 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
                     const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
-                    const double dv = ((hd - d.e0) - d.shift) * d.tau * (double)absC;
+                    const double dv = ((hh[i] - d.e0) - d.shift) * d.tau * (double)absC;
                     const double ad = fabs(dv);
                     const double fl = floor(ad);
                     if (fl > 1073741824.0) {
@@ -538,6 +565,8 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                     const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
                     pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
                 }
+                // Annihilation (Sec. 4.2): present after death -> add; otherwise the
+                // arrived walkers survive only if an initiator sent some of them.
                 const bool present = pd != 0 || D == d.d0;
                 const int64_t sp = sl.spop;
                 int64_t np;
@@ -554,18 +583,15 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                     atomicOr(&a.desc[s].status, ST_POP_OVERFLOW);
                     np = 0;
                 }
-                if (np != 0 || D == d.d0) {
-                    if (p == 0 && D != d.d0) hd = hdiag_of(d, D);  // newly occupied
-                    const int64_t j = insert_unique(d.kv[nxt], d.cap_mask, D);
-                    if (j >= 0) {
-                        d.pop[nxt][j] = (int32_t)np;
-                        d.hdiag[nxt][j] = hd;
-                    } else {
-                        atomicOr(&a.desc[s].status, ST_TABLE_FULL);
-                    }
+                if (np != p) pp[i] = (int32_t)np;
+                if (sl.spop != 0 || sl.sflag != 0)
+                    *reinterpret_cast<unsigned long long *>(&kv[i].spop) = 0ull;
+                if (np != 0 && isnan(hh[i])) {
+                    // newly occupied: its diagonal element is computed below
+                    const int q = atomicAdd(&s_qn, 1);
+                    if (q < POST_QUEUE) s_queue[q] = i;
+                    else hh[i] = hdiag_lds(d.e_core, D, s_hpp, s_jk);
                 }
-                kv[i] = Slot{0ull, 0, 0u};
-                pp[i] = 0;
                 if (D == d.d0) c0 = np;
                 if (np != 0) {
                     nw += np < 0 ? -np : np;
@@ -573,14 +599,21 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                     if (D != d.d0 && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
                 }
             }
+            __syncthreads();
+            const int nq = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
+            for (int j = t; j < nq; j += 256) {
+                const int i = s_queue[j];
+                hh[i] = hdiag_lds(d.e_core, kv[i].det, s_hpp, s_jk);
+            }
         }
         nw = block_sum((long long)nw, shi);
         nd = block_sum((long long)nd, shi);
         c0 = block_sum((long long)c0, shi);
         merged = block_sum((long long)merged, shi);
         aborted = block_sum((long long)aborted, shi);
+        used = block_sum((long long)used, shi);
         num = block_sum(num, shd);
-        if (t == 0) a.chunk_stat[c] = ChunkStat{nw, nd, c0, merged, aborted, num};
+        if (t == 0) a.chunk_stat[c] = ChunkStat{nw, nd, c0, merged, aborted, used, num};
     }
 }
 
@@ -595,10 +628,11 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
     SysDesc &d = a.desc[s];
     if (!participating(d)) return;   // uniform across the workgroup
     const int t = threadIdx.x;
-    int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0;
+    int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0, used = 0;
     double num = 0.0;
     for (int64_t i = t; i < d.nchunks; i += 256) {
         const ChunkStat cs = a.chunk_stat[d.gchunk0 + i];
+        used += cs.used;
         nw += cs.nw;
         nd += cs.nd;
         c0 += cs.c0;
@@ -613,6 +647,7 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
     merged = block_sum((long long)merged, shi);
     aborted = block_sum((long long)aborted, shi);
     att = block_sum((long long)att, shi);
+    used = block_sum((long long)used, shi);
     num = block_sum(num, shd);
     if (t == 0) {
         const int64_t done = d.iter + 1;
@@ -641,6 +676,7 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
         r.spawns = (int64_t)d.spawns;
         r.merged = merged;
         r.aborted = aborted;
+        r.used = used;
         r.n_var = d.n_var;
         r.n_prev = d.n_prev;
         r.num = num;
@@ -650,12 +686,11 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
         a.rec[(int64_t)s * REC_CAP + (done % REC_CAP)] = r;
         d.spawns = 0ull;
         d.iter = done;
-        d.parity ^= 1;
     }
 }
 
-void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int spawn_grid, hipStream_t s,
-                      hipEvent_t *ev) {
+void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, int spawn_grid,
+                      hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)chunk_grid), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[1], s);
@@ -663,7 +698,7 @@ void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int spawn_grid, h
     if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_post, dim3((unsigned)chunk_grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[4], s);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[5], s);
@@ -673,18 +708,18 @@ void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int spawn_grid, h
 // Loading a walker list, rehashing into a grown table, exporting.
 // ---------------------------------------------------------------------------
 __global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const int32_t *pop,
-                       int64_t n, int32_t par, uint32_t *err) {
+                       int64_t n, uint32_t *err) {
     const SysDesc &d = desc[sys];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t D = det[i];
-        const int64_t j = insert_unique(d.kv[par], d.cap_mask, D);
+        const int64_t j = insert_unique(d.kv, d.cap_mask, D);
         if (j < 0) {
             atomicOr(err, 1u);
             continue;
         }
-        d.pop[par][j] = pop[i];
-        d.hdiag[par][j] = hdiag_of(d, D);
+        d.pop[j] = pop[i];
+        d.hdiag[j] = hdiag_of(d, D);
     }
 }
 
@@ -722,11 +757,11 @@ __global__ void k_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint6
 }
 
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
-                       int64_t n, int32_t parity, uint32_t *d_err, hipStream_t s) {
+                       int64_t n, uint32_t *d_err, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t g = (n + 255) / 256;
     hipLaunchKernelGGL(k_load, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, d_desc,
-                       sys, det, pop, n, parity, d_err);
+                       sys, det, pop, n, d_err);
     return hipGetLastError();
 }
 
@@ -755,6 +790,8 @@ hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out
     hipLaunchKernelGGL(k_e0, dim3(1), dim3(64), 0, s, desc, sys, det, out);
     return hipGetLastError();
 }
+
+int post_grid_size() { return spawn_grid_size() / 2; }
 
 int spawn_grid_size() {
     int dev = 0, cus = 256;

@@ -235,7 +235,7 @@ def batch_workload(scale: float = 1.0, n_hubbard: int = 32, n_synth: int = 32):
         target = int(round(10 ** rng.uniform(4.0, 6.0) * scale))
         ham = hubbard_ring(L, u)
         prm = Params(tau=0.01, initiator_threshold=0, target_walkers=max(target, 20),
-                     initial_walkers=10, seed=100 + i)
+                     initial_walkers=10, seed=100 + i, shift_update_every=1)
         out.append((ham, prm))
     for i in range(n_synth):
         frac = i / max(n_synth - 1, 1)
@@ -264,7 +264,7 @@ def serve_requests(n: int = 200, rate: float = 20.0, seed: int = 5, scale: float
             L = int(rng.choice([8, 10, 12, 14, 16]))
             ham = hubbard_ring(L, float(rng.uniform(2.0, 8.0)))
             prm = Params(tau=0.01, initiator_threshold=0, target_walkers=max(target, 20),
-                         seed=1000 + i)
+                         seed=1000 + i, shift_update_every=1)
         elif kind == 1:
             ham = synthetic_molecule(20, 5, 5, seed=300 + i)
             prm = Params(tau=1e-3, initiator_threshold=3, target_walkers=max(target, 20),

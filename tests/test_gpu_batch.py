@@ -1,0 +1,79 @@
+"""Batching and continuous batching: every system of a batch handle, admitted
+or retired at any time, follows exactly the trajectory it has alone (and the
+oracle's)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1305_6981_amd import fciqmc as F
+from paper_1305_6981_amd import systems as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _systems():
+    h1, p1, _ = S.workload("hubbard8", scale=0.2)
+    h2 = S.hubbard_ring(10, 3.0)
+    p2 = S.Params(tau=0.01, shift_update_every=1, target_walkers=3000, seed=101)
+    h3, p3, _ = S.workload("synth10e20o", scale=2e-4)
+    p3.initial_walkers, p3.initial_shift = 300, 0.5
+    h4 = S.synthetic_molecule(16, 6, 6, 204)
+    p4 = S.Params(tau=2e-3, initiator_threshold=3, target_walkers=4000, initial_walkers=300,
+                  initial_shift=0.4, seed=105)
+    return [(h1, p1), (h2, p2), (h3, p3), (h4, p4)]
+
+
+def _oracle_lists(ham, prm, n):
+    o = O.Oracle(ham, prm)
+    o.iterate(n)
+    d, p, f = o.walkers()
+    e = o.estimates()
+    o.close()
+    return d, p, e
+
+
+def test_batch_equals_solo_and_oracle():
+    sy = _systems()
+    print(f"[gpu] batch of {len(sy)}", flush=True)
+    h = F.fciqmc_batch_create(len(sy), [a for a, _ in sy], [b for _, b in sy], F.current_stream())
+    F.fciqmc_batch_iterate(h, 45)
+    for slot, (ham, prm) in enumerate(sy):
+        d, p, _ = F.fciqmc_batch_slot_walkers(h, slot)
+        do, po, eo = _oracle_lists(ham, prm, 45)
+        assert np.array_equal(d, do) and np.array_equal(p, po), slot
+        e = F.fciqmc_batch_slot_estimators(h, slot)
+        assert e["shift"] == eo["shift"] and e["n_walkers"] == eo["n_walkers"]
+    F.fciqmc_free(h)
+
+
+def test_continuous_batching_admit_retire():
+    sy = _systems()
+    print("[gpu] continuous batching", flush=True)
+    h = F.fciqmc_batch_create(3, [sy[0][0], sy[1][0]], [sy[0][1], sy[1][1]], F.current_stream())
+    done = {0: 0, 1: 0}
+    F.fciqmc_batch_iterate(h, 20)
+    done = {k: v + 20 for k, v in done.items()}
+    s2 = F.fciqmc_batch_admit(h, *sy[2])
+    assert s2 == 2
+    done[2] = 0
+    F.fciqmc_batch_iterate_each(h, [15, 25, 30])
+    done[0] += 15
+    done[1] += 25
+    done[2] += 30
+    F.fciqmc_batch_retire(h, 0)
+    assert F.fciqmc_batch_active(h) == 2
+    s3 = F.fciqmc_batch_admit(h, *sy[3])
+    assert s3 == 0
+    owner = {0: 3, 1: 1, 2: 2}
+    done = {0: 0, 1: done[1], 2: done[2]}
+    F.fciqmc_batch_iterate(h, 12)
+    for k in done:
+        done[k] += 12
+    for slot, n in done.items():
+        ham, prm = sy[owner[slot]]
+        d, p, _ = F.fciqmc_batch_slot_walkers(h, slot)
+        do, po, _ = _oracle_lists(ham, prm, n)
+        assert np.array_equal(d, do) and np.array_equal(p, po), (slot, n)
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_batch_admit(h, *sy[0])      # no free slot
+    F.fciqmc_free(h)
