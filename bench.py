@@ -42,21 +42,23 @@ class Roctx:
     """roctxProfilerResume/Pause, so rocprofv3 --selected-regions covers the timed region."""
 
     def __init__(self):
-        self.lib = None
-        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+        self.mod = None
+        py = "/opt/rocm/lib/python%d.%d/site-packages" % sys.version_info[:2]
+        if os.path.isdir(os.path.join(py, "roctx")):
+            sys.path.append(py)
             try:
-                self.lib = ctypes.CDLL(os.path.join("/opt/rocm/lib", name))
-                break
-            except OSError:
-                continue
+                import roctx
+                self.mod = roctx
+            except Exception:
+                self.mod = None
 
     def resume(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerResume(ctypes.c_uint64(0))
+        if self.mod is not None:
+            self.mod.profilerResume(0)
 
     def pause(self):
-        if self.lib is not None:
-            self.lib.roctxProfilerPause(ctypes.c_uint64(0))
+        if self.mod is not None:
+            self.mod.profilerPause(0)
 
 
 def grow(F, solver, target, log_every=40):
@@ -166,28 +168,33 @@ def copy_calibration(roctx, nbytes=1 << 30):
     del x, y
 
 
-def pmc_summary(path):
-    """Average of each counter per dispatch, per kernel, from a rocprofv3 --pmc output tree."""
+def pmc_summary(path, last=0):
+    """Mean of each counter per dispatch, per kernel, from a rocprofv3 --pmc CSV tree
+    (only the last `last` dispatches of each kernel when last > 0)."""
     import csv
     import glob
     rows = {}
-    for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+    for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                name = r.get("Kernel_Name", r.get("Kernel-Name", "?")).split("(")[0]
-                key = (name, r.get("Counter_Name", "?"))
-                v = float(r.get("Counter_Value", "nan"))
-                disp = r.get("Dispatch_Id", r.get("Dispatch-Id", "0"))
-                rows.setdefault(key, {}).setdefault(disp, 0.0)
-                rows[key][disp] += v
+                name = (r.get("Kernel_Name") or r.get("Kernel-Name") or "?").split("(")[0]
+                ctr = r.get("Counter_Name") or r.get("Counter-Name") or "?"
+                v = float(r.get("Counter_Value") or r.get("Counter-Value") or "nan")
+                disp = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or 0)
+                rows.setdefault((name, ctr), {}).setdefault(disp, 0.0)
+                rows[(name, ctr)][disp] += v
+    print(f"# rocprofv3 --pmc summary of {path}; per-dispatch means"
+          + (f" over the last {last} dispatches of each kernel" if last else ""))
     for (name, ctr), d in sorted(rows.items()):
-        vals = list(d.values())
-        print(f"{name:40s} {ctr:12s} dispatches {len(vals):5d} mean/dispatch {sum(vals) / len(vals):.6g}")
+        vals = [d[k] for k in sorted(d)]
+        if last:
+            vals = vals[-last:]
+        print(f"{name:44s} {ctr:22s} dispatches {len(vals):5d} mean {sum(vals) / len(vals):.6g}")
 
 
 def main():
-    if len(sys.argv) == 3 and sys.argv[1] == "--pmc-summary":
-        pmc_summary(sys.argv[2])
+    if len(sys.argv) >= 3 and sys.argv[1] == "--pmc-summary":
+        pmc_summary(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 0)
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

@@ -44,7 +44,7 @@ struct ChunkStat {
 struct SysDesc {
     // --- set by the host
     int32_t active, M, N, n_so;
-    int32_t A, n_a, pad0, pad1;
+    int32_t A, n_a, n_class, pad1;  // n_class: 2 x (largest irrep label + 1)
     double tau, zeta, e0, e_core, p_double, p_single;
     int64_t target;
     uint64_t seed, d0, valid;

@@ -521,6 +521,11 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     d.M = S.M;
     d.N = S.N;
     d.n_so = nso;
+    {
+        int mx = 0;
+        for (int i = 0; i < S.M; ++i) mx = std::max<int>(mx, S.irrep[i]);
+        d.n_class = 2 * (mx + 1);
+    }
     d.A = prm->shift_update_every;
     d.n_a = prm->initiator_threshold;
     d.tau = prm->tau;

@@ -31,10 +31,11 @@ namespace fq {
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // one 32x32->64 product per multiplier gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -55,8 +56,12 @@ __device__ __forceinline__ double u01(uint64_t x) {
     return (double)(x >> 11) * (1.0 / 9007199254740992.0);
 }
 
+// floor(x * n / 2^64) for n < 2^31, from two 32x32->64 products: with
+// x n = hi 2^32 + lo, the result is (hi + (lo >> 32)) >> 32 exactly.
 __device__ __forceinline__ uint32_t pick(uint64_t x, uint32_t n) {
-    return (uint32_t)__umul64hi(x, (uint64_t)n);
+    const uint64_t lo = (uint64_t)(uint32_t)x * (uint64_t)n;
+    const uint64_t hi = (uint64_t)(uint32_t)(x >> 32) * (uint64_t)n;
+    return (uint32_t)((hi + (lo >> 32)) >> 32);
 }
 
 // Position of the k-th (0-based) set bit of x, by halving with popcounts.
@@ -95,14 +100,15 @@ __device__ __forceinline__ uint64_t mix64(uint64_t h) {
 // ---------------------------------------------------------------------------
 // Hamiltonian (spin orbital p = 2 s + sigma).
 // ---------------------------------------------------------------------------
+// Packed-pair index; operands stay below 2^24, so 24-bit multiplies are exact.
 __device__ __forceinline__ int tri(int i, int j) {
-    return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+    const int hi = i >= j ? i : j, lo = i >= j ? j : i;
+    return (int)(__umul24((unsigned)hi, (unsigned)(hi + 1)) >> 1) + lo;
 }
 
 __device__ __forceinline__ double eri_so(const SysDesc &d, int p, int q, int r, int s) {
     if (((p ^ q) | (r ^ s)) & 1) return 0.0;
-    const int a = tri(p >> 1, q >> 1), b = tri(r >> 1, s >> 1);
-    return d.eri[a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a];
+    return d.eri[tri(tri(p >> 1, q >> 1), tri(r >> 1, s >> 1))];
 }
 
 __device__ __forceinline__ double h_so(const SysDesc &d, int p, int q) {
@@ -188,20 +194,23 @@ struct Excit {
     uint64_t det;
     double pgen;
     double hel;
+    int p, a;
 };
 
 constexpr uint64_t EVEN_BITS = 0x5555555555555555ull;
 constexpr uint64_t ODD_BITS = 0xAAAAAAAAAAAAAAAAull;
 
+// recip[k] = 1.0 / k, filled by IEEE division (same bits as dividing in place).
+// For a single excitation the matrix element is left to the caller when
+// defer_single is set (ex.hel = NaN, the orbitals in ex.p / ex.a).
 __device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1, uint64_t x2,
-                       uint64_t x3, Excit &ex) {
+                       uint64_t x3, const double *recip, bool defer_single, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int N = d.N;
     if (!(u01(x0) < d.p_double)) {
         // Single (Sec. 5.1): renormalise over electrons that have an allowed target.
         uint64_t movable = 0;
-#pragma unroll
-        for (int c = 0; c < NCLASS; ++c) {
+        for (int c = 0; c < d.n_class; ++c) {
             const uint64_t cm = d.cmask[c];
             if (emp & cm) movable |= det & cm;
         }
@@ -213,14 +222,17 @@ __device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1,
         const int a = select_bit(tg, pick(x2, nal));
         ex.det = det ^ (1ull << p) ^ (1ull << a);
         ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
-        ex.hel = hel_single(d, det, p, a);
+        ex.p = p;
+        ex.a = a;
+        ex.hel = defer_single ? __longlong_as_double(0x7FF8000000000000ll) : hel_single(d, det, p, a);
         return true;
     }
     // Double (Sec. 5.2): a unique pair by inverse triangular indexing.
     if (N < 2) return false;
-    const uint64_t npairs = (uint64_t)N * (uint64_t)(N - 1) / 2;
-    const int64_t K = (int64_t)__umul64hi(x1, npairs);
-    int j = (int)((1.0 + sqrt(1.0 + 8.0 * (double)K)) * 0.5);
+    const uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
+    const int64_t K = (int64_t)pick(x1, npairs);
+    // estimate, then exact integer correction
+    int j = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)K)) * 0.5f);
     while ((int64_t)j * (j - 1) / 2 > K) --j;
     while ((int64_t)(j + 1) * j / 2 <= K) ++j;
     const int i = (int)(K - (int64_t)j * (j - 1) / 2);
@@ -230,8 +242,7 @@ __device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1,
     const int gpq = irrep_of(d, p >> 1) ^ irrep_of(d, q >> 1);
     // a orbitals whose partner class (Eq. sym1 plus spin) has an empty orbital besides a.
     uint64_t allowed = 0;
-#pragma unroll
-    for (int c = 0; c < NCLASS; ++c) {
+    for (int c = 0; c < d.n_class; ++c) {
         const uint64_t memb = A & d.cmask[c];
         if (!memb) continue;
         const int sb = same ? (p & 1) : 1 - (c & 1);
@@ -251,7 +262,7 @@ __device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1,
     const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
     const int nbb = __popcll(emp & d.cmask[pcb]) - (pcb == cb ? 1 : 0);
     ex.det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
-    ex.pgen = (2.0 * d.p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
+    ex.pgen = (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
               (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
     ex.hel = hel_double(d, det, p, q, a, b);
     return true;
@@ -298,27 +309,36 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
     return r;
 }
 
+// Sum over the 64 lanes of a wavefront with a fixed butterfly (deterministic).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
-// K1: chunk sums of |C| on the current buffer.
+// K1: chunk sums of |C| on the current tables.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a) {
-    __shared__ unsigned long long sh[256];
+    __shared__ unsigned long long sh[4];
     const int64_t nch = *a.nchunks;
+    const int t = threadIdx.x;
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const int s = a.chunk_sys[c];
         unsigned long long sum = 0;
         if (s >= 0) {
             const SysDesc &d = a.desc[s];
             if (participating(d)) {
-                const int32_t *pop = d.pop + (int64_t)a.chunk_local[c] * CHUNK;
-                for (int i = threadIdx.x; i < CHUNK; i += 256) {
-                    const int32_t v = pop[i];
-                    sum += (unsigned long long)(v < 0 ? -(int64_t)v : (int64_t)v);
-                }
+                const int4 v = reinterpret_cast<const int4 *>(d.pop + (int64_t)a.chunk_local[c] * CHUNK)[t];
+                sum = (unsigned long long)(abs(v.x)) + (unsigned long long)(abs(v.y)) +
+                      (unsigned long long)(abs(v.z)) + (unsigned long long)(abs(v.w));
             }
         }
-        sum = block_sum(sum, sh);
-        if (threadIdx.x == 0) a.chunk_nw[c] = sum;
+        sum = wave_sum(sum);
+        if ((t & 63) == 0) sh[t >> 6] = sum;
+        __syncthreads();
+        if (t == 0) a.chunk_nw[c] = sh[0] + sh[1] + sh[2] + sh[3];
+        __syncthreads();
     }
 }
 
@@ -352,10 +372,12 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
 
 // ---------------------------------------------------------------------------
 // K3: spawning. Attempts are numbered globally; a workgroup takes a tile of
-// consecutive attempts, scans the pops of the chunk(s) covering it in LDS and
-// maps attempt t to (slot, walker ordinal k).
+// consecutive attempts, stages the keys and populations of the chunk(s)
+// covering it in LDS with a prefix sum of |C|, and each thread walks a run of
+// consecutive attempts: (slot, walker ordinal k) by one binary search, then
+// k+1 / next occupied slot.
 // ---------------------------------------------------------------------------
-constexpr int SPAWN_TILE = 1024;
+constexpr int SPAWN_TILE = 2048;
 
 __device__ __forceinline__ bool table_add(Slot *kv, uint64_t mask, uint64_t key, int32_t v,
                                           bool init) {
@@ -378,14 +400,54 @@ __device__ __forceinline__ bool table_add(Slot *kv, uint64_t mask, uint64_t key,
     return false;
 }
 
+// Work queued in LDS by the attempt loop and drained by the whole workgroup:
+// single excitations (their matrix element is an O(N) gather loop that would
+// stall a wavefront for one lane) and accepted spawns (their hash-table probe
+// is a dependent HBM round trip).
+struct SingleItem {
+    uint64_t D;        // source determinant
+    double pgen;
+    uint64_t x4;       // acceptance draw
+    int32_t C;         // source population (sign)
+    uint32_t pai;      // p | a << 8 | initiator << 16
+};
+
+constexpr int SGL_QUEUE = 256;
+constexpr int SPW_QUEUE = 512;
+
+__device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double pgen, uint64_t x4,
+                                          int32_t C, uint32_t *status) {
+    const double pr = (d.tau * fabs(hel)) / pgen;
+    const double fl = floor(pr);
+    if (fl > 1073741824.0) {
+        atomicOr(status, ST_SPAWN_OVERFLOW);
+        return 0;
+    }
+    const int32_t m = (int32_t)fl + (u01(x4) < pr - fl ? 1 : 0);
+    return ((C > 0) == (hel > 0.0)) ? -m : m;
+}
+
 __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
     __shared__ unsigned long long s_incl[CHUNK];
+    __shared__ uint64_t s_det[CHUNK];
     __shared__ int32_t s_pop[CHUNK];
-    __shared__ unsigned long long s_part[256];
+    __shared__ unsigned long long s_wsum[4];
     __shared__ long long s_c;
+    __shared__ double s_recip[65];
+    __shared__ SingleItem s_sgl[SGL_QUEUE];
+    __shared__ uint64_t s_spd[SPW_QUEUE];
+    __shared__ int2 s_spv[SPW_QUEUE];   // (signed walkers, initiator flag)
+    __shared__ int s_nsgl, s_nspw;
     const unsigned long long total = *a.total;
     const int64_t nch = *a.nchunks;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    if (t > 0 && t <= 64) s_recip[t] = 1.0 / (double)t;
+    if (t == 0) {
+        s_recip[0] = 0.0;
+        s_nsgl = 0;
+        s_nspw = 0;
+    }
+    __syncthreads();
     for (unsigned long long t0 = (unsigned long long)blockIdx.x * SPAWN_TILE; t0 < total;
          t0 += (unsigned long long)gridDim.x * SPAWN_TILE) {
         const unsigned long long t1 = (t0 + SPAWN_TILE < total) ? t0 + SPAWN_TILE : total;
@@ -411,73 +473,129 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
             }
             const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
             const SysDesc &d = a.desc[s];
+            uint32_t *status = &a.desc[s].status;
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-            const Slot *kvc = d.kv + base;
-            const int32_t *popc = d.pop + base;
-            // LDS scan of |C| over the chunk: 4 consecutive slots per thread.
+            // Stage keys and populations; prefix sum of |C| (4 consecutive slots per thread).
+            const int4 pv = reinterpret_cast<const int4 *>(d.pop + base)[t];
+            const int32_t pa[4] = {pv.x, pv.y, pv.z, pv.w};
             unsigned long long loc[4], run = 0;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int32_t v = popc[4 * t + u];
-                s_pop[4 * t + u] = v;
-                run += (unsigned long long)(v < 0 ? -(int64_t)v : (int64_t)v);
+                const int i = 4 * t + u;
+                s_pop[i] = pa[u];
+                s_det[i] = d.kv[base + i].det;
+                run += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
                 loc[u] = run;
             }
-            s_part[t] = run;
-            __syncthreads();
-            for (int o = 1; o < 256; o <<= 1) {
-                const unsigned long long v = t >= o ? s_part[t - o] : 0ull;
-                __syncthreads();
-                s_part[t] += v;
-                __syncthreads();
+            unsigned long long x = run;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned long long y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
             }
-            const unsigned long long before = s_part[t] - run;
+            if (lane == 63) s_wsum[wid] = x;
+            __syncthreads();
+            unsigned long long before = x - run;
+            for (int w = 0; w < wid; ++w) before += s_wsum[w];
 #pragma unroll
             for (int u = 0; u < 4; ++u) s_incl[4 * t + u] = before + loc[u];
             __syncthreads();
+            // This chunk's part of the tile, split into 256 consecutive runs.
             const unsigned long long lo_t = t0 > off_c ? t0 : off_c;
             const unsigned long long hi_t = (t1 < off_c + nw_c) ? t1 : off_c + nw_c;
-            Slot *kvn = d.kv;
+            const unsigned long long per = (hi_t - lo_t + 255) / 256;
+            unsigned long long at = lo_t + (unsigned long long)t * per;
+            const unsigned long long at_end = (at + per < hi_t) ? at + per : hi_t;
+            const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
             unsigned long long spawned = 0;
-            for (unsigned long long at = lo_t + t; at < hi_t; at += 256) {
+            if (at < at_end) {
                 const unsigned long long local = at - off_c;
-                int lo = 0, hi = CHUNK - 1;  // first slot with inclusive sum > local
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
+                int sl = 0, hi = CHUNK - 1;  // first slot with inclusive sum > local
+                while (sl < hi) {
+                    const int mid = (sl + hi) >> 1;
                     if (s_incl[mid] > local) hi = mid;
-                    else lo = mid + 1;
+                    else sl = mid + 1;
                 }
-                const int32_t C = s_pop[lo];
-                const unsigned long long excl = lo ? s_incl[lo - 1] : 0ull;
-                const uint32_t k = (uint32_t)(local - excl);
-                const uint64_t D = kvc[lo].det;
-                const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
-                const bool init = absC > d.n_a || D == d.d0;
-                uint64_t x0, x1, x2, x3;
-                draw2(d.seed, D, k, d.iter, 0u, x0, x1);
-                draw2(d.seed, D, k, d.iter, 1u, x2, x3);
-                Excit ex;
-                if (!excite(d, D, x0, x1, x2, x3, ex)) continue;
-                if (ex.hel == 0.0) continue;
-                uint64_t x4, x5;
-                draw2(d.seed, D, k, d.iter, 2u, x4, x5);
-                const double pr = (d.tau * fabs(ex.hel)) / ex.pgen;
-                const double fl = floor(pr);
-                if (fl > 1073741824.0) {
-                    atomicOr(&a.desc[s].status, ST_SPAWN_OVERFLOW);
-                    continue;
+                uint32_t k = (uint32_t)(local - (sl ? s_incl[sl - 1] : 0ull));
+                for (;;) {
+                    const int32_t C = s_pop[sl];
+                    const uint64_t D = s_det[sl];
+                    const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
+                    const bool init = absC > d.n_a || D == d.d0;
+                    uint64_t x0, x1, x2, x3, x4, x5;
+                    draw2(d.seed, D, k, d.iter, 0u, x0, x1);
+                    draw2(d.seed, D, k, d.iter, 1u, x2, x3);
+                    draw2(d.seed, D, k, d.iter, 2u, x4, x5);
+                    Excit ex;
+                    if (excite(d, D, x0, x1, x2, x3, s_recip, defer, ex)) {
+                        if (isnan(ex.hel)) {
+                            const int q = atomicAdd(&s_nsgl, 1);
+                            if (q < SGL_QUEUE) {
+                                s_sgl[q] = SingleItem{D, ex.pgen, x4, C,
+                                                      (uint32_t)ex.p | ((uint32_t)ex.a << 8) |
+                                                          ((init ? 1u : 0u) << 16)};
+                            } else {
+                                ex.hel = hel_single(d, D, ex.p, ex.a);
+                            }
+                        }
+                        if (!isnan(ex.hel) && ex.hel != 0.0) {
+                            const int32_t v = accept(d, ex.hel, ex.pgen, x4, C, status);
+                            if (v != 0) {
+                                ++spawned;
+                                const int q = atomicAdd(&s_nspw, 1);
+                                if (q < SPW_QUEUE) {
+                                    s_spd[q] = ex.det;
+                                    s_spv[q] = make_int2(v, init ? 1 : 0);
+                                } else if (!table_add(d.kv, d.cap_mask, ex.det, v, init)) {
+                                    atomicOr(status, ST_TABLE_FULL);
+                                }
+                            }
+                        }
+                    }
+                    if (++at >= at_end) break;
+                    if ((int64_t)(++k) >= absC) {
+                        k = 0;
+                        do ++sl;
+                        while (s_pop[sl] == 0);
+                    }
                 }
-                const int32_t m = (int32_t)fl + (u01(x4) < pr - fl ? 1 : 0);
-                if (m == 0) continue;
-                const int32_t v = ((C > 0) == (ex.hel > 0.0)) ? -m : m;
-                if (!table_add(kvn, d.cap_mask, ex.det, v, init))
-                    atomicOr(&a.desc[s].status, ST_TABLE_FULL);
+            }
+            __syncthreads();
+            // Drain the single-excitation queue: one item per thread.
+            const int nsgl = s_nsgl < SGL_QUEUE ? s_nsgl : SGL_QUEUE;
+            for (int j = t; j < nsgl; j += 256) {
+                const SingleItem it = s_sgl[j];
+                const int p = (int)(it.pai & 0xFFu), q = (int)((it.pai >> 8) & 0xFFu);
+                const double hel = hel_single(d, it.D, p, q);
+                if (hel == 0.0) continue;
+                const int32_t v = accept(d, hel, it.pgen, it.x4, it.C, status);
+                if (v == 0) continue;
                 ++spawned;
+                const uint64_t Dn = it.D ^ (1ull << p) ^ (1ull << q);
+                const bool init = (it.pai >> 16) & 1u;
+                const int qq = atomicAdd(&s_nspw, 1);
+                if (qq < SPW_QUEUE) {
+                    s_spd[qq] = Dn;
+                    s_spv[qq] = make_int2(v, init ? 1 : 0);
+                } else if (!table_add(d.kv, d.cap_mask, Dn, v, init)) {
+                    atomicOr(status, ST_TABLE_FULL);
+                }
+            }
+            __syncthreads();
+            // Drain the spawn queue into the main table: all probes in flight together.
+            const int nspw = s_nspw < SPW_QUEUE ? s_nspw : SPW_QUEUE;
+            for (int j = t; j < nspw; j += 256) {
+                const int2 v = s_spv[j];
+                if (!table_add(d.kv, d.cap_mask, s_spd[j], v.x, v.y != 0))
+                    atomicOr(status, ST_TABLE_FULL);
             }
             // one atomic per wavefront for the spawn counter
-            unsigned long long ws = spawned;
-            for (int o = 32; o > 0; o >>= 1) ws += __shfl_down(ws, o, 64);
-            if ((t & 63) == 0 && ws) atomicAdd(&a.desc[s].spawns, ws);
+            const unsigned long long ws = wave_sum(spawned);
+            if (lane == 0 && ws) atomicAdd(&a.desc[s].spawns, ws);
+            __syncthreads();
+            if (t == 0) {
+                s_nsgl = 0;
+                s_nspw = 0;
+            }
             __syncthreads();
             ++c;
         }
@@ -499,7 +617,7 @@ __device__ __forceinline__ int64_t insert_unique(Slot *kv, uint64_t mask, uint64
     return -1;
 }
 
-constexpr int POST_QUEUE = 512;
+constexpr int POST_QUEUE = 2048;
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
 // ascending (p, q) order from the LDS copies of h_pp and of the pair table.
@@ -514,16 +632,27 @@ __device__ __forceinline__ double hdiag_lds(double e_core, uint64_t det, const d
     return acc;
 }
 
+// Diagonal elements of the queued newly occupied slots, all lanes busy.
+__device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t *queue, int n,
+                                               const double *hpp, const double *jk) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const uint32_t i = queue[j];
+        d.hdiag[i] = hdiag_lds(d.e_core, d.kv[i].det, hpp, jk);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
     __shared__ double s_jk[64 * 64];
     __shared__ double s_hpp[64];
-    __shared__ int s_queue[POST_QUEUE];
+    __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ int s_qn;
-    __shared__ long long shi[256];
-    __shared__ double shd[256];
+    __shared__ long long s_red[4][6];
+    __shared__ double s_redd[4];
     const int64_t nch = *a.nchunks;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     int loaded = -1;
+    if (t == 0) s_qn = 0;
+    __syncthreads();
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const int s = a.chunk_sys[c];
         int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, used = 0;
@@ -531,31 +660,42 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
         const bool live = s >= 0 && participating(a.desc[s]);   // uniform
         if (live) {
             const SysDesc &d = a.desc[s];
-            if (loaded != s) {
+            if (loaded != s || s_qn > POST_QUEUE - CHUNK) {
+                // flush the queue of the previous system (or a nearly full queue)
+                if (loaded >= 0 && s_qn > 0) flush_new_dets(a.desc[loaded], s_queue, s_qn, s_hpp, s_jk);
                 __syncthreads();
-                for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = d.jk[i];
-                for (int i = t; i < d.n_so; i += 256) s_hpp[i] = h_so(d, i, i);
-                loaded = s;
+                if (loaded != s) {
+                    for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = d.jk[i];
+                    for (int i = t; i < d.n_so; i += 256) s_hpp[i] = h_so(d, i, i);
+                    loaded = s;
+                }
+                if (t == 0) s_qn = 0;
+                __syncthreads();
             }
-            if (t == 0) s_qn = 0;
-            __syncthreads();
-            const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-            Slot *kv = d.kv + base;
-            int32_t *pp = d.pop + base;
-            double *hh = d.hdiag + base;
-            for (int i = t; i < CHUNK; i += 256) {
-                const Slot sl = kv[i];
-                if (sl.det == 0) continue;
+            const int64_t base = (int64_t)a.chunk_local[c] * CHUNK + 4 * t;
+            // four consecutive slots per thread, all loads issued before any use
+            Slot sl[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sl[u] = d.kv[base + u];
+            const int4 pv = *reinterpret_cast<const int4 *>(d.pop + base);
+            const double2 h01 = *reinterpret_cast<const double2 *>(d.hdiag + base);
+            const double2 h23 = *reinterpret_cast<const double2 *>(d.hdiag + base + 2);
+            const int32_t pin[4] = {pv.x, pv.y, pv.z, pv.w};
+            const double hin[4] = {h01.x, h01.y, h23.x, h23.y};
+            int32_t pout[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t D = sl[u].det;
+                if (D == 0) continue;
                 ++used;
-                const uint64_t D = sl.det;
-                const int32_t p = pp[i];
+                const int32_t p = pin[u];
                 int64_t pd = p;
                 if (p != 0) {
                     // Eq. pdeath, one stochastic rounding for the whole determinant.
                     uint64_t xd, xu;
                     draw2(d.seed, D, 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
                     const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
-                    const double dv = ((hh[i] - d.e0) - d.shift) * d.tau * (double)absC;
+                    const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
                     const double ad = fabs(dv);
                     const double fl = floor(ad);
                     if (fl > 1073741824.0) {
@@ -568,11 +708,11 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                 // Annihilation (Sec. 4.2): present after death -> add; otherwise the
                 // arrived walkers survive only if an initiator sent some of them.
                 const bool present = pd != 0 || D == d.d0;
-                const int64_t sp = sl.spop;
+                const int64_t sp = sl[u].spop;
                 int64_t np;
                 if (present) {
                     np = pd + sp;
-                } else if (sp != 0 && sl.sflag) {
+                } else if (sp != 0 && sl[u].sflag) {
                     np = sp;
                 } else {
                     np = 0;
@@ -583,14 +723,13 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                     atomicOr(&a.desc[s].status, ST_POP_OVERFLOW);
                     np = 0;
                 }
-                if (np != p) pp[i] = (int32_t)np;
-                if (sl.spop != 0 || sl.sflag != 0)
-                    *reinterpret_cast<unsigned long long *>(&kv[i].spop) = 0ull;
-                if (np != 0 && isnan(hh[i])) {
-                    // newly occupied: its diagonal element is computed below
+                pout[u] = (int32_t)np;
+                if (sl[u].spop != 0 || sl[u].sflag != 0)
+                    *reinterpret_cast<unsigned long long *>(&d.kv[base + u].spop) = 0ull;
+                if (np != 0 && p == 0 && isnan(hin[u])) {
+                    // newly occupied: diagonal element computed with the queue
                     const int q = atomicAdd(&s_qn, 1);
-                    if (q < POST_QUEUE) s_queue[q] = i;
-                    else hh[i] = hdiag_lds(d.e_core, D, s_hpp, s_jk);
+                    s_queue[q] = (uint32_t)(base + u);
                 }
                 if (D == d.d0) c0 = np;
                 if (np != 0) {
@@ -599,22 +738,43 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                     if (D != d.d0 && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
                 }
             }
-            __syncthreads();
-            const int nq = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
-            for (int j = t; j < nq; j += 256) {
-                const int i = s_queue[j];
-                hh[i] = hdiag_lds(d.e_core, kv[i].det, s_hpp, s_jk);
-            }
+            if (pout[0] != pin[0] || pout[1] != pin[1] || pout[2] != pin[2] || pout[3] != pin[3])
+                *reinterpret_cast<int4 *>(d.pop + base) = make_int4(pout[0], pout[1], pout[2], pout[3]);
         }
-        nw = block_sum((long long)nw, shi);
-        nd = block_sum((long long)nd, shi);
-        c0 = block_sum((long long)c0, shi);
-        merged = block_sum((long long)merged, shi);
-        aborted = block_sum((long long)aborted, shi);
-        used = block_sum((long long)used, shi);
-        num = block_sum(num, shd);
-        if (t == 0) a.chunk_stat[c] = ChunkStat{nw, nd, c0, merged, aborted, used, num};
+        // fixed-order reduction: lane butterfly, then waves 0..3
+        nw = wave_sum((long long)nw);
+        nd = wave_sum((long long)nd);
+        c0 = wave_sum((long long)c0);
+        merged = wave_sum((long long)merged);
+        aborted = wave_sum((long long)aborted);
+        used = wave_sum((long long)used);
+        num = wave_sum(num);
+        if (lane == 0) {
+            s_red[wid][0] = nw;
+            s_red[wid][1] = nd;
+            s_red[wid][2] = c0;
+            s_red[wid][3] = merged;
+            s_red[wid][4] = aborted;
+            s_red[wid][5] = used;
+            s_redd[wid] = num;
+        }
+        __syncthreads();
+        if (t == 0) {
+            ChunkStat cs{0, 0, 0, 0, 0, 0, 0.0};
+            for (int w = 0; w < 4; ++w) {
+                cs.nw += s_red[w][0];
+                cs.nd += s_red[w][1];
+                cs.c0 += s_red[w][2];
+                cs.merged += s_red[w][3];
+                cs.aborted += s_red[w][4];
+                cs.used += s_red[w][5];
+                cs.num = cs.num + s_redd[w];
+            }
+            a.chunk_stat[c] = cs;
+        }
+        __syncthreads();
     }
+    if (loaded >= 0 && s_qn > 0) flush_new_dets(a.desc[loaded], s_queue, s_qn, s_hpp, s_jk);
 }
 
 // ---------------------------------------------------------------------------
