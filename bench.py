@@ -192,6 +192,23 @@ def pmc_summary(path, last=0):
         print(f"{name:44s} {ctr:22s} dispatches {len(vals):5d} mean {sum(vals) / len(vals):.6g}")
 
 
+def served(F, S, n_requests, scale, max_iters, seed=5):
+    """Poisson request stream (mean 20 req/s) served with continuous batching."""
+    from paper_1305_6981_amd import serve
+    reqs = []
+    for i, (t, ham, prm) in enumerate(S.serve_requests(n=n_requests, rate=20.0, seed=seed,
+                                                       scale=scale)):
+        prm.avg_start = 0
+        prm.initial_walkers = max(10, prm.target_walkers // 2)
+        reqs.append(serve.Request(ham, prm, arrival=t, max_iters=max_iters, tag=i))
+    srv = serve.SolveServer(max_slots=32, chunk_iters=64, tol=1e-3, min_samples=128)
+    stats = srv.run(reqs)
+    out = stats.summary()
+    out["requests_scale"] = scale
+    out["max_iters"] = max_iters
+    return out
+
+
 def main():
     if len(sys.argv) >= 3 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 0)
@@ -207,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-scale", type=float, default=0.2)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=40)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="add a 1 GiB device copy in its own profiled region")
     args = ap.parse_args()
@@ -297,6 +316,9 @@ def main():
     if not args.no_batched:
         log("[bench] batched vs plain (64 systems)")
         out["batched"] = batched_vs_plain(F, S, 100, args.batched_scale)
+    if not args.no_served:
+        log("[bench] served Poisson stream")
+        out["served"] = served(F, S, args.served_requests, 0.1, 2000)
     print(json.dumps(out), flush=True)
 
 

@@ -1,0 +1,138 @@
+"""Continuous-batching FCIQMC solve server over the C ABI.
+
+Requests (a Hamiltonian, run parameters and an arrival time) are admitted into
+the slots of one batch handle as soon as a slot is free and their tables fit
+in device memory (``fciqmc_batch_admit`` checks the ~32 B/slot footprint of the
+walker target against free HBM and fails with ENOMEM otherwise). All admitted
+systems advance together in graph-captured launches; each runs until its
+projected-energy error bar reaches the tolerance (with a minimum number of
+averaged iterations) or until its iteration budget is spent, then it is
+retired and its slot and memory are reused. Requests that arrive while others
+run are admitted between launches, so their work overlaps on the device.
+
+Each system's trajectory depends only on its own inputs and its own iteration
+count (the random numbers are keyed by determinant and iteration, merges are
+integer sums), so a result is identical whether it was served alone or in the
+mix.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fciqmc as F
+
+
+@dataclass
+class Request:
+    ham: object
+    params: object
+    arrival: float = 0.0          # seconds after the server starts
+    max_iters: int = 20000
+    tag: object = None
+
+
+@dataclass
+class Result:
+    tag: object
+    arrival: float
+    admitted: float
+    finished: float
+    iterations: int
+    e_proj: float
+    e_proj_err: float
+    shift_energy: float
+    attempts: int
+    converged: bool
+    walkers: tuple | None = None
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+@dataclass
+class ServerStats:
+    results: list = field(default_factory=list)
+    wall_s: float = 0.0
+    launches: int = 0
+    peak_active: int = 0
+
+    def summary(self):
+        lat = np.array([r.latency for r in self.results]) if self.results else np.zeros(1)
+        att = sum(r.attempts for r in self.results)
+        return {"requests": len(self.results), "wall_s": self.wall_s,
+                "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99)),
+                "throughput_req_per_s": len(self.results) / max(self.wall_s, 1e-9),
+                "attempts_per_s": att / max(self.wall_s, 1e-9),
+                "converged": sum(1 for r in self.results if r.converged),
+                "launches": self.launches, "peak_active": self.peak_active}
+
+
+class SolveServer:
+    def __init__(self, max_slots=16, chunk_iters=64, tol=1e-3, min_samples=256,
+                 keep_walkers=False, stream=None, clock=time.perf_counter):
+        self.max_slots = max_slots
+        self.chunk_iters = chunk_iters
+        self.tol = tol
+        self.min_samples = min_samples
+        self.keep_walkers = keep_walkers
+        self.stream = stream if stream is not None else F.current_stream()
+        self.clock = clock
+
+    def run(self, requests):
+        """Serve `requests` (arrival times in seconds from now); returns ServerStats."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        h = F.fciqmc_batch_create(self.max_slots, [], [], self.stream)
+        active = {}          # slot -> (request, admitted_at, iterations_done)
+        stats = ServerStats()
+        t0 = self.clock()
+        try:
+            while pending or active:
+                now = self.clock() - t0
+                # admit arrived requests while slots and memory allow
+                while pending and pending[0].arrival <= now and len(active) < self.max_slots:
+                    req = pending[0]
+                    try:
+                        slot = F.fciqmc_batch_admit(h, req.ham, req.params)
+                    except F.FciqmcError as e:
+                        if e.code == -2 and active:      # ENOMEM: wait for a retirement
+                            break
+                        raise
+                    pending.pop(0)
+                    active[slot] = [req, now, 0]
+                stats.peak_active = max(stats.peak_active, len(active))
+                if not active:
+                    # idle until the next arrival
+                    wait = pending[0].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                    continue
+                n = np.zeros(self.max_slots, np.int32)
+                for slot, (req, _, done) in active.items():
+                    n[slot] = min(self.chunk_iters, req.max_iters - done)
+                F.fciqmc_batch_iterate_each(h, n)
+                stats.launches += 1
+                now = self.clock() - t0
+                for slot in list(active):
+                    req, adm, done = active[slot]
+                    done += int(n[slot])
+                    active[slot][2] = done
+                    e = F.fciqmc_batch_slot_estimators(h, slot)
+                    conv = (e["n_samples"] >= self.min_samples and np.isfinite(e["e_proj_err"])
+                            and e["e_proj_err"] <= self.tol)
+                    if conv or done >= req.max_iters:
+                        walkers = F.fciqmc_batch_slot_walkers(h, slot) if self.keep_walkers else None
+                        stats.results.append(Result(
+                            req.tag, req.arrival, adm, now, done, e["e_proj_mean"],
+                            e["e_proj_err"], e["shift_mean"], e["total_attempts"], bool(conv),
+                            walkers))
+                        F.fciqmc_batch_retire(h, slot)
+                        del active[slot]
+        finally:
+            F.fciqmc_free(h)
+        stats.wall_s = self.clock() - t0
+        return stats
