@@ -52,6 +52,7 @@ struct SysDesc {
     uint64_t irr_packed[2];          // 4 bits per spatial orbital
     const double *h1, *eri;
     const double *jk;                // [n_so][64]: (pp|qq) - (pq|qp) for p < q, spin orbitals
+    const double *t3;                // [n_so][64][64]: (pa|qq) - d(s_p,s_q)(pq|qa), same-spin p, a
     Slot *kv;                        // main table: key + spawned walkers of this iteration
     int32_t *pop;                    // signed walker count (0: vacated or not yet occupied)
     double *hdiag;                   // stored H_DD; NaN until the determinant is first occupied

@@ -138,6 +138,8 @@ struct SysHost {
     double *hd = nullptr;
     double *d_h1 = nullptr, *d_eri = nullptr, *d_jk = nullptr;
     std::vector<double> jk;    // [n_so][64] pair table
+    std::vector<double> t3;    // [n_so][64][64] single-excitation term table
+    double *d_t3 = nullptr;
     int64_t growth = 0;        // expected per-iteration increase of used slots
     int64_t reserve_bytes = 0; // admission accounting (target footprint)
     // mirrored dynamics and statistics
@@ -271,7 +273,7 @@ int64_t table_bytes(int64_t cap) {
 
 int64_t integral_doubles(int M) {
     const int64_t np = (int64_t)M * (M + 1) / 2;
-    return (int64_t)M * M + np * (np + 1) / 2 + 64 * 64;
+    return (int64_t)M * M + np * (np + 1) / 2 + 64 * 64 + (int64_t)2 * M * 64 * 64;
 }
 
 int64_t integral_bytes(int M) { return integral_doubles(M) * 8 + 256; }
@@ -317,6 +319,8 @@ void carve(SysHost &S, void *blk, int64_t cap) {
     S.d_eri = (double *)p;
     p += (size_t)S.eri.size() * sizeof(double);
     S.d_jk = (double *)p;
+    p += 64 * 64 * sizeof(double);
+    S.d_t3 = (double *)p;
     S.block = blk;
     S.cap = cap;
 }
@@ -325,6 +329,7 @@ int upload_integrals(fciqmc_t *h, SysHost &S) {
     HIP_TRY(hipMemcpyAsync(S.d_h1, S.h1.data(), S.h1.size() * 8, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(S.d_eri, S.eri.data(), S.eri.size() * 8, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(S.d_jk, S.jk.data(), S.jk.size() * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(S.d_t3, S.t3.data(), S.t3.size() * 8, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return 0;
 }
@@ -338,6 +343,7 @@ void fill_desc_tables(fciqmc_t *h, int s) {
     d.h1 = S.d_h1;
     d.eri = S.d_eri;
     d.jk = S.d_jk;
+    d.t3 = S.d_t3;
     d.cap_mask = (uint64_t)(S.cap - 1);
 }
 
@@ -505,6 +511,18 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
             const double coul = eri_sp(p >> 1, p >> 1, q >> 1, q >> 1);
             const double exch = ((p ^ q) & 1) ? 0.0 : eri_sp(p >> 1, q >> 1, q >> 1, p >> 1);
             S.jk[p * 64 + q] = coul - exch;
+        }
+    // Single-excitation terms: for p -> a (same spin) and each spectator q,
+    // (pa|qq) - [same spin](pq|qa), the difference the Slater-Condon sum adds.
+    S.t3.assign((size_t)nso * 64 * 64, 0.0);
+    for (int p = 0; p < nso; ++p)
+        for (int a = 0; a < nso; ++a) {
+            if ((p ^ a) & 1) continue;
+            for (int q = 0; q < nso; ++q) {
+                const double coul = eri_sp(p >> 1, a >> 1, q >> 1, q >> 1);
+                const double exch = ((p ^ q) & 1) ? 0.0 : eri_sp(p >> 1, q >> 1, q >> 1, a >> 1);
+                S.t3[((size_t)p * 64 + a) * 64 + q] = coul - exch;
+            }
         }
     const int64_t cap = initial_capacity(prm);
     void *blk = nullptr;

@@ -147,11 +147,28 @@ __device__ double hdiag_of(const SysDesc &d, uint64_t det) {
     return acc;
 }
 
+// Single excitation p -> a: h_pa + sum over occupied q != p (ascending) of
+// (pa|qq) - [same spin](pq|qa), each term read from the precomputed row
+// t3[p][a][*]; four loads are issued before they are added, in order.
 __device__ double hel_single(const SysDesc &d, uint64_t det, int p, int a) {
     double acc = h_so(d, p, a);
-    for (uint64_t m = det & ~(1ull << p); m; m &= m - 1) {
-        const int q = __builtin_ctzll(m);
-        acc = acc + (eri_so(d, p, a, q, q) - eri_so(d, p, q, q, a));
+    const double *row = d.t3 + ((p * 64 + a) << 6);
+    uint64_t m = det & ~(1ull << p);
+    while (m) {
+        const int q0 = __builtin_ctzll(m);
+        m &= m - 1;
+        const int q1 = m ? __builtin_ctzll(m) : q0;
+        m &= m - 1;
+        const int q2 = m ? __builtin_ctzll(m) : q0;
+        m &= m - 1;
+        const int q3 = m ? __builtin_ctzll(m) : q0;
+        const int n = 1 + (q1 != q0) + (q2 != q0) + (q3 != q0);
+        m &= m - 1;
+        const double v0 = row[q0], v1 = row[q1], v2 = row[q2], v3 = row[q3];
+        acc = acc + v0;
+        if (n > 1) acc = acc + v1;
+        if (n > 2) acc = acc + v2;
+        if (n > 3) acc = acc + v3;
     }
     return between_parity(det, p, a) ? -acc : acc;
 }
@@ -414,6 +431,8 @@ struct SingleItem {
 
 constexpr int SGL_QUEUE = 256;
 constexpr int SPW_QUEUE = 512;
+constexpr int SGL_DRAIN = 64;     // drain the queues once they hold this many items
+constexpr int SPW_DRAIN = 256;
 
 __device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double pgen, uint64_t x4,
                                           int32_t C, uint32_t *status) {
@@ -427,6 +446,54 @@ __device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double p
     return ((C > 0) == (hel > 0.0)) ? -m : m;
 }
 
+struct SpawnQueues {
+    SingleItem sgl[SGL_QUEUE];
+    uint64_t spd[SPW_QUEUE];
+    int2 spv[SPW_QUEUE];   // (signed walkers, initiator flag)
+    int nsgl, nspw, sys;
+};
+
+// Drain both queues of system d with the whole workgroup (call uniformly).
+__device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
+                             unsigned long long *spawns) {
+    __syncthreads();
+    const int t = threadIdx.x;
+    unsigned long long spawned = 0;
+    const int nsgl = Q.nsgl < SGL_QUEUE ? Q.nsgl : SGL_QUEUE;
+    for (int j = t; j < nsgl; j += blockDim.x) {
+        const SingleItem it = Q.sgl[j];
+        const int p = (int)(it.pai & 0xFFu), q = (int)((it.pai >> 8) & 0xFFu);
+        const double hel = hel_single(d, it.D, p, q);
+        if (hel == 0.0) continue;
+        const int32_t v = accept(d, hel, it.pgen, it.x4, it.C, status);
+        if (v == 0) continue;
+        ++spawned;
+        const uint64_t Dn = it.D ^ (1ull << p) ^ (1ull << q);
+        const bool init = (it.pai >> 16) & 1u;
+        const int qq = atomicAdd(&Q.nspw, 1);
+        if (qq < SPW_QUEUE) {
+            Q.spd[qq] = Dn;
+            Q.spv[qq] = make_int2(v, init ? 1 : 0);
+        } else if (!table_add(d.kv, d.cap_mask, Dn, v, init)) {
+            atomicOr(status, ST_TABLE_FULL);
+        }
+    }
+    const unsigned long long ws = wave_sum(spawned);
+    if ((t & 63) == 0 && ws) atomicAdd(spawns, ws);
+    __syncthreads();
+    const int nspw = Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE;
+    for (int j = t; j < nspw; j += blockDim.x) {
+        const int2 v = Q.spv[j];
+        if (!table_add(d.kv, d.cap_mask, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
+    }
+    __syncthreads();
+    if (t == 0) {
+        Q.nsgl = 0;
+        Q.nspw = 0;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
     __shared__ unsigned long long s_incl[CHUNK];
     __shared__ uint64_t s_det[CHUNK];
@@ -434,18 +501,16 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
     __shared__ unsigned long long s_wsum[4];
     __shared__ long long s_c;
     __shared__ double s_recip[65];
-    __shared__ SingleItem s_sgl[SGL_QUEUE];
-    __shared__ uint64_t s_spd[SPW_QUEUE];
-    __shared__ int2 s_spv[SPW_QUEUE];   // (signed walkers, initiator flag)
-    __shared__ int s_nsgl, s_nspw;
+    __shared__ SpawnQueues Q;
     const unsigned long long total = *a.total;
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     if (t > 0 && t <= 64) s_recip[t] = 1.0 / (double)t;
     if (t == 0) {
         s_recip[0] = 0.0;
-        s_nsgl = 0;
-        s_nspw = 0;
+        Q.nsgl = 0;
+        Q.nspw = 0;
+        Q.sys = -1;
     }
     __syncthreads();
     for (unsigned long long t0 = (unsigned long long)blockIdx.x * SPAWN_TILE; t0 < total;
@@ -474,6 +539,13 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
             const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
             const SysDesc &d = a.desc[s];
             uint32_t *status = &a.desc[s].status;
+            if (Q.sys != s) {
+                // queued work belongs to another system: finish it first
+                if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0))
+                    drain_queues(Q, a.desc[Q.sys], &a.desc[Q.sys].status, &a.desc[Q.sys].spawns);
+                __syncthreads();
+                if (t == 0) Q.sys = s;
+            }
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
             // Stage keys and populations; prefix sum of |C| (4 consecutive slots per thread).
             const int4 pv = reinterpret_cast<const int4 *>(d.pop + base)[t];
@@ -528,9 +600,9 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
                     Excit ex;
                     if (excite(d, D, x0, x1, x2, x3, s_recip, defer, ex)) {
                         if (isnan(ex.hel)) {
-                            const int q = atomicAdd(&s_nsgl, 1);
+                            const int q = atomicAdd(&Q.nsgl, 1);
                             if (q < SGL_QUEUE) {
-                                s_sgl[q] = SingleItem{D, ex.pgen, x4, C,
+                                Q.sgl[q] = SingleItem{D, ex.pgen, x4, C,
                                                       (uint32_t)ex.p | ((uint32_t)ex.a << 8) |
                                                           ((init ? 1u : 0u) << 16)};
                             } else {
@@ -541,10 +613,10 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
                             const int32_t v = accept(d, ex.hel, ex.pgen, x4, C, status);
                             if (v != 0) {
                                 ++spawned;
-                                const int q = atomicAdd(&s_nspw, 1);
+                                const int q = atomicAdd(&Q.nspw, 1);
                                 if (q < SPW_QUEUE) {
-                                    s_spd[q] = ex.det;
-                                    s_spv[q] = make_int2(v, init ? 1 : 0);
+                                    Q.spd[q] = ex.det;
+                                    Q.spv[q] = make_int2(v, init ? 1 : 0);
                                 } else if (!table_add(d.kv, d.cap_mask, ex.det, v, init)) {
                                     atomicOr(status, ST_TABLE_FULL);
                                 }
@@ -559,47 +631,18 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
                     }
                 }
             }
-            __syncthreads();
-            // Drain the single-excitation queue: one item per thread.
-            const int nsgl = s_nsgl < SGL_QUEUE ? s_nsgl : SGL_QUEUE;
-            for (int j = t; j < nsgl; j += 256) {
-                const SingleItem it = s_sgl[j];
-                const int p = (int)(it.pai & 0xFFu), q = (int)((it.pai >> 8) & 0xFFu);
-                const double hel = hel_single(d, it.D, p, q);
-                if (hel == 0.0) continue;
-                const int32_t v = accept(d, hel, it.pgen, it.x4, it.C, status);
-                if (v == 0) continue;
-                ++spawned;
-                const uint64_t Dn = it.D ^ (1ull << p) ^ (1ull << q);
-                const bool init = (it.pai >> 16) & 1u;
-                const int qq = atomicAdd(&s_nspw, 1);
-                if (qq < SPW_QUEUE) {
-                    s_spd[qq] = Dn;
-                    s_spv[qq] = make_int2(v, init ? 1 : 0);
-                } else if (!table_add(d.kv, d.cap_mask, Dn, v, init)) {
-                    atomicOr(status, ST_TABLE_FULL);
-                }
-            }
-            __syncthreads();
-            // Drain the spawn queue into the main table: all probes in flight together.
-            const int nspw = s_nspw < SPW_QUEUE ? s_nspw : SPW_QUEUE;
-            for (int j = t; j < nspw; j += 256) {
-                const int2 v = s_spv[j];
-                if (!table_add(d.kv, d.cap_mask, s_spd[j], v.x, v.y != 0))
-                    atomicOr(status, ST_TABLE_FULL);
-            }
             // one atomic per wavefront for the spawn counter
             const unsigned long long ws = wave_sum(spawned);
             if (lane == 0 && ws) atomicAdd(&a.desc[s].spawns, ws);
             __syncthreads();
-            if (t == 0) {
-                s_nsgl = 0;
-                s_nspw = 0;
-            }
-            __syncthreads();
+            if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN)
+                drain_queues(Q, d, status, &a.desc[s].spawns);
             ++c;
         }
     }
+    __syncthreads();
+    if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0))
+        drain_queues(Q, a.desc[Q.sys], &a.desc[Q.sys].status, &a.desc[Q.sys].spawns);
 }
 
 // ---------------------------------------------------------------------------
