@@ -31,6 +31,13 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit vector lane-operations per second
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic 32-bit lane-operations of one spawning attempt (itemised in the design doc):
+# three Philox4x32-10 blocks (300), index draws (18), excitation selection (126),
+# Slater-Condon double element (26), pgen (15), acceptance (16).
+OPS_PER_ATTEMPT = 500
+PROFILES = os.path.join(ROOT, "profiles")
 KERNELS = ["k_chunk_sum", "k_scan", "k_spawn", "k_post", "k_finalize"]
 
 
@@ -90,6 +97,32 @@ def bytes_per_kernel(rec, n_slots):
         # per attempt: key + population of its source slot; per spawn: one 16-byte slot update
         "k_spawn": 12.0 * rec["attempts"] + 16.0 * spawns,
     }
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1305_6981_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, scaled by the
+    copy-kernel calibration; None when the summary is missing or the kernels changed since."""
+    path = os.path.join(PROFILES, f"{kernel}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernels_sha256") != kernel_source_hash():
+        return None
+    try:
+        return (float(vals["fetch_bytes_per_launch"]) * float(vals["fetch_calibration"]) +
+                float(vals["write_bytes_per_launch"]) * float(vals["write_calibration"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(ham, prm, det, pop, e, budget_attempts):
@@ -283,13 +316,22 @@ def main():
     rec = {"n_dets": e1["n_dets"], "spawns": spawns / args.steps, "merged": e1["merged"],
            "attempts": attempts / args.steps}
     bpk = bytes_per_kernel(rec, n_slots)
-    if dominant in bpk:
-        achieved = bpk[dominant] / (avg_ms[dominant] * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": None, "avg_ms": avg_ms[dominant]}
+
+    def hbm_roofline(k):
+        achieved = bpk[k] / (avg_ms[k] * 1e-3) / 1e9
+        return {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(k),
+                "algorithmic_bytes": bpk[k], "avg_ms": avg_ms[k]}
+
+    if dominant == "k_spawn":
+        ops = OPS_PER_ATTEMPT * rec["attempts"]
+        achieved = ops / (avg_ms[dominant] * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved,
+                    "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / ALU_PEAK_TOPS,
+                    "traffic": measured_traffic(dominant), "ops_per_attempt": OPS_PER_ATTEMPT,
+                    "attempts_per_launch": rec["attempts"], "avg_ms": avg_ms[dominant]}
     else:
-        roofline = None
+        roofline = hbm_roofline(dominant)
 
     out = {
         "metric": "spawn attempts/s + annihilated dets/s at 1e8 walkers; batched vs plain",
@@ -306,6 +348,7 @@ def main():
                    "parallelism": "1 GPU"},
         "kernel_avg_ms": avg_ms,
         "roofline": roofline,
+        "roofline_k_post": hbm_roofline("k_post"),
     }
     sv_e = e1
     if not args.no_cpu_baseline:

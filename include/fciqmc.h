@@ -206,6 +206,20 @@ int32_t fciqmc_batch_active(fciqmc_t *h);
 int fciqmc_set_profiling(fciqmc_t *h, int32_t on);
 int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
 
+/* ---- launch shape ----------------------------------------------------------
+ * spawn_grid: workgroups of the spawning kernel; tile: consecutive attempts a
+ * workgroup takes at a time (256 .. 2^20); post_grid: workgroups of the
+ * death/annihilation kernel. Results never depend on these (every random
+ * number is keyed by determinant and walker ordinal, every merge is an
+ * integer sum). fciqmc_autotune runs iters_per_trial real iterations of every
+ * active system for each candidate shape (spawn grid 2/4/8/16 x CUs, tile
+ * 1024/2048/4096, then post grid 1/2/4/8 x CUs), keeps the shape with the
+ * lowest kernel time per attempt (per slot for the post kernel), and leaves
+ * the systems advanced by those iterations. */
+int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t post_grid);
+int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *post_grid);
+int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial);
+
 #ifdef __cplusplus
 }
 #endif

@@ -71,7 +71,7 @@ struct SysDesc {
 struct EngineArgs {
     SysDesc *desc;
     int32_t max_sys;
-    int32_t pad;
+    int32_t tile;                    // attempts per spawn-kernel tile
     const int32_t *chunk_sys;        // system of each global chunk (-1: unused)
     const int32_t *chunk_local;      // chunk index inside its system's table
     unsigned long long *chunk_nw;    // sum |C| per chunk (this iteration's attempts)

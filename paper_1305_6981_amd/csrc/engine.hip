@@ -170,6 +170,7 @@ struct fciqmc_t {
     uint32_t *d_err = nullptr;
     int spawn_grid = 2048;
     int post_grid = 1024;
+    int tile = 2048;
     std::map<int, hipGraphExec_t> graphs;
     bool use_graph = true;
     bool profiling = false;
@@ -193,6 +194,7 @@ EngineArgs make_args(fciqmc_t *h) {
     a.total = h->d_total;
     a.nchunks = h->d_nchunks;
     a.rec = h->d_rec;
+    a.tile = h->tile;
     return a;
 }
 
@@ -1174,6 +1176,93 @@ int fciqmc_set_profiling(fciqmc_t *h, int32_t on) {
         h->kms[k] = 0.0;
         h->kcount[k] = 0;
     }
+    return 0;
+}
+
+int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t post_grid) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    if (spawn_grid < 1 || post_grid < 1 || tile < 256 || tile > (1 << 20))
+        return set_err(FCIQMC_EINVAL, "launch shape out of range");
+    h->spawn_grid = spawn_grid;
+    h->post_grid = post_grid;
+    h->tile = tile;
+    drop_graphs(h);
+    return 0;
+}
+
+int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *post_grid) {
+    if (!h || !spawn_grid || !tile || !post_grid) return set_err(FCIQMC_EINVAL, "null argument");
+    *spawn_grid = h->spawn_grid;
+    *tile = h->tile;
+    *post_grid = h->post_grid;
+    return 0;
+}
+
+int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
+    if (!h || iters_per_trial < 1) return set_err(FCIQMC_EINVAL, "bad argument");
+    int cus = fq::spawn_grid_size() / 8;
+    const bool was = h->profiling;
+    h->profiling = true;
+    auto trial = [&](int sg, int tl, int pg, double &spawn_ns, double &post_ns) -> int {
+        h->spawn_grid = sg;
+        h->tile = tl;
+        h->post_grid = pg;
+        for (int k = 0; k < 5; ++k) {
+            h->kms[k] = 0.0;
+            h->kcount[k] = 0;
+        }
+        int64_t a0 = 0;
+        for (auto &S : h->sys) a0 += S.active ? S.tot_att : 0;
+        std::vector<int64_t> n(h->max_sys, iters_per_trial);
+        int rc = iterate_each(h, n);
+        if (rc) return rc;
+        int64_t a1 = 0, slots = 0;
+        for (auto &S : h->sys) {
+            a1 += S.active ? S.tot_att : 0;
+            slots += S.active ? S.cap : 0;
+        }
+        spawn_ns = h->kms[2] * 1e6 / (double)std::max<int64_t>(a1 - a0, 1);
+        post_ns = h->kms[3] * 1e6 / (double)std::max<int64_t>(slots * iters_per_trial, 1);
+        return 0;
+    };
+    int best_sg = h->spawn_grid, best_tl = h->tile, best_pg = h->post_grid;
+    double best_s = 1e300, best_p = 1e300;
+    const int sgs[4] = {2, 4, 8, 16}, tls[3] = {1024, 2048, 4096}, pgs[4] = {1, 2, 4, 8};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double sn, pn;
+            int rc = trial(sgs[i] * cus, tls[j], best_pg, sn, pn);
+            if (rc) {
+                h->profiling = was;
+                return rc;
+            }
+            if (sn < best_s) {
+                best_s = sn;
+                best_sg = sgs[i] * cus;
+                best_tl = tls[j];
+            }
+        }
+    for (int i = 0; i < 4; ++i) {
+        double sn, pn;
+        int rc = trial(best_sg, best_tl, pgs[i] * cus, sn, pn);
+        if (rc) {
+            h->profiling = was;
+            return rc;
+        }
+        if (pn < best_p) {
+            best_p = pn;
+            best_pg = pgs[i] * cus;
+        }
+    }
+    h->spawn_grid = best_sg;
+    h->tile = best_tl;
+    h->post_grid = best_pg;
+    h->profiling = was;
+    for (int k = 0; k < 5; ++k) {
+        h->kms[k] = 0.0;
+        h->kcount[k] = 0;
+    }
+    drop_graphs(h);
     return 0;
 }
 

@@ -394,7 +394,6 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
 // consecutive attempts: (slot, walker ordinal k) by one binary search, then
 // k+1 / next occupied slot.
 // ---------------------------------------------------------------------------
-constexpr int SPAWN_TILE = 2048;
 
 __device__ __forceinline__ bool table_add(Slot *kv, uint64_t mask, uint64_t key, int32_t v,
                                           bool init) {
@@ -513,9 +512,10 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
         Q.sys = -1;
     }
     __syncthreads();
-    for (unsigned long long t0 = (unsigned long long)blockIdx.x * SPAWN_TILE; t0 < total;
-         t0 += (unsigned long long)gridDim.x * SPAWN_TILE) {
-        const unsigned long long t1 = (t0 + SPAWN_TILE < total) ? t0 + SPAWN_TILE : total;
+    const unsigned long long tile = (unsigned long long)a.tile;
+    for (unsigned long long t0 = (unsigned long long)blockIdx.x * tile; t0 < total;
+         t0 += (unsigned long long)gridDim.x * tile) {
+        const unsigned long long t1 = (t0 + tile < total) ? t0 + tile : total;
         if (t == 0) {
             int64_t lo = 0, hi = nch;  // first chunk with offset > t0
             while (lo < hi) {

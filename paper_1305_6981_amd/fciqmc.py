@@ -57,7 +57,8 @@ EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
             "fciqmc_batch_create", "fciqmc_batch_iterate", "fciqmc_batch_iterate_each",
             "fciqmc_batch_admit", "fciqmc_batch_retire", "fciqmc_batch_slot_estimators",
             "fciqmc_batch_slot_walkers", "fciqmc_footprint_bytes", "fciqmc_batch_active",
-            "fciqmc_set_profiling", "fciqmc_kernel_times"]
+            "fciqmc_set_profiling", "fciqmc_kernel_times", "fciqmc_set_launch",
+            "fciqmc_get_launch", "fciqmc_autotune"]
 
 
 def lib():
@@ -89,6 +90,9 @@ def lib():
             "fciqmc_batch_active": ([vp], i32),
             "fciqmc_set_profiling": ([vp, i32], C.c_int),
             "fciqmc_kernel_times": ([vp, vp, vp], C.c_int),
+            "fciqmc_set_launch": ([vp, i32, i32, i32], C.c_int),
+            "fciqmc_get_launch": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], C.c_int),
+            "fciqmc_autotune": ([vp, i32], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -267,6 +271,21 @@ def fciqmc_kernel_times(handle):
     cnt = np.zeros(5, np.int64)
     _check(lib().fciqmc_kernel_times(handle, _ptr(ms), _ptr(cnt)))
     return ms, cnt
+
+
+def fciqmc_set_launch(handle, spawn_grid, tile, post_grid):
+    _check(lib().fciqmc_set_launch(handle, spawn_grid, tile, post_grid))
+
+
+def fciqmc_get_launch(handle):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().fciqmc_get_launch(handle, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def fciqmc_autotune(handle, iters_per_trial=2):
+    _check(lib().fciqmc_autotune(handle, iters_per_trial))
+    return fciqmc_get_launch(handle)
 
 
 class Solver:

@@ -58,8 +58,27 @@ def _run_pair(ham, prm, blocks, per_block, tag):
 
 def test_hubbard8_plain_bit_exact():
     ham, prm, _ = S.workload("hubbard8")
-    eg = _run_pair(ham, prm, blocks=6, per_block=50, tag="hubbard8")
+    prm.avg_start = 20
+    eg = _run_pair(ham, prm, blocks=8, per_block=50, tag="hubbard8")
     assert eg["n_walkers"] > 1000
+
+
+def test_estimator_averages_and_error_bars_match():
+    """Blocking means and error bars of E_proj and the shift agree with the oracle's
+    (the series are identical up to the summation order of the numerator)."""
+    ham, prm, _ = S.workload("hubbard8")
+    prm.avg_start = 0
+    print("[gpu] averages", flush=True)
+    gpu = F.Solver(ham, prm, _stream())
+    ref = O.Oracle(ham, prm)
+    gpu.iterate(700)
+    ref.iterate(700)
+    eg, eo = gpu.estimates(), ref.estimates()
+    assert eg["n_samples"] == eo["n_samples"] and eg["n_samples"] > 300
+    for k in ("e_proj_mean", "e_proj_err", "shift_mean", "shift_err"):
+        assert np.isfinite(eo[k]), k
+        assert abs(eg[k] - eo[k]) <= 1e-10 * max(1.0, abs(eo[k])), (k, eg[k], eo[k])
+    gpu.close()
 
 
 def test_synthetic_initiator_bit_exact():
@@ -128,3 +147,26 @@ def test_zero_iterations_and_errors():
     bad = S.Params(tau=-1.0)
     with pytest.raises(F.FciqmcError):
         F.Solver(ham, bad, _stream())
+
+
+def test_launch_shape_and_autotune_are_result_neutral():
+    ham, prm, _ = S.workload("synth24e30o", scale=2e-5)
+    prm.initial_walkers, prm.initial_shift, prm.tau = 300, 1.0, 2e-3
+    print("[gpu] launch shapes", flush=True)
+    runs = []
+    for shape in [(64, 256, 16), (4096, 4096, 2048), None]:
+        sv = F.Solver(ham, prm, _stream())
+        if shape is None:
+            F.fciqmc_autotune(sv.h, 1)        # 16 trial launches of one iteration each
+            sv.iterate(40 - sv.estimates()["iteration"])
+        else:
+            F.fciqmc_set_launch(sv.h, *shape)
+            sv.iterate(40)
+        assert sv.estimates()["iteration"] == 40
+        runs.append(sv.walkers())
+        sv.close()
+    ref = O.Oracle(ham, prm)
+    ref.iterate(40)
+    do, po, _ = ref.walkers()
+    for d, p, _ in runs:
+        assert np.array_equal(d, do) and np.array_equal(p, po)
