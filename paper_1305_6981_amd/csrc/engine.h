@@ -64,14 +64,15 @@ struct SysDesc {
     double shift;
     int32_t varying, pad3;
     int64_t n_prev, n_var;
-    uint32_t status, pad2;
-    unsigned long long spawns;       // spawning events of the running iteration
 };
 
 struct EngineArgs {
     SysDesc *desc;
     int32_t max_sys;
     int32_t tile;                    // attempts per spawn-kernel tile
+    unsigned int *work;              // [0] next spawn tile, [1] next post chunk (reset per iteration)
+    uint32_t *status;                // per system: ST_* bits (kept apart from the read-only
+    unsigned long long *spawns;      // descriptors) and spawning events of the iteration
     const int32_t *chunk_sys;        // system of each global chunk (-1: unused)
     const int32_t *chunk_local;      // chunk index inside its system's table
     unsigned long long *chunk_nw;    // sum |C| per chunk (this iteration's attempts)

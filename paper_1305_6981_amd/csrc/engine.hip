@@ -160,6 +160,10 @@ struct fciqmc_t {
     std::vector<SysDesc> hdesc;
     SysDesc *d_desc = nullptr;
     IterRecord *d_rec = nullptr;
+    uint32_t *d_status = nullptr;           // per system ST_* bits (device)
+    unsigned int *d_work = nullptr;         // dynamic work counters
+    unsigned long long *d_spawns = nullptr; // per system spawn counter (device)
+    std::vector<uint32_t> hstatus;          // host mirror of d_status
     std::vector<IterRecord> hrec;
     // global chunk layout
     int64_t chunk_alloc = 0, n_chunks = 0;
@@ -195,6 +199,9 @@ EngineArgs make_args(fciqmc_t *h) {
     a.nchunks = h->d_nchunks;
     a.rec = h->d_rec;
     a.tile = h->tile;
+    a.status = h->d_status;
+    a.spawns = h->d_spawns;
+    a.work = h->d_work;
     return a;
 }
 
@@ -206,13 +213,22 @@ void drop_graphs(fciqmc_t *h) {
 int upload_desc(fciqmc_t *h) {
     HIP_TRY(hipMemcpyAsync(h->d_desc, h->hdesc.data(), sizeof(SysDesc) * h->max_sys,
                            hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_status, h->hstatus.data(), sizeof(uint32_t) * h->max_sys,
+                           hipMemcpyHostToDevice, h->stream));
     return 0;
 }
 
 int download_desc(fciqmc_t *h) {
     HIP_TRY(hipMemcpyAsync(h->hdesc.data(), h->d_desc, sizeof(SysDesc) * h->max_sys,
                            hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->hstatus.data(), h->d_status, sizeof(uint32_t) * h->max_sys,
+                           hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int reset_spawns(fciqmc_t *h, int s) {
+    HIP_TRY(hipMemsetAsync(h->d_spawns + s, 0, sizeof(unsigned long long), h->stream));
     return 0;
 }
 
@@ -594,9 +610,10 @@ int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::v
         if (rc) return rc;
     }
     S.growth = std::max<int64_t>(S.cap / 16, 2 * n);
-    d.status = 0;
-    d.spawns = 0;
-    int rc = upload_desc(h);
+    h->hstatus[s] = 0;
+    int rc = reset_spawns(h, s);
+    if (rc) return rc;
+    rc = upload_desc(h);
     if (rc) return rc;
     uint64_t *dd = nullptr;
     int32_t *dp = nullptr;
@@ -820,17 +837,19 @@ int run_iterations(fciqmc_t *h, int L) {
             // one, with 25 % slack
             S.growth = std::max<int64_t>(256, seen + seen / 4);
         }
-        if (d.status & ST_TABLE_FULL) {
-            d.status &= ~ST_TABLE_FULL;
-            d.spawns = 0;
+        uint32_t &st = h->hstatus[s];
+        if (st & ST_TABLE_FULL) {
+            st &= ~ST_TABLE_FULL;
+            rc = reset_spawns(h, s);
+            if (rc) return rc;
             rc = grow_system(h, s, S.cap * 2);
             if (rc) return rc;
         }
-        if (d.status) {
+        if (st) {
             S.fatal = FCIQMC_EOVERFLOW;
             return set_err(FCIQMC_EOVERFLOW,
-                           "system " + std::to_string(s) + ": status " + std::to_string(d.status) +
-                               ((d.status & ST_DIED) ? " (walkers died out)" : " (population overflow)"));
+                           "system " + std::to_string(s) + ": status " + std::to_string(st) +
+                               ((st & ST_DIED) ? " (walkers died out)" : " (population overflow)"));
         }
     }
     return 0;
@@ -878,7 +897,13 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     h->max_sys = max_slots;
     h->sys.resize(max_slots);
     h->hdesc.assign(max_slots, SysDesc{});
+    h->hstatus.assign(max_slots, 0u);
     HIP_TRY(hipMalloc(&h->d_desc, sizeof(SysDesc) * max_slots));
+    HIP_TRY(hipMalloc(&h->d_status, sizeof(uint32_t) * max_slots));
+    HIP_TRY(hipMalloc(&h->d_work, sizeof(unsigned int) * 4));
+    HIP_TRY(hipMemsetAsync(h->d_work, 0, sizeof(unsigned int) * 4, h->stream));
+    HIP_TRY(hipMalloc(&h->d_spawns, sizeof(unsigned long long) * max_slots));
+    HIP_TRY(hipMemsetAsync(h->d_spawns, 0, sizeof(unsigned long long) * max_slots, h->stream));
     HIP_TRY(hipMalloc(&h->d_rec, sizeof(IterRecord) * REC_CAP * max_slots));
     HIP_TRY(hipMalloc(&h->d_total, sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
@@ -943,6 +968,9 @@ void release(fciqmc_t *h) {
         if (S.block) hipFree(S.block);
     hipFree(h->d_desc);
     hipFree(h->d_rec);
+    hipFree(h->d_status);
+    hipFree(h->d_work);
+    hipFree(h->d_spawns);
     hipFree(h->d_total);
     hipFree(h->d_nchunks);
     hipFree(h->d_err);
@@ -1102,7 +1130,6 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
     d.n_prev = n_prev;
     d.varying = varying ? 1 : 0;
     d.n_var = n_var;
-    d.spawns = 0;
     int rc = load_list(h, s, dv, pv);
     if (rc) return rc;
     S.s_num.clear();
@@ -1152,6 +1179,7 @@ int fciqmc_batch_retire(fciqmc_t *h, int32_t slot) {
     if (S.block) HIP_TRY(hipFree(S.block));
     S = SysHost();
     h->hdesc[slot] = SysDesc{};
+    h->hstatus[slot] = 0;
     int rc = relayout(h);
     if (rc) return rc;
     return upload_desc(h);

@@ -305,8 +305,8 @@ __device__ double shift_log(double x) {
     return (double)e * 0.6931471805599453 + 2.0 * z * sum;
 }
 
-__device__ __forceinline__ bool participating(const SysDesc &d) {
-    return d.active && d.status == 0 && d.iter < d.stop_at;
+__device__ __forceinline__ bool participating(const SysDesc &d, uint32_t status) {
+    return d.active && status == 0 && d.iter < d.stop_at;
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +336,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 // ---------------------------------------------------------------------------
 // K1: chunk sums of |C| on the current tables.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a) {
+__global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
+                                                   const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long sh[4];
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x;
@@ -344,8 +345,8 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a) {
         const int s = a.chunk_sys[c];
         unsigned long long sum = 0;
         if (s >= 0) {
-            const SysDesc &d = a.desc[s];
-            if (participating(d)) {
+            const SysDesc &d = desc[s];
+            if (participating(d, a.status[s])) {
                 const int4 v = reinterpret_cast<const int4 *>(d.pop + (int64_t)a.chunk_local[c] * CHUNK)[t];
                 sum = (unsigned long long)(abs(v.x)) + (unsigned long long)(abs(v.y)) +
                       (unsigned long long)(abs(v.z)) + (unsigned long long)(abs(v.w));
@@ -384,7 +385,11 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
         a.chunk_off[i] = run;
         run += v;
     }
-    if (t == 1023) *a.total = part[1023];
+    if (t == 1023) {
+        *a.total = part[1023];
+        a.work[0] = 0u;   // dynamic work counters of the spawn and post kernels
+        a.work[1] = 0u;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -428,10 +433,10 @@ struct SingleItem {
     uint32_t pai;      // p | a << 8 | initiator << 16
 };
 
-constexpr int SGL_QUEUE = 256;
-constexpr int SPW_QUEUE = 512;
-constexpr int SGL_DRAIN = 64;     // drain the queues once they hold this many items
-constexpr int SPW_DRAIN = 256;
+constexpr int SGL_QUEUE = 128;
+constexpr int SPW_QUEUE = 256;
+constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
+constexpr int SPW_DRAIN = 128;
 
 __device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double pgen, uint64_t x4,
                                           int32_t C, uint32_t *status) {
@@ -493,12 +498,14 @@ __device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
     __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
+__global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long s_incl[CHUNK];
     __shared__ uint64_t s_det[CHUNK];
     __shared__ int32_t s_pop[CHUNK];
     __shared__ unsigned long long s_wsum[4];
+    __shared__ int s_wcnt[4];
     __shared__ long long s_c;
+    __shared__ unsigned int s_tile;
     __shared__ double s_recip[65];
     __shared__ SpawnQueues Q;
     const unsigned long long total = *a.total;
@@ -513,8 +520,15 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
     }
     __syncthreads();
     const unsigned long long tile = (unsigned long long)a.tile;
-    for (unsigned long long t0 = (unsigned long long)blockIdx.x * tile; t0 < total;
-         t0 += (unsigned long long)gridDim.x * tile) {
+    const unsigned long long n_tiles = (total + tile - 1) / tile;
+    for (;;) {
+        // tiles are handed out dynamically: no workgroup waits for a second round
+        if (t == 0) s_tile = atomicAdd(&a.work[0], 1u);
+        __syncthreads();
+        const unsigned long long tix = s_tile;
+        __syncthreads();
+        if (tix >= n_tiles) break;
+        const unsigned long long t0 = tix * tile;
         const unsigned long long t1 = (t0 + tile < total) ? t0 + tile : total;
         if (t == 0) {
             int64_t lo = 0, hi = nch;  // first chunk with offset > t0
@@ -537,39 +551,58 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
                 continue;
             }
             const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
-            const SysDesc &d = a.desc[s];
-            uint32_t *status = &a.desc[s].status;
+            const SysDesc &d = desc[s];
+            uint32_t *status = &a.status[s];
             if (Q.sys != s) {
                 // queued work belongs to another system: finish it first
-                if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0))
-                    drain_queues(Q, a.desc[Q.sys], &a.desc[Q.sys].status, &a.desc[Q.sys].spawns);
+                if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
+                    const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
+                    drain_queues(Q, desc[qs], &a.status[qs], &a.spawns[qs]);
+                }
                 __syncthreads();
                 if (t == 0) Q.sys = s;
             }
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-            // Stage keys and populations; prefix sum of |C| (4 consecutive slots per thread).
+            // Stage the occupied slots of the chunk, compacted, with the inclusive
+            // prefix sum of |C| (4 consecutive slots per thread).
             const int4 pv = reinterpret_cast<const int4 *>(d.pop + base)[t];
             const int32_t pa[4] = {pv.x, pv.y, pv.z, pv.w};
-            unsigned long long loc[4], run = 0;
+            const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
+            unsigned long long run = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                run += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
+            // block-exclusive prefix of (count, walkers): wavefront scan, then waves in order
+            unsigned long long xw = run, xc = (unsigned long long)nocc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned long long yw = __shfl_up(xw, o, 64);
+                const unsigned long long yc = __shfl_up(xc, o, 64);
+                if (lane >= o) {
+                    xw += yw;
+                    xc += yc;
+                }
+            }
+            if (lane == 63) {
+                s_wsum[wid] = xw;
+                s_wcnt[wid] = (int)xc;
+            }
+            __syncthreads();
+            unsigned long long wbefore = xw - run;
+            int pos = (int)xc - nocc;
+            for (int w = 0; w < wid; ++w) {
+                wbefore += s_wsum[w];
+                pos += s_wcnt[w];
+            }
+            const int n_occ = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int i = 4 * t + u;
-                s_pop[i] = pa[u];
-                s_det[i] = d.kv[base + i].det;
-                run += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
-                loc[u] = run;
+                if (pa[u] == 0) continue;
+                wbefore += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
+                s_pop[pos] = pa[u];
+                s_det[pos] = d.kv[base + 4 * t + u].det;
+                s_incl[pos] = wbefore;
+                ++pos;
             }
-            unsigned long long x = run;
-            for (int o = 1; o < 64; o <<= 1) {
-                const unsigned long long y = __shfl_up(x, o, 64);
-                if (lane >= o) x += y;
-            }
-            if (lane == 63) s_wsum[wid] = x;
-            __syncthreads();
-            unsigned long long before = x - run;
-            for (int w = 0; w < wid; ++w) before += s_wsum[w];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) s_incl[4 * t + u] = before + loc[u];
             __syncthreads();
             // This chunk's part of the tile, split into 256 consecutive runs.
             const unsigned long long lo_t = t0 > off_c ? t0 : off_c;
@@ -581,7 +614,7 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
             unsigned long long spawned = 0;
             if (at < at_end) {
                 const unsigned long long local = at - off_c;
-                int sl = 0, hi = CHUNK - 1;  // first slot with inclusive sum > local
+                int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
                 while (sl < hi) {
                     const int mid = (sl + hi) >> 1;
                     if (s_incl[mid] > local) hi = mid;
@@ -626,23 +659,24 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a) {
                     if (++at >= at_end) break;
                     if ((int64_t)(++k) >= absC) {
                         k = 0;
-                        do ++sl;
-                        while (s_pop[sl] == 0);
+                        ++sl;
                     }
                 }
             }
             // one atomic per wavefront for the spawn counter
             const unsigned long long ws = wave_sum(spawned);
-            if (lane == 0 && ws) atomicAdd(&a.desc[s].spawns, ws);
+            if (lane == 0 && ws) atomicAdd(&a.spawns[s], ws);
             __syncthreads();
             if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN)
-                drain_queues(Q, d, status, &a.desc[s].spawns);
+                drain_queues(Q, d, status, &a.spawns[s]);
             ++c;
         }
     }
     __syncthreads();
-    if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0))
-        drain_queues(Q, a.desc[Q.sys], &a.desc[Q.sys].status, &a.desc[Q.sys].spawns);
+    if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
+        const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
+        drain_queues(Q, desc[qs], &a.status[qs], &a.spawns[qs]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -684,28 +718,35 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_post(EngineArgs a) {
+__global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ double s_jk[64 * 64];
     __shared__ double s_hpp[64];
     __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ int s_qn;
     __shared__ long long s_red[4][6];
     __shared__ double s_redd[4];
+    __shared__ unsigned int s_next;
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     int loaded = -1;
     if (t == 0) s_qn = 0;
     __syncthreads();
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    for (;;) {
+        // chunks are handed out dynamically, in order (systems stay contiguous)
+        if (t == 0) s_next = atomicAdd(&a.work[1], 1u);
+        __syncthreads();
+        const int64_t c = s_next;
+        __syncthreads();
+        if (c >= nch) break;
         const int s = a.chunk_sys[c];
         int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, used = 0;
         double num = 0.0;
-        const bool live = s >= 0 && participating(a.desc[s]);   // uniform
+        const bool live = s >= 0 && participating(desc[s], a.status[s]);   // uniform
         if (live) {
-            const SysDesc &d = a.desc[s];
+            const SysDesc &d = desc[s];
             if (loaded != s || s_qn > POST_QUEUE - CHUNK) {
                 // flush the queue of the previous system (or a nearly full queue)
-                if (loaded >= 0 && s_qn > 0) flush_new_dets(a.desc[loaded], s_queue, s_qn, s_hpp, s_jk);
+                if (loaded >= 0 && s_qn > 0) flush_new_dets(desc[loaded], s_queue, s_qn, s_hpp, s_jk);
                 __syncthreads();
                 if (loaded != s) {
                     for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = d.jk[i];
@@ -742,7 +783,7 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                     const double ad = fabs(dv);
                     const double fl = floor(ad);
                     if (fl > 1073741824.0) {
-                        atomicOr(&a.desc[s].status, ST_POP_OVERFLOW);
+                        atomicOr(&a.status[s], ST_POP_OVERFLOW);
                         continue;
                     }
                     const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
@@ -763,7 +804,7 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
                 }
                 if (sp != 0) ++merged;
                 if (np > 2147483647ll || np < -2147483647ll) {
-                    atomicOr(&a.desc[s].status, ST_POP_OVERFLOW);
+                    atomicOr(&a.status[s], ST_POP_OVERFLOW);
                     np = 0;
                 }
                 pout[u] = (int32_t)np;
@@ -817,7 +858,7 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a) {
         }
         __syncthreads();
     }
-    if (loaded >= 0 && s_qn > 0) flush_new_dets(a.desc[loaded], s_queue, s_qn, s_hpp, s_jk);
+    if (loaded >= 0 && s_qn > 0) flush_new_dets(desc[loaded], s_queue, s_qn, s_hpp, s_jk);
 }
 
 // ---------------------------------------------------------------------------
@@ -829,7 +870,7 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
     const int s = blockIdx.x;
     if (s >= a.max_sys) return;
     SysDesc &d = a.desc[s];
-    if (!participating(d)) return;   // uniform across the workgroup
+    if (!participating(d, a.status[s])) return;   // uniform across the workgroup
     const int t = threadIdx.x;
     int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0, used = 0;
     double num = 0.0;
@@ -854,7 +895,7 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
     num = block_sum(num, shd);
     if (t == 0) {
         const int64_t done = d.iter + 1;
-        if (d.status == 0) {
+        {
             if (done % d.A == 0) {
                 if (!d.varying) {
                     if (nw >= d.target) {
@@ -868,7 +909,7 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
                     d.n_prev = nw;
                 }
             }
-            if (nw == 0) d.status |= ST_DIED;
+            if (nw == 0) a.status[s] |= ST_DIED;
         }
         IterRecord r;
         r.iter = done;
@@ -876,7 +917,7 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
         r.nd = nd;
         r.c0 = c0;
         r.attempts = att;
-        r.spawns = (int64_t)d.spawns;
+        r.spawns = (int64_t)a.spawns[s];
         r.merged = merged;
         r.aborted = aborted;
         r.used = used;
@@ -885,9 +926,9 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
         r.num = num;
         r.shift = d.shift;
         r.varying = d.varying;
-        r.status = (int32_t)d.status;
+        r.status = (int32_t)a.status[s];
         a.rec[(int64_t)s * REC_CAP + (done % REC_CAP)] = r;
-        d.spawns = 0ull;
+        a.spawns[s] = 0ull;
         d.iter = done;
     }
 }
@@ -895,13 +936,16 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
 void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, int spawn_grid,
                       hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)chunk_grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)chunk_grid), dim3(256), 0, s, a,
+                       (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
+                       (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
+                       (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[4], s);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[5], s);
