@@ -188,14 +188,17 @@ def batched_vs_plain(F, S, iters, scale):
 
 
 def copy_calibration(roctx, nbytes=1 << 30):
-    """One plain device copy of nbytes inside a profiled region: the HBM counters of this
-    kernel calibrate FETCH_SIZE / WRITE_SIZE against a known traffic."""
+    """One plain streaming kernel of known traffic inside a profiled region: an elementwise
+    multiply reading nbytes and writing nbytes (caches evicted first by a 2x larger fill).
+    The HBM counters of this kernel calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
+    z = torch.empty(2 * nbytes // 4, dtype=torch.float32, device="cuda").fill_(2.0)
     torch.cuda.synchronize()
+    del z
     roctx.resume()
-    y.copy_(x)
+    torch.mul(x, 1.0, out=y)
     torch.cuda.synchronize()
     roctx.pause()
     del x, y

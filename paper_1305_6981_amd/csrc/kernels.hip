@@ -317,7 +317,7 @@ __device__ __forceinline__ T block_sum(T v, T *sh) {
     const int t = threadIdx.x;
     sh[t] = v;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
         if (t < s) sh[t] = sh[t] + sh[t + s];
         __syncthreads();
     }
@@ -367,10 +367,21 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
     __shared__ unsigned long long part[1024];
     const int64_t n = *a.nchunks;
     const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
+    // contiguous ranges of an even length per thread: two-element vector loads
+    const int64_t per = (((n + 1023) / 1024) + 1) & ~(int64_t)1;
     const int64_t b = t * per, e = (b + per < n) ? b + per : n;
     unsigned long long s = 0;
-    for (int64_t i = b; i < e; ++i) s += a.chunk_nw[i];
+    if (b < e) {
+        int64_t i = b;
+        for (; i + 8 <= e; i += 8) {
+            const ulonglong2 v0 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
+            const ulonglong2 v1 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 2);
+            const ulonglong2 v2 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 4);
+            const ulonglong2 v3 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 6);
+            s += v0.x + v0.y + v1.x + v1.y + v2.x + v2.y + v3.x + v3.y;
+        }
+        for (; i < e; ++i) s += a.chunk_nw[i];
+    }
     part[t] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -380,10 +391,20 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
         __syncthreads();
     }
     unsigned long long run = part[t] - s;  // exclusive
-    for (int64_t i = b; i < e; ++i) {
-        const unsigned long long v = a.chunk_nw[i];
-        a.chunk_off[i] = run;
-        run += v;
+    if (b < e) {
+        int64_t i = b;
+        for (; i + 2 <= e; i += 2) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
+            ulonglong2 o;
+            o.x = run;
+            o.y = run + v.x;
+            run += v.x + v.y;
+            *reinterpret_cast<ulonglong2 *>(a.chunk_off + i) = o;
+        }
+        for (; i < e; ++i) {
+            a.chunk_off[i] = run;
+            run += a.chunk_nw[i];
+        }
     }
     if (t == 1023) {
         *a.total = part[1023];
@@ -864,9 +885,9 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
 // ---------------------------------------------------------------------------
 // K5: per-system reduction, record, shift update (one workgroup per system).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
-    __shared__ long long shi[256];
-    __shared__ double shd[256];
+__global__ __launch_bounds__(1024) void k_finalize(EngineArgs a) {
+    __shared__ long long shi[1024];
+    __shared__ double shd[1024];
     const int s = blockIdx.x;
     if (s >= a.max_sys) return;
     SysDesc &d = a.desc[s];
@@ -874,7 +895,8 @@ __global__ __launch_bounds__(256) void k_finalize(EngineArgs a) {
     const int t = threadIdx.x;
     int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0, used = 0;
     double num = 0.0;
-    for (int64_t i = t; i < d.nchunks; i += 256) {
+#pragma unroll 4
+    for (int64_t i = t; i < d.nchunks; i += 1024) {
         const ChunkStat cs = a.chunk_stat[d.gchunk0 + i];
         used += cs.used;
         nw += cs.nw;
@@ -947,7 +969,7 @@ void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, in
     hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[4], s);
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(1024), 0, s, a);
     if (ev) (void)hipEventRecord(ev[5], s);
 }
 
