@@ -16,13 +16,6 @@ constexpr uint32_t ST_POP_OVERFLOW = 2u;   // a population left int32
 constexpr uint32_t ST_DIED = 4u;           // N_w reached zero
 constexpr uint32_t ST_SPAWN_OVERFLOW = 8u; // one spawning event would create > 2^30 walkers
 
-// One main-table slot: the determinant key and the spawned walkers that
-// arrive on it during the current iteration (signed sum, OR of initiator flags).
-struct alignas(16) Slot {
-    uint64_t det;      // 0 = empty
-    int32_t spop;
-    uint32_t sflag;
-};
 
 struct IterRecord {
     int64_t iter;      // completed iterations after this one
@@ -53,7 +46,9 @@ struct SysDesc {
     const double *h1, *eri;
     const double *jk;                // [n_so][64]: (pp|qq) - (pq|qp) for p < q, spin orbitals
     const double *t3;                // [n_so][64][64]: (pa|qq) - d(s_p,s_q)(pq|qa), same-spin p, a
-    Slot *kv;                        // main table: key + spawned walkers of this iteration
+    uint64_t *key;                   // main table (structure of arrays): determinant, 0 = empty
+    int2 *acc;                       // walkers spawned onto the slot this iteration (signed sum,
+                                     // OR of initiator flags)
     int32_t *pop;                    // signed walker count (0: vacated or not yet occupied)
     double *hdiag;                   // stored H_DD; NaN until the determinant is first occupied
     uint64_t cap_mask;               // capacity - 1 (capacity a power of two >= CHUNK)
@@ -77,8 +72,9 @@ struct EngineArgs {
     const int32_t *chunk_local;      // chunk index inside its system's table
     unsigned long long *chunk_nw;    // sum |C| per chunk (this iteration's attempts)
     unsigned long long *chunk_off;   // exclusive scan of chunk_nw
+    unsigned long long *chunk_toff;  // exclusive scan of the spawn tiles of each chunk
     ChunkStat *chunk_stat;
-    unsigned long long *total;       // total attempts of the iteration
+    unsigned long long *total;       // [0] total attempts, [1] total spawn tiles
     const int64_t *nchunks;          // global chunks in use
     IterRecord *rec;                 // [max_sys][REC_CAP]
 };
@@ -88,10 +84,11 @@ void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, in
                       hipStream_t s, hipEvent_t *ev /* 6 events or nullptr */);
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
                        int64_t n, uint32_t *d_err, hipStream_t s);
-hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const Slot *src_kv, const int32_t *src_pop,
-                         const double *src_hd, int64_t src_cap, Slot *dst_kv, int32_t *dst_pop,
-                         double *dst_hd, uint32_t *d_err, hipStream_t s);
-hipError_t launch_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint64_t *out_det,
+hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,
+                         const int32_t *src_pop, const double *src_hd, int64_t src_cap,
+                         uint64_t *dst_key, int32_t *dst_pop, double *dst_hd, uint32_t *d_err,
+                         hipStream_t s);
+hipError_t launch_compact(const uint64_t *key, const int32_t *pop, int64_t cap, uint64_t *out_det,
                           int32_t *out_pop, unsigned long long *count, hipStream_t s);
 hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s);
 int spawn_grid_size();

@@ -1,8 +1,8 @@
 // Host engine of libfciqmc: the C ABI declared in include/fciqmc.h.
 //
 // A handle holds up to max_slots independent systems. Each system owns an
-// open-addressing main table in device memory (Slot key + spawned sum,
-// population, stored diagonal element), its integrals, and a row of the device
+// open-addressing main table in device memory (structure of arrays: key,
+// spawned-walker accumulator, population, stored diagonal element), its integrals, and a row of the device
 // descriptor table. One iteration of every system is one pass of five kernels
 // over the descriptor table; up to 64 iterations are captured in one HIP
 // graph. Slots are updated in place; a vacated slot keeps its key until the
@@ -133,7 +133,8 @@ struct SysHost {
     uint64_t d0 = 0;
     int64_t cap = 0;           // table slots
     void *block = nullptr;     // one device allocation for the table + integrals
-    Slot *kv = nullptr;
+    uint64_t *key = nullptr;
+    int2 *acc = nullptr;
     int32_t *pop = nullptr;
     double *hd = nullptr;
     double *d_h1 = nullptr, *d_eri = nullptr, *d_jk = nullptr;
@@ -169,6 +170,7 @@ struct fciqmc_t {
     int64_t chunk_alloc = 0, n_chunks = 0;
     int32_t *d_chunk_sys = nullptr, *d_chunk_local = nullptr;
     unsigned long long *d_chunk_nw = nullptr, *d_chunk_off = nullptr, *d_total = nullptr;
+    unsigned long long *d_chunk_toff = nullptr;
     ChunkStat *d_chunk_stat = nullptr;
     int64_t *d_nchunks = nullptr;
     uint32_t *d_err = nullptr;
@@ -194,6 +196,7 @@ EngineArgs make_args(fciqmc_t *h) {
     a.chunk_local = h->d_chunk_local;
     a.chunk_nw = h->d_chunk_nw;
     a.chunk_off = h->d_chunk_off;
+    a.chunk_toff = h->d_chunk_toff;
     a.chunk_stat = h->d_chunk_stat;
     a.total = h->d_total;
     a.nchunks = h->d_nchunks;
@@ -243,6 +246,7 @@ int relayout(fciqmc_t *h) {
         hipFree(h->d_chunk_local);
         hipFree(h->d_chunk_nw);
         hipFree(h->d_chunk_off);
+        hipFree(h->d_chunk_toff);
         hipFree(h->d_chunk_stat);
         h->d_chunk_sys = nullptr;
         h->chunk_alloc = 0;
@@ -250,6 +254,7 @@ int relayout(fciqmc_t *h) {
         HIP_TRY(hipMalloc(&h->d_chunk_local, na * sizeof(int32_t)));
         HIP_TRY(hipMalloc(&h->d_chunk_nw, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_off, na * sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc(&h->d_chunk_toff, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_stat, na * sizeof(ChunkStat)));
         h->chunk_alloc = na;
         drop_graphs(h);
@@ -286,7 +291,7 @@ int relayout(fciqmc_t *h) {
 }
 
 int64_t table_bytes(int64_t cap) {
-    return cap * (int64_t)(sizeof(Slot) + sizeof(int32_t) + sizeof(double));
+    return cap * (int64_t)(sizeof(uint64_t) + sizeof(int2) + sizeof(int32_t) + sizeof(double));
 }
 
 int64_t integral_doubles(int M) {
@@ -299,10 +304,11 @@ int64_t integral_bytes(int M) { return integral_doubles(M) * 8 + 256; }
 // Empty table: keys and populations zero, diagonal elements NaN ("not computed").
 int clear_table(fciqmc_t *h, void *blk, int64_t cap) {
     char *p = (char *)blk;
-    HIP_TRY(hipMemsetAsync(p, 0, (size_t)cap * sizeof(Slot), h->stream));
-    HIP_TRY(hipMemsetAsync(p + cap * sizeof(Slot), 0xFF, (size_t)cap * sizeof(double), h->stream));
-    HIP_TRY(hipMemsetAsync(p + cap * (sizeof(Slot) + sizeof(double)), 0,
-                           (size_t)cap * sizeof(int32_t), h->stream));
+    const size_t kb = (size_t)cap * (sizeof(uint64_t) + sizeof(int2));   // keys + accumulators
+    HIP_TRY(hipMemsetAsync(p, 0, kb, h->stream));
+    HIP_TRY(hipMemsetAsync(p + kb, 0xFF, (size_t)cap * sizeof(double), h->stream));
+    HIP_TRY(hipMemsetAsync(p + kb + cap * sizeof(double), 0, (size_t)cap * sizeof(int32_t),
+                           h->stream));
     return 0;
 }
 
@@ -325,8 +331,10 @@ int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
 
 void carve(SysHost &S, void *blk, int64_t cap) {
     char *p = (char *)blk;
-    S.kv = (Slot *)p;
-    p += cap * sizeof(Slot);
+    S.key = (uint64_t *)p;
+    p += cap * sizeof(uint64_t);
+    S.acc = (int2 *)p;
+    p += cap * sizeof(int2);
     S.hd = (double *)p;
     p += cap * sizeof(double);
     S.pop = (int32_t *)p;
@@ -355,7 +363,8 @@ int upload_integrals(fciqmc_t *h, SysHost &S) {
 void fill_desc_tables(fciqmc_t *h, int s) {
     SysHost &S = h->sys[s];
     SysDesc &d = h->hdesc[s];
-    d.kv = S.kv;
+    d.key = S.key;
+    d.acc = S.acc;
     d.pop = S.pop;
     d.hdiag = S.hd;
     d.h1 = S.d_h1;
@@ -382,7 +391,7 @@ int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
     rc = upload_desc(h);
     if (rc) return rc;
     HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_rehash(h->d_desc, s, S.kv, S.pop, S.hd, S.cap, T.kv, T.pop, T.hd, h->d_err,
+    HIP_TRY(launch_rehash(h->d_desc, s, S.key, S.pop, S.hd, S.cap, T.key, T.pop, T.hd, h->d_err,
                           h->stream));
     uint32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
@@ -648,7 +657,7 @@ int export_walkers(fciqmc_t *h, int s, Walkers &w) {
     HIP_TRY(hipMalloc(&op, S.cap * 4));
     HIP_TRY(hipMalloc(&cnt, 8));
     HIP_TRY(hipMemsetAsync(cnt, 0, 8, h->stream));
-    HIP_TRY(launch_compact(S.kv, S.pop, S.cap, od, op, cnt, h->stream));
+    HIP_TRY(launch_compact(S.key, S.pop, S.cap, od, op, cnt, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -905,7 +914,7 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_spawns, sizeof(unsigned long long) * max_slots));
     HIP_TRY(hipMemsetAsync(h->d_spawns, 0, sizeof(unsigned long long) * max_slots, h->stream));
     HIP_TRY(hipMalloc(&h->d_rec, sizeof(IterRecord) * REC_CAP * max_slots));
-    HIP_TRY(hipMalloc(&h->d_total, sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_total, 2 * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
     HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
@@ -978,6 +987,7 @@ void release(fciqmc_t *h) {
     hipFree(h->d_chunk_local);
     hipFree(h->d_chunk_nw);
     hipFree(h->d_chunk_off);
+    hipFree(h->d_chunk_toff);
     hipFree(h->d_chunk_stat);
     for (auto &e : h->ev)
         if (e) hipEventDestroy(e);

@@ -364,50 +364,50 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
 // K2: exclusive scan of the chunk sums (one workgroup).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
-    __shared__ unsigned long long part[1024];
+    __shared__ unsigned long long part[1024], tpart[1024];
     const int64_t n = *a.nchunks;
+    const unsigned long long tile = (unsigned long long)a.tile;
     const int t = threadIdx.x;
     // contiguous ranges of an even length per thread: two-element vector loads
     const int64_t per = (((n + 1023) / 1024) + 1) & ~(int64_t)1;
     const int64_t b = t * per, e = (b + per < n) ? b + per : n;
-    unsigned long long s = 0;
+    unsigned long long s = 0, st = 0;
     if (b < e) {
         int64_t i = b;
-        for (; i + 8 <= e; i += 8) {
+        for (; i + 4 <= e; i += 4) {
             const ulonglong2 v0 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
             const ulonglong2 v1 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 2);
-            const ulonglong2 v2 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 4);
-            const ulonglong2 v3 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 6);
-            s += v0.x + v0.y + v1.x + v1.y + v2.x + v2.y + v3.x + v3.y;
+            s += v0.x + v0.y + v1.x + v1.y;
+            st += (v0.x + tile - 1) / tile + (v0.y + tile - 1) / tile + (v1.x + tile - 1) / tile +
+                  (v1.y + tile - 1) / tile;
         }
-        for (; i < e; ++i) s += a.chunk_nw[i];
+        for (; i < e; ++i) {
+            s += a.chunk_nw[i];
+            st += (a.chunk_nw[i] + tile - 1) / tile;
+        }
     }
     part[t] = s;
+    tpart[t] = st;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        const unsigned long long vt = t >= off ? tpart[t - off] : 0ull;
         __syncthreads();
         part[t] += v;
+        tpart[t] += vt;
         __syncthreads();
     }
-    unsigned long long run = part[t] - s;  // exclusive
-    if (b < e) {
-        int64_t i = b;
-        for (; i + 2 <= e; i += 2) {
-            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
-            ulonglong2 o;
-            o.x = run;
-            o.y = run + v.x;
-            run += v.x + v.y;
-            *reinterpret_cast<ulonglong2 *>(a.chunk_off + i) = o;
-        }
-        for (; i < e; ++i) {
-            a.chunk_off[i] = run;
-            run += a.chunk_nw[i];
-        }
+    unsigned long long run = part[t] - s, trun = tpart[t] - st;  // exclusive
+    for (int64_t i = b; i < e; ++i) {
+        const unsigned long long v = a.chunk_nw[i];
+        a.chunk_off[i] = run;
+        a.chunk_toff[i] = trun;
+        run += v;
+        trun += (v + tile - 1) / tile;
     }
     if (t == 1023) {
-        *a.total = part[1023];
+        a.total[0] = part[1023];
+        a.total[1] = tpart[1023];
         a.work[0] = 0u;   // dynamic work counters of the spawn and post kernels
         a.work[1] = 0u;
     }
@@ -421,20 +421,19 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
 // k+1 / next occupied slot.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool table_add(Slot *kv, uint64_t mask, uint64_t key, int32_t v,
-                                          bool init) {
-    uint64_t h = mix64(key) & mask;
+__device__ __forceinline__ bool table_add(uint64_t *key, int2 *acc, uint64_t mask, uint64_t k,
+                                          int32_t v, bool init) {
+    uint64_t h = mix64(k) & mask;
     for (uint64_t n = 0; n <= mask; ++n) {
-        uint64_t cur = __hip_atomic_load(&kv[h].det, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t cur = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == 0) {
-            cur = atomicCAS((unsigned long long *)&kv[h].det, 0ull, (unsigned long long)key);
-            if (cur == 0) cur = key;
+            cur = atomicCAS((unsigned long long *)&key[h], 0ull, (unsigned long long)k);
+            if (cur == 0) cur = k;
         }
-        if (cur == key) {
-            atomicAdd(&kv[h].spop, v);
-            if (init && __hip_atomic_load(&kv[h].sflag, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT) == 0u)
-                atomicOr(&kv[h].sflag, 1u);
+        if (cur == k) {
+            atomicAdd(&acc[h].x, v);
+            if (init && __hip_atomic_load(&acc[h].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                atomicOr(&acc[h].y, 1);
             return true;
         }
         h = (h + 1) & mask;
@@ -499,7 +498,7 @@ __device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
         if (qq < SPW_QUEUE) {
             Q.spd[qq] = Dn;
             Q.spv[qq] = make_int2(v, init ? 1 : 0);
-        } else if (!table_add(d.kv, d.cap_mask, Dn, v, init)) {
+        } else if (!table_add(d.key, d.acc, d.cap_mask, Dn, v, init)) {
             atomicOr(status, ST_TABLE_FULL);
         }
     }
@@ -509,7 +508,7 @@ __device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
     const int nspw = Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE;
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
-        if (!table_add(d.kv, d.cap_mask, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
+        if (!table_add(d.key, d.acc, d.cap_mask, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
     }
     __syncthreads();
     if (t == 0) {
@@ -529,8 +528,9 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
     __shared__ unsigned int s_tile;
     __shared__ double s_recip[65];
     __shared__ SpawnQueues Q;
-    const unsigned long long total = *a.total;
+    const unsigned long long n_tiles = a.total[1];
     const int64_t nch = *a.nchunks;
+    const unsigned long long tile = (unsigned long long)a.tile;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     if (t > 0 && t <= 64) s_recip[t] = 1.0 / (double)t;
     if (t == 0) {
@@ -540,158 +540,150 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
         Q.sys = -1;
     }
     __syncthreads();
-    const unsigned long long tile = (unsigned long long)a.tile;
-    const unsigned long long n_tiles = (total + tile - 1) / tile;
     for (;;) {
-        // tiles are handed out dynamically: no workgroup waits for a second round
-        if (t == 0) s_tile = atomicAdd(&a.work[0], 1u);
+        // Tiles never cross a chunk: chunk c owns ceil(N_c / tile) consecutive tiles.
+        // They are handed out dynamically, so no workgroup waits for a second round.
+        if (t == 0) {
+            const unsigned int tix = atomicAdd(&a.work[0], 1u);
+            s_tile = tix;
+            if (tix < n_tiles) {
+                int64_t lo = 0, hi = nch;  // first chunk with tile offset > tix
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a.chunk_toff[mid] <= tix) lo = mid + 1;
+                    else hi = mid;
+                }
+                s_c = lo - 1;
+            }
+        }
         __syncthreads();
         const unsigned long long tix = s_tile;
+        const int64_t c = s_c;
         __syncthreads();
         if (tix >= n_tiles) break;
-        const unsigned long long t0 = tix * tile;
-        const unsigned long long t1 = (t0 + tile < total) ? t0 + tile : total;
-        if (t == 0) {
-            int64_t lo = 0, hi = nch;  // first chunk with offset > t0
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (a.chunk_off[mid] <= t0) lo = mid + 1;
-                else hi = mid;
+        const unsigned long long off_c = a.chunk_off[c];
+        const unsigned long long nw_c = a.chunk_nw[c];
+        const unsigned long long j = tix - a.chunk_toff[c];
+        const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
+        const SysDesc &d = desc[s];
+        uint32_t *status = &a.status[s];
+        if (Q.sys != s) {
+            // queued work belongs to another system: finish it first
+            if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
+                const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
+                drain_queues(Q, desc[qs], &a.status[qs], &a.spawns[qs]);
             }
-            s_c = lo - 1;
+            __syncthreads();
+            if (t == 0) Q.sys = s;
+        }
+        const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
+        // Stage the occupied slots of the chunk, compacted, with the inclusive
+        // prefix sum of |C| (4 consecutive slots per thread).
+        const int4 pv = reinterpret_cast<const int4 *>(d.pop + base)[t];
+        const ulonglong2 k01 = reinterpret_cast<const ulonglong2 *>(d.key + base)[2 * t];
+        const ulonglong2 k23 = reinterpret_cast<const ulonglong2 *>(d.key + base)[2 * t + 1];
+        const int32_t pa[4] = {pv.x, pv.y, pv.z, pv.w};
+        const uint64_t ka[4] = {k01.x, k01.y, k23.x, k23.y};
+        const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
+        unsigned long long run = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            run += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
+        unsigned long long xw = run, xc = (unsigned long long)nocc;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long yw = __shfl_up(xw, o, 64);
+            const unsigned long long yc = __shfl_up(xc, o, 64);
+            if (lane >= o) {
+                xw += yw;
+                xc += yc;
+            }
+        }
+        if (lane == 63) {
+            s_wsum[wid] = xw;
+            s_wcnt[wid] = (int)xc;
         }
         __syncthreads();
-        int64_t c = s_c;
+        unsigned long long wbefore = xw - run;
+        int pos = (int)xc - nocc;
+        for (int w = 0; w < wid; ++w) {
+            wbefore += s_wsum[w];
+            pos += s_wcnt[w];
+        }
+        const int n_occ = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (pa[u] == 0) continue;
+            wbefore += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
+            s_pop[pos] = pa[u];
+            s_det[pos] = ka[u];
+            s_incl[pos] = wbefore;
+            ++pos;
+        }
         __syncthreads();
-        while (c < nch) {
-            const unsigned long long off_c = a.chunk_off[c];
-            if (off_c >= t1) break;
-            const unsigned long long nw_c = a.chunk_nw[c];
-            if (nw_c == 0) {
-                ++c;
-                continue;
+        // This tile's attempts, split into 256 consecutive runs.
+        const unsigned long long lo_t = off_c + j * tile;
+        const unsigned long long hi_t = (lo_t + tile < off_c + nw_c) ? lo_t + tile : off_c + nw_c;
+        const unsigned long long per = (hi_t - lo_t + 255) / 256;
+        unsigned long long at = lo_t + (unsigned long long)t * per;
+        const unsigned long long at_end = (at + per < hi_t) ? at + per : hi_t;
+        const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
+        unsigned long long spawned = 0;
+        if (at < at_end) {
+            const unsigned long long local = at - off_c;
+            int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
+            while (sl < hi) {
+                const int mid = (sl + hi) >> 1;
+                if (s_incl[mid] > local) hi = mid;
+                else sl = mid + 1;
             }
-            const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
-            const SysDesc &d = desc[s];
-            uint32_t *status = &a.status[s];
-            if (Q.sys != s) {
-                // queued work belongs to another system: finish it first
-                if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
-                    const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-                    drain_queues(Q, desc[qs], &a.status[qs], &a.spawns[qs]);
-                }
-                __syncthreads();
-                if (t == 0) Q.sys = s;
-            }
-            const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-            // Stage the occupied slots of the chunk, compacted, with the inclusive
-            // prefix sum of |C| (4 consecutive slots per thread).
-            const int4 pv = reinterpret_cast<const int4 *>(d.pop + base)[t];
-            const int32_t pa[4] = {pv.x, pv.y, pv.z, pv.w};
-            const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
-            unsigned long long run = 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                run += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
-            // block-exclusive prefix of (count, walkers): wavefront scan, then waves in order
-            unsigned long long xw = run, xc = (unsigned long long)nocc;
-            for (int o = 1; o < 64; o <<= 1) {
-                const unsigned long long yw = __shfl_up(xw, o, 64);
-                const unsigned long long yc = __shfl_up(xc, o, 64);
-                if (lane >= o) {
-                    xw += yw;
-                    xc += yc;
-                }
-            }
-            if (lane == 63) {
-                s_wsum[wid] = xw;
-                s_wcnt[wid] = (int)xc;
-            }
-            __syncthreads();
-            unsigned long long wbefore = xw - run;
-            int pos = (int)xc - nocc;
-            for (int w = 0; w < wid; ++w) {
-                wbefore += s_wsum[w];
-                pos += s_wcnt[w];
-            }
-            const int n_occ = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (pa[u] == 0) continue;
-                wbefore += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
-                s_pop[pos] = pa[u];
-                s_det[pos] = d.kv[base + 4 * t + u].det;
-                s_incl[pos] = wbefore;
-                ++pos;
-            }
-            __syncthreads();
-            // This chunk's part of the tile, split into 256 consecutive runs.
-            const unsigned long long lo_t = t0 > off_c ? t0 : off_c;
-            const unsigned long long hi_t = (t1 < off_c + nw_c) ? t1 : off_c + nw_c;
-            const unsigned long long per = (hi_t - lo_t + 255) / 256;
-            unsigned long long at = lo_t + (unsigned long long)t * per;
-            const unsigned long long at_end = (at + per < hi_t) ? at + per : hi_t;
-            const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
-            unsigned long long spawned = 0;
-            if (at < at_end) {
-                const unsigned long long local = at - off_c;
-                int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
-                while (sl < hi) {
-                    const int mid = (sl + hi) >> 1;
-                    if (s_incl[mid] > local) hi = mid;
-                    else sl = mid + 1;
-                }
-                uint32_t k = (uint32_t)(local - (sl ? s_incl[sl - 1] : 0ull));
-                for (;;) {
-                    const int32_t C = s_pop[sl];
-                    const uint64_t D = s_det[sl];
-                    const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
-                    const bool init = absC > d.n_a || D == d.d0;
-                    uint64_t x0, x1, x2, x3, x4, x5;
-                    draw2(d.seed, D, k, d.iter, 0u, x0, x1);
-                    draw2(d.seed, D, k, d.iter, 1u, x2, x3);
-                    draw2(d.seed, D, k, d.iter, 2u, x4, x5);
-                    Excit ex;
-                    if (excite(d, D, x0, x1, x2, x3, s_recip, defer, ex)) {
-                        if (isnan(ex.hel)) {
-                            const int q = atomicAdd(&Q.nsgl, 1);
-                            if (q < SGL_QUEUE) {
-                                Q.sgl[q] = SingleItem{D, ex.pgen, x4, C,
-                                                      (uint32_t)ex.p | ((uint32_t)ex.a << 8) |
-                                                          ((init ? 1u : 0u) << 16)};
-                            } else {
-                                ex.hel = hel_single(d, D, ex.p, ex.a);
-                            }
+            uint32_t k = (uint32_t)(local - (sl ? s_incl[sl - 1] : 0ull));
+            for (;;) {
+                const int32_t C = s_pop[sl];
+                const uint64_t D = s_det[sl];
+                const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
+                const bool init = absC > d.n_a || D == d.d0;
+                uint64_t x0, x1, x2, x3, x4, x5;
+                draw2(d.seed, D, k, d.iter, 0u, x0, x1);
+                draw2(d.seed, D, k, d.iter, 1u, x2, x3);
+                draw2(d.seed, D, k, d.iter, 2u, x4, x5);
+                Excit ex;
+                if (excite(d, D, x0, x1, x2, x3, s_recip, defer, ex)) {
+                    if (isnan(ex.hel)) {
+                        const int q = atomicAdd(&Q.nsgl, 1);
+                        if (q < SGL_QUEUE) {
+                            Q.sgl[q] = SingleItem{D, ex.pgen, x4, C,
+                                                  (uint32_t)ex.p | ((uint32_t)ex.a << 8) |
+                                                      ((init ? 1u : 0u) << 16)};
+                        } else {
+                            ex.hel = hel_single(d, D, ex.p, ex.a);
                         }
-                        if (!isnan(ex.hel) && ex.hel != 0.0) {
-                            const int32_t v = accept(d, ex.hel, ex.pgen, x4, C, status);
-                            if (v != 0) {
-                                ++spawned;
-                                const int q = atomicAdd(&Q.nspw, 1);
-                                if (q < SPW_QUEUE) {
-                                    Q.spd[q] = ex.det;
-                                    Q.spv[q] = make_int2(v, init ? 1 : 0);
-                                } else if (!table_add(d.kv, d.cap_mask, ex.det, v, init)) {
-                                    atomicOr(status, ST_TABLE_FULL);
-                                }
+                    }
+                    if (!isnan(ex.hel) && ex.hel != 0.0) {
+                        const int32_t v = accept(d, ex.hel, ex.pgen, x4, C, status);
+                        if (v != 0) {
+                            ++spawned;
+                            const int q = atomicAdd(&Q.nspw, 1);
+                            if (q < SPW_QUEUE) {
+                                Q.spd[q] = ex.det;
+                                Q.spv[q] = make_int2(v, init ? 1 : 0);
+                            } else if (!table_add(d.key, d.acc, d.cap_mask, ex.det, v, init)) {
+                                atomicOr(status, ST_TABLE_FULL);
                             }
                         }
                     }
-                    if (++at >= at_end) break;
-                    if ((int64_t)(++k) >= absC) {
-                        k = 0;
-                        ++sl;
-                    }
+                }
+                if (++at >= at_end) break;
+                if ((int64_t)(++k) >= absC) {
+                    k = 0;
+                    ++sl;
                 }
             }
-            // one atomic per wavefront for the spawn counter
-            const unsigned long long ws = wave_sum(spawned);
-            if (lane == 0 && ws) atomicAdd(&a.spawns[s], ws);
-            __syncthreads();
-            if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN)
-                drain_queues(Q, d, status, &a.spawns[s]);
-            ++c;
         }
+        // one atomic per wavefront for the spawn counter
+        const unsigned long long ws = wave_sum(spawned);
+        if (lane == 0 && ws) atomicAdd(&a.spawns[s], ws);
+        __syncthreads();
+        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, d, status, &a.spawns[s]);
     }
     __syncthreads();
     if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
@@ -704,11 +696,11 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
 // K4: death, annihilation and initiator test per slot, in place; the
 // diagonal element of newly occupied determinants; estimator partials.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t insert_unique(Slot *kv, uint64_t mask, uint64_t key) {
+__device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t mask, uint64_t key) {
     uint64_t h = mix64(key) & mask;
     for (uint64_t n = 0; n <= mask; ++n) {
         const unsigned long long old =
-            atomicCAS((unsigned long long *)&kv[h].det, 0ull, (unsigned long long)key);
+            atomicCAS((unsigned long long *)&keys[h], 0ull, (unsigned long long)key);
         if (old == 0ull) return (int64_t)h;
         h = (h + 1) & mask;
     }
@@ -735,7 +727,7 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
                                                const double *hpp, const double *jk) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const uint32_t i = queue[j];
-        d.hdiag[i] = hdiag_lds(d.e_core, d.kv[i].det, hpp, jk);
+        d.hdiag[i] = hdiag_lds(d.e_core, d.key[i], hpp, jk);
     }
 }
 
@@ -779,9 +771,13 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
             }
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK + 4 * t;
             // four consecutive slots per thread, all loads issued before any use
-            Slot sl[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) sl[u] = d.kv[base + u];
+            const ulonglong2 k01 = *reinterpret_cast<const ulonglong2 *>(d.key + base);
+            const ulonglong2 k23 = *reinterpret_cast<const ulonglong2 *>(d.key + base + 2);
+            const int4 a01 = *reinterpret_cast<const int4 *>(d.acc + base);
+            const int4 a23 = *reinterpret_cast<const int4 *>(d.acc + base + 2);
+            const uint64_t kin[4] = {k01.x, k01.y, k23.x, k23.y};
+            const int2 ain[4] = {make_int2(a01.x, a01.y), make_int2(a01.z, a01.w),
+                                 make_int2(a23.x, a23.y), make_int2(a23.z, a23.w)};
             const int4 pv = *reinterpret_cast<const int4 *>(d.pop + base);
             const double2 h01 = *reinterpret_cast<const double2 *>(d.hdiag + base);
             const double2 h23 = *reinterpret_cast<const double2 *>(d.hdiag + base + 2);
@@ -790,7 +786,7 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
             int32_t pout[4] = {pv.x, pv.y, pv.z, pv.w};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint64_t D = sl[u].det;
+                const uint64_t D = kin[u];
                 if (D == 0) continue;
                 ++used;
                 const int32_t p = pin[u];
@@ -813,11 +809,11 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
                 // Annihilation (Sec. 4.2): present after death -> add; otherwise the
                 // arrived walkers survive only if an initiator sent some of them.
                 const bool present = pd != 0 || D == d.d0;
-                const int64_t sp = sl[u].spop;
+                const int64_t sp = ain[u].x;
                 int64_t np;
                 if (present) {
                     np = pd + sp;
-                } else if (sp != 0 && sl[u].sflag) {
+                } else if (sp != 0 && ain[u].y) {
                     np = sp;
                 } else {
                     np = 0;
@@ -829,8 +825,6 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
                     np = 0;
                 }
                 pout[u] = (int32_t)np;
-                if (sl[u].spop != 0 || sl[u].sflag != 0)
-                    *reinterpret_cast<unsigned long long *>(&d.kv[base + u].spop) = 0ull;
                 if (np != 0 && p == 0 && isnan(hin[u])) {
                     // newly occupied: diagonal element computed with the queue
                     const int q = atomicAdd(&s_qn, 1);
@@ -845,6 +839,11 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
             }
             if (pout[0] != pin[0] || pout[1] != pin[1] || pout[2] != pin[2] || pout[3] != pin[3])
                 *reinterpret_cast<int4 *>(d.pop + base) = make_int4(pout[0], pout[1], pout[2], pout[3]);
+            // clear the arrived walkers of the iteration
+            if (a01.x | a01.y | a01.z | a01.w)
+                *reinterpret_cast<int4 *>(d.acc + base) = make_int4(0, 0, 0, 0);
+            if (a23.x | a23.y | a23.z | a23.w)
+                *reinterpret_cast<int4 *>(d.acc + base + 2) = make_int4(0, 0, 0, 0);
         }
         // fixed-order reduction: lane butterfly, then waves 0..3
         nw = wave_sum((long long)nw);
@@ -982,7 +981,7 @@ __global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const in
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t D = det[i];
-        const int64_t j = insert_unique(d.kv, d.cap_mask, D);
+        const int64_t j = insert_unique(d.key, d.cap_mask, D);
         if (j < 0) {
             atomicOr(err, 1u);
             continue;
@@ -992,13 +991,13 @@ __global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const in
     }
 }
 
-__global__ void k_rehash(SysDesc *desc, int32_t sys, const Slot *skv, const int32_t *spop,
-                         const double *shd, int64_t scap, Slot *dkv, int32_t *dpop, double *dhd,
+__global__ void k_rehash(SysDesc *desc, int32_t sys, const uint64_t *skv, const int32_t *spop,
+                         const double *shd, int64_t scap, uint64_t *dkv, int32_t *dpop, double *dhd,
                          uint32_t *err) {
     const SysDesc &d = desc[sys];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < scap;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t D = skv[i].det;
+        const uint64_t D = skv[i];
         if (D == 0) continue;
         const int32_t p = spop[i];
         if (p == 0 && D != d.d0) continue;
@@ -1012,11 +1011,11 @@ __global__ void k_rehash(SysDesc *desc, int32_t sys, const Slot *skv, const int3
     }
 }
 
-__global__ void k_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint64_t *odet,
+__global__ void k_compact(const uint64_t *kv, const int32_t *pop, int64_t cap, uint64_t *odet,
                           int32_t *opop, unsigned long long *count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t D = kv[i].det;
+        const uint64_t D = kv[i];
         const int32_t p = pop[i];
         if (D == 0 || p == 0) continue;
         const unsigned long long j = atomicAdd(count, 1ull);
@@ -1034,8 +1033,9 @@ hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const 
     return hipGetLastError();
 }
 
-hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const Slot *src_kv, const int32_t *src_pop,
-                         const double *src_hd, int64_t src_cap, Slot *dst_kv, int32_t *dst_pop,
+hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_kv,
+                         const int32_t *src_pop, const double *src_hd, int64_t src_cap,
+                         uint64_t *dst_kv, int32_t *dst_pop,
                          double *dst_hd, uint32_t *d_err, hipStream_t s) {
     const int64_t g = (src_cap + 255) / 256;
     hipLaunchKernelGGL(k_rehash, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, d_desc,
@@ -1043,7 +1043,7 @@ hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const Slot *src_kv, const
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const Slot *kv, const int32_t *pop, int64_t cap, uint64_t *out_det,
+hipError_t launch_compact(const uint64_t *kv, const int32_t *pop, int64_t cap, uint64_t *out_det,
                           int32_t *out_pop, unsigned long long *count, hipStream_t s) {
     const int64_t g = (cap + 255) / 256;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, kv,
