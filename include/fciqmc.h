@@ -208,7 +208,8 @@ int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
 
 /* ---- launch shape ----------------------------------------------------------
  * spawn_grid: workgroups of the spawning kernel; tile: consecutive attempts a
- * workgroup takes at a time (256 .. 2^20); post_grid: workgroups of the
+ * workgroup takes at a time (a power of two, 256 .. 2^20; a tile never spans
+ * two chunks of the table); post_grid: workgroups of the
  * death/annihilation kernel. Results never depend on these (every random
  * number is keyed by determinant and walker ordinal, every merge is an
  * integer sum). fciqmc_autotune runs iters_per_trial real iterations of every

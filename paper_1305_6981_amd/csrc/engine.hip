@@ -1219,8 +1219,8 @@ int fciqmc_set_profiling(fciqmc_t *h, int32_t on) {
 
 int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t post_grid) {
     if (!h) return set_err(FCIQMC_EINVAL, "null handle");
-    if (spawn_grid < 1 || post_grid < 1 || tile < 256 || tile > (1 << 20))
-        return set_err(FCIQMC_EINVAL, "launch shape out of range");
+    if (spawn_grid < 1 || post_grid < 1 || tile < 256 || tile > (1 << 20) || (tile & (tile - 1)))
+        return set_err(FCIQMC_EINVAL, "launch shape out of range (tile: a power of two, 256..2^20)");
     h->spawn_grid = spawn_grid;
     h->post_grid = post_grid;
     h->tile = tile;

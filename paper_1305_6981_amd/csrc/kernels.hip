@@ -366,7 +366,9 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
 __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
     __shared__ unsigned long long part[1024], tpart[1024];
     const int64_t n = *a.nchunks;
-    const unsigned long long tile = (unsigned long long)a.tile;
+    const unsigned long long tile = (unsigned long long)a.tile;   // a power of two
+    const int tsh = __builtin_ctzll(tile);
+    const unsigned long long tm = tile - 1;
     const int t = threadIdx.x;
     // contiguous ranges of an even length per thread: two-element vector loads
     const int64_t per = (((n + 1023) / 1024) + 1) & ~(int64_t)1;
@@ -378,12 +380,12 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
             const ulonglong2 v0 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
             const ulonglong2 v1 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 2);
             s += v0.x + v0.y + v1.x + v1.y;
-            st += (v0.x + tile - 1) / tile + (v0.y + tile - 1) / tile + (v1.x + tile - 1) / tile +
-                  (v1.y + tile - 1) / tile;
+            st += ((v0.x + tm) >> tsh) + ((v0.y + tm) >> tsh) + ((v1.x + tm) >> tsh) +
+                  ((v1.y + tm) >> tsh);
         }
         for (; i < e; ++i) {
             s += a.chunk_nw[i];
-            st += (a.chunk_nw[i] + tile - 1) / tile;
+            st += (a.chunk_nw[i] + tm) >> tsh;
         }
     }
     part[t] = s;
@@ -398,12 +400,27 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
         __syncthreads();
     }
     unsigned long long run = part[t] - s, trun = tpart[t] - st;  // exclusive
-    for (int64_t i = b; i < e; ++i) {
-        const unsigned long long v = a.chunk_nw[i];
-        a.chunk_off[i] = run;
-        a.chunk_toff[i] = trun;
-        run += v;
-        trun += (v + tile - 1) / tile;
+    if (b < e) {
+        int64_t i = b;
+        for (; i + 2 <= e; i += 2) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
+            ulonglong2 o, ot;
+            o.x = run;
+            o.y = run + v.x;
+            ot.x = trun;
+            ot.y = trun + ((v.x + tm) >> tsh);
+            run += v.x + v.y;
+            trun = ot.y + ((v.y + tm) >> tsh);
+            *reinterpret_cast<ulonglong2 *>(a.chunk_off + i) = o;
+            *reinterpret_cast<ulonglong2 *>(a.chunk_toff + i) = ot;
+        }
+        for (; i < e; ++i) {
+            const unsigned long long v = a.chunk_nw[i];
+            a.chunk_off[i] = run;
+            a.chunk_toff[i] = trun;
+            run += v;
+            trun += (v + tm) >> tsh;
+        }
     }
     if (t == 1023) {
         a.total[0] = part[1023];
