@@ -91,11 +91,13 @@ def bytes_per_kernel(rec, n_slots):
     return {
         # read the population of every slot of the table
         "k_chunk_sum": 4.0 * n_slots,
-        # read key+spawned sum, population, diagonal element of every slot; clear key+spawned
-        # sum and population; write key, population, diagonal element of every survivor
-        "k_post": (16 + 4 + 8) * n_slots + (16 + 4) * n_slots + (8 + 4 + 8) * nd,
-        # per attempt: key + population of its source slot; per spawn: one 16-byte slot update
-        "k_spawn": 12.0 * rec["attempts"] + 16.0 * spawns,
+        # read key, spawned-walker accumulator, population and diagonal element of every slot;
+        # write the new population of each occupied slot, clear each accumulator that
+        # received walkers, store H_DD of each newly occupied determinant (at most merged)
+        "k_post": 28.0 * n_slots + 4.0 * nd + 8.0 * merged + 8.0 * merged,
+        # stage key + population of every slot once; one key probe + one accumulator update
+        # (8 + 8 bytes) per accepted spawn
+        "k_spawn": 12.0 * n_slots + 16.0 * spawns,
     }
 
 
