@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "fciqmc_oracle.c")
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fPIC",
-           "-shared", "-o", LIB + ".tmp", src, "-lm"]
+           "-shared", "-pthread", "-o", LIB + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

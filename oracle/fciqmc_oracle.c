@@ -19,7 +19,17 @@
  *     and of the double-excitation formula (Sec. 5, 5.1, 5.2);
  *   - Slater-Condon matrix elements ("standard rules", Sec. 2);
  *   - projected energy (Eq. ProjE) and the shift (Sec. 2);
- *   - blocking analysis of the correlated ratio (Sec. 7, Flyvbjerg-Petersen).
+ *   - blocking analysis of the correlated ratio (Sec. 7, Flyvbjerg-Petersen);
+ *   - optionally, the distribution of determinants over P virtual processes
+ *     (Sec. 4.1): each determinant lives on the process picked by a second
+ *     Algorithm-1 hash (own random map, range P), every process spawns from
+ *     its own list into one block per destination, the blocks are transposed
+ *     (the all-to-all exchange), and each process compresses and annihilates
+ *     what it received against its own list. Optionally the reference gets a
+ *     process of its own and the rest are hashed over the other P-1. The
+ *     processes may run on host threads; results do not depend on P or on
+ *     the thread count (integer merges, determinant-keyed random numbers),
+ *     except the rounding order of the projected-energy numerator sum.
  *
  * Readings where the paper is silent (each listed in the design notes):
  *   RNG = Philox4x32-10 (Salmon et al., SC'11) keyed by the seed, with a
@@ -37,11 +47,14 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
-static char g_err[512];
+/* Per host thread, so that worker threads of the virtual-process mode keep
+ * their own message until the caller collects it. */
+static _Thread_local char g_err[512];
 
 static int fail(const char *msg)
 {
@@ -565,6 +578,25 @@ static uint64_t splitmix64(uint64_t *state)
     return z ^ (z >> 31);
 }
 
+/* A 1-to-1 map from spin orbitals to distinct random integers (Algorithm 1). */
+static void make_map(int64_t map[64], uint64_t seed)
+{
+    uint64_t st = seed;
+    for (int r = 0; r < 64; r++) {
+        for (;;) {
+            int64_t v = (int64_t)(splitmix64(&st) >> 2);
+            int dup = 0;
+            for (int t = 0; t < r; t++)
+                if (map[t] == v)
+                    dup = 1;
+            if (!dup && v != 0) {
+                map[r] = v;
+                break;
+            }
+        }
+    }
+}
+
 static int ml_init(mainlist_t *ml, int64_t cap, int64_t range, uint64_t hash_seed)
 {
     memset(ml, 0, sizeof *ml);
@@ -580,21 +612,7 @@ static int ml_init(mainlist_t *ml, int64_t cap, int64_t range, uint64_t hash_see
         return fail("oracle: out of host memory");
     for (int64_t i = 0; i < range; i++)
         ml->head[i] = -1;
-    /* A 1-to-1 map from spin orbitals to distinct random integers. */
-    uint64_t st = hash_seed;
-    for (int r = 0; r < 64; r++) {
-        for (;;) {
-            int64_t v = (int64_t)(splitmix64(&st) >> 2);
-            int dup = 0;
-            for (int t = 0; t < r; t++)
-                if (ml->map[t] == v)
-                    dup = 1;
-            if (!dup && v != 0) {
-                ml->map[r] = v;
-                break;
-            }
-        }
-    }
+    make_map(ml->map, hash_seed);
     return 0;
 }
 
@@ -724,12 +742,27 @@ typedef struct {
     uint32_t flag;
 } spawn_t;
 
+/* One virtual process (Sec. 4.1): its part of the main list, the spawned
+ * records it created, bucketed by destination process, and the records it
+ * received in the exchange. */
+typedef struct {
+    mainlist_t ml;
+    spawn_t **out;            /* out[q]: records created here for process q */
+    int64_t *n_out, *cap_out;
+    spawn_t *in;              /* records received from every process, sender order */
+    int64_t n_in, cap_in;
+    /* this process's share of the last iteration's statistics */
+    int64_t attempts, merged, aborted, nw, nd, c0;
+    double num;
+    char err[512];
+} proc_t;
+
 struct orc_state {
     sys_t sys;
     orc_params prm;
-    mainlist_t ml;
-    spawn_t *spawn;
-    int64_t n_spawn, cap_spawn;
+    int32_t n_procs, n_threads;
+    proc_t *proc;
+    int64_t pmap[64];         /* Algorithm 1 map of the process hash */
     /* dynamics */
     int64_t iter;
     double shift;
@@ -749,21 +782,40 @@ static int cmp_spawn(const void *a, const void *b)
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
-static int push_spawn(orc_state *st, uint64_t det, int64_t pop, uint32_t flag)
+static int push_rec(spawn_t **buf, int64_t *n, int64_t *cap, uint64_t det, int64_t pop,
+                    uint32_t flag)
 {
-    if (st->n_spawn == st->cap_spawn) {
-        int64_t nc = st->cap_spawn ? st->cap_spawn * 2 : 1024;
-        spawn_t *p = realloc(st->spawn, (size_t)nc * sizeof(spawn_t));
+    if (*n == *cap) {
+        int64_t nc = *cap ? *cap * 2 : 1024;
+        spawn_t *p = realloc(*buf, (size_t)nc * sizeof(spawn_t));
         if (!p)
             return fail("oracle: out of host memory");
-        st->spawn = p;
-        st->cap_spawn = nc;
+        *buf = p;
+        *cap = nc;
     }
-    st->spawn[st->n_spawn].det = det;
-    st->spawn[st->n_spawn].pop = pop;
-    st->spawn[st->n_spawn].flag = flag;
-    st->n_spawn++;
+    (*buf)[*n].det = det;
+    (*buf)[*n].pop = pop;
+    (*buf)[*n].flag = flag;
+    (*n)++;
     return 0;
+}
+
+/* Owning process of a determinant: the process hash of Sec. 4.1 (Algorithm 1
+ * with its own map, over the range of processes); with a dedicated reference
+ * process, the reference sits on process 0 and the rest hash over 1..P-1. */
+static int owner_of(const orc_state *st, uint64_t det)
+{
+    if (st->n_procs == 1)
+        return 0;
+    int lo = 0;
+    if (st->prm.ref_own_proc) {
+        if (det == st->sys.d0)
+            return 0;
+        lo = 1;
+    }
+    int32_t occ[64];
+    int n = orc_decode(det, occ);
+    return lo + (int)hash_alg1(st->pmap, occ, n, st->n_procs - lo);
 }
 
 static int push_series(orc_state *st, double num, double den, double shift)
@@ -971,6 +1023,46 @@ int orc_blocking(const double *num, const double *den, int64_t n, double *mean_r
 /* ------------------------------------------------------------------------ */
 /* Run interface.                                                            */
 /* ------------------------------------------------------------------------ */
+static void procs_free(orc_state *st)
+{
+    if (!st->proc)
+        return;
+    for (int p = 0; p < st->n_procs; p++) {
+        proc_t *pr = &st->proc[p];
+        ml_free(&pr->ml);
+        if (pr->out)
+            for (int q = 0; q < st->n_procs; q++)
+                free(pr->out[q]);
+        free(pr->out);
+        free(pr->n_out);
+        free(pr->cap_out);
+        free(pr->in);
+    }
+    free(st->proc);
+    st->proc = NULL;
+}
+
+/* Empty main lists on every process, hashed over `range` buckets each. */
+static int procs_init(orc_state *st, int64_t range)
+{
+    const int P = st->n_procs;
+    uint64_t hs = st->prm.hash_seed ? st->prm.hash_seed : 0x5EED5EEDull;
+    st->proc = calloc((size_t)P, sizeof(proc_t));
+    if (!st->proc)
+        return fail("oracle: out of host memory");
+    for (int p = 0; p < P; p++) {
+        proc_t *pr = &st->proc[p];
+        pr->out = calloc((size_t)P, sizeof(spawn_t *));
+        pr->n_out = calloc((size_t)P, sizeof(int64_t));
+        pr->cap_out = calloc((size_t)P, sizeof(int64_t));
+        if (!pr->out || !pr->n_out || !pr->cap_out)
+            return fail("oracle: out of host memory");
+        if (ml_init(&pr->ml, 1024, range, hs) != 0)
+            return -1;
+    }
+    return 0;
+}
+
 int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
 {
     *out = NULL;
@@ -980,6 +1072,10 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
         return fail("oracle: tau must be positive");
     if (prm->shift_every <= 0)
         return fail("oracle: shift_every must be positive");
+    if (prm->n_procs < 0 || prm->n_procs > 4096 || prm->n_threads < 0)
+        return fail("oracle: n_procs must be in 0..4096 and n_threads >= 0");
+    if (prm->ref_own_proc && prm->n_procs < 2)
+        return fail("oracle: a dedicated reference process needs n_procs >= 2");
     orc_state *st = calloc(1, sizeof *st);
     if (!st)
         return fail("oracle: out of host memory");
@@ -990,15 +1086,20 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
         return -1;
     }
     st->prm = *prm;
+    st->n_procs = prm->n_procs > 0 ? prm->n_procs : 1;
+    st->n_threads = prm->n_threads > 0 ? prm->n_threads : 1;
+    make_map(st->pmap, prm->proc_seed ? prm->proc_seed : 0xD15781B7ull);
     int64_t range = prm->hash_range > 0 ? prm->hash_range : 1024;
-    if (ml_init(&st->ml, 1024, range, prm->hash_seed ? prm->hash_seed : 0x5EED5EEDull) != 0) {
+    if (procs_init(st, range) != 0) {
         orc_free(st);
         return -1;
     }
     int64_t n0 = prm->n_init > 0 ? prm->n_init : 10;
-    if (n0 > 2147483647)
+    if (n0 > 2147483647) {
+        orc_free(st);
         return fail("oracle: initial population exceeds int32");
-    ml_insert(&st->ml, st->sys.d0, (int32_t)n0, st->sys.e0);
+    }
+    ml_insert(&st->proc[owner_of(st, st->sys.d0)].ml, st->sys.d0, (int32_t)n0, st->sys.e0);
     st->shift = prm->shift0;
     st->nw = n0;
     st->nd = 1;
@@ -1011,8 +1112,7 @@ void orc_free(orc_state *st)
 {
     if (!st)
         return;
-    ml_free(&st->ml);
-    free(st->spawn);
+    procs_free(st);
     free(st->sys.h1);
     free(st->sys.eri);
     free(st->s_num);
@@ -1027,20 +1127,21 @@ static int is_initiator(const orc_state *st, uint64_t det, int32_t pop)
     return a > st->prm.n_a || det == st->sys.d0;
 }
 
-/* One iteration in the paper's order: spawning from every walker, death on
- * each determinant, then compression and annihilation of the spawned list
- * against the main list with the initiator test, then the estimators. */
-static int one_iteration(orc_state *st)
+/* First half of an iteration on process p: spawning from every walker of its
+ * list and death on each of its determinants (Sec. 2). Spawned records go to
+ * the block of the process that owns the child (Sec. 4.1). */
+static int proc_spawn_death(orc_state *st, int p)
 {
     const sys_t *s = &st->sys;
     const double tau = st->prm.tau;
     const int64_t it = st->iter;
-    mainlist_t *ml = &st->ml;
-    st->n_spawn = 0;
+    proc_t *pr = &st->proc[p];
+    mainlist_t *ml = &pr->ml;
+    for (int q = 0; q < st->n_procs; q++)
+        pr->n_out[q] = 0;
     int64_t attempts = 0;
     detinfo_t di;
 
-    /* Spawning and death, one occupied determinant at a time (Sec. 2). */
     int64_t high = ml->high;
     for (int64_t slot = 0; slot < high; slot++) {
         uint64_t D = ml->det[slot];
@@ -1068,15 +1169,16 @@ static int one_iteration(orc_state *st)
             draw_block(st->prm.seed, D, (uint32_t)k, it, 2, b);
             x[4] = b[0];
             /* Eq. pspawn: integer part created deterministically, fraction stochastically. */
-            double pr = (tau * fabs(ex.hel)) / ex.pgen;
-            double fl = floor(pr);
+            double ps = (tau * fabs(ex.hel)) / ex.pgen;
+            double fl = floor(ps);
             if (fl > 1073741824.0)
                 return fail("oracle: spawn count overflow");
-            int64_t m = (int64_t)fl + (unit_uniform(x[4]) < pr - fl ? 1 : 0);
+            int64_t m = (int64_t)fl + (unit_uniform(x[4]) < ps - fl ? 1 : 0);
             if (m == 0)
                 continue;
             int64_t sgn = ((C > 0) ? 1 : -1) * (ex.hel > 0.0 ? 1 : -1);
-            if (push_spawn(st, ex.det, -sgn * m, flag) != 0)
+            int q = owner_of(st, ex.det);
+            if (push_rec(&pr->out[q], &pr->n_out[q], &pr->cap_out[q], ex.det, -sgn * m, flag) != 0)
                 return -1;
         }
         /* Eq. pdeath, all walkers on the determinant at once. */
@@ -1096,19 +1198,81 @@ static int one_iteration(orc_state *st)
         else
             ml->pop[slot] = (int32_t)cnew;
     }
+    pr->attempts = attempts;
+    return 0;
+}
 
-    /* Sort and compress the spawned list (Sec. 4.1): sum signed walkers on each
-     * determinant, OR the initiator flags, drop entries that cancel to zero. */
-    qsort(st->spawn, (size_t)st->n_spawn, sizeof(spawn_t), cmp_spawn);
+/* This process's share of N_w, N_d, C_0 and the numerator of Eq. ProjE. */
+static void proc_stats(orc_state *st, int q)
+{
+    const sys_t *s = &st->sys;
+    proc_t *pr = &st->proc[q];
+    const mainlist_t *ml = &pr->ml;
+    int64_t nw = 0, nd = 0, c0 = 0;
+    double num = 0.0;
+    for (int64_t slot = 0; slot < ml->high; slot++) {
+        uint64_t D = ml->det[slot];
+        if (!D)
+            continue;
+        int32_t C = ml->pop[slot];
+        if (D == s->d0)
+            c0 = C;
+        if (C == 0)
+            continue;
+        nw += C < 0 ? -(int64_t)C : C;
+        nd++;
+        if (D != s->d0 && popcount64(D ^ s->d0) <= 4)
+            num = num + hel_general(s, D, s->d0) * (double)C;
+    }
+    pr->nw = nw;
+    pr->nd = nd;
+    pr->c0 = c0;
+    pr->num = num;
+}
+
+/* Sum of the per-process shares, in process order. */
+static void gather_stats(orc_state *st)
+{
+    st->nw = st->nd = st->c0 = 0;
+    st->num = 0.0;
+    for (int p = 0; p < st->n_procs; p++) {
+        st->nw += st->proc[p].nw;
+        st->nd += st->proc[p].nd;
+        st->c0 += st->proc[p].c0;
+        st->num = st->num + st->proc[p].num;
+    }
+}
+
+/* Second half on process q: receive the blocks addressed to it (the
+ * exchange of Sec. 4.1, a transpose of the per-destination blocks), sort and
+ * compress them, annihilate against the local list with the initiator test
+ * (Sec. 4.2), then this process's share of the estimators (Eq. ProjE). */
+static int proc_annihilate(orc_state *st, int q)
+{
+    const sys_t *s = &st->sys;
+    proc_t *pr = &st->proc[q];
+    mainlist_t *ml = &pr->ml;
+    pr->n_in = 0;
+    for (int p = 0; p < st->n_procs; p++) {
+        const proc_t *src = &st->proc[p];
+        for (int64_t t = 0; t < src->n_out[q]; t++)
+            if (push_rec(&pr->in, &pr->n_in, &pr->cap_in, src->out[q][t].det,
+                         src->out[q][t].pop, src->out[q][t].flag) != 0)
+                return -1;
+    }
+
+    /* Sort and compress (Sec. 4.1): sum signed walkers on each determinant,
+     * OR the initiator flags, drop entries that cancel to zero. */
+    qsort(pr->in, (size_t)pr->n_in, sizeof(spawn_t), cmp_spawn);
     int64_t merged = 0, aborted = 0;
     int64_t i = 0;
-    while (i < st->n_spawn) {
-        uint64_t D = st->spawn[i].det;
+    while (i < pr->n_in) {
+        uint64_t D = pr->in[i].det;
         int64_t c = 0;
         uint32_t f = 0;
-        while (i < st->n_spawn && st->spawn[i].det == D) {
-            c += st->spawn[i].pop;
-            f |= st->spawn[i].flag;
+        while (i < pr->n_in && pr->in[i].det == D) {
+            c += pr->in[i].pop;
+            f |= pr->in[i].flag;
             i++;
         }
         if (c == 0)
@@ -1133,34 +1297,102 @@ static int one_iteration(orc_state *st)
             aborted += c < 0 ? -c : c;
         }
     }
+    pr->merged = merged;
+    pr->aborted = aborted;
+    proc_stats(st, q);
+    return 0;
+}
 
-    /* Estimators on the new list (Eq. ProjE). */
-    int64_t nw = 0, nd = 0, c0 = 0;
-    double num = 0.0;
-    for (int64_t slot = 0; slot < ml->high; slot++) {
-        uint64_t D = ml->det[slot];
-        if (!D)
-            continue;
-        int32_t C = ml->pop[slot];
-        if (D == s->d0)
-            c0 = C;
-        if (C == 0)
-            continue;
-        nw += C < 0 ? -(int64_t)C : C;
-        nd++;
-        if (D != s->d0 && popcount64(D ^ s->d0) <= 4)
-            num = num + hel_general(s, D, s->d0) * (double)C;
+typedef struct {
+    orc_state *st;
+    int phase, first, stride;
+    int bad;                  /* lowest failing process, or -1 */
+} job_t;
+
+static void *run_job(void *arg)
+{
+    job_t *j = arg;
+    j->bad = -1;
+    for (int p = j->first; p < j->st->n_procs; p += j->stride) {
+        int rc = j->phase == 0 ? proc_spawn_death(j->st, p) : proc_annihilate(j->st, p);
+        if (rc != 0) {
+            snprintf(j->st->proc[p].err, sizeof j->st->proc[p].err, "%s", g_err);
+            j->bad = p;
+            break;
+        }
     }
-    st->nw = nw;
-    st->nd = nd;
-    st->c0 = c0;
-    st->num = num;
+    return NULL;
+}
+
+/* Run one phase on every process, spread round-robin over the host threads;
+ * a failure is reported for the lowest failing process. */
+static int run_phase(orc_state *st, int phase)
+{
+    int T = st->n_threads < st->n_procs ? st->n_threads : st->n_procs;
+    job_t jobs[256];
+    pthread_t th[256];
+    if (T > 256)
+        T = 256;
+    int started = 1;
+    for (int t = 0; t < T; t++) {
+        jobs[t].st = st;
+        jobs[t].phase = phase;
+        jobs[t].first = t;
+        jobs[t].stride = T;
+        jobs[t].bad = -1;
+    }
+    for (int t = 1; t < T; t++) {
+        if (pthread_create(&th[t], NULL, run_job, &jobs[t]) != 0)
+            break;
+        started++;
+    }
+    if (started < T) {
+        /* Not enough threads: do the rest on this one. */
+        for (int t = started; t < T; t++)
+            run_job(&jobs[t]);
+    }
+    run_job(&jobs[0]);
+    for (int t = 1; t < started; t++)
+        pthread_join(th[t], NULL);
+    int bad = -1;
+    for (int t = 0; t < T; t++)
+        if (jobs[t].bad >= 0 && (bad < 0 || jobs[t].bad < bad))
+            bad = jobs[t].bad;
+    if (bad >= 0)
+        return fail(st->proc[bad].err);
+    return 0;
+}
+
+/* One iteration in the paper's order: spawning from every walker, death on
+ * each determinant, then the exchange, compression and annihilation of the
+ * spawned list against the main list with the initiator test, then the
+ * estimators and the shift. */
+static int one_iteration(orc_state *st)
+{
+    const double tau = st->prm.tau;
+    const int P = st->n_procs;
+    if (run_phase(st, 0) != 0 || run_phase(st, 1) != 0)
+        return -1;
+
+    /* Statistics aggregation over processes, in process order. */
+    int64_t attempts = 0, spawns = 0, merged = 0, aborted = 0;
+    for (int p = 0; p < P; p++) {
+        const proc_t *pr = &st->proc[p];
+        attempts += pr->attempts;
+        for (int q = 0; q < P; q++)
+            spawns += pr->n_out[q];
+        merged += pr->merged;
+        aborted += pr->aborted;
+    }
+    gather_stats(st);
+    const int64_t nw = st->nw, c0 = st->c0;
+    const double num = st->num;
     st->attempts = attempts;
-    st->spawns = st->n_spawn;
+    st->spawns = spawns;
     st->merged = merged;
     st->aborted = aborted;
     st->tot_attempts += attempts;
-    st->tot_spawns += st->n_spawn;
+    st->tot_spawns += spawns;
     st->iter++;
 
     /* Shift: held until the walker target is reached, then
@@ -1235,22 +1467,28 @@ int64_t orc_walkers(orc_state *st, uint64_t *det, int32_t *pop, uint32_t *flags,
     if (!st)
         return fail("oracle: null state");
     int64_t n = 0;
-    for (int64_t slot = 0; slot < st->ml.high; slot++)
-        if (st->ml.det[slot] && st->ml.pop[slot] != 0)
-            n++;
+    for (int p = 0; p < st->n_procs; p++) {
+        const mainlist_t *ml = &st->proc[p].ml;
+        for (int64_t slot = 0; slot < ml->high; slot++)
+            if (ml->det[slot] && ml->pop[slot] != 0)
+                n++;
+    }
     if (!det)
         return n;
     spawn_t *tmp = malloc((size_t)(n ? n : 1) * sizeof(spawn_t));
     if (!tmp)
         return fail("oracle: out of host memory");
     int64_t k = 0;
-    for (int64_t slot = 0; slot < st->ml.high; slot++)
-        if (st->ml.det[slot] && st->ml.pop[slot] != 0) {
-            tmp[k].det = st->ml.det[slot];
-            tmp[k].pop = st->ml.pop[slot];
-            tmp[k].flag = (uint32_t)is_initiator(st, st->ml.det[slot], st->ml.pop[slot]);
-            k++;
-        }
+    for (int p = 0; p < st->n_procs; p++) {
+        const mainlist_t *ml = &st->proc[p].ml;
+        for (int64_t slot = 0; slot < ml->high; slot++)
+            if (ml->det[slot] && ml->pop[slot] != 0) {
+                tmp[k].det = ml->det[slot];
+                tmp[k].pop = ml->pop[slot];
+                tmp[k].flag = (uint32_t)is_initiator(st, ml->det[slot], ml->pop[slot]);
+                k++;
+            }
+    }
     qsort(tmp, (size_t)n, sizeof(spawn_t), cmp_spawn);
     for (int64_t t = 0; t < n && t < cap; t++) {
         det[t] = tmp[t].det;
@@ -1263,29 +1501,39 @@ int64_t orc_walkers(orc_state *st, uint64_t *det, int32_t *pop, uint32_t *flags,
     return n;
 }
 
+int64_t orc_proc_dets(orc_state *st, int32_t p)
+{
+    if (!st || p < 0 || p >= st->n_procs)
+        return fail("oracle: bad process index");
+    return st->proc[p].ml.n_entries;
+}
+
+int32_t orc_owner(const orc_state *st, uint64_t det) { return owner_of(st, det); }
+
 int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int64_t n,
                      int64_t iteration, double shift, int64_t n_prev, int32_t varying,
                      int64_t n_var)
 {
     if (!st)
         return fail("oracle: null state");
-    uint64_t hs = st->prm.hash_seed ? st->prm.hash_seed : 0x5EED5EEDull;
-    int64_t range = st->ml.range;
-    ml_free(&st->ml);
-    if (ml_init(&st->ml, 1024, range, hs) != 0)
+    int64_t range = st->proc[0].ml.range;
+    procs_free(st);
+    if (procs_init(st, range) != 0)
         return -1;
     int have_ref = 0;
     for (int64_t t = 0; t < n; t++) {
         if (pop[t] == 0)
             continue;
-        if (ml_find(&st->ml, det[t]) >= 0)
+        mainlist_t *ml = &st->proc[owner_of(st, det[t])].ml;
+        if (ml_find(ml, det[t]) >= 0)
             return fail("oracle: duplicate determinant in walker list");
         if (det[t] == st->sys.d0)
             have_ref = 1;
-        if (ml_insert(&st->ml, det[t], pop[t], hdiag_of(&st->sys, det[t])) < 0)
+        if (ml_insert(ml, det[t], pop[t], hdiag_of(&st->sys, det[t])) < 0)
             return -1;
     }
-    if (!have_ref && ml_insert(&st->ml, st->sys.d0, 0, st->sys.e0) < 0)
+    if (!have_ref &&
+        ml_insert(&st->proc[owner_of(st, st->sys.d0)].ml, st->sys.d0, 0, st->sys.e0) < 0)
         return -1;
     st->iter = iteration;
     st->shift = shift;
@@ -1293,22 +1541,9 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
     st->varying = varying;
     st->n_var = n_var;
     st->n_series = 0;
-    st->nw = st->nd = st->c0 = 0;
-    st->num = 0.0;
-    for (int64_t slot = 0; slot < st->ml.high; slot++) {
-        uint64_t D = st->ml.det[slot];
-        int32_t C = st->ml.pop[slot];
-        if (!D)
-            continue;
-        if (D == st->sys.d0)
-            st->c0 = C;
-        if (C == 0)
-            continue;
-        st->nw += C < 0 ? -(int64_t)C : C;
-        st->nd++;
-        if (D != st->sys.d0 && popcount64(D ^ st->sys.d0) <= 4)
-            st->num = st->num + hel_general(&st->sys, D, st->sys.d0) * (double)C;
-    }
+    for (int p = 0; p < st->n_procs; p++)
+        proc_stats(st, p);
+    gather_stats(st);
     return 0;
 }
 
@@ -1319,7 +1554,7 @@ int64_t orc_hash(const orc_state *st, uint64_t det, int64_t range)
 {
     int32_t occ[64];
     int n = orc_decode(det, occ);
-    return hash_alg1(st->ml.map, occ, n, range);
+    return hash_alg1(st->proc[0].ml.map, occ, n, range);
 }
 
 double orc_hel(const orc_state *st, uint64_t bra, uint64_t ket)

@@ -3,9 +3,10 @@
  * "Linear-scaling and parallelizable algorithms for stochastic quantum
  * chemistry" (arXiv:1305.6981).
  *
- * TEST INFRASTRUCTURE ONLY. This is a plain, slow, single-threaded reference
- * implementation used by the test-suite, the smoke check and the CPU baseline
- * leg of the benchmark. The product library never links, loads or calls it,
+ * TEST INFRASTRUCTURE ONLY. This is a plain, slow reference implementation
+ * (single-threaded unless the virtual processes are spread over host threads)
+ * used by the test-suite, the smoke check and the CPU baseline leg of the
+ * benchmark. The product library never links, loads or calls it,
  * and it shares no source with the HIP path.
  *
  * Conventions (shared only as a *data format* with the product ABI):
@@ -40,6 +41,12 @@ typedef struct {
     int32_t avg_start, pad0;
     uint64_t hash_seed;         /* seeds the random orbital map of Algorithm 1 */
     int64_t hash_range;         /* initial size of the main-list hash table; 0 = auto */
+    /* Virtual processes (Sec. 4.1): 0 or 1 = one list. */
+    int32_t n_procs;
+    int32_t ref_own_proc;       /* 1: the reference alone on process 0 (needs n_procs >= 2) */
+    uint64_t proc_seed;         /* seeds the random map of the process hash; 0 = default */
+    int32_t n_threads;          /* host threads over which the processes run; 0 = 1 */
+    int32_t pad1;
 } orc_params;
 
 typedef struct {
@@ -63,6 +70,8 @@ int     orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop,
                          int64_t iteration, double shift, int64_t n_prev, int32_t varying,
                          int64_t n_var);
 void    orc_free(orc_state *st);
+int64_t orc_proc_dets(orc_state *st, int32_t p);           /* main-list entries on process p */
+int32_t orc_owner(const orc_state *st, uint64_t det);     /* process that owns det */
 const char *orc_last_error(void);
 
 /* Unit-level entry points used by the pins. */

@@ -23,7 +23,9 @@ class OrcParams(C.Structure):
                 ("shift_every", C.c_int32), ("n_a", C.c_int32),
                 ("target", C.c_int64), ("n_init", C.c_int64), ("seed", C.c_uint64),
                 ("avg_start", C.c_int32), ("pad0", C.c_int32),
-                ("hash_seed", C.c_uint64), ("hash_range", C.c_int64)]
+                ("hash_seed", C.c_uint64), ("hash_range", C.c_int64),
+                ("n_procs", C.c_int32), ("ref_own_proc", C.c_int32),
+                ("proc_seed", C.c_uint64), ("n_threads", C.c_int32), ("pad1", C.c_int32)]
 
 
 class OrcEst(C.Structure):
@@ -58,6 +60,10 @@ def lib():
         L.orc_decode.argtypes = [C.c_uint64, vp]
         L.orc_hash.argtypes = [vp, C.c_uint64, C.c_int64]
         L.orc_hash.restype = C.c_int64
+        L.orc_proc_dets.argtypes = [vp, C.c_int32]
+        L.orc_proc_dets.restype = C.c_int64
+        L.orc_owner.argtypes = [vp, C.c_uint64]
+        L.orc_owner.restype = C.c_int32
         L.orc_hel.argtypes = [vp, C.c_uint64, C.c_uint64]
         L.orc_hel.restype = C.c_double
         L.orc_hdiag.argtypes = [vp, C.c_uint64]
@@ -98,9 +104,16 @@ def blocking(num, den=None):
 
 
 class Oracle:
-    """One FCIQMC run on the CPU (plain, single-threaded)."""
+    """One FCIQMC run on the CPU.
 
-    def __init__(self, ham, params, hash_seed: int = 0, hash_range: int = 0):
+    By default one main list on one thread. With ``n_procs`` > 1 the
+    determinants are distributed over that many virtual processes by the
+    process hash of Sec. 4.1 (``ref_own_proc``: the reference alone on process
+    0), which run on ``n_threads`` host threads."""
+
+    def __init__(self, ham, params, hash_seed: int = 0, hash_range: int = 0,
+                 n_procs: int = 1, ref_own_proc: bool = False, proc_seed: int = 0,
+                 n_threads: int = 1):
         L = lib()
         self._h1 = np.ascontiguousarray(ham.h1, dtype=np.float64)
         self._eri = np.ascontiguousarray(ham.eri, dtype=np.float64)
@@ -115,7 +128,8 @@ class Oracle:
         p = OrcParams(params.tau, params.shift_damping, params.initial_shift,
                       params.shift_update_every, params.initiator_threshold,
                       params.target_walkers, params.initial_walkers, params.seed,
-                      params.avg_start, 0, hash_seed, hash_range)
+                      params.avg_start, 0, hash_seed, hash_range, n_procs,
+                      int(bool(ref_own_proc)), proc_seed, n_threads, 0)
         self._h = C.c_void_p()
         if L.orc_create(C.byref(h), C.byref(p), C.byref(self._h)) != 0:
             raise RuntimeError(L.orc_last_error().decode())
@@ -165,6 +179,15 @@ class Oracle:
 
     def hdiag(self, det: int) -> float:
         return lib().orc_hdiag(self._h, C.c_uint64(det))
+
+    def proc_dets(self, p: int) -> int:
+        n = lib().orc_proc_dets(self._h, p)
+        if n < 0:
+            raise RuntimeError(lib().orc_last_error().decode())
+        return n
+
+    def owner(self, det: int) -> int:
+        return lib().orc_owner(self._h, C.c_uint64(det))
 
     def hash(self, det: int, rng: int) -> int:
         return lib().orc_hash(self._h, C.c_uint64(det), rng)
