@@ -131,13 +131,9 @@ def cpu_baseline(ham, prm, det, pop, e, budget_attempts):
     from oracle import oracle as O
     rng = np.random.default_rng(7)
     order = rng.permutation(len(det))
-    take, acc = [], 0
-    for i in order:
-        take.append(i)
-        acc += abs(int(pop[i]))
-        if acc >= budget_attempts:
-            break
-    take = np.sort(np.asarray(take))
+    acc = np.cumsum(np.abs(pop[order].astype(np.int64)))
+    n_take = min(len(order), int(np.searchsorted(acc, budget_attempts)) + 1)
+    take = np.sort(order[:n_take])
     o = O.Oracle(ham, prm)
     o.load_walkers(det[take], pop[take], iteration=e["iteration"], shift=e["shift"],
                    n_prev=e["n_prev"], varying=1, n_var=e["n_var"])
@@ -145,13 +141,31 @@ def cpu_baseline(ham, prm, det, pop, e, budget_attempts):
     o.iterate(1)
     dt = time.perf_counter() - t0
     eo = o.estimates()
+    w1 = o.walkers()
     o.close()
-    return {"value": eo["attempts"] / dt, "unit": "spawn attempts/s", "cores": 1,
-            "kind": "oracle",
-            "annihilated_dets_per_s": eo["spawns"] / dt,
-            "sample": f"one iteration of the single-threaded oracle on {len(take)} determinants "
-                      f"({eo['attempts']} walkers) drawn at random from the timed walker list; "
-                      f"{dt:.1f} s"}
+    out = {"value": eo["attempts"] / dt, "unit": "spawn attempts/s", "cores": 1,
+           "kind": "oracle",
+           "annihilated_dets_per_s": eo["spawns"] / dt,
+           "sample": f"one iteration of the single-threaded oracle on {len(take)} determinants "
+                     f"({eo['attempts']} walkers) drawn at random from the timed walker list; "
+                     f"{dt:.1f} s"}
+    # The same iteration with the determinants distributed over one virtual
+    # process per host thread (the paper's parallel scheme, on the host cores).
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    o = O.Oracle(ham, prm, n_procs=threads, n_threads=threads)
+    o.load_walkers(det[take], pop[take], iteration=e["iteration"], shift=e["shift"],
+                   n_prev=e["n_prev"], varying=1, n_var=e["n_var"])
+    t0 = time.perf_counter()
+    o.iterate(1)
+    dt = time.perf_counter() - t0
+    ep = o.estimates()
+    same = all(np.array_equal(a, b) for a, b in zip(w1, o.walkers()))
+    o.close()
+    out["virtual_processes"] = {"value": ep["attempts"] / dt, "unit": "spawn attempts/s",
+                                "cores": threads, "processes": threads,
+                                "annihilated_dets_per_s": ep["spawns"] / dt,
+                                "same_walkers_as_single_thread": bool(same)}
+    return out
 
 
 def batched_vs_plain(F, S, iters, scale):
@@ -258,7 +272,7 @@ def main():
     ap.add_argument("--walkers", type=float, default=1e8)
     ap.add_argument("--growth-shift", type=float, default=40.0)
     ap.add_argument("--initial-walkers", type=int, default=20000)
-    ap.add_argument("--cpu-attempts", type=float, default=4e6)
+    ap.add_argument("--cpu-attempts", type=float, default=2.5e7)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-scale", type=float, default=0.2)
