@@ -9,6 +9,11 @@ constexpr int CHUNK = 1024;          // main-table slots per chunk (one workgrou
 constexpr int NCLASS = 16;           // symmetry classes: 2 spins x up to 8 abelian irreps
 constexpr int REC_CAP = 256;         // per-system ring of per-iteration records
 constexpr int MAX_GRAPH_ITERS = 64;  // iterations captured in one graph launch
+constexpr int SCAN_G = 2048;         // workgroups of the chunk-sum and scan-down kernels; each
+                                     // takes one contiguous range of chunks
+constexpr int FIN_BLOCKS = 64;       // workgroups per system reducing the chunk statistics
+constexpr int SLOTS_PER_SPAWN_REC = 8; // spawned-list capacity: one record per 8 table slots
+                                       // (at least 2^20); a fuller list is merged directly
 
 // Status bits set on the device.
 constexpr uint32_t ST_TABLE_FULL = 1u;     // a spawn found no free slot: grow and redo
@@ -31,6 +36,20 @@ struct ChunkStat {
     double num;
 };
 
+// A spawning event waiting for annihilation: child determinant, signed walkers,
+// (system << 1) | initiator flag of the parent.
+struct SpawnRec {
+    uint64_t det;
+    int32_t v;
+    uint32_t sys_flag;
+};
+
+// One workgroup's share of a system's iteration statistics.
+struct FinPart {
+    int64_t nw, nd, c0, merged, aborted, used, attempts;
+    double num;
+};
+
 // Per-system descriptor, resident in device memory. The first block is
 // written by the host at admission / growth; the second block is updated by
 // the finalize kernel every iteration.
@@ -47,8 +66,9 @@ struct SysDesc {
     const double *jk;                // [n_so][64]: (pp|qq) - (pq|qp) for p < q, spin orbitals
     const double *t3;                // [n_so][64][64]: (pa|qq) - d(s_p,s_q)(pq|qa), same-spin p, a
     uint64_t *key;                   // main table (structure of arrays): determinant, 0 = empty
-    int2 *acc;                       // walkers spawned onto the slot this iteration (signed sum,
-                                     // OR of initiator flags)
+    long long *acc;                  // walkers spawned onto the slot this iteration:
+                                     // (initiator spawns) * 2^32 + (signed walker sum), one
+                                     // 64-bit integer sum, so a spawn is one atomic add
     int32_t *pop;                    // signed walker count (0: vacated or not yet occupied)
     double *hdiag;                   // stored H_DD; NaN until the determinant is first occupied
     uint64_t cap_mask;               // capacity - 1 (capacity a power of two >= CHUNK)
@@ -74,14 +94,21 @@ struct EngineArgs {
     unsigned long long *chunk_off;   // exclusive scan of chunk_nw
     unsigned long long *chunk_toff;  // exclusive scan of the spawn tiles of each chunk
     ChunkStat *chunk_stat;
+    unsigned long long *blk;         // [4][SCAN_G]: per chunk range sum |C|, tiles, and their
+                                     // exclusive scans
+    FinPart *fin_part;               // [max_sys][FIN_BLOCKS]
+    SpawnRec *sbuf;                  // spawned list of the iteration (all systems)
+    unsigned long long *scount;      // records appended to sbuf (reset per iteration)
+    unsigned long long scap;         // capacity of sbuf; records past it are merged directly
     unsigned long long *total;       // [0] total attempts, [1] total spawn tiles
     const int64_t *nchunks;          // global chunks in use
     IterRecord *rec;                 // [max_sys][REC_CAP]
 };
 
 // Kernel launchers (kernels.hip).
-void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, int spawn_grid,
-                      hipStream_t s, hipEvent_t *ev /* 6 events or nullptr */);
+constexpr int NKERN = 6;   // profiled kernel groups: chunk sums, scans, spawn, insert, post, finalize
+void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStream_t s,
+                      hipEvent_t *ev /* NKERN + 1 events or nullptr */);
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
                        int64_t n, uint32_t *d_err, hipStream_t s);
 hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,

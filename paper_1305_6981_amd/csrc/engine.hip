@@ -134,7 +134,7 @@ struct SysHost {
     int64_t cap = 0;           // table slots
     void *block = nullptr;     // one device allocation for the table + integrals
     uint64_t *key = nullptr;
-    int2 *acc = nullptr;
+    long long *acc = nullptr;
     int32_t *pop = nullptr;
     double *hd = nullptr;
     double *d_h1 = nullptr, *d_eri = nullptr, *d_jk = nullptr;
@@ -172,6 +172,11 @@ struct fciqmc_t {
     unsigned long long *d_chunk_nw = nullptr, *d_chunk_off = nullptr, *d_total = nullptr;
     unsigned long long *d_chunk_toff = nullptr;
     ChunkStat *d_chunk_stat = nullptr;
+    unsigned long long *d_blk = nullptr;    // [4][SCAN_G] range sums and scans
+    FinPart *d_fin = nullptr;               // [max_sys][FIN_BLOCKS]
+    SpawnRec *d_sbuf = nullptr;             // spawned list of an iteration
+    unsigned long long *d_scount = nullptr;
+    int64_t scap = 0;
     int64_t *d_nchunks = nullptr;
     uint32_t *d_err = nullptr;
     int spawn_grid = 2048;
@@ -180,9 +185,9 @@ struct fciqmc_t {
     std::map<int, hipGraphExec_t> graphs;
     bool use_graph = true;
     bool profiling = false;
-    hipEvent_t ev[6] = {};
-    double kms[5] = {0, 0, 0, 0, 0};
-    int64_t kcount[5] = {0, 0, 0, 0, 0};
+    hipEvent_t ev[NKERN + 1] = {};
+    double kms[NKERN] = {};
+    int64_t kcount[NKERN] = {};
     double ms_last = 0.0;
 };
 
@@ -198,6 +203,11 @@ EngineArgs make_args(fciqmc_t *h) {
     a.chunk_off = h->d_chunk_off;
     a.chunk_toff = h->d_chunk_toff;
     a.chunk_stat = h->d_chunk_stat;
+    a.blk = h->d_blk;
+    a.fin_part = h->d_fin;
+    a.sbuf = h->d_sbuf;
+    a.scount = h->d_scount;
+    a.scap = (unsigned long long)h->scap;
     a.total = h->d_total;
     a.nchunks = h->d_nchunks;
     a.rec = h->d_rec;
@@ -259,6 +269,21 @@ int relayout(fciqmc_t *h) {
         h->chunk_alloc = na;
         drop_graphs(h);
     }
+    // spawned list: one record per SLOTS_PER_SPAWN_REC table slots, at least 2^20; if
+    // the device cannot hold a larger one the old one stays (overflow is merged directly)
+    const int64_t want = next_pow2(std::max<int64_t>(total * CHUNK / SLOTS_PER_SPAWN_REC, 1 << 20));
+    if (want > h->scap) {
+        SpawnRec *nb = nullptr;
+        if (hipMalloc(&nb, (size_t)want * sizeof(SpawnRec)) == hipSuccess) {
+            hipFree(h->d_sbuf);
+            h->d_sbuf = nb;
+            h->scap = want;
+            drop_graphs(h);
+        } else {
+            (void)hipGetLastError();
+            if (!h->d_sbuf) return set_err(FCIQMC_ENOMEM, "device allocation of the spawned list failed");
+        }
+    }
     std::vector<int32_t> cs(total), cl(total);
     int64_t g = 0;
     for (int s = 0; s < h->max_sys; ++s) {
@@ -291,7 +316,7 @@ int relayout(fciqmc_t *h) {
 }
 
 int64_t table_bytes(int64_t cap) {
-    return cap * (int64_t)(sizeof(uint64_t) + sizeof(int2) + sizeof(int32_t) + sizeof(double));
+    return cap * (int64_t)(sizeof(uint64_t) + sizeof(long long) + sizeof(int32_t) + sizeof(double));
 }
 
 int64_t integral_doubles(int M) {
@@ -304,7 +329,7 @@ int64_t integral_bytes(int M) { return integral_doubles(M) * 8 + 256; }
 // Empty table: keys and populations zero, diagonal elements NaN ("not computed").
 int clear_table(fciqmc_t *h, void *blk, int64_t cap) {
     char *p = (char *)blk;
-    const size_t kb = (size_t)cap * (sizeof(uint64_t) + sizeof(int2));   // keys + accumulators
+    const size_t kb = (size_t)cap * (sizeof(uint64_t) + sizeof(long long));   // keys + accumulators
     HIP_TRY(hipMemsetAsync(p, 0, kb, h->stream));
     HIP_TRY(hipMemsetAsync(p + kb, 0xFF, (size_t)cap * sizeof(double), h->stream));
     HIP_TRY(hipMemsetAsync(p + kb + cap * sizeof(double), 0, (size_t)cap * sizeof(int32_t),
@@ -333,8 +358,8 @@ void carve(SysHost &S, void *blk, int64_t cap) {
     char *p = (char *)blk;
     S.key = (uint64_t *)p;
     p += cap * sizeof(uint64_t);
-    S.acc = (int2 *)p;
-    p += cap * sizeof(int2);
+    S.acc = (long long *)p;
+    p += cap * sizeof(long long);
     S.hd = (double *)p;
     p += cap * sizeof(double);
     S.pop = (int32_t *)p;
@@ -474,7 +499,8 @@ int64_t initial_capacity(const fciqmc_params *prm) {
 
 int64_t target_footprint(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     const int64_t cap = next_pow2(std::max<int64_t>(2 * std::max<int64_t>(prm->target_walkers, 1), 4 * CHUNK));
-    return table_bytes(cap) + integral_bytes(ham->n_orb);
+    return table_bytes(cap) + cap / SLOTS_PER_SPAWN_REC * (int64_t)sizeof(SpawnRec) +
+           integral_bytes(ham->n_orb);
 }
 
 int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop);
@@ -598,7 +624,6 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
 // Replace the list of system s by (det, pop); computes E0 on the device.
 int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop) {
     SysHost &S = h->sys[s];
-    SysDesc &d = h->hdesc[s];
     const int64_t n = (int64_t)det.size();
     int64_t need = next_pow2(std::max<int64_t>(4 * CHUNK, 3 * n));
     if (need > S.cap) {
@@ -748,7 +773,7 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     EngineArgs a = make_args(h);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
-    for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->post_grid, h->spawn_grid, h->stream, nullptr);
+    for (int i = 0; i < L; ++i) launch_iteration(a, h->post_grid, h->spawn_grid, h->stream, nullptr);
     HIP_TRY(hipStreamEndCapture(h->stream, &g));
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
@@ -796,9 +821,9 @@ int run_iterations(fciqmc_t *h, int L) {
     EngineArgs a = make_args(h);
     if (h->profiling) {
         for (int i = 0; i < L; ++i) {
-            launch_iteration(a, h->chunk_alloc, h->post_grid, h->spawn_grid, h->stream, h->ev);
-            HIP_TRY(hipEventSynchronize(h->ev[5]));
-            for (int k = 0; k < 5; ++k) {
+            launch_iteration(a, h->post_grid, h->spawn_grid, h->stream, h->ev);
+            HIP_TRY(hipEventSynchronize(h->ev[NKERN]));
+            for (int k = 0; k < NKERN; ++k) {
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
                 h->kms[k] += ms;
@@ -812,7 +837,7 @@ int run_iterations(fciqmc_t *h, int L) {
         if (rc) return rc;
         HIP_TRY(hipGraphLaunch(ex, h->stream));
     } else {
-        for (int i = 0; i < L; ++i) launch_iteration(a, h->chunk_alloc, h->post_grid, h->spawn_grid, h->stream, nullptr);
+        for (int i = 0; i < L; ++i) launch_iteration(a, h->post_grid, h->spawn_grid, h->stream, nullptr);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -916,9 +941,12 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_rec, sizeof(IterRecord) * REC_CAP * max_slots));
     HIP_TRY(hipMalloc(&h->d_total, 2 * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
+    HIP_TRY(hipMalloc(&h->d_blk, 4 * SCAN_G * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_fin, sizeof(FinPart) * FIN_BLOCKS * max_slots));
+    HIP_TRY(hipMalloc(&h->d_scount, sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
     HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
-    for (int k = 0; k < 6; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
+    for (int k = 0; k <= NKERN; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
     h->spawn_grid = spawn_grid_size();
     h->post_grid = post_grid_size();
     int rc = upload_desc(h);
@@ -982,6 +1010,10 @@ void release(fciqmc_t *h) {
     hipFree(h->d_spawns);
     hipFree(h->d_total);
     hipFree(h->d_nchunks);
+    hipFree(h->d_blk);
+    hipFree(h->d_fin);
+    hipFree(h->d_sbuf);
+    hipFree(h->d_scount);
     hipFree(h->d_err);
     hipFree(h->d_chunk_sys);
     hipFree(h->d_chunk_local);
@@ -1210,7 +1242,7 @@ int64_t fciqmc_footprint_bytes(const fciqmc_hamiltonian *ham, const fciqmc_param
 int fciqmc_set_profiling(fciqmc_t *h, int32_t on) {
     if (!h) return set_err(FCIQMC_EINVAL, "null handle");
     h->profiling = on != 0;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < NKERN; ++k) {
         h->kms[k] = 0.0;
         h->kcount[k] = 0;
     }
@@ -1245,7 +1277,7 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
         h->spawn_grid = sg;
         h->tile = tl;
         h->post_grid = pg;
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < NKERN; ++k) {
             h->kms[k] = 0.0;
             h->kcount[k] = 0;
         }
@@ -1259,8 +1291,8 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
             a1 += S.active ? S.tot_att : 0;
             slots += S.active ? S.cap : 0;
         }
-        spawn_ns = h->kms[2] * 1e6 / (double)std::max<int64_t>(a1 - a0, 1);
-        post_ns = h->kms[3] * 1e6 / (double)std::max<int64_t>(slots * iters_per_trial, 1);
+        spawn_ns = (h->kms[2] + h->kms[3]) * 1e6 / (double)std::max<int64_t>(a1 - a0, 1);
+        post_ns = h->kms[4] * 1e6 / (double)std::max<int64_t>(slots * iters_per_trial, 1);
         return 0;
     };
     int best_sg = h->spawn_grid, best_tl = h->tile, best_pg = h->post_grid;
@@ -1296,7 +1328,7 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
     h->tile = best_tl;
     h->post_grid = best_pg;
     h->profiling = was;
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < NKERN; ++k) {
         h->kms[k] = 0.0;
         h->kcount[k] = 0;
     }
@@ -1304,9 +1336,9 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
     return 0;
 }
 
-int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]) {
+int fciqmc_kernel_times(fciqmc_t *h, double ms[6], int64_t counts[6]) {
     if (!h || !ms || !counts) return set_err(FCIQMC_EINVAL, "null argument");
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < NKERN; ++k) {
         ms[k] = h->kms[k];
         counts[k] = h->kcount[k];
     }

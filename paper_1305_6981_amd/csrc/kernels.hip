@@ -1,13 +1,17 @@
 // HIP kernels of the FCIQMC iteration (Booth, Smart & Alavi, arXiv:1305.6981)
-// for gfx950. One iteration of every active system is five launches:
+// for gfx950. One iteration of every active system is eight launches:
 //
-//   k_chunk_sum   sum |C| over each 1024-slot chunk of the current main tables
-//   k_scan        exclusive scan of the chunk sums -> global attempt offsets
+//   k_chunk_sum   sum |C| over each 1024-slot chunk of the current main tables,
+//                 and over fixed contiguous ranges of chunks
+//   k_scan        exclusive scan of the range sums (one workgroup)
+//   k_scan_down   per chunk: global attempt offset and spawn-tile offset
 //   k_spawn       one spawning attempt per walker (Sec. 2, Eq. pspawn): random
 //                 excitation with its pgen (Sec. 5), Slater-Condon element,
-//                 acceptance; accepted walkers are summed straight into the
-//                 target determinant's slot of the main table (the merge of
-//                 equal spawned determinants of Sec. 4.1, done by atomics)
+//                 acceptance; accepted spawns are appended to the
+//                 iteration's spawned list (Sec. 4.1)
+//   k_insert      merges the spawned list into the main table: each record is
+//                 summed into its determinant's slot by atomics (the merge of
+//                 equal spawned determinants and the annihilation of Sec. 4.1-4.2)
 //   k_post        per slot, in place: death/cloning (Eq. pdeath), annihilation
 //                 of the arrived walkers with the initiator test for
 //                 determinants that are empty after death, the stored diagonal
@@ -15,8 +19,10 @@
 //                 pair table staged in LDS; estimator partial sums (Eq. ProjE).
 //                 A vacated slot keeps its key (and H_DD) until the table is
 //                 compacted, so no slot ever moves during an iteration.
-//   k_finalize    per system: fixed-order reduction of the partial sums, the
-//                 shift update, the per-iteration record
+//   k_reduce      per system, 64 workgroups: fixed-order reduction of the
+//                 chunk statistics over fixed ranges of chunks
+//   k_finalize    per system, one wavefront: sum of the 64 shares, the shift
+//                 update, the per-iteration record
 //
 // All floating-point decisions follow the same operation order as the CPU
 // oracle and are compiled with -ffp-contract=off.
@@ -106,18 +112,54 @@ __device__ __forceinline__ int tri(int i, int j) {
     return (int)(__umul24((unsigned)hi, (unsigned)(hi + 1)) >> 1) + lo;
 }
 
+// The integral tables live in global memory; saying so lets the compiler use
+// global (not flat) loads, which do not hold up the LDS wait counter.
+typedef __attribute__((address_space(1))) const double gdouble;
+__device__ __forceinline__ const gdouble *gptr(const double *p) { return (const gdouble *)p; }
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+// 16-byte global loads and stores through plain vector types.
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
+typedef double v2f64 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int4 gload_i4(const int32_t *p) {
+    const v4i32 v = *gp(reinterpret_cast<const v4i32 *>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ ulonglong2 gload_u2(const uint64_t *p) {
+    const v2u64 v = *gp(reinterpret_cast<const v2u64 *>(p));
+    return make_ulonglong2(v.x, v.y);
+}
+__device__ __forceinline__ double2 gload_d2(const double *p) {
+    const v2f64 v = *gp(reinterpret_cast<const v2f64 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore_i4(void *p, int x, int y, int z, int w) {
+    v4i32 v;
+    v.x = x;
+    v.y = y;
+    v.z = z;
+    v.w = w;
+    *gp(reinterpret_cast<v4i32 *>(p)) = v;
+}
+
 __device__ __forceinline__ double eri_so(const SysDesc &d, int p, int q, int r, int s) {
     if (((p ^ q) | (r ^ s)) & 1) return 0.0;
-    return d.eri[tri(tri(p >> 1, q >> 1), tri(r >> 1, s >> 1))];
+    return gptr(d.eri)[tri(tri(p >> 1, q >> 1), tri(r >> 1, s >> 1))];
 }
 
 __device__ __forceinline__ double h_so(const SysDesc &d, int p, int q) {
     if ((p ^ q) & 1) return 0.0;
-    return d.h1[(p >> 1) * d.M + (q >> 1)];
+    return gptr(d.h1)[(p >> 1) * d.M + (q >> 1)];
 }
 
+// Both words are read at uniform addresses (scalar loads); the lane's label is
+// then picked out with ALU operations only.
 __device__ __forceinline__ int irrep_of(const SysDesc &d, int s) {
-    return (int)((d.irr_packed[s >> 4] >> (4 * (s & 15))) & 0xFull);
+    const uint64_t w0 = d.irr_packed[0], w1 = d.irr_packed[1];
+    return (int)((((s & 16) ? w1 : w0) >> (4 * (s & 15))) & 0xFull);
 }
 
 __device__ __forceinline__ int class_of(const SysDesc &d, int p) {
@@ -152,7 +194,7 @@ __device__ double hdiag_of(const SysDesc &d, uint64_t det) {
 // t3[p][a][*]; four loads are issued before they are added, in order.
 __device__ double hel_single(const SysDesc &d, uint64_t det, int p, int a) {
     double acc = h_so(d, p, a);
-    const double *row = d.t3 + ((p * 64 + a) << 6);
+    const gdouble *row = gptr(d.t3) + ((p * 64 + a) << 6);
     uint64_t m = det & ~(1ull << p);
     while (m) {
         const int q0 = __builtin_ctzll(m);
@@ -217,24 +259,47 @@ struct Excit {
 constexpr uint64_t EVEN_BITS = 0x5555555555555555ull;
 constexpr uint64_t ODD_BITS = 0xAAAAAAAAAAAAAAAAull;
 
+// Symmetry classes seen from the excitation generator. With no point group
+// (every orbital in irrep 0, two classes: the spins) everything is bit
+// arithmetic; otherwise the class masks are read from an LDS copy, since the
+// class index differs between lanes.
+template <bool C1>
+struct ClassView {
+    uint64_t valid;
+    const uint64_t *cm;   // LDS copy of SysDesc::cmask (unused when C1)
+    __device__ __forceinline__ uint64_t mask(int c) const {
+        if (C1) return valid & ((c & 1) ? ODD_BITS : EVEN_BITS);
+        return cm[c];
+    }
+    __device__ __forceinline__ int irrep(const SysDesc &d, int s) const {
+        return C1 ? 0 : irrep_of(d, s);
+    }
+    __device__ __forceinline__ int cls(const SysDesc &d, int p) const {
+        return C1 ? (p & 1) : class_of(d, p);
+    }
+};
+
 // recip[k] = 1.0 / k, filled by IEEE division (same bits as dividing in place).
 // For a single excitation the matrix element is left to the caller when
 // defer_single is set (ex.hel = NaN, the orbitals in ex.p / ex.a).
-__device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1, uint64_t x2,
-                       uint64_t x3, const double *recip, bool defer_single, Excit &ex) {
+template <bool C1>
+__device__ __forceinline__ bool excite(const SysDesc &d, const ClassView<C1> &cv, uint64_t det,
+                                       uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3,
+                                       const double *recip, bool defer_single, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int N = d.N;
+    const int n_class = C1 ? 2 : d.n_class;
     if (!(u01(x0) < d.p_double)) {
         // Single (Sec. 5.1): renormalise over electrons that have an allowed target.
         uint64_t movable = 0;
-        for (int c = 0; c < d.n_class; ++c) {
-            const uint64_t cm = d.cmask[c];
+        for (int c = 0; c < n_class; ++c) {
+            const uint64_t cm = C1 ? cv.mask(c) : d.cmask[c];
             if (emp & cm) movable |= det & cm;
         }
         const uint32_t nmov = (uint32_t)__popcll(movable);
         if (nmov == 0) return false;
         const int p = select_bit(movable, pick(x1, nmov));
-        const uint64_t tg = emp & d.cmask[class_of(d, p)];
+        const uint64_t tg = emp & cv.mask(cv.cls(d, p));
         const uint32_t nal = (uint32_t)__popcll(tg);
         const int a = select_bit(tg, pick(x2, nal));
         ex.det = det ^ (1ull << p) ^ (1ull << a);
@@ -256,28 +321,28 @@ __device__ bool excite(const SysDesc &d, uint64_t det, uint64_t x0, uint64_t x1,
     const int p = select_bit(det, (uint32_t)i), q = select_bit(det, (uint32_t)j);
     const bool same = ((p ^ q) & 1) == 0;
     const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
-    const int gpq = irrep_of(d, p >> 1) ^ irrep_of(d, q >> 1);
+    const int gpq = cv.irrep(d, p >> 1) ^ cv.irrep(d, q >> 1);
     // a orbitals whose partner class (Eq. sym1 plus spin) has an empty orbital besides a.
     uint64_t allowed = 0;
-    for (int c = 0; c < d.n_class; ++c) {
-        const uint64_t memb = A & d.cmask[c];
+    for (int c = 0; c < n_class; ++c) {
+        const uint64_t memb = A & (C1 ? cv.mask(c) : d.cmask[c]);
         if (!memb) continue;
         const int sb = same ? (p & 1) : 1 - (c & 1);
         const int pc = 2 * (gpq ^ (c >> 1)) + sb;
-        const int nb = __popcll(emp & d.cmask[pc]) - (pc == c ? 1 : 0);
+        const int nb = __popcll(emp & cv.mask(pc)) - (pc == c ? 1 : 0);
         if (nb > 0) allowed |= memb;
     }
     const uint32_t nal = (uint32_t)__popcll(allowed);
     if (nal == 0) return false;
     const int a = select_bit(allowed, pick(x2, nal));
-    const int ca = class_of(d, a);
+    const int ca = cv.cls(d, a);
     const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
-    const uint64_t bset = emp & d.cmask[pca] & ~(1ull << a);
+    const uint64_t bset = emp & cv.mask(pca) & ~(1ull << a);
     const uint32_t nba = (uint32_t)__popcll(bset);
     const int b = select_bit(bset, pick(x3, nba));
-    const int cb = class_of(d, b);
+    const int cb = cv.cls(d, b);
     const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
-    const int nbb = __popcll(emp & d.cmask[pcb]) - (pcb == cb ? 1 : 0);
+    const int nbb = __popcll(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
     ex.det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
     ex.pgen = (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
               (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
@@ -334,62 +399,75 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // ---------------------------------------------------------------------------
-// K1: chunk sums of |C| on the current tables.
+// K1: chunk sums of |C| on the current tables. Workgroup g takes the chunks
+// [g per, (g+1) per) (per = ceil(chunks / SCAN_G)), four at a time, writes
+// each chunk's sum and the range's total attempts and spawn tiles.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long abs_sum4(int4 v) {
+    return (unsigned long long)(abs(v.x)) + (unsigned long long)(abs(v.y)) +
+           (unsigned long long)(abs(v.z)) + (unsigned long long)(abs(v.w));
+}
+
 __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
                                                    const SysDesc *__restrict__ desc) {
-    __shared__ unsigned long long sh[4];
+    __shared__ unsigned long long sh[4][4];
     const int64_t nch = *a.nchunks;
+    const int64_t per = (nch + SCAN_G - 1) / SCAN_G;
+    const int64_t c0 = (int64_t)blockIdx.x * per;
+    const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+    const int tsh = __builtin_ctzll((unsigned long long)a.tile);
+    const unsigned long long tm = (unsigned long long)a.tile - 1ull;
     const int t = threadIdx.x;
-    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int s = a.chunk_sys[c];
-        unsigned long long sum = 0;
-        if (s >= 0) {
-            const SysDesc &d = desc[s];
-            if (participating(d, a.status[s])) {
-                const int4 v = reinterpret_cast<const int4 *>(d.pop + (int64_t)a.chunk_local[c] * CHUNK)[t];
-                sum = (unsigned long long)(abs(v.x)) + (unsigned long long)(abs(v.y)) +
-                      (unsigned long long)(abs(v.z)) + (unsigned long long)(abs(v.w));
+    unsigned long long bs = 0, bt = 0;    // range totals, kept by thread 0
+    for (int64_t c = c0; c < c1; c += 4) {
+        unsigned long long v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = 0;
+            const int64_t cc = c + k;
+            if (cc < c1) {
+                const int sy = a.chunk_sys[cc];
+                if (sy >= 0) {
+                    const SysDesc &d = desc[sy];
+                    if (participating(d, a.status[sy]))
+                        v[k] = abs_sum4(reinterpret_cast<const int4 *>(
+                            d.pop + (int64_t)a.chunk_local[cc] * CHUNK)[t]);
+                }
             }
         }
-        sum = wave_sum(sum);
-        if ((t & 63) == 0) sh[t >> 6] = sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned long long w = wave_sum(v[k]);
+            if ((t & 63) == 0) sh[k][t >> 6] = w;
+        }
         __syncthreads();
-        if (t == 0) a.chunk_nw[c] = sh[0] + sh[1] + sh[2] + sh[3];
+        if (t == 0) {
+            for (int k = 0; k < 4 && c + k < c1; ++k) {
+                const unsigned long long x = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
+                a.chunk_nw[c + k] = x;
+                bs += x;
+                bt += (x + tm) >> tsh;
+            }
+        }
         __syncthreads();
+    }
+    if (t == 0) {
+        a.blk[blockIdx.x] = bs;
+        a.blk[SCAN_G + blockIdx.x] = bt;
     }
 }
 
 // ---------------------------------------------------------------------------
-// K2: exclusive scan of the chunk sums (one workgroup).
+// K2a: exclusive scan of the SCAN_G range totals (one workgroup, two per
+// thread); also resets the dynamic work counters of the spawn and post kernels.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
     __shared__ unsigned long long part[1024], tpart[1024];
-    const int64_t n = *a.nchunks;
-    const unsigned long long tile = (unsigned long long)a.tile;   // a power of two
-    const int tsh = __builtin_ctzll(tile);
-    const unsigned long long tm = tile - 1;
     const int t = threadIdx.x;
-    // contiguous ranges of an even length per thread: two-element vector loads
-    const int64_t per = (((n + 1023) / 1024) + 1) & ~(int64_t)1;
-    const int64_t b = t * per, e = (b + per < n) ? b + per : n;
-    unsigned long long s = 0, st = 0;
-    if (b < e) {
-        int64_t i = b;
-        for (; i + 4 <= e; i += 4) {
-            const ulonglong2 v0 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
-            const ulonglong2 v1 = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i + 2);
-            s += v0.x + v0.y + v1.x + v1.y;
-            st += ((v0.x + tm) >> tsh) + ((v0.y + tm) >> tsh) + ((v1.x + tm) >> tsh) +
-                  ((v1.y + tm) >> tsh);
-        }
-        for (; i < e; ++i) {
-            s += a.chunk_nw[i];
-            st += (a.chunk_nw[i] + tm) >> tsh;
-        }
-    }
-    part[t] = s;
-    tpart[t] = st;
+    const unsigned long long s0 = a.blk[2 * t], s1 = a.blk[2 * t + 1];
+    const unsigned long long t0 = a.blk[SCAN_G + 2 * t], t1 = a.blk[SCAN_G + 2 * t + 1];
+    part[t] = s0 + s1;
+    tpart[t] = t0 + t1;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const unsigned long long v = t >= off ? part[t - off] : 0ull;
@@ -399,34 +477,66 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
         tpart[t] += vt;
         __syncthreads();
     }
-    unsigned long long run = part[t] - s, trun = tpart[t] - st;  // exclusive
-    if (b < e) {
-        int64_t i = b;
-        for (; i + 2 <= e; i += 2) {
-            const ulonglong2 v = *reinterpret_cast<const ulonglong2 *>(a.chunk_nw + i);
-            ulonglong2 o, ot;
-            o.x = run;
-            o.y = run + v.x;
-            ot.x = trun;
-            ot.y = trun + ((v.x + tm) >> tsh);
-            run += v.x + v.y;
-            trun = ot.y + ((v.y + tm) >> tsh);
-            *reinterpret_cast<ulonglong2 *>(a.chunk_off + i) = o;
-            *reinterpret_cast<ulonglong2 *>(a.chunk_toff + i) = ot;
-        }
-        for (; i < e; ++i) {
-            const unsigned long long v = a.chunk_nw[i];
-            a.chunk_off[i] = run;
-            a.chunk_toff[i] = trun;
-            run += v;
-            trun += (v + tm) >> tsh;
-        }
-    }
+    const unsigned long long run = part[t] - (s0 + s1), trun = tpart[t] - (t0 + t1);
+    a.blk[2 * SCAN_G + 2 * t] = run;
+    a.blk[2 * SCAN_G + 2 * t + 1] = run + s0;
+    a.blk[3 * SCAN_G + 2 * t] = trun;
+    a.blk[3 * SCAN_G + 2 * t + 1] = trun + t0;
     if (t == 1023) {
         a.total[0] = part[1023];
         a.total[1] = tpart[1023];
-        a.work[0] = 0u;   // dynamic work counters of the spawn and post kernels
+        a.work[0] = 0u;
         a.work[1] = 0u;
+        *a.scount = 0ull;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2b: per chunk, the exclusive scans of |C| sums (attempt offsets) and of
+// spawn tiles, inside each range from the range's offset.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
+    __shared__ unsigned long long ws[4], wt[4];
+    const int64_t nch = *a.nchunks;
+    const int64_t per = (nch + SCAN_G - 1) / SCAN_G;
+    const int64_t c0 = (int64_t)blockIdx.x * per;
+    const int64_t c1 = c0 + per < nch ? c0 + per : nch;
+    const int tsh = __builtin_ctzll((unsigned long long)a.tile);
+    const unsigned long long tm = (unsigned long long)a.tile - 1ull;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    unsigned long long base = a.blk[2 * SCAN_G + blockIdx.x];
+    unsigned long long tbase = a.blk[3 * SCAN_G + blockIdx.x];
+    for (int64_t c = c0; c < c1; c += 256) {
+        const int64_t i = c + t;
+        const unsigned long long v = i < c1 ? a.chunk_nw[i] : 0ull;
+        const unsigned long long vt = (v + tm) >> tsh;
+        // inclusive scans inside the wavefront
+        unsigned long long x = v, xt = vt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, o, 64);
+            const unsigned long long yt = __shfl_up(xt, o, 64);
+            if (lane >= o) {
+                x += y;
+                xt += yt;
+            }
+        }
+        if (lane == 63) {
+            ws[w] = x;
+            wt[w] = xt;
+        }
+        __syncthreads();
+        unsigned long long pre = 0, pret = 0;
+        for (int k = 0; k < w; ++k) {
+            pre += ws[k];
+            pret += wt[k];
+        }
+        if (i < c1) {
+            a.chunk_off[i] = base + pre + x - v;
+            a.chunk_toff[i] = tbase + pret + xt - vt;
+        }
+        base += ws[0] + ws[1] + ws[2] + ws[3];
+        tbase += wt[0] + wt[1] + wt[2] + wt[3];
+        __syncthreads();
     }
 }
 
@@ -438,19 +548,21 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
 // k+1 / next occupied slot.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool table_add(uint64_t *key, int2 *acc, uint64_t mask, uint64_t k,
+// Merge one spawning event into the main table (the annihilation of Sec. 4.2
+// done by atomics): find or claim the determinant's slot by linear probing
+// (one compare-and-swap per probe: it claims an empty slot or returns the key
+// there), then add (initiator ? 2^32 : 0) + v to the slot's accumulator with
+// one atomic whose result is not needed.
+__device__ __forceinline__ bool table_add(uint64_t *key, long long *acc, uint64_t mask, uint64_t k,
                                           int32_t v, bool init) {
     uint64_t h = mix64(k) & mask;
     for (uint64_t n = 0; n <= mask; ++n) {
-        uint64_t cur = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (cur == 0) {
-            cur = atomicCAS((unsigned long long *)&key[h], 0ull, (unsigned long long)k);
-            if (cur == 0) cur = k;
-        }
-        if (cur == k) {
-            atomicAdd(&acc[h].x, v);
-            if (init && __hip_atomic_load(&acc[h].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                atomicOr(&acc[h].y, 1);
+        uint64_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(gp(&key[h]), &expect, k, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+            expect == k) {
+            const long long inc = (init ? (1ll << 32) : 0ll) + (long long)v;
+            __hip_atomic_fetch_add(gp(&acc[h]), inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return true;
         }
         h = (h + 1) & mask;
@@ -458,10 +570,17 @@ __device__ __forceinline__ bool table_add(uint64_t *key, int2 *acc, uint64_t mas
     return false;
 }
 
+// Signed walker sum and initiator flag of an accumulator (the sum fits 32 bits).
+__device__ __forceinline__ int32_t acc_walkers(long long x) { return (int32_t)(uint32_t)x; }
+__device__ __forceinline__ bool acc_initiator(long long x) {
+    return ((x - (long long)acc_walkers(x)) >> 32) != 0;
+}
+
 // Work queued in LDS by the attempt loop and drained by the whole workgroup:
 // single excitations (their matrix element is an O(N) gather loop that would
-// stall a wavefront for one lane) and accepted spawns (their hash-table probe
-// is a dependent HBM round trip).
+// stall a wavefront for one lane) and accepted spawns, which are appended to
+// the iteration's spawned list in one block (one reservation per drain) and
+// merged into the table by k_insert.
 struct SingleItem {
     uint64_t D;        // source determinant
     double pgen;
@@ -470,6 +589,7 @@ struct SingleItem {
     uint32_t pai;      // p | a << 8 | initiator << 16
 };
 
+constexpr int SPAWN_GRAB = 4;    // spawn tiles per dynamic grab (one counter serves the chip)
 constexpr int SGL_QUEUE = 128;
 constexpr int SPW_QUEUE = 256;
 constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
@@ -492,14 +612,41 @@ struct SpawnQueues {
     uint64_t spd[SPW_QUEUE];
     int2 spv[SPW_QUEUE];   // (signed walkers, initiator flag)
     int nsgl, nspw, sys;
+    unsigned long long base;
 };
 
-// Drain both queues of system d with the whole workgroup (call uniformly).
-__device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
-                             unsigned long long *spawns) {
+// Append one spawning event of system s to the spawned list, or merge it
+// directly when the list is full.
+__device__ __forceinline__ void emit_spawn(const EngineArgs &a, const SysDesc &d, int s,
+                                           unsigned long long idx, uint64_t det, int32_t v,
+                                           bool init) {
+    if (idx < a.scap) {
+        SpawnRec r;
+        r.det = det;
+        r.v = v;
+        r.sys_flag = ((uint32_t)s << 1) | (init ? 1u : 0u);
+        a.sbuf[idx] = r;
+    } else if (!table_add(d.key, d.acc, d.cap_mask, det, v, init)) {
+        atomicOr(&a.status[s], ST_TABLE_FULL);
+    }
+}
+
+// Add the wavefront's spawning events of system s to its counter and reset the
+// per-thread tallies. The counter is one address for the whole chip, so it is
+// touched once per wavefront per system, not per tile.
+__device__ __forceinline__ void flush_spawn_count(unsigned long long *counter,
+                                                  unsigned long long &spawned) {
+    const unsigned long long ws = wave_sum(spawned);
+    if ((threadIdx.x & 63) == 0 && ws) atomicAdd(counter, ws);
+    spawned = 0;
+}
+
+// Drain both queues of system s with the whole workgroup (call uniformly).
+__device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc &d, int s,
+                             unsigned long long &spawned) {
     __syncthreads();
     const int t = threadIdx.x;
-    unsigned long long spawned = 0;
+    uint32_t *status = &a.status[s];
     const int nsgl = Q.nsgl < SGL_QUEUE ? Q.nsgl : SGL_QUEUE;
     for (int j = t; j < nsgl; j += blockDim.x) {
         const SingleItem it = Q.sgl[j];
@@ -519,13 +666,13 @@ __device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
             atomicOr(status, ST_TABLE_FULL);
         }
     }
-    const unsigned long long ws = wave_sum(spawned);
-    if ((t & 63) == 0 && ws) atomicAdd(spawns, ws);
     __syncthreads();
     const int nspw = Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE;
+    if (t == 0 && nspw > 0) Q.base = atomicAdd(a.scount, (unsigned long long)nspw);
+    __syncthreads();
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
-        if (!table_add(d.key, d.acc, d.cap_mask, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
+        emit_spawn(a, d, s, Q.base + (unsigned long long)j, Q.spd[j], v.x, v.y != 0);
     }
     __syncthreads();
     if (t == 0) {
@@ -533,6 +680,25 @@ __device__ void drain_queues(SpawnQueues &Q, const SysDesc &d, uint32_t *status,
         Q.nspw = 0;
     }
     __syncthreads();
+}
+
+// Last index i < n with v[i] <= x, for v non-decreasing with v[0] <= x, by a
+// whole wavefront: 64 samples per round, so 2^17 entries take three dependent
+// loads instead of seventeen. Call with all 64 lanes active.
+__device__ __forceinline__ int64_t last_le(const unsigned long long *v, int64_t n,
+                                           unsigned long long x, int lane) {
+    int64_t lo = 0, hi = n;
+    while (hi - lo > 64) {
+        const int64_t step = (hi - lo + 63) >> 6;
+        const int64_t i = lo + (int64_t)lane * step;
+        const bool le = i < hi && v[i] <= x;
+        const int k = __popcll(__ballot(le)) - 1;   // samples <= x form a prefix of lanes
+        lo = lo + (int64_t)k * step;
+        hi = lo + step < hi ? lo + step : hi;
+    }
+    const int64_t i = lo + lane;
+    const bool le = i < hi && v[i] <= x;
+    return lo + __popcll(__ballot(le)) - 1;
 }
 
 __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
@@ -544,6 +710,7 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
     __shared__ long long s_c;
     __shared__ unsigned int s_tile;
     __shared__ double s_recip[65];
+    __shared__ uint64_t s_cm[NCLASS];
     __shared__ SpawnQueues Q;
     const unsigned long long n_tiles = a.total[1];
     const int64_t nch = *a.nchunks;
@@ -557,20 +724,23 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
         Q.sys = -1;
     }
     __syncthreads();
+    unsigned int next_tile = 0, grab_end = 0;   // wavefront 0's current grab of tiles
+    unsigned long long spawned = 0;             // this thread's spawning events of system Q.sys
     for (;;) {
         // Tiles never cross a chunk: chunk c owns ceil(N_c / tile) consecutive tiles.
         // They are handed out dynamically, so no workgroup waits for a second round.
-        if (t == 0) {
-            const unsigned int tix = atomicAdd(&a.work[0], 1u);
-            s_tile = tix;
+        if (wid == 0) {
+            if (next_tile >= grab_end) {
+                unsigned int g = 0;
+                if (lane == 0) g = atomicAdd(&a.work[0], (unsigned int)SPAWN_GRAB);
+                next_tile = __shfl(g, 0, 64);
+                grab_end = next_tile + SPAWN_GRAB;
+            }
+            const unsigned int tix = next_tile++;
+            if (lane == 0) s_tile = tix;
             if (tix < n_tiles) {
-                int64_t lo = 0, hi = nch;  // first chunk with tile offset > tix
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi) >> 1;
-                    if (a.chunk_toff[mid] <= tix) lo = mid + 1;
-                    else hi = mid;
-                }
-                s_c = lo - 1;
+                const int64_t cc = last_le(a.chunk_toff, nch, tix, lane);
+                if (lane == 0) s_c = cc;
             }
         }
         __syncthreads();
@@ -585,20 +755,22 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
         const SysDesc &d = desc[s];
         uint32_t *status = &a.status[s];
         if (Q.sys != s) {
-            // queued work belongs to another system: finish it first
-            if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
+            // queued work and tallies belong to another system: finish them first
+            if (Q.sys >= 0) {
                 const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-                drain_queues(Q, desc[qs], &a.status[qs], &a.spawns[qs]);
+                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, spawned);
+                flush_spawn_count(&a.spawns[qs], spawned);
             }
             __syncthreads();
             if (t == 0) Q.sys = s;
         }
+        if (t < NCLASS) s_cm[t] = d.cmask[t];   // ordered before use by the barrier below
         const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
         // Stage the occupied slots of the chunk, compacted, with the inclusive
         // prefix sum of |C| (4 consecutive slots per thread).
-        const int4 pv = reinterpret_cast<const int4 *>(d.pop + base)[t];
-        const ulonglong2 k01 = reinterpret_cast<const ulonglong2 *>(d.key + base)[2 * t];
-        const ulonglong2 k23 = reinterpret_cast<const ulonglong2 *>(d.key + base)[2 * t + 1];
+        const int4 pv = gload_i4(d.pop + base + 4 * t);
+        const ulonglong2 k01 = gload_u2(d.key + base + 4 * t);
+        const ulonglong2 k23 = gload_u2(d.key + base + 4 * t + 2);
         const int32_t pa[4] = {pv.x, pv.y, pv.z, pv.w};
         const uint64_t ka[4] = {k01.x, k01.y, k23.x, k23.y};
         const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
@@ -644,7 +816,9 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
         unsigned long long at = lo_t + (unsigned long long)t * per;
         const unsigned long long at_end = (at + per < hi_t) ? at + per : hi_t;
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
-        unsigned long long spawned = 0;
+        const bool c1 = d.n_class == 2;          // no point group: classes are the spins
+        ClassView<true> cv1{d.valid, nullptr};
+        ClassView<false> cvg{d.valid, s_cm};
         if (at < at_end) {
             const unsigned long long local = at - off_c;
             int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
@@ -664,7 +838,9 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
                 draw2(d.seed, D, k, d.iter, 1u, x2, x3);
                 draw2(d.seed, D, k, d.iter, 2u, x4, x5);
                 Excit ex;
-                if (excite(d, D, x0, x1, x2, x3, s_recip, defer, ex)) {
+                const bool ok = c1 ? excite(d, cv1, D, x0, x1, x2, x3, s_recip, defer, ex)
+                                   : excite(d, cvg, D, x0, x1, x2, x3, s_recip, defer, ex);
+                if (ok) {
                     if (isnan(ex.hel)) {
                         const int q = atomicAdd(&Q.nsgl, 1);
                         if (q < SGL_QUEUE) {
@@ -696,16 +872,33 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
                 }
             }
         }
-        // one atomic per wavefront for the spawn counter
-        const unsigned long long ws = wave_sum(spawned);
-        if (lane == 0 && ws) atomicAdd(&a.spawns[s], ws);
         __syncthreads();
-        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, d, status, &a.spawns[s]);
+        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, spawned);
     }
     __syncthreads();
-    if (Q.sys >= 0 && (Q.nsgl > 0 || Q.nspw > 0)) {
+    if (Q.sys >= 0) {
         const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-        drain_queues(Q, desc[qs], &a.status[qs], &a.spawns[qs]);
+        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, spawned);
+        flush_spawn_count(&a.spawns[qs], spawned);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3b: merge the iteration's spawned list into the main tables. Every record
+// is independent (integer sums), so the whole chip works on the list with no
+// barriers and the probes' round trips overlap across many wavefronts.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_insert(EngineArgs a, const SysDesc *__restrict__ desc) {
+    const unsigned long long cnt = *a.scount;
+    const unsigned long long n = cnt < a.scap ? cnt : a.scap;
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride) {
+        const SpawnRec r = a.sbuf[i];
+        const int s = (int)(r.sys_flag >> 1);
+        const SysDesc &d = desc[s];
+        if (!table_add(d.key, d.acc, d.cap_mask, r.det, r.v, (r.sys_flag & 1u) != 0))
+            atomicOr(&a.status[s], ST_TABLE_FULL);
     }
 }
 
@@ -725,6 +918,7 @@ __device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t mask, 
 }
 
 constexpr int POST_QUEUE = 2048;
+constexpr int POST_GRAB = 4;      // chunks per dynamic grab in k_post
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
 // ascending (p, q) order from the LDS copies of h_pp and of the pair table.
@@ -744,7 +938,7 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
                                                const double *hpp, const double *jk) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const uint32_t i = queue[j];
-        d.hdiag[i] = hdiag_lds(d.e_core, d.key[i], hpp, jk);
+        *gp(d.hdiag + i) = hdiag_lds(d.e_core, *gp(d.key + i), hpp, jk);
     }
 }
 
@@ -761,12 +955,17 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
     int loaded = -1;
     if (t == 0) s_qn = 0;
     __syncthreads();
-    for (;;) {
-        // chunks are handed out dynamically, in order (systems stay contiguous)
-        if (t == 0) s_next = atomicAdd(&a.work[1], 1u);
-        __syncthreads();
-        const int64_t c = s_next;
-        __syncthreads();
+    // Chunks are handed out dynamically, POST_GRAB consecutive ones per atomic
+    // (one counter serves the whole chip, so grabs are kept few), in order.
+    int64_t c = 0, c_end = 0;
+    for (;; ++c) {
+        if (c >= c_end) {
+            if (t == 0) s_next = atomicAdd(&a.work[1], (unsigned int)POST_GRAB);
+            __syncthreads();
+            c = s_next;
+            c_end = c + POST_GRAB;
+            __syncthreads();
+        }
         if (c >= nch) break;
         const int s = a.chunk_sys[c];
         int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, used = 0;
@@ -779,7 +978,7 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
                 if (loaded >= 0 && s_qn > 0) flush_new_dets(desc[loaded], s_queue, s_qn, s_hpp, s_jk);
                 __syncthreads();
                 if (loaded != s) {
-                    for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = d.jk[i];
+                    for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = gptr(d.jk)[i];
                     for (int i = t; i < d.n_so; i += 256) s_hpp[i] = h_so(d, i, i);
                     loaded = s;
                 }
@@ -788,16 +987,16 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
             }
             const int64_t base = (int64_t)a.chunk_local[c] * CHUNK + 4 * t;
             // four consecutive slots per thread, all loads issued before any use
-            const ulonglong2 k01 = *reinterpret_cast<const ulonglong2 *>(d.key + base);
-            const ulonglong2 k23 = *reinterpret_cast<const ulonglong2 *>(d.key + base + 2);
-            const int4 a01 = *reinterpret_cast<const int4 *>(d.acc + base);
-            const int4 a23 = *reinterpret_cast<const int4 *>(d.acc + base + 2);
+            const ulonglong2 k01 = gload_u2(d.key + base);
+            const ulonglong2 k23 = gload_u2(d.key + base + 2);
+            const ulonglong2 a01 = gload_u2(reinterpret_cast<const uint64_t *>(d.acc + base));
+            const ulonglong2 a23 = gload_u2(reinterpret_cast<const uint64_t *>(d.acc + base + 2));
             const uint64_t kin[4] = {k01.x, k01.y, k23.x, k23.y};
-            const int2 ain[4] = {make_int2(a01.x, a01.y), make_int2(a01.z, a01.w),
-                                 make_int2(a23.x, a23.y), make_int2(a23.z, a23.w)};
-            const int4 pv = *reinterpret_cast<const int4 *>(d.pop + base);
-            const double2 h01 = *reinterpret_cast<const double2 *>(d.hdiag + base);
-            const double2 h23 = *reinterpret_cast<const double2 *>(d.hdiag + base + 2);
+            const long long ain[4] = {(long long)a01.x, (long long)a01.y, (long long)a23.x,
+                                      (long long)a23.y};
+            const int4 pv = gload_i4(d.pop + base);
+            const double2 h01 = gload_d2(d.hdiag + base);
+            const double2 h23 = gload_d2(d.hdiag + base + 2);
             const int32_t pin[4] = {pv.x, pv.y, pv.z, pv.w};
             const double hin[4] = {h01.x, h01.y, h23.x, h23.y};
             int32_t pout[4] = {pv.x, pv.y, pv.z, pv.w};
@@ -826,11 +1025,11 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
                 // Annihilation (Sec. 4.2): present after death -> add; otherwise the
                 // arrived walkers survive only if an initiator sent some of them.
                 const bool present = pd != 0 || D == d.d0;
-                const int64_t sp = ain[u].x;
+                const int64_t sp = acc_walkers(ain[u]);
                 int64_t np;
                 if (present) {
                     np = pd + sp;
-                } else if (sp != 0 && ain[u].y) {
+                } else if (sp != 0 && acc_initiator(ain[u])) {
                     np = sp;
                 } else {
                     np = 0;
@@ -855,12 +1054,10 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
                 }
             }
             if (pout[0] != pin[0] || pout[1] != pin[1] || pout[2] != pin[2] || pout[3] != pin[3])
-                *reinterpret_cast<int4 *>(d.pop + base) = make_int4(pout[0], pout[1], pout[2], pout[3]);
+                gstore_i4(d.pop + base, pout[0], pout[1], pout[2], pout[3]);
             // clear the arrived walkers of the iteration
-            if (a01.x | a01.y | a01.z | a01.w)
-                *reinterpret_cast<int4 *>(d.acc + base) = make_int4(0, 0, 0, 0);
-            if (a23.x | a23.y | a23.z | a23.w)
-                *reinterpret_cast<int4 *>(d.acc + base + 2) = make_int4(0, 0, 0, 0);
+            if (a01.x | a01.y) gstore_i4(d.acc + base, 0, 0, 0, 0);
+            if (a23.x | a23.y) gstore_i4(d.acc + base + 2, 0, 0, 0, 0);
         }
         // fixed-order reduction: lane butterfly, then waves 0..3
         nw = wave_sum((long long)nw);
@@ -899,20 +1096,22 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
 }
 
 // ---------------------------------------------------------------------------
-// K5: per-system reduction, record, shift update (one workgroup per system).
+// K5a: per system, FIN_BLOCKS workgroups each reduce one contiguous range of
+// the system's chunk statistics (fixed ranges and trees: deterministic).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finalize(EngineArgs a) {
-    __shared__ long long shi[1024];
-    __shared__ double shd[1024];
-    const int s = blockIdx.x;
-    if (s >= a.max_sys) return;
-    SysDesc &d = a.desc[s];
+__global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
+    __shared__ long long shi[256];
+    __shared__ double shd[256];
+    const int s = blockIdx.y;
+    const SysDesc &d = a.desc[s];
     if (!participating(d, a.status[s])) return;   // uniform across the workgroup
     const int t = threadIdx.x;
+    const int64_t per = (d.nchunks + FIN_BLOCKS - 1) / FIN_BLOCKS;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < d.nchunks ? lo + per : d.nchunks;
     int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0, used = 0;
     double num = 0.0;
-#pragma unroll 4
-    for (int64_t i = t; i < d.nchunks; i += 1024) {
+    for (int64_t i = lo + t; i < hi; i += 256) {
         const ChunkStat cs = a.chunk_stat[d.gchunk0 + i];
         used += cs.used;
         nw += cs.nw;
@@ -923,14 +1122,36 @@ __global__ __launch_bounds__(1024) void k_finalize(EngineArgs a) {
         num = num + cs.num;
         att += (int64_t)a.chunk_nw[d.gchunk0 + i];
     }
-    nw = block_sum((long long)nw, shi);
-    nd = block_sum((long long)nd, shi);
-    c0 = block_sum((long long)c0, shi);
-    merged = block_sum((long long)merged, shi);
-    aborted = block_sum((long long)aborted, shi);
-    att = block_sum((long long)att, shi);
-    used = block_sum((long long)used, shi);
-    num = block_sum(num, shd);
+    FinPart p;
+    p.nw = block_sum((long long)nw, shi);
+    p.nd = block_sum((long long)nd, shi);
+    p.c0 = block_sum((long long)c0, shi);
+    p.merged = block_sum((long long)merged, shi);
+    p.aborted = block_sum((long long)aborted, shi);
+    p.attempts = block_sum((long long)att, shi);
+    p.used = block_sum((long long)used, shi);
+    p.num = block_sum(num, shd);
+    if (t == 0) a.fin_part[(int64_t)s * FIN_BLOCKS + blockIdx.x] = p;
+}
+
+// ---------------------------------------------------------------------------
+// K5b: per system (one wavefront): sum of the FIN_BLOCKS shares by a fixed
+// butterfly, the shift update, the per-iteration record.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
+    const int s = blockIdx.x;
+    SysDesc &d = a.desc[s];
+    if (!participating(d, a.status[s])) return;   // uniform across the wavefront
+    const int t = threadIdx.x;
+    const FinPart p = a.fin_part[(int64_t)s * FIN_BLOCKS + t];
+    const int64_t nw = wave_sum((long long)p.nw);
+    const int64_t nd = wave_sum((long long)p.nd);
+    const int64_t c0 = wave_sum((long long)p.c0);
+    const int64_t merged = wave_sum((long long)p.merged);
+    const int64_t aborted = wave_sum((long long)p.aborted);
+    const int64_t att = wave_sum((long long)p.attempts);
+    const int64_t used = wave_sum((long long)p.used);
+    const double num = wave_sum(p.num);
     if (t == 0) {
         const int64_t done = d.iter + 1;
         {
@@ -971,22 +1192,29 @@ __global__ __launch_bounds__(1024) void k_finalize(EngineArgs a) {
     }
 }
 
-void launch_iteration(const EngineArgs &a, int64_t chunk_grid, int post_grid, int spawn_grid,
-                      hipStream_t s, hipEvent_t *ev) {
+static_assert(FIN_BLOCKS == 64, "k_finalize sums one share per lane of a wavefront");
+static_assert(SCAN_G == 2048, "k_scan takes two range totals per thread of 1024");
+
+void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStream_t s,
+                      hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_chunk_sum, dim3((unsigned)chunk_grid), dim3(256), 0, s, a,
-                       (const SysDesc *)a.desc);
+    hipLaunchKernelGGL(k_chunk_sum, dim3(SCAN_G), dim3(256), 0, s, a, (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scan_down, dim3(SCAN_G), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
+    hipLaunchKernelGGL(k_insert, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[4], s);
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
+                       (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[5], s);
+    hipLaunchKernelGGL(k_reduce, dim3(FIN_BLOCKS, (unsigned)a.max_sys), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(64), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[6], s);
 }
 
 // ---------------------------------------------------------------------------
