@@ -38,7 +38,7 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Slater-Condon double element (26), pgen (15), acceptance (16).
 OPS_PER_ATTEMPT = 500
 PROFILES = os.path.join(ROOT, "profiles")
-KERNELS = ["k_chunk_sum", "k_scan", "k_spawn", "k_insert", "k_post", "k_finalize"]
+KERNELS = ["k_chunk_sum", "k_scan", "k_spawn", "k_post", "k_finalize"]
 
 
 def log(*a):
@@ -95,10 +95,9 @@ def bytes_per_kernel(rec, n_slots):
         # write the new population of each occupied slot, clear each accumulator that
         # received walkers, store H_DD of each newly occupied determinant (at most merged)
         "k_post": 28.0 * n_slots + 4.0 * nd + 8.0 * merged + 8.0 * merged,
-        # stage key + population of every slot once; write one 16-byte record per accepted spawn
-        "k_spawn": 12.0 * n_slots + 16.0 * spawns,
-        # per record: read it (16), probe the key (8), read-modify-write the accumulator (8 + 8)
-        "k_insert": 40.0 * spawns,
+        # stage key + population of every slot once; per accepted spawn probe the key (8) and
+        # read-modify-write the accumulator (8 + 8)
+        "k_spawn": 12.0 * n_slots + 24.0 * spawns,
     }
 
 
@@ -369,7 +368,6 @@ def main():
         "kernel_avg_ms": avg_ms,
         "roofline": roofline,
         "roofline_k_post": hbm_roofline("k_post"),
-        "roofline_k_insert": hbm_roofline("k_insert"),
     }
     sv_e = e1
     if not args.no_cpu_baseline:

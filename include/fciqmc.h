@@ -180,9 +180,9 @@ int fciqmc_batch_iterate(fciqmc_t *h, int32_t n_iterations);
 int fciqmc_batch_iterate_each(fciqmc_t *h, const int32_t *n_iter);
 
 /* Admit one system into a free slot while others may be mid-run. Fails with
- * ENOMEM when its tables (30 B per table slot: key 8, accumulator 8, population
- * 4, diagonal element 8, and a 2-byte share of the spawned list; two slots per
- * target walker, rounded up to a power of two) do not fit in the free device
+ * ENOMEM when its tables (28 B per table slot: key 8, accumulator 8, population
+ * 4, diagonal element 8; two slots per target walker, rounded up to a power of
+ * two) do not fit in the free device
  * memory left after the reserve, with ESTATE when no slot is free. */
 int fciqmc_batch_admit(fciqmc_t *h, const fciqmc_hamiltonian *ham, const fciqmc_params *prm,
                        int32_t *slot);
@@ -203,12 +203,12 @@ int32_t fciqmc_batch_active(fciqmc_t *h);
  * Per-kernel device time (ms) accumulated since the last reset, measured with
  * HIP events on the handle's stream around each kernel of non-graph launches
  * (enable with fciqmc_set_profiling(h, 1); graph launches are then disabled).
- * Kernel groups: 0 chunk sums, 1 chunk scans, 2 spawning (appends the
- * spawned list), 3 merge of the spawned list into the main table, 4 death +
- * annihilation per slot, 5 statistics reduction / shift. counts[k] is the
- * number of launches measured. */
+ * Kernel groups: 0 chunk sums, 1 chunk scans, 2 spawning (with the merge of
+ * spawned walkers into the main table), 3 death + annihilation per slot,
+ * 4 statistics reduction / shift. counts[k] is the number of launches
+ * measured. */
 int fciqmc_set_profiling(fciqmc_t *h, int32_t on);
-int fciqmc_kernel_times(fciqmc_t *h, double ms[6], int64_t counts[6]);
+int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
 
 /* ---- launch shape ----------------------------------------------------------
  * spawn_grid: workgroups of the spawning kernel; tile: consecutive attempts a

@@ -12,8 +12,6 @@ constexpr int MAX_GRAPH_ITERS = 64;  // iterations captured in one graph launch
 constexpr int SCAN_G = 2048;         // workgroups of the chunk-sum and scan-down kernels; each
                                      // takes one contiguous range of chunks
 constexpr int FIN_BLOCKS = 64;       // workgroups per system reducing the chunk statistics
-constexpr int SLOTS_PER_SPAWN_REC = 8; // spawned-list capacity: one record per 8 table slots
-                                       // (at least 2^20); a fuller list is merged directly
 
 // Status bits set on the device.
 constexpr uint32_t ST_TABLE_FULL = 1u;     // a spawn found no free slot: grow and redo
@@ -34,14 +32,6 @@ struct IterRecord {
 struct ChunkStat {
     int64_t nw, nd, c0, merged, aborted, used;
     double num;
-};
-
-// A spawning event waiting for annihilation: child determinant, signed walkers,
-// (system << 1) | initiator flag of the parent.
-struct SpawnRec {
-    uint64_t det;
-    int32_t v;
-    uint32_t sys_flag;
 };
 
 // One workgroup's share of a system's iteration statistics.
@@ -97,16 +87,13 @@ struct EngineArgs {
     unsigned long long *blk;         // [4][SCAN_G]: per chunk range sum |C|, tiles, and their
                                      // exclusive scans
     FinPart *fin_part;               // [max_sys][FIN_BLOCKS]
-    SpawnRec *sbuf;                  // spawned list of the iteration (all systems)
-    unsigned long long *scount;      // records appended to sbuf (reset per iteration)
-    unsigned long long scap;         // capacity of sbuf; records past it are merged directly
     unsigned long long *total;       // [0] total attempts, [1] total spawn tiles
     const int64_t *nchunks;          // global chunks in use
     IterRecord *rec;                 // [max_sys][REC_CAP]
 };
 
 // Kernel launchers (kernels.hip).
-constexpr int NKERN = 6;   // profiled kernel groups: chunk sums, scans, spawn, insert, post, finalize
+constexpr int NKERN = 5;   // profiled kernel groups: chunk sums, scans, spawn, post, finalize
 void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStream_t s,
                       hipEvent_t *ev /* NKERN + 1 events or nullptr */);
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,

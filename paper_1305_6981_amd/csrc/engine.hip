@@ -174,9 +174,6 @@ struct fciqmc_t {
     ChunkStat *d_chunk_stat = nullptr;
     unsigned long long *d_blk = nullptr;    // [4][SCAN_G] range sums and scans
     FinPart *d_fin = nullptr;               // [max_sys][FIN_BLOCKS]
-    SpawnRec *d_sbuf = nullptr;             // spawned list of an iteration
-    unsigned long long *d_scount = nullptr;
-    int64_t scap = 0;
     int64_t *d_nchunks = nullptr;
     uint32_t *d_err = nullptr;
     int spawn_grid = 2048;
@@ -205,9 +202,6 @@ EngineArgs make_args(fciqmc_t *h) {
     a.chunk_stat = h->d_chunk_stat;
     a.blk = h->d_blk;
     a.fin_part = h->d_fin;
-    a.sbuf = h->d_sbuf;
-    a.scount = h->d_scount;
-    a.scap = (unsigned long long)h->scap;
     a.total = h->d_total;
     a.nchunks = h->d_nchunks;
     a.rec = h->d_rec;
@@ -268,21 +262,6 @@ int relayout(fciqmc_t *h) {
         HIP_TRY(hipMalloc(&h->d_chunk_stat, na * sizeof(ChunkStat)));
         h->chunk_alloc = na;
         drop_graphs(h);
-    }
-    // spawned list: one record per SLOTS_PER_SPAWN_REC table slots, at least 2^20; if
-    // the device cannot hold a larger one the old one stays (overflow is merged directly)
-    const int64_t want = next_pow2(std::max<int64_t>(total * CHUNK / SLOTS_PER_SPAWN_REC, 1 << 20));
-    if (want > h->scap) {
-        SpawnRec *nb = nullptr;
-        if (hipMalloc(&nb, (size_t)want * sizeof(SpawnRec)) == hipSuccess) {
-            hipFree(h->d_sbuf);
-            h->d_sbuf = nb;
-            h->scap = want;
-            drop_graphs(h);
-        } else {
-            (void)hipGetLastError();
-            if (!h->d_sbuf) return set_err(FCIQMC_ENOMEM, "device allocation of the spawned list failed");
-        }
     }
     std::vector<int32_t> cs(total), cl(total);
     int64_t g = 0;
@@ -499,8 +478,7 @@ int64_t initial_capacity(const fciqmc_params *prm) {
 
 int64_t target_footprint(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     const int64_t cap = next_pow2(std::max<int64_t>(2 * std::max<int64_t>(prm->target_walkers, 1), 4 * CHUNK));
-    return table_bytes(cap) + cap / SLOTS_PER_SPAWN_REC * (int64_t)sizeof(SpawnRec) +
-           integral_bytes(ham->n_orb);
+    return table_bytes(cap) + integral_bytes(ham->n_orb);
 }
 
 int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop);
@@ -943,7 +921,6 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
     HIP_TRY(hipMalloc(&h->d_blk, 4 * SCAN_G * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_fin, sizeof(FinPart) * FIN_BLOCKS * max_slots));
-    HIP_TRY(hipMalloc(&h->d_scount, sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
     HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
     for (int k = 0; k <= NKERN; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
@@ -1012,8 +989,6 @@ void release(fciqmc_t *h) {
     hipFree(h->d_nchunks);
     hipFree(h->d_blk);
     hipFree(h->d_fin);
-    hipFree(h->d_sbuf);
-    hipFree(h->d_scount);
     hipFree(h->d_err);
     hipFree(h->d_chunk_sys);
     hipFree(h->d_chunk_local);
@@ -1291,8 +1266,8 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
             a1 += S.active ? S.tot_att : 0;
             slots += S.active ? S.cap : 0;
         }
-        spawn_ns = (h->kms[2] + h->kms[3]) * 1e6 / (double)std::max<int64_t>(a1 - a0, 1);
-        post_ns = h->kms[4] * 1e6 / (double)std::max<int64_t>(slots * iters_per_trial, 1);
+        spawn_ns = h->kms[2] * 1e6 / (double)std::max<int64_t>(a1 - a0, 1);
+        post_ns = h->kms[3] * 1e6 / (double)std::max<int64_t>(slots * iters_per_trial, 1);
         return 0;
     };
     int best_sg = h->spawn_grid, best_tl = h->tile, best_pg = h->post_grid;
@@ -1336,7 +1311,7 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
     return 0;
 }
 
-int fciqmc_kernel_times(fciqmc_t *h, double ms[6], int64_t counts[6]) {
+int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]) {
     if (!h || !ms || !counts) return set_err(FCIQMC_EINVAL, "null argument");
     for (int k = 0; k < NKERN; ++k) {
         ms[k] = h->kms[k];

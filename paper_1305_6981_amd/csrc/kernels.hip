@@ -1,5 +1,5 @@
 // HIP kernels of the FCIQMC iteration (Booth, Smart & Alavi, arXiv:1305.6981)
-// for gfx950. One iteration of every active system is eight launches:
+// for gfx950. One iteration of every active system is seven launches:
 //
 //   k_chunk_sum   sum |C| over each 1024-slot chunk of the current main tables,
 //                 and over fixed contiguous ranges of chunks
@@ -7,11 +7,9 @@
 //   k_scan_down   per chunk: global attempt offset and spawn-tile offset
 //   k_spawn       one spawning attempt per walker (Sec. 2, Eq. pspawn): random
 //                 excitation with its pgen (Sec. 5), Slater-Condon element,
-//                 acceptance; accepted spawns are appended to the
-//                 iteration's spawned list (Sec. 4.1)
-//   k_insert      merges the spawned list into the main table: each record is
-//                 summed into its determinant's slot by atomics (the merge of
-//                 equal spawned determinants and the annihilation of Sec. 4.1-4.2)
+//                 acceptance; accepted walkers are summed straight into the
+//                 target determinant's slot of the main table (the merge of
+//                 equal spawned determinants of Sec. 4.1, done by atomics)
 //   k_post        per slot, in place: death/cloning (Eq. pdeath), annihilation
 //                 of the arrived walkers with the initiator test for
 //                 determinants that are empty after death, the stored diagonal
@@ -487,7 +485,6 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
         a.total[1] = tpart[1023];
         a.work[0] = 0u;
         a.work[1] = 0u;
-        *a.scount = 0ull;
     }
 }
 
@@ -578,9 +575,9 @@ __device__ __forceinline__ bool acc_initiator(long long x) {
 
 // Work queued in LDS by the attempt loop and drained by the whole workgroup:
 // single excitations (their matrix element is an O(N) gather loop that would
-// stall a wavefront for one lane) and accepted spawns, which are appended to
-// the iteration's spawned list in one block (one reservation per drain) and
-// merged into the table by k_insert.
+// stall a wavefront for one lane) and accepted spawns (their merge into the
+// table is a chain of HBM round trips, overlapped with the other workgroups'
+// spawning).
 struct SingleItem {
     uint64_t D;        // source determinant
     double pgen;
@@ -612,24 +609,7 @@ struct SpawnQueues {
     uint64_t spd[SPW_QUEUE];
     int2 spv[SPW_QUEUE];   // (signed walkers, initiator flag)
     int nsgl, nspw, sys;
-    unsigned long long base;
 };
-
-// Append one spawning event of system s to the spawned list, or merge it
-// directly when the list is full.
-__device__ __forceinline__ void emit_spawn(const EngineArgs &a, const SysDesc &d, int s,
-                                           unsigned long long idx, uint64_t det, int32_t v,
-                                           bool init) {
-    if (idx < a.scap) {
-        SpawnRec r;
-        r.det = det;
-        r.v = v;
-        r.sys_flag = ((uint32_t)s << 1) | (init ? 1u : 0u);
-        a.sbuf[idx] = r;
-    } else if (!table_add(d.key, d.acc, d.cap_mask, det, v, init)) {
-        atomicOr(&a.status[s], ST_TABLE_FULL);
-    }
-}
 
 // Add the wavefront's spawning events of system s to its counter and reset the
 // per-thread tallies. The counter is one address for the whole chip, so it is
@@ -668,11 +648,9 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
     }
     __syncthreads();
     const int nspw = Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE;
-    if (t == 0 && nspw > 0) Q.base = atomicAdd(a.scount, (unsigned long long)nspw);
-    __syncthreads();
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
-        emit_spawn(a, d, s, Q.base + (unsigned long long)j, Q.spd[j], v.x, v.y != 0);
+        if (!table_add(d.key, d.acc, d.cap_mask, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
     }
     __syncthreads();
     if (t == 0) {
@@ -701,7 +679,9 @@ __device__ __forceinline__ int64_t last_le(const unsigned long long *v, int64_t 
     return lo + __popcll(__ballot(le)) - 1;
 }
 
-__global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
+// At most 96 VGPRs: five wavefronts per SIMD (the LDS use allows five workgroups per CU).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5)))
+void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long s_incl[CHUNK];
     __shared__ uint64_t s_det[CHUNK];
     __shared__ int32_t s_pop[CHUNK];
@@ -880,25 +860,6 @@ __global__ __launch_bounds__(256) void k_spawn(EngineArgs a, const SysDesc *__re
         const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
         if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, spawned);
         flush_spawn_count(&a.spawns[qs], spawned);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K3b: merge the iteration's spawned list into the main tables. Every record
-// is independent (integer sums), so the whole chip works on the list with no
-// barriers and the probes' round trips overlap across many wavefronts.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_insert(EngineArgs a, const SysDesc *__restrict__ desc) {
-    const unsigned long long cnt = *a.scount;
-    const unsigned long long n = cnt < a.scap ? cnt : a.scap;
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += stride) {
-        const SpawnRec r = a.sbuf[i];
-        const int s = (int)(r.sys_flag >> 1);
-        const SysDesc &d = desc[s];
-        if (!table_add(d.key, d.acc, d.cap_mask, r.det, r.v, (r.sys_flag & 1u) != 0))
-            atomicOr(&a.status[s], ST_TABLE_FULL);
     }
 }
 
@@ -1206,15 +1167,12 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStr
     hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_insert, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
-                       (const SysDesc *)a.desc);
-    if (ev) (void)hipEventRecord(ev[4], s);
     hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
-    if (ev) (void)hipEventRecord(ev[5], s);
+    if (ev) (void)hipEventRecord(ev[4], s);
     hipLaunchKernelGGL(k_reduce, dim3(FIN_BLOCKS, (unsigned)a.max_sys), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)a.max_sys), dim3(64), 0, s, a);
-    if (ev) (void)hipEventRecord(ev[6], s);
+    if (ev) (void)hipEventRecord(ev[5], s);
 }
 
 // ---------------------------------------------------------------------------

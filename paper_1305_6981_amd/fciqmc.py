@@ -267,8 +267,8 @@ def fciqmc_set_profiling(handle, on):
 
 
 def fciqmc_kernel_times(handle):
-    ms = np.zeros(6)
-    cnt = np.zeros(6, np.int64)
+    ms = np.zeros(5)
+    cnt = np.zeros(5, np.int64)
     _check(lib().fciqmc_kernel_times(handle, _ptr(ms), _ptr(cnt)))
     return ms, cnt
 

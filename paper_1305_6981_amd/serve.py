@@ -2,7 +2,7 @@
 
 Requests (a Hamiltonian, run parameters and an arrival time) are admitted into
 the slots of one batch handle as soon as a slot is free and their tables fit
-in device memory (``fciqmc_batch_admit`` checks the 30 B/slot footprint of the
+in device memory (``fciqmc_batch_admit`` checks the 28 B/slot footprint of the
 walker target against free HBM and fails with ENOMEM otherwise). All admitted
 systems advance together in graph-captured launches; each runs until its
 projected-energy error bar reaches the tolerance (with a minimum number of
