@@ -878,7 +878,7 @@ __device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t mask, 
     return -1;
 }
 
-constexpr int POST_QUEUE = 2048;
+constexpr int POST_QUEUE = 1536;  // with the 32 KiB pair table: four workgroups per CU
 constexpr int POST_GRAB = 4;      // chunks per dynamic grab in k_post
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
@@ -903,7 +903,8 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ double s_jk[64 * 64];
     __shared__ double s_hpp[64];
     __shared__ uint32_t s_queue[POST_QUEUE];
