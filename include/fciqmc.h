@@ -181,8 +181,8 @@ int fciqmc_batch_iterate_each(fciqmc_t *h, const int32_t *n_iter);
 
 /* Admit one system into a free slot while others may be mid-run. Fails with
  * ENOMEM when its tables (28 B per table slot: key 8, accumulator 8, population
- * 4, diagonal element 8; two slots per target walker, rounded up to a power of
- * two) do not fit in the free device
+ * 4, diagonal element 8; two slots per target walker, rounded up to a multiple
+ * of 4096) do not fit in the free device
  * memory left after the reserve, with ESTATE when no slot is free. */
 int fciqmc_batch_admit(fciqmc_t *h, const fciqmc_hamiltonian *ham, const fciqmc_params *prm,
                        int32_t *slot);

@@ -61,7 +61,7 @@ struct SysDesc {
                                      // 64-bit integer sum, so a spawn is one atomic add
     int32_t *pop;                    // signed walker count (0: vacated or not yet occupied)
     double *hdiag;                   // stored H_DD; NaN until the determinant is first occupied
-    uint64_t cap_mask;               // capacity - 1 (capacity a power of two >= CHUNK)
+    uint64_t cap;                    // table slots, a multiple of 4 CHUNK
     int64_t nchunks, gchunk0;        // chunks of this system and the first global chunk
     int64_t stop_at;                 // iterate while iter < stop_at
     // --- updated on the device

@@ -43,6 +43,12 @@ int set_err(int code, const std::string &msg) {
             return set_err(FCIQMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Table capacities: a multiple of 4 chunks, at least 4 chunks.
+int64_t round_cap(int64_t x) {
+    const int64_t q = 4 * CHUNK;
+    return std::max<int64_t>(q, (x + q - 1) / q * q);
+}
+
 int64_t next_pow2(int64_t x) {
     int64_t p = 1;
     while (p < x) p <<= 1;
@@ -375,7 +381,7 @@ void fill_desc_tables(fciqmc_t *h, int s) {
     d.eri = S.d_eri;
     d.jk = S.d_jk;
     d.t3 = S.d_t3;
-    d.cap_mask = (uint64_t)(S.cap - 1);
+    d.cap = (uint64_t)S.cap;
 }
 
 // Compact (and possibly grow) the table of system s into new_cap slots: only
@@ -390,8 +396,8 @@ int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
     carve(T, blk, new_cap);
     rc = upload_integrals(h, T);
     if (rc) return rc;
-    // the rehash kernel reads the new mask from the descriptor
-    h->hdesc[s].cap_mask = (uint64_t)(new_cap - 1);
+    // the rehash kernel reads the new capacity from the descriptor
+    h->hdesc[s].cap = (uint64_t)new_cap;
     rc = upload_desc(h);
     if (rc) return rc;
     HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
@@ -473,11 +479,11 @@ int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
 
 int64_t initial_capacity(const fciqmc_params *prm) {
     int64_t want = prm->det_capacity > 0 ? prm->det_capacity : 4 * std::max<int64_t>(prm->initial_walkers, 1024);
-    return next_pow2(std::max<int64_t>(want, 4 * CHUNK));
+    return round_cap(want);
 }
 
 int64_t target_footprint(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
-    const int64_t cap = next_pow2(std::max<int64_t>(2 * std::max<int64_t>(prm->target_walkers, 1), 4 * CHUNK));
+    const int64_t cap = round_cap(2 * std::max<int64_t>(prm->target_walkers, 1));
     return table_bytes(cap) + integral_bytes(ham->n_orb);
 }
 
@@ -603,7 +609,7 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
 int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop) {
     SysHost &S = h->sys[s];
     const int64_t n = (int64_t)det.size();
-    int64_t need = next_pow2(std::max<int64_t>(4 * CHUNK, 3 * n));
+    int64_t need = round_cap(3 * n);
     if (need > S.cap) {
         void *blk = nullptr;
         int rc = alloc_tables(h, S, need, &blk);
@@ -776,9 +782,9 @@ int plan_launch(fciqmc_t *h, int L, int *L_out) {
         const int64_t limit = S.cap * 7 / 10;
         int64_t used = std::max<int64_t>(S.last.used, S.last.nd);
         if (used + 4 * g > limit) {
+            // at least 1.5 x, and 50 % load after 8 more iterations of growth
             const int64_t live = S.last.nd + 1;
-            int64_t nc = S.cap;
-            while (live + 16 * g > nc * 45 / 100) nc <<= 1;
+            const int64_t nc = round_cap(std::max<int64_t>(S.cap + S.cap / 2, 2 * (live + 8 * g)));
             int rc = grow_system(h, s, nc);
             if (rc) return rc;
             used = live;

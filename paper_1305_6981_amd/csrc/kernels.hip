@@ -101,6 +101,12 @@ __device__ __forceinline__ uint64_t mix64(uint64_t h) {
     return h;
 }
 
+// First probe of a key in a table of cap slots (any cap): the high word of
+// mix64(k) * cap, i.e. the hash scaled onto [0, cap).
+__device__ __forceinline__ uint64_t home_slot(uint64_t k, uint64_t cap) {
+    return __umul64hi(mix64(k), cap);
+}
+
 // ---------------------------------------------------------------------------
 // Hamiltonian (spin orbital p = 2 s + sigma).
 // ---------------------------------------------------------------------------
@@ -550,10 +556,10 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
 // (one compare-and-swap per probe: it claims an empty slot or returns the key
 // there), then add (initiator ? 2^32 : 0) + v to the slot's accumulator with
 // one atomic whose result is not needed.
-__device__ __forceinline__ bool table_add(uint64_t *key, long long *acc, uint64_t mask, uint64_t k,
+__device__ __forceinline__ bool table_add(uint64_t *key, long long *acc, uint64_t cap, uint64_t k,
                                           int32_t v, bool init) {
-    uint64_t h = mix64(k) & mask;
-    for (uint64_t n = 0; n <= mask; ++n) {
+    uint64_t h = home_slot(k, cap);
+    for (uint64_t n = 0; n < cap; ++n) {
         uint64_t expect = 0;
         if (__hip_atomic_compare_exchange_strong(gp(&key[h]), &expect, k, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
@@ -562,7 +568,7 @@ __device__ __forceinline__ bool table_add(uint64_t *key, long long *acc, uint64_
             __hip_atomic_fetch_add(gp(&acc[h]), inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return true;
         }
-        h = (h + 1) & mask;
+        h = h + 1 == cap ? 0 : h + 1;
     }
     return false;
 }
@@ -642,7 +648,7 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         if (qq < SPW_QUEUE) {
             Q.spd[qq] = Dn;
             Q.spv[qq] = make_int2(v, init ? 1 : 0);
-        } else if (!table_add(d.key, d.acc, d.cap_mask, Dn, v, init)) {
+        } else if (!table_add(d.key, d.acc, d.cap, Dn, v, init)) {
             atomicOr(status, ST_TABLE_FULL);
         }
     }
@@ -650,7 +656,7 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
     const int nspw = Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE;
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
-        if (!table_add(d.key, d.acc, d.cap_mask, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
+        if (!table_add(d.key, d.acc, d.cap, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
     }
     __syncthreads();
     if (t == 0) {
@@ -839,7 +845,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                             if (q < SPW_QUEUE) {
                                 Q.spd[q] = ex.det;
                                 Q.spv[q] = make_int2(v, init ? 1 : 0);
-                            } else if (!table_add(d.key, d.acc, d.cap_mask, ex.det, v, init)) {
+                            } else if (!table_add(d.key, d.acc, d.cap, ex.det, v, init)) {
                                 atomicOr(status, ST_TABLE_FULL);
                             }
                         }
@@ -867,13 +873,13 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
 // K4: death, annihilation and initiator test per slot, in place; the
 // diagonal element of newly occupied determinants; estimator partials.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t mask, uint64_t key) {
-    uint64_t h = mix64(key) & mask;
-    for (uint64_t n = 0; n <= mask; ++n) {
+__device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t cap, uint64_t key) {
+    uint64_t h = home_slot(key, cap);
+    for (uint64_t n = 0; n < cap; ++n) {
         const unsigned long long old =
             atomicCAS((unsigned long long *)&keys[h], 0ull, (unsigned long long)key);
         if (old == 0ull) return (int64_t)h;
-        h = (h + 1) & mask;
+        h = h + 1 == cap ? 0 : h + 1;
     }
     return -1;
 }
@@ -1185,7 +1191,7 @@ __global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const in
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t D = det[i];
-        const int64_t j = insert_unique(d.key, d.cap_mask, D);
+        const int64_t j = insert_unique(d.key, d.cap, D);
         if (j < 0) {
             atomicOr(err, 1u);
             continue;
@@ -1205,7 +1211,7 @@ __global__ void k_rehash(SysDesc *desc, int32_t sys, const uint64_t *skv, const 
         if (D == 0) continue;
         const int32_t p = spop[i];
         if (p == 0 && D != d.d0) continue;
-        const int64_t j = insert_unique(dkv, d.cap_mask, D);
+        const int64_t j = insert_unique(dkv, d.cap, D);
         if (j < 0) {
             atomicOr(err, 1u);
             continue;
