@@ -283,38 +283,54 @@ struct ClassView {
     }
 };
 
-// recip[k] = 1.0 / k, filled by IEEE division (same bits as dividing in place).
-// For a single excitation the matrix element is left to the caller when
-// defer_single is set (ex.hel = NaN, the orbitals in ex.p / ex.a).
+// Single excitation (Sec. 5.1) from the electron draw x1 and the hole draw x2:
+// renormalised over the electrons that have an allowed target. Returns false
+// for a null excitation; otherwise the child, pgen and the orbitals p -> a.
 template <bool C1>
-__device__ __forceinline__ bool excite(const SysDesc &d, const ClassView<C1> &cv, uint64_t det,
-                                       uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3,
-                                       const double *recip, bool defer_single, Excit &ex) {
+__device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<C1> &cv,
+                                              uint64_t det, uint64_t x1, uint64_t x2, Excit &ex) {
+    const uint64_t emp = ~det & d.valid;
+    const int n_class = C1 ? 2 : d.n_class;
+    uint64_t movable = 0;
+    for (int c = 0; c < n_class; ++c) {
+        const uint64_t cm = C1 ? cv.mask(c) : d.cmask[c];
+        if (emp & cm) movable |= det & cm;
+    }
+    const uint32_t nmov = (uint32_t)__popcll(movable);
+    if (nmov == 0) return false;
+    const int p = select_bit(movable, pick(x1, nmov));
+    const uint64_t tg = emp & cv.mask(cv.cls(d, p));
+    const uint32_t nal = (uint32_t)__popcll(tg);
+    const int a = select_bit(tg, pick(x2, nal));
+    ex.det = det ^ (1ull << p) ^ (1ull << a);
+    ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
+    ex.p = p;
+    ex.a = a;
+    return true;
+}
+
+constexpr int EX_NULL = 0, EX_OK = 1, EX_SINGLE_DEFERRED = 2;
+
+// One excitation from the draws x0 (type), x1 (electron or pair), x2, x3
+// (holes). recip[k] = 1.0 / k, filled by IEEE division (same bits as dividing
+// in place). With defer_single a single excitation is only recognised
+// (EX_SINGLE_DEFERRED): the caller queues its draws and generates it later, so
+// the rare singles do not make whole wavefronts run the single path.
+template <bool C1>
+__device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv, uint64_t det,
+                                      uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3,
+                                      const double *recip, bool defer_single, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int N = d.N;
     const int n_class = C1 ? 2 : d.n_class;
     if (!(u01(x0) < d.p_double)) {
-        // Single (Sec. 5.1): renormalise over electrons that have an allowed target.
-        uint64_t movable = 0;
-        for (int c = 0; c < n_class; ++c) {
-            const uint64_t cm = C1 ? cv.mask(c) : d.cmask[c];
-            if (emp & cm) movable |= det & cm;
-        }
-        const uint32_t nmov = (uint32_t)__popcll(movable);
-        if (nmov == 0) return false;
-        const int p = select_bit(movable, pick(x1, nmov));
-        const uint64_t tg = emp & cv.mask(cv.cls(d, p));
-        const uint32_t nal = (uint32_t)__popcll(tg);
-        const int a = select_bit(tg, pick(x2, nal));
-        ex.det = det ^ (1ull << p) ^ (1ull << a);
-        ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
-        ex.p = p;
-        ex.a = a;
-        ex.hel = defer_single ? __longlong_as_double(0x7FF8000000000000ll) : hel_single(d, det, p, a);
-        return true;
+        if (defer_single) return EX_SINGLE_DEFERRED;
+        if (!excite_single(d, cv, det, x1, x2, ex)) return EX_NULL;
+        ex.hel = hel_single(d, det, ex.p, ex.a);
+        return EX_OK;
     }
     // Double (Sec. 5.2): a unique pair by inverse triangular indexing.
-    if (N < 2) return false;
+    if (N < 2) return EX_NULL;
     const uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
     const int64_t K = (int64_t)pick(x1, npairs);
     // estimate, then exact integer correction
@@ -337,7 +353,7 @@ __device__ __forceinline__ bool excite(const SysDesc &d, const ClassView<C1> &cv
         if (nb > 0) allowed |= memb;
     }
     const uint32_t nal = (uint32_t)__popcll(allowed);
-    if (nal == 0) return false;
+    if (nal == 0) return EX_NULL;
     const int a = select_bit(allowed, pick(x2, nal));
     const int ca = cv.cls(d, a);
     const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
@@ -351,7 +367,7 @@ __device__ __forceinline__ bool excite(const SysDesc &d, const ClassView<C1> &cv
     ex.pgen = (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
               (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
     ex.hel = hel_double(d, det, p, q, a, b);
-    return true;
+    return EX_OK;
 }
 
 // Natural log for the shift update: x = m 2^e with m in (1/sqrt2, sqrt2],
@@ -586,10 +602,10 @@ __device__ __forceinline__ bool acc_initiator(long long x) {
 // spawning).
 struct SingleItem {
     uint64_t D;        // source determinant
-    double pgen;
+    uint64_t x1, x2;   // electron and hole draws
     uint64_t x4;       // acceptance draw
     int32_t C;         // source population (sign)
-    uint32_t pai;      // p | a << 8 | initiator << 16
+    uint32_t init;     // initiator flag of the source
 };
 
 constexpr int SPAWN_GRAB = 4;    // spawn tiles per dynamic grab (one counter serves the chip)
@@ -636,14 +652,18 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
     const int nsgl = Q.nsgl < SGL_QUEUE ? Q.nsgl : SGL_QUEUE;
     for (int j = t; j < nsgl; j += blockDim.x) {
         const SingleItem it = Q.sgl[j];
-        const int p = (int)(it.pai & 0xFFu), q = (int)((it.pai >> 8) & 0xFFu);
-        const double hel = hel_single(d, it.D, p, q);
+        Excit ex;
+        const bool ok = d.n_class == 2
+                            ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.x1, it.x2, ex)
+                            : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.x1, it.x2, ex);
+        if (!ok) continue;
+        const double hel = hel_single(d, it.D, ex.p, ex.a);
         if (hel == 0.0) continue;
-        const int32_t v = accept(d, hel, it.pgen, it.x4, it.C, status);
+        const int32_t v = accept(d, hel, ex.pgen, it.x4, it.C, status);
         if (v == 0) continue;
         ++spawned;
-        const uint64_t Dn = it.D ^ (1ull << p) ^ (1ull << q);
-        const bool init = (it.pai >> 16) & 1u;
+        const uint64_t Dn = ex.det;
+        const bool init = it.init != 0;
         const int qq = atomicAdd(&Q.nspw, 1);
         if (qq < SPW_QUEUE) {
             Q.spd[qq] = Dn;
@@ -824,20 +844,23 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                 draw2(d.seed, D, k, d.iter, 1u, x2, x3);
                 draw2(d.seed, D, k, d.iter, 2u, x4, x5);
                 Excit ex;
-                const bool ok = c1 ? excite(d, cv1, D, x0, x1, x2, x3, s_recip, defer, ex)
-                                   : excite(d, cvg, D, x0, x1, x2, x3, s_recip, defer, ex);
-                if (ok) {
-                    if (isnan(ex.hel)) {
-                        const int q = atomicAdd(&Q.nsgl, 1);
-                        if (q < SGL_QUEUE) {
-                            Q.sgl[q] = SingleItem{D, ex.pgen, x4, C,
-                                                  (uint32_t)ex.p | ((uint32_t)ex.a << 8) |
-                                                      ((init ? 1u : 0u) << 16)};
-                        } else {
-                            ex.hel = hel_single(d, D, ex.p, ex.a);
-                        }
+                int r = c1 ? excite(d, cv1, D, x0, x1, x2, x3, s_recip, defer, ex)
+                           : excite(d, cvg, D, x0, x1, x2, x3, s_recip, defer, ex);
+                if (r == EX_SINGLE_DEFERRED) {
+                    const int q = atomicAdd(&Q.nsgl, 1);
+                    if (q < SGL_QUEUE) {
+                        Q.sgl[q] = SingleItem{D, x1, x2, x4, C, init ? 1u : 0u};
+                        r = EX_NULL;
+                    } else {
+                        // queue full: generate it here
+                        const bool ok = c1 ? excite_single(d, cv1, D, x1, x2, ex)
+                                           : excite_single(d, cvg, D, x1, x2, ex);
+                        r = ok ? EX_OK : EX_NULL;
+                        if (ok) ex.hel = hel_single(d, D, ex.p, ex.a);
                     }
-                    if (!isnan(ex.hel) && ex.hel != 0.0) {
+                }
+                if (r == EX_OK) {
+                    if (ex.hel != 0.0) {
                         const int32_t v = accept(d, ex.hel, ex.pgen, x4, C, status);
                         if (v != 0) {
                             ++spawned;
