@@ -220,6 +220,74 @@ def copy_calibration(roctx, nbytes=1 << 30):
     del x, y
 
 
+def pmc_means(path, last=0):
+    """{(kernel, counter): mean per dispatch} from a rocprofv3 --pmc CSV tree (only the
+    last `last` dispatches of each kernel when last > 0)."""
+    import csv
+    import glob
+    rows = {}
+    for f in sorted(glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                name = (r.get("Kernel_Name") or r.get("Kernel-Name") or "?").split("(")[0]
+                ctr = r.get("Counter_Name") or r.get("Counter-Name") or "?"
+                v = float(r.get("Counter_Value") or r.get("Counter-Value") or "nan")
+                disp = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or 0)
+                rows.setdefault((name, ctr), {}).setdefault(disp, 0.0)
+                rows[(name, ctr)][disp] += v
+    out = {}
+    for key, d in rows.items():
+        vals = [d[k] for k in sorted(d)]
+        if last:
+            vals = vals[-last:]
+        out[key] = (sum(vals) / len(vals), len(vals))
+    return out
+
+
+TRAFFIC_KERNELS = ("k_spawn", "k_post", "k_chunk_sum")
+CALIBRATION_KERNEL = "MulFunctor"
+
+
+def write_traffic(fetch_dir, write_dir, last, command):
+    """Write profiles/<kernel>_hbm_traffic.txt for the iteration kernels from a FETCH_SIZE
+    run and a WRITE_SIZE run of `bench.py --calibrate-copy`: the per-dispatch means of the
+    last `last` dispatches, scaled by what the same counters read for the calibration
+    multiply (1 GiB read + 1 GiB written)."""
+    f = pmc_means(fetch_dir, last)
+    w = pmc_means(write_dir, last)
+    cal_f = [v for (k, c), v in f.items() if CALIBRATION_KERNEL in k and c == "FETCH_SIZE"]
+    cal_w = [v for (k, c), v in w.items() if CALIBRATION_KERNEL in k and c == "WRITE_SIZE"]
+    if not cal_f or not cal_w:
+        raise SystemExit("no calibration kernel in the counter runs (use --calibrate-copy)")
+    fc = 1048576.0 / cal_f[0][0]
+    wc = 1048576.0 / cal_w[0][0]
+    for kern in TRAFFIC_KERNELS:
+        fk = [v for (k, c), v in f.items() if k.endswith("::" + kern) and c == "FETCH_SIZE"]
+        wk = [v for (k, c), v in w.items() if k.endswith("::" + kern) and c == "WRITE_SIZE"]
+        if not fk or not wk:
+            continue
+        fb, wb = fk[0][0] * 1024.0, wk[0][0] * 1024.0
+        with open(os.path.join(PROFILES, f"{kern}_hbm_traffic.txt"), "w") as out:
+            out.write(f"# HBM traffic of {kern} per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE\n"
+                      f"# (KiB per dispatch, mean of the last {fk[0][1]} dispatches = the timed ones),\n"
+                      "# scaled by the counters' reading for an elementwise multiply that reads and\n"
+                      "# writes 1 GiB each (caches evicted first) in the same runs.\n"
+                      "# Workload: bench.py defaults (synthetic 24e/30o band system, growth to 1e8\n"
+                      "# walkers, 5 warm-up + 20 timed iterations).\n"
+                      "# Commands (repository root, one MI355X):\n")
+            for c in command:
+                out.write(f"#   {c}\n")
+            out.write(f"kernels_sha256: {kernel_source_hash()}\n"
+                      f"fetch_kib_per_launch_raw: {fk[0][0]:.0f}\n"
+                      f"write_kib_per_launch_raw: {wk[0][0]:.0f}\n"
+                      f"fetch_bytes_per_launch: {fb:.0f}\n"
+                      f"write_bytes_per_launch: {wb:.0f}\n"
+                      f"fetch_calibration: {fc:.6f}\n"
+                      f"write_calibration: {wc:.6f}\n"
+                      f"calibrated_total_bytes_per_launch: {fb * fc + wb * wc:.4g}\n")
+        print(f"wrote {kern}: {(fb * fc + wb * wc) / 1e9:.3f} GB per launch")
+
+
 def pmc_summary(path, last=0):
     """Mean of each counter per dispatch, per kernel, from a rocprofv3 --pmc CSV tree
     (only the last `last` dispatches of each kernel when last > 0)."""
@@ -265,6 +333,10 @@ def main():
     if len(sys.argv) >= 3 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 0)
         return
+    if len(sys.argv) >= 5 and sys.argv[1] == "--write-traffic":
+        # --write-traffic FETCH_DIR WRITE_DIR LAST [command lines ...]
+        write_traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -305,8 +377,16 @@ def main():
     sv.set_shift(s_est, 1)
     log(f"[bench] grown in {time.perf_counter() - t_g:.1f} s: N_w {e['n_walkers']} N_d "
         f"{e['n_dets']} C0 {e['ref_pop']}; shift set to E_proj - E0 = {s_est:.4f}")
+    nd0 = sv.estimates()["n_dets"]
     sv.iterate(args.warmup)
-    log("[bench] warm-up done")
+    # Size the table for the timed iterations now (growth rate of the warm-up, 30 % slack,
+    # 40 % of the slots holding live determinants at the end: vacated slots keep their
+    # key until the next rehash), so that no rehash falls inside the timed region.
+    ew = sv.estimates()
+    g = max(0.0, (ew["n_dets"] - nd0) / max(args.warmup, 1))
+    sv.reserve(int(2.5 * (ew["n_dets"] + 1.3 * g * (args.steps + 2))))
+    log(f"[bench] warm-up done; table {sv.estimates()['table_slots']} slots for N_d "
+        f"{ew['n_dets']} growing by ~{g:.3g} per iteration")
 
     F.fciqmc_set_profiling(sv.h, 1)
     e0 = sv.estimates()
@@ -327,10 +407,14 @@ def main():
     spawns = e1["total_spawns"] - e0["total_spawns"]
     log(f"[bench] timed {args.steps} iterations in {dt:.3f} s: N_w {e1['n_walkers']} N_d "
         f"{e1['n_dets']} attempts {attempts} spawns {spawns}")
+    grew = e1["table_slots"] != e0["table_slots"]
+    if grew:
+        log(f"[bench] the table grew inside the timed region ({e0['table_slots']} -> "
+            f"{e1['table_slots']} slots); per-launch bytes use the mean of the two")
 
     avg_ms = {k: float(kms[i] / max(kcnt[i], 1)) for i, k in enumerate(KERNELS)}
     dominant = max(("k_spawn", "k_post", "k_chunk_sum"), key=lambda k: avg_ms[k])
-    n_slots = e1["table_slots"]
+    n_slots = 0.5 * (e0["table_slots"] + e1["table_slots"])
     det, pop, _ = sv.walkers()
     rec = {"n_dets": e1["n_dets"], "spawns": spawns / args.steps, "merged": e1["merged"],
            "attempts": attempts / args.steps}
@@ -363,7 +447,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "synthetic 24e/30o with a 12-orbital band at +-0.2 Ha, initiator n_a=3, "
                                f"tau=5e-4, {e1['n_walkers']} walkers on {e1['n_dets']} dets",
-                   "walkers": e1["n_walkers"], "dets": e1["n_dets"], "table_slots": n_slots,
+                   "walkers": e1["n_walkers"], "dets": e1["n_dets"],
+                   "table_slots": e1["table_slots"], "table_grew_in_timed_region": grew,
                    "parallelism": "1 GPU"},
         "kernel_avg_ms": avg_ms,
         "roofline": roofline,

@@ -157,6 +157,13 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
  * iteration. Used to end a growth stage run at a raised shift. */
 int fciqmc_set_shift(fciqmc_t *h, double shift, int32_t varying);
 
+/* Grow the main table of every active system to at least `slots` slots
+ * (rounded up to a multiple of 4096) now, rather than when the table fills;
+ * the rehash drops vacated slots. A table already that large is left alone.
+ * Results never depend on table sizes. Errors: EINVAL (slots < 0), ECAPACITY
+ * (the device cannot hold the larger table; the old one stays). */
+int fciqmc_reserve(fciqmc_t *h, int64_t slots);
+
 /* Thread-local message of the last failure ("" when none). */
 const char *fciqmc_last_error(void);
 

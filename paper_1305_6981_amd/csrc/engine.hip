@@ -1178,6 +1178,19 @@ int fciqmc_set_shift(fciqmc_t *h, double shift, int32_t varying) {
     return upload_desc(h);
 }
 
+int fciqmc_reserve(fciqmc_t *h, int64_t slots) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    if (slots < 0) return set_err(FCIQMC_EINVAL, "slots must be >= 0");
+    const int64_t want = round_cap(slots);
+    for (int s = 0; s < h->max_sys; ++s) {
+        SysHost &S = h->sys[s];
+        if (!S.active || S.fatal || S.cap >= want) continue;
+        const int rc = grow_system(h, s, want);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
 int fciqmc_batch_admit(fciqmc_t *h, const fciqmc_hamiltonian *ham, const fciqmc_params *prm,
                        int32_t *slot) {
     if (!h || !slot) return set_err(FCIQMC_EINVAL, "null argument");

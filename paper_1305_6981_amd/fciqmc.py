@@ -53,7 +53,8 @@ class Estimates(C.Structure):
 
 
 EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
-            "fciqmc_walkers", "fciqmc_load_walkers", "fciqmc_set_shift", "fciqmc_last_error",
+            "fciqmc_walkers", "fciqmc_load_walkers", "fciqmc_set_shift", "fciqmc_reserve",
+            "fciqmc_last_error",
             "fciqmc_batch_create", "fciqmc_batch_iterate", "fciqmc_batch_iterate_each",
             "fciqmc_batch_admit", "fciqmc_batch_retire", "fciqmc_batch_slot_estimators",
             "fciqmc_batch_slot_walkers", "fciqmc_footprint_bytes", "fciqmc_batch_active",
@@ -78,6 +79,7 @@ def lib():
             "fciqmc_walkers": ([vp, vp, vp, vp, i64], i64),
             "fciqmc_load_walkers": ([vp, vp, vp, i64, i64, C.c_double, i64, i32, i64], C.c_int),
             "fciqmc_set_shift": ([vp, C.c_double, i32], C.c_int),
+            "fciqmc_reserve": ([vp, C.c_int64], C.c_int),
             "fciqmc_last_error": ([], C.c_char_p),
             "fciqmc_batch_create": ([i32, i32, H, P, vp, C.POINTER(vp)], C.c_int),
             "fciqmc_batch_iterate": ([vp, i32], C.c_int),
@@ -202,6 +204,10 @@ def fciqmc_set_shift(handle, shift, varying=1):
     _check(lib().fciqmc_set_shift(handle, shift, varying))
 
 
+def fciqmc_reserve(handle, slots):
+    _check(lib().fciqmc_reserve(handle, int(slots)))
+
+
 def fciqmc_last_error():
     return lib().fciqmc_last_error().decode()
 
@@ -308,6 +314,9 @@ class Solver:
 
     def set_shift(self, shift, varying=1):
         fciqmc_set_shift(self.h, shift, varying)
+
+    def reserve(self, slots):
+        fciqmc_reserve(self.h, slots)
 
     def close(self):
         if self.h:

@@ -113,6 +113,27 @@ def test_forced_table_growth_is_result_neutral():
     _run_pair(ham, prm, blocks=3, per_block=60, tag="growth")
 
 
+def test_reserve_is_result_neutral():
+    """Growing the table on request (odd sizes, mid-run, also a no-op request) changes
+    nothing in the trajectory."""
+    ham, prm, _ = S.workload("synth10e20o", scale=2e-4)
+    prm.initial_walkers, prm.initial_shift = 400, 0.5
+    print("[gpu] reserve", flush=True)
+    gpu = F.Solver(ham, prm, _stream())
+    ref = O.Oracle(ham, prm)
+    for b, slots in enumerate([0, 12345, 100000, 50000, 4096 * 37]):
+        gpu.reserve(slots)
+        assert gpu.estimates()["table_slots"] >= slots
+        assert gpu.estimates()["table_slots"] % 4096 == 0
+        gpu.iterate(9)
+        ref.iterate(9)
+        _same_lists(gpu, ref, f"reserve{b}")
+        _same_estimates(gpu.estimates(), ref.estimates(), f"reserve{b}")
+    with pytest.raises(F.FciqmcError):
+        gpu.reserve(-1)
+    gpu.close()
+
+
 def test_snapshot_restart_matches_oracle():
     ham, prm, _ = S.workload("synth10e20o", scale=2e-4)
     prm.initial_walkers = 400
