@@ -29,14 +29,19 @@ struct IterRecord {
     int32_t varying, status;
 };
 
+// Per-chunk statistics of an iteration. counts packs three numbers of at most
+// CHUNK each: slots holding a key | merged spawn targets << 21 | occupied << 42.
 struct ChunkStat {
-    int64_t nw, nd, c0, merged, aborted, used;
+    int64_t nw, aborted;
+    uint64_t counts;
     double num;
 };
+constexpr int CNT_SHIFT_MERGED = 21, CNT_SHIFT_ND = 42;
+constexpr uint64_t CNT_FIELD = (1ull << 21) - 1;
 
 // One workgroup's share of a system's iteration statistics.
 struct FinPart {
-    int64_t nw, nd, c0, merged, aborted, used, attempts;
+    int64_t nw, nd, merged, aborted, used, attempts;
     double num;
 };
 
@@ -87,6 +92,7 @@ struct EngineArgs {
     unsigned long long *blk;         // [4][SCAN_G]: per chunk range sum |C|, tiles, and their
                                      // exclusive scans
     FinPart *fin_part;               // [max_sys][FIN_BLOCKS]
+    int64_t *c0;                     // [max_sys] population on the reference after the iteration
     unsigned long long *total;       // [0] total attempts, [1] total spawn tiles
     const int64_t *nchunks;          // global chunks in use
     IterRecord *rec;                 // [max_sys][REC_CAP]

@@ -180,6 +180,7 @@ struct fciqmc_t {
     ChunkStat *d_chunk_stat = nullptr;
     unsigned long long *d_blk = nullptr;    // [4][SCAN_G] range sums and scans
     FinPart *d_fin = nullptr;               // [max_sys][FIN_BLOCKS]
+    int64_t *d_c0 = nullptr;                // [max_sys]
     int64_t *d_nchunks = nullptr;
     uint32_t *d_err = nullptr;
     int spawn_grid = 2048;
@@ -208,6 +209,7 @@ EngineArgs make_args(fciqmc_t *h) {
     a.chunk_stat = h->d_chunk_stat;
     a.blk = h->d_blk;
     a.fin_part = h->d_fin;
+    a.c0 = h->d_c0;
     a.total = h->d_total;
     a.nchunks = h->d_nchunks;
     a.rec = h->d_rec;
@@ -927,6 +929,7 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
     HIP_TRY(hipMalloc(&h->d_blk, 4 * SCAN_G * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_fin, sizeof(FinPart) * FIN_BLOCKS * max_slots));
+    HIP_TRY(hipMalloc(&h->d_c0, sizeof(int64_t) * max_slots));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
     HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
     for (int k = 0; k <= NKERN; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
@@ -995,6 +998,7 @@ void release(fciqmc_t *h) {
     hipFree(h->d_nchunks);
     hipFree(h->d_blk);
     hipFree(h->d_fin);
+    hipFree(h->d_c0);
     hipFree(h->d_err);
     hipFree(h->d_chunk_sys);
     hipFree(h->d_chunk_local);

@@ -911,24 +911,44 @@ constexpr int POST_QUEUE = 1536;  // with the 32 KiB pair table: four workgroups
 constexpr int POST_GRAB = 4;      // chunks per dynamic grab in k_post
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
-// ascending (p, q) order from the LDS copies of h_pp and of the pair table.
-__device__ __forceinline__ double hdiag_lds(double e_core, uint64_t det, const double *hpp,
-                                            const double *jk) {
-    double acc = e_core;
-    for (uint64_t m = det; m; m &= m - 1) acc = acc + hpp[__builtin_ctzll(m)];
-    for (uint64_t m1 = det; m1; m1 &= m1 - 1) {
-        const double *row = jk + 64 * __builtin_ctzll(m1);
-        for (uint64_t m2 = m1 & (m1 - 1); m2; m2 &= m2 - 1) acc = acc + row[__builtin_ctzll(m2)];
+// ascending (p, q) order from the LDS copies of h_pp and of the pair table, for
+// two determinants with the same number of electrons at once: the two sums are
+// independent chains that hide each other's add latency, and each keeps the
+// order of a single sum.
+__device__ __forceinline__ void hdiag_lds2(double e_core, uint64_t da, uint64_t db,
+                                           const double *hpp, const double *jk, double &ra,
+                                           double &rb) {
+    double xa = e_core, xb = e_core;
+    for (uint64_t ma = da, mb = db; ma; ma &= ma - 1, mb &= mb - 1) {
+        xa = xa + hpp[__builtin_ctzll(ma)];
+        xb = xb + hpp[__builtin_ctzll(mb)];
     }
-    return acc;
+    for (uint64_t m1a = da, m1b = db; m1a; m1a &= m1a - 1, m1b &= m1b - 1) {
+        const double *rowa = jk + 64 * __builtin_ctzll(m1a);
+        const double *rowb = jk + 64 * __builtin_ctzll(m1b);
+        for (uint64_t m2a = m1a & (m1a - 1), m2b = m1b & (m1b - 1); m2a;
+             m2a &= m2a - 1, m2b &= m2b - 1) {
+            xa = xa + rowa[__builtin_ctzll(m2a)];
+            xb = xb + rowb[__builtin_ctzll(m2b)];
+        }
+    }
+    ra = xa;
+    rb = xb;
 }
 
-// Diagonal elements of the queued newly occupied slots, all lanes busy.
+// Diagonal elements of the queued newly occupied slots (all of one system, so
+// all with the same electron count), two per thread at a time.
 __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t *queue, int n,
                                                const double *hpp, const double *jk) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const uint32_t i = queue[j];
-        *gp(d.hdiag + i) = hdiag_lds(d.e_core, *gp(d.key + i), hpp, jk);
+    const int step = 2 * (int)blockDim.x;
+    for (int j = threadIdx.x; j < n; j += step) {
+        const uint32_t i0 = queue[j];
+        const bool two = j + (int)blockDim.x < n;
+        const uint32_t i1 = two ? queue[j + blockDim.x] : i0;
+        double h0, h1;
+        hdiag_lds2(d.e_core, *gp(d.key + i0), *gp(d.key + i1), hpp, jk, h0, h1);
+        *gp(d.hdiag + i0) = h0;
+        if (two) *gp(d.hdiag + i1) = h1;
     }
 }
 
@@ -938,7 +958,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ double s_hpp[64];
     __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ int s_qn;
-    __shared__ long long s_red[4][6];
+    __shared__ long long s_red[4][3];
     __shared__ double s_redd[4];
     __shared__ unsigned int s_next;
     const int64_t nch = *a.nchunks;
@@ -959,7 +979,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
         }
         if (c >= nch) break;
         const int s = a.chunk_sys[c];
-        int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, used = 0;
+        int64_t nw = 0, aborted = 0;
+        uint64_t cnt = 0;   // slots holding a key | merged targets << 21 | occupied << 42
         double num = 0.0;
         const bool live = s >= 0 && participating(desc[s], a.status[s]);   // uniform
         if (live) {
@@ -995,7 +1016,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             for (int u = 0; u < 4; ++u) {
                 const uint64_t D = kin[u];
                 if (D == 0) continue;
-                ++used;
+                cnt += 1ull;
                 const int32_t p = pin[u];
                 int64_t pd = p;
                 if (p != 0) {
@@ -1026,7 +1047,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     np = 0;
                     if (sp != 0) aborted += sp < 0 ? -sp : sp;
                 }
-                if (sp != 0) ++merged;
+                if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
                 if (np > 2147483647ll || np < -2147483647ll) {
                     atomicOr(&a.status[s], ST_POP_OVERFLOW);
                     np = 0;
@@ -1037,10 +1058,10 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     const int q = atomicAdd(&s_qn, 1);
                     s_queue[q] = (uint32_t)(base + u);
                 }
-                if (D == d.d0) c0 = np;
+                if (D == d.d0) a.c0[s] = np;   // the reference has one slot
                 if (np != 0) {
                     nw += np < 0 ? -np : np;
-                    ++nd;
+                    cnt += 1ull << CNT_SHIFT_ND;
                     if (D != d.d0 && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
                 }
             }
@@ -1052,31 +1073,22 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
         }
         // fixed-order reduction: lane butterfly, then waves 0..3
         nw = wave_sum((long long)nw);
-        nd = wave_sum((long long)nd);
-        c0 = wave_sum((long long)c0);
-        merged = wave_sum((long long)merged);
         aborted = wave_sum((long long)aborted);
-        used = wave_sum((long long)used);
+        cnt = wave_sum((unsigned long long)cnt);
         num = wave_sum(num);
         if (lane == 0) {
             s_red[wid][0] = nw;
-            s_red[wid][1] = nd;
-            s_red[wid][2] = c0;
-            s_red[wid][3] = merged;
-            s_red[wid][4] = aborted;
-            s_red[wid][5] = used;
+            s_red[wid][1] = aborted;
+            s_red[wid][2] = (long long)cnt;
             s_redd[wid] = num;
         }
         __syncthreads();
         if (t == 0) {
-            ChunkStat cs{0, 0, 0, 0, 0, 0, 0.0};
+            ChunkStat cs{0, 0, 0ull, 0.0};
             for (int w = 0; w < 4; ++w) {
                 cs.nw += s_red[w][0];
-                cs.nd += s_red[w][1];
-                cs.c0 += s_red[w][2];
-                cs.merged += s_red[w][3];
-                cs.aborted += s_red[w][4];
-                cs.used += s_red[w][5];
+                cs.aborted += s_red[w][1];
+                cs.counts += (uint64_t)s_red[w][2];
                 cs.num = cs.num + s_redd[w];
             }
             a.chunk_stat[c] = cs;
@@ -1100,15 +1112,14 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
     const int64_t per = (d.nchunks + FIN_BLOCKS - 1) / FIN_BLOCKS;
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < d.nchunks ? lo + per : d.nchunks;
-    int64_t nw = 0, nd = 0, c0 = 0, merged = 0, aborted = 0, att = 0, used = 0;
+    int64_t nw = 0, nd = 0, merged = 0, aborted = 0, att = 0, used = 0;
     double num = 0.0;
     for (int64_t i = lo + t; i < hi; i += 256) {
         const ChunkStat cs = a.chunk_stat[d.gchunk0 + i];
-        used += cs.used;
+        used += (int64_t)(cs.counts & CNT_FIELD);
+        merged += (int64_t)((cs.counts >> CNT_SHIFT_MERGED) & CNT_FIELD);
+        nd += (int64_t)(cs.counts >> CNT_SHIFT_ND);
         nw += cs.nw;
-        nd += cs.nd;
-        c0 += cs.c0;
-        merged += cs.merged;
         aborted += cs.aborted;
         num = num + cs.num;
         att += (int64_t)a.chunk_nw[d.gchunk0 + i];
@@ -1116,7 +1127,6 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
     FinPart p;
     p.nw = block_sum((long long)nw, shi);
     p.nd = block_sum((long long)nd, shi);
-    p.c0 = block_sum((long long)c0, shi);
     p.merged = block_sum((long long)merged, shi);
     p.aborted = block_sum((long long)aborted, shi);
     p.attempts = block_sum((long long)att, shi);
@@ -1137,7 +1147,7 @@ __global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
     const FinPart p = a.fin_part[(int64_t)s * FIN_BLOCKS + t];
     const int64_t nw = wave_sum((long long)p.nw);
     const int64_t nd = wave_sum((long long)p.nd);
-    const int64_t c0 = wave_sum((long long)p.c0);
+    const int64_t c0 = a.c0[s];
     const int64_t merged = wave_sum((long long)p.merged);
     const int64_t aborted = wave_sum((long long)p.aborted);
     const int64_t att = wave_sum((long long)p.attempts);
