@@ -754,6 +754,9 @@ typedef struct {
     /* this process's share of the last iteration's statistics */
     int64_t attempts, merged, aborted, nw, nd, c0;
     double num;
+    /* entries of a walker list being loaded that this process owns */
+    int64_t *load_idx;
+    int64_t n_load;
     char err[512];
 } proc_t;
 
@@ -762,6 +765,8 @@ struct orc_state {
     orc_params prm;
     int32_t n_procs, n_threads;
     proc_t *proc;
+    const uint64_t *load_det;     /* walker list being loaded (during orc_load_walkers) */
+    const int32_t *load_pop;
     int64_t pmap[64];         /* Algorithm 1 map of the process hash */
     /* dynamics */
     int64_t iter;
@@ -1037,6 +1042,7 @@ static void procs_free(orc_state *st)
         free(pr->n_out);
         free(pr->cap_out);
         free(pr->in);
+        free(pr->load_idx);
     }
     free(st->proc);
     st->proc = NULL;
@@ -1309,12 +1315,32 @@ typedef struct {
     int bad;                  /* lowest failing process, or -1 */
 } job_t;
 
+/* Insert the loaded entries this process owns, in input order, each with its
+ * diagonal element; then this process's share of the statistics. */
+static int proc_load(orc_state *st, int q)
+{
+    proc_t *pr = &st->proc[q];
+    mainlist_t *ml = &pr->ml;
+    for (int64_t u = 0; u < pr->n_load; u++) {
+        const int64_t t = pr->load_idx[u];
+        const uint64_t D = st->load_det[t];
+        if (ml_find(ml, D) >= 0)
+            return fail("oracle: duplicate determinant in walker list");
+        if (ml_insert(ml, D, st->load_pop[t], hdiag_of(&st->sys, D)) < 0)
+            return -1;
+    }
+    proc_stats(st, q);
+    return 0;
+}
+
 static void *run_job(void *arg)
 {
     job_t *j = arg;
     j->bad = -1;
     for (int p = j->first; p < j->st->n_procs; p += j->stride) {
-        int rc = j->phase == 0 ? proc_spawn_death(j->st, p) : proc_annihilate(j->st, p);
+        int rc = j->phase == 0   ? proc_spawn_death(j->st, p)
+                 : j->phase == 1 ? proc_annihilate(j->st, p)
+                                 : proc_load(j->st, p);
         if (rc != 0) {
             snprintf(j->st->proc[p].err, sizeof j->st->proc[p].err, "%s", g_err);
             j->bad = p;
@@ -1520,20 +1546,54 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
     procs_free(st);
     if (procs_init(st, range) != 0)
         return -1;
+    /* Bucket the entries by owning process (input order kept), then let every
+     * process insert its own bucket. */
+    const int P = st->n_procs;
     int have_ref = 0;
+    int32_t *own = malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+    if (!own)
+        return fail("oracle: out of host memory");
     for (int64_t t = 0; t < n; t++) {
+        own[t] = -1;
         if (pop[t] == 0)
             continue;
-        mainlist_t *ml = &st->proc[owner_of(st, det[t])].ml;
-        if (ml_find(ml, det[t]) >= 0)
-            return fail("oracle: duplicate determinant in walker list");
         if (det[t] == st->sys.d0)
             have_ref = 1;
-        if (ml_insert(ml, det[t], pop[t], hdiag_of(&st->sys, det[t])) < 0)
-            return -1;
+        own[t] = owner_of(st, det[t]);
+        st->proc[own[t]].n_load++;
     }
-    if (!have_ref &&
-        ml_insert(&st->proc[owner_of(st, st->sys.d0)].ml, st->sys.d0, 0, st->sys.e0) < 0)
+    int rc = 0;
+    for (int p = 0; p < P && rc == 0; p++) {
+        st->proc[p].load_idx = malloc((size_t)(st->proc[p].n_load ? st->proc[p].n_load : 1) *
+                                      sizeof(int64_t));
+        if (!st->proc[p].load_idx)
+            rc = fail("oracle: out of host memory");
+        st->proc[p].n_load = 0;
+    }
+    if (rc == 0) {
+        for (int64_t t = 0; t < n; t++)
+            if (own[t] >= 0) {
+                proc_t *pr = &st->proc[own[t]];
+                pr->load_idx[pr->n_load++] = t;
+            }
+        if (!have_ref)
+            rc = ml_insert(&st->proc[owner_of(st, st->sys.d0)].ml, st->sys.d0, 0, st->sys.e0) < 0
+                     ? -1
+                     : 0;
+    }
+    free(own);
+    st->load_det = det;
+    st->load_pop = pop;
+    if (rc == 0)
+        rc = run_phase(st, 2);
+    st->load_det = NULL;
+    st->load_pop = NULL;
+    for (int p = 0; p < P; p++) {
+        free(st->proc[p].load_idx);
+        st->proc[p].load_idx = NULL;
+        st->proc[p].n_load = 0;
+    }
+    if (rc != 0)
         return -1;
     st->iter = iteration;
     st->shift = shift;
@@ -1541,8 +1601,6 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
     st->varying = varying;
     st->n_var = n_var;
     st->n_series = 0;
-    for (int p = 0; p < st->n_procs; p++)
-        proc_stats(st, p);
     gather_stats(st);
     return 0;
 }
