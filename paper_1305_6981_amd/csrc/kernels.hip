@@ -815,12 +815,15 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             ++pos;
         }
         __syncthreads();
-        // This tile's attempts, split into 256 consecutive runs.
+        // This tile's attempts, split into 256 consecutive runs whose lengths differ by
+        // at most one (the longer runs first), so no wavefront idles lanes at the end.
         const unsigned long long lo_t = off_c + j * tile;
         const unsigned long long hi_t = (lo_t + tile < off_c + nw_c) ? lo_t + tile : off_c + nw_c;
-        const unsigned long long per = (hi_t - lo_t + 255) / 256;
-        unsigned long long at = lo_t + (unsigned long long)t * per;
-        const unsigned long long at_end = (at + per < hi_t) ? at + per : hi_t;
+        const unsigned long long n_t = hi_t - lo_t;   // <= tile <= 2^20
+        const unsigned long long q_t = n_t >> 8, r_t = n_t & 255ull;
+        const unsigned long long tt = (unsigned long long)t;
+        unsigned long long at = lo_t + tt * q_t + (tt < r_t ? tt : r_t);
+        const unsigned long long at_end = at + q_t + (tt < r_t ? 1ull : 0ull);
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
         const bool c1 = d.n_class == 2;          // no point group: classes are the spins
         ClassView<true> cv1{d.valid, nullptr};
