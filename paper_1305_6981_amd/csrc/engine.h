@@ -37,6 +37,7 @@ struct ChunkStat {
     double num;
 };
 constexpr int CNT_SHIFT_MERGED = 21, CNT_SHIFT_ND = 42;
+constexpr int POST_WAVES = 4;   // wavefronts of a k_post workgroup; one ChunkStat share each
 constexpr uint64_t CNT_FIELD = (1ull << 21) - 1;
 
 // One workgroup's share of a system's iteration statistics.
@@ -88,7 +89,7 @@ struct EngineArgs {
     unsigned long long *chunk_nw;    // sum |C| per chunk (this iteration's attempts)
     unsigned long long *chunk_off;   // exclusive scan of chunk_nw
     unsigned long long *chunk_toff;  // exclusive scan of the spawn tiles of each chunk
-    ChunkStat *chunk_stat;
+    ChunkStat *chunk_stat;           // [chunks][POST_WAVES]
     unsigned long long *blk;         // [4][SCAN_G]: per chunk range sum |C|, tiles, and their
                                      // exclusive scans
     FinPart *fin_part;               // [max_sys][FIN_BLOCKS]

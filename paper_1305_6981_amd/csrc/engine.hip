@@ -267,7 +267,7 @@ int relayout(fciqmc_t *h) {
         HIP_TRY(hipMalloc(&h->d_chunk_nw, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_off, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_toff, na * sizeof(unsigned long long)));
-        HIP_TRY(hipMalloc(&h->d_chunk_stat, na * sizeof(ChunkStat)));
+        HIP_TRY(hipMalloc(&h->d_chunk_stat, na * POST_WAVES * sizeof(ChunkStat)));
         h->chunk_alloc = na;
         drop_graphs(h);
     }

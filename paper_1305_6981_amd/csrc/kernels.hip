@@ -961,8 +961,6 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ double s_hpp[64];
     __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ int s_qn;
-    __shared__ long long s_red[4][3];
-    __shared__ double s_redd[4];
     __shared__ unsigned int s_next;
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -1075,27 +1073,15 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             if (a23.x | a23.y) gstore_i4(d.acc + base + 2, 0, 0, 0, 0);
         }
         // fixed-order reduction: lane butterfly, then waves 0..3
+        // fixed-order reduction per wavefront (lane butterfly); each wavefront writes its
+        // own share of the chunk
         nw = wave_sum((long long)nw);
         aborted = wave_sum((long long)aborted);
         cnt = wave_sum((unsigned long long)cnt);
         num = wave_sum(num);
-        if (lane == 0) {
-            s_red[wid][0] = nw;
-            s_red[wid][1] = aborted;
-            s_red[wid][2] = (long long)cnt;
-            s_redd[wid] = num;
-        }
-        __syncthreads();
-        if (t == 0) {
-            ChunkStat cs{0, 0, 0ull, 0.0};
-            for (int w = 0; w < 4; ++w) {
-                cs.nw += s_red[w][0];
-                cs.aborted += s_red[w][1];
-                cs.counts += (uint64_t)s_red[w][2];
-                cs.num = cs.num + s_redd[w];
-            }
-            a.chunk_stat[c] = cs;
-        }
+        if (lane == 0) a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
+        // every wavefront has queued its new determinants before the queue test of the
+        // next chunk, which must see the same count in all of them
         __syncthreads();
     }
     if (loaded >= 0 && s_qn > 0) flush_new_dets(desc[loaded], s_queue, s_qn, s_hpp, s_jk);
@@ -1118,13 +1104,15 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
     int64_t nw = 0, nd = 0, merged = 0, aborted = 0, att = 0, used = 0;
     double num = 0.0;
     for (int64_t i = lo + t; i < hi; i += 256) {
-        const ChunkStat cs = a.chunk_stat[d.gchunk0 + i];
-        used += (int64_t)(cs.counts & CNT_FIELD);
-        merged += (int64_t)((cs.counts >> CNT_SHIFT_MERGED) & CNT_FIELD);
-        nd += (int64_t)(cs.counts >> CNT_SHIFT_ND);
-        nw += cs.nw;
-        aborted += cs.aborted;
-        num = num + cs.num;
+        for (int w = 0; w < POST_WAVES; ++w) {
+            const ChunkStat cs = a.chunk_stat[(d.gchunk0 + i) * POST_WAVES + w];
+            used += (int64_t)(cs.counts & CNT_FIELD);
+            merged += (int64_t)((cs.counts >> CNT_SHIFT_MERGED) & CNT_FIELD);
+            nd += (int64_t)(cs.counts >> CNT_SHIFT_ND);
+            nw += cs.nw;
+            aborted += cs.aborted;
+            num = num + cs.num;
+        }
         att += (int64_t)a.chunk_nw[d.gchunk0 + i];
     }
     FinPart p;
@@ -1198,6 +1186,7 @@ __global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
 
 static_assert(FIN_BLOCKS == 64, "k_finalize sums one share per lane of a wavefront");
 static_assert(SCAN_G == 2048, "k_scan takes two range totals per thread of 1024");
+static_assert(POST_WAVES * 64 == 256, "one ChunkStat share per wavefront of a k_post workgroup");
 
 void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStream_t s,
                       hipEvent_t *ev) {
