@@ -33,10 +33,10 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: 32-bit vector lane-operations per second
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Algorithmic 32-bit lane-operations of one spawning attempt (itemised in the design doc):
-# three Philox4x32-10 blocks (300), index draws (18), excitation selection (126),
-# Slater-Condon double element (26), pgen (15), acceptance (16).
-OPS_PER_ATTEMPT = 500
+# Algorithmic 32-bit lane-operations of one spawning attempt: one Philox4x32-10 block (100),
+# type decision and acceptance rescaling (5), three index draws (3), excitation selection
+# (126), Slater-Condon double element (26), pgen (15), acceptance (16).
+OPS_PER_ATTEMPT = 290
 PROFILES = os.path.join(ROOT, "profiles")
 KERNELS = ["k_chunk_sum", "k_scan", "k_spawn", "k_post", "k_finalize"]
 
@@ -86,7 +86,7 @@ def grow(F, solver, target, log_every=40):
 
 
 def bytes_per_kernel(rec, n_slots):
-    """Algorithmic HBM bytes of one launch of each kernel (per-unit figures in the design notes)."""
+    """Algorithmic HBM bytes of one launch of each kernel, from per-slot and per-spawn figures."""
     nd, spawns, merged = rec["n_dets"], rec["spawns"], rec["merged"]
     return {
         # read the population of every slot of the table

@@ -31,9 +31,12 @@
  *     the thread count (integer merges, determinant-keyed random numbers),
  *     except the rounding order of the projected-energy numerator sum.
  *
- * Readings where the paper is silent (each listed in the design notes):
+ * Readings where the paper is silent:
  *   RNG = Philox4x32-10 (Salmon et al., SC'11) keyed by the seed, with a
- *   counter built from (determinant, walker ordinal, iteration, block);
+ *   counter built from (determinant, walker ordinal, iteration, block); a
+ *   spawning attempt uses one block: word 0 picks the type and, rescaled
+ *   within the chosen type's probability interval, is the acceptance uniform;
+ *   words 1-3 pick the orbitals (index = floor(w n / 2^32));
  *   the a/b orbitals are picked by enumerating the allowed set (the paper's
  *   stated alternative to drawing with rejection; same pgen); initiator =
  *   |C| > n_a or the reference; the merged spawn flag is the OR of parents'
@@ -123,6 +126,24 @@ static double unit_uniform(uint64_t x)
     return (double)(x >> 11) * (1.0 / 9007199254740992.0);
 }
 
+/* The four 32-bit words of one Philox block, for a spawning attempt: word 0
+ * decides the type (and, rescaled, the acceptance), words 1-3 the orbitals. */
+static void draw_words(uint64_t seed, uint64_t det, uint32_t k, int64_t iter, uint32_t block,
+                       uint32_t w[4])
+{
+    uint32_t ctr[4], key[2];
+    ctr[0] = (uint32_t)det;
+    ctr[1] = (uint32_t)(det >> 32);
+    ctr[2] = k;
+    ctr[3] = ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block;
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    orc_philox4x32_10(ctr, key, w);
+}
+
+/* w / 2^32, exact in double. */
+static double unit_uniform32(uint32_t w) { return (double)w * (1.0 / 4294967296.0); }
+
 /* Natural logarithm used by the shift update. Method: write x = m 2^e with
  * m in (1/sqrt2, sqrt2], then ln x = e ln2 + 2 atanh(z), z = (m-1)/(m+1),
  * with the odd series of atanh summed by Horner's rule up to z^25
@@ -150,9 +171,10 @@ double orc_log(double x)
 }
 
 /* Uniform index in [0, n): floor(x * n / 2^64). */
-static uint64_t uniform_index(uint64_t x, uint64_t n)
+/* floor(w n / 2^32): an index in [0, n) (bias below n / 2^32). */
+static uint64_t uniform_index32(uint32_t w, uint64_t n)
 {
-    return (uint64_t)(((unsigned __int128)x * (unsigned __int128)n) >> 64);
+    return ((uint64_t)w * n) >> 32;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -212,6 +234,7 @@ typedef struct {
     int n_class;
     int class_of[64];
     double p_double, p_single;
+    double inv_p_double, inv_p_single;   /* 1/P_double, 1/P_single (0 when the type is impossible) */
     uint64_t d0;
     double e0;
 } sys_t;
@@ -395,15 +418,15 @@ typedef struct {
     double hel;
 } excit_t;
 
-/* One excitation from the three choice draws x[1..3] and the type draw x[0]. */
-static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], excit_t *out)
+/* One excitation from the type word w[0] and the choice words w[1..3]. */
+static void gen_excit(const sys_t *s, const detinfo_t *di, const uint32_t w[4], excit_t *out)
 {
     const int N = di->n;
     const uint64_t det = di->det;
     out->det = 0;
     out->pgen = 0.0;
     out->hel = 0.0;
-    int is_double = unit_uniform(x[0]) < s->p_double;
+    int is_double = unit_uniform32(w[0]) < s->p_double;
     if (!is_double) {
         /* Sec. 5.1: renormalise over the electrons that have an allowed a. */
         int n_allow[64], delta_s = 0;
@@ -414,7 +437,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], 
         }
         if (N - delta_s == 0)
             return;
-        uint64_t ke = uniform_index(x[1], (uint64_t)(N - delta_s));
+        uint64_t ke = uniform_index32(w[1], (uint64_t)(N - delta_s));
         int esel = -1;
         for (int e = 0; e < N; e++) {
             if (n_allow[e] == 0)
@@ -427,7 +450,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], 
         }
         int p = di->occ[esel];
         int cls = s->class_of[p];
-        uint64_t ka = uniform_index(x[2], (uint64_t)n_allow[esel]);
+        uint64_t ka = uniform_index32(w[2], (uint64_t)n_allow[esel]);
         int a = -1;
         for (int r = 0; r < s->n_so; r++) {
             if (((det >> r) & 1u) || s->class_of[r] != cls)
@@ -447,7 +470,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], 
     if (N < 2)
         return;
     int64_t n_pairs = (int64_t)N * (N - 1) / 2;
-    int64_t K = (int64_t)uniform_index(x[1], (uint64_t)n_pairs);
+    int64_t K = (int64_t)uniform_index32(w[1], (uint64_t)n_pairs);
     int j = 1;
     while ((int64_t)(j + 1) * j / 2 <= K)
         j++;
@@ -467,7 +490,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], 
     }
     if (n_a_set - delta_d == 0)
         return;
-    uint64_t ka = uniform_index(x[2], (uint64_t)(n_a_set - delta_d));
+    uint64_t ka = uniform_index32(w[2], (uint64_t)(n_a_set - delta_d));
     int a = -1;
     for (int r = 0; r < s->n_so; r++) {
         if ((det >> r) & 1u)
@@ -483,7 +506,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint64_t x[4], 
         ka--;
     }
     int nba = n_partner(s, di, p, q, a);
-    uint64_t kb = uniform_index(x[3], (uint64_t)nba);
+    uint64_t kb = uniform_index32(w[3], (uint64_t)nba);
     int b = -1;
     for (int r = 0; r < s->n_so; r++) {
         if ((det >> r) & 1u)
@@ -925,6 +948,8 @@ static int sys_init(sys_t *s, const orc_ham *h)
         s->p_double = (ns + nd) > 0 ? (double)nd / (double)(ns + nd) : 0.0;
     }
     s->p_single = 1.0 - s->p_double;
+    s->inv_p_double = s->p_double > 0.0 ? 1.0 / s->p_double : 0.0;
+    s->inv_p_single = s->p_single > 0.0 ? 1.0 / s->p_single : 0.0;
     return 0;
 }
 
@@ -1160,26 +1185,24 @@ static int proc_spawn_death(orc_state *st, int p)
         uint32_t flag = (uint32_t)is_initiator(st, D, C);
         det_setup(s, D, &di);
         for (int64_t k = 0; k < absC; k++) {
-            uint64_t x[5], b[2];
-            draw_block(st->prm.seed, D, (uint32_t)k, it, 0, b);
-            x[0] = b[0];
-            x[1] = b[1];
-            draw_block(st->prm.seed, D, (uint32_t)k, it, 1, b);
-            x[2] = b[0];
-            x[3] = b[1];
+            uint32_t w[4];
+            draw_words(st->prm.seed, D, (uint32_t)k, it, 0, w);
             excit_t ex;
-            gen_excit(s, &di, x, &ex);
+            gen_excit(s, &di, w, &ex);
             attempts++;
             if (!ex.det || ex.hel == 0.0)
                 continue;
-            draw_block(st->prm.seed, D, (uint32_t)k, it, 2, b);
-            x[4] = b[0];
+            /* The acceptance uniform is the type word's uniform rescaled within the
+             * chosen type's interval: given the type it is uniform on [0, 1) and
+             * independent of the orbital words. */
+            double u = unit_uniform32(w[0]);
+            double ua = u < s->p_double ? u * s->inv_p_double : (u - s->p_double) * s->inv_p_single;
             /* Eq. pspawn: integer part created deterministically, fraction stochastically. */
             double ps = (tau * fabs(ex.hel)) / ex.pgen;
             double fl = floor(ps);
             if (fl > 1073741824.0)
                 return fail("oracle: spawn count overflow");
-            int64_t m = (int64_t)fl + (unit_uniform(x[4]) < ps - fl ? 1 : 0);
+            int64_t m = (int64_t)fl + (ua < ps - fl ? 1 : 0);
             if (m == 0)
                 continue;
             int64_t sgn = ((C > 0) ? 1 : -1) * (ex.hel > 0.0 ? 1 : -1);
@@ -1637,15 +1660,10 @@ int orc_sample_excitations(const orc_state *st, uint64_t det, int64_t iteration,
     detinfo_t di;
     det_setup(&st->sys, det, &di);
     for (int64_t k = 0; k < n_samples; k++) {
-        uint64_t x[4], b[2];
-        draw_block(st->prm.seed, det, (uint32_t)k, iteration, 0, b);
-        x[0] = b[0];
-        x[1] = b[1];
-        draw_block(st->prm.seed, det, (uint32_t)k, iteration, 1, b);
-        x[2] = b[0];
-        x[3] = b[1];
+        uint32_t w[4];
+        draw_words(st->prm.seed, det, (uint32_t)k, iteration, 0, w);
         excit_t ex;
-        gen_excit(&st->sys, &di, x, &ex);
+        gen_excit(&st->sys, &di, w, &ex);
         out_det[k] = ex.det;
         out_pgen[k] = ex.pgen;
         out_hel[k] = ex.hel;

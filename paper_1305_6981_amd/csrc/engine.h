@@ -54,6 +54,7 @@ struct SysDesc {
     int32_t active, M, N, n_so;
     int32_t A, n_a, n_class, pad1;  // n_class: 2 x (largest irrep label + 1)
     double tau, zeta, e0, e_core, p_double, p_single;
+    double inv_p_double, inv_p_single;   // 1/P_double, 1/P_single (0 when the type is impossible)
     int64_t target;
     uint64_t seed, d0, valid;
     uint64_t cmask[NCLASS];

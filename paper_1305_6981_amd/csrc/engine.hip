@@ -590,6 +590,8 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     d.e_core = S.e_core;
     d.p_double = S.p_double;
     d.p_single = 1.0 - S.p_double;
+    d.inv_p_double = d.p_double > 0.0 ? 1.0 / d.p_double : 0.0;
+    d.inv_p_single = d.p_single > 0.0 ? 1.0 / d.p_single : 0.0;
     d.target = prm->target_walkers;
     d.seed = prm->seed;
     d.d0 = S.d0;

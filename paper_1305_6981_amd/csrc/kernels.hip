@@ -60,13 +60,23 @@ __device__ __forceinline__ double u01(uint64_t x) {
     return (double)(x >> 11) * (1.0 / 9007199254740992.0);
 }
 
-// floor(x * n / 2^64) for n < 2^31, from two 32x32->64 products: with
-// x n = hi 2^32 + lo, the result is (hi + (lo >> 32)) >> 32 exactly.
-__device__ __forceinline__ uint32_t pick(uint64_t x, uint32_t n) {
-    const uint64_t lo = (uint64_t)(uint32_t)x * (uint64_t)n;
-    const uint64_t hi = (uint64_t)(uint32_t)(x >> 32) * (uint64_t)n;
-    return (uint32_t)((hi + (lo >> 32)) >> 32);
+// The four words of one Philox block of a spawning attempt: word 0 picks the
+// type and, rescaled within the chosen type's interval, is the acceptance
+// uniform; words 1-3 pick the orbitals.
+__device__ __forceinline__ uint4 draw_words(uint64_t seed, uint64_t det, uint32_t k, int64_t iter,
+                                            uint32_t block) {
+    const uint4 ctr = make_uint4((uint32_t)det, (uint32_t)(det >> 32), k,
+                                 ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block);
+    return philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
 }
+
+// w / 2^32, exact in double.
+__device__ __forceinline__ double u01_32(uint32_t w) {
+    return (double)w * (1.0 / 4294967296.0);
+}
+
+// floor(w n / 2^32): an index in [0, n).
+__device__ __forceinline__ uint32_t pick(uint32_t w, uint32_t n) { return __umulhi(w, n); }
 
 // Position of the k-th (0-based) set bit of x, by halving with popcounts.
 __device__ __forceinline__ int select_bit(uint64_t x, uint32_t k) {
@@ -283,12 +293,12 @@ struct ClassView {
     }
 };
 
-// Single excitation (Sec. 5.1) from the electron draw x1 and the hole draw x2:
+// Single excitation (Sec. 5.1) from the electron word w1 and the hole word w2:
 // renormalised over the electrons that have an allowed target. Returns false
 // for a null excitation; otherwise the child, pgen and the orbitals p -> a.
 template <bool C1>
 __device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<C1> &cv,
-                                              uint64_t det, uint64_t x1, uint64_t x2, Excit &ex) {
+                                              uint64_t det, uint32_t w1, uint32_t w2, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int n_class = C1 ? 2 : d.n_class;
     uint64_t movable = 0;
@@ -298,10 +308,10 @@ __device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<
     }
     const uint32_t nmov = (uint32_t)__popcll(movable);
     if (nmov == 0) return false;
-    const int p = select_bit(movable, pick(x1, nmov));
+    const int p = select_bit(movable, pick(w1, nmov));
     const uint64_t tg = emp & cv.mask(cv.cls(d, p));
     const uint32_t nal = (uint32_t)__popcll(tg);
-    const int a = select_bit(tg, pick(x2, nal));
+    const int a = select_bit(tg, pick(w2, nal));
     ex.det = det ^ (1ull << p) ^ (1ull << a);
     ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
     ex.p = p;
@@ -311,28 +321,28 @@ __device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<
 
 constexpr int EX_NULL = 0, EX_OK = 1, EX_SINGLE_DEFERRED = 2;
 
-// One excitation from the draws x0 (type), x1 (electron or pair), x2, x3
-// (holes). recip[k] = 1.0 / k, filled by IEEE division (same bits as dividing
-// in place). With defer_single a single excitation is only recognised
-// (EX_SINGLE_DEFERRED): the caller queues its draws and generates it later, so
-// the rare singles do not make whole wavefronts run the single path.
+// One excitation from the words of one Philox block: w.x (type), w.y
+// (electron or pair), w.z, w.w (holes). recip[k] = 1.0 / k, filled by IEEE
+// division (same bits as dividing in place). With defer_single a single
+// excitation is only recognised (EX_SINGLE_DEFERRED): the caller queues its
+// words and generates it later, so the rare singles do not make whole
+// wavefronts run the single path.
 template <bool C1>
 __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv, uint64_t det,
-                                      uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3,
-                                      const double *recip, bool defer_single, Excit &ex) {
+                                      uint4 w, const double *recip, bool defer_single, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int N = d.N;
     const int n_class = C1 ? 2 : d.n_class;
-    if (!(u01(x0) < d.p_double)) {
+    if (!(u01_32(w.x) < d.p_double)) {
         if (defer_single) return EX_SINGLE_DEFERRED;
-        if (!excite_single(d, cv, det, x1, x2, ex)) return EX_NULL;
+        if (!excite_single(d, cv, det, w.y, w.z, ex)) return EX_NULL;
         ex.hel = hel_single(d, det, ex.p, ex.a);
         return EX_OK;
     }
     // Double (Sec. 5.2): a unique pair by inverse triangular indexing.
     if (N < 2) return EX_NULL;
     const uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
-    const int64_t K = (int64_t)pick(x1, npairs);
+    const int64_t K = (int64_t)pick(w.y, npairs);
     // estimate, then exact integer correction
     int j = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)K)) * 0.5f);
     while ((int64_t)j * (j - 1) / 2 > K) --j;
@@ -354,12 +364,12 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
     }
     const uint32_t nal = (uint32_t)__popcll(allowed);
     if (nal == 0) return EX_NULL;
-    const int a = select_bit(allowed, pick(x2, nal));
+    const int a = select_bit(allowed, pick(w.z, nal));
     const int ca = cv.cls(d, a);
     const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
     const uint64_t bset = emp & cv.mask(pca) & ~(1ull << a);
     const uint32_t nba = (uint32_t)__popcll(bset);
-    const int b = select_bit(bset, pick(x3, nba));
+    const int b = select_bit(bset, pick(w.w, nba));
     const int cb = cv.cls(d, b);
     const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
     const int nbb = __popcll(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
@@ -601,11 +611,11 @@ __device__ __forceinline__ bool acc_initiator(long long x) {
 // table is a chain of HBM round trips, overlapped with the other workgroups'
 // spawning).
 struct SingleItem {
-    uint64_t D;        // source determinant
-    uint64_t x1, x2;   // electron and hole draws
-    uint64_t x4;       // acceptance draw
-    int32_t C;         // source population (sign)
-    uint32_t init;     // initiator flag of the source
+    uint64_t D;          // source determinant
+    uint32_t w0, w1, w2; // type/acceptance, electron and hole words
+    int32_t C;           // source population (sign)
+    uint32_t init;       // initiator flag of the source
+    uint32_t pad;
 };
 
 constexpr int SPAWN_GRAB = 4;    // spawn tiles per dynamic grab (one counter serves the chip)
@@ -614,7 +624,15 @@ constexpr int SPW_QUEUE = 256;
 constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
 constexpr int SPW_DRAIN = 128;
 
-__device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double pgen, uint64_t x4,
+// The acceptance uniform: the type word's uniform rescaled within the chosen
+// type's interval [0, P_double) or [P_double, 1); given the type it is uniform
+// on [0, 1) and independent of the orbital words.
+__device__ __forceinline__ double accept_uniform(const SysDesc &d, uint32_t w0) {
+    const double u = u01_32(w0);
+    return u < d.p_double ? u * d.inv_p_double : (u - d.p_double) * d.inv_p_single;
+}
+
+__device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double pgen, double ua,
                                           int32_t C, uint32_t *status) {
     const double pr = (d.tau * fabs(hel)) / pgen;
     const double fl = floor(pr);
@@ -622,7 +640,7 @@ __device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double p
         atomicOr(status, ST_SPAWN_OVERFLOW);
         return 0;
     }
-    const int32_t m = (int32_t)fl + (u01(x4) < pr - fl ? 1 : 0);
+    const int32_t m = (int32_t)fl + (ua < pr - fl ? 1 : 0);
     return ((C > 0) == (hel > 0.0)) ? -m : m;
 }
 
@@ -654,12 +672,12 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         const SingleItem it = Q.sgl[j];
         Excit ex;
         const bool ok = d.n_class == 2
-                            ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.x1, it.x2, ex)
-                            : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.x1, it.x2, ex);
+                            ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.w1, it.w2, ex)
+                            : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.w1, it.w2, ex);
         if (!ok) continue;
         const double hel = hel_single(d, it.D, ex.p, ex.a);
         if (hel == 0.0) continue;
-        const int32_t v = accept(d, hel, ex.pgen, it.x4, it.C, status);
+        const int32_t v = accept(d, hel, ex.pgen, accept_uniform(d, it.w0), it.C, status);
         if (v == 0) continue;
         ++spawned;
         const uint64_t Dn = ex.det;
@@ -842,29 +860,26 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                 const uint64_t D = s_det[sl];
                 const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
                 const bool init = absC > d.n_a || D == d.d0;
-                uint64_t x0, x1, x2, x3, x4, x5;
-                draw2(d.seed, D, k, d.iter, 0u, x0, x1);
-                draw2(d.seed, D, k, d.iter, 1u, x2, x3);
-                draw2(d.seed, D, k, d.iter, 2u, x4, x5);
+                const uint4 w = draw_words(d.seed, D, k, d.iter, 0u);
                 Excit ex;
-                int r = c1 ? excite(d, cv1, D, x0, x1, x2, x3, s_recip, defer, ex)
-                           : excite(d, cvg, D, x0, x1, x2, x3, s_recip, defer, ex);
+                int r = c1 ? excite(d, cv1, D, w, s_recip, defer, ex)
+                           : excite(d, cvg, D, w, s_recip, defer, ex);
                 if (r == EX_SINGLE_DEFERRED) {
                     const int q = atomicAdd(&Q.nsgl, 1);
                     if (q < SGL_QUEUE) {
-                        Q.sgl[q] = SingleItem{D, x1, x2, x4, C, init ? 1u : 0u};
+                        Q.sgl[q] = SingleItem{D, w.x, w.y, w.z, C, init ? 1u : 0u, 0u};
                         r = EX_NULL;
                     } else {
                         // queue full: generate it here
-                        const bool ok = c1 ? excite_single(d, cv1, D, x1, x2, ex)
-                                           : excite_single(d, cvg, D, x1, x2, ex);
+                        const bool ok = c1 ? excite_single(d, cv1, D, w.y, w.z, ex)
+                                           : excite_single(d, cvg, D, w.y, w.z, ex);
                         r = ok ? EX_OK : EX_NULL;
                         if (ok) ex.hel = hel_single(d, D, ex.p, ex.a);
                     }
                 }
                 if (r == EX_OK) {
                     if (ex.hel != 0.0) {
-                        const int32_t v = accept(d, ex.hel, ex.pgen, x4, C, status);
+                        const int32_t v = accept(d, ex.hel, ex.pgen, accept_uniform(d, w.x), C, status);
                         if (v != 0) {
                             ++spawned;
                             const int q = atomicAdd(&Q.nspw, 1);
