@@ -87,12 +87,15 @@ struct EngineArgs {
     unsigned long long *spawns;      // descriptors) and spawning events of the iteration
     const int32_t *chunk_sys;        // system of each global chunk (-1: unused)
     const int32_t *chunk_local;      // chunk index inside its system's table
-    unsigned long long *chunk_nw;    // sum |C| per chunk (this iteration's attempts)
+    unsigned long long *chunk_nw;    // [2][chunk_cap] sum |C| per chunk: this iteration's
+                                     // attempts in half (step & 1), the next one's in the other
+    int64_t chunk_cap;
+    unsigned long long *step;        // iterations run by this handle (selects the halves)
     unsigned long long *chunk_off;   // exclusive scan of chunk_nw
     unsigned long long *chunk_toff;  // exclusive scan of the spawn tiles of each chunk
     ChunkStat *chunk_stat;           // [chunks][POST_WAVES]
-    unsigned long long *blk;         // [4][SCAN_G]: per chunk range sum |C|, tiles, and their
-                                     // exclusive scans
+    unsigned long long *blk;         // [2][4][SCAN_G]: per chunk range sum |C|, tiles, and
+                                     // their exclusive scans, halves selected like chunk_nw
     FinPart *fin_part;               // [max_sys][FIN_BLOCKS]
     int64_t *c0;                     // [max_sys] population on the reference after the iteration
     unsigned long long *total;       // [0] total attempts, [1] total spawn tiles
@@ -102,8 +105,10 @@ struct EngineArgs {
 
 // Kernel launchers (kernels.hip).
 constexpr int NKERN = 5;   // profiled kernel groups: chunk sums, scans, spawn, post, finalize
-void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStream_t s,
-                      hipEvent_t *ev /* NKERN + 1 events or nullptr */);
+// first: the chunk sums are taken from the tables (the first iteration of a launch, after
+// any host-side change); later iterations use the sums the previous iteration's k_post wrote.
+void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool first,
+                      hipStream_t s, hipEvent_t *ev /* NKERN + 1 events or nullptr */);
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
                        int64_t n, uint32_t *d_err, hipStream_t s);
 hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,

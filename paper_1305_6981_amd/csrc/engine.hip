@@ -178,7 +178,8 @@ struct fciqmc_t {
     unsigned long long *d_chunk_nw = nullptr, *d_chunk_off = nullptr, *d_total = nullptr;
     unsigned long long *d_chunk_toff = nullptr;
     ChunkStat *d_chunk_stat = nullptr;
-    unsigned long long *d_blk = nullptr;    // [4][SCAN_G] range sums and scans
+    unsigned long long *d_blk = nullptr;    // [2][4][SCAN_G] range sums and scans
+    unsigned long long *d_step = nullptr;   // iterations run (selects the halves of the sums)
     FinPart *d_fin = nullptr;               // [max_sys][FIN_BLOCKS]
     int64_t *d_c0 = nullptr;                // [max_sys]
     int64_t *d_nchunks = nullptr;
@@ -204,6 +205,8 @@ EngineArgs make_args(fciqmc_t *h) {
     a.chunk_sys = h->d_chunk_sys;
     a.chunk_local = h->d_chunk_local;
     a.chunk_nw = h->d_chunk_nw;
+    a.chunk_cap = h->chunk_alloc;
+    a.step = h->d_step;
     a.chunk_off = h->d_chunk_off;
     a.chunk_toff = h->d_chunk_toff;
     a.chunk_stat = h->d_chunk_stat;
@@ -264,7 +267,7 @@ int relayout(fciqmc_t *h) {
         h->chunk_alloc = 0;
         HIP_TRY(hipMalloc(&h->d_chunk_sys, na * sizeof(int32_t)));
         HIP_TRY(hipMalloc(&h->d_chunk_local, na * sizeof(int32_t)));
-        HIP_TRY(hipMalloc(&h->d_chunk_nw, na * sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc(&h->d_chunk_nw, 2 * na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_off, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_toff, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_stat, na * POST_WAVES * sizeof(ChunkStat)));
@@ -761,7 +764,8 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     EngineArgs a = make_args(h);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
-    for (int i = 0; i < L; ++i) launch_iteration(a, h->post_grid, h->spawn_grid, h->stream, nullptr);
+    for (int i = 0; i < L; ++i)
+        launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
     HIP_TRY(hipStreamEndCapture(h->stream, &g));
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
@@ -809,7 +813,7 @@ int run_iterations(fciqmc_t *h, int L) {
     EngineArgs a = make_args(h);
     if (h->profiling) {
         for (int i = 0; i < L; ++i) {
-            launch_iteration(a, h->post_grid, h->spawn_grid, h->stream, h->ev);
+            launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, h->ev);
             HIP_TRY(hipEventSynchronize(h->ev[NKERN]));
             for (int k = 0; k < NKERN; ++k) {
                 float ms = 0.f;
@@ -825,7 +829,8 @@ int run_iterations(fciqmc_t *h, int L) {
         if (rc) return rc;
         HIP_TRY(hipGraphLaunch(ex, h->stream));
     } else {
-        for (int i = 0; i < L; ++i) launch_iteration(a, h->post_grid, h->spawn_grid, h->stream, nullptr);
+        for (int i = 0; i < L; ++i)
+        launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -929,7 +934,9 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_rec, sizeof(IterRecord) * REC_CAP * max_slots));
     HIP_TRY(hipMalloc(&h->d_total, 2 * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
-    HIP_TRY(hipMalloc(&h->d_blk, 4 * SCAN_G * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_blk, 2 * 4 * SCAN_G * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_step, sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(h->d_step, 0, sizeof(unsigned long long), h->stream));
     HIP_TRY(hipMalloc(&h->d_fin, sizeof(FinPart) * FIN_BLOCKS * max_slots));
     HIP_TRY(hipMalloc(&h->d_c0, sizeof(int64_t) * max_slots));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
@@ -999,6 +1006,7 @@ void release(fciqmc_t *h) {
     hipFree(h->d_total);
     hipFree(h->d_nchunks);
     hipFree(h->d_blk);
+    hipFree(h->d_step);
     hipFree(h->d_fin);
     hipFree(h->d_c0);
     hipFree(h->d_err);

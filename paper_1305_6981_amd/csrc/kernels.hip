@@ -428,6 +428,15 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Halves of the chunk sums and range sums: this iteration's in (step & 1).
+__device__ __forceinline__ unsigned cur_half(const EngineArgs &a) { return (unsigned)(*a.step & 1ull); }
+__device__ __forceinline__ unsigned long long *sums(const EngineArgs &a, unsigned h) {
+    return a.chunk_nw + (h ? a.chunk_cap : 0);
+}
+__device__ __forceinline__ unsigned long long *ranges(const EngineArgs &a, unsigned h) {
+    return a.blk + (h ? 4 * SCAN_G : 0);
+}
+
 // ---------------------------------------------------------------------------
 // K1: chunk sums of |C| on the current tables. Workgroup g takes the chunks
 // [g per, (g+1) per) (per = ceil(chunks / SCAN_G)), four at a time, writes
@@ -448,6 +457,8 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
     const int tsh = __builtin_ctzll((unsigned long long)a.tile);
     const unsigned long long tm = (unsigned long long)a.tile - 1ull;
     const int t = threadIdx.x;
+    unsigned long long *const nws = sums(a, cur_half(a));
+    unsigned long long *const rg = ranges(a, cur_half(a));
     unsigned long long bs = 0, bt = 0;    // range totals, kept by thread 0
     for (int64_t c = c0; c < c1; c += 4) {
         unsigned long long v[4];
@@ -474,7 +485,7 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
         if (t == 0) {
             for (int k = 0; k < 4 && c + k < c1; ++k) {
                 const unsigned long long x = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
-                a.chunk_nw[c + k] = x;
+                nws[c + k] = x;
                 bs += x;
                 bt += (x + tm) >> tsh;
             }
@@ -482,20 +493,27 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
         __syncthreads();
     }
     if (t == 0) {
-        a.blk[blockIdx.x] = bs;
-        a.blk[SCAN_G + blockIdx.x] = bt;
+        rg[blockIdx.x] = bs;
+        rg[SCAN_G + blockIdx.x] = bt;
     }
 }
 
 // ---------------------------------------------------------------------------
 // K2a: exclusive scan of the SCAN_G range totals (one workgroup, two per
-// thread); also resets the dynamic work counters of the spawn and post kernels.
+// thread); also resets the dynamic work counters of the spawn and post kernels
+// and the range sums that k_post accumulates for the next iteration.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
     __shared__ unsigned long long part[1024], tpart[1024];
     const int t = threadIdx.x;
-    const unsigned long long s0 = a.blk[2 * t], s1 = a.blk[2 * t + 1];
-    const unsigned long long t0 = a.blk[SCAN_G + 2 * t], t1 = a.blk[SCAN_G + 2 * t + 1];
+    unsigned long long *const rg = ranges(a, cur_half(a));
+    unsigned long long *const rn = ranges(a, cur_half(a) ^ 1u);
+    rn[2 * t] = 0ull;
+    rn[2 * t + 1] = 0ull;
+    rn[SCAN_G + 2 * t] = 0ull;
+    rn[SCAN_G + 2 * t + 1] = 0ull;
+    const unsigned long long s0 = rg[2 * t], s1 = rg[2 * t + 1];
+    const unsigned long long t0 = rg[SCAN_G + 2 * t], t1 = rg[SCAN_G + 2 * t + 1];
     part[t] = s0 + s1;
     tpart[t] = t0 + t1;
     __syncthreads();
@@ -508,10 +526,10 @@ __global__ __launch_bounds__(1024) void k_scan(EngineArgs a) {
         __syncthreads();
     }
     const unsigned long long run = part[t] - (s0 + s1), trun = tpart[t] - (t0 + t1);
-    a.blk[2 * SCAN_G + 2 * t] = run;
-    a.blk[2 * SCAN_G + 2 * t + 1] = run + s0;
-    a.blk[3 * SCAN_G + 2 * t] = trun;
-    a.blk[3 * SCAN_G + 2 * t + 1] = trun + t0;
+    rg[2 * SCAN_G + 2 * t] = run;
+    rg[2 * SCAN_G + 2 * t + 1] = run + s0;
+    rg[3 * SCAN_G + 2 * t] = trun;
+    rg[3 * SCAN_G + 2 * t + 1] = trun + t0;
     if (t == 1023) {
         a.total[0] = part[1023];
         a.total[1] = tpart[1023];
@@ -533,11 +551,13 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
     const int tsh = __builtin_ctzll((unsigned long long)a.tile);
     const unsigned long long tm = (unsigned long long)a.tile - 1ull;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    unsigned long long base = a.blk[2 * SCAN_G + blockIdx.x];
-    unsigned long long tbase = a.blk[3 * SCAN_G + blockIdx.x];
+    const unsigned long long *const nws = sums(a, cur_half(a));
+    const unsigned long long *const rg = ranges(a, cur_half(a));
+    unsigned long long base = rg[2 * SCAN_G + blockIdx.x];
+    unsigned long long tbase = rg[3 * SCAN_G + blockIdx.x];
     for (int64_t c = c0; c < c1; c += 256) {
         const int64_t i = c + t;
-        const unsigned long long v = i < c1 ? a.chunk_nw[i] : 0ull;
+        const unsigned long long v = i < c1 ? nws[i] : 0ull;
         const unsigned long long vt = (v + tm) >> tsh;
         // inclusive scans inside the wavefront
         unsigned long long x = v, xt = vt;
@@ -773,7 +793,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         __syncthreads();
         if (tix >= n_tiles) break;
         const unsigned long long off_c = a.chunk_off[c];
-        const unsigned long long nw_c = a.chunk_nw[c];
+        const unsigned long long nw_c = sums(a, cur_half(a))[c];
         const unsigned long long j = tix - a.chunk_toff[c];
         const int s = __builtin_amdgcn_readfirstlane(a.chunk_sys[c]);
         const SysDesc &d = desc[s];
@@ -925,7 +945,9 @@ __device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t cap, u
     return -1;
 }
 
-constexpr int POST_QUEUE = 1536;  // with the 32 KiB pair table: four workgroups per CU
+constexpr int POST_QUEUE = 1536;  // new-determinant queue entries per workgroup (split over
+                                  // its wavefronts); with the 32 KiB pair table: four
+                                  // workgroups per CU
 constexpr int POST_GRAB = 4;      // chunks per dynamic grab in k_post
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
@@ -974,14 +996,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ double s_jk[64 * 64];
     __shared__ double s_hpp[64];
+    // New determinants are queued for the workgroup. Whether to flush the queue at
+    // the start of a chunk is decided by thread 0 two chunks earlier (s_flush, by
+    // the parity of the workgroup's chunk count), so every wavefront reads a value
+    // that no one is changing; a full queue makes a thread compute its own entry.
     __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ int s_qn;
+    __shared__ int s_flush[2];
     __shared__ unsigned int s_next;
+    __shared__ unsigned long long s_nwn[2][POST_WAVES];   // next-iteration sums, by chunk parity
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    // The next iteration's chunk sums (its attempts) are the new |C| totals found here:
+    // written per chunk, and added into the range sums that k_scan will read.
+    unsigned long long *const nws_next = sums(a, cur_half(a) ^ 1u);
+    unsigned long long *const rg_next = ranges(a, cur_half(a) ^ 1u);
+    const int64_t per_range = (nch + SCAN_G - 1) / SCAN_G;
+    const int tsh = __builtin_ctzll((unsigned long long)a.tile);
+    const unsigned long long tm = (unsigned long long)a.tile - 1ull;
     int loaded = -1;
-    if (t == 0) s_qn = 0;
+    if (t == 0) {
+        s_qn = 0;
+        s_flush[0] = 0;
+        s_flush[1] = 0;
+    }
     __syncthreads();
+    unsigned seq = 0;   // chunks this workgroup has processed
     // Chunks are handed out dynamically, POST_GRAB consecutive ones per atomic
     // (one counter serves the whole chip, so grabs are kept few), in order.
     int64_t c = 0, c_end = 0;
@@ -1001,9 +1041,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
         const bool live = s >= 0 && participating(desc[s], a.status[s]);   // uniform
         if (live) {
             const SysDesc &d = desc[s];
-            if (loaded != s || s_qn > POST_QUEUE - CHUNK) {
-                // flush the queue of the previous system (or a nearly full queue)
-                if (loaded >= 0 && s_qn > 0) flush_new_dets(desc[loaded], s_queue, s_qn, s_hpp, s_jk);
+            if (loaded != s || s_flush[seq & 1u]) {
+                // another system, or a queue decided to be flushed (both uniform): no
+                // wavefront is adding to the queue now
+                const int n = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
+                if (loaded >= 0 && n > 0) flush_new_dets(desc[loaded], s_queue, n, s_hpp, s_jk);
                 __syncthreads();
                 if (loaded != s) {
                     for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = gptr(d.jk)[i];
@@ -1072,7 +1114,13 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (np != 0 && p == 0 && isnan(hin[u])) {
                     // newly occupied: diagonal element computed with the queue
                     const int q = atomicAdd(&s_qn, 1);
-                    s_queue[q] = (uint32_t)(base + u);
+                    if (q < POST_QUEUE) {
+                        s_queue[q] = (uint32_t)(base + u);
+                    } else {
+                        double h, h2;
+                        hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, h, h2);
+                        *gp(d.hdiag + base + u) = h;
+                    }
                 }
                 if (D == d.d0) a.c0[s] = np;   // the reference has one slot
                 if (np != 0) {
@@ -1087,19 +1135,41 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             if (a01.x | a01.y) gstore_i4(d.acc + base, 0, 0, 0, 0);
             if (a23.x | a23.y) gstore_i4(d.acc + base + 2, 0, 0, 0, 0);
         }
-        // fixed-order reduction: lane butterfly, then waves 0..3
         // fixed-order reduction per wavefront (lane butterfly); each wavefront writes its
         // own share of the chunk
         nw = wave_sum((long long)nw);
         aborted = wave_sum((long long)aborted);
         cnt = wave_sum((unsigned long long)cnt);
         num = wave_sum(num);
-        if (lane == 0) a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
-        // every wavefront has queued its new determinants before the queue test of the
-        // next chunk, which must see the same count in all of them
+        if (lane == 0) {
+            a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
+            // walkers that spawn next iteration: none if the system stops after this one
+            const bool next = live && desc[s].iter + 1 < desc[s].stop_at;
+            s_nwn[c & 1][wid] = next ? (unsigned long long)nw : 0ull;
+        }
+        // the shares of all wavefronts are in s_nwn before thread 0 adds them up
         __syncthreads();
+        if (t == 0) {
+            // flush at the start of the chunk after next when the queue is half full
+            // (the other wavefronts may already be adding to it: the count is a bound)
+            s_flush[seq & 1u] = s_qn > POST_QUEUE / 2 ? 1 : 0;
+            // (the other wavefronts may already be on chunk c + 1, which writes the other
+            // parity of s_nwn)
+            unsigned long long x = 0ull;
+            for (int w = 0; w < POST_WAVES; ++w) x += s_nwn[c & 1][w];
+            nws_next[c] = x;
+            if (x) {
+                atomicAdd(&rg_next[c / per_range], x);
+                atomicAdd(&rg_next[SCAN_G + c / per_range], (x + tm) >> tsh);
+            }
+        }
+        ++seq;
     }
-    if (loaded >= 0 && s_qn > 0) flush_new_dets(desc[loaded], s_queue, s_qn, s_hpp, s_jk);
+    __syncthreads();
+    {
+        const int n = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
+        if (loaded >= 0 && n > 0) flush_new_dets(desc[loaded], s_queue, n, s_hpp, s_jk);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,7 +1198,7 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
             aborted += cs.aborted;
             num = num + cs.num;
         }
-        att += (int64_t)a.chunk_nw[d.gchunk0 + i];
+        att += (int64_t)sums(a, cur_half(a))[d.gchunk0 + i];
     }
     FinPart p;
     p.nw = block_sum((long long)nw, shi);
@@ -1147,6 +1217,7 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
     const int s = blockIdx.x;
+    if (s == 0 && threadIdx.x == 0) *a.step += 1ull;   // every kernel of this iteration has read it
     SysDesc &d = a.desc[s];
     if (!participating(d, a.status[s])) return;   // uniform across the wavefront
     const int t = threadIdx.x;
@@ -1203,10 +1274,11 @@ static_assert(FIN_BLOCKS == 64, "k_finalize sums one share per lane of a wavefro
 static_assert(SCAN_G == 2048, "k_scan takes two range totals per thread of 1024");
 static_assert(POST_WAVES * 64 == 256, "one ChunkStat share per wavefront of a k_post workgroup");
 
-void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, hipStream_t s,
-                      hipEvent_t *ev) {
+void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool first,
+                      hipStream_t s, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipLaunchKernelGGL(k_chunk_sum, dim3(SCAN_G), dim3(256), 0, s, a, (const SysDesc *)a.desc);
+    if (first)
+        hipLaunchKernelGGL(k_chunk_sum, dim3(SCAN_G), dim3(256), 0, s, a, (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_scan_down, dim3(SCAN_G), dim3(256), 0, s, a);
