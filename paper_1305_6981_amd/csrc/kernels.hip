@@ -1,8 +1,10 @@
 // HIP kernels of the FCIQMC iteration (Booth, Smart & Alavi, arXiv:1305.6981)
-// for gfx950. One iteration of every active system is seven launches:
+// for gfx950. One iteration of every active system is six launches (seven in
+// the first iteration of a launch sequence):
 //
 //   k_chunk_sum   sum |C| over each 1024-slot chunk of the current main tables,
-//                 and over fixed contiguous ranges of chunks
+//                 and over fixed contiguous ranges of chunks (first iteration of
+//                 a launch sequence only; afterwards k_post provides the sums)
 //   k_scan        exclusive scan of the range sums (one workgroup)
 //   k_scan_down   per chunk: global attempt offset and spawn-tile offset
 //   k_spawn       one spawning attempt per walker (Sec. 2, Eq. pspawn): random
@@ -14,7 +16,8 @@
 //                 of the arrived walkers with the initiator test for
 //                 determinants that are empty after death, the stored diagonal
 //                 element for newly occupied determinants (Sec. 4.2) from a
-//                 pair table staged in LDS; estimator partial sums (Eq. ProjE).
+//                 pair table staged in LDS; estimator partial sums (Eq. ProjE);
+//                 the next iteration's chunk and range sums of |C|.
 //                 A vacated slot keeps its key (and H_DD) until the table is
 //                 compacted, so no slot ever moves during an iteration.
 //   k_reduce      per system, 64 workgroups: fixed-order reduction of the
