@@ -244,7 +244,7 @@ def pmc_means(path, last=0):
     return out
 
 
-TRAFFIC_KERNELS = ("k_spawn", "k_post", "k_chunk_sum")
+TRAFFIC_KERNELS = ("k_spawn", "k_post")
 CALIBRATION_KERNEL = "MulFunctor"
 
 

@@ -1007,7 +1007,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ int s_qn;
     __shared__ int s_flush[2];
     __shared__ unsigned int s_next;
-    __shared__ unsigned long long s_nwn[2][POST_WAVES];   // next-iteration sums, by chunk parity
+    __shared__ unsigned long long s_nwn[2][POST_WAVES];   // next-iteration sums, by seq parity
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     // The next iteration's chunk sums (its attempts) are the new |C| totals found here:
@@ -1148,7 +1148,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
             // walkers that spawn next iteration: none if the system stops after this one
             const bool next = live && desc[s].iter + 1 < desc[s].stop_at;
-            s_nwn[c & 1][wid] = next ? (unsigned long long)nw : 0ull;
+            s_nwn[seq & 1u][wid] = next ? (unsigned long long)nw : 0ull;
         }
         // the shares of all wavefronts are in s_nwn before thread 0 adds them up
         __syncthreads();
@@ -1159,7 +1159,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             // (the other wavefronts may already be on chunk c + 1, which writes the other
             // parity of s_nwn)
             unsigned long long x = 0ull;
-            for (int w = 0; w < POST_WAVES; ++w) x += s_nwn[c & 1][w];
+            for (int w = 0; w < POST_WAVES; ++w) x += s_nwn[seq & 1u][w];
             nws_next[c] = x;
             if (x) {
                 atomicAdd(&rg_next[c / per_range], x);
