@@ -313,7 +313,8 @@ def pmc_summary(path, last=0):
 
 
 def served(F, S, n_requests, scale, max_iters, seed=5):
-    """Poisson request stream (mean 20 req/s) served with continuous batching."""
+    """Poisson request stream (mean 20 req/s) served with continuous batching; each
+    request runs to a projected-energy error bar of 1e-3 Ha or max_iters iterations."""
     from paper_1305_6981_amd import serve
     reqs = []
     for i, (t, ham, prm) in enumerate(S.serve_requests(n=n_requests, rate=20.0, seed=seed,
@@ -321,7 +322,13 @@ def served(F, S, n_requests, scale, max_iters, seed=5):
         prm.avg_start = 0
         prm.initial_walkers = max(10, prm.target_walkers // 2)
         reqs.append(serve.Request(ham, prm, arrival=t, max_iters=max_iters, tag=i))
-    srv = serve.SolveServer(max_slots=32, chunk_iters=64, tol=1e-3, min_samples=128)
+
+    def progress(r):
+        log(f"[served] request {r.tag} ({reqs[r.tag].ham.name}, target "
+            f"{reqs[r.tag].params.target_walkers}) retired after {r.iterations} iterations, "
+            f"error bar {r.e_proj_err:.2e} Ha, latency {r.latency:.1f} s")
+    srv = serve.SolveServer(max_slots=32, chunk_iters=64, tol=1e-3, min_samples=128,
+                            on_result=progress)
     stats = srv.run(reqs)
     out = stats.summary()
     out["requests_scale"] = scale
@@ -350,6 +357,9 @@ def main():
     ap.add_argument("--batched-scale", type=float, default=0.2)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=40)
+    ap.add_argument("--served-scale", type=float, default=1.0,
+                    help="walker targets of the served requests, times 1e4..1e6")
+    ap.add_argument("--served-max-iters", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="add a 1 GiB device copy in its own profiled region")
     args = ap.parse_args()
@@ -465,7 +475,8 @@ def main():
         out["batched"] = batched_vs_plain(F, S, 100, args.batched_scale)
     if not args.no_served:
         log("[bench] served Poisson stream")
-        out["served"] = served(F, S, args.served_requests, 0.1, 2000)
+        out["served"] = served(F, S, args.served_requests, args.served_scale,
+                               args.served_max_iters)
     print(json.dumps(out), flush=True)
 
 

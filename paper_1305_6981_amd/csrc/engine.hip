@@ -790,9 +790,14 @@ int plan_launch(fciqmc_t *h, int L, int *L_out) {
         const int64_t limit = S.cap * 7 / 10;
         int64_t used = std::max<int64_t>(S.last.used, S.last.nd);
         if (used + 4 * g > limit) {
-            // at least 1.5 x, and 50 % load after 8 more iterations of growth
+            // Rehash for 50 % load after 8 more iterations of growth. Vacated slots
+            // are what fills a table whose live count has levelled off, so while
+            // that load fits the present capacity the rehash only compacts (same
+            // size); otherwise it grows by at least 1.5 x.
             const int64_t live = S.last.nd + 1;
-            const int64_t nc = round_cap(std::max<int64_t>(S.cap + S.cap / 2, 2 * (live + 8 * g)));
+            const int64_t want = 2 * (live + 8 * g);
+            const int64_t nc = want <= S.cap ? S.cap
+                                             : round_cap(std::max<int64_t>(S.cap + S.cap / 2, want));
             int rc = grow_system(h, s, nc);
             if (rc) return rc;
             used = live;

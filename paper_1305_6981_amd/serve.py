@@ -69,12 +69,16 @@ class ServerStats:
                 "throughput_req_per_s": len(self.results) / max(self.wall_s, 1e-9),
                 "attempts_per_s": att / max(self.wall_s, 1e-9),
                 "converged": sum(1 for r in self.results if r.converged),
+                "e_proj_err_p50": float(np.median([r.e_proj_err for r in self.results]))
+                if self.results else float("nan"),
+                "iterations_p50": float(np.median([r.iterations for r in self.results]))
+                if self.results else 0.0,
                 "launches": self.launches, "peak_active": self.peak_active}
 
 
 class SolveServer:
     def __init__(self, max_slots=16, chunk_iters=64, tol=1e-3, min_samples=256,
-                 keep_walkers=False, stream=None, clock=time.perf_counter):
+                 keep_walkers=False, stream=None, clock=time.perf_counter, on_result=None):
         self.max_slots = max_slots
         self.chunk_iters = chunk_iters
         self.tol = tol
@@ -82,6 +86,7 @@ class SolveServer:
         self.keep_walkers = keep_walkers
         self.stream = stream if stream is not None else F.current_stream()
         self.clock = clock
+        self.on_result = on_result        # called with each Result as it is retired
 
     def run(self, requests):
         """Serve `requests` (arrival times in seconds from now); returns ServerStats."""
@@ -130,6 +135,8 @@ class SolveServer:
                             req.tag, req.arrival, adm, now, done, e["e_proj_mean"],
                             e["e_proj_err"], e["shift_mean"], e["total_attempts"], bool(conv),
                             walkers))
+                        if self.on_result is not None:
+                            self.on_result(stats.results[-1])
                         F.fciqmc_batch_retire(h, slot)
                         del active[slot]
         finally:

@@ -113,6 +113,39 @@ def test_forced_table_growth_is_result_neutral():
     _run_pair(ham, prm, blocks=3, per_block=60, tag="growth")
 
 
+def test_table_stays_bounded_under_turnover():
+    """A population that has levelled off keeps visiting new determinants; their
+    vacated slots fill the table, and the rehash that follows must compact it
+    rather than grow it without bound. The trajectory stays the oracle's.
+
+    Bound: a rehash grows only when 2(live + 8g) exceeds the capacity, to at most
+    1.5 times that, where g (new keys per iteration, 25 % slack, at least 256) is
+    at most 1.25 x the spawns of one iteration."""
+    ham = S.hubbard_ring(12, 4.0)
+    prm = S.Params(tau=0.01, initiator_threshold=3, target_walkers=4000, initial_walkers=2000,
+                   seed=3, shift_update_every=1, det_capacity=4096)
+    print("[gpu] turnover hubbard12", flush=True)
+    gpu = F.Solver(ham, prm, _stream())
+    ref = O.Oracle(ham, prm)
+    max_nd = max_sp = 0
+    for b in range(8):
+        for _ in range(5):
+            gpu.iterate(15)
+            e = gpu.estimates()
+            max_nd, max_sp = max(max_nd, e["n_dets"]), max(max_sp, e["spawns"])
+        ref.iterate(75)
+        _same_lists(gpu, ref, f"turnover{b}")
+        _same_estimates(gpu.estimates(), ref.estimates(), f"turnover{b}")
+    slots = gpu.estimates()["table_slots"]
+    g = max(256, 1.25 * 1.5 * max_sp + 1)      # spawns sampled every 15 iterations: 50 % margin
+    bound = 1.5 * 2 * (max_nd + 1 + 8 * g) + 4096
+    print(f"[gpu] turnover: slots={slots} max_nd={max_nd} max_spawns={max_sp} bound={bound:.0f}",
+          flush=True)
+    assert e["total_spawns"] > 5 * slots, "too little turnover to exercise compaction"
+    assert slots <= bound
+    gpu.close()
+
+
 def test_reserve_is_result_neutral():
     """Growing the table on request (odd sizes, mid-run, also a no-op request) changes
     nothing in the trajectory."""
