@@ -43,7 +43,9 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        // three-input XORs (0x96 is the truth table of a ^ b ^ c)
+        c = make_uint4(__builtin_amdgcn_bitop3_b32(hi1, c.y, k0, 0x96), lo1,
+                       __builtin_amdgcn_bitop3_b32(hi0, c.w, k1, 0x96), lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -81,8 +83,22 @@ __device__ __forceinline__ double u01_32(uint32_t w) {
 // floor(w n / 2^32): an index in [0, n).
 __device__ __forceinline__ uint32_t pick(uint32_t w, uint32_t n) { return __umulhi(w, n); }
 
-// Position of the k-th (0-based) set bit of x, by halving with popcounts.
-__device__ __forceinline__ int select_bit(uint64_t x, uint32_t k) {
+// Positions of the set bits of each byte value: the k-th (0-based) set bit of
+// byte b sits at bits [3k, 3k + 3) of sel8_entry(b).
+__device__ __forceinline__ uint32_t sel8_entry(uint32_t b) {
+    uint32_t e = 0, n = 0;
+    for (uint32_t i = 0; i < 8; ++i)
+        if (b & (1u << i)) {
+            e |= i << (3 * n);
+            ++n;
+        }
+    return e;
+}
+
+// Position of the k-th (0-based) set bit of x (k < popcount(x)): halving with
+// popcounts down to one byte, then that byte's entry of the table sel8 (the
+// sel8_entry values, staged in LDS).
+__device__ __forceinline__ int select_bit(uint64_t x, uint32_t k, const uint32_t *sel8) {
     int pos = 0;
     uint32_t c = (uint32_t)__popc((uint32_t)x);
     if (k >= c) {
@@ -95,13 +111,7 @@ __device__ __forceinline__ int select_bit(uint64_t x, uint32_t k) {
     if (k >= c) { k -= c; w >>= 16; pos += 16; }
     c = (uint32_t)__popc(w & 0xFFu);
     if (k >= c) { k -= c; w >>= 8; pos += 8; }
-    c = (uint32_t)__popc(w & 0xFu);
-    if (k >= c) { k -= c; w >>= 4; pos += 4; }
-    c = (uint32_t)__popc(w & 0x3u);
-    if (k >= c) { k -= c; w >>= 2; pos += 2; }
-    c = w & 1u;
-    if (k >= c) pos += 1;
-    return pos;
+    return pos + (int)((sel8[w & 0xFFu] >> (3u * k)) & 7u);
 }
 
 // 64-bit finaliser of MurmurHash3 (public domain): table placement only.
@@ -301,7 +311,8 @@ struct ClassView {
 // for a null excitation; otherwise the child, pgen and the orbitals p -> a.
 template <bool C1>
 __device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<C1> &cv,
-                                              uint64_t det, uint32_t w1, uint32_t w2, Excit &ex) {
+                                              uint64_t det, uint32_t w1, uint32_t w2,
+                                              const uint32_t *sel8, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int n_class = C1 ? 2 : d.n_class;
     uint64_t movable = 0;
@@ -311,10 +322,10 @@ __device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<
     }
     const uint32_t nmov = (uint32_t)__popcll(movable);
     if (nmov == 0) return false;
-    const int p = select_bit(movable, pick(w1, nmov));
+    const int p = select_bit(movable, pick(w1, nmov), sel8);
     const uint64_t tg = emp & cv.mask(cv.cls(d, p));
     const uint32_t nal = (uint32_t)__popcll(tg);
-    const int a = select_bit(tg, pick(w2, nal));
+    const int a = select_bit(tg, pick(w2, nal), sel8);
     ex.det = det ^ (1ull << p) ^ (1ull << a);
     ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
     ex.p = p;
@@ -332,26 +343,27 @@ constexpr int EX_NULL = 0, EX_OK = 1, EX_SINGLE_DEFERRED = 2;
 // wavefronts run the single path.
 template <bool C1>
 __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv, uint64_t det,
-                                      uint4 w, const double *recip, bool defer_single, Excit &ex) {
+                                      uint4 w, const double *recip, const uint32_t *sel8,
+                                      bool defer_single, Excit &ex) {
     const uint64_t emp = ~det & d.valid;
     const int N = d.N;
     const int n_class = C1 ? 2 : d.n_class;
     if (!(u01_32(w.x) < d.p_double)) {
         if (defer_single) return EX_SINGLE_DEFERRED;
-        if (!excite_single(d, cv, det, w.y, w.z, ex)) return EX_NULL;
+        if (!excite_single(d, cv, det, w.y, w.z, sel8, ex)) return EX_NULL;
         ex.hel = hel_single(d, det, ex.p, ex.a);
         return EX_OK;
     }
     // Double (Sec. 5.2): a unique pair by inverse triangular indexing.
     if (N < 2) return EX_NULL;
     const uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
-    const int64_t K = (int64_t)pick(w.y, npairs);
-    // estimate, then exact integer correction
-    int j = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)K)) * 0.5f);
-    while ((int64_t)j * (j - 1) / 2 > K) --j;
-    while ((int64_t)(j + 1) * j / 2 <= K) ++j;
-    const int i = (int)(K - (int64_t)j * (j - 1) / 2);
-    const int p = select_bit(det, (uint32_t)i), q = select_bit(det, (uint32_t)j);
+    const uint32_t K = pick(w.y, npairs);   // < 2016
+    // estimate from the hardware square root, then exact integer correction
+    uint32_t j = (uint32_t)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)K)) * 0.5f);
+    while (__umul24(j, j - 1) / 2 > K) --j;
+    while (__umul24(j + 1, j) / 2 <= K) ++j;
+    const uint32_t i = K - __umul24(j, j - 1) / 2;
+    const int p = select_bit(det, i, sel8), q = select_bit(det, j, sel8);
     const bool same = ((p ^ q) & 1) == 0;
     const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
     const int gpq = cv.irrep(d, p >> 1) ^ cv.irrep(d, q >> 1);
@@ -367,12 +379,12 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
     }
     const uint32_t nal = (uint32_t)__popcll(allowed);
     if (nal == 0) return EX_NULL;
-    const int a = select_bit(allowed, pick(w.z, nal));
+    const int a = select_bit(allowed, pick(w.z, nal), sel8);
     const int ca = cv.cls(d, a);
     const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
     const uint64_t bset = emp & cv.mask(pca) & ~(1ull << a);
     const uint32_t nba = (uint32_t)__popcll(bset);
-    const int b = select_bit(bset, pick(w.w, nba));
+    const int b = select_bit(bset, pick(w.w, nba), sel8);
     const int cb = cv.cls(d, b);
     const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
     const int nbb = __popcll(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
@@ -686,7 +698,7 @@ __device__ __forceinline__ void flush_spawn_count(unsigned long long *counter,
 
 // Drain both queues of system s with the whole workgroup (call uniformly).
 __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc &d, int s,
-                             unsigned long long &spawned) {
+                             const uint32_t *sel8, unsigned long long &spawned) {
     __syncthreads();
     const int t = threadIdx.x;
     uint32_t *status = &a.status[s];
@@ -695,8 +707,8 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         const SingleItem it = Q.sgl[j];
         Excit ex;
         const bool ok = d.n_class == 2
-                            ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.w1, it.w2, ex)
-                            : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.w1, it.w2, ex);
+                            ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.w1, it.w2, sel8, ex)
+                            : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.w1, it.w2, sel8, ex);
         if (!ok) continue;
         const double hel = hel_single(d, it.D, ex.p, ex.a);
         if (hel == 0.0) continue;
@@ -757,6 +769,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ long long s_c;
     __shared__ unsigned int s_tile;
     __shared__ double s_recip[65];
+    __shared__ uint32_t s_sel8[256];
     __shared__ uint64_t s_cm[NCLASS];
     __shared__ SpawnQueues Q;
     const unsigned long long n_tiles = a.total[1];
@@ -764,6 +777,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     const unsigned long long tile = (unsigned long long)a.tile;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     if (t > 0 && t <= 64) s_recip[t] = 1.0 / (double)t;
+    s_sel8[t] = sel8_entry((uint32_t)t);
     if (t == 0) {
         s_recip[0] = 0.0;
         Q.nsgl = 0;
@@ -805,7 +819,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             // queued work and tallies belong to another system: finish them first
             if (Q.sys >= 0) {
                 const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, spawned);
+                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, spawned);
                 flush_spawn_count(&a.spawns[qs], spawned);
             }
             __syncthreads();
@@ -885,8 +899,8 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                 const bool init = absC > d.n_a || D == d.d0;
                 const uint4 w = draw_words(d.seed, D, k, d.iter, 0u);
                 Excit ex;
-                int r = c1 ? excite(d, cv1, D, w, s_recip, defer, ex)
-                           : excite(d, cvg, D, w, s_recip, defer, ex);
+                int r = c1 ? excite(d, cv1, D, w, s_recip, s_sel8, defer, ex)
+                           : excite(d, cvg, D, w, s_recip, s_sel8, defer, ex);
                 if (r == EX_SINGLE_DEFERRED) {
                     const int q = atomicAdd(&Q.nsgl, 1);
                     if (q < SGL_QUEUE) {
@@ -894,8 +908,8 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                         r = EX_NULL;
                     } else {
                         // queue full: generate it here
-                        const bool ok = c1 ? excite_single(d, cv1, D, w.y, w.z, ex)
-                                           : excite_single(d, cvg, D, w.y, w.z, ex);
+                        const bool ok = c1 ? excite_single(d, cv1, D, w.y, w.z, s_sel8, ex)
+                                           : excite_single(d, cvg, D, w.y, w.z, s_sel8, ex);
                         r = ok ? EX_OK : EX_NULL;
                         if (ok) ex.hel = hel_single(d, D, ex.p, ex.a);
                     }
@@ -923,12 +937,12 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             }
         }
         __syncthreads();
-        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, spawned);
+        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, s_sel8, spawned);
     }
     __syncthreads();
     if (Q.sys >= 0) {
         const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, spawned);
+        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, spawned);
         flush_spawn_count(&a.spawns[qs], spawned);
     }
 }
