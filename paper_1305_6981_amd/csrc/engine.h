@@ -55,6 +55,12 @@ struct SysDesc {
     int32_t A, n_a, n_class, pad1;  // n_class: 2 x (largest irrep label + 1)
     double tau, zeta, e0, e_core, p_double, p_single;
     double inv_p_double, inv_p_single;   // 1/P_double, 1/P_single (0 when the type is impossible)
+    // With no point group (two classes, the spins) every determinant has n_emp[s]
+    // empty orbitals of spin s, and a double excitation's pgen is pgen_c1[s] (both
+    // electrons of spin s) or pgen_c1[2 + s] (unlike spins, first hole of spin s);
+    // 0 where the case cannot occur.
+    double pgen_c1[4];
+    int32_t n_emp[2];
     int64_t target;
     uint64_t seed, d0, valid;
     uint64_t cmask[NCLASS];

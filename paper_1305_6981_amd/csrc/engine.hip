@@ -595,6 +595,24 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     d.p_single = 1.0 - S.p_double;
     d.inv_p_double = d.p_double > 0.0 ? 1.0 / d.p_double : 0.0;
     d.inv_p_single = d.p_single > 0.0 ? 1.0 / d.p_single : 0.0;
+    {
+        // pgen of a double excitation without a point group, by the same operations
+        // as the general branch of the kernels' excitation generator
+        const int ne[2] = {S.M - __builtin_popcountll(S.d0 & 0x5555555555555555ull),
+                           S.M - __builtin_popcountll(S.d0 & 0xAAAAAAAAAAAAAAAAull)};
+        d.n_emp[0] = ne[0];
+        d.n_emp[1] = ne[1];
+        auto pg = [&](int nba, int nbb, int nal) {
+            return (2.0 * d.p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
+                   (double)((int64_t)S.N * (int64_t)(S.N - 1) * (int64_t)nal);
+        };
+        const int nal_u = (ne[1] > 0 ? ne[0] : 0) + (ne[0] > 0 ? ne[1] : 0);
+        for (int sp = 0; sp < 2; ++sp) {
+            d.pgen_c1[sp] = ne[sp] >= 2 && S.N >= 2 ? pg(ne[sp] - 1, ne[sp] - 1, ne[sp]) : 0.0;
+            d.pgen_c1[2 + sp] =
+                ne[sp] > 0 && ne[1 - sp] > 0 && S.N >= 2 ? pg(ne[1 - sp], ne[sp], nal_u) : 0.0;
+        }
+    }
     d.target = prm->target_walkers;
     d.seed = prm->seed;
     d.d0 = S.d0;

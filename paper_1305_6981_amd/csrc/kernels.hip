@@ -193,11 +193,13 @@ __device__ __forceinline__ int class_of(const SysDesc &d, int p) {
     return 2 * irrep_of(d, p >> 1) + (p & 1);
 }
 
-// Parity of the number of occupied orbitals strictly between p and a.
-__device__ __forceinline__ int between_parity(uint64_t det, int p, int a) {
+// The orbitals strictly between p and a, and the parity of the occupied ones.
+__device__ __forceinline__ uint64_t between_mask(int p, int a) {
     const int lo = p < a ? p : a, hi = p < a ? a : p;
-    const uint64_t m = ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
-    return __popcll(det & m) & 1;
+    return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+}
+__device__ __forceinline__ int between_parity(uint64_t det, int p, int a) {
+    return __popcll(det & between_mask(p, a)) & 1;
 }
 
 __device__ double hdiag_of(const SysDesc &d, uint64_t det) {
@@ -254,9 +256,9 @@ __device__ double hel_double(const SysDesc &d, uint64_t det, int p, int q, int a
         ap = a < b ? a : b;
         bp = a < b ? b : a;
     }
-    int par = between_parity(det, q, bp);
+    // the two parities at once: parity(x) ^ parity(y) = parity(x ^ y)
     const uint64_t d1 = (det & ~(1ull << q)) | (1ull << bp);
-    par ^= between_parity(d1, p, ap);
+    const int par = __popcll((det & between_mask(q, bp)) ^ (d1 & between_mask(p, ap))) & 1;
     const double v = eri_so(d, p, ap, q, bp) - eri_so(d, p, bp, q, ap);
     return par ? -v : v;
 }
@@ -365,32 +367,60 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
     const uint32_t i = K - __umul24(j, j - 1) / 2;
     const int p = select_bit(det, i, sel8), q = select_bit(det, j, sel8);
     const bool same = ((p ^ q) & 1) == 0;
-    const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
-    const int gpq = cv.irrep(d, p >> 1) ^ cv.irrep(d, q >> 1);
-    // a orbitals whose partner class (Eq. sym1 plus spin) has an empty orbital besides a.
-    uint64_t allowed = 0;
-    for (int c = 0; c < n_class; ++c) {
-        const uint64_t memb = A & (C1 ? cv.mask(c) : d.cmask[c]);
-        if (!memb) continue;
-        const int sb = same ? (p & 1) : 1 - (c & 1);
-        const int pc = 2 * (gpq ^ (c >> 1)) + sb;
-        const int nb = __popcll(emp & cv.mask(pc)) - (pc == c ? 1 : 0);
-        if (nb > 0) allowed |= memb;
+    int a, b;
+    if (C1) {
+        // No point group: every determinant has the same number of empty orbitals of
+        // each spin (d.n_emp), so the allowed sets and their sizes follow from the
+        // spins alone, and pgen is one of four per-system values (the general branch
+        // below gives the same sets, counts and pgen).
+        const int sp = p & 1;
+        const uint64_t e0 = emp & EVEN_BITS, e1 = emp & ODD_BITS;
+        const uint32_t n0 = (uint32_t)d.n_emp[0], n1 = (uint32_t)d.n_emp[1];
+        uint64_t allowed;
+        uint32_t nal;
+        if (same) {
+            allowed = sp ? e1 : e0;
+            const uint32_t ne = sp ? n1 : n0;
+            nal = ne >= 2 ? ne : 0;
+        } else {
+            allowed = (n1 > 0 ? e0 : 0ull) | (n0 > 0 ? e1 : 0ull);
+            nal = (n1 > 0 ? n0 : 0u) + (n0 > 0 ? n1 : 0u);
+        }
+        if (nal == 0) return EX_NULL;
+        a = select_bit(allowed, pick(w.z, nal), sel8);
+        const int sa = a & 1;
+        const uint64_t bset = same ? (allowed & ~(1ull << a)) : (sa ? e0 : e1);
+        const uint32_t nba = same ? nal - 1 : (sa ? n0 : n1);
+        b = select_bit(bset, pick(w.w, nba), sel8);
+        ex.pgen = same ? (sp ? d.pgen_c1[1] : d.pgen_c1[0]) : (sa ? d.pgen_c1[3] : d.pgen_c1[2]);
+    } else {
+        const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
+        const int gpq = cv.irrep(d, p >> 1) ^ cv.irrep(d, q >> 1);
+        // a orbitals whose partner class (Eq. sym1 plus spin) has an empty orbital besides a.
+        uint64_t allowed = 0;
+        for (int c = 0; c < n_class; ++c) {
+            const uint64_t memb = A & d.cmask[c];
+            if (!memb) continue;
+            const int sb = same ? (p & 1) : 1 - (c & 1);
+            const int pc = 2 * (gpq ^ (c >> 1)) + sb;
+            const int nb = __popcll(emp & cv.mask(pc)) - (pc == c ? 1 : 0);
+            if (nb > 0) allowed |= memb;
+        }
+        const uint32_t nal = (uint32_t)__popcll(allowed);
+        if (nal == 0) return EX_NULL;
+        a = select_bit(allowed, pick(w.z, nal), sel8);
+        const int ca = cv.cls(d, a);
+        const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
+        const uint64_t bset = emp & cv.mask(pca) & ~(1ull << a);
+        const uint32_t nba = (uint32_t)__popcll(bset);
+        b = select_bit(bset, pick(w.w, nba), sel8);
+        const int cb = cv.cls(d, b);
+        const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
+        const int nbb = __popcll(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
+        ex.pgen = (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
+                  (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
     }
-    const uint32_t nal = (uint32_t)__popcll(allowed);
-    if (nal == 0) return EX_NULL;
-    const int a = select_bit(allowed, pick(w.z, nal), sel8);
-    const int ca = cv.cls(d, a);
-    const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
-    const uint64_t bset = emp & cv.mask(pca) & ~(1ull << a);
-    const uint32_t nba = (uint32_t)__popcll(bset);
-    const int b = select_bit(bset, pick(w.w, nba), sel8);
-    const int cb = cv.cls(d, b);
-    const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
-    const int nbb = __popcll(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
     ex.det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
-    ex.pgen = (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
-              (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
     ex.hel = hel_double(d, det, p, q, a, b);
     return EX_OK;
 }
