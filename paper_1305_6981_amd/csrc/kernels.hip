@@ -95,6 +95,11 @@ __device__ __forceinline__ uint32_t sel8_entry(uint32_t b) {
     return e;
 }
 
+// j (j - 1) / 2 for j < 2^12 (0 for j = 0): the index of the first pair (i, j).
+__device__ __forceinline__ uint32_t pair_base(uint32_t j) {
+    return (uint32_t)__umul24(j, j - 1u) >> 1;
+}
+
 // Position of the k-th (0-based) set bit of x (k < popcount(x)): halving with
 // popcounts down to one byte, then that byte's entry of the table sel8 (the
 // sel8_entry values, staged in LDS).
@@ -360,11 +365,14 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
     if (N < 2) return EX_NULL;
     const uint32_t npairs = (uint32_t)(N * (N - 1) / 2);
     const uint32_t K = pick(w.y, npairs);   // < 2016
-    // estimate from the hardware square root, then exact integer correction
-    uint32_t j = (uint32_t)((1.0f + __builtin_amdgcn_sqrtf(1.0f + 8.0f * (float)K)) * 0.5f);
-    while (__umul24(j, j - 1) / 2 > K) --j;
-    while (__umul24(j + 1, j) / 2 <= K) ++j;
-    const uint32_t i = K - __umul24(j, j - 1) / 2;
+    // The estimate from the hardware square root is within one of j (the largest
+    // j with j (j - 1) / 2 <= K); one exact integer correction each way.
+    // (float)(8 K + 1), exact below 2^23, by the mantissa trick
+    const float x = __int_as_float((int)(0x4B000000u | (8u * K + 1u))) - 8388608.0f;
+    uint32_t j = (uint32_t)((1.0f + __builtin_amdgcn_sqrtf(x)) * 0.5f);
+    j -= pair_base(j) > K ? 1u : 0u;
+    j += pair_base(j + 1) <= K ? 1u : 0u;
+    const uint32_t i = K - pair_base(j);
     const int p = select_bit(det, i, sel8), q = select_bit(det, j, sel8);
     const bool same = ((p ^ q) & 1) == 0;
     int a, b;
