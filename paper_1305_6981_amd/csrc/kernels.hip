@@ -1000,31 +1000,33 @@ __device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t cap, u
     return -1;
 }
 
-constexpr int POST_QUEUE = 1536;  // new-determinant queue entries per workgroup (split over
-                                  // its wavefronts); with the 32 KiB pair table: four
-                                  // workgroups per CU
+constexpr int POST_QUEUE = 1536;  // new-determinant queue entries per workgroup; with the
+                                  // 16 KiB triangular pair table: six workgroups per CU
 constexpr int POST_GRAB = 4;      // chunks per dynamic grab in k_post
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
-// ascending (p, q) order from the LDS copies of h_pp and of the pair table, for
-// two determinants with the same number of electrons at once: the two sums are
+// ascending (p, q) order from the LDS copies of h_pp and of the pair table (its
+// upper triangle, row after row: entry (p, q) at pair_row(p, n) + q), for two
+// determinants with the same number of electrons at once: the two sums are
 // independent chains that hide each other's add latency, and each keeps the
 // order of a single sum.
+__device__ __forceinline__ int pair_row(int p, int n) { return p * (2 * n - p - 3) / 2 - 1; }
+
 __device__ __forceinline__ void hdiag_lds2(double e_core, uint64_t da, uint64_t db,
-                                           const double *hpp, const double *jk, double &ra,
-                                           double &rb) {
+                                           const double *hpp, const double *jk, int n,
+                                           double &ra, double &rb) {
     double xa = e_core, xb = e_core;
     for (uint64_t ma = da, mb = db; ma; ma &= ma - 1, mb &= mb - 1) {
         xa = xa + hpp[__builtin_ctzll(ma)];
         xb = xb + hpp[__builtin_ctzll(mb)];
     }
     for (uint64_t m1a = da, m1b = db; m1a; m1a &= m1a - 1, m1b &= m1b - 1) {
-        const double *rowa = jk + 64 * __builtin_ctzll(m1a);
-        const double *rowb = jk + 64 * __builtin_ctzll(m1b);
+        const int ba = pair_row(__builtin_ctzll(m1a), n);
+        const int bb = pair_row(__builtin_ctzll(m1b), n);
         for (uint64_t m2a = m1a & (m1a - 1), m2b = m1b & (m1b - 1); m2a;
              m2a &= m2a - 1, m2b &= m2b - 1) {
-            xa = xa + rowa[__builtin_ctzll(m2a)];
-            xb = xb + rowb[__builtin_ctzll(m2b)];
+            xa = xa + jk[ba + __builtin_ctzll(m2a)];
+            xb = xb + jk[bb + __builtin_ctzll(m2b)];
         }
     }
     ra = xa;
@@ -1041,15 +1043,15 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
         const bool two = j + (int)blockDim.x < n;
         const uint32_t i1 = two ? queue[j + blockDim.x] : i0;
         double h0, h1;
-        hdiag_lds2(d.e_core, *gp(d.key + i0), *gp(d.key + i1), hpp, jk, h0, h1);
+        hdiag_lds2(d.e_core, *gp(d.key + i0), *gp(d.key + i1), hpp, jk, d.n_so, h0, h1);
         *gp(d.hdiag + i0) = h0;
         if (two) *gp(d.hdiag + i1) = h1;
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
 void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
-    __shared__ double s_jk[64 * 64];
+    __shared__ double s_jk[64 * 63 / 2];   // upper triangle of the pair table
     __shared__ double s_hpp[64];
     // New determinants are queued for the workgroup. Whether to flush the queue at
     // the start of a chunk is decided by thread 0 two chunks earlier (s_flush, by
@@ -1103,7 +1105,10 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (loaded >= 0 && n > 0) flush_new_dets(desc[loaded], s_queue, n, s_hpp, s_jk);
                 __syncthreads();
                 if (loaded != s) {
-                    for (int i = t; i < d.n_so * 64; i += 256) s_jk[i] = gptr(d.jk)[i];
+                    for (int i = t; i < d.n_so * 64; i += 256) {
+                        const int p = i >> 6, q = i & 63;
+                        if (q > p && q < d.n_so) s_jk[pair_row(p, d.n_so) + q] = gptr(d.jk)[i];
+                    }
                     for (int i = t; i < d.n_so; i += 256) s_hpp[i] = h_so(d, i, i);
                     loaded = s;
                 }
@@ -1173,7 +1178,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         s_queue[q] = (uint32_t)(base + u);
                     } else {
                         double h, h2;
-                        hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, h, h2);
+                        hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, d.n_so, h, h2);
                         *gp(d.hdiag + base + u) = h;
                     }
                 }
@@ -1437,7 +1442,7 @@ hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out
     return hipGetLastError();
 }
 
-int post_grid_size() { return spawn_grid_size() / 2; }
+int post_grid_size() { return spawn_grid_size() / 8 * 6; }   // six workgroups per CU
 
 int spawn_grid_size() {
     int dev = 0, cus = 256;
