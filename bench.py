@@ -220,6 +220,24 @@ def copy_calibration(roctx, nbytes=1 << 30):
     del x, y
 
 
+def stream_bandwidth(nbytes=1 << 30, reps=5):
+    """Measured device-to-device copy bandwidth (GB/s, read + write bytes over the best
+    of `reps` copies of nbytes, timed with events on the current stream)."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del x, y
+    return 2.0 * nbytes / best / 1e9
+
+
 def pmc_means(path, last=0):
     """{(kernel, counter): mean per dispatch} from a rocprofv3 --pmc CSV tree (only the
     last `last` dispatches of each kernel when last > 0)."""
@@ -430,11 +448,14 @@ def main():
            "attempts": attempts / args.steps}
     bpk = bytes_per_kernel(rec, n_slots)
 
+    copy_gbs = stream_bandwidth()
+
     def hbm_roofline(k):
         achieved = bpk[k] / (avg_ms[k] * 1e-3) / 1e9
         return {"bound": "hbm", "kernel": k, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(k),
-                "algorithmic_bytes": bpk[k], "avg_ms": avg_ms[k]}
+                "algorithmic_bytes": bpk[k], "avg_ms": avg_ms[k],
+                "measured_copy_gbs": copy_gbs, "frac_of_measured_copy": achieved / copy_gbs}
 
     if dominant == "k_spawn":
         ops = OPS_PER_ATTEMPT * rec["attempts"]

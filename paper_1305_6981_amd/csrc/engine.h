@@ -107,6 +107,8 @@ struct EngineArgs {
     unsigned long long *total;       // [0] total attempts, [1] total spawn tiles
     const int64_t *nchunks;          // global chunks in use
     IterRecord *rec;                 // [max_sys][REC_CAP]
+    uint32_t *tile_chunk;            // [tile_cap] chunk of each spawn tile (k_scan_down); tiles
+    int64_t tile_cap;                // beyond the capacity are found by search
 };
 
 // Kernel launchers (kernels.hip).

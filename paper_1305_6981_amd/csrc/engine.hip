@@ -178,6 +178,8 @@ struct fciqmc_t {
     unsigned long long *d_chunk_nw = nullptr, *d_chunk_off = nullptr, *d_total = nullptr;
     unsigned long long *d_chunk_toff = nullptr;
     ChunkStat *d_chunk_stat = nullptr;
+    uint32_t *d_tile_chunk = nullptr;       // chunk of each spawn tile
+    int64_t tile_cap = 0;
     unsigned long long *d_blk = nullptr;    // [2][4][SCAN_G] range sums and scans
     unsigned long long *d_step = nullptr;   // iterations run (selects the halves of the sums)
     FinPart *d_fin = nullptr;               // [max_sys][FIN_BLOCKS]
@@ -220,6 +222,8 @@ EngineArgs make_args(fciqmc_t *h) {
     a.status = h->d_status;
     a.spawns = h->d_spawns;
     a.work = h->d_work;
+    a.tile_chunk = h->d_tile_chunk;
+    a.tile_cap = h->tile_cap;
     return a;
 }
 
@@ -302,6 +306,26 @@ int relayout(fciqmc_t *h) {
     HIP_TRY(hipMemcpyAsync(h->d_nchunks, &h->n_chunks, sizeof(int64_t), hipMemcpyHostToDevice,
                            h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+// The tile -> chunk map: room for every chunk's first tile and for twice the
+// walkers of the last iteration in whole tiles, grown by doubling (a graph holds
+// the pointer, so growing drops the graphs). Tiles beyond it are found by search.
+int ensure_tile_map(fciqmc_t *h) {
+    int64_t walkers = 0;
+    for (int s = 0; s < h->max_sys; ++s)
+        if (h->sys[s].active) walkers += std::max<int64_t>(h->sys[s].last.nw, 0);
+    const int64_t want = h->n_chunks + 2 * walkers / std::max(h->tile, 1) + 65536;
+    if (want <= h->tile_cap) return 0;
+    const int64_t cap = std::max<int64_t>(want, 2 * h->tile_cap);
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hipFree(h->d_tile_chunk);
+    h->d_tile_chunk = nullptr;
+    h->tile_cap = 0;
+    HIP_TRY(hipMalloc(&h->d_tile_chunk, cap * sizeof(uint32_t)));
+    h->tile_cap = cap;
+    drop_graphs(h);
     return 0;
 }
 
@@ -831,7 +855,9 @@ int plan_launch(fciqmc_t *h, int L, int *L_out) {
 int run_iterations(fciqmc_t *h, int L) {
     std::vector<int64_t> before(h->max_sys);
     for (int s = 0; s < h->max_sys; ++s) before[s] = h->hdesc[s].iter;
-    int rc = upload_desc(h);
+    int rc = ensure_tile_map(h);
+    if (rc) return rc;
+    rc = upload_desc(h);
     if (rc) return rc;
     EngineArgs a = make_args(h);
     if (h->profiling) {
@@ -1039,6 +1065,7 @@ void release(fciqmc_t *h) {
     hipFree(h->d_chunk_off);
     hipFree(h->d_chunk_toff);
     hipFree(h->d_chunk_stat);
+    hipFree(h->d_tile_chunk);
     for (auto &e : h->ev)
         if (e) hipEventDestroy(e);
     if (h->own_stream) hipStreamDestroy(h->stream);

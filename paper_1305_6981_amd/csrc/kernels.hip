@@ -632,9 +632,23 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
             pre += ws[k];
             pret += wt[k];
         }
+        // The chunk of each of its tiles, for k_spawn's tile grabs: up to eight by the
+        // chunk's thread, the rest (the reference determinant's chunk has thousands)
+        // by the whole wavefront.
+        const unsigned long long to = tbase + pret + xt - vt;
+        const unsigned long long cap = (unsigned long long)a.tile_cap;
         if (i < c1) {
             a.chunk_off[i] = base + pre + x - v;
-            a.chunk_toff[i] = tbase + pret + xt - vt;
+            a.chunk_toff[i] = to;
+            const unsigned long long te = to + (vt < 8ull ? vt : 8ull);
+            for (unsigned long long k = to; k < te && k < cap; ++k) a.tile_chunk[k] = (uint32_t)i;
+        }
+        for (uint64_t big = __ballot(i < c1 && vt > 8ull); big; big &= big - 1) {
+            const int l = __builtin_ctzll(big);
+            const unsigned long long tl = __shfl(to, l, 64), vl = __shfl(vt, l, 64);
+            const unsigned long long te = tl + vl < cap ? tl + vl : cap;
+            for (unsigned long long k = tl + 8ull + (unsigned long long)lane; k < te; k += 64ull)
+                a.tile_chunk[k] = (uint32_t)(c + 64 * w + l);
         }
         base += ws[0] + ws[1] + ws[2] + ws[3];
         tbase += wt[0] + wt[1] + wt[2] + wt[3];
@@ -695,7 +709,7 @@ constexpr int SPAWN_GRAB = 4;    // spawn tiles per dynamic grab (one counter se
 constexpr int SGL_QUEUE = 128;
 constexpr int SPW_QUEUE = 256;
 constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
-constexpr int SPW_DRAIN = 128;
+constexpr int SPW_DRAIN = 192;     // (a tile adds about 30 spawns; a fuller queue is merged inline)
 
 // The acceptance uniform: the type word's uniform rescaled within the chosen
 // type's interval [0, P_double) or [P_double, 1); given the type it is uniform
@@ -838,7 +852,9 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             const unsigned int tix = next_tile++;
             if (lane == 0) s_tile = tix;
             if (tix < n_tiles) {
-                const int64_t cc = last_le(a.chunk_toff, nch, tix, lane);
+                const int64_t cc = tix < (unsigned long long)a.tile_cap
+                                       ? (int64_t)a.tile_chunk[tix]
+                                       : last_le(a.chunk_toff, nch, tix, lane);
                 if (lane == 0) s_c = cc;
             }
         }
