@@ -166,7 +166,8 @@ struct fciqmc_t {
     std::vector<SysHost> sys;
     std::vector<SysDesc> hdesc;
     SysDesc *d_desc = nullptr;
-    IterRecord *d_rec = nullptr;
+    IterRecord *d_rec = nullptr;            // per-iteration records: pinned host memory that
+    IterRecord *h_rec = nullptr;            // k_finalize writes through d_rec, read as h_rec
     uint32_t *d_status = nullptr;           // per system ST_* bits (device)
     unsigned int *d_work = nullptr;         // dynamic work counters
     unsigned long long *d_spawns = nullptr; // per system spawn counter (device)
@@ -179,6 +180,8 @@ struct fciqmc_t {
     unsigned long long *d_chunk_toff = nullptr;
     ChunkStat *d_chunk_stat = nullptr;
     uint32_t *d_tile_chunk = nullptr;       // chunk of each spawn tile
+    void *d_scratch = nullptr;              // scratch table for compaction in place
+    size_t scratch_bytes = 0;
     int64_t tile_cap = 0;
     unsigned long long *d_blk = nullptr;    // [2][4][SCAN_G] range sums and scans
     unsigned long long *d_step = nullptr;   // iterations run (selects the halves of the sums)
@@ -443,6 +446,49 @@ int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
     rc = relayout(h);
     if (rc) return rc;
     return upload_desc(h);
+}
+
+// Compaction at the same capacity: rehash the occupied determinants into the
+// handle's scratch table, then copy its three arrays back. No allocation of the
+// system's block, no upload of integrals and no new chunk layout, so it is cheap
+// enough to run between any two launches. The spawned-walker accumulators are
+// zero between iterations and stay so.
+int compact_system(fciqmc_t *h, int s) {
+    SysHost &S = h->sys[s];
+    const int64_t cap = S.cap;
+    const size_t need = (size_t)cap * (sizeof(uint64_t) + sizeof(double) + sizeof(int32_t));
+    if (need > h->scratch_bytes) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        hipFree(h->d_scratch);
+        h->d_scratch = nullptr;
+        const size_t want = std::max(need, 2 * h->scratch_bytes);
+        h->scratch_bytes = 0;
+        if (hipMalloc(&h->d_scratch, want) != hipSuccess) {
+            (void)hipGetLastError();
+            h->d_scratch = nullptr;
+            return grow_system(h, s, cap);   // no room for scratch: rebuild in a new block
+        }
+        h->scratch_bytes = want;
+    }
+    char *p = (char *)h->d_scratch;
+    uint64_t *tk = (uint64_t *)p;
+    double *th = (double *)(p + (size_t)cap * sizeof(uint64_t));
+    int32_t *tp = (int32_t *)(p + (size_t)cap * (sizeof(uint64_t) + sizeof(double)));
+    HIP_TRY(hipMemsetAsync(tk, 0, (size_t)cap * sizeof(uint64_t), h->stream));
+    HIP_TRY(hipMemsetAsync(th, 0xFF, (size_t)cap * sizeof(double), h->stream));   // NaN
+    HIP_TRY(hipMemsetAsync(tp, 0, (size_t)cap * sizeof(int32_t), h->stream));
+    HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
+    // the rehash kernel reads the (unchanged) capacity from the descriptor
+    HIP_TRY(launch_rehash(h->d_desc, s, S.key, S.pop, S.hd, cap, tk, tp, th, h->d_err, h->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (err) return set_err(FCIQMC_ECAPACITY, "compaction of the table failed");
+    HIP_TRY(hipMemcpyAsync(S.key, tk, (size_t)cap * sizeof(uint64_t), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(S.hd, th, (size_t)cap * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(S.pop, tp, (size_t)cap * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+    S.last.used = S.last.nd + 1;
+    return 0;
 }
 
 uint64_t aufbau(const std::vector<double> &h1, int M, int na, int nb) {
@@ -840,7 +886,7 @@ int plan_launch(fciqmc_t *h, int L, int *L_out) {
             const int64_t want = 2 * (live + 8 * g);
             const int64_t nc = want <= S.cap ? S.cap
                                              : round_cap(std::max<int64_t>(S.cap + S.cap / 2, want));
-            int rc = grow_system(h, s, nc);
+            int rc = nc == S.cap ? compact_system(h, s) : grow_system(h, s, nc);
             if (rc) return rc;
             used = live;
         }
@@ -891,10 +937,8 @@ int run_iterations(fciqmc_t *h, int L) {
         SysDesc &d = h->hdesc[s];
         const int64_t n_new = d.iter - before[s];
         if (n_new > 0) {
-            std::vector<IterRecord> rr(REC_CAP);
-            HIP_TRY(hipMemcpyAsync(rr.data(), h->d_rec + (int64_t)s * REC_CAP,
-                                   sizeof(IterRecord) * REC_CAP, hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipStreamSynchronize(h->stream));
+            // the stream has been synchronised: the records are in host memory
+            const IterRecord *rr = h->h_rec + (int64_t)s * REC_CAP;
             int64_t prev_used = S.last.used, seen = 0;
             for (int64_t it = before[s] + 1; it <= d.iter; ++it) {
                 const IterRecord &r = rr[it % REC_CAP];
@@ -980,7 +1024,10 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMemsetAsync(h->d_work, 0, sizeof(unsigned int) * 4, h->stream));
     HIP_TRY(hipMalloc(&h->d_spawns, sizeof(unsigned long long) * max_slots));
     HIP_TRY(hipMemsetAsync(h->d_spawns, 0, sizeof(unsigned long long) * max_slots, h->stream));
-    HIP_TRY(hipMalloc(&h->d_rec, sizeof(IterRecord) * REC_CAP * max_slots));
+    HIP_TRY(hipHostMalloc((void **)&h->h_rec, sizeof(IterRecord) * REC_CAP * max_slots,
+                          hipHostMallocDefault));
+    std::memset(h->h_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots);
+    HIP_TRY(hipHostGetDevicePointer((void **)&h->d_rec, h->h_rec, 0));
     HIP_TRY(hipMalloc(&h->d_total, 2 * sizeof(unsigned long long)));
     HIP_TRY(hipMalloc(&h->d_nchunks, sizeof(int64_t)));
     HIP_TRY(hipMalloc(&h->d_blk, 2 * 4 * SCAN_G * sizeof(unsigned long long)));
@@ -989,7 +1036,6 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_fin, sizeof(FinPart) * FIN_BLOCKS * max_slots));
     HIP_TRY(hipMalloc(&h->d_c0, sizeof(int64_t) * max_slots));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
-    HIP_TRY(hipMemsetAsync(h->d_rec, 0, sizeof(IterRecord) * REC_CAP * max_slots, h->stream));
     for (int k = 0; k <= NKERN; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
     h->spawn_grid = spawn_grid_size();
     h->post_grid = post_grid_size();
@@ -1048,7 +1094,7 @@ void release(fciqmc_t *h) {
     for (auto &S : h->sys)
         if (S.block) hipFree(S.block);
     hipFree(h->d_desc);
-    hipFree(h->d_rec);
+    if (h->h_rec) hipHostFree(h->h_rec);
     hipFree(h->d_status);
     hipFree(h->d_work);
     hipFree(h->d_spawns);
@@ -1066,6 +1112,7 @@ void release(fciqmc_t *h) {
     hipFree(h->d_chunk_toff);
     hipFree(h->d_chunk_stat);
     hipFree(h->d_tile_chunk);
+    hipFree(h->d_scratch);
     for (auto &e : h->ev)
         if (e) hipEventDestroy(e);
     if (h->own_stream) hipStreamDestroy(h->stream);
