@@ -426,8 +426,9 @@ int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
     if (rc) return rc == FCIQMC_ENOMEM ? FCIQMC_ECAPACITY : rc;
     SysHost T = S;
     carve(T, blk, new_cap);
-    rc = upload_integrals(h, T);
-    if (rc) return rc;
+    // the integrals (same layout after the tables) move device to device
+    const size_t ib = (size_t)((const char *)(S.d_t3 + S.t3.size()) - (const char *)S.d_h1);
+    HIP_TRY(hipMemcpyAsync(T.d_h1, S.d_h1, ib, hipMemcpyDeviceToDevice, h->stream));
     // the rehash kernel reads the new capacity from the descriptor
     h->hdesc[s].cap = (uint64_t)new_cap;
     rc = upload_desc(h);
