@@ -180,6 +180,7 @@ struct fciqmc_t {
     unsigned long long *d_chunk_toff = nullptr;
     ChunkStat *d_chunk_stat = nullptr;
     uint32_t *d_tile_chunk = nullptr;       // chunk of each spawn tile
+    bool tile_map_off = false;              // its allocation failed once: search instead
     void *d_scratch = nullptr;              // scratch table for compaction in place
     size_t scratch_bytes = 0;
     int64_t tile_cap = 0;
@@ -320,15 +321,20 @@ int ensure_tile_map(fciqmc_t *h) {
     for (int s = 0; s < h->max_sys; ++s)
         if (h->sys[s].active) walkers += std::max<int64_t>(h->sys[s].last.nw, 0);
     const int64_t want = h->n_chunks + 2 * walkers / std::max(h->tile, 1) + 65536;
-    if (want <= h->tile_cap) return 0;
+    if (want <= h->tile_cap || h->tile_map_off) return 0;
     const int64_t cap = std::max<int64_t>(want, 2 * h->tile_cap);
     HIP_TRY(hipStreamSynchronize(h->stream));
     hipFree(h->d_tile_chunk);
     h->d_tile_chunk = nullptr;
     h->tile_cap = 0;
-    HIP_TRY(hipMalloc(&h->d_tile_chunk, cap * sizeof(uint32_t)));
-    h->tile_cap = cap;
     drop_graphs(h);
+    if (hipMalloc(&h->d_tile_chunk, cap * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();   // no room: every tile grab searches instead
+        h->d_tile_chunk = nullptr;
+        h->tile_map_off = true;
+        return 0;
+    }
+    h->tile_cap = cap;
     return 0;
 }
 
