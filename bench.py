@@ -405,16 +405,19 @@ def main():
     sv.set_shift(s_est, 1)
     log(f"[bench] grown in {time.perf_counter() - t_g:.1f} s: N_w {e['n_walkers']} N_d "
         f"{e['n_dets']} C0 {e['ref_pop']}; shift set to E_proj - E0 = {s_est:.4f}")
-    nd0 = sv.estimates()["n_dets"]
-    sv.iterate(args.warmup)
-    # Size the table for the timed iterations now (growth rate of the warm-up, 30 % slack,
-    # 40 % of the slots holding live determinants at the end: vacated slots keep their
-    # key until the next rehash), so that no rehash falls inside the timed region.
+    used = [sv.estimates()["table_used"]]
+    for _ in range(args.warmup):
+        sv.iterate(1)
+        used.append(sv.estimates()["table_used"])
+    # Size the table for the timed iterations by the library's own headroom rule: slots
+    # holding a key (occupied or vacated) stay below 70 % while the largest per-iteration
+    # growth of the warm-up, with 25 % slack, continues through the window (and four
+    # iterations more), so no rehash falls inside the timed region.
     ew = sv.estimates()
-    g = max(0.0, (ew["n_dets"] - nd0) / max(args.warmup, 1))
-    sv.reserve(int(2.5 * (ew["n_dets"] + 1.3 * g * (args.steps + 2))))
-    log(f"[bench] warm-up done; table {sv.estimates()['table_slots']} slots for N_d "
-        f"{ew['n_dets']} growing by ~{g:.3g} per iteration")
+    gu = max([b - a for a, b in zip(used, used[1:])] + [0])
+    sv.reserve(int((ew["table_used"] + 1.25 * gu * (args.steps + 4)) / 0.7) + 1)
+    log(f"[bench] warm-up done; table {sv.estimates()['table_slots']} slots, "
+        f"{ew['table_used']} holding keys, growing by up to {gu} per iteration; N_d {ew['n_dets']}")
 
     F.fciqmc_set_profiling(sv.h, 1)
     e0 = sv.estimates()
@@ -436,6 +439,9 @@ def main():
     log(f"[bench] timed {args.steps} iterations in {dt:.3f} s: N_w {e1['n_walkers']} N_d "
         f"{e1['n_dets']} attempts {attempts} spawns {spawns}")
     grew = e1["table_slots"] != e0["table_slots"]
+    rehashed = grew or e1["table_used"] < e0["table_used"]
+    log(f"[bench] slots holding keys {e0['table_used']} -> {e1['table_used']} of {e1['table_slots']}"
+        + (" (rehashed inside the timed region)" if rehashed else ""))
     if grew:
         log(f"[bench] the table grew inside the timed region ({e0['table_slots']} -> "
             f"{e1['table_slots']} slots); per-launch bytes use the mean of the two")
@@ -480,6 +486,8 @@ def main():
                                f"tau=5e-4, {e1['n_walkers']} walkers on {e1['n_dets']} dets",
                    "walkers": e1["n_walkers"], "dets": e1["n_dets"],
                    "table_slots": e1["table_slots"], "table_grew_in_timed_region": grew,
+                   "table_rehashed_in_timed_region": rehashed,
+                   "table_used_start": e0["table_used"], "table_used_end": e1["table_used"],
                    "parallelism": "1 GPU"},
         "kernel_avg_ms": avg_ms,
         "roofline": roofline,

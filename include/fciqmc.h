@@ -105,6 +105,9 @@ typedef struct {
     int64_t n_var;              /* iteration at which the shift started to vary */
     int64_t n_prev;             /* N_w at the last shift update */
     int64_t table_slots;        /* slots per main-table buffer (layout only) */
+    int64_t table_used;         /* slots holding a key, occupied or vacated, after the last
+                                   iteration (layout only; the table is compacted or grown
+                                   before this passes 70 % of table_slots) */
     double shift;               /* S, relative to E0 */
     double e_ref;               /* E0 = H_00 */
     double p_double;

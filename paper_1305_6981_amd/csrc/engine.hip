@@ -813,6 +813,7 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
     o->n_var = h->hdesc[s].n_var;
     o->n_prev = h->hdesc[s].n_prev;
     o->table_slots = S.cap;
+    o->table_used = std::max<int64_t>(r.used, r.nd);
     o->shift = h->hdesc[s].shift;
     o->e_ref = S.e0;
     o->p_double = S.p_double;

@@ -42,7 +42,7 @@ class Params(C.Structure):
 
 _EST_INT = ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
             "aborted", "total_attempts", "total_spawns", "n_samples", "n_var", "n_prev",
-            "table_slots")
+            "table_slots", "table_used")
 _EST_DBL = ("shift", "e_ref", "p_double", "proj_num", "e_proj_inst", "e_proj_mean",
             "e_proj_err", "shift_mean", "shift_err", "ms_last_call")
 
