@@ -133,6 +133,8 @@ def test_table_stays_bounded_under_turnover():
             gpu.iterate(15)
             e = gpu.estimates()
             max_nd, max_sp = max(max_nd, e["n_dets"]), max(max_sp, e["spawns"])
+            # slots holding keys: at least the occupied ones, within the table
+            assert e["n_dets"] <= e["table_used"] <= e["table_slots"]
         ref.iterate(75)
         _same_lists(gpu, ref, f"turnover{b}")
         _same_estimates(gpu.estimates(), ref.estimates(), f"turnover{b}")
