@@ -118,6 +118,14 @@ typedef struct {
     double ms_last_call;        /* wall time of the last fciqmc_iterate on this handle */
     int32_t shift_varying;
     int32_t status;             /* 0, or the FCIQMC_E* code that stopped this system */
+    int64_t redos;              /* total: iterations re-run after a table overflowed (each
+                                   re-run is bit-identical to an uninterrupted one) */
+    /* Device time (ms) of the phases of one iteration of the handle: the last
+     * iteration of the last fciqmc_iterate call runs as direct launches bracketed
+     * by events (the others run in graphs). Spawning includes the attempt mapping
+     * (chunk scans); death runs inside the annihilation pass, so ms_death is 0 and
+     * its time is part of ms_annihilate; the estimators include the shift. */
+    double ms_spawn, ms_death, ms_annihilate, ms_estimators;
 } fciqmc_estimates;
 
 /* Create a handle holding one system, place initial_walkers on the reference.
@@ -234,6 +242,25 @@ int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
 int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t post_grid);
 int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *post_grid);
 int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial);
+
+/* ---- error bars -------------------------------------------------------------
+ * The blocking analysis behind e_proj_err / shift_err, for a caller's own
+ * series (host only, no device work): blocks of 2^l consecutive samples are
+ * averaged level by level, kept online in O(log n) memory, and the error of
+ * <num>/<den> (den NULL: of <num>) is read at the first level with >= 16 blocks
+ * whose error the next two levels do not exceed by more than its relative
+ * uncertainty 1/sqrt(2(n-1)) -- the blocking of correlated ratios cited in the
+ * paper's Sec. 7. *err is NaN when no level has 16 blocks. Errors: EINVAL. */
+int fciqmc_blocking(const double *num, const double *den, int64_t n, double *mean, double *err);
+
+/* ---- test knobs -------------------------------------------------------------
+ * planner = 0: do not size tables before each launch, so that overflows are
+ * met inside an iteration and handled by the grow-and-redo path (counted in
+ * fciqmc_estimates.redos); tile_map_limit >= 0 caps the map from spawn tiles to
+ * chunks at that many entries (0: no map), so tile grabs beyond it search the
+ * chunk offsets instead; -1 restores the default. Results do not depend on
+ * either. Errors: EINVAL. */
+int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit);
 
 #ifdef __cplusplus
 }

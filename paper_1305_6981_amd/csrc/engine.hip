@@ -56,78 +56,100 @@ int64_t next_pow2(int64_t x) {
 }
 
 // ---------------------------------------------------------------------------
-// Blocking analysis (Flyvbjerg & Petersen) of <num>/<den> (den == nullptr:
-// of <num>). Pairwise averaging per level, trailing odd sample dropped; the
-// error is taken at the first level with >= 16 blocks whose value the next two
-// levels do not exceed by more than its own uncertainty e/sqrt(2(n-1)).
+// Error bars of correlated averages by blocking (Flyvbjerg & Petersen, the
+// analysis of correlated ratios the paper's conclusions cite), kept online in
+// O(log n) memory. Level 0 receives every sample (x, y); each completed pair at
+// level l is averaged and passed to level l + 1, so level l sees the first
+// floor(n / 2^l) block means. Per level the accumulators hold sums of the
+// deviations from the level's first value (dx = x - x_first, ...): dx, dy,
+// dx^2, dy^2 and dx dy, from which the level's means, variances of the mean and
+// covariance follow. The error of the ratio <x>/<y> is the standard error of the
+// linearised ratio estimator, sqrt(var(xbar - r ybar)) / ybar with r = xbar/ybar;
+// a plain mean is the case y = 1. The level reported is the first one with at
+// least 16 blocks whose error the next two levels (with >= 16 blocks) do not
+// exceed by more than the error's own relative uncertainty 1/sqrt(2(n - 1));
+// when none qualifies, the deepest level with >= 16 blocks.
 // ---------------------------------------------------------------------------
-void blocking(const std::vector<double> &num, const std::vector<double> *den, double &mean,
-              double &err) {
-    const size_t n = num.size();
-    mean = NAN;
-    err = NAN;
-    if (n == 0) return;
-    double sx = 0.0, sy = 0.0;
-    for (size_t t = 0; t < n; ++t) {
-        sx = sx + num[t];
-        sy = sy + (den ? (*den)[t] : 1.0);
-    }
-    mean = den ? (sx / (double)n) / (sy / (double)n) : sx / (double)n;
-    std::vector<double> x(num), y(n, 1.0);
-    if (den) y = *den;
-    std::vector<double> ev;
-    std::vector<size_t> nv;
-    size_t m = n;
-    while (m >= 2) {
-        double xm = 0.0, ym = 0.0;
-        for (size_t t = 0; t < m; ++t) {
-            xm = xm + x[t];
-            ym = ym + y[t];
-        }
-        xm = xm / (double)m;
-        ym = ym / (double)m;
-        double vx = 0.0, vy = 0.0, c = 0.0;
-        for (size_t t = 0; t < m; ++t) {
-            vx = vx + (x[t] - xm) * (x[t] - xm);
-            vy = vy + (y[t] - ym) * (y[t] - ym);
-            c = c + (x[t] - xm) * (y[t] - ym);
-        }
-        const double nn = (double)m * (double)(m - 1);
-        vx = vx / nn;
-        vy = vy / nn;
-        c = c / nn;
-        double var;
-        if (den) {
-            const double r = xm / ym;
-            var = r * r * (vx / (xm * xm) + vy / (ym * ym) - 2.0 * c / (xm * ym));
-        } else {
-            var = vx;
-        }
-        ev.push_back(std::sqrt(var > 0.0 ? var : 0.0));
-        nv.push_back(m);
-        const size_t h = m / 2;
-        for (size_t t = 0; t < h; ++t) {
-            x[t] = (x[2 * t] + x[2 * t + 1]) * 0.5;
-            y[t] = (y[2 * t] + y[2 * t + 1]) * 0.5;
-        }
-        m = h;
-    }
-    int chosen = -1, last_ok = -1;
-    for (size_t l = 0; l < ev.size(); ++l) {
-        if (nv[l] < 16) break;
-        last_ok = (int)l;
-        const double tol = ev[l] + ev[l] / std::sqrt(2.0 * (double)(nv[l] - 1));
-        bool ok = true;
-        for (size_t k = 1; k <= 2; ++k)
-            if (l + k < ev.size() && nv[l + k] >= 16 && ev[l + k] > tol) ok = false;
-        if (ok) {
-            chosen = (int)l;
-            break;
+class Blocker {
+  public:
+    void clear() { *this = Blocker(); }
+    int64_t count() const { return lev_[0].n; }
+
+    void add(double x, double y) {
+        for (int l = 0; l < kLevels; ++l) {
+            Level &L = lev_[l];
+            if (L.n == 0) {
+                L.x0 = x;
+                L.y0 = y;
+            }
+            const double dx = x - L.x0, dy = y - L.y0;
+            L.sx += dx;
+            L.sy += dy;
+            L.sxx += dx * dx;
+            L.syy += dy * dy;
+            L.sxy += dx * dy;
+            L.n += 1;
+            if (!L.pending) {
+                L.pending = true;
+                L.px = x;
+                L.py = y;
+                return;
+            }
+            L.pending = false;
+            x = (L.px + x) * 0.5;
+            y = (L.py + y) * 0.5;
         }
     }
-    if (chosen < 0) chosen = last_ok;
-    if (chosen >= 0) err = ev[chosen];
-}
+
+    // Mean of x / mean of y over all samples, and its error bar (NaN when no
+    // level has 16 blocks).
+    void result(double &mean, double &err) const {
+        mean = NAN;
+        err = NAN;
+        const Level &L0 = lev_[0];
+        if (L0.n == 0) return;
+        mean = (L0.x0 + L0.sx / (double)L0.n) / (L0.y0 + L0.sy / (double)L0.n);
+        double e[kLevels];
+        int top = 0;   // levels with >= 16 blocks: 0 .. top-1
+        while (top < kLevels && lev_[top].n >= 16) {
+            e[top] = level_error(lev_[top]);
+            ++top;
+        }
+        if (top == 0) return;
+        int pick = top - 1;
+        for (int l = 0; l < top; ++l) {
+            const double allow = e[l] * (1.0 + 1.0 / std::sqrt(2.0 * (double)(lev_[l].n - 1)));
+            const bool next_ok = l + 1 >= top || e[l + 1] <= allow;
+            const bool next2_ok = l + 2 >= top || e[l + 2] <= allow;
+            if (next_ok && next2_ok) {
+                pick = l;
+                break;
+            }
+        }
+        err = e[pick];
+    }
+
+  private:
+    static constexpr int kLevels = 64;
+    struct Level {
+        int64_t n = 0;
+        double x0 = 0, y0 = 0, sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
+        bool pending = false;
+        double px = 0, py = 0;
+    };
+    static double level_error(const Level &L) {
+        const double n = (double)L.n;
+        const double norm = n * (n - 1.0);
+        const double vx = (L.sxx - L.sx * L.sx / n) / norm;
+        const double vy = (L.syy - L.sy * L.sy / n) / norm;
+        const double cxy = (L.sxy - L.sx * L.sy / n) / norm;
+        const double xbar = L.x0 + L.sx / n, ybar = L.y0 + L.sy / n;
+        const double r = xbar / ybar;
+        const double v = (vx - 2.0 * r * cxy + r * r * vy) / (ybar * ybar);
+        return std::sqrt(v > 0.0 ? v : 0.0);
+    }
+    Level lev_[kLevels];
+};
 
 struct SysHost {
     bool active = false;
@@ -152,7 +174,8 @@ struct SysHost {
     // mirrored dynamics and statistics
     IterRecord last{};
     int64_t tot_att = 0, tot_sp = 0;
-    std::vector<double> s_num, s_den, s_shift;
+    int64_t redos = 0;         // iterations re-run after a table overflowed
+    Blocker e_blk, s_blk;      // (num, C_0) and (S, 1) samples of the averaging window
     int fatal = 0;
 };
 
@@ -199,7 +222,10 @@ struct fciqmc_t {
     hipEvent_t ev[NKERN + 1] = {};
     double kms[NKERN] = {};
     int64_t kcount[NKERN] = {};
+    double phase_ms[NKERN] = {};            // kernel groups of the last sampled iteration
     double ms_last = 0.0;
+    bool planner = true;                    // size tables before each launch (test knob)
+    int64_t tile_map_limit = -1;            // cap on the tile map (test knob; -1: none)
 };
 
 namespace {
@@ -320,9 +346,11 @@ int ensure_tile_map(fciqmc_t *h) {
     int64_t walkers = 0;
     for (int s = 0; s < h->max_sys; ++s)
         if (h->sys[s].active) walkers += std::max<int64_t>(h->sys[s].last.nw, 0);
-    const int64_t want = h->n_chunks + 2 * walkers / std::max(h->tile, 1) + 65536;
+    int64_t want = h->n_chunks + 2 * walkers / std::max(h->tile, 1) + 65536;
+    if (h->tile_map_limit >= 0) want = std::min<int64_t>(want, h->tile_map_limit);
     if (want <= h->tile_cap || h->tile_map_off) return 0;
-    const int64_t cap = std::max<int64_t>(want, 2 * h->tile_cap);
+    int64_t cap = std::max<int64_t>(want, 2 * h->tile_cap);
+    if (h->tile_map_limit >= 0) cap = std::min<int64_t>(cap, h->tile_map_limit);
     HIP_TRY(hipStreamSynchronize(h->stream));
     hipFree(h->d_tile_chunk);
     h->d_tile_chunk = nullptr;
@@ -809,7 +837,7 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
     o->aborted = r.aborted;
     o->total_attempts = S.tot_att;
     o->total_spawns = S.tot_sp;
-    o->n_samples = (int64_t)S.s_num.size();
+    o->n_samples = S.e_blk.count();
     o->n_var = h->hdesc[s].n_var;
     o->n_prev = h->hdesc[s].n_prev;
     o->table_slots = S.cap;
@@ -820,13 +848,18 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
     o->proj_num = r.num;
     o->e_proj_inst = r.c0 != 0 ? S.e0 + r.num / (double)r.c0 : NAN;
     double m, e;
-    blocking(S.s_num, &S.s_den, m, e);
+    S.e_blk.result(m, e);
     o->e_proj_mean = S.e0 + m;
     o->e_proj_err = e;
-    blocking(S.s_shift, nullptr, m, e);
+    S.s_blk.result(m, e);
     o->shift_mean = S.e0 + m;
     o->shift_err = e;
     o->ms_last_call = h->ms_last;
+    o->redos = S.redos;
+    o->ms_spawn = h->phase_ms[0] + h->phase_ms[1] + h->phase_ms[2];
+    o->ms_death = 0.0;   // death runs inside the annihilation pass
+    o->ms_annihilate = h->phase_ms[3];
+    o->ms_estimators = h->phase_ms[4];
     o->shift_varying = h->hdesc[s].varying;
     o->status = S.fatal;
     return 0;
@@ -849,7 +882,7 @@ int refresh_stats_after_load(fciqmc_t *h, int s, const std::vector<uint64_t> &de
     return 0;
 }
 
-int run_iterations(fciqmc_t *h, int L);
+int run_iterations(fciqmc_t *h, int L, bool sample);
 
 int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     auto it = h->graphs.find(L);
@@ -885,6 +918,7 @@ int plan_launch(fciqmc_t *h, int L, int *L_out) {
         const int64_t g = std::max<int64_t>(S.growth, 256);
         const int64_t limit = S.cap * 7 / 10;
         int64_t used = std::max<int64_t>(S.last.used, S.last.nd);
+        if (!h->planner) continue;   // overflows are left to the grow-and-redo path
         if (used + 4 * g > limit) {
             // Rehash for 50 % load after 8 more iterations of growth. Vacated slots
             // are what fills a table whose live count has levelled off, so while
@@ -905,8 +939,10 @@ int plan_launch(fciqmc_t *h, int L, int *L_out) {
     return 0;
 }
 
-// Launch L iterations (graph or direct), then read records and statuses.
-int run_iterations(fciqmc_t *h, int L) {
+// Launch L iterations (graph or direct), then read records and statuses. With
+// `sample` the last iteration runs as direct launches bracketed by events, which
+// gives the per-phase device times of one iteration on the graph path too.
+int run_iterations(fciqmc_t *h, int L, bool sample) {
     std::vector<int64_t> before(h->max_sys);
     for (int s = 0; s < h->max_sys; ++s) before[s] = h->hdesc[s].iter;
     int rc = ensure_tile_map(h);
@@ -927,10 +963,23 @@ int run_iterations(fciqmc_t *h, int L) {
         }
         HIP_TRY(hipGetLastError());
     } else if (h->use_graph) {
-        hipGraphExec_t ex = nullptr;
-        rc = capture_or_get(h, L, &ex);
-        if (rc) return rc;
-        HIP_TRY(hipGraphLaunch(ex, h->stream));
+        const int Lg = sample ? L - 1 : L;
+        if (Lg > 0) {
+            hipGraphExec_t ex = nullptr;
+            rc = capture_or_get(h, Lg, &ex);
+            if (rc) return rc;
+            HIP_TRY(hipGraphLaunch(ex, h->stream));
+        }
+        if (sample) {
+            launch_iteration(a, h->post_grid, h->spawn_grid, true, h->stream, h->ev);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipEventSynchronize(h->ev[NKERN]));
+            for (int k = 0; k < NKERN; ++k) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+                h->phase_ms[k] = ms;
+            }
+        }
     } else {
         for (int i = 0; i < L; ++i)
         launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
@@ -955,9 +1004,8 @@ int run_iterations(fciqmc_t *h, int L) {
                 S.tot_att += r.attempts;
                 S.tot_sp += r.spawns;
                 if (r.varying && r.iter - r.n_var >= S.prm.avg_start) {
-                    S.s_num.push_back(r.num);
-                    S.s_den.push_back((double)r.c0);
-                    S.s_shift.push_back(r.shift);
+                    S.e_blk.add(r.num, (double)r.c0);
+                    S.s_blk.add(r.shift, 1.0);
                 }
                 S.last = r;
             }
@@ -968,6 +1016,7 @@ int run_iterations(fciqmc_t *h, int L) {
         uint32_t &st = h->hstatus[s];
         if (st & ST_TABLE_FULL) {
             st &= ~ST_TABLE_FULL;
+            S.redos += 1;
             rc = reset_spawns(h, s);
             if (rc) return rc;
             rc = grow_system(h, s, S.cap * 2);
@@ -999,7 +1048,8 @@ int iterate_each(fciqmc_t *h, const std::vector<int64_t> &n) {
         int L = 0;
         int rc = plan_launch(h, (int)std::min<int64_t>(rem, MAX_GRAPH_ITERS), &L);
         if (rc) return rc;
-        rc = run_iterations(h, L);
+        // the launch that ends the call samples the per-phase times of its last iteration
+        rc = run_iterations(h, L, L >= rem);
         if (rc) return rc;
     }
     HIP_TRY(hipEventRecord(t1, h->stream));
@@ -1016,6 +1066,7 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     fciqmc_t *h = new (std::nothrow) fciqmc_t();
     if (!h) return set_err(FCIQMC_ENOMEM, "host allocation failed");
     HIP_TRY(hipGetDevice(&h->dev));
+
     if (stream) {
         h->stream = (hipStream_t)stream;
     } else {
@@ -1274,9 +1325,8 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
     d.n_var = n_var;
     int rc = load_list(h, s, dv, pv);
     if (rc) return rc;
-    S.s_num.clear();
-    S.s_den.clear();
-    S.s_shift.clear();
+    S.e_blk.clear();
+    S.s_blk.clear();
     S.fatal = 0;
     refresh_stats_after_load(h, s, dv, pv, NAN);
     return upload_desc(h);
@@ -1291,9 +1341,8 @@ int fciqmc_set_shift(fciqmc_t *h, double shift, int32_t varying) {
         d.n_prev = h->sys[0].last.nw;
         d.n_var = d.iter;
     }
-    h->sys[0].s_num.clear();
-    h->sys[0].s_den.clear();
-    h->sys[0].s_shift.clear();
+    h->sys[0].e_blk.clear();
+    h->sys[0].s_blk.clear();
     return upload_desc(h);
 }
 
@@ -1446,6 +1495,30 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
         h->kcount[k] = 0;
     }
     drop_graphs(h);
+    return 0;
+}
+
+int fciqmc_blocking(const double *num, const double *den, int64_t n, double *mean, double *err) {
+    if (n < 0 || (n > 0 && !num) || !mean || !err) return set_err(FCIQMC_EINVAL, "bad argument");
+    Blocker b;
+    for (int64_t t = 0; t < n; ++t) b.add(num[t], den ? den[t] : 1.0);
+    b.result(*mean, *err);
+    return 0;
+}
+
+int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    if (tile_map_limit < -1) return set_err(FCIQMC_EINVAL, "tile_map_limit must be >= -1");
+    h->planner = planner != 0;
+    if (tile_map_limit != h->tile_map_limit) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        hipFree(h->d_tile_chunk);
+        h->d_tile_chunk = nullptr;
+        h->tile_cap = 0;
+        h->tile_map_off = false;
+        h->tile_map_limit = tile_map_limit;
+        drop_graphs(h);
+    }
     return 0;
 }
 

@@ -668,11 +668,15 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
 // done by atomics): find or claim the determinant's slot by linear probing
 // (one compare-and-swap per probe: it claims an empty slot or returns the key
 // there), then add (initiator ? 2^32 : 0) + v to the slot's accumulator with
-// one atomic whose result is not needed.
+// one atomic whose result is not needed. A probe sequence longer than
+// PROBE_LIMIT (far beyond any run at the 70 % load the tables are kept under)
+// reports the table full: the iteration is then re-run after growth.
+constexpr uint64_t PROBE_LIMIT = 4096;
 __device__ __forceinline__ bool table_add(uint64_t *key, long long *acc, uint64_t cap, uint64_t k,
                                           int32_t v, bool init) {
     uint64_t h = home_slot(k, cap);
-    for (uint64_t n = 0; n < cap; ++n) {
+    const uint64_t lim = cap < PROBE_LIMIT ? cap : PROBE_LIMIT;
+    for (uint64_t n = 0; n < lim; ++n) {
         uint64_t expect = 0;
         if (__hip_atomic_compare_exchange_strong(gp(&key[h]), &expect, k, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
@@ -754,7 +758,9 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
     __syncthreads();
     const int t = threadIdx.x;
     uint32_t *status = &a.status[s];
-    const int nsgl = Q.nsgl < SGL_QUEUE ? Q.nsgl : SGL_QUEUE;
+    // a system whose table overflowed re-runs the iteration: drop its queued work
+    const bool dead = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)status) != 0;
+    const int nsgl = dead ? 0 : (Q.nsgl < SGL_QUEUE ? Q.nsgl : SGL_QUEUE);
     for (int j = t; j < nsgl; j += blockDim.x) {
         const SingleItem it = Q.sgl[j];
         Excit ex;
@@ -778,7 +784,7 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         }
     }
     __syncthreads();
-    const int nspw = Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE;
+    const int nspw = dead ? 0 : (Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE);
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
         if (!table_add(d.key, d.acc, d.cap, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
@@ -933,11 +939,13 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         const unsigned long long tt = (unsigned long long)t;
         unsigned long long at = lo_t + tt * q_t + (tt < r_t ? tt : r_t);
         const unsigned long long at_end = at + q_t + (tt < r_t ? 1ull : 0ull);
+        // no attempts for a system that has stopped this iteration (its table overflowed)
+        const bool stopped = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)status) != 0;
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
         const bool c1 = d.n_class == 2;          // no point group: classes are the spins
         ClassView<true> cv1{d.valid, nullptr};
         ClassView<false> cvg{d.valid, s_cm};
-        if (at < at_end) {
+        if (at < at_end && !stopped) {
             const unsigned long long local = at - off_c;
             int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
             while (sl < hi) {

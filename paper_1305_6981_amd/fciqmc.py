@@ -49,7 +49,9 @@ _EST_DBL = ("shift", "e_ref", "p_double", "proj_num", "e_proj_inst", "e_proj_mea
 
 class Estimates(C.Structure):
     _fields_ = [(n, C.c_int64) for n in _EST_INT] + [(n, C.c_double) for n in _EST_DBL] + \
-               [("shift_varying", C.c_int32), ("status", C.c_int32)]
+               [("shift_varying", C.c_int32), ("status", C.c_int32), ("redos", C.c_int64)] + \
+               [(n, C.c_double) for n in ("ms_spawn", "ms_death", "ms_annihilate",
+                                          "ms_estimators")]
 
 
 EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
@@ -59,7 +61,8 @@ EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
             "fciqmc_batch_admit", "fciqmc_batch_retire", "fciqmc_batch_slot_estimators",
             "fciqmc_batch_slot_walkers", "fciqmc_footprint_bytes", "fciqmc_batch_active",
             "fciqmc_set_profiling", "fciqmc_kernel_times", "fciqmc_set_launch",
-            "fciqmc_get_launch", "fciqmc_autotune"]
+            "fciqmc_get_launch", "fciqmc_autotune", "fciqmc_blocking",
+            "fciqmc_set_test_options"]
 
 
 def lib():
@@ -95,6 +98,9 @@ def lib():
             "fciqmc_set_launch": ([vp, i32, i32, i32], C.c_int),
             "fciqmc_get_launch": ([vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)], C.c_int),
             "fciqmc_autotune": ([vp, i32], C.c_int),
+            "fciqmc_blocking": ([vp, vp, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+                                C.c_int),
+            "fciqmc_set_test_options": ([vp, i32, i64], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -292,6 +298,19 @@ def fciqmc_get_launch(handle):
 def fciqmc_autotune(handle, iters_per_trial=2):
     _check(lib().fciqmc_autotune(handle, iters_per_trial))
     return fciqmc_get_launch(handle)
+
+
+def fciqmc_blocking(num, den=None):
+    """(mean, error) of <num>/<den> (or <num>) by the library's blocking analysis."""
+    num = np.ascontiguousarray(num, dtype=np.float64)
+    d = None if den is None else np.ascontiguousarray(den, dtype=np.float64)
+    m, e = C.c_double(), C.c_double()
+    _check(lib().fciqmc_blocking(_ptr(num), _ptr(d), len(num), C.byref(m), C.byref(e)))
+    return m.value, e.value
+
+
+def fciqmc_set_test_options(handle, planner=1, tile_map_limit=-1):
+    _check(lib().fciqmc_set_test_options(handle, int(planner), int(tile_map_limit)))
 
 
 class Solver:

@@ -46,8 +46,8 @@ def star(leaves=(P1, P2, P3), ref_linked=False, hub_diag=0.0) -> S.Hamiltonian:
                          name="star5")
 
 
-def params(seed: int = 11, iteration: int = 0) -> S.Params:
-    return S.Params(tau=TAU, initiator_threshold=N_A, target_walkers=10**9, seed=seed,
+def params(seed: int = 11, tau: float = TAU) -> S.Params:
+    return S.Params(tau=tau, initiator_threshold=N_A, target_walkers=10**9, seed=seed,
                     shift_update_every=1)
 
 
@@ -56,10 +56,10 @@ def as_dict(walkers):
     return dict(zip((int(x) for x in d), (int(x) for x in p)))
 
 
-def one_step(make, ham, entries, seed: int = 11, iteration: int = 0):
+def one_step(make, ham, entries, seed: int = 11, iteration: int = 0, tau: float = TAU):
     """Load `entries` [(orbital, population)], run one iteration; return the walker
     list as {det: pop} and the estimates."""
-    run = make(ham, params(seed))
+    run = make(ham, params(seed, tau))
     try:
         run.load_walkers(np.array([det(o) for o, _ in entries], np.uint64),
                          np.array([p for _, p in entries], np.int32), iteration=iteration)
@@ -136,6 +136,17 @@ def check_reference_is_always_initiator(make):
     w, e = one_step(make, ham, [(REF, N_A)])
     assert e["spawns"] > 0 and e["aborted"] == 0
     assert w[det(HUB)] == e["spawns"]
+
+
+def check_multi_walker_spawns(make):
+    """tau |h| / pgen above 1 (Eq. pspawn): tau = 0.5 gives exactly 2 walkers per
+    spawn onto the hub, tau = 0.6 gives 2 or 3 (2 + Bernoulli(0.4))."""
+    ham = star(leaves=(P1,))
+    w, e = one_step(make, ham, [(P1, N_A + 1), (REF, 10)], tau=0.5)
+    assert e["spawns"] > 0 and w[det(HUB)] == 2 * e["spawns"]
+    w, e = one_step(make, ham, [(P1, -(N_A + 1)), (REF, 10)], tau=0.6)
+    n = e["spawns"]
+    assert n > 0 and -3 * n < w[det(HUB)] < -2 * n    # some 3s, not all (P = 0.4 each)
 
 
 def check_shift_schedule(make, ham, prm, n_iter):

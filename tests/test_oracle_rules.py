@@ -69,3 +69,7 @@ def test_initiator_energy_with_shift_update_every_ten_matches_ed():
     assert e["n_samples"] > 1000
     assert abs(e["e_proj_mean"] - exact) < 4 * e["e_proj_err"] + 1e-4
     assert abs(e["shift_mean"] - exact) < 4 * e["shift_err"] + 2e-3
+
+
+def test_spawning_more_than_one_walker():
+    R.check_multi_walker_spawns(make)
