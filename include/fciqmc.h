@@ -243,6 +243,21 @@ int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t pos
 int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *post_grid);
 int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial);
 
+/* ---- export without allocation ------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as fciqmc_walkers (system 0, sorted by determinant, flags as there),
+ * staged on the device in a fixed area that the library holds on each GPU
+ * until the process ends (32 MiB + 256 B: at most 2^21 = 2097152 occupied
+ * determinants), so the call allocates nothing. Every call on one GPU shares
+ * that GPU's area: calls that overlap in time on one GPU (from several host
+ * threads or handles) race and must be serialised by the caller. Returns the
+ * number of occupied determinants (only min(n, cap) entries are written), or
+ * ECAPACITY when the list exceeds 2^21 determinants (nothing written),
+ * EINVAL, ESTATE, EDEVICE. */
+int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags,
+                               int64_t cap);
+
 /* ---- error bars -------------------------------------------------------------
  * The blocking analysis behind e_proj_err / shift_err, for a caller's own
  * series (host only, no device work): blocks of 2^l consecutive samples are

@@ -111,6 +111,15 @@ struct EngineArgs {
     int64_t tile_cap;                // beyond the capacity are found by search
 };
 
+// Staging area of the export that allocates nothing (fciqmc_walkers_noalloc): a
+// 64-bit counter, then keys, populations and initiator flags of up to
+// NOALLOC_MAX_DETS entries (32 MiB + 256 B).
+constexpr int64_t NOALLOC_MAX_DETS = (int64_t)1 << 21;
+constexpr size_t NOALLOC_KEYS_OFF = 256;
+constexpr size_t NOALLOC_VALS_OFF = NOALLOC_KEYS_OFF + 8 * (size_t)NOALLOC_MAX_DETS;
+constexpr size_t NOALLOC_FLAGS_OFF = NOALLOC_VALS_OFF + 4 * (size_t)NOALLOC_MAX_DETS;
+constexpr size_t NOALLOC_BYTES = NOALLOC_FLAGS_OFF + 4 * (size_t)NOALLOC_MAX_DETS;
+
 // Kernel launchers (kernels.hip).
 constexpr int NKERN = 5;   // profiled kernel groups: chunk sums, scans, spawn, post, finalize
 // first: the chunk sums are taken from the tables (the first iteration of a launch, after
@@ -125,6 +134,14 @@ hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,
                          hipStream_t s);
 hipError_t launch_compact(const uint64_t *key, const int32_t *pop, int64_t cap, uint64_t *out_det,
                           int32_t *out_pop, unsigned long long *count, hipStream_t s);
+// Export into the staging area `stage` (NOALLOC layout): compaction of the occupied
+// slots (entries past NOALLOC_MAX_DETS are counted, not written), then a bitonic
+// sort by determinant of the first n entries padded to a power of two.
+hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, int64_t cap, void *stage,
+                                hipStream_t s);
+hipError_t launch_stage_sort(void *stage, int64_t n, hipStream_t s);
+// Initiator flag of each of the n sorted entries: |pop| > n_a, or the reference.
+hipError_t launch_stage_flags(void *stage, int64_t n, int32_t n_a, uint64_t d0, hipStream_t s);
 hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s);
 int spawn_grid_size();
 int post_grid_size();

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,12 @@
 #include "engine.h"
 
 using namespace fq;
+
+// Device staging area of fciqmc_walkers_noalloc (every call on a GPU shares
+// that GPU's copy). Host code never uses this name as an address: the address
+// of each device's copy is taken once per device with hipGetSymbolAddress when
+// the first handle on that device is created, and passed to the kernels.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
 
 namespace {
 
@@ -205,6 +212,7 @@ struct fciqmc_t {
     uint32_t *d_tile_chunk = nullptr;       // chunk of each spawn tile
     bool tile_map_off = false;              // its allocation failed once: search instead
     void *d_scratch = nullptr;              // scratch table for compaction in place
+    void *d_stage = nullptr;                // this device's staging area (not owned)
     size_t scratch_bytes = 0;
     int64_t tile_cap = 0;
     unsigned long long *d_blk = nullptr;    // [2][4][SCAN_G] range sums and scans
@@ -1062,11 +1070,36 @@ int iterate_each(fciqmc_t *h, const std::vector<int64_t> &n) {
     return 0;
 }
 
+// Address of the staging area on each device (resolved once per device, with
+// that device current).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_stage_mu;
+void *g_stage_ptr[MAX_DEVICES] = {};
+
+int resolve_stage(int dev, void **out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return set_err(FCIQMC_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    if (!g_stage_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return set_err(FCIQMC_EDEVICE, "staging area has no device address");
+        g_stage_ptr[dev] = p;
+    }
+    *out = g_stage_ptr[dev];
+    return 0;
+}
+
 int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     fciqmc_t *h = new (std::nothrow) fciqmc_t();
     if (!h) return set_err(FCIQMC_ENOMEM, "host allocation failed");
     HIP_TRY(hipGetDevice(&h->dev));
-
+    {
+        const int rc = resolve_stage(h->dev, &h->d_stage);
+        if (rc) {
+            delete h;
+            return rc;
+        }
+    }
     if (stream) {
         h->stream = (hipStream_t)stream;
     } else {
@@ -1520,6 +1553,41 @@ int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit
         drop_graphs(h);
     }
     return 0;
+}
+
+int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags,
+                               int64_t cap) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    if (cap < 0) return set_err(FCIQMC_EINVAL, "cap must be >= 0");
+    const int s = 0;
+    const SysHost &S = h->sys[s];
+    if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
+    HIP_TRY(launch_stage_compact(S.key, S.pop, S.cap, h->d_stage, h->stream));
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, h->d_stage, sizeof n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if ((int64_t)n > NOALLOC_MAX_DETS)
+        return set_err(FCIQMC_ECAPACITY, "walker list of " + std::to_string(n) +
+                                             " determinants exceeds the staging limit of " +
+                                             std::to_string(NOALLOC_MAX_DETS));
+    const int64_t m = std::min<int64_t>((int64_t)n, cap);
+    if (m > 0 && (det || pop || flags)) {
+        HIP_TRY(launch_stage_sort(h->d_stage, (int64_t)n, h->stream));
+        if (flags)
+            HIP_TRY(launch_stage_flags(h->d_stage, m, S.prm.initiator_threshold, S.d0, h->stream));
+        const char *p = (const char *)h->d_stage;
+        if (det)
+            HIP_TRY(hipMemcpyAsync(det, p + NOALLOC_KEYS_OFF, (size_t)m * 8, hipMemcpyDeviceToHost,
+                                   h->stream));
+        if (pop)
+            HIP_TRY(hipMemcpyAsync(pop, p + NOALLOC_VALS_OFF, (size_t)m * 4, hipMemcpyDeviceToHost,
+                                   h->stream));
+        if (flags)
+            HIP_TRY(hipMemcpyAsync(flags, p + NOALLOC_FLAGS_OFF, (size_t)m * 4,
+                                   hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    return (int64_t)n;
 }
 
 int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]) {

@@ -1457,6 +1457,113 @@ hipError_t launch_compact(const uint64_t *kv, const int32_t *pop, int64_t cap, u
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Export through a fixed staging area (no allocation): the counter is cleared by
+// a kernel (no memset node), the occupied slots are compacted with one counter
+// atomic per wavefront, and the keys are sorted by a bitonic network over the
+// next power of two (padding keys ~0 sort last).
+// ---------------------------------------------------------------------------
+__global__ void k_stage_clear(unsigned long long *count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_stage_compact(const uint64_t *kv, const int32_t *pop,
+                                                       int64_t cap, unsigned long long *count,
+                                                       uint64_t *okey, int32_t *oval) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cap;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t D = i < cap ? kv[i] : 0ull;
+        const int32_t p = i < cap ? pop[i] : 0;
+        const bool take = D != 0ull && p != 0;
+        const uint64_t m = __ballot(take);
+        if (!m) continue;
+        unsigned long long b = 0;
+        const int first = __builtin_ctzll(m);
+        if (lane == first) b = atomicAdd(count, (unsigned long long)__popcll(m));
+        b = __shfl(b, first, 64);
+        if (take) {
+            const unsigned long long j = b + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+            if (j < (unsigned long long)NOALLOC_MAX_DETS) {
+                okey[j] = D;
+                oval[j] = p;
+            }
+        }
+    }
+}
+
+__global__ void k_stage_pad(uint64_t *key, int64_t n, int64_t P) {
+    for (int64_t i = n + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P;
+         i += (int64_t)gridDim.x * blockDim.x)
+        key[i] = ~0ull;
+}
+
+__global__ void k_stage_bitonic(uint64_t *key, int32_t *val, int64_t P, int64_t j, int64_t k) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = i ^ j;
+        if (l <= i) continue;
+        const bool up = (i & k) == 0;
+        const uint64_t a = key[i], b = key[l];
+        if ((a > b) == up) {
+            key[i] = b;
+            key[l] = a;
+            const int32_t t = val[i];
+            val[i] = val[l];
+            val[l] = t;
+        }
+    }
+}
+
+__global__ void k_stage_flags(const uint64_t *key, const int32_t *val, int64_t n, int32_t n_a,
+                              uint64_t d0, uint32_t *flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = val[i] < 0 ? -(int64_t)val[i] : (int64_t)val[i];
+        flags[i] = (a > (int64_t)n_a || key[i] == d0) ? 1u : 0u;
+    }
+}
+
+hipError_t launch_stage_flags(void *stage, int64_t n, int32_t n_a, uint64_t d0, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    char *p = (char *)stage;
+    const int64_t g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_stage_flags, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, s,
+                       (const uint64_t *)(p + NOALLOC_KEYS_OFF), (const int32_t *)(p + NOALLOC_VALS_OFF),
+                       n, n_a, d0, (uint32_t *)(p + NOALLOC_FLAGS_OFF));
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, int64_t cap, void *stage,
+                                hipStream_t s) {
+    char *p = (char *)stage;
+    unsigned long long *count = (unsigned long long *)p;
+    hipLaunchKernelGGL(k_stage_clear, dim3(1), dim3(64), 0, s, count);
+    const int64_t g = (cap + 255) / 256;
+    hipLaunchKernelGGL(k_stage_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
+                       key, pop, cap, count, (uint64_t *)(p + NOALLOC_KEYS_OFF),
+                       (int32_t *)(p + NOALLOC_VALS_OFF));
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_sort(void *stage, int64_t n, hipStream_t s) {
+    if (n > NOALLOC_MAX_DETS) return hipErrorInvalidValue;
+    char *p = (char *)stage;
+    uint64_t *key = (uint64_t *)(p + NOALLOC_KEYS_OFF);
+    int32_t *val = (int32_t *)(p + NOALLOC_VALS_OFF);
+    int64_t P = 1;
+    while (P < n) P <<= 1;
+    if (P < 2) return hipSuccess;
+    const int64_t g = (P + 255) / 256;
+    const unsigned grid = (unsigned)(g < 8192 ? g : 8192);
+    hipLaunchKernelGGL(k_stage_pad, dim3(grid), dim3(256), 0, s, key, n, P);
+    for (int64_t k = 2; k <= P; k <<= 1)
+        for (int64_t j = k >> 1; j > 0; j >>= 1)
+            hipLaunchKernelGGL(k_stage_bitonic, dim3(grid), dim3(256), 0, s, key, val, P, j, k);
+    return hipGetLastError();
+}
+
 __global__ void k_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *out = hdiag_of(desc[sys], det);
 }

@@ -62,7 +62,7 @@ EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
             "fciqmc_batch_slot_walkers", "fciqmc_footprint_bytes", "fciqmc_batch_active",
             "fciqmc_set_profiling", "fciqmc_kernel_times", "fciqmc_set_launch",
             "fciqmc_get_launch", "fciqmc_autotune", "fciqmc_blocking",
-            "fciqmc_set_test_options"]
+            "fciqmc_set_test_options", "fciqmc_walkers_noalloc"]
 
 
 def lib():
@@ -101,6 +101,7 @@ def lib():
             "fciqmc_blocking": ([vp, vp, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
                                 C.c_int),
             "fciqmc_set_test_options": ([vp, i32, i64], C.c_int),
+            "fciqmc_walkers_noalloc": ([vp, vp, vp, vp, i64], i64),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -197,6 +198,17 @@ def _walkers(fn, *lead):
 
 def fciqmc_walkers(handle):
     return _walkers(lib().fciqmc_walkers, handle)
+
+
+def fciqmc_walkers_noalloc(handle, det, pop, flags):
+    """Fill the caller's arrays (any may be None; the shortest non-None length is the
+    capacity) through the library's fixed staging area; returns the determinant count."""
+    arrs = [a for a in (det, pop, flags) if a is not None]
+    cap = min(len(a) for a in arrs) if arrs else 0
+    for a, dt in ((det, np.uint64), (pop, np.int32), (flags, np.uint32)):
+        if a is not None:
+            assert a.dtype == dt and a.flags.c_contiguous
+    return _check(lib().fciqmc_walkers_noalloc(handle, _ptr(det), _ptr(pop), _ptr(flags), cap))
 
 
 def fciqmc_load_walkers(handle, det, pop, iteration=0, shift=0.0, n_prev=0, varying=0, n_var=0):
