@@ -118,8 +118,12 @@ typedef struct {
     double ms_last_call;        /* wall time of the last fciqmc_iterate on this handle */
     int32_t shift_varying;
     int32_t status;             /* 0, or the FCIQMC_E* code that stopped this system */
-    int64_t redos;              /* total: iterations re-run after a table overflowed (each
-                                   re-run is bit-identical to an uninterrupted one) */
+    int64_t redos;              /* total: iterations re-run after the spawn-record buffer
+                                   overflowed (each re-run is bit-identical to an
+                                   uninterrupted one) */
+    int64_t spills;             /* total: iterations whose new determinants overflowed
+                                   their bucket (completed through the spill list, then
+                                   re-bucketed; results unaffected) */
     /* Device time (ms) of the phases of one iteration of the handle: the last
      * iteration of the last fciqmc_iterate call runs as direct launches bracketed
      * by events (the others run in graphs). Spawning includes the attempt mapping
@@ -269,13 +273,17 @@ int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_
 int fciqmc_blocking(const double *num, const double *den, int64_t n, double *mean, double *err);
 
 /* ---- test knobs -------------------------------------------------------------
- * planner = 0: do not size tables before each launch, so that overflows are
- * met inside an iteration and handled by the grow-and-redo path (counted in
- * fciqmc_estimates.redos); tile_map_limit >= 0 caps the map from spawn tiles to
- * chunks at that many entries (0: no map), so tile grabs beyond it search the
- * chunk offsets instead; -1 restores the default. Results do not depend on
- * either. Errors: EINVAL. */
-int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit);
+ * planner = 0: do not size the buckets or the spawn-record buffer before each
+ * launch, so that overflows are met inside an iteration: an overflowing record
+ * buffer abandons the iteration, grows and re-runs it (fciqmc_estimates.redos),
+ * an overflowing bucket completes the iteration through the spill list and is
+ * re-bucketed (fciqmc_estimates.spills). record_capacity > 0 replaces the record
+ * buffer by one of that many records now (0: leave it). tile_map_limit >= 0 caps
+ * the map from spawn tiles to buckets at that many entries (0: no map), so tile
+ * grabs beyond it search the bucket offsets instead; -1 restores the default.
+ * Results do not depend on any of these. Errors: EINVAL, ENOMEM. */
+int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit,
+                            int64_t record_capacity);
 
 #ifdef __cplusplus
 }

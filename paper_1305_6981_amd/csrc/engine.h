@@ -5,7 +5,9 @@
 
 namespace fq {
 
-constexpr int CHUNK = 1024;          // main-table slots per chunk (one workgroup's unit)
+constexpr int CHUNK = 1024;          // entries per bucket of the main list: the unit of
+                                     // attempt mapping, spawn staging and annihilation
+constexpr int BUCKET_FILL = 512;     // planned mean entries per bucket (half full)
 constexpr int NCLASS = 16;           // symmetry classes: 2 spins x up to 8 abelian irreps
 constexpr int REC_CAP = 256;         // per-system ring of per-iteration records
 constexpr int MAX_GRAPH_ITERS = 64;  // iterations captured in one graph launch
@@ -14,23 +16,28 @@ constexpr int SCAN_G = 2048;         // workgroups of the chunk-sum and scan-dow
 constexpr int FIN_BLOCKS = 64;       // workgroups per system reducing the chunk statistics
 
 // Status bits set on the device.
-constexpr uint32_t ST_TABLE_FULL = 1u;     // a spawn found no free slot: grow and redo
+constexpr uint32_t ST_TABLE_FULL = 1u;     // the spawn-record buffer overflowed: the iteration
+                                           // is abandoned, the buffer grown, the iteration redone
 constexpr uint32_t ST_POP_OVERFLOW = 2u;   // a population left int32
 constexpr uint32_t ST_DIED = 4u;           // N_w reached zero
 constexpr uint32_t ST_SPAWN_OVERFLOW = 8u; // one spawning event would create > 2^30 walkers
+constexpr uint32_t ST_SPILLED = 16u;       // new determinants did not fit their bucket: the
+                                           // iteration completed with them in the spill list,
+                                           // the system pauses until the host re-buckets
+constexpr uint32_t ST_SPILL_FULL = 32u;    // the spill list itself overflowed (fatal)
 
 
 struct IterRecord {
     int64_t iter;      // completed iterations after this one
     int64_t nw, nd, c0, attempts, spawns, merged, aborted;
-    int64_t used;      // table slots holding a key (occupied + vacated) after the iteration
+    int64_t used;      // entries in the buckets after the iteration (occupied + the reference)
     int64_t n_var, n_prev;
     double num, shift;
     int32_t varying, status;
 };
 
-// Per-chunk statistics of an iteration. counts packs three numbers of at most
-// CHUNK each: slots holding a key | merged spawn targets << 21 | occupied << 42.
+// Per-bucket statistics of an iteration. counts packs three numbers of at most
+// 2 CHUNK each: entries | merged spawn targets << 21 | occupied << 42.
 struct ChunkStat {
     int64_t nw, aborted;
     uint64_t counts;
@@ -68,14 +75,15 @@ struct SysDesc {
     const double *h1, *eri;
     const double *jk;                // [n_so][64]: (pp|qq) - (pq|qp) for p < q, spin orbitals
     const double *t3;                // [n_so][64][64]: (pa|qq) - d(s_p,s_q)(pq|qa), same-spin p, a
-    uint64_t *key;                   // main table (structure of arrays): determinant, 0 = empty
-    long long *acc;                  // walkers spawned onto the slot this iteration:
-                                     // (initiator spawns) * 2^32 + (signed walker sum), one
-                                     // 64-bit integer sum, so a spawn is one atomic add
-    int32_t *pop;                    // signed walker count (0: vacated or not yet occupied)
-    double *hdiag;                   // stored H_DD; NaN until the determinant is first occupied
-    uint64_t cap;                    // table slots, a multiple of 4 CHUNK
-    int64_t nchunks, gchunk0;        // chunks of this system and the first global chunk
+    // Main list: nb buckets of CHUNK entries (structure of arrays); a determinant lives
+    // in bucket floor(mix64(D) nb / 2^64), the entries of bucket b are the first
+    // bcnt[b] of [b CHUNK, (b+1) CHUNK), every one occupied (the reference may sit at 0).
+    uint64_t *key;                   // determinant
+    int32_t *pop;                    // signed walker count
+    double *hdiag;                   // stored H_DD
+    int32_t *bcnt;                   // entries per bucket
+    uint64_t cap;                    // nb * CHUNK
+    int64_t nchunks, gchunk0;        // buckets (= chunks) of this system and the first global one
     int64_t stop_at;                 // iterate while iter < stop_at
     // --- updated on the device
     int64_t iter;
@@ -109,6 +117,27 @@ struct EngineArgs {
     IterRecord *rec;                 // [max_sys][REC_CAP]
     uint32_t *tile_chunk;            // [tile_cap] chunk of each spawn tile (k_scan_down); tiles
     int64_t tile_cap;                // beyond the capacity are found by search
+    // Spawn records of the iteration (the per-destination blocks of Sec. 4.1, with the
+    // bucket as destination): appended by k_spawn, counted per bucket, sorted by bucket.
+    uint64_t *rec_det;               // [rec_cap] child determinant
+    int32_t *rec_w;                  // [rec_cap] signed walkers
+    uint32_t *rec_gf;                // [rec_cap] system (from k_spawn), then global bucket
+                                     // (from k_hist) | initiator flag << 31
+    uint64_t *srt_det;               // [rec_cap] the records grouped by bucket
+    int32_t *srt_w;
+    uint32_t *srt_f;                 // bit 0 initiator flag, bit 1 deferred to a later round
+    unsigned long long *rec_count;   // records appended this iteration
+    int64_t rec_cap;
+    uint32_t *bhist;                 // [chunk_cap] records per bucket
+    uint32_t *bcur;                  // [chunk_cap] scatter cursor per bucket
+    uint32_t *boff;                  // [chunk_cap] first sorted record of each bucket
+    // New determinants that did not fit their bucket (completed, then re-bucketed by the host).
+    uint64_t *sp_det;
+    int32_t *sp_pop, *sp_sys;
+    double *sp_hd;
+    unsigned long long *sp_count;
+    int64_t sp_cap;
+    uint32_t *spilled;               // [max_sys] set by k_post when a bucket spilled
 };
 
 // Staging area of the export that allocates nothing (fciqmc_walkers_noalloc): a
@@ -121,24 +150,29 @@ constexpr size_t NOALLOC_FLAGS_OFF = NOALLOC_VALS_OFF + 4 * (size_t)NOALLOC_MAX_
 constexpr size_t NOALLOC_BYTES = NOALLOC_FLAGS_OFF + 4 * (size_t)NOALLOC_MAX_DETS;
 
 // Kernel launchers (kernels.hip).
-constexpr int NKERN = 5;   // profiled kernel groups: chunk sums, scans, spawn, post, finalize
+constexpr int NKERN = 5;   // profiled kernel groups: chunk sums, scans, spawn, annihilation
+                           // (record sort + death/annihilation pass), statistics/shift
 // first: the chunk sums are taken from the tables (the first iteration of a launch, after
 // any host-side change); later iterations use the sums the previous iteration's k_post wrote.
 void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool first,
                       hipStream_t s, hipEvent_t *ev /* NKERN + 1 events or nullptr */);
 hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
                        int64_t n, uint32_t *d_err, hipStream_t s);
-hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,
-                         const int32_t *src_pop, const double *src_hd, int64_t src_cap,
-                         uint64_t *dst_key, int32_t *dst_pop, double *dst_hd, uint32_t *d_err,
-                         hipStream_t s);
-hipError_t launch_compact(const uint64_t *key, const int32_t *pop, int64_t cap, uint64_t *out_det,
-                          int32_t *out_pop, unsigned long long *count, hipStream_t s);
+// Move every entry of the buckets (src_*, src_nb buckets, counts src_cnt) and the spill
+// entries of system sys into the descriptor's (empty) buckets.
+hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,
+                           const int32_t *src_pop, const double *src_hd, const int32_t *src_cnt,
+                           int64_t src_nb, const uint64_t *sp_det, const int32_t *sp_pop,
+                           const double *sp_hd, const int32_t *sp_sys, int64_t n_sp,
+                           uint32_t *d_err, hipStream_t s);
+hipError_t launch_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt, int64_t nb,
+                          uint64_t *out_det, int32_t *out_pop, unsigned long long *count,
+                          hipStream_t s);
 // Export into the staging area `stage` (NOALLOC layout): compaction of the occupied
 // slots (entries past NOALLOC_MAX_DETS are counted, not written), then a bitonic
 // sort by determinant of the first n entries padded to a power of two.
-hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, int64_t cap, void *stage,
-                                hipStream_t s);
+hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt,
+                                int64_t nb, void *stage, hipStream_t s);
 hipError_t launch_stage_sort(void *stage, int64_t n, hipStream_t s);
 // Initiator flag of each of the n sorted entries: |pop| > n_a, or the reference.
 hipError_t launch_stage_flags(void *stage, int64_t n, int32_t n_a, uint64_t d0, hipStream_t s);

@@ -1,16 +1,18 @@
 // Host engine of libfciqmc: the C ABI declared in include/fciqmc.h.
 //
-// A handle holds up to max_slots independent systems. Each system owns an
-// open-addressing main table in device memory (structure of arrays: key,
-// spawned-walker accumulator, population, stored diagonal element), its integrals, and a row of the device
-// descriptor table. One iteration of every system is one pass of five kernels
-// over the descriptor table; up to 64 iterations are captured in one HIP
-// graph. Slots are updated in place; a vacated slot keeps its key until the
-// table is compacted. Between launches the host reads the per-iteration
-// records, keeps the estimator series for blocking, and compacts or grows a
-// table whose headroom would not last the next launch (an iteration whose
-// spawns overflowed a table is re-run after growth; the counter-based random
-// numbers make the re-run identical).
+// A handle holds up to max_slots independent systems. Each system owns a main
+// list in device memory, hash-partitioned into buckets of at most 1024 packed
+// entries (structure of arrays: determinant, population, stored diagonal
+// element, plus a count per bucket), its integrals, and a row of the device
+// descriptor table. One iteration of every system is one pass of the kernels
+// over the descriptor table; up to 64 iterations are captured in one HIP graph.
+// Between launches the host reads the per-iteration records, feeds the
+// estimator averages, and re-buckets a list whose buckets would fill up, or
+// grows the spawn-record buffer. An iteration whose records overflowed the
+// buffer is abandoned and re-run after growth (the counter-based random
+// numbers make the re-run identical); new determinants that did not fit their
+// bucket complete the iteration in a spill list and are re-bucketed before the
+// system continues.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -50,10 +52,15 @@ int set_err(int code, const std::string &msg) {
             return set_err(FCIQMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-// Table capacities: a multiple of 4 chunks, at least 4 chunks.
+// Main-list capacities: a multiple of 4 buckets, at least 4 buckets.
 int64_t round_cap(int64_t x) {
     const int64_t q = 4 * CHUNK;
     return std::max<int64_t>(q, (x + q - 1) / q * q);
+}
+
+// Buckets for `entries` entries at the planned mean fill.
+int64_t cap_for_entries(int64_t entries) {
+    return round_cap((std::max<int64_t>(entries, 1) + BUCKET_FILL - 1) / BUCKET_FILL * CHUNK);
 }
 
 int64_t next_pow2(int64_t x) {
@@ -166,22 +173,25 @@ struct SysHost {
     std::vector<uint8_t> irrep;
     double e_core = 0.0, p_double = 0.0, e0 = 0.0;
     uint64_t d0 = 0;
-    int64_t cap = 0;           // table slots
-    void *block = nullptr;     // one device allocation for the table + integrals
+    int64_t cap = 0;           // main-list capacity: buckets * CHUNK
+    void *block = nullptr;     // one device allocation for the main list + integrals
     uint64_t *key = nullptr;
-    long long *acc = nullptr;
     int32_t *pop = nullptr;
     double *hd = nullptr;
+    int32_t *bcnt = nullptr;
     double *d_h1 = nullptr, *d_eri = nullptr, *d_jk = nullptr;
     std::vector<double> jk;    // [n_so][64] pair table
     std::vector<double> t3;    // [n_so][64][64] single-excitation term table
     double *d_t3 = nullptr;
-    int64_t growth = 0;        // expected per-iteration increase of used slots
+    int64_t growth = 0;        // expected per-iteration increase of the entries
+    int64_t spawn_peak = 0;    // most spawn records of one iteration in the last launch
+    double spawn_rate = 1.0;   // largest ratio of consecutive iterations' records
     int64_t reserve_bytes = 0; // admission accounting (target footprint)
     // mirrored dynamics and statistics
     IterRecord last{};
     int64_t tot_att = 0, tot_sp = 0;
-    int64_t redos = 0;         // iterations re-run after a table overflowed
+    int64_t redos = 0;         // iterations re-run after the record buffer overflowed
+    int64_t spills = 0;        // iterations whose new determinants overflowed a bucket
     Blocker e_blk, s_blk;      // (num, C_0) and (S, 1) samples of the averaging window
     int fatal = 0;
 };
@@ -211,9 +221,16 @@ struct fciqmc_t {
     ChunkStat *d_chunk_stat = nullptr;
     uint32_t *d_tile_chunk = nullptr;       // chunk of each spawn tile
     bool tile_map_off = false;              // its allocation failed once: search instead
-    void *d_scratch = nullptr;              // scratch table for compaction in place
     void *d_stage = nullptr;                // this device's staging area (not owned)
-    size_t scratch_bytes = 0;
+    // spawn records (see EngineArgs) and the spill list
+    void *d_recs = nullptr;
+    int64_t rec_cap = 0;
+    unsigned long long *d_rec_count = nullptr;
+    uint32_t *d_bhist = nullptr, *d_bcur = nullptr, *d_boff = nullptr;
+    void *d_spill = nullptr;
+    int64_t sp_cap = 0;
+    unsigned long long *d_sp_count = nullptr;
+    uint32_t *d_spilled = nullptr;
     int64_t tile_cap = 0;
     unsigned long long *d_blk = nullptr;    // [2][4][SCAN_G] range sums and scans
     unsigned long long *d_step = nullptr;   // iterations run (selects the halves of the sums)
@@ -237,6 +254,11 @@ struct fciqmc_t {
 };
 
 namespace {
+
+void drop_graphs(fciqmc_t *h) {
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+}
 
 EngineArgs make_args(fciqmc_t *h) {
     EngineArgs a{};
@@ -262,12 +284,46 @@ EngineArgs make_args(fciqmc_t *h) {
     a.work = h->d_work;
     a.tile_chunk = h->d_tile_chunk;
     a.tile_cap = h->tile_cap;
+    char *r = (char *)h->d_recs;
+    const size_t rc = (size_t)h->rec_cap;
+    a.rec_det = (uint64_t *)r;
+    a.srt_det = (uint64_t *)(r + 8 * rc);
+    a.rec_w = (int32_t *)(r + 16 * rc);
+    a.rec_gf = (uint32_t *)(r + 20 * rc);
+    a.srt_w = (int32_t *)(r + 24 * rc);
+    a.srt_f = (uint32_t *)(r + 28 * rc);
+    a.rec_count = h->d_rec_count;
+    a.rec_cap = h->rec_cap;
+    a.bhist = h->d_bhist;
+    a.bcur = h->d_bcur;
+    a.boff = h->d_boff;
+    char *q = (char *)h->d_spill;
+    const size_t sc = (size_t)h->sp_cap;
+    a.sp_det = (uint64_t *)q;
+    a.sp_hd = (double *)(q + 8 * sc);
+    a.sp_pop = (int32_t *)(q + 16 * sc);
+    a.sp_sys = (int32_t *)(q + 20 * sc);
+    a.sp_count = h->d_sp_count;
+    a.sp_cap = h->sp_cap;
+    a.spilled = h->d_spilled;
     return a;
 }
 
-void drop_graphs(fciqmc_t *h) {
-    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-    h->graphs.clear();
+// The spawn-record buffer for `cap` records (32 B each: unsorted and sorted copies).
+int ensure_records(fciqmc_t *h, int64_t cap) {
+    if (cap <= h->rec_cap) return 0;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hipFree(h->d_recs);
+    h->d_recs = nullptr;
+    h->rec_cap = 0;
+    drop_graphs(h);
+    if (hipMalloc(&h->d_recs, (size_t)cap * 32) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(FCIQMC_ENOMEM, "spawn-record buffer of " + std::to_string(cap) +
+                                          " records does not fit in device memory");
+    }
+    h->rec_cap = cap;
+    return 0;
 }
 
 int upload_desc(fciqmc_t *h) {
@@ -305,6 +361,9 @@ int relayout(fciqmc_t *h) {
         hipFree(h->d_chunk_off);
         hipFree(h->d_chunk_toff);
         hipFree(h->d_chunk_stat);
+        hipFree(h->d_bhist);
+        hipFree(h->d_bcur);
+        hipFree(h->d_boff);
         h->d_chunk_sys = nullptr;
         h->chunk_alloc = 0;
         HIP_TRY(hipMalloc(&h->d_chunk_sys, na * sizeof(int32_t)));
@@ -313,9 +372,15 @@ int relayout(fciqmc_t *h) {
         HIP_TRY(hipMalloc(&h->d_chunk_off, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_toff, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_stat, na * POST_WAVES * sizeof(ChunkStat)));
+        HIP_TRY(hipMalloc(&h->d_bhist, na * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&h->d_bcur, na * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&h->d_boff, na * sizeof(uint32_t)));
         h->chunk_alloc = na;
         drop_graphs(h);
     }
+    // record counts start at zero (k_post keeps them so after every iteration)
+    HIP_TRY(hipMemsetAsync(h->d_bhist, 0, h->chunk_alloc * sizeof(uint32_t), h->stream));
+    HIP_TRY(hipMemsetAsync(h->d_bcur, 0, h->chunk_alloc * sizeof(uint32_t), h->stream));
     std::vector<int32_t> cs(total), cl(total);
     int64_t g = 0;
     for (int s = 0; s < h->max_sys; ++s) {
@@ -374,8 +439,11 @@ int ensure_tile_map(fciqmc_t *h) {
     return 0;
 }
 
+// Device bytes of a main list of cap entries: determinant, population, H_DD
+// per entry, and one count per bucket.
 int64_t table_bytes(int64_t cap) {
-    return cap * (int64_t)(sizeof(uint64_t) + sizeof(long long) + sizeof(int32_t) + sizeof(double));
+    return cap * (int64_t)(sizeof(uint64_t) + sizeof(int32_t) + sizeof(double)) +
+           (cap / CHUNK) * (int64_t)sizeof(int32_t) + 256;
 }
 
 int64_t integral_doubles(int M) {
@@ -385,44 +453,16 @@ int64_t integral_doubles(int M) {
 
 int64_t integral_bytes(int M) { return integral_doubles(M) * 8 + 256; }
 
-// Empty table: keys and populations zero, diagonal elements NaN ("not computed").
-int clear_table(fciqmc_t *h, void *blk, int64_t cap) {
-    char *p = (char *)blk;
-    const size_t kb = (size_t)cap * (sizeof(uint64_t) + sizeof(long long));   // keys + accumulators
-    HIP_TRY(hipMemsetAsync(p, 0, kb, h->stream));
-    HIP_TRY(hipMemsetAsync(p + kb, 0xFF, (size_t)cap * sizeof(double), h->stream));
-    HIP_TRY(hipMemsetAsync(p + kb + cap * sizeof(double), 0, (size_t)cap * sizeof(int32_t),
-                           h->stream));
-    return 0;
-}
-
-// Allocate (and zero) the tables of a system at capacity cap; integrals are
-// copied in as well. Old storage is released by the caller.
-int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
-    const int64_t tb = table_bytes(cap), ib = integral_bytes(S.M);
-    void *blk = nullptr;
-    hipError_t e = hipMalloc(&blk, (size_t)(tb + ib));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return set_err(FCIQMC_ENOMEM, "device allocation of " + std::to_string(tb + ib) +
-                                          " bytes failed: " + hipGetErrorString(e));
-    }
-    int rc = clear_table(h, blk, cap);
-    if (rc) return rc;
-    *block_out = blk;
-    return 0;
-}
-
 void carve(SysHost &S, void *blk, int64_t cap) {
     char *p = (char *)blk;
     S.key = (uint64_t *)p;
     p += cap * sizeof(uint64_t);
-    S.acc = (long long *)p;
-    p += cap * sizeof(long long);
     S.hd = (double *)p;
     p += cap * sizeof(double);
     S.pop = (int32_t *)p;
     p += cap * sizeof(int32_t);
+    S.bcnt = (int32_t *)p;
+    p += (cap / CHUNK) * sizeof(int32_t);
     p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
     S.d_h1 = (double *)p;
     p += (size_t)S.M * S.M * sizeof(double);
@@ -433,6 +473,24 @@ void carve(SysHost &S, void *blk, int64_t cap) {
     S.d_t3 = (double *)p;
     S.block = blk;
     S.cap = cap;
+}
+
+// Allocate the main list of a system with cap entries (every bucket empty) and
+// room for its integrals. Old storage is released by the caller.
+int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
+    const int64_t tb = table_bytes(cap), ib = integral_bytes(S.M);
+    void *blk = nullptr;
+    hipError_t e = hipMalloc(&blk, (size_t)(tb + ib));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_err(FCIQMC_ENOMEM, "device allocation of " + std::to_string(tb + ib) +
+                                          " bytes failed: " + hipGetErrorString(e));
+    }
+    SysHost T = S;
+    carve(T, blk, cap);
+    HIP_TRY(hipMemsetAsync(T.bcnt, 0, (size_t)(cap / CHUNK) * sizeof(int32_t), h->stream));
+    *block_out = blk;
+    return 0;
 }
 
 int upload_integrals(fciqmc_t *h, SysHost &S) {
@@ -448,9 +506,9 @@ void fill_desc_tables(fciqmc_t *h, int s) {
     SysHost &S = h->sys[s];
     SysDesc &d = h->hdesc[s];
     d.key = S.key;
-    d.acc = S.acc;
     d.pop = S.pop;
     d.hdiag = S.hd;
+    d.bcnt = S.bcnt;
     d.h1 = S.d_h1;
     d.eri = S.d_eri;
     d.jk = S.d_jk;
@@ -458,80 +516,52 @@ void fill_desc_tables(fciqmc_t *h, int s) {
     d.cap = (uint64_t)S.cap;
 }
 
-// Compact (and possibly grow) the table of system s into new_cap slots: only
-// occupied determinants (and the reference) are carried over, vacated keys are
-// dropped, the spawned-walker fields start at zero.
-int grow_system(fciqmc_t *h, int s, int64_t new_cap) {
+// Move the main list of system s (and any of its entries waiting in the spill
+// list) into new_cap entries' worth of buckets, in a new allocation.
+int rebucket_system(fciqmc_t *h, int s, int64_t new_cap, int64_t n_spill) {
     SysHost &S = h->sys[s];
-    void *blk = nullptr;
-    int rc = alloc_tables(h, S, new_cap, &blk);
-    if (rc) return rc == FCIQMC_ENOMEM ? FCIQMC_ECAPACITY : rc;
-    SysHost T = S;
-    carve(T, blk, new_cap);
-    // the integrals (same layout after the tables) move device to device
-    const size_t ib = (size_t)((const char *)(S.d_t3 + S.t3.size()) - (const char *)S.d_h1);
-    HIP_TRY(hipMemcpyAsync(T.d_h1, S.d_h1, ib, hipMemcpyDeviceToDevice, h->stream));
-    // the rehash kernel reads the new capacity from the descriptor
-    h->hdesc[s].cap = (uint64_t)new_cap;
-    rc = upload_desc(h);
-    if (rc) return rc;
-    HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_rehash(h->d_desc, s, S.key, S.pop, S.hd, S.cap, T.key, T.pop, T.hd, h->d_err,
-                          h->stream));
-    uint32_t err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    if (err) return set_err(FCIQMC_ECAPACITY, "rehash into the grown table failed");
-    HIP_TRY(hipFree(S.block));
-    carve(S, blk, new_cap);
-    fill_desc_tables(h, s);
-    S.last.used = S.last.nd + 1;
-    rc = relayout(h);
-    if (rc) return rc;
-    return upload_desc(h);
-}
-
-// Compaction at the same capacity: rehash the occupied determinants into the
-// handle's scratch table, then copy its three arrays back. No allocation of the
-// system's block, no upload of integrals and no new chunk layout, so it is cheap
-// enough to run between any two launches. The spawned-walker accumulators are
-// zero between iterations and stay so.
-int compact_system(fciqmc_t *h, int s) {
-    SysHost &S = h->sys[s];
-    const int64_t cap = S.cap;
-    const size_t need = (size_t)cap * (sizeof(uint64_t) + sizeof(double) + sizeof(int32_t));
-    if (need > h->scratch_bytes) {
+    for (int attempt = 0;; ++attempt) {
+        void *blk = nullptr;
+        int rc = alloc_tables(h, S, new_cap, &blk);
+        if (rc) return rc == FCIQMC_ENOMEM ? FCIQMC_ECAPACITY : rc;
+        SysHost T = S;
+        carve(T, blk, new_cap);
+        // the integrals (same layout after the list) move device to device
+        const size_t ib = (size_t)((const char *)(S.d_t3 + S.t3.size()) - (const char *)S.d_h1);
+        HIP_TRY(hipMemcpyAsync(T.d_h1, S.d_h1, ib, hipMemcpyDeviceToDevice, h->stream));
+        // the kernel reads the destination from the descriptor
+        SysDesc keep = h->hdesc[s];
+        SysHost S_old = S;
+        carve(S, blk, new_cap);
+        fill_desc_tables(h, s);
+        h->hdesc[s].nchunks = new_cap / CHUNK;
+        rc = upload_desc(h);
+        if (rc) return rc;
+        HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
+        const EngineArgs a = make_args(h);
+        HIP_TRY(launch_rebucket(h->d_desc, s, S_old.key, S_old.pop, S_old.hd, S_old.bcnt,
+                                S_old.cap / CHUNK, a.sp_det, a.sp_pop, a.sp_hd, a.sp_sys, n_spill,
+                                h->d_err, h->stream));
+        uint32_t err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        hipFree(h->d_scratch);
-        h->d_scratch = nullptr;
-        const size_t want = std::max(need, 2 * h->scratch_bytes);
-        h->scratch_bytes = 0;
-        if (hipMalloc(&h->d_scratch, want) != hipSuccess) {
-            (void)hipGetLastError();
-            h->d_scratch = nullptr;
-            return grow_system(h, s, cap);   // no room for scratch: rebuild in a new block
+        if (!err) {
+            HIP_TRY(hipFree(S_old.block));
+            S.last.used = std::max<int64_t>(S.last.used, S.last.nd + 1);
+            rc = relayout(h);
+            if (rc) return rc;
+            return upload_desc(h);
         }
-        h->scratch_bytes = want;
+        // a bucket overflowed (far beyond the planned fill): back out, try twice the buckets
+        HIP_TRY(hipFree(blk));
+        S = S_old;
+        h->hdesc[s] = keep;
+        fill_desc_tables(h, s);
+        rc = upload_desc(h);
+        if (rc) return rc;
+        if (attempt >= 4) return set_err(FCIQMC_ECAPACITY, "re-bucketing the main list failed");
+        new_cap *= 2;
     }
-    char *p = (char *)h->d_scratch;
-    uint64_t *tk = (uint64_t *)p;
-    double *th = (double *)(p + (size_t)cap * sizeof(uint64_t));
-    int32_t *tp = (int32_t *)(p + (size_t)cap * (sizeof(uint64_t) + sizeof(double)));
-    HIP_TRY(hipMemsetAsync(tk, 0, (size_t)cap * sizeof(uint64_t), h->stream));
-    HIP_TRY(hipMemsetAsync(th, 0xFF, (size_t)cap * sizeof(double), h->stream));   // NaN
-    HIP_TRY(hipMemsetAsync(tp, 0, (size_t)cap * sizeof(int32_t), h->stream));
-    HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-    // the rehash kernel reads the (unchanged) capacity from the descriptor
-    HIP_TRY(launch_rehash(h->d_desc, s, S.key, S.pop, S.hd, cap, tk, tp, th, h->d_err, h->stream));
-    uint32_t err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    if (err) return set_err(FCIQMC_ECAPACITY, "compaction of the table failed");
-    HIP_TRY(hipMemcpyAsync(S.key, tk, (size_t)cap * sizeof(uint64_t), hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(S.hd, th, (size_t)cap * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(S.pop, tp, (size_t)cap * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
-    S.last.used = S.last.nd + 1;
-    return 0;
 }
 
 uint64_t aufbau(const std::vector<double> &h1, int M, int na, int nb) {
@@ -596,10 +626,12 @@ int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
 }
 
 int64_t initial_capacity(const fciqmc_params *prm) {
-    int64_t want = prm->det_capacity > 0 ? prm->det_capacity : 4 * std::max<int64_t>(prm->initial_walkers, 1024);
-    return round_cap(want);
+    return prm->det_capacity > 0 ? round_cap(prm->det_capacity)
+                                 : cap_for_entries(4 * std::max<int64_t>(prm->initial_walkers, 1024));
 }
 
+// Device bytes reserved for a system at its walker target: a main list of twice
+// the target in entries, and its integrals.
 int64_t target_footprint(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     const int64_t cap = round_cap(2 * std::max<int64_t>(prm->target_walkers, 1));
     return table_bytes(cap) + integral_bytes(ham->n_orb);
@@ -743,48 +775,56 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     return 0;
 }
 
-// Replace the list of system s by (det, pop); computes E0 on the device.
+// Replace the list of system s by (det, pop).
 int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop) {
     SysHost &S = h->sys[s];
     const int64_t n = (int64_t)det.size();
-    int64_t need = round_cap(3 * n);
-    if (need > S.cap) {
-        void *blk = nullptr;
-        int rc = alloc_tables(h, S, need, &blk);
-        if (rc) return rc;
-        SysHost T = S;
-        carve(T, blk, need);
-        rc = upload_integrals(h, T);
-        if (rc) return rc;
-        HIP_TRY(hipFree(S.block));
-        carve(S, blk, need);
-        fill_desc_tables(h, s);
-        int r = relayout(h);
-        if (r) return r;
-    } else {
-        int rc = clear_table(h, S.block, S.cap);
-        if (rc) return rc;
-    }
-    S.growth = std::max<int64_t>(S.cap / 16, 2 * n);
-    h->hstatus[s] = 0;
-    int rc = reset_spawns(h, s);
-    if (rc) return rc;
-    rc = upload_desc(h);
-    if (rc) return rc;
     uint64_t *dd = nullptr;
     int32_t *dp = nullptr;
     HIP_TRY(hipMalloc(&dd, std::max<int64_t>(n, 1) * 8));
     HIP_TRY(hipMalloc(&dp, std::max<int64_t>(n, 1) * 4));
     HIP_TRY(hipMemcpyAsync(dd, det.data(), n * 8, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(dp, pop.data(), n * 4, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-    HIP_TRY(launch_load(h->d_desc, s, dd, dp, n, h->d_err, h->stream));
-    uint32_t err = 0;
-    HIP_TRY(hipMemcpyAsync(&err, h->d_err, 4, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    int64_t need = std::max<int64_t>(S.cap, cap_for_entries(n));
+    int rc = 0;
+    for (int attempt = 0; rc == 0; ++attempt) {
+        if (need > S.cap) {
+            void *blk = nullptr;
+            rc = alloc_tables(h, S, need, &blk);
+            if (rc) break;
+            SysHost T = S;
+            carve(T, blk, need);
+            rc = upload_integrals(h, T);
+            if (rc) break;
+            HIP_TRY(hipFree(S.block));
+            carve(S, blk, need);
+            fill_desc_tables(h, s);
+            rc = relayout(h);
+            if (rc) break;
+        } else {
+            HIP_TRY(hipMemsetAsync(S.bcnt, 0, (size_t)(S.cap / CHUNK) * sizeof(int32_t), h->stream));
+        }
+        h->hstatus[s] = 0;
+        rc = reset_spawns(h, s);
+        if (rc) break;
+        rc = upload_desc(h);
+        if (rc) break;
+        HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
+        HIP_TRY(launch_load(h->d_desc, s, dd, dp, n, h->d_err, h->stream));
+        uint32_t err = 0;
+        HIP_TRY(hipMemcpyAsync(&err, h->d_err, 4, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (!err) break;
+        // a bucket overflowed: twice the buckets
+        if (attempt >= 4) rc = set_err(FCIQMC_ECAPACITY, "walker list does not fit the buckets");
+        need = 2 * S.cap;
+    }
     hipFree(dd);
     hipFree(dp);
-    if (err) return set_err(FCIQMC_ECAPACITY, "walker list does not fit the table");
+    if (rc) return rc;
+    S.growth = std::max<int64_t>(256, n / 8);
+    S.spawn_peak = 0;
+    S.spawn_rate = 1.0;
     return 0;
 }
 
@@ -804,7 +844,7 @@ int export_walkers(fciqmc_t *h, int s, Walkers &w) {
     HIP_TRY(hipMalloc(&op, S.cap * 4));
     HIP_TRY(hipMalloc(&cnt, 8));
     HIP_TRY(hipMemsetAsync(cnt, 0, 8, h->stream));
-    HIP_TRY(launch_compact(S.key, S.pop, S.cap, od, op, cnt, h->stream));
+    HIP_TRY(launch_compact(S.key, S.pop, S.bcnt, S.cap / CHUNK, od, op, cnt, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -864,6 +904,7 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
     o->shift_err = e;
     o->ms_last_call = h->ms_last;
     o->redos = S.redos;
+    o->spills = S.spills;
     o->ms_spawn = h->phase_ms[0] + h->phase_ms[1] + h->phase_ms[2];
     o->ms_death = 0.0;   // death runs inside the annihilation pass
     o->ms_annihilate = h->phase_ms[3];
@@ -912,45 +953,65 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     return 0;
 }
 
-// Before a launch of up to L iterations: compact or grow any table whose
-// free slots would not last, and return how many iterations the headroom of
-// every table allows (each iteration can add at most `growth` keys, the
-// largest increase seen so far; the overflow path catches the rest).
+// Before a launch of up to L iterations: re-bucket any main list whose buckets
+// would pass 5/8 full on average during the launch (each iteration adds at most
+// `growth` entries, the largest increase seen, with slack), size the spawn-record
+// buffer for the launch (the largest record count of the last launch growing at
+// the largest rate seen), and return how many iterations that headroom allows.
+// Whatever the estimates miss is caught on the device: an overflowing record
+// buffer abandons the iteration for a re-run, an overflowing bucket spills.
 int plan_launch(fciqmc_t *h, int L, int *L_out) {
     int allowed = L;
+    int64_t rec_need = 0;
+    double rate = 1.0;
     for (int s = 0; s < h->max_sys; ++s) {
         SysHost &S = h->sys[s];
         if (!S.active || S.fatal) continue;
         const SysDesc &d = h->hdesc[s];
         if (d.iter >= d.stop_at) continue;
+        // records of one iteration: at most one per attempt before anything is known
+        rec_need += S.spawn_peak > 0 ? S.spawn_peak : std::max<int64_t>(S.last.nw, 1);
+        rate = std::max(rate, S.spawn_rate);
+        if (!h->planner) continue;   // overflows are left to the redo and spill paths
         const int64_t g = std::max<int64_t>(S.growth, 256);
-        const int64_t limit = S.cap * 7 / 10;
-        int64_t used = std::max<int64_t>(S.last.used, S.last.nd);
-        if (!h->planner) continue;   // overflows are left to the grow-and-redo path
-        if (used + 4 * g > limit) {
-            // Rehash for 50 % load after 8 more iterations of growth. Vacated slots
-            // are what fills a table whose live count has levelled off, so while
-            // that load fits the present capacity the rehash only compacts (same
-            // size); otherwise it grows by at least 1.5 x.
-            const int64_t live = S.last.nd + 1;
-            const int64_t want = 2 * (live + 8 * g);
-            const int64_t nc = want <= S.cap ? S.cap
-                                             : round_cap(std::max<int64_t>(S.cap + S.cap / 2, want));
-            int rc = nc == S.cap ? compact_system(h, s) : grow_system(h, s, nc);
+        int64_t used = std::max<int64_t>(S.last.used, S.last.nd + 1);
+        if (used + 4 * g > S.cap * 5 / 8) {
+            const int64_t nc = std::max<int64_t>(cap_for_entries(used + 8 * g),
+                                                 round_cap(S.cap + S.cap / 2));
+            const int rc = rebucket_system(h, s, nc, 0);
             if (rc) return rc;
-            used = live;
         }
-        const int64_t room = (S.cap * 7 / 10 - used) / g;
+        const int64_t room = (S.cap * 5 / 8 - used) / g;
         allowed = (int)std::max<int64_t>(1, std::min<int64_t>(allowed, room));
+    }
+    if (h->planner && rec_need > 0) {
+        const int lg = std::min(allowed, 8);
+        const double grow = std::pow(rate, (double)lg);
+        const int64_t want = (int64_t)(1.5 * (double)rec_need * grow) + 65536;
+        if (want > h->rec_cap) {
+            const int rc = ensure_records(h, std::max<int64_t>(want, h->rec_cap + h->rec_cap / 2));
+            if (rc) return rc;
+        }
+        if (rate > 1.0) {
+            const double fit = std::log((double)h->rec_cap / (1.25 * (double)rec_need)) / std::log(rate);
+            allowed = (int)std::max<double>(1.0, std::min<double>((double)allowed, std::floor(fit)));
+        }
     }
     *L_out = allowed;
     return 0;
+}
+
+// Spawn records of iteration `it` of system s (from the host ring of records).
+int64_t rr_spawns(const fciqmc_t *h, int s, int64_t it) {
+    return h->h_rec[(int64_t)s * REC_CAP + it % REC_CAP].spawns;
 }
 
 // Launch L iterations (graph or direct), then read records and statuses. With
 // `sample` the last iteration runs as direct launches bracketed by events, which
 // gives the per-phase device times of one iteration on the graph path too.
 int run_iterations(fciqmc_t *h, int L, bool sample) {
+    bool grow_records = false;
+    std::vector<int> spilled;
     std::vector<int64_t> before(h->max_sys);
     for (int s = 0; s < h->max_sys; ++s) before[s] = h->hdesc[s].iter;
     int rc = ensure_tile_map(h);
@@ -1017,25 +1078,62 @@ int run_iterations(fciqmc_t *h, int L, bool sample) {
                 }
                 S.last = r;
             }
-            // headroom estimate for the next launch: the largest growth of the last
-            // one, with 25 % slack
+            // headroom estimates for the next launch: the largest growth of the entries
+            // and the largest record count of this one, with 25 % slack, and the largest
+            // ratio of consecutive record counts
             S.growth = std::max<int64_t>(256, seen + seen / 4);
+            int64_t peak = 0, prev = 0;
+            double rt = 1.0;
+            for (int64_t it = before[s] + 1; it <= d.iter; ++it) {
+                const int64_t sp = rr_spawns(h, s, it);
+                peak = std::max(peak, sp);
+                if (prev > 0) rt = std::max(rt, (double)sp / (double)prev);
+                prev = sp;
+            }
+            S.spawn_peak = peak + peak / 4;
+            S.spawn_rate = std::min(rt, 4.0);
         }
         uint32_t &st = h->hstatus[s];
         if (st & ST_TABLE_FULL) {
+            // the record buffer overflowed: this iteration was abandoned and runs again
             st &= ~ST_TABLE_FULL;
             S.redos += 1;
             rc = reset_spawns(h, s);
             if (rc) return rc;
-            rc = grow_system(h, s, S.cap * 2);
-            if (rc) return rc;
+            grow_records = true;
+        }
+        if (st & ST_SPILLED) {
+            st &= ~ST_SPILLED;
+            S.spills += 1;
+            spilled.push_back(s);
         }
         if (st) {
-            S.fatal = FCIQMC_EOVERFLOW;
-            return set_err(FCIQMC_EOVERFLOW,
+            S.fatal = (st & ST_SPILL_FULL) ? FCIQMC_ECAPACITY : FCIQMC_EOVERFLOW;
+            return set_err(S.fatal,
                            "system " + std::to_string(s) + ": status " + std::to_string(st) +
-                               ((st & ST_DIED) ? " (walkers died out)" : " (population overflow)"));
+                               ((st & ST_DIED) ? " (walkers died out)"
+                                : (st & ST_SPILL_FULL) ? " (more new determinants than the spill list holds)"
+                                                       : " (population overflow)"));
         }
+    }
+    if (grow_records) {
+        rc = ensure_records(h, 2 * h->rec_cap);
+        if (rc) return rc;
+    }
+    if (!spilled.empty()) {
+        unsigned long long n_sp = 0;
+        HIP_TRY(hipMemcpyAsync(&n_sp, h->d_sp_count, sizeof n_sp, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const int64_t n_take = std::min<int64_t>((int64_t)n_sp, h->sp_cap);
+        for (int s : spilled) {
+            SysHost &S = h->sys[s];
+            const int64_t used = std::max<int64_t>(S.last.used, S.last.nd + 1) + n_take;
+            const int64_t nc = std::max<int64_t>(cap_for_entries(used + 8 * S.growth),
+                                                 round_cap(2 * S.cap));
+            rc = rebucket_system(h, s, nc, n_take);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipMemsetAsync(h->d_sp_count, 0, sizeof(unsigned long long), h->stream));
     }
     return 0;
 }
@@ -1069,6 +1167,9 @@ int iterate_each(fciqmc_t *h, const std::vector<int64_t> &n) {
     hipEventDestroy(t1);
     return 0;
 }
+
+// Entries of the spill list (new determinants that did not fit their bucket).
+constexpr int64_t SPILL_CAP = (int64_t)1 << 16;
 
 // Address of the staging area on each device (resolved once per device, with
 // that device current).
@@ -1128,6 +1229,18 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_fin, sizeof(FinPart) * FIN_BLOCKS * max_slots));
     HIP_TRY(hipMalloc(&h->d_c0, sizeof(int64_t) * max_slots));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&h->d_rec_count, sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(h->d_rec_count, 0, sizeof(unsigned long long), h->stream));
+    {
+        const int rc = ensure_records(h, 65536);
+        if (rc) return rc;
+    }
+    h->sp_cap = SPILL_CAP;
+    HIP_TRY(hipMalloc(&h->d_spill, (size_t)h->sp_cap * 24));
+    HIP_TRY(hipMalloc(&h->d_sp_count, sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(h->d_sp_count, 0, sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipMalloc(&h->d_spilled, sizeof(uint32_t) * max_slots));
+    HIP_TRY(hipMemsetAsync(h->d_spilled, 0, sizeof(uint32_t) * max_slots, h->stream));
     for (int k = 0; k <= NKERN; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
     h->spawn_grid = spawn_grid_size();
     h->post_grid = post_grid_size();
@@ -1204,7 +1317,14 @@ void release(fciqmc_t *h) {
     hipFree(h->d_chunk_toff);
     hipFree(h->d_chunk_stat);
     hipFree(h->d_tile_chunk);
-    hipFree(h->d_scratch);
+    hipFree(h->d_recs);
+    hipFree(h->d_rec_count);
+    hipFree(h->d_bhist);
+    hipFree(h->d_bcur);
+    hipFree(h->d_boff);
+    hipFree(h->d_spill);
+    hipFree(h->d_sp_count);
+    hipFree(h->d_spilled);
     for (auto &e : h->ev)
         if (e) hipEventDestroy(e);
     if (h->own_stream) hipStreamDestroy(h->stream);
@@ -1386,7 +1506,7 @@ int fciqmc_reserve(fciqmc_t *h, int64_t slots) {
     for (int s = 0; s < h->max_sys; ++s) {
         SysHost &S = h->sys[s];
         if (!S.active || S.fatal || S.cap >= want) continue;
-        const int rc = grow_system(h, s, want);
+        const int rc = rebucket_system(h, s, want, 0);
         if (rc) return rc;
     }
     return 0;
@@ -1539,10 +1659,20 @@ int fciqmc_blocking(const double *num, const double *den, int64_t n, double *mea
     return 0;
 }
 
-int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit) {
+int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit,
+                            int64_t record_capacity) {
     if (!h) return set_err(FCIQMC_EINVAL, "null handle");
     if (tile_map_limit < -1) return set_err(FCIQMC_EINVAL, "tile_map_limit must be >= -1");
+    if (record_capacity < 0) return set_err(FCIQMC_EINVAL, "record_capacity must be >= 0");
     h->planner = planner != 0;
+    if (record_capacity > 0) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        hipFree(h->d_recs);
+        h->d_recs = nullptr;
+        h->rec_cap = 0;
+        const int rc = ensure_records(h, record_capacity);
+        if (rc) return rc;
+    }
     if (tile_map_limit != h->tile_map_limit) {
         HIP_TRY(hipStreamSynchronize(h->stream));
         hipFree(h->d_tile_chunk);
@@ -1562,7 +1692,7 @@ int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_
     const int s = 0;
     const SysHost &S = h->sys[s];
     if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
-    HIP_TRY(launch_stage_compact(S.key, S.pop, S.cap, h->d_stage, h->stream));
+    HIP_TRY(launch_stage_compact(S.key, S.pop, S.bcnt, S.cap / CHUNK, h->d_stage, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, h->d_stage, sizeof n, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));

@@ -1,27 +1,35 @@
 // HIP kernels of the FCIQMC iteration (Booth, Smart & Alavi, arXiv:1305.6981)
-// for gfx950. One iteration of every active system is six launches (seven in
-// the first iteration of a launch sequence):
+// for gfx950.
 //
-//   k_chunk_sum   sum |C| over each 1024-slot chunk of the current main tables,
-//                 and over fixed contiguous ranges of chunks (first iteration of
-//                 a launch sequence only; afterwards k_post provides the sums)
+// The main list of a system is hash-partitioned into buckets of at most 1024
+// densely packed entries (determinant, population, stored H_DD): the paper's
+// distribution of determinants over processes by a hash (Sec. 4.1), with a
+// workgroup in the role of a process. One iteration of every active system is
+// nine launches (ten in the first iteration of a launch sequence):
+//
+//   k_chunk_sum   sum |C| over each bucket and over fixed contiguous ranges of
+//                 buckets (first iteration of a launch sequence only;
+//                 afterwards k_post provides the sums)
 //   k_scan        exclusive scan of the range sums (one workgroup)
-//   k_scan_down   per chunk: global attempt offset and spawn-tile offset
+//   k_scan_down   per bucket: global attempt offset and spawn-tile offset
 //   k_spawn       one spawning attempt per walker (Sec. 2, Eq. pspawn): random
 //                 excitation with its pgen (Sec. 5), Slater-Condon element,
-//                 acceptance; accepted walkers are summed straight into the
-//                 target determinant's slot of the main table (the merge of
-//                 equal spawned determinants of Sec. 4.1, done by atomics)
-//   k_post        per slot, in place: death/cloning (Eq. pdeath), annihilation
-//                 of the arrived walkers with the initiator test for
-//                 determinants that are empty after death, the stored diagonal
-//                 element for newly occupied determinants (Sec. 4.2) from a
+//                 acceptance; each accepted spawn becomes a record (child,
+//                 signed walkers, initiator flag) addressed to the child's
+//                 bucket -- the per-destination blocks of Sec. 4.1
+//   k_hist        the child's bucket of every record, records per bucket
+//   k_bscan       exclusive scan of the records per bucket (one workgroup)
+//   k_scatter     the records grouped by bucket (a counting sort)
+//   k_post        per bucket, by one workgroup: the records merged per child in
+//                 an LDS hash (the sort and compress of Sec. 4.1); death/cloning
+//                 of every entry (Eq. pdeath); annihilation with the initiator
+//                 test for children that are unoccupied after death (Sec. 4.2);
+//                 new determinants placed into the holes left by emptied
+//                 entries, the bucket re-packed, H_DD of new determinants from a
 //                 pair table staged in LDS; estimator partial sums (Eq. ProjE);
-//                 the next iteration's chunk and range sums of |C|.
-//                 A vacated slot keeps its key (and H_DD) until the table is
-//                 compacted, so no slot ever moves during an iteration.
+//                 the next iteration's bucket and range sums of |C|
 //   k_reduce      per system, 64 workgroups: fixed-order reduction of the
-//                 chunk statistics over fixed ranges of chunks
+//                 bucket statistics over fixed ranges of buckets
 //   k_finalize    per system, one wavefront: sum of the 64 shares, the shift
 //                 update, the per-iteration record
 //
@@ -129,10 +137,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t h) {
     return h;
 }
 
-// First probe of a key in a table of cap slots (any cap): the high word of
-// mix64(k) * cap, i.e. the hash scaled onto [0, cap).
-__device__ __forceinline__ uint64_t home_slot(uint64_t k, uint64_t cap) {
-    return __umul64hi(mix64(k), cap);
+// Bucket of a determinant among nb buckets: the high word of mix64(D) * nb, i.e.
+// the hash scaled onto [0, nb) (the placement of Sec. 4.1's process hash; the
+// paper's Algorithm 1 is kept in the CPU oracle, results do not depend on it).
+__device__ __forceinline__ uint32_t bucket_of(uint64_t D, uint64_t nb) {
+    return (uint32_t)__umul64hi(mix64(D), nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,9 +532,15 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
                 const int sy = a.chunk_sys[cc];
                 if (sy >= 0) {
                     const SysDesc &d = desc[sy];
-                    if (participating(d, a.status[sy]))
-                        v[k] = abs_sum4(reinterpret_cast<const int4 *>(
-                            d.pop + (int64_t)a.chunk_local[cc] * CHUNK)[t]);
+                    const int b = a.chunk_local[cc];
+                    const int n = d.bcnt[b];
+                    if (participating(d, a.status[sy]) && 4 * t < n) {
+                        int4 q = reinterpret_cast<const int4 *>(d.pop + (int64_t)b * CHUNK)[t];
+                        if (4 * t + 1 >= n) q.y = 0;
+                        if (4 * t + 2 >= n) q.z = 0;
+                        if (4 * t + 3 >= n) q.w = 0;
+                        v[k] = abs_sum4(q);
+                    }
                 }
             }
         }
@@ -664,36 +679,34 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
 // k+1 / next occupied slot.
 // ---------------------------------------------------------------------------
 
-// Merge one spawning event into the main table (the annihilation of Sec. 4.2
-// done by atomics): find or claim the determinant's slot by linear probing
-// (one compare-and-swap per probe: it claims an empty slot or returns the key
-// there), then add (initiator ? 2^32 : 0) + v to the slot's accumulator with
-// one atomic whose result is not needed. A probe sequence longer than
-// PROBE_LIMIT (far beyond any run at the 70 % load the tables are kept under)
-// reports the table full: the iteration is then re-run after growth.
-constexpr uint64_t PROBE_LIMIT = 4096;
-__device__ __forceinline__ bool table_add(uint64_t *key, long long *acc, uint64_t cap, uint64_t k,
-                                          int32_t v, bool init) {
-    uint64_t h = home_slot(k, cap);
-    const uint64_t lim = cap < PROBE_LIMIT ? cap : PROBE_LIMIT;
-    for (uint64_t n = 0; n < lim; ++n) {
-        uint64_t expect = 0;
-        if (__hip_atomic_compare_exchange_strong(gp(&key[h]), &expect, k, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-            expect == k) {
-            const long long inc = (init ? (1ll << 32) : 0ll) + (long long)v;
-            __hip_atomic_fetch_add(gp(&acc[h]), inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return true;
-        }
-        h = h + 1 == cap ? 0 : h + 1;
+// Spawn records. A record is (child, signed walkers, system | initiator flag <<
+// 31), appended to the iteration's record buffer (k_hist later replaces the
+// system by the child's bucket). A record that would land past the buffer's
+// capacity is dropped and the system marked: the iteration is then abandoned
+// and re-run after the buffer grows.
+__device__ __forceinline__ void put_record(const EngineArgs &a, int s, unsigned long long j,
+                                           uint64_t D, int32_t v, bool init, uint32_t *status) {
+    if (j >= (unsigned long long)a.rec_cap) {
+        atomicOr(status, ST_TABLE_FULL);
+        return;
     }
-    return false;
+    a.rec_det[j] = D;
+    a.rec_w[j] = v;
+    a.rec_gf[j] = (uint32_t)s | (init ? 0x80000000u : 0u);
 }
 
-// Signed walker sum and initiator flag of an accumulator (the sum fits 32 bits).
-__device__ __forceinline__ int32_t acc_walkers(long long x) { return (int32_t)(uint32_t)x; }
-__device__ __forceinline__ bool acc_initiator(long long x) {
-    return ((x - (long long)acc_walkers(x)) >> 32) != 0;
+// One record per active lane, with one buffer reservation for the wavefront
+// (callable from divergent code).
+__device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint64_t D, int32_t v,
+                                                bool init, uint32_t *status) {
+    const uint64_t m = __ballot(1);
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(a.rec_count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    put_record(a, s, base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull)), D, v, init,
+               status);
 }
 
 // Work queued in LDS by the attempt loop and drained by the whole workgroup:
@@ -740,6 +753,8 @@ struct SpawnQueues {
     uint64_t spd[SPW_QUEUE];
     int2 spv[SPW_QUEUE];   // (signed walkers, initiator flag)
     int nsgl, nspw, sys;
+    unsigned long long base;   // first record of a drain
+    uint32_t dead;             // the drained system's status, as seen by thread 0
 };
 
 // Add the wavefront's spawning events of system s to its counter and reset the
@@ -755,11 +770,13 @@ __device__ __forceinline__ void flush_spawn_count(unsigned long long *counter,
 // Drain both queues of system s with the whole workgroup (call uniformly).
 __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc &d, int s,
                              const uint32_t *sel8, unsigned long long &spawned) {
-    __syncthreads();
     const int t = threadIdx.x;
     uint32_t *status = &a.status[s];
-    // a system whose table overflowed re-runs the iteration: drop its queued work
-    const bool dead = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)status) != 0;
+    // a system whose record buffer overflowed re-runs the iteration: drop its queued work
+    // (decided once for the workgroup: other workgroups may set the status meanwhile)
+    if (t == 0) Q.dead = *(volatile uint32_t *)status;
+    __syncthreads();
+    const bool dead = Q.dead != 0;
     const int nsgl = dead ? 0 : (Q.nsgl < SGL_QUEUE ? Q.nsgl : SGL_QUEUE);
     for (int j = t; j < nsgl; j += blockDim.x) {
         const SingleItem it = Q.sgl[j];
@@ -779,15 +796,18 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         if (qq < SPW_QUEUE) {
             Q.spd[qq] = Dn;
             Q.spv[qq] = make_int2(v, init ? 1 : 0);
-        } else if (!table_add(d.key, d.acc, d.cap, Dn, v, init)) {
-            atomicOr(status, ST_TABLE_FULL);
+        } else {
+            put_record_wave(a, s, Dn, v, init, status);
         }
     }
     __syncthreads();
+    // the queued records: one buffer reservation for the workgroup
     const int nspw = dead ? 0 : (Q.nspw < SPW_QUEUE ? Q.nspw : SPW_QUEUE);
+    if (t == 0 && nspw > 0) Q.base = atomicAdd(a.rec_count, (unsigned long long)nspw);
+    __syncthreads();
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
-        if (!table_add(d.key, d.acc, d.cap, Q.spd[j], v.x, v.y != 0)) atomicOr(status, ST_TABLE_FULL);
+        put_record(a, s, Q.base + (unsigned long long)j, Q.spd[j], v.x, v.y != 0, status);
     }
     __syncthreads();
     if (t == 0) {
@@ -887,12 +907,16 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         }
         if (t < NCLASS) s_cm[t] = d.cmask[t];   // ordered before use by the barrier below
         const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-        // Stage the occupied slots of the chunk, compacted, with the inclusive
-        // prefix sum of |C| (4 consecutive slots per thread).
+        const int n_b = d.bcnt[a.chunk_local[c]];
+        // Stage the bucket's entries that hold walkers, compacted, with the inclusive
+        // prefix sum of |C| (4 consecutive entries per thread).
+        // (a bucket's CHUNK entries are always allocated: entries past the count are read
+        // and ignored)
         const int4 pv = gload_i4(d.pop + base + 4 * t);
         const ulonglong2 k01 = gload_u2(d.key + base + 4 * t);
         const ulonglong2 k23 = gload_u2(d.key + base + 4 * t + 2);
-        const int32_t pa[4] = {pv.x, pv.y, pv.z, pv.w};
+        const int32_t pa[4] = {4 * t < n_b ? pv.x : 0, 4 * t + 1 < n_b ? pv.y : 0,
+                               4 * t + 2 < n_b ? pv.z : 0, 4 * t + 3 < n_b ? pv.w : 0};
         const uint64_t ka[4] = {k01.x, k01.y, k23.x, k23.y};
         const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
         unsigned long long run = 0;
@@ -939,7 +963,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         const unsigned long long tt = (unsigned long long)t;
         unsigned long long at = lo_t + tt * q_t + (tt < r_t ? tt : r_t);
         const unsigned long long at_end = at + q_t + (tt < r_t ? 1ull : 0ull);
-        // no attempts for a system that has stopped this iteration (its table overflowed)
+        // no attempts for a system that has stopped this iteration (its record buffer overflowed)
         const bool stopped = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)status) != 0;
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
         const bool c1 = d.n_class == 2;          // no point group: classes are the spins
@@ -985,8 +1009,8 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                             if (q < SPW_QUEUE) {
                                 Q.spd[q] = ex.det;
                                 Q.spv[q] = make_int2(v, init ? 1 : 0);
-                            } else if (!table_add(d.key, d.acc, d.cap, ex.det, v, init)) {
-                                atomicOr(status, ST_TABLE_FULL);
+                            } else {
+                                put_record_wave(a, s, ex.det, v, init, status);
                             }
                         }
                     }
@@ -1010,23 +1034,133 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
 }
 
 // ---------------------------------------------------------------------------
-// K4: death, annihilation and initiator test per slot, in place; the
-// diagonal element of newly occupied determinants; estimator partials.
+// K4a: the bucket of each record's child, and the records per bucket.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t insert_unique(uint64_t *keys, uint64_t cap, uint64_t key) {
-    uint64_t h = home_slot(key, cap);
-    for (uint64_t n = 0; n < cap; ++n) {
-        const unsigned long long old =
-            atomicCAS((unsigned long long *)&keys[h], 0ull, (unsigned long long)key);
-        if (old == 0ull) return (int64_t)h;
-        h = h + 1 == cap ? 0 : h + 1;
+__global__ __launch_bounds__(256) void k_hist(EngineArgs a, const SysDesc *__restrict__ desc) {
+    const unsigned long long cnt = *a.rec_count;
+    const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t gf = a.rec_gf[i];
+        const SysDesc &d = desc[gf & 0x7FFFFFFFu];
+        const uint32_t gb = (uint32_t)d.gchunk0 + bucket_of(a.rec_det[i], (uint64_t)d.nchunks);
+        a.rec_gf[i] = gb | (gf & 0x80000000u);
+        __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    return -1;
 }
 
-constexpr int POST_QUEUE = 1536;  // new-determinant queue entries per workgroup; with the
-                                  // 16 KiB triangular pair table: six workgroups per CU
-constexpr int POST_GRAB = 4;      // chunks per dynamic grab in k_post
+// ---------------------------------------------------------------------------
+// K4b: exclusive scan of the records per bucket (one workgroup; each thread
+// takes a contiguous range of buckets).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_bscan(EngineArgs a) {
+    __shared__ unsigned long long part[1024];
+    const int64_t nch = *a.nchunks;
+    const int64_t per = (nch + 1023) / 1024;
+    const int t = threadIdx.x;
+    const int64_t lo = (int64_t)t * per;
+    const int64_t hi = lo + per < nch ? lo + per : nch;
+    unsigned long long sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += a.bhist[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    unsigned long long run = part[t] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        a.boff[i] = (uint32_t)run;
+        run += a.bhist[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4c: the records grouped by bucket (order inside a bucket is immaterial:
+// every merge is an integer sum).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_scatter(EngineArgs a) {
+    const unsigned long long cnt = *a.rec_count;
+    const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t gf = a.rec_gf[i];
+        const uint32_t gb = gf & 0x7FFFFFFFu;
+        const uint32_t pos =
+            a.boff[gb] + __hip_atomic_fetch_add(&a.bcur[gb], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        a.srt_det[pos] = a.rec_det[i];
+        a.srt_w[pos] = a.rec_w[i];
+        a.srt_f[pos] = gf >> 31;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4d: per bucket, one workgroup: merge of the arrived records, death,
+// annihilation with the initiator test, new determinants, re-packing;
+// estimator partials and the next iteration's sums of |C|.
+// ---------------------------------------------------------------------------
+constexpr int NCAND = 256;              // new-determinant candidates per round in LDS
+constexpr int NLDS = CHUNK + NCAND;     // LDS entries: the bucket's entries, then candidates
+constexpr int LHASH = 2048;             // LDS hash slots over those entries (load <= 0.63)
+constexpr int POST_QUEUE = 768;         // new determinants whose H_DD is still to be computed
+constexpr int POST_GRAB = 4;            // buckets per dynamic grab in k_post
+constexpr uint32_t F_INIT = 1u;         // record flags: from an initiator parent,
+constexpr uint32_t F_MAYBE = 2u;        // found no room in the candidate area this round,
+constexpr uint32_t F_DEFER = 4u;        // left for a later round
+
+__device__ __forceinline__ uint32_t lds_home(uint64_t D) {
+    return (uint32_t)mix64(D) & (uint32_t)(LHASH - 1);
+}
+
+// Entry index of D in the LDS hash (-1: absent). Call when no thread inserts.
+__device__ __forceinline__ int lds_find(uint64_t D, const uint64_t *s_det, const uint32_t *s_hash) {
+    uint32_t h = lds_home(D);
+    for (;;) {
+        const uint32_t x = s_hash[h];
+        if (x == 0u) return -1;
+        if (s_det[x - 1u] == D) return (int)x - 1;
+        h = (h + 1u) & (uint32_t)(LHASH - 1);
+    }
+}
+
+// Entry index of D, claiming a candidate entry for it when absent (concurrent
+// callers with the same D agree on one entry: the entry's key is published
+// before the hash slot that points to it). -1 when D is absent and the
+// candidate area is full; D may then have been inserted meanwhile by another
+// thread, which a lookup after a barrier settles.
+__device__ __forceinline__ int lds_find_or_claim(uint64_t D, uint64_t *s_det, uint32_t *s_hash,
+                                                 int *s_ncand) {
+    uint32_t h = lds_home(D);
+    int mine = -1;
+    for (;;) {
+        uint32_t x = __hip_atomic_load(&s_hash[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (x == 0u) {
+            if (mine < 0) {
+                const int k = atomicAdd(s_ncand, 1);
+                if (k >= NCAND) return -1;
+                mine = CHUNK + k;
+                __hip_atomic_store(&s_det[mine], D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            uint32_t expect = 0u;
+            if (__hip_atomic_compare_exchange_strong(&s_hash[h], &expect, (uint32_t)mine + 1u,
+                                                     __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
+                return mine;
+            x = expect;
+        }
+        const uint64_t k = __hip_atomic_load(&s_det[x - 1u], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k == D) {
+            if (mine >= 0)   // the entry this thread claimed is not needed: mark it unused
+                __hip_atomic_store(&s_det[mine], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return (int)x - 1;
+        }
+        h = (h + 1u) & (uint32_t)(LHASH - 1);
+    }
+}
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
 // ascending (p, q) order from the LDS copies of h_pp and of the pair table (its
@@ -1057,8 +1191,9 @@ __device__ __forceinline__ void hdiag_lds2(double e_core, uint64_t da, uint64_t 
     rb = xb;
 }
 
-// Diagonal elements of the queued newly occupied slots (all of one system, so
-// all with the same electron count), two per thread at a time.
+// Diagonal elements of the queued new determinants (positions in the system's
+// arrays, all of one system, so all with the same electron count), two per
+// thread at a time.
 __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t *queue, int n,
                                                const double *hpp, const double *jk) {
     const int step = 2 * (int)blockDim.x;
@@ -1073,38 +1208,52 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6)))
-void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
+// Exclusive prefix of per-thread counts over the workgroup (threads in order);
+// *total gets the sum. Uses s_w[POST_WAVES]; call uniformly.
+__device__ __forceinline__ int block_excl_scan(int v, int *s_w, int *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    int pre = x - v, tot = 0;
+    for (int w = 0; w < POST_WAVES; ++w) {
+        if (w < wid) pre += s_w[w];
+        tot += s_w[w];
+    }
+    *total = tot;
+    return pre;
+}
+
+__global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ double s_jk[64 * 63 / 2];   // upper triangle of the pair table
     __shared__ double s_hpp[64];
-    // New determinants are queued for the workgroup. Whether to flush the queue at
-    // the start of a chunk is decided by thread 0 two chunks earlier (s_flush, by
-    // the parity of the workgroup's chunk count), so every wavefront reads a value
-    // that no one is changing; a full queue makes a thread compute its own entry.
+    __shared__ uint64_t s_det[NLDS];
+    __shared__ long long s_acc[NLDS];      // walkers arrived per entry
+    __shared__ uint32_t s_flg[NLDS / 32];  // initiator flag per entry (OR over its records)
+    __shared__ uint32_t s_hash[LHASH];     // entry index + 1, 0 = empty
+    __shared__ uint16_t s_free[CHUNK];     // positions emptied this iteration, ascending
     __shared__ uint32_t s_queue[POST_QUEUE];
-    __shared__ int s_qn;
-    __shared__ int s_flush[2];
+    __shared__ int s_ncand, s_nhole, s_nlive, s_kplaced, s_maybe, s_defer, s_qn, s_live;
+    __shared__ int s_w[POST_WAVES];
     __shared__ unsigned int s_next;
-    __shared__ unsigned long long s_nwn[2][POST_WAVES];   // next-iteration sums, by seq parity
+    __shared__ unsigned long long s_nwn[POST_WAVES];
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    // The next iteration's chunk sums (its attempts) are the new |C| totals found here:
-    // written per chunk, and added into the range sums that k_scan will read.
+    // k_scatter has consumed this iteration's records
+    if (blockIdx.x == 0 && t == 0) *a.rec_count = 0ull;
     unsigned long long *const nws_next = sums(a, cur_half(a) ^ 1u);
     unsigned long long *const rg_next = ranges(a, cur_half(a) ^ 1u);
     const int64_t per_range = (nch + SCAN_G - 1) / SCAN_G;
     const int tsh = __builtin_ctzll((unsigned long long)a.tile);
     const unsigned long long tm = (unsigned long long)a.tile - 1ull;
     int loaded = -1;
-    if (t == 0) {
-        s_qn = 0;
-        s_flush[0] = 0;
-        s_flush[1] = 0;
-    }
+    if (t == 0) s_qn = 0;
     __syncthreads();
-    unsigned seq = 0;   // chunks this workgroup has processed
-    // Chunks are handed out dynamically, POST_GRAB consecutive ones per atomic
-    // (one counter serves the whole chip, so grabs are kept few), in order.
     int64_t c = 0, c_end = 0;
     for (;; ++c) {
         if (c >= c_end) {
@@ -1117,16 +1266,22 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
         if (c >= nch) break;
         const int s = a.chunk_sys[c];
         int64_t nw = 0, aborted = 0;
-        uint64_t cnt = 0;   // slots holding a key | merged targets << 21 | occupied << 42
+        uint64_t cnt = 0;                 // entries | merged targets << 21 | occupied << 42
         double num = 0.0;
-        const bool live = s >= 0 && participating(desc[s], a.status[s]);   // uniform
+        unsigned long long nwb = 0;       // sum |C| over the bucket's entries after the iteration
+        // decided once for the workgroup (other workgroups may set status bits meanwhile)
+        if (t == 0) s_live = (s >= 0 && participating(desc[s], *(volatile uint32_t *)&a.status[s])) ? 1 : 0;
+        __syncthreads();
+        const bool live = s_live != 0;
+        const uint32_t nr = a.bhist[c], r0 = a.boff[c];
         if (live) {
             const SysDesc &d = desc[s];
-            if (loaded != s || s_flush[seq & 1u]) {
-                // another system, or a queue decided to be flushed (both uniform): no
-                // wavefront is adding to the queue now
-                const int n = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
-                if (loaded >= 0 && n > 0) flush_new_dets(desc[loaded], s_queue, n, s_hpp, s_jk);
+            uint32_t *status = &a.status[s];
+            if (loaded != s || s_qn + NCAND > POST_QUEUE) {
+                // another system, or the H_DD queue could overflow in this bucket (both
+                // uniform): compute the queued elements now
+                const int nq = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
+                if (loaded >= 0 && nq > 0) flush_new_dets(desc[loaded], s_queue, nq, s_hpp, s_jk);
                 __syncthreads();
                 if (loaded != s) {
                     for (int i = t; i < d.n_so * 64; i += 256) {
@@ -1139,120 +1294,298 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (t == 0) s_qn = 0;
                 __syncthreads();
             }
-            const int64_t base = (int64_t)a.chunk_local[c] * CHUNK + 4 * t;
-            // four consecutive slots per thread, all loads issued before any use
-            const ulonglong2 k01 = gload_u2(d.key + base);
-            const ulonglong2 k23 = gload_u2(d.key + base + 2);
-            const ulonglong2 a01 = gload_u2(reinterpret_cast<const uint64_t *>(d.acc + base));
-            const ulonglong2 a23 = gload_u2(reinterpret_cast<const uint64_t *>(d.acc + base + 2));
-            const uint64_t kin[4] = {k01.x, k01.y, k23.x, k23.y};
-            const long long ain[4] = {(long long)a01.x, (long long)a01.y, (long long)a23.x,
-                                      (long long)a23.y};
-            const int4 pv = gload_i4(d.pop + base);
-            const double2 h01 = gload_d2(d.hdiag + base);
-            const double2 h23 = gload_d2(d.hdiag + base + 2);
-            const int32_t pin[4] = {pv.x, pv.y, pv.z, pv.w};
-            const double hin[4] = {h01.x, h01.y, h23.x, h23.y};
-            int32_t pout[4] = {pv.x, pv.y, pv.z, pv.w};
+            const int b = a.chunk_local[c];
+            const int64_t base = (int64_t)b * CHUNK;
+            const int n = d.bcnt[b];
+            // the bucket's entries, four consecutive per thread, all loads issued first
+            uint64_t kin[4] = {0ull, 0ull, 0ull, 0ull};
+            int32_t pin[4] = {0, 0, 0, 0};
+            double hin[4] = {0.0, 0.0, 0.0, 0.0};
+            if (4 * t < n) {
+                const ulonglong2 k01 = gload_u2(d.key + base + 4 * t);
+                const ulonglong2 k23 = gload_u2(d.key + base + 4 * t + 2);
+                const int4 pv = gload_i4(d.pop + base + 4 * t);
+                const double2 h01 = gload_d2(d.hdiag + base + 4 * t);
+                const double2 h23 = gload_d2(d.hdiag + base + 4 * t + 2);
+                kin[0] = k01.x; kin[1] = k01.y; kin[2] = k23.x; kin[3] = k23.y;
+                pin[0] = pv.x; pin[1] = pv.y; pin[2] = pv.z; pin[3] = pv.w;
+                hin[0] = h01.x; hin[1] = h01.y; hin[2] = h23.x; hin[3] = h23.y;
+            }
+            for (int i = t; i < LHASH; i += 256) s_hash[i] = 0u;
+            for (int i = t; i < NLDS; i += 256) s_acc[i] = 0ll;
+            if (t < NLDS / 32) s_flg[t] = 0u;
+            if (t == 0) {
+                s_ncand = 0;
+                s_maybe = 0;
+                s_defer = 0;
+                s_kplaced = 0;
+            }
+            __syncthreads();
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint64_t D = kin[u];
-                if (D == 0) continue;
-                cnt += 1ull;
-                const int32_t p = pin[u];
-                int64_t pd = p;
-                if (p != 0) {
-                    // Eq. pdeath, one stochastic rounding for the whole determinant.
-                    uint64_t xd, xu;
-                    draw2(d.seed, D, 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
-                    const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
-                    const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
-                    const double ad = fabs(dv);
-                    const double fl = floor(ad);
-                    if (fl > 1073741824.0) {
-                        atomicOr(&a.status[s], ST_POP_OVERFLOW);
-                        continue;
-                    }
-                    const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
-                    pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
-                }
-                // Annihilation (Sec. 4.2): present after death -> add; otherwise the
-                // arrived walkers survive only if an initiator sent some of them.
-                const bool present = pd != 0 || D == d.d0;
-                const int64_t sp = acc_walkers(ain[u]);
-                int64_t np;
-                if (present) {
-                    np = pd + sp;
-                } else if (sp != 0 && acc_initiator(ain[u])) {
-                    np = sp;
-                } else {
-                    np = 0;
-                    if (sp != 0) aborted += sp < 0 ? -sp : sp;
-                }
-                if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
-                if (np > 2147483647ll || np < -2147483647ll) {
-                    atomicOr(&a.status[s], ST_POP_OVERFLOW);
-                    np = 0;
-                }
-                pout[u] = (int32_t)np;
-                if (np != 0 && p == 0 && isnan(hin[u])) {
-                    // newly occupied: diagonal element computed with the queue
-                    const int q = atomicAdd(&s_qn, 1);
-                    if (q < POST_QUEUE) {
-                        s_queue[q] = (uint32_t)(base + u);
-                    } else {
-                        double h, h2;
-                        hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, d.n_so, h, h2);
-                        *gp(d.hdiag + base + u) = h;
-                    }
-                }
-                if (D == d.d0) a.c0[s] = np;   // the reference has one slot
-                if (np != 0) {
-                    nw += np < 0 ? -np : np;
-                    cnt += 1ull << CNT_SHIFT_ND;
-                    if (D != d.d0 && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
+                const int e = 4 * t + u;
+                if (e >= n) continue;
+                s_det[e] = kin[u];
+                uint32_t h = lds_home(kin[u]);
+                for (;;) {   // the bucket's keys are distinct: claim the first free slot
+                    uint32_t expect = 0u;
+                    if (__hip_atomic_compare_exchange_strong(&s_hash[h], &expect, (uint32_t)e + 1u,
+                                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;
+                    h = (h + 1u) & (uint32_t)(LHASH - 1);
                 }
             }
-            if (pout[0] != pin[0] || pout[1] != pin[1] || pout[2] != pin[2] || pout[3] != pin[3])
-                gstore_i4(d.pop + base, pout[0], pout[1], pout[2], pout[3]);
-            // clear the arrived walkers of the iteration
-            if (a01.x | a01.y) gstore_i4(d.acc + base, 0, 0, 0, 0);
-            if (a23.x | a23.y) gstore_i4(d.acc + base + 2, 0, 0, 0, 0);
+            __syncthreads();
+            int32_t npv[4] = {0, 0, 0, 0};
+            bool keep[4] = {false, false, false, false};
+            for (int round = 0;; ++round) {
+                // Arrivals: each record's walkers added to its child's entry, initiator
+                // flags OR-ed (the sort and compress of Sec. 4.1, by hashing).
+                for (uint32_t j = t; j < nr; j += 256) {
+                    const uint32_t f = a.srt_f[r0 + j];
+                    if (round > 0 && !(f & F_DEFER)) continue;
+                    const uint64_t D = a.srt_det[r0 + j];
+                    const int e = lds_find_or_claim(D, s_det, s_hash, &s_ncand);
+                    if (e < 0) {
+                        a.srt_f[r0 + j] = (f & F_INIT) | F_MAYBE;
+                        s_maybe = 1;
+                        continue;
+                    }
+                    if (f & F_DEFER) a.srt_f[r0 + j] = f & F_INIT;
+                    atomicAdd((unsigned long long *)&s_acc[e],
+                              (unsigned long long)(long long)a.srt_w[r0 + j]);
+                    if (f & F_INIT) atomicOr(&s_flg[e >> 5], 1u << (e & 31));
+                }
+                __syncthreads();
+                if (s_maybe) {
+                    // records that found the candidate area full: merged after all if their
+                    // child was entered meanwhile, otherwise left for the next round
+                    for (uint32_t j = t; j < nr; j += 256) {
+                        const uint32_t f = a.srt_f[r0 + j];
+                        if (!(f & F_MAYBE)) continue;
+                        const uint64_t D = a.srt_det[r0 + j];
+                        const int e = lds_find(D, s_det, s_hash);
+                        if (e < 0) {
+                            a.srt_f[r0 + j] = (f & F_INIT) | F_DEFER;
+                            s_defer = 1;
+                            continue;
+                        }
+                        a.srt_f[r0 + j] = f & F_INIT;
+                        atomicAdd((unsigned long long *)&s_acc[e],
+                                  (unsigned long long)(long long)a.srt_w[r0 + j]);
+                        if (f & F_INIT) atomicOr(&s_flg[e >> 5], 1u << (e & 31));
+                    }
+                    __syncthreads();
+                }
+                if (round == 0) {
+                    // The bucket's own entries: death (Eq. pdeath, one stochastic rounding
+                    // for the whole determinant), then annihilation (Sec. 4.2): occupied
+                    // after death -> add the arrived walkers; otherwise they survive only
+                    // if an initiator sent some of them.
+                    int nhole = 0, nlive = 0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = 4 * t + u;
+                        if (e >= n) continue;
+                        const uint64_t D = kin[u];
+                        const int32_t p = pin[u];
+                        int64_t pd = p;
+                        if (p != 0) {
+                            uint64_t xd, xu;
+                            draw2(d.seed, D, 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
+                            const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
+                            const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
+                            const double ad = fabs(dv);
+                            const double fl = floor(ad);
+                            if (fl > 1073741824.0) {
+                                atomicOr(status, ST_POP_OVERFLOW);
+                                keep[u] = true;
+                                npv[u] = p;
+                                ++nlive;
+                                continue;
+                            }
+                            const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
+                            pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
+                        }
+                        const bool present = pd != 0 || D == d.d0;
+                        const long long sp = s_acc[e];
+                        const bool fl = (s_flg[e >> 5] >> (e & 31)) & 1u;
+                        int64_t np;
+                        if (present) {
+                            np = pd + sp;
+                        } else if (sp != 0 && fl) {
+                            np = sp;
+                        } else {
+                            np = 0;
+                            if (sp != 0) aborted += sp < 0 ? -sp : sp;
+                        }
+                        if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
+                        if (np > 2147483647ll || np < -2147483647ll) {
+                            atomicOr(status, ST_POP_OVERFLOW);
+                            np = 0;
+                        }
+                        npv[u] = (int32_t)np;
+                        keep[u] = np != 0 || D == d.d0;   // the reference keeps its entry at 0
+                        if (D == d.d0) a.c0[s] = np;
+                        if (np != 0) {
+                            const int64_t an = np < 0 ? -np : np;
+                            nw += an;
+                            nwb += (unsigned long long)an;
+                            cnt += 1ull << CNT_SHIFT_ND;
+                            if (D != d.d0 && __popcll(D ^ d.d0) <= 4)
+                                num = num + hel_to_ref(d, D) * (double)np;
+                        }
+                        nhole += keep[u] ? 0 : 1;
+                        nlive += keep[u] ? 1 : 0;
+                    }
+                    // positions emptied this iteration, in ascending order
+                    int tot;
+                    int pre = block_excl_scan(nhole, s_w, &tot);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (4 * t + u < n && !keep[u]) s_free[pre++] = (uint16_t)(4 * t + u);
+                    int tl;
+                    (void)block_excl_scan(nlive, s_w, &tl);
+                    if (t == 0) {
+                        s_nhole = tot;
+                        s_nlive = tl;
+                    }
+                    __syncthreads();
+                }
+                // This round's candidates: children not in the bucket. With an initiator
+                // parent the merged walkers form a new determinant in the next free
+                // position (an emptied one first, then past the end); otherwise they are
+                // discarded (Sec. 4.2).
+                const int ncand = s_ncand < NCAND ? s_ncand : NCAND;
+                const int nh = s_nhole;
+                for (int i = t; i < ncand; i += 256) {
+                    const int e = CHUNK + i;
+                    const uint64_t D = s_det[e];
+                    if (D == 0ull) continue;   // claimed, then not needed
+                    const long long sp = s_acc[e];
+                    if (sp == 0) continue;     // cancelled out
+                    cnt += 1ull << CNT_SHIFT_MERGED;
+                    if (!((s_flg[e >> 5] >> (e & 31)) & 1u)) {
+                        aborted += sp < 0 ? -sp : sp;
+                        continue;
+                    }
+                    if (sp > 2147483647ll || sp < -2147483647ll) {
+                        atomicOr(status, ST_POP_OVERFLOW);
+                        continue;
+                    }
+                    const int k = atomicAdd(&s_kplaced, 1);
+                    const int pos = k < nh ? (int)s_free[k] : n + (k - nh);
+                    const int64_t an = sp < 0 ? -sp : sp;
+                    nw += an;
+                    cnt += 1ull << CNT_SHIFT_ND;
+                    if (__popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)sp;
+                    if (pos < CHUNK) {
+                        nwb += (unsigned long long)an;
+                        *gp(d.key + base + pos) = D;
+                        *gp(d.pop + base + pos) = (int32_t)sp;
+                        const int q = atomicAdd(&s_qn, 1);
+                        if (q < POST_QUEUE) {
+                            s_queue[q] = (uint32_t)(base + pos);
+                        } else {   // (only after several rounds in one bucket)
+                            double h0, h1;
+                            hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, d.n_so, h0, h1);
+                            *gp(d.hdiag + base + pos) = h0;
+                        }
+                    } else {
+                        // the bucket is full: completed in the spill list, re-bucketed by the host
+                        double h0, h1;
+                        hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, d.n_so, h0, h1);
+                        const unsigned long long j = atomicAdd(a.sp_count, 1ull);
+                        if (j < (unsigned long long)a.sp_cap) {
+                            a.sp_det[j] = D;
+                            a.sp_pop[j] = (int32_t)sp;
+                            a.sp_hd[j] = h0;
+                            a.sp_sys[j] = s;
+                            a.spilled[s] = 1u;
+                        } else {
+                            atomicOr(status, ST_SPILL_FULL);
+                        }
+                    }
+                }
+                __syncthreads();
+                if (!s_defer) break;
+                // Another round for the records left over: none of their children is an
+                // entry of the bucket or a candidate of an earlier round.
+                for (int i = t; i < LHASH; i += 256) s_hash[i] = 0u;
+                for (int i = CHUNK + t; i < NLDS; i += 256) s_acc[i] = 0ll;
+                if (t < NCAND / 32) s_flg[CHUNK / 32 + t] = 0u;
+                __syncthreads();
+                if (t == 0) {
+                    s_ncand = 0;
+                    s_maybe = 0;
+                    s_defer = 0;
+                }
+                __syncthreads();
+            }
+            // Re-pack: the bucket keeps n' = (kept entries) + (new determinants) entries;
+            // when fewer new determinants than emptied positions arrived, the kept
+            // entries past n' move into the emptied positions that remain below n'.
+            const int K = s_kplaced, H = s_nhole, L = s_nlive;
+            const int np_ = L + K < CHUNK ? L + K : CHUNK;
+            bool moved[4] = {false, false, false, false};
+            if (K < H) {   // uniform
+                int nm = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    moved[u] = 4 * t + u < n && keep[u] && 4 * t + u >= np_;
+                    nm += moved[u] ? 1 : 0;
+                }
+                int tot;
+                int r = block_excl_scan(nm, s_w, &tot);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!moved[u]) continue;
+                    const int64_t dst = base + s_free[K + r++];
+                    *gp(d.key + dst) = kin[u];
+                    *gp(d.pop + dst) = npv[u];
+                    *gp(d.hdiag + dst) = hin[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (keep[u] && !moved[u] && npv[u] != pin[u]) *gp(d.pop + base + 4 * t + u) = npv[u];
+            if (t == 0) {
+                d.bcnt[b] = np_;
+                cnt += (uint64_t)np_;
+            }
         }
         // fixed-order reduction per wavefront (lane butterfly); each wavefront writes its
-        // own share of the chunk
+        // own share of the bucket
         nw = wave_sum((long long)nw);
         aborted = wave_sum((long long)aborted);
         cnt = wave_sum((unsigned long long)cnt);
         num = wave_sum(num);
+        nwb = wave_sum(nwb);
         if (lane == 0) {
             a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
             // walkers that spawn next iteration: none if the system stops after this one
             const bool next = live && desc[s].iter + 1 < desc[s].stop_at;
-            s_nwn[seq & 1u][wid] = next ? (unsigned long long)nw : 0ull;
+            s_nwn[wid] = next ? nwb : 0ull;
         }
-        // the shares of all wavefronts are in s_nwn before thread 0 adds them up
         __syncthreads();
         if (t == 0) {
-            // flush at the start of the chunk after next when the queue is half full
-            // (the other wavefronts may already be adding to it: the count is a bound)
-            s_flush[seq & 1u] = s_qn > POST_QUEUE / 2 ? 1 : 0;
-            // (the other wavefronts may already be on chunk c + 1, which writes the other
-            // parity of s_nwn)
             unsigned long long x = 0ull;
-            for (int w = 0; w < POST_WAVES; ++w) x += s_nwn[seq & 1u][w];
+            for (int w = 0; w < POST_WAVES; ++w) x += s_nwn[w];
             nws_next[c] = x;
             if (x) {
                 atomicAdd(&rg_next[c / per_range], x);
                 atomicAdd(&rg_next[SCAN_G + c / per_range], (x + tm) >> tsh);
             }
+            // the bucket's records are consumed: counts start at zero next iteration
+            a.bhist[c] = 0u;
+            a.bcur[c] = 0u;
         }
-        ++seq;
     }
     __syncthreads();
     {
-        const int n = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
-        if (loaded >= 0 && n > 0) flush_new_dets(desc[loaded], s_queue, n, s_hpp, s_jk);
+        const int nq = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
+        if (loaded >= 0 && nq > 0) flush_new_dets(desc[loaded], s_queue, nq, s_hpp, s_jk);
     }
 }
 
@@ -1348,6 +1681,12 @@ __global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
         r.shift = d.shift;
         r.varying = d.varying;
         r.status = (int32_t)a.status[s];
+        if (a.spilled[s]) {
+            // new determinants wait in the spill list: pause until the host re-buckets
+            a.status[s] |= ST_SPILLED;
+            r.status = (int32_t)a.status[s];
+            a.spilled[s] = 0u;
+        }
         a.rec[(int64_t)s * REC_CAP + (done % REC_CAP)] = r;
         a.spawns[s] = 0ull;
         d.iter = done;
@@ -1370,6 +1709,10 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool f
     hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[3], s);
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
+                       (const SysDesc *)a.desc);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)spawn_grid), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[4], s);
@@ -1379,54 +1722,90 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool f
 }
 
 // ---------------------------------------------------------------------------
-// Loading a walker list, rehashing into a grown table, exporting.
+// Loading a walker list, re-bucketing into more (or fewer) buckets, exporting.
 // ---------------------------------------------------------------------------
+// Append determinant D (population p, diagonal element hd) to its bucket.
+__device__ __forceinline__ bool bucket_put(const SysDesc &d, uint64_t D, int32_t p, double hd) {
+    const uint32_t b = bucket_of(D, (uint64_t)d.nchunks);
+    const int pos = atomicAdd(&d.bcnt[b], 1);
+    if (pos >= CHUNK) return false;
+    const int64_t j = (int64_t)b * CHUNK + pos;
+    d.key[j] = D;
+    d.pop[j] = p;
+    d.hdiag[j] = hd;
+    return true;
+}
+
 __global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const int32_t *pop,
                        int64_t n, uint32_t *err) {
     const SysDesc &d = desc[sys];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t D = det[i];
-        const int64_t j = insert_unique(d.key, d.cap, D);
-        if (j < 0) {
-            atomicOr(err, 1u);
-            continue;
-        }
-        d.pop[j] = pop[i];
-        d.hdiag[j] = hdiag_of(d, D);
+        if (!bucket_put(d, D, pop[i], hdiag_of(d, D))) atomicOr(err, 1u);
     }
 }
 
-__global__ void k_rehash(SysDesc *desc, int32_t sys, const uint64_t *skv, const int32_t *spop,
-                         const double *shd, int64_t scap, uint64_t *dkv, int32_t *dpop, double *dhd,
-                         uint32_t *err) {
+__global__ void k_rebucket(SysDesc *desc, int32_t sys, const uint64_t *skey, const int32_t *spop,
+                           const double *shd, const int32_t *scnt, int64_t snb,
+                           const uint64_t *xdet, const int32_t *xpop, const double *xhd,
+                           const int32_t *xsys, int64_t nx, uint32_t *err) {
     const SysDesc &d = desc[sys];
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < scap;
+    const int64_t ns = snb * CHUNK;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns + nx;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t D = skv[i];
-        if (D == 0) continue;
-        const int32_t p = spop[i];
-        if (p == 0 && D != d.d0) continue;
-        const int64_t j = insert_unique(dkv, d.cap, D);
-        if (j < 0) {
-            atomicOr(err, 1u);
-            continue;
+        uint64_t D;
+        int32_t p;
+        double hd;
+        if (i < ns) {
+            if ((int)(i % CHUNK) >= scnt[i / CHUNK]) continue;
+            D = skey[i];
+            p = spop[i];
+            hd = shd[i];
+        } else {
+            const int64_t k = i - ns;
+            if (xsys[k] != sys) continue;
+            D = xdet[k];
+            p = xpop[k];
+            hd = xhd[k];
         }
-        dpop[j] = p;
-        dhd[j] = shd[i];
+        if (p == 0 && D != d.d0) continue;
+        if (!bucket_put(d, D, p, hd)) atomicOr(err, 1u);
     }
 }
 
-__global__ void k_compact(const uint64_t *kv, const int32_t *pop, int64_t cap, uint64_t *odet,
-                          int32_t *opop, unsigned long long *count) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t D = kv[i];
-        const int32_t p = pop[i];
-        if (D == 0 || p == 0) continue;
-        const unsigned long long j = atomicAdd(count, 1ull);
-        odet[j] = D;
-        opop[j] = p;
+// Occupied entries (population != 0) of nb buckets, in any order, into odet/opop
+// (at most `limit` written; *count gets the total). One counter atomic per wavefront.
+__global__ __launch_bounds__(256) void k_compact(const uint64_t *kv, const int32_t *pop,
+                                                 const int32_t *cnt, int64_t nb, uint64_t *odet,
+                                                 int32_t *opop, unsigned long long *count,
+                                                 int64_t limit) {
+    const int lane = threadIdx.x & 63;
+    const int64_t ns = nb * CHUNK;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ns;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        bool take = false;
+        uint64_t D = 0;
+        int32_t p = 0;
+        if (i < ns && (int)(i % CHUNK) < cnt[i / CHUNK]) {
+            D = kv[i];
+            p = pop[i];
+            take = p != 0;
+        }
+        const uint64_t m = __ballot(take);
+        if (!m) continue;
+        unsigned long long b = 0;
+        const int first = __builtin_ctzll(m);
+        if (lane == first) b = atomicAdd(count, (unsigned long long)__popcll(m));
+        b = __shfl(b, first, 64);
+        if (take) {
+            const unsigned long long j = b + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+            if (j < (unsigned long long)limit) {
+                odet[j] = D;
+                opop[j] = p;
+            }
+        }
     }
 }
 
@@ -1439,21 +1818,25 @@ hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const 
     return hipGetLastError();
 }
 
-hipError_t launch_rehash(SysDesc *d_desc, int32_t sys, const uint64_t *src_kv,
-                         const int32_t *src_pop, const double *src_hd, int64_t src_cap,
-                         uint64_t *dst_kv, int32_t *dst_pop,
-                         double *dst_hd, uint32_t *d_err, hipStream_t s) {
-    const int64_t g = (src_cap + 255) / 256;
-    hipLaunchKernelGGL(k_rehash, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, d_desc,
-                       sys, src_kv, src_pop, src_hd, src_cap, dst_kv, dst_pop, dst_hd, d_err);
+hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,
+                           const int32_t *src_pop, const double *src_hd, const int32_t *src_cnt,
+                           int64_t src_nb, const uint64_t *sp_det, const int32_t *sp_pop,
+                           const double *sp_hd, const int32_t *sp_sys, int64_t n_sp,
+                           uint32_t *d_err, hipStream_t s) {
+    const int64_t g = (src_nb * CHUNK + n_sp + 255) / 256;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rebucket, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
+                       d_desc, sys, src_key, src_pop, src_hd, src_cnt, src_nb, sp_det, sp_pop,
+                       sp_hd, sp_sys, n_sp, d_err);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const uint64_t *kv, const int32_t *pop, int64_t cap, uint64_t *out_det,
-                          int32_t *out_pop, unsigned long long *count, hipStream_t s) {
-    const int64_t g = (cap + 255) / 256;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, kv,
-                       pop, cap, out_det, out_pop, count);
+hipError_t launch_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt, int64_t nb,
+                          uint64_t *out_det, int32_t *out_pop, unsigned long long *count,
+                          hipStream_t s) {
+    const int64_t g = (nb * CHUNK + 255) / 256;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, key,
+                       pop, cnt, nb, out_det, out_pop, count, nb * CHUNK);
     return hipGetLastError();
 }
 
@@ -1465,32 +1848,6 @@ hipError_t launch_compact(const uint64_t *kv, const int32_t *pop, int64_t cap, u
 // ---------------------------------------------------------------------------
 __global__ void k_stage_clear(unsigned long long *count) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0ull;
-}
-
-__global__ __launch_bounds__(256) void k_stage_compact(const uint64_t *kv, const int32_t *pop,
-                                                       int64_t cap, unsigned long long *count,
-                                                       uint64_t *okey, int32_t *oval) {
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cap;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const uint64_t D = i < cap ? kv[i] : 0ull;
-        const int32_t p = i < cap ? pop[i] : 0;
-        const bool take = D != 0ull && p != 0;
-        const uint64_t m = __ballot(take);
-        if (!m) continue;
-        unsigned long long b = 0;
-        const int first = __builtin_ctzll(m);
-        if (lane == first) b = atomicAdd(count, (unsigned long long)__popcll(m));
-        b = __shfl(b, first, 64);
-        if (take) {
-            const unsigned long long j = b + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
-            if (j < (unsigned long long)NOALLOC_MAX_DETS) {
-                okey[j] = D;
-                oval[j] = p;
-            }
-        }
-    }
 }
 
 __global__ void k_stage_pad(uint64_t *key, int64_t n, int64_t P) {
@@ -1535,15 +1892,15 @@ hipError_t launch_stage_flags(void *stage, int64_t n, int32_t n_a, uint64_t d0, 
     return hipGetLastError();
 }
 
-hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, int64_t cap, void *stage,
-                                hipStream_t s) {
+hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt,
+                                int64_t nb, void *stage, hipStream_t s) {
     char *p = (char *)stage;
     unsigned long long *count = (unsigned long long *)p;
     hipLaunchKernelGGL(k_stage_clear, dim3(1), dim3(64), 0, s, count);
-    const int64_t g = (cap + 255) / 256;
-    hipLaunchKernelGGL(k_stage_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
-                       key, pop, cap, count, (uint64_t *)(p + NOALLOC_KEYS_OFF),
-                       (int32_t *)(p + NOALLOC_VALS_OFF));
+    const int64_t g = (nb * CHUNK + 255) / 256;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, key,
+                       pop, cnt, nb, (uint64_t *)(p + NOALLOC_KEYS_OFF),
+                       (int32_t *)(p + NOALLOC_VALS_OFF), count, (int64_t)NOALLOC_MAX_DETS);
     return hipGetLastError();
 }
 
@@ -1573,7 +1930,7 @@ hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out
     return hipGetLastError();
 }
 
-int post_grid_size() { return spawn_grid_size() / 8 * 6; }   // six workgroups per CU
+int post_grid_size() { return spawn_grid_size() / 8 * 3; }   // three workgroups per CU (LDS)
 
 int spawn_grid_size() {
     int dev = 0, cus = 256;

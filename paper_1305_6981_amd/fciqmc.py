@@ -49,7 +49,8 @@ _EST_DBL = ("shift", "e_ref", "p_double", "proj_num", "e_proj_inst", "e_proj_mea
 
 class Estimates(C.Structure):
     _fields_ = [(n, C.c_int64) for n in _EST_INT] + [(n, C.c_double) for n in _EST_DBL] + \
-               [("shift_varying", C.c_int32), ("status", C.c_int32), ("redos", C.c_int64)] + \
+               [("shift_varying", C.c_int32), ("status", C.c_int32), ("redos", C.c_int64),
+                ("spills", C.c_int64)] + \
                [(n, C.c_double) for n in ("ms_spawn", "ms_death", "ms_annihilate",
                                           "ms_estimators")]
 
@@ -100,7 +101,7 @@ def lib():
             "fciqmc_autotune": ([vp, i32], C.c_int),
             "fciqmc_blocking": ([vp, vp, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
                                 C.c_int),
-            "fciqmc_set_test_options": ([vp, i32, i64], C.c_int),
+            "fciqmc_set_test_options": ([vp, i32, i64, i64], C.c_int),
             "fciqmc_walkers_noalloc": ([vp, vp, vp, vp, i64], i64),
         }
         for name, (args, res) in sig.items():
@@ -321,8 +322,9 @@ def fciqmc_blocking(num, den=None):
     return m.value, e.value
 
 
-def fciqmc_set_test_options(handle, planner=1, tile_map_limit=-1):
-    _check(lib().fciqmc_set_test_options(handle, int(planner), int(tile_map_limit)))
+def fciqmc_set_test_options(handle, planner=1, tile_map_limit=-1, record_capacity=0):
+    _check(lib().fciqmc_set_test_options(handle, int(planner), int(tile_map_limit),
+                                         int(record_capacity)))
 
 
 class Solver:

@@ -15,24 +15,28 @@ from test_gpu_parity import _same_estimates, _same_lists, _stream
 pytestmark = pytest.mark.gpu
 
 
-def test_overflow_inside_iteration_is_redone_bit_exactly():
-    """With the planner off a 4096-slot table fills up during spawning; the
-    iteration is abandoned, the table grown, and the iteration run again."""
+def test_overflows_inside_iterations_are_handled_bit_exactly():
+    """With the planner off, a 4096-entry main list and a 512-record spawn buffer
+    overflow during iterations: an iteration whose records do not fit is
+    abandoned and re-run after the buffer grows, and new determinants that do
+    not fit their bucket complete the iteration through the spill list before
+    the list is re-bucketed."""
     ham, prm, _ = S.workload("hubbard8")
     prm.det_capacity = 4096
     prm.target_walkers = 30000
-    print("[gpu] redo: hubbard8, planner off", flush=True)
+    print("[gpu] overflow paths: hubbard8, planner off", flush=True)
     gpu = F.Solver(ham, prm, _stream())
-    F.fciqmc_set_test_options(gpu.h, 0, -1)
+    F.fciqmc_set_test_options(gpu.h, 0, -1, 512)
     ref = O.Oracle(ham, prm)
     for b in range(4):
         gpu.iterate(40)
         ref.iterate(40)
-        _same_lists(gpu, ref, f"redo{b}")
-        _same_estimates(gpu.estimates(), ref.estimates(), f"redo{b}")
+        _same_lists(gpu, ref, f"overflow{b}")
+        _same_estimates(gpu.estimates(), ref.estimates(), f"overflow{b}")
     e = gpu.estimates()
-    print(f"[gpu] redo: {e['redos']} iterations re-run, {e['table_slots']} slots", flush=True)
-    assert e["redos"] > 0
+    print(f"[gpu] overflow paths: {e['redos']} iterations re-run, {e['spills']} spilled, "
+          f"{e['table_slots']} slots", flush=True)
+    assert e["redos"] > 0 and e["spills"] > 0
     gpu.close()
 
 
@@ -44,7 +48,7 @@ def test_tile_search_without_map(limit):
     prm.initial_walkers, prm.initial_shift, prm.tau = 300, 1.0, 2e-3
     print(f"[gpu] tile search: map limit {limit}", flush=True)
     gpu = F.Solver(ham, prm, _stream())
-    F.fciqmc_set_test_options(gpu.h, 1, limit)
+    F.fciqmc_set_test_options(gpu.h, 1, limit, 0)
     F.fciqmc_set_launch(gpu.h, 512, 256, 256)       # small tiles: many of them
     ref = O.Oracle(ham, prm)
     for b in range(3):
