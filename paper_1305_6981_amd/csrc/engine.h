@@ -5,9 +5,12 @@
 
 namespace fq {
 
-constexpr int CHUNK = 1024;          // entries per bucket of the main list: the unit of
-                                     // attempt mapping, spawn staging and annihilation
-constexpr int BUCKET_FILL = 512;     // planned mean entries per bucket (half full)
+constexpr int BQ = 256;              // entries per bucket of the main list (a wavefront's unit
+                                     // in annihilation: four per lane)
+constexpr int CHUNK = 1024;          // four consecutive buckets: the unit of attempt mapping and
+                                     // spawn staging, and one workgroup's unit in annihilation
+constexpr int BPC = CHUNK / BQ;      // buckets per chunk
+constexpr int BUCKET_FILL = 128;     // planned mean entries per bucket (half full)
 constexpr int NCLASS = 16;           // symmetry classes: 2 spins x up to 8 abelian irreps
 constexpr int REC_CAP = 256;         // per-system ring of per-iteration records
 constexpr int MAX_GRAPH_ITERS = 64;  // iterations captured in one graph launch
@@ -36,15 +39,17 @@ struct IterRecord {
     int32_t varying, status;
 };
 
-// Per-bucket statistics of an iteration. counts packs three numbers of at most
-// 2 CHUNK each: entries | merged spawn targets << 21 | occupied << 42.
+// Statistics of one bucket of an iteration (one share per wavefront of a chunk).
+// counts packs three numbers below 2^21: entries | merged spawn targets << 21 |
+// occupied << 42.
 struct ChunkStat {
     int64_t nw, aborted;
     uint64_t counts;
     double num;
 };
 constexpr int CNT_SHIFT_MERGED = 21, CNT_SHIFT_ND = 42;
-constexpr int POST_WAVES = 4;   // wavefronts of a k_post workgroup; one ChunkStat share each
+constexpr int POST_WAVES = BPC;   // wavefronts of a k_post workgroup: one bucket and one
+                                   // ChunkStat share each
 constexpr uint64_t CNT_FIELD = (1ull << 21) - 1;
 
 // One workgroup's share of a system's iteration statistics.
@@ -75,15 +80,16 @@ struct SysDesc {
     const double *h1, *eri;
     const double *jk;                // [n_so][64]: (pp|qq) - (pq|qp) for p < q, spin orbitals
     const double *t3;                // [n_so][64][64]: (pa|qq) - d(s_p,s_q)(pq|qa), same-spin p, a
-    // Main list: nb buckets of CHUNK entries (structure of arrays); a determinant lives
+    // Main list: nb buckets of BQ entries (structure of arrays); a determinant lives
     // in bucket floor(mix64(D) nb / 2^64), the entries of bucket b are the first
-    // bcnt[b] of [b CHUNK, (b+1) CHUNK), every one occupied (the reference may sit at 0).
+    // bcnt[b] of [b BQ, (b+1) BQ), every one occupied (the reference may sit at 0).
     uint64_t *key;                   // determinant
     int32_t *pop;                    // signed walker count
     double *hdiag;                   // stored H_DD
     int32_t *bcnt;                   // entries per bucket
-    uint64_t cap;                    // nb * CHUNK
-    int64_t nchunks, gchunk0;        // buckets (= chunks) of this system and the first global one
+    uint64_t cap;                    // nb * BQ
+    int64_t nbuckets;                // nb
+    int64_t nchunks, gchunk0;        // chunks (nb / BPC) of this system and the first global one
     int64_t stop_at;                 // iterate while iter < stop_at
     // --- updated on the device
     int64_t iter;
@@ -118,19 +124,24 @@ struct EngineArgs {
     uint32_t *tile_chunk;            // [tile_cap] chunk of each spawn tile (k_scan_down); tiles
     int64_t tile_cap;                // beyond the capacity are found by search
     // Spawn records of the iteration (the per-destination blocks of Sec. 4.1, with the
-    // bucket as destination): appended by k_spawn, counted per bucket, sorted by bucket.
+    // bucket as destination): appended by k_spawn with their rank among the bucket's
+    // records, grouped by bucket by k_scatter.
     uint64_t *rec_det;               // [rec_cap] child determinant
     int32_t *rec_w;                  // [rec_cap] signed walkers
-    uint32_t *rec_gf;                // [rec_cap] system (from k_spawn), then global bucket
-                                     // (from k_hist) | initiator flag << 31
+    uint32_t *rec_gf;                // [rec_cap] global bucket | initiator flag << 31, or the
+                                     // system | REC_UNRANKED for k_fix to place
+    uint32_t *rec_rank;              // [rec_cap] rank among its bucket's records
     uint64_t *srt_det;               // [rec_cap] the records grouped by bucket
     int32_t *srt_w;
     uint32_t *srt_f;                 // bit 0 initiator flag, bit 1 deferred to a later round
     unsigned long long *rec_count;   // records appended this iteration
     int64_t rec_cap;
-    uint32_t *bhist;                 // [chunk_cap] records per bucket
-    uint32_t *bcur;                  // [chunk_cap] scatter cursor per bucket
-    uint32_t *boff;                  // [chunk_cap] first sorted record of each bucket
+    uint32_t *bhist;                 // [BPC chunk_cap] records per bucket (zeroed by k_bscan_down)
+    uint32_t *boff;                  // [BPC chunk_cap + 1] first sorted record of each bucket,
+                                     // and the end of the last one
+    long long *d0acc;                // [max_sys] walkers spawned onto the reference (kept out of
+                                     // the records: the reference is the hot spot of Sec. 4.1)
+    unsigned long long *boff_rg;     // [2 SCAN_G] records per range of buckets, their scan
     // New determinants that did not fit their bucket (completed, then re-bucketed by the host).
     uint64_t *sp_det;
     int32_t *sp_pop, *sp_sys;

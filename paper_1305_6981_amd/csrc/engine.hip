@@ -58,9 +58,9 @@ int64_t round_cap(int64_t x) {
     return std::max<int64_t>(q, (x + q - 1) / q * q);
 }
 
-// Buckets for `entries` entries at the planned mean fill.
+// Main-list capacity for `entries` entries at the planned mean bucket fill.
 int64_t cap_for_entries(int64_t entries) {
-    return round_cap((std::max<int64_t>(entries, 1) + BUCKET_FILL - 1) / BUCKET_FILL * CHUNK);
+    return round_cap((std::max<int64_t>(entries, 1) + BUCKET_FILL - 1) / BUCKET_FILL * BQ);
 }
 
 int64_t next_pow2(int64_t x) {
@@ -173,7 +173,7 @@ struct SysHost {
     std::vector<uint8_t> irrep;
     double e_core = 0.0, p_double = 0.0, e0 = 0.0;
     uint64_t d0 = 0;
-    int64_t cap = 0;           // main-list capacity: buckets * CHUNK
+    int64_t cap = 0;           // main-list capacity: buckets * BQ
     void *block = nullptr;     // one device allocation for the main list + integrals
     uint64_t *key = nullptr;
     int32_t *pop = nullptr;
@@ -226,7 +226,9 @@ struct fciqmc_t {
     void *d_recs = nullptr;
     int64_t rec_cap = 0;
     unsigned long long *d_rec_count = nullptr;
-    uint32_t *d_bhist = nullptr, *d_bcur = nullptr, *d_boff = nullptr;
+    uint32_t *d_bhist = nullptr, *d_boff = nullptr;
+    long long *d_d0acc = nullptr;
+    unsigned long long *d_boff_rg = nullptr;
     void *d_spill = nullptr;
     int64_t sp_cap = 0;
     unsigned long long *d_sp_count = nullptr;
@@ -292,11 +294,13 @@ EngineArgs make_args(fciqmc_t *h) {
     a.rec_gf = (uint32_t *)(r + 20 * rc);
     a.srt_w = (int32_t *)(r + 24 * rc);
     a.srt_f = (uint32_t *)(r + 28 * rc);
+    a.rec_rank = (uint32_t *)(r + 32 * rc);
     a.rec_count = h->d_rec_count;
     a.rec_cap = h->rec_cap;
     a.bhist = h->d_bhist;
-    a.bcur = h->d_bcur;
+    a.d0acc = h->d_d0acc;
     a.boff = h->d_boff;
+    a.boff_rg = h->d_boff_rg;
     char *q = (char *)h->d_spill;
     const size_t sc = (size_t)h->sp_cap;
     a.sp_det = (uint64_t *)q;
@@ -309,7 +313,7 @@ EngineArgs make_args(fciqmc_t *h) {
     return a;
 }
 
-// The spawn-record buffer for `cap` records (32 B each: unsorted and sorted copies).
+// The spawn-record buffer for `cap` records (36 B each: unsorted with rank, and sorted).
 int ensure_records(fciqmc_t *h, int64_t cap) {
     if (cap <= h->rec_cap) return 0;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -317,7 +321,7 @@ int ensure_records(fciqmc_t *h, int64_t cap) {
     h->d_recs = nullptr;
     h->rec_cap = 0;
     drop_graphs(h);
-    if (hipMalloc(&h->d_recs, (size_t)cap * 32) != hipSuccess) {
+    if (hipMalloc(&h->d_recs, (size_t)cap * 36) != hipSuccess) {
         (void)hipGetLastError();
         return set_err(FCIQMC_ENOMEM, "spawn-record buffer of " + std::to_string(cap) +
                                           " records does not fit in device memory");
@@ -343,8 +347,11 @@ int download_desc(fciqmc_t *h) {
     return 0;
 }
 
+// Clear what spawning accumulates for system s outside the records (its event
+// count and its walkers onto the reference): after an abandoned iteration or a load.
 int reset_spawns(fciqmc_t *h, int s) {
     HIP_TRY(hipMemsetAsync(h->d_spawns + s, 0, sizeof(unsigned long long), h->stream));
+    HIP_TRY(hipMemsetAsync(h->d_d0acc + s, 0, sizeof(long long), h->stream));
     return 0;
 }
 
@@ -362,7 +369,6 @@ int relayout(fciqmc_t *h) {
         hipFree(h->d_chunk_toff);
         hipFree(h->d_chunk_stat);
         hipFree(h->d_bhist);
-        hipFree(h->d_bcur);
         hipFree(h->d_boff);
         h->d_chunk_sys = nullptr;
         h->chunk_alloc = 0;
@@ -372,15 +378,13 @@ int relayout(fciqmc_t *h) {
         HIP_TRY(hipMalloc(&h->d_chunk_off, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_toff, na * sizeof(unsigned long long)));
         HIP_TRY(hipMalloc(&h->d_chunk_stat, na * POST_WAVES * sizeof(ChunkStat)));
-        HIP_TRY(hipMalloc(&h->d_bhist, na * sizeof(uint32_t)));
-        HIP_TRY(hipMalloc(&h->d_bcur, na * sizeof(uint32_t)));
-        HIP_TRY(hipMalloc(&h->d_boff, na * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&h->d_bhist, BPC * na * sizeof(uint32_t)));
+        HIP_TRY(hipMalloc(&h->d_boff, (BPC * na + 1) * sizeof(uint32_t)));
         h->chunk_alloc = na;
         drop_graphs(h);
     }
-    // record counts start at zero (k_post keeps them so after every iteration)
-    HIP_TRY(hipMemsetAsync(h->d_bhist, 0, h->chunk_alloc * sizeof(uint32_t), h->stream));
-    HIP_TRY(hipMemsetAsync(h->d_bcur, 0, h->chunk_alloc * sizeof(uint32_t), h->stream));
+    // record counts start at zero (the record scan keeps them so after every iteration)
+    HIP_TRY(hipMemsetAsync(h->d_bhist, 0, BPC * h->chunk_alloc * sizeof(uint32_t), h->stream));
     std::vector<int32_t> cs(total), cl(total);
     int64_t g = 0;
     for (int s = 0; s < h->max_sys; ++s) {
@@ -388,11 +392,13 @@ int relayout(fciqmc_t *h) {
         if (!h->sys[s].active) {
             d.gchunk0 = 0;
             d.nchunks = 0;
+            d.nbuckets = 0;
             continue;
         }
         const int64_t nc = h->sys[s].cap / CHUNK;
         d.gchunk0 = g;
         d.nchunks = nc;
+        d.nbuckets = h->sys[s].cap / BQ;
         for (int64_t c = 0; c < nc; ++c) {
             cs[g + c] = s;
             cl[g + c] = (int32_t)c;
@@ -443,7 +449,7 @@ int ensure_tile_map(fciqmc_t *h) {
 // per entry, and one count per bucket.
 int64_t table_bytes(int64_t cap) {
     return cap * (int64_t)(sizeof(uint64_t) + sizeof(int32_t) + sizeof(double)) +
-           (cap / CHUNK) * (int64_t)sizeof(int32_t) + 256;
+           (cap / BQ) * (int64_t)sizeof(int32_t) + 256;
 }
 
 int64_t integral_doubles(int M) {
@@ -462,7 +468,7 @@ void carve(SysHost &S, void *blk, int64_t cap) {
     S.pop = (int32_t *)p;
     p += cap * sizeof(int32_t);
     S.bcnt = (int32_t *)p;
-    p += (cap / CHUNK) * sizeof(int32_t);
+    p += (cap / BQ) * sizeof(int32_t);
     p = (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
     S.d_h1 = (double *)p;
     p += (size_t)S.M * S.M * sizeof(double);
@@ -488,7 +494,7 @@ int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
     }
     SysHost T = S;
     carve(T, blk, cap);
-    HIP_TRY(hipMemsetAsync(T.bcnt, 0, (size_t)(cap / CHUNK) * sizeof(int32_t), h->stream));
+    HIP_TRY(hipMemsetAsync(T.bcnt, 0, (size_t)(cap / BQ) * sizeof(int32_t), h->stream));
     *block_out = blk;
     return 0;
 }
@@ -514,6 +520,7 @@ void fill_desc_tables(fciqmc_t *h, int s) {
     d.jk = S.d_jk;
     d.t3 = S.d_t3;
     d.cap = (uint64_t)S.cap;
+    d.nbuckets = S.cap / BQ;
 }
 
 // Move the main list of system s (and any of its entries waiting in the spill
@@ -535,12 +542,13 @@ int rebucket_system(fciqmc_t *h, int s, int64_t new_cap, int64_t n_spill) {
         carve(S, blk, new_cap);
         fill_desc_tables(h, s);
         h->hdesc[s].nchunks = new_cap / CHUNK;
+        h->hdesc[s].nbuckets = new_cap / BQ;
         rc = upload_desc(h);
         if (rc) return rc;
         HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
         const EngineArgs a = make_args(h);
         HIP_TRY(launch_rebucket(h->d_desc, s, S_old.key, S_old.pop, S_old.hd, S_old.bcnt,
-                                S_old.cap / CHUNK, a.sp_det, a.sp_pop, a.sp_hd, a.sp_sys, n_spill,
+                                S_old.cap / BQ, a.sp_det, a.sp_pop, a.sp_hd, a.sp_sys, n_spill,
                                 h->d_err, h->stream));
         uint32_t err = 0;
         HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
@@ -802,7 +810,7 @@ int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::v
             rc = relayout(h);
             if (rc) break;
         } else {
-            HIP_TRY(hipMemsetAsync(S.bcnt, 0, (size_t)(S.cap / CHUNK) * sizeof(int32_t), h->stream));
+            HIP_TRY(hipMemsetAsync(S.bcnt, 0, (size_t)(S.cap / BQ) * sizeof(int32_t), h->stream));
         }
         h->hstatus[s] = 0;
         rc = reset_spawns(h, s);
@@ -844,7 +852,7 @@ int export_walkers(fciqmc_t *h, int s, Walkers &w) {
     HIP_TRY(hipMalloc(&op, S.cap * 4));
     HIP_TRY(hipMalloc(&cnt, 8));
     HIP_TRY(hipMemsetAsync(cnt, 0, 8, h->stream));
-    HIP_TRY(launch_compact(S.key, S.pop, S.bcnt, S.cap / CHUNK, od, op, cnt, h->stream));
+    HIP_TRY(launch_compact(S.key, S.pop, S.bcnt, S.cap / BQ, od, op, cnt, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1230,6 +1238,9 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
     HIP_TRY(hipMalloc(&h->d_c0, sizeof(int64_t) * max_slots));
     HIP_TRY(hipMalloc(&h->d_err, sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&h->d_rec_count, sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_boff_rg, 2 * SCAN_G * sizeof(unsigned long long)));
+    HIP_TRY(hipMalloc(&h->d_d0acc, sizeof(long long) * max_slots));
+    HIP_TRY(hipMemsetAsync(h->d_d0acc, 0, sizeof(long long) * max_slots, h->stream));
     HIP_TRY(hipMemsetAsync(h->d_rec_count, 0, sizeof(unsigned long long), h->stream));
     {
         const int rc = ensure_records(h, 65536);
@@ -1320,8 +1331,9 @@ void release(fciqmc_t *h) {
     hipFree(h->d_recs);
     hipFree(h->d_rec_count);
     hipFree(h->d_bhist);
-    hipFree(h->d_bcur);
     hipFree(h->d_boff);
+    hipFree(h->d_boff_rg);
+    hipFree(h->d_d0acc);
     hipFree(h->d_spill);
     hipFree(h->d_sp_count);
     hipFree(h->d_spilled);
@@ -1692,7 +1704,7 @@ int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_
     const int s = 0;
     const SysHost &S = h->sys[s];
     if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
-    HIP_TRY(launch_stage_compact(S.key, S.pop, S.bcnt, S.cap / CHUNK, h->d_stage, h->stream));
+    HIP_TRY(launch_stage_compact(S.key, S.pop, S.bcnt, S.cap / BQ, h->d_stage, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, h->d_stage, sizeof n, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));

@@ -5,7 +5,7 @@
 // densely packed entries (determinant, population, stored H_DD): the paper's
 // distribution of determinants over processes by a hash (Sec. 4.1), with a
 // workgroup in the role of a process. One iteration of every active system is
-// nine launches (ten in the first iteration of a launch sequence):
+// eleven launches (twelve in the first iteration of a launch sequence):
 //
 //   k_chunk_sum   sum |C| over each bucket and over fixed contiguous ranges of
 //                 buckets (first iteration of a launch sequence only;
@@ -17,8 +17,9 @@
 //                 acceptance; each accepted spawn becomes a record (child,
 //                 signed walkers, initiator flag) addressed to the child's
 //                 bucket -- the per-destination blocks of Sec. 4.1
-//   k_hist        the child's bucket of every record, records per bucket
-//   k_bscan       exclusive scan of the records per bucket (one workgroup)
+//   k_fix         bucket and rank of records left unranked by k_spawn (rare)
+//   k_bscan_*     exclusive scan of the records per bucket (range totals, their
+//                 scan, then the scan inside each range)
 //   k_scatter     the records grouped by bucket (a counting sort)
 //   k_post        per bucket, by one workgroup: the records merged per child in
 //                 an LDS hash (the sort and compress of Sec. 4.1); death/cloning
@@ -161,6 +162,14 @@ template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
     return (__attribute__((address_space(1))) T *)p;
 }
+// A load through the constant address space: for a uniform address the compiler
+// issues a scalar load (scalar cache, scalar registers). Only for values this kernel
+// reads before (or never) writing them.
+template <typename T>
+__device__ __forceinline__ T ld_uniform(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // 16-byte global loads and stores through plain vector types.
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
@@ -531,14 +540,16 @@ __global__ __launch_bounds__(256) void k_chunk_sum(EngineArgs a,
             if (cc < c1) {
                 const int sy = a.chunk_sys[cc];
                 if (sy >= 0) {
+                    // the chunk's four buckets, one per wavefront, four entries per lane
                     const SysDesc &d = desc[sy];
-                    const int b = a.chunk_local[cc];
-                    const int n = d.bcnt[b];
-                    if (participating(d, a.status[sy]) && 4 * t < n) {
-                        int4 q = reinterpret_cast<const int4 *>(d.pop + (int64_t)b * CHUNK)[t];
-                        if (4 * t + 1 >= n) q.y = 0;
-                        if (4 * t + 2 >= n) q.z = 0;
-                        if (4 * t + 3 >= n) q.w = 0;
+                    const int64_t lb = (int64_t)a.chunk_local[cc] * BPC + (t >> 6);
+                    const int e = 4 * (t & 63);
+                    const int n = d.bcnt[lb];
+                    if (participating(d, a.status[sy]) && e < n) {
+                        int4 q = *reinterpret_cast<const int4 *>(d.pop + lb * BQ + e);
+                        if (e + 1 >= n) q.y = 0;
+                        if (e + 2 >= n) q.z = 0;
+                        if (e + 3 >= n) q.w = 0;
                         v[k] = abs_sum4(q);
                     }
                 }
@@ -679,24 +690,32 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
 // k+1 / next occupied slot.
 // ---------------------------------------------------------------------------
 
-// Spawn records. A record is (child, signed walkers, system | initiator flag <<
-// 31), appended to the iteration's record buffer (k_hist later replaces the
-// system by the child's bucket). A record that would land past the buffer's
-// capacity is dropped and the system marked: the iteration is then abandoned
-// and re-run after the buffer grows.
-__device__ __forceinline__ void put_record(const EngineArgs &a, int s, unsigned long long j,
-                                           uint64_t D, int32_t v, bool init, uint32_t *status) {
+// Spawn records. A record is (child, signed walkers, child's global bucket |
+// initiator flag << 31, rank among that bucket's records), appended to the
+// iteration's record buffer; the rank comes from the bucket's record counter. A
+// record that would land past the buffer's capacity is dropped and the system
+// marked: the iteration is then abandoned and re-run after the buffer grows.
+// Walkers spawned onto the reference go to a per-system sum instead (every
+// iteration sends it many: the reference is the hot spot of Sec. 4.1).
+constexpr uint32_t REC_UNRANKED = 0x40000000u;
+__device__ __forceinline__ void put_record(const EngineArgs &a, const SysDesc &d, int s,
+                                           unsigned long long j, uint64_t D, int32_t v, bool init,
+                                           uint32_t *status) {
     if (j >= (unsigned long long)a.rec_cap) {
         atomicOr(status, ST_TABLE_FULL);
         return;
     }
+    const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(D, (uint64_t)d.nbuckets);
+    a.rec_rank[j] = __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
     a.rec_det[j] = D;
     a.rec_w[j] = v;
-    a.rec_gf[j] = (uint32_t)s | (init ? 0x80000000u : 0u);
+    a.rec_gf[j] = gb | (init ? 0x80000000u : 0u);
 }
 
 // One record per active lane, with one buffer reservation for the wavefront
-// (callable from divergent code).
+// (callable from divergent code). Its bucket and rank are left to k_fix, which
+// keeps this path short in the spawning loop.
 __device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint64_t D, int32_t v,
                                                 bool init, uint32_t *status) {
     const uint64_t m = __ballot(1);
@@ -705,8 +724,14 @@ __device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint
     unsigned long long base = 0;
     if (lane == leader) base = atomicAdd(a.rec_count, (unsigned long long)__popcll(m));
     base = __shfl(base, leader, 64);
-    put_record(a, s, base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull)), D, v, init,
-               status);
+    const unsigned long long j = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+    if (j >= (unsigned long long)a.rec_cap) {
+        atomicOr(status, ST_TABLE_FULL);
+        return;
+    }
+    a.rec_det[j] = D;
+    a.rec_w[j] = v;
+    a.rec_gf[j] = (uint32_t)s | REC_UNRANKED | (init ? 0x80000000u : 0u);
 }
 
 // Work queued in LDS by the attempt loop and drained by the whole workgroup:
@@ -792,6 +817,10 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         ++spawned;
         const uint64_t Dn = ex.det;
         const bool init = it.init != 0;
+        if (Dn == d.d0) {
+            __hip_atomic_fetch_add(&a.d0acc[s], (long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
         const int qq = atomicAdd(&Q.nspw, 1);
         if (qq < SPW_QUEUE) {
             Q.spd[qq] = Dn;
@@ -807,7 +836,7 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
     __syncthreads();
     for (int j = t; j < nspw; j += blockDim.x) {
         const int2 v = Q.spv[j];
-        put_record(a, s, Q.base + (unsigned long long)j, Q.spd[j], v.x, v.y != 0, status);
+        put_record(a, d, s, Q.base + (unsigned long long)j, Q.spd[j], v.x, v.y != 0, status);
     }
     __syncthreads();
     if (t == 0) {
@@ -906,17 +935,18 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             if (t == 0) Q.sys = s;
         }
         if (t < NCLASS) s_cm[t] = d.cmask[t];   // ordered before use by the barrier below
-        const int64_t base = (int64_t)a.chunk_local[c] * CHUNK;
-        const int n_b = d.bcnt[a.chunk_local[c]];
-        // Stage the bucket's entries that hold walkers, compacted, with the inclusive
-        // prefix sum of |C| (4 consecutive entries per thread).
-        // (a bucket's CHUNK entries are always allocated: entries past the count are read
-        // and ignored)
-        const int4 pv = gload_i4(d.pop + base + 4 * t);
-        const ulonglong2 k01 = gload_u2(d.key + base + 4 * t);
-        const ulonglong2 k23 = gload_u2(d.key + base + 4 * t + 2);
-        const int32_t pa[4] = {4 * t < n_b ? pv.x : 0, 4 * t + 1 < n_b ? pv.y : 0,
-                               4 * t + 2 < n_b ? pv.z : 0, 4 * t + 3 < n_b ? pv.w : 0};
+        // Stage the chunk's entries that hold walkers (its four buckets, one per
+        // wavefront, four entries per lane), compacted, with the inclusive prefix sum
+        // of |C|. (A bucket's BQ entries are always allocated: entries past its count
+        // are read and ignored.)
+        const int64_t lb = (int64_t)a.chunk_local[c] * BPC + wid;
+        const int64_t base = lb * BQ + 4 * lane;
+        const int n_b = d.bcnt[lb] - 4 * lane;
+        const int4 pv = gload_i4(d.pop + base);
+        const ulonglong2 k01 = gload_u2(d.key + base);
+        const ulonglong2 k23 = gload_u2(d.key + base + 2);
+        const int32_t pa[4] = {0 < n_b ? pv.x : 0, 1 < n_b ? pv.y : 0, 2 < n_b ? pv.z : 0,
+                               3 < n_b ? pv.w : 0};
         const uint64_t ka[4] = {k01.x, k01.y, k23.x, k23.y};
         const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
         unsigned long long run = 0;
@@ -1003,7 +1033,11 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (r == EX_OK) {
                     if (ex.hel != 0.0) {
                         const int32_t v = accept(d, ex.hel, ex.pgen, accept_uniform(d, w.x), C, status);
-                        if (v != 0) {
+                        if (v != 0 && ex.det == d.d0) {
+                            ++spawned;
+                            __hip_atomic_fetch_add(&a.d0acc[s], (long long)v, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        } else if (v != 0) {
                             ++spawned;
                             const int q = atomicAdd(&Q.nspw, 1);
                             if (q < SPW_QUEUE) {
@@ -1034,18 +1068,21 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
 }
 
 // ---------------------------------------------------------------------------
-// K4a: the bucket of each record's child, and the records per bucket.
+// K4a: bucket and rank of the records the spawning loop left unranked (those
+// written while its queue was full; usually none).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_hist(EngineArgs a, const SysDesc *__restrict__ desc) {
+__global__ __launch_bounds__(256) void k_fix(EngineArgs a, const SysDesc *__restrict__ desc) {
     const unsigned long long cnt = *a.rec_count;
     const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t gf = a.rec_gf[i];
-        const SysDesc &d = desc[gf & 0x7FFFFFFFu];
-        const uint32_t gb = (uint32_t)d.gchunk0 + bucket_of(a.rec_det[i], (uint64_t)d.nchunks);
+        if (!(gf & REC_UNRANKED)) continue;
+        const SysDesc &d = desc[gf & 0x3FFFFFFFu];
+        const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(a.rec_det[i], (uint64_t)d.nbuckets);
+        a.rec_rank[i] = __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
         a.rec_gf[i] = gb | (gf & 0x80000000u);
-        __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1053,28 +1090,74 @@ __global__ __launch_bounds__(256) void k_hist(EngineArgs a, const SysDesc *__res
 // K4b: exclusive scan of the records per bucket (one workgroup; each thread
 // takes a contiguous range of buckets).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_bscan(EngineArgs a) {
+// Bucket b's range of the record scan: SCAN_G ranges of ceil(buckets / SCAN_G).
+__device__ __forceinline__ void bscan_range(int64_t nch, int g, int64_t &lo, int64_t &hi) {
+    const int64_t per = (nch + SCAN_G - 1) / SCAN_G;
+    lo = (int64_t)g * per;
+    hi = lo + per < nch ? lo + per : nch;
+    if (lo > nch) lo = nch;
+}
+
+// Records per range of buckets (coalesced: the workgroup reads its range in
+// consecutive blocks of 256).
+__global__ __launch_bounds__(256) void k_bscan_up(EngineArgs a) {
+    __shared__ unsigned long long ws[4];
+    int64_t lo, hi;
+    bscan_range(*a.nchunks * BPC, blockIdx.x, lo, hi);
+    unsigned long long v = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) v += a.bhist[i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) a.boff_rg[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Exclusive scan of the SCAN_G range totals (one workgroup, two per thread).
+__global__ __launch_bounds__(1024) void k_bscan_top(EngineArgs a) {
     __shared__ unsigned long long part[1024];
-    const int64_t nch = *a.nchunks;
-    const int64_t per = (nch + 1023) / 1024;
     const int t = threadIdx.x;
-    const int64_t lo = (int64_t)t * per;
-    const int64_t hi = lo + per < nch ? lo + per : nch;
-    unsigned long long sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += a.bhist[i];
-    part[t] = sum;
+    const unsigned long long s0 = a.boff_rg[2 * t], s1 = a.boff_rg[2 * t + 1];
+    part[t] = s0 + s1;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        const unsigned long long v = t >= off ? part[t - off] : 0ull;
+        const unsigned long long x = t >= off ? part[t - off] : 0ull;
         __syncthreads();
-        part[t] += v;
+        part[t] += x;
         __syncthreads();
     }
-    unsigned long long run = part[t] - sum;
-    for (int64_t i = lo; i < hi; ++i) {
-        a.boff[i] = (uint32_t)run;
-        run += a.bhist[i];
+    const unsigned long long run = part[t] - (s0 + s1);
+    a.boff_rg[SCAN_G + 2 * t] = run;
+    a.boff_rg[SCAN_G + 2 * t + 1] = run + s0;
+}
+
+// First sorted record of each bucket: the range's offset plus a scan inside the range.
+__global__ __launch_bounds__(256) void k_bscan_down(EngineArgs a) {
+    __shared__ unsigned long long ws[4];
+    int64_t lo, hi;
+    bscan_range(*a.nchunks * BPC, blockIdx.x, lo, hi);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    unsigned long long base = a.boff_rg[SCAN_G + blockIdx.x];
+    for (int64_t c = lo; c < hi; c += 256) {
+        const int64_t i = c + t;
+        const unsigned long long v = i < hi ? a.bhist[i] : 0ull;
+        unsigned long long x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) ws[w] = x;
+        __syncthreads();
+        unsigned long long pre = 0;
+        for (int k = 0; k < w; ++k) pre += ws[k];
+        if (i < hi) {
+            a.boff[i] = (uint32_t)(base + pre + x - v);
+            a.bhist[i] = 0u;   // counted afresh next iteration
+        }
+        base += ws[0] + ws[1] + ws[2] + ws[3];
+        __syncthreads();
     }
+    // the end of the last bucket's records
+    if (threadIdx.x == 0 && hi == *a.nchunks * BPC && lo < hi) a.boff[hi] = (uint32_t)base;
 }
 
 // ---------------------------------------------------------------------------
@@ -1088,9 +1171,7 @@ __global__ __launch_bounds__(256) void k_scatter(EngineArgs a) {
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t gf = a.rec_gf[i];
         const uint32_t gb = gf & 0x7FFFFFFFu;
-        const uint32_t pos =
-            a.boff[gb] + __hip_atomic_fetch_add(&a.bcur[gb], 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t pos = a.boff[gb] + a.rec_rank[i];
         a.srt_det[pos] = a.rec_det[i];
         a.srt_w[pos] = a.rec_w[i];
         a.srt_f[pos] = gf >> 31;
@@ -1098,68 +1179,92 @@ __global__ __launch_bounds__(256) void k_scatter(EngineArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K4d: per bucket, one workgroup: merge of the arrived records, death,
-// annihilation with the initiator test, new determinants, re-packing;
-// estimator partials and the next iteration's sums of |C|.
+// K4d: annihilation. A workgroup takes a contiguous range of chunks and, in each,
+// every wavefront one bucket, with no workgroup barrier inside a bucket:
+//   - the bucket's records are merged per child in the wavefront's LDS hash
+//     (the sort and compress of Sec. 4.1, by hashing);
+//   - every entry dies first (Eq. pdeath); then the walkers that arrived for it
+//     are added if it is still occupied, and otherwise survive only if an
+//     initiator sent some of them (Sec. 4.2);
+//   - children outside the bucket with an initiator parent become new entries
+//     (emptied positions first); the other children are discarded;
+//   - the bucket is re-packed; the estimator partials and the next iteration's
+//     sum of |C| are written.
+// A bucket with more than NREC records (rare at the planned sizes) merges them in
+// rounds of at most NREC distinct children, staging its new determinants in the
+// unsorted record buffer, which k_scatter has consumed by then.
 // ---------------------------------------------------------------------------
-constexpr int NCAND = 256;              // new-determinant candidates per round in LDS
-constexpr int NLDS = CHUNK + NCAND;     // LDS entries: the bucket's entries, then candidates
-constexpr int LHASH = 2048;             // LDS hash slots over those entries (load <= 0.63)
-constexpr int POST_QUEUE = 768;         // new determinants whose H_DD is still to be computed
-constexpr int POST_GRAB = 4;            // buckets per dynamic grab in k_post
-constexpr uint32_t F_INIT = 1u;         // record flags: from an initiator parent,
-constexpr uint32_t F_MAYBE = 2u;        // found no room in the candidate area this round,
-constexpr uint32_t F_DEFER = 4u;        // left for a later round
+constexpr int NREC = 64;                // distinct children per round in a wavefront's hash
+constexpr int WHASH = 128;              // hash slots per wavefront (load <= 0.5)
+constexpr int POST_QUEUE = 1024;        // new determinants whose H_DD is still to be computed
+constexpr int POST_MAX_SYS = 256;       // systems whose status k_post snapshots in LDS
+constexpr uint32_t F_INIT = 1u;         // from an initiator parent (records and hash slots)
+constexpr uint32_t F_MATCHED = 2u;      // hash slot: the child is an entry of the bucket
+constexpr uint32_t F_MAYBE = 2u;        // record: found the hash full in this round,
+constexpr uint32_t F_DEFER = 4u;        // record: left for a later round
 
-__device__ __forceinline__ uint32_t lds_home(uint64_t D) {
-    return (uint32_t)mix64(D) & (uint32_t)(LHASH - 1);
+// Orders the LDS accesses of a wavefront's lanes around it (LDS operations of one
+// wavefront complete in issue order, so no wait is needed, only no code motion).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
-// Entry index of D in the LDS hash (-1: absent). Call when no thread inserts.
-__device__ __forceinline__ int lds_find(uint64_t D, const uint64_t *s_det, const uint32_t *s_hash) {
-    uint32_t h = lds_home(D);
+__device__ __forceinline__ uint32_t wh_home(uint64_t D) {
+    return (uint32_t)mix64(D) & (uint32_t)(WHASH - 1);
+}
+
+// Slot of D in a wavefront's hash (-1: absent). Call when no lane inserts.
+__device__ __forceinline__ int wh_find(uint64_t D, const uint64_t *hk) {
+    uint32_t h = wh_home(D);
+    for (int k = 0; k < WHASH; ++k) {
+        const uint64_t x = hk[h];
+        if (x == D) return (int)h;
+        if (x == 0ull) return -1;
+        h = (h + 1u) & (uint32_t)(WHASH - 1);
+    }
+    return -1;
+}
+
+// Slot of D, claimed when absent. Lanes that race for an empty slot with the same D
+// agree on it; with different D the losers probe on. For at most WHASH - 1
+// distinct children (no limit needed).
+__device__ __forceinline__ int wh_claim(uint64_t D, uint64_t *hk) {
+    uint32_t h = wh_home(D);
     for (;;) {
-        const uint32_t x = s_hash[h];
-        if (x == 0u) return -1;
-        if (s_det[x - 1u] == D) return (int)x - 1;
-        h = (h + 1u) & (uint32_t)(LHASH - 1);
+        const uint64_t x = hk[h];
+        if (x == D) return (int)h;
+        if (x == 0ull) {
+            const unsigned long long old =
+                atomicCAS((unsigned long long *)&hk[h], 0ull, (unsigned long long)D);
+            if (old == 0ull || old == D) return (int)h;
+        }
+        h = (h + 1u) & (uint32_t)(WHASH - 1);
     }
 }
 
-// Entry index of D, claiming a candidate entry for it when absent (concurrent
-// callers with the same D agree on one entry: the entry's key is published
-// before the hash slot that points to it). -1 when D is absent and the
-// candidate area is full; D may then have been inserted meanwhile by another
-// thread, which a lookup after a barrier settles.
-__device__ __forceinline__ int lds_find_or_claim(uint64_t D, uint64_t *s_det, uint32_t *s_hash,
-                                                 int *s_ncand) {
-    uint32_t h = lds_home(D);
-    int mine = -1;
-    for (;;) {
-        uint32_t x = __hip_atomic_load(&s_hash[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (x == 0u) {
-            if (mine < 0) {
-                const int k = atomicAdd(s_ncand, 1);
-                if (k >= NCAND) return -1;
-                mine = CHUNK + k;
-                __hip_atomic_store(&s_det[mine], D, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// As wh_claim, with at most NREC claims per round: *ncl counts claims made and
+// claims in flight. -1 when D is absent and no claim is left (D may have been
+// entered meanwhile by another lane, which a lookup afterwards settles).
+__device__ __forceinline__ int wh_claim_limited(uint64_t D, uint64_t *hk, int *ncl) {
+    uint32_t h = wh_home(D);
+    for (int k = 0; k < WHASH; ++k) {
+        const uint64_t x = hk[h];
+        if (x == D) return (int)h;
+        if (x == 0ull) {
+            if (atomicAdd(ncl, 1) >= NREC) {
+                atomicSub(ncl, 1);
+                return -1;
             }
-            uint32_t expect = 0u;
-            if (__hip_atomic_compare_exchange_strong(&s_hash[h], &expect, (uint32_t)mine + 1u,
-                                                     __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP))
-                return mine;
-            x = expect;
+            const unsigned long long old =
+                atomicCAS((unsigned long long *)&hk[h], 0ull, (unsigned long long)D);
+            if (old == 0ull) return (int)h;
+            atomicSub(ncl, 1);   // the slot went to another lane's claim
+            if (old == D) return (int)h;
         }
-        const uint64_t k = __hip_atomic_load(&s_det[x - 1u], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == D) {
-            if (mine >= 0)   // the entry this thread claimed is not needed: mark it unused
-                __hip_atomic_store(&s_det[mine], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            return (int)x - 1;
-        }
-        h = (h + 1u) & (uint32_t)(LHASH - 1);
+        h = (h + 1u) & (uint32_t)(WHASH - 1);
     }
+    return -1;
 }
 
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
@@ -1208,340 +1313,389 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
     }
 }
 
-// Exclusive prefix of per-thread counts over the workgroup (threads in order);
-// *total gets the sum. Uses s_w[POST_WAVES]; call uniformly.
-__device__ __forceinline__ int block_excl_scan(int v, int *s_w, int *total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    __syncthreads();
-    if (lane == 63) s_w[wid] = x;
-    __syncthreads();
-    int pre = x - v, tot = 0;
-    for (int w = 0; w < POST_WAVES; ++w) {
-        if (w < wid) pre += s_w[w];
-        tot += s_w[w];
-    }
-    *total = tot;
-    return pre;
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
+// Exclusive prefix over the wavefront's lanes of a per-lane count v < 8, and its
+// total, from ballots of its bits.
+__device__ __forceinline__ int wave_prefix8(int v, int lane) {
+    const uint64_t lt = lanes_below(lane);
+    return __popcll(__ballot(v & 1) & lt) + 2 * __popcll(__ballot(v & 2) & lt) +
+           4 * __popcll(__ballot(v & 4) & lt);
+}
+__device__ __forceinline__ int wave_total8(int v) {
+    return __popcll(__ballot(v & 1)) + 2 * __popcll(__ballot(v & 2)) + 4 * __popcll(__ballot(v & 4));
 }
 
-__global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
-    __shared__ double s_jk[64 * 63 / 2];   // upper triangle of the pair table
-    __shared__ double s_hpp[64];
-    __shared__ uint64_t s_det[NLDS];
-    __shared__ long long s_acc[NLDS];      // walkers arrived per entry
-    __shared__ uint32_t s_flg[NLDS / 32];  // initiator flag per entry (OR over its records)
-    __shared__ uint32_t s_hash[LHASH];     // entry index + 1, 0 = empty
-    __shared__ uint16_t s_free[CHUNK];     // positions emptied this iteration, ascending
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
+    // Each wavefront's working set, and (between chunks only) the pair table from
+    // which the diagonal elements of new determinants are computed.
+    struct WaveLds {
+        uint64_t key[WHASH];       // child (0: empty)
+        long long acc[WHASH];      // walkers arrived for it
+        uint32_t flg[WHASH];       // F_INIT | F_MATCHED
+        uint16_t free_[BQ];        // positions emptied this iteration, ascending
+    };
+    union PostLds {
+        WaveLds w[POST_WAVES];
+        struct {
+            double jk[64 * 63 / 2];
+            double hpp[64];
+        } tab;
+    };
+    __shared__ PostLds L;
     __shared__ uint32_t s_queue[POST_QUEUE];
-    __shared__ int s_ncand, s_nhole, s_nlive, s_kplaced, s_maybe, s_defer, s_qn, s_live;
-    __shared__ int s_w[POST_WAVES];
-    __shared__ unsigned int s_next;
+    __shared__ uint32_t s_stat[POST_MAX_SYS];   // the systems' status at the kernel's start
+    __shared__ int s_qn, s_qsys;
+    __shared__ int s_ncl[POST_WAVES];
     __shared__ unsigned long long s_nwn[POST_WAVES];
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    // k_scatter has consumed this iteration's records
-    if (blockIdx.x == 0 && t == 0) *a.rec_count = 0ull;
+    WaveLds &W = L.w[wid];
+    if (blockIdx.x == 0 && t == 0) *a.rec_count = 0ull;   // k_scatter has consumed the records
     unsigned long long *const nws_next = sums(a, cur_half(a) ^ 1u);
     unsigned long long *const rg_next = ranges(a, cur_half(a) ^ 1u);
     const int64_t per_range = (nch + SCAN_G - 1) / SCAN_G;
     const int tsh = __builtin_ctzll((unsigned long long)a.tile);
     const unsigned long long tm = (unsigned long long)a.tile - 1ull;
-    int loaded = -1;
-    if (t == 0) s_qn = 0;
+    // Which systems take part is decided once, from the status at the start: bits set
+    // while this kernel runs (population overflow) are fatal to their system anyway,
+    // and a decision shared by the workgroup keeps its barriers uniform.
+    for (int i = t; i < a.max_sys && i < POST_MAX_SYS; i += 256) s_stat[i] = a.status[i];
+    if (t == 0) {
+        s_qn = 0;
+        s_qsys = -1;
+    }
     __syncthreads();
-    int64_t c = 0, c_end = 0;
-    for (;; ++c) {
-        if (c >= c_end) {
-            if (t == 0) s_next = atomicAdd(&a.work[1], (unsigned int)POST_GRAB);
-            __syncthreads();
-            c = s_next;
-            c_end = c + POST_GRAB;
+    auto flush = [&]() {   // (uniform) H_DD of the queued new determinants
+        const SysDesc &dq = desc[s_qsys];
+        for (int i = t; i < dq.n_so * 64; i += 256) {
+            const int p = i >> 6, q = i & 63;
+            if (q > p && q < dq.n_so) L.tab.jk[pair_row(p, dq.n_so) + q] = gptr(dq.jk)[i];
+        }
+        for (int i = t; i < dq.n_so; i += 256) L.tab.hpp[i] = h_so(dq, i, i);
+        __syncthreads();
+        flush_new_dets(dq, s_queue, s_qn < POST_QUEUE ? s_qn : POST_QUEUE, L.tab.hpp, L.tab.jk);
+        __syncthreads();
+    };
+    const int64_t per = (nch + gridDim.x - 1) / gridDim.x;
+    const int64_t c_lo = (int64_t)blockIdx.x * per;
+    const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
+    for (int64_t c = c_lo; c < c_hi; ++c) {
+        const int s = ld_uniform(a.chunk_sys + c);
+        const bool live = s >= 0 && (s >= POST_MAX_SYS ? participating(desc[s], 1u)
+                                                       : participating(desc[s], s_stat[s]));
+        if (live && s_qsys >= 0 && (s_qsys != s || s_qn > POST_QUEUE / 2)) {
+            // the queued determinants are another system's, or the queue is filling up
+            flush();
+            if (t == 0) {
+                s_qn = 0;
+                s_qsys = -1;
+            }
             __syncthreads();
         }
-        if (c >= nch) break;
-        const int s = a.chunk_sys[c];
         int64_t nw = 0, aborted = 0;
         uint64_t cnt = 0;                 // entries | merged targets << 21 | occupied << 42
         double num = 0.0;
         unsigned long long nwb = 0;       // sum |C| over the bucket's entries after the iteration
-        // decided once for the workgroup (other workgroups may set status bits meanwhile)
-        if (t == 0) s_live = (s >= 0 && participating(desc[s], *(volatile uint32_t *)&a.status[s])) ? 1 : 0;
-        __syncthreads();
-        const bool live = s_live != 0;
-        const uint32_t nr = a.bhist[c], r0 = a.boff[c];
         if (live) {
             const SysDesc &d = desc[s];
             uint32_t *status = &a.status[s];
-            if (loaded != s || s_qn + NCAND > POST_QUEUE) {
-                // another system, or the H_DD queue could overflow in this bucket (both
-                // uniform): compute the queued elements now
-                const int nq = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
-                if (loaded >= 0 && nq > 0) flush_new_dets(desc[loaded], s_queue, nq, s_hpp, s_jk);
-                __syncthreads();
-                if (loaded != s) {
-                    for (int i = t; i < d.n_so * 64; i += 256) {
-                        const int p = i >> 6, q = i & 63;
-                        if (q > p && q < d.n_so) s_jk[pair_row(p, d.n_so) + q] = gptr(d.jk)[i];
-                    }
-                    for (int i = t; i < d.n_so; i += 256) s_hpp[i] = h_so(d, i, i);
-                    loaded = s;
-                }
-                if (t == 0) s_qn = 0;
-                __syncthreads();
-            }
-            const int b = a.chunk_local[c];
-            const int64_t base = (int64_t)b * CHUNK;
-            const int n = d.bcnt[b];
-            // the bucket's entries, four consecutive per thread, all loads issued first
+            if (t == 0) s_qsys = s;
+            const int64_t lb = (int64_t)ld_uniform(a.chunk_local + c) * BPC + wid;
+            const int64_t gb = c * BPC + wid;
+            const int64_t base = lb * BQ;
+            const int n = ld_uniform(d.bcnt + lb);
+            const uint32_t r0 = ld_uniform(a.boff + gb);
+            const uint32_t nr = ld_uniform(a.boff + gb + 1) - r0;
+            const int e0 = 4 * lane;
             uint64_t kin[4] = {0ull, 0ull, 0ull, 0ull};
             int32_t pin[4] = {0, 0, 0, 0};
             double hin[4] = {0.0, 0.0, 0.0, 0.0};
-            if (4 * t < n) {
-                const ulonglong2 k01 = gload_u2(d.key + base + 4 * t);
-                const ulonglong2 k23 = gload_u2(d.key + base + 4 * t + 2);
-                const int4 pv = gload_i4(d.pop + base + 4 * t);
-                const double2 h01 = gload_d2(d.hdiag + base + 4 * t);
-                const double2 h23 = gload_d2(d.hdiag + base + 4 * t + 2);
+            if (e0 < n) {
+                const ulonglong2 k01 = gload_u2(d.key + base + e0);
+                const ulonglong2 k23 = gload_u2(d.key + base + e0 + 2);
+                const int4 pv = gload_i4(d.pop + base + e0);
+                const double2 h01 = gload_d2(d.hdiag + base + e0);
+                const double2 h23 = gload_d2(d.hdiag + base + e0 + 2);
                 kin[0] = k01.x; kin[1] = k01.y; kin[2] = k23.x; kin[3] = k23.y;
                 pin[0] = pv.x; pin[1] = pv.y; pin[2] = pv.z; pin[3] = pv.w;
                 hin[0] = h01.x; hin[1] = h01.y; hin[2] = h23.x; hin[3] = h23.y;
             }
-            for (int i = t; i < LHASH; i += 256) s_hash[i] = 0u;
-            for (int i = t; i < NLDS; i += 256) s_acc[i] = 0ll;
-            if (t < NLDS / 32) s_flg[t] = 0u;
-            if (t == 0) {
-                s_ncand = 0;
-                s_maybe = 0;
-                s_defer = 0;
-                s_kplaced = 0;
+            uint64_t rd = 0ull;   // this lane's record (fast path)
+            int32_t rw = 0;
+            uint32_t rf = 0u;
+            if ((uint32_t)lane < nr && nr <= (uint32_t)NREC) {
+                rd = a.srt_det[r0 + lane];
+                rw = a.srt_w[r0 + lane];
+                rf = a.srt_f[r0 + lane];
             }
-            __syncthreads();
+            W.key[lane] = 0ull;
+            W.key[lane + 64] = 0ull;
+            W.acc[lane] = 0ll;
+            W.acc[lane + 64] = 0ll;
+            W.flg[lane] = 0u;
+            W.flg[lane + 64] = 0u;
+            // death of every entry (Eq. pdeath, one stochastic rounding for the whole
+            // determinant); it depends on nothing that arrives
+            int32_t pdv[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int e = 4 * t + u;
-                if (e >= n) continue;
-                s_det[e] = kin[u];
-                uint32_t h = lds_home(kin[u]);
-                for (;;) {   // the bucket's keys are distinct: claim the first free slot
-                    uint32_t expect = 0u;
-                    if (__hip_atomic_compare_exchange_strong(&s_hash[h], &expect, (uint32_t)e + 1u,
-                                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_WORKGROUP))
-                        break;
-                    h = (h + 1u) & (uint32_t)(LHASH - 1);
+                const int32_t p = pin[u];
+                if (e0 + u >= n || p == 0) continue;
+                uint64_t xd, xu;
+                draw2(d.seed, kin[u], 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
+                const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
+                const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
+                const double ad = fabs(dv);
+                const double fl = floor(ad);
+                int64_t pd = p;
+                if (fl > 1073741824.0) {
+                    atomicOr(status, ST_POP_OVERFLOW);
+                } else {
+                    const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
+                    pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
+                    if (pd > 2147483647ll || pd < -2147483647ll) {
+                        atomicOr(status, ST_POP_OVERFLOW);
+                        pd = 0;
+                    }
                 }
+                pdv[u] = (int32_t)pd;
             }
-            __syncthreads();
-            int32_t npv[4] = {0, 0, 0, 0};
-            bool keep[4] = {false, false, false, false};
-            for (int round = 0;; ++round) {
-                // Arrivals: each record's walkers added to its child's entry, initiator
-                // flags OR-ed (the sort and compress of Sec. 4.1, by hashing).
-                for (uint32_t j = t; j < nr; j += 256) {
-                    const uint32_t f = a.srt_f[r0 + j];
-                    if (round > 0 && !(f & F_DEFER)) continue;
-                    const uint64_t D = a.srt_det[r0 + j];
-                    const int e = lds_find_or_claim(D, s_det, s_hash, &s_ncand);
-                    if (e < 0) {
-                        a.srt_f[r0 + j] = (f & F_INIT) | F_MAYBE;
-                        s_maybe = 1;
-                        continue;
-                    }
-                    if (f & F_DEFER) a.srt_f[r0 + j] = f & F_INIT;
-                    atomicAdd((unsigned long long *)&s_acc[e],
-                              (unsigned long long)(long long)a.srt_w[r0 + j]);
-                    if (f & F_INIT) atomicOr(&s_flg[e >> 5], 1u << (e & 31));
+            wave_sync();
+            long long spv[4] = {0ll, 0ll, 0ll, 0ll};   // walkers arrived per entry
+            uint32_t flv = 0u;                         // bit u: an initiator sent some
+            int kc = 0;                                // slow path: staged children (uniform)
+            if (nr <= (uint32_t)NREC) {
+                // Fast path: at most NREC records, so at most NREC distinct children.
+                if ((uint32_t)lane < nr) {
+                    const int h = wh_claim(rd, W.key);
+                    atomicAdd((unsigned long long *)&W.acc[h], (unsigned long long)(long long)rw);
+                    if (rf & F_INIT) atomicOr(&W.flg[h], F_INIT);
                 }
-                __syncthreads();
-                if (s_maybe) {
-                    // records that found the candidate area full: merged after all if their
-                    // child was entered meanwhile, otherwise left for the next round
-                    for (uint32_t j = t; j < nr; j += 256) {
-                        const uint32_t f = a.srt_f[r0 + j];
-                        if (!(f & F_MAYBE)) continue;
-                        const uint64_t D = a.srt_det[r0 + j];
-                        const int e = lds_find(D, s_det, s_hash);
-                        if (e < 0) {
-                            a.srt_f[r0 + j] = (f & F_INIT) | F_DEFER;
-                            s_defer = 1;
-                            continue;
-                        }
-                        a.srt_f[r0 + j] = f & F_INIT;
-                        atomicAdd((unsigned long long *)&s_acc[e],
-                                  (unsigned long long)(long long)a.srt_w[r0 + j]);
-                        if (f & F_INIT) atomicOr(&s_flg[e >> 5], 1u << (e & 31));
-                    }
-                    __syncthreads();
-                }
-                if (round == 0) {
-                    // The bucket's own entries: death (Eq. pdeath, one stochastic rounding
-                    // for the whole determinant), then annihilation (Sec. 4.2): occupied
-                    // after death -> add the arrived walkers; otherwise they survive only
-                    // if an initiator sent some of them.
-                    int nhole = 0, nlive = 0;
+                wave_sync();
+                if (nr > 0) {
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const int e = 4 * t + u;
-                        if (e >= n) continue;
-                        const uint64_t D = kin[u];
-                        const int32_t p = pin[u];
-                        int64_t pd = p;
-                        if (p != 0) {
-                            uint64_t xd, xu;
-                            draw2(d.seed, D, 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
-                            const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
-                            const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
-                            const double ad = fabs(dv);
-                            const double fl = floor(ad);
-                            if (fl > 1073741824.0) {
-                                atomicOr(status, ST_POP_OVERFLOW);
-                                keep[u] = true;
-                                npv[u] = p;
-                                ++nlive;
+                        if (e0 + u >= n) continue;
+                        const int h = wh_find(kin[u], W.key);
+                        if (h < 0) continue;
+                        spv[u] = W.acc[h];
+                        flv |= (W.flg[h] & F_INIT) << u;
+                        W.flg[h] |= F_MATCHED;   // a child matches at most one entry
+                    }
+                }
+                wave_sync();
+            } else {
+                // Slow path: rounds of at most NREC distinct children. A child whose
+                // records found the hash full is left whole for a later round; the
+                // children outside the bucket are staged, merged, in the bucket's range
+                // of the unsorted record buffer.
+                for (int round = 0;; ++round) {
+                    if (round > 0) {
+                        W.key[lane] = 0ull;
+                        W.key[lane + 64] = 0ull;
+                        W.acc[lane] = 0ll;
+                        W.acc[lane + 64] = 0ll;
+                        W.flg[lane] = 0u;
+                        W.flg[lane + 64] = 0u;
+                    }
+                    if (lane == 0) s_ncl[wid] = 0;
+                    wave_sync();
+                    bool maybe = false;
+                    for (uint32_t j = lane; j < nr; j += 64) {   // (a record stays with its lane)
+                        const uint32_t f = a.srt_f[r0 + j];
+                        if (round > 0 && !(f & F_DEFER)) continue;
+                        const uint64_t D = a.srt_det[r0 + j];
+                        const int h = wh_claim_limited(D, W.key, &s_ncl[wid]);
+                        if (h < 0) {
+                            a.srt_f[r0 + j] = (f & F_INIT) | F_MAYBE;
+                            maybe = true;
+                            continue;
+                        }
+                        if (f & F_DEFER) a.srt_f[r0 + j] = f & F_INIT;
+                        atomicAdd((unsigned long long *)&W.acc[h],
+                                  (unsigned long long)(long long)a.srt_w[r0 + j]);
+                        if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
+                    }
+                    wave_sync();
+                    bool defer = false;
+                    if (__ballot(maybe)) {
+                        for (uint32_t j = lane; j < nr; j += 64) {
+                            const uint32_t f = a.srt_f[r0 + j];
+                            if (!(f & F_MAYBE)) continue;
+                            const int h = wh_find(a.srt_det[r0 + j], W.key);
+                            if (h < 0) {
+                                a.srt_f[r0 + j] = (f & F_INIT) | F_DEFER;
+                                defer = true;
                                 continue;
                             }
-                            const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
-                            pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
+                            a.srt_f[r0 + j] = f & F_INIT;
+                            atomicAdd((unsigned long long *)&W.acc[h],
+                                      (unsigned long long)(long long)a.srt_w[r0 + j]);
+                            if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
                         }
-                        const bool present = pd != 0 || D == d.d0;
-                        const long long sp = s_acc[e];
-                        const bool fl = (s_flg[e >> 5] >> (e & 31)) & 1u;
-                        int64_t np;
-                        if (present) {
-                            np = pd + sp;
-                        } else if (sp != 0 && fl) {
-                            np = sp;
-                        } else {
-                            np = 0;
-                            if (sp != 0) aborted += sp < 0 ? -sp : sp;
-                        }
-                        if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
-                        if (np > 2147483647ll || np < -2147483647ll) {
-                            atomicOr(status, ST_POP_OVERFLOW);
-                            np = 0;
-                        }
-                        npv[u] = (int32_t)np;
-                        keep[u] = np != 0 || D == d.d0;   // the reference keeps its entry at 0
-                        if (D == d.d0) a.c0[s] = np;
-                        if (np != 0) {
-                            const int64_t an = np < 0 ? -np : np;
-                            nw += an;
-                            nwb += (unsigned long long)an;
-                            cnt += 1ull << CNT_SHIFT_ND;
-                            if (D != d.d0 && __popcll(D ^ d.d0) <= 4)
-                                num = num + hel_to_ref(d, D) * (double)np;
-                        }
-                        nhole += keep[u] ? 0 : 1;
-                        nlive += keep[u] ? 1 : 0;
+                        wave_sync();
                     }
-                    // positions emptied this iteration, in ascending order
-                    int tot;
-                    int pre = block_excl_scan(nhole, s_w, &tot);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (4 * t + u < n && !keep[u]) s_free[pre++] = (uint16_t)(4 * t + u);
-                    int tl;
-                    (void)block_excl_scan(nlive, s_w, &tl);
-                    if (t == 0) {
-                        s_nhole = tot;
-                        s_nlive = tl;
+                    for (int u = 0; u < 4; ++u) {
+                        if (e0 + u >= n) continue;
+                        const int h = wh_find(kin[u], W.key);
+                        if (h < 0) continue;
+                        spv[u] += W.acc[h];
+                        flv |= (W.flg[h] & F_INIT) << u;
+                        W.flg[h] |= F_MATCHED;
                     }
-                    __syncthreads();
+                    wave_sync();
+                    // stage this round's children outside the bucket (one per slot)
+                    for (int h = lane; h < WHASH; h += 64) {
+                        const uint64_t D = W.key[h];
+                        const bool cand = D != 0ull && !(W.flg[h] & F_MATCHED);
+                        const uint64_t m = __ballot(cand);
+                        if (cand) {
+                            const uint32_t j = r0 + (uint32_t)kc + (uint32_t)__popcll(m & lanes_below(lane));
+                            long long sp = W.acc[h];
+                            if (sp > 2147483647ll || sp < -2147483647ll) {
+                                atomicOr(status, ST_POP_OVERFLOW);
+                                sp = 0;
+                            }
+                            a.rec_det[j] = D;
+                            a.rec_w[j] = (int32_t)sp;
+                            a.rec_gf[j] = W.flg[h] & F_INIT;
+                        }
+                        kc += __popcll(m);
+                    }
+                    wave_sync();
+                    if (!__ballot(defer)) break;
                 }
-                // This round's candidates: children not in the bucket. With an initiator
-                // parent the merged walkers form a new determinant in the next free
-                // position (an emptied one first, then past the end); otherwise they are
-                // discarded (Sec. 4.2).
-                const int ncand = s_ncand < NCAND ? s_ncand : NCAND;
-                const int nh = s_nhole;
-                for (int i = t; i < ncand; i += 256) {
-                    const int e = CHUNK + i;
-                    const uint64_t D = s_det[e];
-                    if (D == 0ull) continue;   // claimed, then not needed
-                    const long long sp = s_acc[e];
-                    if (sp == 0) continue;     // cancelled out
-                    cnt += 1ull << CNT_SHIFT_MERGED;
-                    if (!((s_flg[e >> 5] >> (e & 31)) & 1u)) {
-                        aborted += sp < 0 ? -sp : sp;
-                        continue;
+                __threadfence();   // the staged children, read back below by other lanes
+            }
+            // Annihilation (Sec. 4.2) of the bucket's own entries.
+            const long long to_ref = ld_uniform(a.d0acc + s);   // walkers spawned onto the reference
+            int32_t npv[4] = {0, 0, 0, 0};
+            uint32_t keepm = 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (e0 + u >= n) continue;
+                const uint64_t D = kin[u];
+                const bool is_ref = D == d.d0;
+                const int64_t pd = pdv[u];
+                const long long sp = spv[u] + (is_ref ? to_ref : 0ll);
+                int64_t np;
+                if (pd != 0 || is_ref) {
+                    np = pd + sp;
+                } else if (sp != 0 && ((flv >> u) & 1u)) {
+                    np = sp;
+                } else {
+                    np = 0;
+                    if (sp != 0) aborted += sp < 0 ? -sp : sp;
+                }
+                if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
+                if (np > 2147483647ll || np < -2147483647ll) {
+                    atomicOr(status, ST_POP_OVERFLOW);
+                    np = 0;
+                }
+                npv[u] = (int32_t)np;
+                if (is_ref) {
+                    a.c0[s] = np;
+                    a.d0acc[s] = 0ll;   // consumed
+                }
+                if (np != 0) {
+                    const int64_t an = np < 0 ? -np : np;
+                    nw += an;
+                    nwb += (unsigned long long)an;
+                    cnt += 1ull << CNT_SHIFT_ND;
+                    if (!is_ref && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
+                }
+                if (np != 0 || is_ref) keepm |= 1u << u;   // the reference keeps its entry at 0
+            }
+            const int nin = e0 < n ? (n - e0 < 4 ? n - e0 : 4) : 0;
+            const int nkeep = __popc(keepm), nhole = nin - nkeep;
+            {   // positions emptied this iteration, ascending
+                int k = wave_prefix8(nhole, lane);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < nin && !((keepm >> u) & 1u)) W.free_[k++] = (uint16_t)(e0 + u);
+            }
+            const int H = wave_total8(nhole);
+            const int Lk = n - H;
+            wave_sync();
+            // New determinants: children outside the bucket with an initiator parent go
+            // to the emptied positions first, then past the end; the others are discarded.
+            int K = 0;
+            auto place = [&](uint64_t D, long long sp, bool init) {   // (all lanes; D = 0: none)
+                const bool real = D != 0ull && sp != 0;
+                if (real) cnt += 1ull << CNT_SHIFT_MERGED;
+                if (real && !init) aborted += sp < 0 ? -sp : sp;
+                const bool nd = real && init;
+                const uint64_t m = __ballot(nd);
+                const int k = K + __popcll(m & lanes_below(lane));
+                K += __popcll(m);
+                if (!nd) return;
+                const int64_t an = sp < 0 ? -sp : sp;
+                nw += an;
+                cnt += 1ull << CNT_SHIFT_ND;
+                if (__popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)sp;
+                const int pos = k < H ? (int)W.free_[k] : n + (k - H);
+                if (pos < BQ) {
+                    nwb += (unsigned long long)an;
+                    *gp(d.key + base + pos) = D;
+                    *gp(d.pop + base + pos) = (int32_t)sp;
+                    const int q = atomicAdd(&s_qn, 1);
+                    if (q < POST_QUEUE) {
+                        s_queue[q] = (uint32_t)(base + pos);
+                    } else {   // (only after buckets with many new determinants)
+                        *gp(d.hdiag + base + pos) = hdiag_of(d, D);
                     }
+                } else {
+                    // the bucket is full: completed in the spill list, re-bucketed by the host
+                    const unsigned long long j = atomicAdd(a.sp_count, 1ull);
+                    if (j < (unsigned long long)a.sp_cap) {
+                        a.sp_det[j] = D;
+                        a.sp_pop[j] = (int32_t)sp;
+                        a.sp_hd[j] = hdiag_of(d, D);
+                        a.sp_sys[j] = s;
+                        a.spilled[s] = 1u;
+                    } else {
+                        atomicOr(status, ST_SPILL_FULL);
+                    }
+                }
+            };
+            if (nr <= (uint32_t)NREC) {
+                for (int h = lane; h < WHASH; h += 64) {
+                    const uint64_t D = W.key[h];
+                    const uint32_t f = W.flg[h];
+                    const bool cand = D != 0ull && !(f & F_MATCHED);
+                    const long long sp = cand ? W.acc[h] : 0ll;
                     if (sp > 2147483647ll || sp < -2147483647ll) {
                         atomicOr(status, ST_POP_OVERFLOW);
-                        continue;
-                    }
-                    const int k = atomicAdd(&s_kplaced, 1);
-                    const int pos = k < nh ? (int)s_free[k] : n + (k - nh);
-                    const int64_t an = sp < 0 ? -sp : sp;
-                    nw += an;
-                    cnt += 1ull << CNT_SHIFT_ND;
-                    if (__popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)sp;
-                    if (pos < CHUNK) {
-                        nwb += (unsigned long long)an;
-                        *gp(d.key + base + pos) = D;
-                        *gp(d.pop + base + pos) = (int32_t)sp;
-                        const int q = atomicAdd(&s_qn, 1);
-                        if (q < POST_QUEUE) {
-                            s_queue[q] = (uint32_t)(base + pos);
-                        } else {   // (only after several rounds in one bucket)
-                            double h0, h1;
-                            hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, d.n_so, h0, h1);
-                            *gp(d.hdiag + base + pos) = h0;
-                        }
+                        place(0ull, 0ll, false);
                     } else {
-                        // the bucket is full: completed in the spill list, re-bucketed by the host
-                        double h0, h1;
-                        hdiag_lds2(d.e_core, D, D, s_hpp, s_jk, d.n_so, h0, h1);
-                        const unsigned long long j = atomicAdd(a.sp_count, 1ull);
-                        if (j < (unsigned long long)a.sp_cap) {
-                            a.sp_det[j] = D;
-                            a.sp_pop[j] = (int32_t)sp;
-                            a.sp_hd[j] = h0;
-                            a.sp_sys[j] = s;
-                            a.spilled[s] = 1u;
-                        } else {
-                            atomicOr(status, ST_SPILL_FULL);
-                        }
+                        place(cand ? D : 0ull, sp, (f & F_INIT) != 0u);
                     }
                 }
-                __syncthreads();
-                if (!s_defer) break;
-                // Another round for the records left over: none of their children is an
-                // entry of the bucket or a candidate of an earlier round.
-                for (int i = t; i < LHASH; i += 256) s_hash[i] = 0u;
-                for (int i = CHUNK + t; i < NLDS; i += 256) s_acc[i] = 0ll;
-                if (t < NCAND / 32) s_flg[CHUNK / 32 + t] = 0u;
-                __syncthreads();
-                if (t == 0) {
-                    s_ncand = 0;
-                    s_maybe = 0;
-                    s_defer = 0;
+            } else {
+                for (int i0 = 0; i0 < kc; i0 += 64) {
+                    const int i = i0 + lane;
+                    const bool in = i < kc;
+                    place(in ? a.rec_det[r0 + i] : 0ull, in ? (long long)a.rec_w[r0 + i] : 0ll,
+                          in && (a.rec_gf[r0 + i] & F_INIT));
                 }
-                __syncthreads();
             }
-            // Re-pack: the bucket keeps n' = (kept entries) + (new determinants) entries;
-            // when fewer new determinants than emptied positions arrived, the kept
-            // entries past n' move into the emptied positions that remain below n'.
-            const int K = s_kplaced, H = s_nhole, L = s_nlive;
-            const int np_ = L + K < CHUNK ? L + K : CHUNK;
-            bool moved[4] = {false, false, false, false};
+            // Re-pack: n' = (kept entries) + (new determinants); when fewer new
+            // determinants than emptied positions arrived, the kept entries past n' move
+            // into the emptied positions that remain below n'.
+            const int np_ = Lk + K < BQ ? Lk + K : BQ;
+            uint32_t movedm = 0u;
             if (K < H) {   // uniform
-                int nm = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (((keepm >> u) & 1u) && e0 + u >= np_) movedm |= 1u << u;
+                int r = K + wave_prefix8(__popc(movedm), lane);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    moved[u] = 4 * t + u < n && keep[u] && 4 * t + u >= np_;
-                    nm += moved[u] ? 1 : 0;
-                }
-                int tot;
-                int r = block_excl_scan(nm, s_w, &tot);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!moved[u]) continue;
-                    const int64_t dst = base + s_free[K + r++];
+                    if (!((movedm >> u) & 1u)) continue;
+                    const int64_t dst = base + W.free_[r++];
                     *gp(d.key + dst) = kin[u];
                     *gp(d.pop + dst) = npv[u];
                     *gp(d.hdiag + dst) = hin[u];
@@ -1549,14 +1703,14 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (keep[u] && !moved[u] && npv[u] != pin[u]) *gp(d.pop + base + 4 * t + u) = npv[u];
-            if (t == 0) {
-                d.bcnt[b] = np_;
+                if (((keepm & ~movedm) >> u) & 1u && npv[u] != pin[u])
+                    *gp(d.pop + base + e0 + u) = npv[u];
+            if (lane == 0) {
+                d.bcnt[lb] = np_;
                 cnt += (uint64_t)np_;
             }
         }
-        // fixed-order reduction per wavefront (lane butterfly); each wavefront writes its
-        // own share of the bucket
+        // fixed-order reduction per wavefront; each wavefront writes its bucket's share
         nw = wave_sum((long long)nw);
         aborted = wave_sum((long long)aborted);
         cnt = wave_sum((unsigned long long)cnt);
@@ -1577,16 +1731,10 @@ __global__ __launch_bounds__(256) void k_post(EngineArgs a, const SysDesc *__res
                 atomicAdd(&rg_next[c / per_range], x);
                 atomicAdd(&rg_next[SCAN_G + c / per_range], (x + tm) >> tsh);
             }
-            // the bucket's records are consumed: counts start at zero next iteration
-            a.bhist[c] = 0u;
-            a.bcur[c] = 0u;
         }
     }
     __syncthreads();
-    {
-        const int nq = s_qn < POST_QUEUE ? s_qn : POST_QUEUE;
-        if (loaded >= 0 && nq > 0) flush_new_dets(desc[loaded], s_queue, nq, s_hpp, s_jk);
-    }
+    if (s_qsys >= 0 && s_qn > 0) flush();   // uniform
 }
 
 // ---------------------------------------------------------------------------
@@ -1709,9 +1857,11 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool f
     hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[3], s);
-    hipLaunchKernelGGL(k_hist, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
+    hipLaunchKernelGGL(k_fix, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
-    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_bscan_up, dim3(SCAN_G), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bscan_top, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_bscan_down, dim3(SCAN_G), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)spawn_grid), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_post, dim3((unsigned)post_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
@@ -1726,10 +1876,10 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool f
 // ---------------------------------------------------------------------------
 // Append determinant D (population p, diagonal element hd) to its bucket.
 __device__ __forceinline__ bool bucket_put(const SysDesc &d, uint64_t D, int32_t p, double hd) {
-    const uint32_t b = bucket_of(D, (uint64_t)d.nchunks);
+    const uint32_t b = bucket_of(D, (uint64_t)d.nbuckets);
     const int pos = atomicAdd(&d.bcnt[b], 1);
-    if (pos >= CHUNK) return false;
-    const int64_t j = (int64_t)b * CHUNK + pos;
+    if (pos >= BQ) return false;
+    const int64_t j = (int64_t)b * BQ + pos;
     d.key[j] = D;
     d.pop[j] = p;
     d.hdiag[j] = hd;
@@ -1751,14 +1901,14 @@ __global__ void k_rebucket(SysDesc *desc, int32_t sys, const uint64_t *skey, con
                            const uint64_t *xdet, const int32_t *xpop, const double *xhd,
                            const int32_t *xsys, int64_t nx, uint32_t *err) {
     const SysDesc &d = desc[sys];
-    const int64_t ns = snb * CHUNK;
+    const int64_t ns = snb * BQ;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns + nx;
          i += (int64_t)gridDim.x * blockDim.x) {
         uint64_t D;
         int32_t p;
         double hd;
         if (i < ns) {
-            if ((int)(i % CHUNK) >= scnt[i / CHUNK]) continue;
+            if ((int)(i % BQ) >= scnt[i / BQ]) continue;
             D = skey[i];
             p = spop[i];
             hd = shd[i];
@@ -1781,14 +1931,14 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *kv, const int32
                                                  int32_t *opop, unsigned long long *count,
                                                  int64_t limit) {
     const int lane = threadIdx.x & 63;
-    const int64_t ns = nb * CHUNK;
+    const int64_t ns = nb * BQ;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ns;
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = base + threadIdx.x;
         bool take = false;
         uint64_t D = 0;
         int32_t p = 0;
-        if (i < ns && (int)(i % CHUNK) < cnt[i / CHUNK]) {
+        if (i < ns && (int)(i % BQ) < cnt[i / BQ]) {
             D = kv[i];
             p = pop[i];
             take = p != 0;
@@ -1823,7 +1973,7 @@ hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key
                            int64_t src_nb, const uint64_t *sp_det, const int32_t *sp_pop,
                            const double *sp_hd, const int32_t *sp_sys, int64_t n_sp,
                            uint32_t *d_err, hipStream_t s) {
-    const int64_t g = (src_nb * CHUNK + n_sp + 255) / 256;
+    const int64_t g = (src_nb * BQ + n_sp + 255) / 256;
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rebucket, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
                        d_desc, sys, src_key, src_pop, src_hd, src_cnt, src_nb, sp_det, sp_pop,
@@ -1834,9 +1984,9 @@ hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key
 hipError_t launch_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt, int64_t nb,
                           uint64_t *out_det, int32_t *out_pop, unsigned long long *count,
                           hipStream_t s) {
-    const int64_t g = (nb * CHUNK + 255) / 256;
+    const int64_t g = (nb * BQ + 255) / 256;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, key,
-                       pop, cnt, nb, out_det, out_pop, count, nb * CHUNK);
+                       pop, cnt, nb, out_det, out_pop, count, nb * BQ);
     return hipGetLastError();
 }
 
@@ -1897,7 +2047,7 @@ hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, const i
     char *p = (char *)stage;
     unsigned long long *count = (unsigned long long *)p;
     hipLaunchKernelGGL(k_stage_clear, dim3(1), dim3(64), 0, s, count);
-    const int64_t g = (nb * CHUNK + 255) / 256;
+    const int64_t g = (nb * BQ + 255) / 256;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, key,
                        pop, cnt, nb, (uint64_t *)(p + NOALLOC_KEYS_OFF),
                        (int32_t *)(p + NOALLOC_VALS_OFF), count, (int64_t)NOALLOC_MAX_DETS);
@@ -1930,7 +2080,7 @@ hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out
     return hipGetLastError();
 }
 
-int post_grid_size() { return spawn_grid_size() / 8 * 3; }   // three workgroups per CU (LDS)
+int post_grid_size() { return spawn_grid_size() / 8 * 4; }   // four workgroups per CU
 
 int spawn_grid_size() {
     int dev = 0, cus = 256;
