@@ -98,6 +98,14 @@ struct SysDesc {
     int64_t n_prev, n_var;
 };
 
+// A spawn record (16 B, written and read with one vector access): child
+// determinant, signed walkers, and a tag word whose meaning depends on the buffer.
+struct __attribute__((aligned(16))) SpawnRec {
+    uint64_t det;
+    int32_t w;
+    uint32_t tag;
+};
+
 struct EngineArgs {
     SysDesc *desc;
     int32_t max_sys;
@@ -126,14 +134,11 @@ struct EngineArgs {
     // Spawn records of the iteration (the per-destination blocks of Sec. 4.1, with the
     // bucket as destination): appended by k_spawn with their rank among the bucket's
     // records, grouped by bucket by k_scatter.
-    uint64_t *rec_det;               // [rec_cap] child determinant
-    int32_t *rec_w;                  // [rec_cap] signed walkers
-    uint32_t *rec_gf;                // [rec_cap] global bucket | initiator flag << 31, or the
-                                     // system | REC_UNRANKED for k_fix to place
+    SpawnRec *recs;                  // [rec_cap] tag: global bucket | initiator flag << 31, or
+                                     // the system | REC_UNRANKED for k_fix to place
     uint32_t *rec_rank;              // [rec_cap] rank among its bucket's records
-    uint64_t *srt_det;               // [rec_cap] the records grouped by bucket
-    int32_t *srt_w;
-    uint32_t *srt_f;                 // bit 0 initiator flag, bit 1 deferred to a later round
+    SpawnRec *srt;                   // [rec_cap] the records grouped by bucket; tag: bit 0
+                                     // initiator flag, bits 1-2 k_post's round marks
     unsigned long long *rec_count;   // records appended this iteration
     int64_t rec_cap;
     uint32_t *bhist;                 // [BPC chunk_cap] records per bucket (zeroed by k_bscan_down)

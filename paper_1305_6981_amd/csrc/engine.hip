@@ -288,12 +288,8 @@ EngineArgs make_args(fciqmc_t *h) {
     a.tile_cap = h->tile_cap;
     char *r = (char *)h->d_recs;
     const size_t rc = (size_t)h->rec_cap;
-    a.rec_det = (uint64_t *)r;
-    a.srt_det = (uint64_t *)(r + 8 * rc);
-    a.rec_w = (int32_t *)(r + 16 * rc);
-    a.rec_gf = (uint32_t *)(r + 20 * rc);
-    a.srt_w = (int32_t *)(r + 24 * rc);
-    a.srt_f = (uint32_t *)(r + 28 * rc);
+    a.recs = (SpawnRec *)r;
+    a.srt = (SpawnRec *)(r + 16 * rc);
     a.rec_rank = (uint32_t *)(r + 32 * rc);
     a.rec_count = h->d_rec_count;
     a.rec_cap = h->rec_cap;

@@ -195,6 +195,19 @@ __device__ __forceinline__ void gstore_i4(void *p, int x, int y, int z, int w) {
     *gp(reinterpret_cast<v4i32 *>(p)) = v;
 }
 
+// Spawn records, one 16-byte access each.
+__device__ __forceinline__ void put_rec(SpawnRec *p, uint64_t D, int32_t w, uint32_t tag) {
+    gstore_i4(p, (int)(uint32_t)D, (int)(uint32_t)(D >> 32), w, (int)tag);
+}
+__device__ __forceinline__ SpawnRec get_rec(const SpawnRec *p) {
+    const int4 x = gload_i4((const int32_t *)p);
+    SpawnRec r;
+    r.det = (uint64_t)(uint32_t)x.x | ((uint64_t)(uint32_t)x.y << 32);
+    r.w = x.z;
+    r.tag = (uint32_t)x.w;
+    return r;
+}
+
 __device__ __forceinline__ double eri_so(const SysDesc &d, int p, int q, int r, int s) {
     if (((p ^ q) | (r ^ s)) & 1) return 0.0;
     return gptr(d.eri)[tri(tri(p >> 1, q >> 1), tri(r >> 1, s >> 1))];
@@ -708,9 +721,7 @@ __device__ __forceinline__ void put_record(const EngineArgs &a, const SysDesc &d
     const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(D, (uint64_t)d.nbuckets);
     a.rec_rank[j] = __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-    a.rec_det[j] = D;
-    a.rec_w[j] = v;
-    a.rec_gf[j] = gb | (init ? 0x80000000u : 0u);
+    put_rec(a.recs + j, D, v, gb | (init ? 0x80000000u : 0u));
 }
 
 // One record per active lane, with one buffer reservation for the wavefront
@@ -729,9 +740,7 @@ __device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint
         atomicOr(status, ST_TABLE_FULL);
         return;
     }
-    a.rec_det[j] = D;
-    a.rec_w[j] = v;
-    a.rec_gf[j] = (uint32_t)s | REC_UNRANKED | (init ? 0x80000000u : 0u);
+    put_rec(a.recs + j, D, v, (uint32_t)s | REC_UNRANKED | (init ? 0x80000000u : 0u));
 }
 
 // Work queued in LDS by the attempt loop and drained by the whole workgroup:
@@ -1076,13 +1085,13 @@ __global__ __launch_bounds__(256) void k_fix(EngineArgs a, const SysDesc *__rest
     const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t gf = a.rec_gf[i];
+        const uint32_t gf = a.recs[i].tag;
         if (!(gf & REC_UNRANKED)) continue;
         const SysDesc &d = desc[gf & 0x3FFFFFFFu];
-        const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(a.rec_det[i], (uint64_t)d.nbuckets);
+        const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(a.recs[i].det, (uint64_t)d.nbuckets);
         a.rec_rank[i] = __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-        a.rec_gf[i] = gb | (gf & 0x80000000u);
+        a.recs[i].tag = gb | (gf & 0x80000000u);
     }
 }
 
@@ -1169,12 +1178,10 @@ __global__ __launch_bounds__(256) void k_scatter(EngineArgs a) {
     const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t gf = a.rec_gf[i];
-        const uint32_t gb = gf & 0x7FFFFFFFu;
+        const SpawnRec r = get_rec(a.recs + i);
+        const uint32_t gb = r.tag & 0x7FFFFFFFu;
         const uint32_t pos = a.boff[gb] + a.rec_rank[i];
-        a.srt_det[pos] = a.rec_det[i];
-        a.srt_w[pos] = a.rec_w[i];
-        a.srt_f[pos] = gf >> 31;
+        put_rec(a.srt + pos, r.det, r.w, r.tag >> 31);
     }
 }
 
@@ -1198,6 +1205,7 @@ constexpr int NREC = 64;                // distinct children per round in a wave
 constexpr int WHASH = 128;              // hash slots per wavefront (load <= 0.5)
 constexpr int POST_QUEUE = 1024;        // new determinants whose H_DD is still to be computed
 constexpr int POST_MAX_SYS = 256;       // systems whose status k_post snapshots in LDS
+constexpr int POST_WIN = 32;            // chunks per window of bucket metadata in LDS
 constexpr uint32_t F_INIT = 1u;         // from an initiator parent (records and hash slots)
 constexpr uint32_t F_MATCHED = 2u;      // hash slot: the child is an entry of the bucket
 constexpr uint32_t F_MAYBE = 2u;        // record: found the hash full in this round,
@@ -1346,9 +1354,16 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ PostLds L;
     __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ uint32_t s_stat[POST_MAX_SYS];   // the systems' status at the kernel's start
+    // Metadata of a window of POST_WIN chunks, read once for all its buckets.
+    __shared__ int s_csys[POST_WIN];                 // system of the chunk (-1: not taking part)
+    __shared__ int s_cloc[POST_WIN];                 // chunk index inside its system's table
+    __shared__ uint8_t s_cnext[POST_WIN];            // its walkers spawn next iteration
+    __shared__ int16_t s_bn[POST_WIN * BPC];         // entries per bucket
+    __shared__ uint32_t s_boff[POST_WIN * BPC + 1];  // first sorted record per bucket, and the end
+    __shared__ unsigned long long s_cnws[POST_WIN];  // the chunk's sum of |C| after the iteration
+    __shared__ int s_cdone[POST_WIN];                // wavefronts done with the chunk
     __shared__ int s_qn, s_qsys;
     __shared__ int s_ncl[POST_WAVES];
-    __shared__ unsigned long long s_nwn[POST_WAVES];
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     WaveLds &W = L.w[wid];
@@ -1358,15 +1373,13 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     const int64_t per_range = (nch + SCAN_G - 1) / SCAN_G;
     const int tsh = __builtin_ctzll((unsigned long long)a.tile);
     const unsigned long long tm = (unsigned long long)a.tile - 1ull;
-    // Which systems take part is decided once, from the status at the start: bits set
-    // while this kernel runs (population overflow) are fatal to their system anyway,
-    // and a decision shared by the workgroup keeps its barriers uniform.
+    // Which systems take part is decided from the status at the start: bits set while
+    // this kernel runs (population overflow) are fatal to their system anyway.
     for (int i = t; i < a.max_sys && i < POST_MAX_SYS; i += 256) s_stat[i] = a.status[i];
     if (t == 0) {
         s_qn = 0;
         s_qsys = -1;
     }
-    __syncthreads();
     auto flush = [&]() {   // (uniform) H_DD of the queued new determinants
         const SysDesc &dq = desc[s_qsys];
         for (int i = t; i < dq.n_so * 64; i += 256) {
@@ -1378,363 +1391,407 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
         flush_new_dets(dq, s_queue, s_qn < POST_QUEUE ? s_qn : POST_QUEUE, L.tab.hpp, L.tab.jk);
         __syncthreads();
     };
+    // Each workgroup takes a contiguous range of chunks, in windows of POST_WIN; inside
+    // a window the wavefronts run through the chunks independently, and the last one
+    // done with a chunk writes the chunk's sum for the next iteration.
     const int64_t per = (nch + gridDim.x - 1) / gridDim.x;
     const int64_t c_lo = (int64_t)blockIdx.x * per;
     const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
-    for (int64_t c = c_lo; c < c_hi; ++c) {
-        const int s = ld_uniform(a.chunk_sys + c);
-        const bool live = s >= 0 && (s >= POST_MAX_SYS ? participating(desc[s], 1u)
-                                                       : participating(desc[s], s_stat[s]));
-        if (live && s_qsys >= 0 && (s_qsys != s || s_qn > POST_QUEUE / 2)) {
-            // the queued determinants are another system's, or the queue is filling up
+    for (int64_t c0 = c_lo; c0 < c_hi; c0 += POST_WIN) {
+        const int nwin = (int)(c_hi - c0 < POST_WIN ? c_hi - c0 : POST_WIN);
+        __syncthreads();   // the previous window is done
+        if (s_qn > 0) {    // (uniform)
             flush();
             if (t == 0) {
                 s_qn = 0;
                 s_qsys = -1;
             }
-            __syncthreads();
         }
-        int64_t nw = 0, aborted = 0;
-        uint64_t cnt = 0;                 // entries | merged targets << 21 | occupied << 42
-        double num = 0.0;
-        unsigned long long nwb = 0;       // sum |C| over the bucket's entries after the iteration
-        if (live) {
-            const SysDesc &d = desc[s];
-            uint32_t *status = &a.status[s];
-            if (t == 0) s_qsys = s;
-            const int64_t lb = (int64_t)ld_uniform(a.chunk_local + c) * BPC + wid;
-            const int64_t gb = c * BPC + wid;
-            const int64_t base = lb * BQ;
-            const int n = ld_uniform(d.bcnt + lb);
-            const uint32_t r0 = ld_uniform(a.boff + gb);
-            const uint32_t nr = ld_uniform(a.boff + gb + 1) - r0;
-            const int e0 = 4 * lane;
-            uint64_t kin[4] = {0ull, 0ull, 0ull, 0ull};
-            int32_t pin[4] = {0, 0, 0, 0};
-            double hin[4] = {0.0, 0.0, 0.0, 0.0};
-            if (e0 < n) {
-                const ulonglong2 k01 = gload_u2(d.key + base + e0);
-                const ulonglong2 k23 = gload_u2(d.key + base + e0 + 2);
-                const int4 pv = gload_i4(d.pop + base + e0);
-                const double2 h01 = gload_d2(d.hdiag + base + e0);
-                const double2 h23 = gload_d2(d.hdiag + base + e0 + 2);
-                kin[0] = k01.x; kin[1] = k01.y; kin[2] = k23.x; kin[3] = k23.y;
-                pin[0] = pv.x; pin[1] = pv.y; pin[2] = pv.z; pin[3] = pv.w;
-                hin[0] = h01.x; hin[1] = h01.y; hin[2] = h23.x; hin[3] = h23.y;
+        if (t < nwin) {
+            const int sc = a.chunk_sys[c0 + t];
+            bool live = false, next = false;
+            if (sc >= 0) {
+                const SysDesc &dc = desc[sc];
+                live = participating(dc, sc < POST_MAX_SYS ? s_stat[sc] : a.status[sc]);
+                next = live && dc.iter + 1 < dc.stop_at;
             }
-            uint64_t rd = 0ull;   // this lane's record (fast path)
-            int32_t rw = 0;
-            uint32_t rf = 0u;
-            if ((uint32_t)lane < nr && nr <= (uint32_t)NREC) {
-                rd = a.srt_det[r0 + lane];
-                rw = a.srt_w[r0 + lane];
-                rf = a.srt_f[r0 + lane];
-            }
-            W.key[lane] = 0ull;
-            W.key[lane + 64] = 0ull;
-            W.acc[lane] = 0ll;
-            W.acc[lane + 64] = 0ll;
-            W.flg[lane] = 0u;
-            W.flg[lane + 64] = 0u;
-            // death of every entry (Eq. pdeath, one stochastic rounding for the whole
-            // determinant); it depends on nothing that arrives
-            int32_t pdv[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t p = pin[u];
-                if (e0 + u >= n || p == 0) continue;
-                uint64_t xd, xu;
-                draw2(d.seed, kin[u], 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
-                const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
-                const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
-                const double ad = fabs(dv);
-                const double fl = floor(ad);
-                int64_t pd = p;
-                if (fl > 1073741824.0) {
-                    atomicOr(status, ST_POP_OVERFLOW);
-                } else {
-                    const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
-                    pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
-                    if (pd > 2147483647ll || pd < -2147483647ll) {
+            s_csys[t] = live ? sc : -1;
+            s_cloc[t] = a.chunk_local[c0 + t];
+            s_cnext[t] = next ? 1 : 0;
+            s_cnws[t] = 0ull;
+            s_cdone[t] = 0;
+        }
+        if (t <= nwin * BPC) s_boff[t] = a.boff[c0 * BPC + t];
+        __syncthreads();
+        if (t < nwin * BPC) {
+            const int sc = s_csys[t / BPC];
+            s_bn[t] = sc >= 0 ? (int16_t)desc[sc].bcnt[(int64_t)s_cloc[t / BPC] * BPC + t % BPC] : 0;
+        }
+        __syncthreads();
+        for (int ci = 0; ci < nwin; ++ci) {
+            const int64_t c = c0 + ci;
+            const int s = s_csys[ci];
+            const bool live = s >= 0;
+            int64_t nw = 0, aborted = 0;
+            uint64_t cnt = 0;                 // entries | merged targets << 21 | occupied << 42
+            double num = 0.0;
+            unsigned long long nwb = 0;       // sum |C| over the bucket's entries after the iteration
+            if (live) {
+                const SysDesc &d = desc[s];
+                uint32_t *status = &a.status[s];
+                const int64_t lb = (int64_t)s_cloc[ci] * BPC + wid;
+                const int64_t base = lb * BQ;
+                const int n = s_bn[ci * BPC + wid];
+                const uint32_t r0 = s_boff[ci * BPC + wid];
+                const uint32_t nr = s_boff[ci * BPC + wid + 1] - r0;
+                // the H_DD queue serves one system at a time: the first to use it in a window
+                if (lane == 0 && s_qsys < 0) atomicCAS(&s_qsys, -1, s);
+                const int e0 = 4 * lane;
+                uint64_t kin[4] = {0ull, 0ull, 0ull, 0ull};
+                int32_t pin[4] = {0, 0, 0, 0};
+                double hin[4] = {0.0, 0.0, 0.0, 0.0};
+                if (e0 < n) {
+                    const ulonglong2 k01 = gload_u2(d.key + base + e0);
+                    const ulonglong2 k23 = gload_u2(d.key + base + e0 + 2);
+                    const int4 pv = gload_i4(d.pop + base + e0);
+                    const double2 h01 = gload_d2(d.hdiag + base + e0);
+                    const double2 h23 = gload_d2(d.hdiag + base + e0 + 2);
+                    kin[0] = k01.x; kin[1] = k01.y; kin[2] = k23.x; kin[3] = k23.y;
+                    pin[0] = pv.x; pin[1] = pv.y; pin[2] = pv.z; pin[3] = pv.w;
+                    hin[0] = h01.x; hin[1] = h01.y; hin[2] = h23.x; hin[3] = h23.y;
+                }
+                uint64_t rd = 0ull;   // this lane's record (fast path)
+                int32_t rw = 0;
+                uint32_t rf = 0u;
+                if ((uint32_t)lane < nr && nr <= (uint32_t)NREC) {
+                    const SpawnRec r = get_rec(a.srt + r0 + lane);
+                    rd = r.det;
+                    rw = r.w;
+                    rf = r.tag;
+                }
+                W.key[lane] = 0ull;
+                W.key[lane + 64] = 0ull;
+                W.acc[lane] = 0ll;
+                W.acc[lane + 64] = 0ll;
+                W.flg[lane] = 0u;
+                W.flg[lane + 64] = 0u;
+                // death of every entry (Eq. pdeath, one stochastic rounding for the whole
+                // determinant); it depends on nothing that arrives
+                int32_t pdv[4] = {0, 0, 0, 0};
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t p = pin[u];
+                    if (e0 + u >= n || p == 0) continue;
+                    uint64_t xd, xu;
+                    draw2(d.seed, kin[u], 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
+                    const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
+                    const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
+                    const double ad = fabs(dv);
+                    const double fl = floor(ad);
+                    int64_t pd = p;
+                    if (fl > 1073741824.0) {
                         atomicOr(status, ST_POP_OVERFLOW);
-                        pd = 0;
-                    }
-                }
-                pdv[u] = (int32_t)pd;
-            }
-            wave_sync();
-            long long spv[4] = {0ll, 0ll, 0ll, 0ll};   // walkers arrived per entry
-            uint32_t flv = 0u;                         // bit u: an initiator sent some
-            int kc = 0;                                // slow path: staged children (uniform)
-            if (nr <= (uint32_t)NREC) {
-                // Fast path: at most NREC records, so at most NREC distinct children.
-                if ((uint32_t)lane < nr) {
-                    const int h = wh_claim(rd, W.key);
-                    atomicAdd((unsigned long long *)&W.acc[h], (unsigned long long)(long long)rw);
-                    if (rf & F_INIT) atomicOr(&W.flg[h], F_INIT);
-                }
-                wave_sync();
-                if (nr > 0) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (e0 + u >= n) continue;
-                        const int h = wh_find(kin[u], W.key);
-                        if (h < 0) continue;
-                        spv[u] = W.acc[h];
-                        flv |= (W.flg[h] & F_INIT) << u;
-                        W.flg[h] |= F_MATCHED;   // a child matches at most one entry
-                    }
-                }
-                wave_sync();
-            } else {
-                // Slow path: rounds of at most NREC distinct children. A child whose
-                // records found the hash full is left whole for a later round; the
-                // children outside the bucket are staged, merged, in the bucket's range
-                // of the unsorted record buffer.
-                for (int round = 0;; ++round) {
-                    if (round > 0) {
-                        W.key[lane] = 0ull;
-                        W.key[lane + 64] = 0ull;
-                        W.acc[lane] = 0ll;
-                        W.acc[lane + 64] = 0ll;
-                        W.flg[lane] = 0u;
-                        W.flg[lane + 64] = 0u;
-                    }
-                    if (lane == 0) s_ncl[wid] = 0;
-                    wave_sync();
-                    bool maybe = false;
-                    for (uint32_t j = lane; j < nr; j += 64) {   // (a record stays with its lane)
-                        const uint32_t f = a.srt_f[r0 + j];
-                        if (round > 0 && !(f & F_DEFER)) continue;
-                        const uint64_t D = a.srt_det[r0 + j];
-                        const int h = wh_claim_limited(D, W.key, &s_ncl[wid]);
-                        if (h < 0) {
-                            a.srt_f[r0 + j] = (f & F_INIT) | F_MAYBE;
-                            maybe = true;
-                            continue;
+                    } else {
+                        const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
+                        pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
+                        if (pd > 2147483647ll || pd < -2147483647ll) {
+                            atomicOr(status, ST_POP_OVERFLOW);
+                            pd = 0;
                         }
-                        if (f & F_DEFER) a.srt_f[r0 + j] = f & F_INIT;
-                        atomicAdd((unsigned long long *)&W.acc[h],
-                                  (unsigned long long)(long long)a.srt_w[r0 + j]);
-                        if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
+                    }
+                    pdv[u] = (int32_t)pd;
+                }
+                wave_sync();
+                long long spv[4] = {0ll, 0ll, 0ll, 0ll};   // walkers arrived per entry
+                uint32_t flv = 0u;                         // bit u: an initiator sent some
+                int kc = 0;                                // slow path: staged children (uniform)
+                if (nr <= (uint32_t)NREC) {
+                    // Fast path: at most NREC records, so at most NREC distinct children.
+                    if ((uint32_t)lane < nr) {
+                        const int h = wh_claim(rd, W.key);
+                        atomicAdd((unsigned long long *)&W.acc[h], (unsigned long long)(long long)rw);
+                        if (rf & F_INIT) atomicOr(&W.flg[h], F_INIT);
                     }
                     wave_sync();
-                    bool defer = false;
-                    if (__ballot(maybe)) {
-                        for (uint32_t j = lane; j < nr; j += 64) {
-                            const uint32_t f = a.srt_f[r0 + j];
-                            if (!(f & F_MAYBE)) continue;
-                            const int h = wh_find(a.srt_det[r0 + j], W.key);
+                    if (nr > 0) {
+    #pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (e0 + u >= n) continue;
+                            const int h = wh_find(kin[u], W.key);
+                            if (h < 0) continue;
+                            spv[u] = W.acc[h];
+                            flv |= (W.flg[h] & F_INIT) << u;
+                            W.flg[h] |= F_MATCHED;   // a child matches at most one entry
+                        }
+                    }
+                    wave_sync();
+                } else {
+                    // Slow path: rounds of at most NREC distinct children. A child whose
+                    // records found the hash full is left whole for a later round; the
+                    // children outside the bucket are staged, merged, in the bucket's range
+                    // of the unsorted record buffer.
+                    for (int round = 0;; ++round) {
+                        if (round > 0) {
+                            W.key[lane] = 0ull;
+                            W.key[lane + 64] = 0ull;
+                            W.acc[lane] = 0ll;
+                            W.acc[lane + 64] = 0ll;
+                            W.flg[lane] = 0u;
+                            W.flg[lane + 64] = 0u;
+                        }
+                        if (lane == 0) s_ncl[wid] = 0;
+                        wave_sync();
+                        bool maybe = false;
+                        for (uint32_t j = lane; j < nr; j += 64) {   // (a record stays with its lane)
+                            const uint32_t f = a.srt[r0 + j].tag;
+                            if (round > 0 && !(f & F_DEFER)) continue;
+                            const uint64_t D = a.srt[r0 + j].det;
+                            const int h = wh_claim_limited(D, W.key, &s_ncl[wid]);
                             if (h < 0) {
-                                a.srt_f[r0 + j] = (f & F_INIT) | F_DEFER;
-                                defer = true;
+                                a.srt[r0 + j].tag = (f & F_INIT) | F_MAYBE;
+                                maybe = true;
                                 continue;
                             }
-                            a.srt_f[r0 + j] = f & F_INIT;
+                            if (f & F_DEFER) a.srt[r0 + j].tag = f & F_INIT;
                             atomicAdd((unsigned long long *)&W.acc[h],
-                                      (unsigned long long)(long long)a.srt_w[r0 + j]);
+                                      (unsigned long long)(long long)a.srt[r0 + j].w);
                             if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
                         }
                         wave_sync();
+                        bool defer = false;
+                        if (__ballot(maybe)) {
+                            for (uint32_t j = lane; j < nr; j += 64) {
+                                const uint32_t f = a.srt[r0 + j].tag;
+                                if (!(f & F_MAYBE)) continue;
+                                const int h = wh_find(a.srt[r0 + j].det, W.key);
+                                if (h < 0) {
+                                    a.srt[r0 + j].tag = (f & F_INIT) | F_DEFER;
+                                    defer = true;
+                                    continue;
+                                }
+                                a.srt[r0 + j].tag = f & F_INIT;
+                                atomicAdd((unsigned long long *)&W.acc[h],
+                                          (unsigned long long)(long long)a.srt[r0 + j].w);
+                                if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
+                            }
+                            wave_sync();
+                        }
+    #pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (e0 + u >= n) continue;
+                            const int h = wh_find(kin[u], W.key);
+                            if (h < 0) continue;
+                            spv[u] += W.acc[h];
+                            flv |= (W.flg[h] & F_INIT) << u;
+                            W.flg[h] |= F_MATCHED;
+                        }
+                        wave_sync();
+                        // stage this round's children outside the bucket (one per slot)
+                        for (int h = lane; h < WHASH; h += 64) {
+                            const uint64_t D = W.key[h];
+                            const bool cand = D != 0ull && !(W.flg[h] & F_MATCHED);
+                            const uint64_t m = __ballot(cand);
+                            if (cand) {
+                                const uint32_t j = r0 + (uint32_t)kc + (uint32_t)__popcll(m & lanes_below(lane));
+                                long long sp = W.acc[h];
+                                if (sp > 2147483647ll || sp < -2147483647ll) {
+                                    atomicOr(status, ST_POP_OVERFLOW);
+                                    sp = 0;
+                                }
+                                put_rec(a.recs + j, D, (int32_t)sp, W.flg[h] & F_INIT);
+                            }
+                            kc += __popcll(m);
+                        }
+                        wave_sync();
+                        if (!__ballot(defer)) break;
                     }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        if (e0 + u >= n) continue;
-                        const int h = wh_find(kin[u], W.key);
-                        if (h < 0) continue;
-                        spv[u] += W.acc[h];
-                        flv |= (W.flg[h] & F_INIT) << u;
-                        W.flg[h] |= F_MATCHED;
+                    __threadfence();   // the staged children, read back below by other lanes
+                }
+                // Annihilation (Sec. 4.2) of the bucket's own entries.
+                int32_t npv[4] = {0, 0, 0, 0};
+                uint32_t keepm = 0u;
+                uint32_t nearm = 0u;   // bit u: entry u contributes to the projected energy
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (e0 + u >= n) continue;
+                    const uint64_t D = kin[u];
+                    const bool is_ref = D == d.d0;
+                    const int64_t pd = pdv[u];
+                    // (walkers spawned onto the reference arrive in their own sum)
+                    const long long sp = spv[u] + (is_ref ? a.d0acc[s] : 0ll);
+                    int64_t np;
+                    if (pd != 0 || is_ref) {
+                        np = pd + sp;
+                    } else if (sp != 0 && ((flv >> u) & 1u)) {
+                        np = sp;
+                    } else {
+                        np = 0;
+                        if (sp != 0) aborted += sp < 0 ? -sp : sp;
                     }
-                    wave_sync();
-                    // stage this round's children outside the bucket (one per slot)
+                    if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
+                    if (np > 2147483647ll || np < -2147483647ll) {
+                        atomicOr(status, ST_POP_OVERFLOW);
+                        np = 0;
+                    }
+                    npv[u] = (int32_t)np;
+                    if (is_ref) {
+                        a.c0[s] = np;
+                        a.d0acc[s] = 0ll;   // consumed
+                    }
+                    if (np != 0) {
+                        const int64_t an = np < 0 ? -np : np;
+                        nw += an;
+                        nwb += (unsigned long long)an;
+                        cnt += 1ull << CNT_SHIFT_ND;
+                        if (!is_ref && __popcll(D ^ d.d0) <= 4) nearm |= 1u << u;
+                    }
+                    if (np != 0 || is_ref) keepm |= 1u << u;   // the reference keeps its entry at 0
+                }
+                const int nin = e0 < n ? (n - e0 < 4 ? n - e0 : 4) : 0;
+                const int nkeep = __popc(keepm), nhole = nin - nkeep;
+                {   // positions emptied this iteration, ascending
+                    int k = wave_prefix8(nhole, lane);
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (u < nin && !((keepm >> u) & 1u)) W.free_[k++] = (uint16_t)(e0 + u);
+                }
+                const int H = wave_total8(nhole);
+                const int Lk = n - H;
+                wave_sync();
+                // New determinants: children outside the bucket with an initiator parent go
+                // to the emptied positions first, then past the end; the others are discarded.
+                int K = 0;
+                int calls = 0;
+                uint32_t nearn = 0u;   // fast path: bit i, the new determinant of slot lane + 64 i
+                                       // contributes to the projected energy
+                auto place = [&](uint64_t D, long long sp, bool init) {   // (all lanes; D = 0: none)
+                    const bool real = D != 0ull && sp != 0;
+                    if (real) cnt += 1ull << CNT_SHIFT_MERGED;
+                    if (real && !init) aborted += sp < 0 ? -sp : sp;
+                    const bool nd = real && init;
+                    const uint64_t m = __ballot(nd);
+                    const int k = K + __popcll(m & lanes_below(lane));
+                    K += __popcll(m);
+                    const int call = calls++;
+                    if (!nd) return;
+                    const int64_t an = sp < 0 ? -sp : sp;
+                    nw += an;
+                    cnt += 1ull << CNT_SHIFT_ND;
+                    if (call < 32 && __popcll(D ^ d.d0) <= 4) nearn |= 1u << call;
+                    const int pos = k < H ? (int)W.free_[k] : n + (k - H);
+                    if (pos < BQ) {
+                        nwb += (unsigned long long)an;
+                        *gp(d.key + base + pos) = D;
+                        *gp(d.pop + base + pos) = (int32_t)sp;
+                        const int q = s_qsys == s ? atomicAdd(&s_qn, 1) : POST_QUEUE;
+                        if (q < POST_QUEUE) {
+                            s_queue[q] = (uint32_t)(base + pos);
+                        } else {   // (another system's window, or many new determinants)
+                            *gp(d.hdiag + base + pos) = hdiag_of(d, D);
+                        }
+                    } else {
+                        // the bucket is full: completed in the spill list, re-bucketed by the host
+                        const unsigned long long j = atomicAdd(a.sp_count, 1ull);
+                        if (j < (unsigned long long)a.sp_cap) {
+                            a.sp_det[j] = D;
+                            a.sp_pop[j] = (int32_t)sp;
+                            a.sp_hd[j] = hdiag_of(d, D);
+                            a.sp_sys[j] = s;
+                            a.spilled[s] = 1u;
+                        } else {
+                            atomicOr(status, ST_SPILL_FULL);
+                        }
+                    }
+                };
+                if (nr <= (uint32_t)NREC) {
                     for (int h = lane; h < WHASH; h += 64) {
                         const uint64_t D = W.key[h];
-                        const bool cand = D != 0ull && !(W.flg[h] & F_MATCHED);
-                        const uint64_t m = __ballot(cand);
-                        if (cand) {
-                            const uint32_t j = r0 + (uint32_t)kc + (uint32_t)__popcll(m & lanes_below(lane));
-                            long long sp = W.acc[h];
-                            if (sp > 2147483647ll || sp < -2147483647ll) {
-                                atomicOr(status, ST_POP_OVERFLOW);
-                                sp = 0;
-                            }
-                            a.rec_det[j] = D;
-                            a.rec_w[j] = (int32_t)sp;
-                            a.rec_gf[j] = W.flg[h] & F_INIT;
+                        const uint32_t f = W.flg[h];
+                        const bool cand = D != 0ull && !(f & F_MATCHED);
+                        const long long sp = cand ? W.acc[h] : 0ll;
+                        if (sp > 2147483647ll || sp < -2147483647ll) {
+                            atomicOr(status, ST_POP_OVERFLOW);
+                            place(0ull, 0ll, false);
+                        } else {
+                            place(cand ? D : 0ull, sp, (f & F_INIT) != 0u);
                         }
-                        kc += __popcll(m);
-                    }
-                    wave_sync();
-                    if (!__ballot(defer)) break;
-                }
-                __threadfence();   // the staged children, read back below by other lanes
-            }
-            // Annihilation (Sec. 4.2) of the bucket's own entries.
-            const long long to_ref = ld_uniform(a.d0acc + s);   // walkers spawned onto the reference
-            int32_t npv[4] = {0, 0, 0, 0};
-            uint32_t keepm = 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (e0 + u >= n) continue;
-                const uint64_t D = kin[u];
-                const bool is_ref = D == d.d0;
-                const int64_t pd = pdv[u];
-                const long long sp = spv[u] + (is_ref ? to_ref : 0ll);
-                int64_t np;
-                if (pd != 0 || is_ref) {
-                    np = pd + sp;
-                } else if (sp != 0 && ((flv >> u) & 1u)) {
-                    np = sp;
-                } else {
-                    np = 0;
-                    if (sp != 0) aborted += sp < 0 ? -sp : sp;
-                }
-                if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
-                if (np > 2147483647ll || np < -2147483647ll) {
-                    atomicOr(status, ST_POP_OVERFLOW);
-                    np = 0;
-                }
-                npv[u] = (int32_t)np;
-                if (is_ref) {
-                    a.c0[s] = np;
-                    a.d0acc[s] = 0ll;   // consumed
-                }
-                if (np != 0) {
-                    const int64_t an = np < 0 ? -np : np;
-                    nw += an;
-                    nwb += (unsigned long long)an;
-                    cnt += 1ull << CNT_SHIFT_ND;
-                    if (!is_ref && __popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)np;
-                }
-                if (np != 0 || is_ref) keepm |= 1u << u;   // the reference keeps its entry at 0
-            }
-            const int nin = e0 < n ? (n - e0 < 4 ? n - e0 : 4) : 0;
-            const int nkeep = __popc(keepm), nhole = nin - nkeep;
-            {   // positions emptied this iteration, ascending
-                int k = wave_prefix8(nhole, lane);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u < nin && !((keepm >> u) & 1u)) W.free_[k++] = (uint16_t)(e0 + u);
-            }
-            const int H = wave_total8(nhole);
-            const int Lk = n - H;
-            wave_sync();
-            // New determinants: children outside the bucket with an initiator parent go
-            // to the emptied positions first, then past the end; the others are discarded.
-            int K = 0;
-            auto place = [&](uint64_t D, long long sp, bool init) {   // (all lanes; D = 0: none)
-                const bool real = D != 0ull && sp != 0;
-                if (real) cnt += 1ull << CNT_SHIFT_MERGED;
-                if (real && !init) aborted += sp < 0 ? -sp : sp;
-                const bool nd = real && init;
-                const uint64_t m = __ballot(nd);
-                const int k = K + __popcll(m & lanes_below(lane));
-                K += __popcll(m);
-                if (!nd) return;
-                const int64_t an = sp < 0 ? -sp : sp;
-                nw += an;
-                cnt += 1ull << CNT_SHIFT_ND;
-                if (__popcll(D ^ d.d0) <= 4) num = num + hel_to_ref(d, D) * (double)sp;
-                const int pos = k < H ? (int)W.free_[k] : n + (k - H);
-                if (pos < BQ) {
-                    nwb += (unsigned long long)an;
-                    *gp(d.key + base + pos) = D;
-                    *gp(d.pop + base + pos) = (int32_t)sp;
-                    const int q = atomicAdd(&s_qn, 1);
-                    if (q < POST_QUEUE) {
-                        s_queue[q] = (uint32_t)(base + pos);
-                    } else {   // (only after buckets with many new determinants)
-                        *gp(d.hdiag + base + pos) = hdiag_of(d, D);
                     }
                 } else {
-                    // the bucket is full: completed in the spill list, re-bucketed by the host
-                    const unsigned long long j = atomicAdd(a.sp_count, 1ull);
-                    if (j < (unsigned long long)a.sp_cap) {
-                        a.sp_det[j] = D;
-                        a.sp_pop[j] = (int32_t)sp;
-                        a.sp_hd[j] = hdiag_of(d, D);
-                        a.sp_sys[j] = s;
-                        a.spilled[s] = 1u;
-                    } else {
-                        atomicOr(status, ST_SPILL_FULL);
+                    for (int i0 = 0; i0 < kc; i0 += 64) {
+                        const int i = i0 + lane;
+                        const bool in = i < kc;
+                        place(in ? a.recs[r0 + i].det : 0ull, in ? (long long)a.recs[r0 + i].w : 0ll,
+                              in && (a.recs[r0 + i].tag & F_INIT));
                     }
                 }
-            };
-            if (nr <= (uint32_t)NREC) {
-                for (int h = lane; h < WHASH; h += 64) {
-                    const uint64_t D = W.key[h];
-                    const uint32_t f = W.flg[h];
-                    const bool cand = D != 0ull && !(f & F_MATCHED);
-                    const long long sp = cand ? W.acc[h] : 0ll;
-                    if (sp > 2147483647ll || sp < -2147483647ll) {
-                        atomicOr(status, ST_POP_OVERFLOW);
-                        place(0ull, 0ll, false);
-                    } else {
-                        place(cand ? D : 0ull, sp, (f & F_INIT) != 0u);
+                // Re-pack: n' = (kept entries) + (new determinants); when fewer new
+                // determinants than emptied positions arrived, the kept entries past n' move
+                // into the emptied positions that remain below n'.
+                const int np_ = Lk + K < BQ ? Lk + K : BQ;
+                uint32_t movedm = 0u;
+                if (K < H) {   // uniform
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (((keepm >> u) & 1u) && e0 + u >= np_) movedm |= 1u << u;
+                    int r = K + wave_prefix8(__popc(movedm), lane);
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (!((movedm >> u) & 1u)) continue;
+                        const int64_t dst = base + W.free_[r++];
+                        *gp(d.key + dst) = kin[u];
+                        *gp(d.pop + dst) = npv[u];
+                        *gp(d.hdiag + dst) = hin[u];
                     }
                 }
-            } else {
-                for (int i0 = 0; i0 < kc; i0 += 64) {
-                    const int i = i0 + lane;
-                    const bool in = i < kc;
-                    place(in ? a.rec_det[r0 + i] : 0ull, in ? (long long)a.rec_w[r0 + i] : 0ll,
-                          in && (a.rec_gf[r0 + i] & F_INIT));
+    #pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (((keepm & ~movedm) >> u) & 1u && npv[u] != pin[u])
+                        *gp(d.pop + base + e0 + u) = npv[u];
+                if (lane == 0) {
+                    d.bcnt[lb] = np_;
+                    cnt += (uint64_t)np_;
                 }
-            }
-            // Re-pack: n' = (kept entries) + (new determinants); when fewer new
-            // determinants than emptied positions arrived, the kept entries past n' move
-            // into the emptied positions that remain below n'.
-            const int np_ = Lk + K < BQ ? Lk + K : BQ;
-            uint32_t movedm = 0u;
-            if (K < H) {   // uniform
+                // Projected-energy numerator (Eq. ProjE): the occupied determinants within a
+                // double excitation of the reference, taken last, when few values are live.
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if (((keepm >> u) & 1u) && e0 + u >= np_) movedm |= 1u << u;
-                int r = K + wave_prefix8(__popc(movedm), lane);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (!((movedm >> u) & 1u)) continue;
-                    const int64_t dst = base + W.free_[r++];
-                    *gp(d.key + dst) = kin[u];
-                    *gp(d.pop + dst) = npv[u];
-                    *gp(d.hdiag + dst) = hin[u];
+                    if ((nearm >> u) & 1u) num = num + hel_to_ref(d, kin[u]) * (double)npv[u];
+                if (nr <= (uint32_t)NREC) {
+                    for (int i = 0; i < 2; ++i)
+                        if ((nearn >> i) & 1u)
+                            num = num + hel_to_ref(d, W.key[lane + 64 * i]) * (double)W.acc[lane + 64 * i];
+                } else {
+                    for (int i = lane; i < kc; i += 64) {
+                        const uint64_t D = a.recs[r0 + i].det;
+                        const int32_t sp = a.recs[r0 + i].w;
+                        if (sp != 0 && (a.recs[r0 + i].tag & F_INIT) && __popcll(D ^ d.d0) <= 4)
+                            num = num + hel_to_ref(d, D) * (double)sp;
+                    }
                 }
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (((keepm & ~movedm) >> u) & 1u && npv[u] != pin[u])
-                    *gp(d.pop + base + e0 + u) = npv[u];
+            // fixed-order reduction per wavefront; each wavefront writes its bucket's share
+            nw = wave_sum((long long)nw);
+            aborted = wave_sum((long long)aborted);
+            cnt = wave_sum((unsigned long long)cnt);
+            num = wave_sum(num);
+            nwb = wave_sum(nwb);
             if (lane == 0) {
-                d.bcnt[lb] = np_;
-                cnt += (uint64_t)np_;
-            }
-        }
-        // fixed-order reduction per wavefront; each wavefront writes its bucket's share
-        nw = wave_sum((long long)nw);
-        aborted = wave_sum((long long)aborted);
-        cnt = wave_sum((unsigned long long)cnt);
-        num = wave_sum(num);
-        nwb = wave_sum(nwb);
-        if (lane == 0) {
-            a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
-            // walkers that spawn next iteration: none if the system stops after this one
-            const bool next = live && desc[s].iter + 1 < desc[s].stop_at;
-            s_nwn[wid] = next ? nwb : 0ull;
-        }
-        __syncthreads();
-        if (t == 0) {
-            unsigned long long x = 0ull;
-            for (int w = 0; w < POST_WAVES; ++w) x += s_nwn[w];
-            nws_next[c] = x;
-            if (x) {
-                atomicAdd(&rg_next[c / per_range], x);
-                atomicAdd(&rg_next[SCAN_G + c / per_range], (x + tm) >> tsh);
+                a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
+                // walkers that spawn next iteration: none if the system stops after this one
+                if (s_cnext[ci] && nwb) atomicAdd(&s_cnws[ci], nwb);
+                if (atomicAdd(&s_cdone[ci], 1) == POST_WAVES - 1) {
+                    const unsigned long long x = atomicAdd(&s_cnws[ci], 0ull);
+                    nws_next[c] = x;
+                    if (x) {
+                        atomicAdd(&rg_next[c / per_range], x);
+                        atomicAdd(&rg_next[SCAN_G + c / per_range], (x + tm) >> tsh);
+                    }
+                }
             }
         }
     }
     __syncthreads();
-    if (s_qsys >= 0 && s_qn > 0) flush();   // uniform
+    if (s_qn > 0) flush();   // uniform
 }
 
 // ---------------------------------------------------------------------------
