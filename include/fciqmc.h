@@ -130,7 +130,21 @@ typedef struct {
      * (chunk scans); death runs inside the annihilation pass, so ms_death is 0 and
      * its time is part of ms_annihilate; the estimators include the shift. */
     double ms_spawn, ms_death, ms_annihilate, ms_estimators;
+    int64_t born;               /* determinants that entered the main list: unoccupied
+                                   after death, with an initiator among the parents of
+                                   their merged spawns (Sec. 4.2) */
 } fciqmc_estimates;
+
+/* One iteration's record (the last 256 iterations of each slot are kept). */
+typedef struct {
+    int64_t iteration;          /* completed iterations after this one */
+    int64_t n_walkers, n_dets, ref_pop;
+    int64_t attempts, spawns, merged, aborted, born;
+    int64_t entries;            /* main-list entries after the iteration (the occupied
+                                   determinants and the reference) */
+    double proj_num, shift;
+    int32_t shift_varying, status;
+} fciqmc_iteration;
 
 /* Create a handle holding one system, place initial_walkers on the reference.
  * hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream),
@@ -232,17 +246,24 @@ int32_t fciqmc_batch_active(fciqmc_t *h);
 int fciqmc_set_profiling(fciqmc_t *h, int32_t on);
 int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
 
+/* Records of iterations first .. first + n - 1 of a slot (each must be among the
+ * slot's last 256 iterations) into out[0 .. n). Returns n, or EINVAL / ESTATE. */
+int64_t fciqmc_history(fciqmc_t *h, int32_t slot, int64_t first, int64_t n, fciqmc_iteration *out);
+
 /* ---- launch shape ----------------------------------------------------------
  * spawn_grid: workgroups of the spawning kernel; tile: consecutive attempts a
  * workgroup takes at a time (a power of two, 256 .. 2^20; a tile never spans
  * two chunks of the table); post_grid: workgroups of the
  * death/annihilation kernel. Results never depend on these (every random
  * number is keyed by determinant and walker ordinal, every merge is an
- * integer sum). fciqmc_autotune runs iters_per_trial real iterations of every
- * active system for each candidate shape (spawn grid 2/4/8/16 x CUs, tile
- * 1024/2048/4096, then post grid 1/2/4/8 x CUs), keeps the shape with the
- * lowest kernel time per attempt (per slot for the post kernel), and leaves
- * the systems advanced by those iterations. */
+ * integer sum). fciqmc_autotune saves every active system (walker list,
+ * dynamics, statistics, iteration log), runs iters_per_trial iterations of all
+ * of them for each candidate shape (spawn grid 2/4/8/16 x CUs with tile
+ * 1024/2048/4096, then post grid 2/3/4/6/8 x CUs), keeps the shape with the
+ * lowest spawning time per attempt and annihilation time per iteration, and
+ * restores the systems: their walker lists continue exactly as if no trial
+ * had run (the projected-energy numerator may differ in its last bits, since
+ * its partial sums follow the table layout). */
 int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t post_grid);
 int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *post_grid);
 int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial);

@@ -775,7 +775,7 @@ typedef struct {
     spawn_t *in;              /* records received from every process, sender order */
     int64_t n_in, cap_in;
     /* this process's share of the last iteration's statistics */
-    int64_t attempts, merged, aborted, nw, nd, c0;
+    int64_t attempts, merged, aborted, born, nw, nd, c0;
     double num;
     /* entries of a walker list being loaded that this process owns */
     int64_t *load_idx;
@@ -797,7 +797,7 @@ struct orc_state {
     int varying;
     int64_t n_prev, n_var;
     /* last iteration's statistics */
-    int64_t nw, nd, c0, attempts, spawns, merged, aborted, tot_attempts, tot_spawns;
+    int64_t nw, nd, c0, attempts, spawns, merged, aborted, born, tot_attempts, tot_spawns;
     double num;
     /* series for the averages */
     double *s_num, *s_den, *s_shift;
@@ -1293,7 +1293,7 @@ static int proc_annihilate(orc_state *st, int q)
     /* Sort and compress (Sec. 4.1): sum signed walkers on each determinant,
      * OR the initiator flags, drop entries that cancel to zero. */
     qsort(pr->in, (size_t)pr->n_in, sizeof(spawn_t), cmp_spawn);
-    int64_t merged = 0, aborted = 0;
+    int64_t merged = 0, aborted = 0, born = 0;
     int64_t i = 0;
     while (i < pr->n_in) {
         uint64_t D = pr->in[i].det;
@@ -1322,12 +1322,14 @@ static int proc_annihilate(orc_state *st, int q)
                 return fail("oracle: population overflow");
             if (ml_insert(ml, D, (int32_t)c, hdiag_of(s, D)) < 0)
                 return -1;
+            born++;
         } else {
             aborted += c < 0 ? -c : c;
         }
     }
     pr->merged = merged;
     pr->aborted = aborted;
+    pr->born = born;
     proc_stats(st, q);
     return 0;
 }
@@ -1424,7 +1426,7 @@ static int one_iteration(orc_state *st)
         return -1;
 
     /* Statistics aggregation over processes, in process order. */
-    int64_t attempts = 0, spawns = 0, merged = 0, aborted = 0;
+    int64_t attempts = 0, spawns = 0, merged = 0, aborted = 0, born = 0;
     for (int p = 0; p < P; p++) {
         const proc_t *pr = &st->proc[p];
         attempts += pr->attempts;
@@ -1432,6 +1434,7 @@ static int one_iteration(orc_state *st)
             spawns += pr->n_out[q];
         merged += pr->merged;
         aborted += pr->aborted;
+        born += pr->born;
     }
     gather_stats(st);
     const int64_t nw = st->nw, c0 = st->c0;
@@ -1440,6 +1443,7 @@ static int one_iteration(orc_state *st)
     st->spawns = spawns;
     st->merged = merged;
     st->aborted = aborted;
+    st->born = born;
     st->tot_attempts += attempts;
     st->tot_spawns += spawns;
     st->iter++;
@@ -1489,6 +1493,7 @@ int orc_estimates(orc_state *st, orc_est *out)
     out->spawns = st->spawns;
     out->merged = st->merged;
     out->aborted = st->aborted;
+    out->born = st->born;
     out->total_attempts = st->tot_attempts;
     out->total_spawns = st->tot_spawns;
     out->n_samples = st->n_series;

@@ -57,6 +57,7 @@ typedef struct {
     double e_proj_mean, e_proj_err, shift_mean, shift_err;
     int32_t shift_varying, pad0;
     int64_t n_prev;
+    int64_t born;               /* determinants entering the main list (Sec. 4.2) */
 } orc_est;
 
 typedef struct orc_state orc_state;

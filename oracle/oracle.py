@@ -35,7 +35,8 @@ class OrcEst(C.Structure):
                [(n, C.c_double) for n in
                 ("shift", "e_ref", "p_double", "proj_num", "e_proj_inst", "e_proj_mean",
                  "e_proj_err", "shift_mean", "shift_err")] + \
-               [("shift_varying", C.c_int32), ("pad0", C.c_int32), ("n_prev", C.c_int64)]
+               [("shift_varying", C.c_int32), ("pad0", C.c_int32), ("n_prev", C.c_int64),
+                ("born", C.c_int64)]
 
 
 def lib():

@@ -33,6 +33,7 @@ constexpr uint32_t ST_SPILL_FULL = 32u;    // the spill list itself overflowed (
 struct IterRecord {
     int64_t iter;      // completed iterations after this one
     int64_t nw, nd, c0, attempts, spawns, merged, aborted;
+    int64_t born;      // determinants that entered the main list
     int64_t used;      // entries in the buckets after the iteration (occupied + the reference)
     int64_t n_var, n_prev;
     double num, shift;
@@ -46,6 +47,7 @@ struct ChunkStat {
     int64_t nw, aborted;
     uint64_t counts;
     double num;
+    int64_t born;
 };
 constexpr int CNT_SHIFT_MERGED = 21, CNT_SHIFT_ND = 42;
 constexpr int POST_WAVES = BPC;   // wavefronts of a k_post workgroup: one bucket and one
@@ -54,7 +56,7 @@ constexpr uint64_t CNT_FIELD = (1ull << 21) - 1;
 
 // One workgroup's share of a system's iteration statistics.
 struct FinPart {
-    int64_t nw, nd, merged, aborted, used, attempts;
+    int64_t nw, nd, merged, aborted, used, attempts, born;
     double num;
 };
 

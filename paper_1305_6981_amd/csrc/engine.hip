@@ -887,6 +887,7 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
     o->spawns = r.spawns;
     o->merged = r.merged;
     o->aborted = r.aborted;
+    o->born = r.born;
     o->total_attempts = S.tot_att;
     o->total_spawns = S.tot_sp;
     o->n_samples = S.e_blk.count();
@@ -1591,9 +1592,87 @@ int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *
     return 0;
 }
 
+// What an autotuning trial advances of one system, restored after the trials: the
+// walker list, the dynamics, the statistics and the per-iteration records.
+struct SysSnapshot {
+    int s = 0;
+    std::vector<uint64_t> det;
+    std::vector<int32_t> pop;
+    SysDesc desc{};
+    IterRecord last{};
+    int64_t tot_att = 0, tot_sp = 0, redos = 0, spills = 0, growth = 0, spawn_peak = 0;
+    double spawn_rate = 1.0;
+    Blocker e_blk, s_blk;
+    std::vector<IterRecord> ring;
+};
+
+int take_snapshot(fciqmc_t *h, int s, SysSnapshot &o) {
+    SysHost &S = h->sys[s];
+    Walkers w;
+    const int rc = export_walkers(h, s, w);
+    if (rc) return rc;
+    o.s = s;
+    o.det = std::move(w.det);
+    o.pop = std::move(w.pop);
+    if (!std::binary_search(o.det.begin(), o.det.end(), S.d0)) {   // the reference at 0
+        const size_t at = std::lower_bound(o.det.begin(), o.det.end(), S.d0) - o.det.begin();
+        o.det.insert(o.det.begin() + at, S.d0);
+        o.pop.insert(o.pop.begin() + at, 0);
+    }
+    o.desc = h->hdesc[s];
+    o.last = S.last;
+    o.tot_att = S.tot_att;
+    o.tot_sp = S.tot_sp;
+    o.redos = S.redos;
+    o.spills = S.spills;
+    o.growth = S.growth;
+    o.spawn_peak = S.spawn_peak;
+    o.spawn_rate = S.spawn_rate;
+    o.e_blk = S.e_blk;
+    o.s_blk = S.s_blk;
+    o.ring.assign(h->h_rec + (int64_t)s * REC_CAP, h->h_rec + (int64_t)(s + 1) * REC_CAP);
+    return 0;
+}
+
+int restore_snapshot(fciqmc_t *h, const SysSnapshot &o) {
+    const int s = o.s;
+    SysHost &S = h->sys[s];
+    SysDesc &d = h->hdesc[s];
+    d.iter = o.desc.iter;
+    d.stop_at = o.desc.iter;
+    d.shift = o.desc.shift;
+    d.varying = o.desc.varying;
+    d.n_prev = o.desc.n_prev;
+    d.n_var = o.desc.n_var;
+    const int rc = load_list(h, s, o.det, o.pop);
+    if (rc) return rc;
+    S.last = o.last;
+    S.tot_att = o.tot_att;
+    S.tot_sp = o.tot_sp;
+    S.redos = o.redos;
+    S.spills = o.spills;
+    S.growth = o.growth;
+    S.spawn_peak = o.spawn_peak;
+    S.spawn_rate = o.spawn_rate;
+    S.e_blk = o.e_blk;
+    S.s_blk = o.s_blk;
+    S.fatal = 0;
+    std::copy(o.ring.begin(), o.ring.end(), h->h_rec + (int64_t)s * REC_CAP);
+    return upload_desc(h);
+}
+
 int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
     if (!h || iters_per_trial < 1) return set_err(FCIQMC_EINVAL, "bad argument");
     int cus = fq::spawn_grid_size() / 8;
+    // The trials run on the live systems; their state is saved first and restored
+    // afterwards, so tuning leaves every trajectory where it was.
+    std::vector<SysSnapshot> snaps;
+    for (int s = 0; s < h->max_sys; ++s) {
+        if (!h->sys[s].active || h->sys[s].fatal) continue;
+        snaps.emplace_back();
+        const int rc = take_snapshot(h, s, snaps.back());
+        if (rc) return rc;
+    }
     const bool was = h->profiling;
     h->profiling = true;
     auto trial = [&](int sg, int tl, int pg, double &spawn_ns, double &post_ns) -> int {
@@ -1609,18 +1688,16 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
         std::vector<int64_t> n(h->max_sys, iters_per_trial);
         int rc = iterate_each(h, n);
         if (rc) return rc;
-        int64_t a1 = 0, slots = 0;
-        for (auto &S : h->sys) {
-            a1 += S.active ? S.tot_att : 0;
-            slots += S.active ? S.cap : 0;
-        }
+        int64_t a1 = 0;
+        for (auto &S : h->sys) a1 += S.active ? S.tot_att : 0;
         spawn_ns = h->kms[2] * 1e6 / (double)std::max<int64_t>(a1 - a0, 1);
-        post_ns = h->kms[3] * 1e6 / (double)std::max<int64_t>(slots * iters_per_trial, 1);
+        post_ns = h->kms[3] * 1e6 / (double)iters_per_trial;   // per iteration
         return 0;
     };
     int best_sg = h->spawn_grid, best_tl = h->tile, best_pg = h->post_grid;
     double best_s = 1e300, best_p = 1e300;
-    const int sgs[4] = {2, 4, 8, 16}, tls[3] = {1024, 2048, 4096}, pgs[4] = {1, 2, 4, 8};
+    // (k_post is compiled for four resident workgroups per CU)
+    const int sgs[4] = {2, 4, 8, 16}, tls[3] = {1024, 2048, 4096}, pgs[5] = {2, 3, 4, 6, 8};
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 3; ++j) {
             double sn, pn;
@@ -1635,7 +1712,7 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
                 best_tl = tls[j];
             }
         }
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
         double sn, pn;
         int rc = trial(best_sg, best_tl, pgs[i] * cus, sn, pn);
         if (rc) {
@@ -1656,7 +1733,39 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
         h->kcount[k] = 0;
     }
     drop_graphs(h);
+    for (const SysSnapshot &o : snaps) {
+        const int rc = restore_snapshot(h, o);
+        if (rc) return rc;
+    }
     return 0;
+}
+
+int64_t fciqmc_history(fciqmc_t *h, int32_t slot, int64_t first, int64_t n, fciqmc_iteration *out) {
+    if (!h || slot < 0 || slot >= h->max_sys || n < 0 || (n > 0 && !out))
+        return set_err(FCIQMC_EINVAL, "bad argument");
+    if (!h->sys[slot].active) return set_err(FCIQMC_ESTATE, "slot is not active");
+    const int64_t cur = h->hdesc[slot].iter;
+    const int64_t lo = std::max<int64_t>(1, cur - REC_CAP + 1);
+    if (first < lo || first + n - 1 > cur) return set_err(FCIQMC_EINVAL, "iterations not in the log");
+    for (int64_t i = 0; i < n; ++i) {
+        const IterRecord &r = h->h_rec[(int64_t)slot * REC_CAP + (first + i) % REC_CAP];
+        fciqmc_iteration &o = out[i];
+        o.iteration = r.iter;
+        o.n_walkers = r.nw;
+        o.n_dets = r.nd;
+        o.ref_pop = r.c0;
+        o.attempts = r.attempts;
+        o.spawns = r.spawns;
+        o.merged = r.merged;
+        o.aborted = r.aborted;
+        o.born = r.born;
+        o.entries = r.used;
+        o.proj_num = r.num;
+        o.shift = r.shift;
+        o.shift_varying = r.varying;
+        o.status = r.status;
+    }
+    return n;
 }
 
 int fciqmc_blocking(const double *num, const double *den, int64_t n, double *mean, double *err) {

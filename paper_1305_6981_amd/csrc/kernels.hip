@@ -946,14 +946,18 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         if (t < NCLASS) s_cm[t] = d.cmask[t];   // ordered before use by the barrier below
         // Stage the chunk's entries that hold walkers (its four buckets, one per
         // wavefront, four entries per lane), compacted, with the inclusive prefix sum
-        // of |C|. (A bucket's BQ entries are always allocated: entries past its count
-        // are read and ignored.)
+        // of |C|. Only the lanes over a bucket's entries read (the entries are packed
+        // at the front of the bucket).
         const int64_t lb = (int64_t)a.chunk_local[c] * BPC + wid;
         const int64_t base = lb * BQ + 4 * lane;
         const int n_b = d.bcnt[lb] - 4 * lane;
-        const int4 pv = gload_i4(d.pop + base);
-        const ulonglong2 k01 = gload_u2(d.key + base);
-        const ulonglong2 k23 = gload_u2(d.key + base + 2);
+        int4 pv = make_int4(0, 0, 0, 0);
+        ulonglong2 k01 = make_ulonglong2(0ull, 0ull), k23 = make_ulonglong2(0ull, 0ull);
+        if (n_b > 0) {
+            pv = gload_i4(d.pop + base);
+            k01 = gload_u2(d.key + base);
+            k23 = gload_u2(d.key + base + 2);
+        }
         const int32_t pa[4] = {0 < n_b ? pv.x : 0, 1 < n_b ? pv.y : 0, 2 < n_b ? pv.z : 0,
                                3 < n_b ? pv.w : 0};
         const uint64_t ka[4] = {k01.x, k01.y, k23.x, k23.y};
@@ -1436,6 +1440,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             uint64_t cnt = 0;                 // entries | merged targets << 21 | occupied << 42
             double num = 0.0;
             unsigned long long nwb = 0;       // sum |C| over the bucket's entries after the iteration
+            int64_t born = 0;                 // new determinants (uniform)
             if (live) {
                 const SysDesc &d = desc[s];
                 uint32_t *status = &a.status[s];
@@ -1611,6 +1616,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 int32_t npv[4] = {0, 0, 0, 0};
                 uint32_t keepm = 0u;
                 uint32_t nearm = 0u;   // bit u: entry u contributes to the projected energy
+                int reborn = 0;        // entries emptied by death and re-entered by initiator
+                                       // spawns (new determinants kept in place)
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (e0 + u >= n) continue;
@@ -1624,6 +1631,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         np = pd + sp;
                     } else if (sp != 0 && ((flv >> u) & 1u)) {
                         np = sp;
+                        ++reborn;
                     } else {
                         np = 0;
                         if (sp != 0) aborted += sp < 0 ? -sp : sp;
@@ -1751,6 +1759,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     d.bcnt[lb] = np_;
                     cnt += (uint64_t)np_;
                 }
+                born = K + wave_total8(reborn);
                 // Projected-energy numerator (Eq. ProjE): the occupied determinants within a
                 // double excitation of the reference, taken last, when few values are live.
 #pragma unroll
@@ -1776,7 +1785,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             num = wave_sum(num);
             nwb = wave_sum(nwb);
             if (lane == 0) {
-                a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num};
+                a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num, born};
                 // walkers that spawn next iteration: none if the system stops after this one
                 if (s_cnext[ci] && nwb) atomicAdd(&s_cnws[ci], nwb);
                 if (atomicAdd(&s_cdone[ci], 1) == POST_WAVES - 1) {
@@ -1808,7 +1817,7 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
     const int64_t per = (d.nchunks + FIN_BLOCKS - 1) / FIN_BLOCKS;
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < d.nchunks ? lo + per : d.nchunks;
-    int64_t nw = 0, nd = 0, merged = 0, aborted = 0, att = 0, used = 0;
+    int64_t nw = 0, nd = 0, merged = 0, aborted = 0, att = 0, used = 0, born = 0;
     double num = 0.0;
     for (int64_t i = lo + t; i < hi; i += 256) {
         for (int w = 0; w < POST_WAVES; ++w) {
@@ -1818,6 +1827,7 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
             nd += (int64_t)(cs.counts >> CNT_SHIFT_ND);
             nw += cs.nw;
             aborted += cs.aborted;
+            born += cs.born;
             num = num + cs.num;
         }
         att += (int64_t)sums(a, cur_half(a))[d.gchunk0 + i];
@@ -1829,6 +1839,7 @@ __global__ __launch_bounds__(256) void k_reduce(EngineArgs a) {
     p.aborted = block_sum((long long)aborted, shi);
     p.attempts = block_sum((long long)att, shi);
     p.used = block_sum((long long)used, shi);
+    p.born = block_sum((long long)born, shi);
     p.num = block_sum(num, shd);
     if (t == 0) a.fin_part[(int64_t)s * FIN_BLOCKS + blockIdx.x] = p;
 }
@@ -1851,6 +1862,7 @@ __global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
     const int64_t aborted = wave_sum((long long)p.aborted);
     const int64_t att = wave_sum((long long)p.attempts);
     const int64_t used = wave_sum((long long)p.used);
+    const int64_t born = wave_sum((long long)p.born);
     const double num = wave_sum(p.num);
     if (t == 0) {
         const int64_t done = d.iter + 1;
@@ -1879,6 +1891,7 @@ __global__ __launch_bounds__(64) void k_finalize(EngineArgs a) {
         r.spawns = (int64_t)a.spawns[s];
         r.merged = merged;
         r.aborted = aborted;
+        r.born = born;
         r.used = used;
         r.n_var = d.n_var;
         r.n_prev = d.n_prev;

@@ -52,7 +52,15 @@ class Estimates(C.Structure):
                [("shift_varying", C.c_int32), ("status", C.c_int32), ("redos", C.c_int64),
                 ("spills", C.c_int64)] + \
                [(n, C.c_double) for n in ("ms_spawn", "ms_death", "ms_annihilate",
-                                          "ms_estimators")]
+                                          "ms_estimators")] + [("born", C.c_int64)]
+
+
+class Iteration(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in
+                ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
+                 "aborted", "born", "entries")] + \
+               [("proj_num", C.c_double), ("shift", C.c_double),
+                ("shift_varying", C.c_int32), ("status", C.c_int32)]
 
 
 EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
@@ -63,7 +71,7 @@ EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
             "fciqmc_batch_slot_walkers", "fciqmc_footprint_bytes", "fciqmc_batch_active",
             "fciqmc_set_profiling", "fciqmc_kernel_times", "fciqmc_set_launch",
             "fciqmc_get_launch", "fciqmc_autotune", "fciqmc_blocking",
-            "fciqmc_set_test_options", "fciqmc_walkers_noalloc"]
+            "fciqmc_set_test_options", "fciqmc_walkers_noalloc", "fciqmc_history"]
 
 
 def lib():
@@ -103,6 +111,7 @@ def lib():
                                 C.c_int),
             "fciqmc_set_test_options": ([vp, i32, i64, i64], C.c_int),
             "fciqmc_walkers_noalloc": ([vp, vp, vp, vp, i64], i64),
+            "fciqmc_history": ([vp, i32, i64, i64, C.POINTER(Iteration)], i64),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -306,6 +315,13 @@ def fciqmc_get_launch(handle):
     a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
     _check(lib().fciqmc_get_launch(handle, C.byref(a), C.byref(b), C.byref(c)))
     return a.value, b.value, c.value
+
+
+def fciqmc_history(handle, slot, first, n):
+    """Records of iterations first .. first + n - 1 of a slot, as a list of dicts."""
+    out = (Iteration * max(n, 1))()
+    _check(lib().fciqmc_history(handle, slot, first, n, out))
+    return [{f[0]: getattr(out[i], f[0]) for f in Iteration._fields_} for i in range(n)]
 
 
 def fciqmc_autotune(handle, iters_per_trial=2):

@@ -250,8 +250,11 @@ def batch_workload(scale: float = 1.0, n_hubbard: int = 32, n_synth: int = 32):
 
 
 def serve_requests(n: int = 200, rate: float = 20.0, seed: int = 5, scale: float = 1.0):
-    """Poisson request stream of solves shaped like the Hubbard 8-16 site rings
-    and the synthetic 10e/20o .. 24e/30o molecules. Returns a list of
+    """Poisson request stream of solves of the three workload shapes: the 8-site
+    Hubbard ring (U/t in [2, 8]), the synthetic 10e/20o molecule and the 24e/30o
+    band molecule, drawn with equal probability. Walker targets are log-uniform
+    in [1e4, 1e6], and in [1e6, 1e7] for the 24e/30o shape (shift damping 0.5
+    there, 0.05 otherwise). Returns a list of
     (arrival_time_s, Hamiltonian, Params)."""
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -259,10 +262,10 @@ def serve_requests(n: int = 200, rate: float = 20.0, seed: int = 5, scale: float
     for i in range(n):
         t += float(rng.exponential(1.0 / rate))
         kind = int(rng.integers(0, 3))
-        target = int(round(10 ** rng.uniform(4.0, 6.0) * scale))
+        lo, hi = (6.0, 7.0) if kind == 2 else (4.0, 6.0)
+        target = int(round(10 ** rng.uniform(lo, hi) * scale))
         if kind == 0:
-            L = int(rng.choice([8, 10, 12, 14, 16]))
-            ham = hubbard_ring(L, float(rng.uniform(2.0, 8.0)))
+            ham = hubbard_ring(8, float(rng.uniform(2.0, 8.0)))
             prm = Params(tau=0.01, initiator_threshold=0, target_walkers=max(target, 20),
                          seed=1000 + i, shift_update_every=1)
         elif kind == 1:
@@ -270,8 +273,11 @@ def serve_requests(n: int = 200, rate: float = 20.0, seed: int = 5, scale: float
             prm = Params(tau=1e-3, initiator_threshold=3, target_walkers=max(target, 20),
                          seed=1000 + i)
         else:
+            # the dominant eigenvalue of this shape's initiator dynamics lies far below
+            # E0: a strongly damped shift (gap x 0.5 per update) keeps the population
+            # near its target instead of letting it grow many-fold first
             ham = synthetic_molecule(30, 12, 12, seed=300 + i, orb_energy=band_energies(30))
             prm = Params(tau=5e-4, initiator_threshold=3, target_walkers=max(target, 20),
-                         seed=1000 + i)
+                         seed=1000 + i, shift_damping=0.5)
         out.append((t, ham, prm))
     return out

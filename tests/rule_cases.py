@@ -78,11 +78,12 @@ def check_threshold_is_strict(make):
         assert e["spawns"] > 0
         assert det(HUB) not in w
         assert e["aborted"] == e["spawns"]          # one walker per spawn, all onto the hub
+        assert e["born"] == 0
         assert w[det(P1)] == sign * N_A and w[det(REF)] == 10
         w, e = one_step(make, ham, [(P1, sign * (N_A + 1)), (REF, 10)])
         assert e["spawns"] > 0 and e["aborted"] == 0
         assert w[det(HUB)] == sign * e["spawns"]     # spawned sign: -sign(C) sign(h) = sign(C)
-        assert e["merged"] == 1
+        assert e["merged"] == 1 and e["born"] == 1
 
 
 def _alone(make, ham, leaf, pop):
@@ -101,7 +102,7 @@ def check_flags_are_ored(make):
     c3 = _alone(make, ham, P3, N_A + 1)
     w, e = one_step(make, ham, [(P1, N_A), (P2, N_A), (P3, N_A + 1), (REF, 10)])
     assert e["spawns"] == c1 + c2 + c3
-    assert e["aborted"] == 0
+    assert e["aborted"] == 0 and e["born"] == 1
     assert w[det(HUB)] == c1 + c2 + c3
     # signed sum: the second non-initiator parent negative
     w, e = one_step(make, ham, [(P1, N_A), (P2, -N_A), (P3, N_A + 1), (REF, 10)])
@@ -110,7 +111,7 @@ def check_flags_are_ored(make):
     # no initiator parent: the whole merged record is discarded
     w, e = one_step(make, ham, [(P1, N_A), (P2, N_A), (REF, 10)])
     assert det(HUB) not in w
-    assert e["aborted"] == c1 + c2
+    assert e["aborted"] == c1 + c2 and e["born"] == 0
 
 
 def check_occupancy_after_death(make):
@@ -126,7 +127,7 @@ def check_occupancy_after_death(make):
     assert w[det(P1)] in (N_A, N_A + 1)       # plus the hub's own attempt, if it picked P1
     ci = _alone(make, ham, P1, N_A + 1)
     w, e = one_step(make, ham, [(P1, N_A + 1), (HUB, 1), (REF, 10)])
-    assert e["aborted"] == 0
+    assert e["aborted"] == 0 and e["born"] == 1      # emptied by death, then re-entered
     assert w[det(HUB)] == ci
 
 

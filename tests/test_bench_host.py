@@ -1,5 +1,6 @@
 """Host-side logic of bench.py that needs no GPU: the one-GPU guard, the
-algorithmic byte counts and the parsing of rocprofv3 counter CSV files."""
+algorithmic byte counts, the averaging start and the parsing of rocprofv3
+counter CSV files."""
 import json
 import os
 import subprocess
@@ -20,14 +21,25 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes():
-    rec = {"n_dets": 1000, "spawns": 50, "merged": 40}
-    b = bench.bytes_per_kernel(rec, 4096)
-    assert b["k_chunk_sum"] == 4.0 * 4096
-    # every slot: key 8 + accumulator 8 + population 4 + H_DD 8; population written per
-    # occupied determinant, accumulator cleared and H_DD or list entry per merged target
-    assert b["k_post"] == 28.0 * 4096 + 4.0 * 1000 + 16.0 * 40
-    # staging key + population per slot; per spawn a key probe and an accumulator update
-    assert b["k_spawn"] == 12.0 * 4096 + 24.0 * 50
+    # two iterations: the main list read before each is the previous iteration's
+    recs = [{"n_dets": 1100, "spawns": 50, "merged": 40, "born": 30},
+            {"n_dets": 1200, "spawns": 60, "merged": 45, "born": 35}]
+    group, post = bench.method_bytes(recs, 1000)
+    # per occupied determinant 21 B read + 4 B written; per spawn record 16 B read;
+    # per merged target 16 B; per new determinant 20 B
+    p1 = 25.0 * 1000 + 16.0 * 50 + 16.0 * 40 + 20.0 * 30
+    p2 = 25.0 * 1100 + 16.0 * 60 + 16.0 * 45 + 20.0 * 35
+    assert post == (p1 + p2) / 2
+    # the partition by bucket adds 32 B per spawn record (read + write)
+    assert group == (p1 + 32.0 * 50 + p2 + 32.0 * 60) / 2
+
+
+def test_avg_start_is_one_unit_of_imaginary_time():
+    class P:
+        tau = 5e-4
+    assert bench.avg_start_for(P) == 2000
+    P.tau = 0.01
+    assert bench.avg_start_for(P) == 200
 
 
 def test_counter_csv_means(tmp_path):

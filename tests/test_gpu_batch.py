@@ -77,3 +77,49 @@ def test_continuous_batching_admit_retire():
     with pytest.raises(F.FciqmcError):
         F.fciqmc_batch_admit(h, *sy[0])      # no free slot
     F.fciqmc_free(h)
+
+
+def test_autotune_leaves_every_trajectory_unchanged():
+    """Autotuning runs its trials on the live systems and restores them: the walker
+    lists and the shift then continue exactly as in an untuned run (and the
+    oracle's)."""
+    sy = _systems()
+    print("[gpu] autotune on a batch handle", flush=True)
+    h = F.fciqmc_batch_create(len(sy), [a for a, _ in sy], [b for _, b in sy], F.current_stream())
+    F.fciqmc_batch_iterate(h, 25)
+    before = [F.fciqmc_batch_slot_estimators(h, s) for s in range(len(sy))]
+    F.fciqmc_autotune(h, 2)
+    for s in range(len(sy)):
+        e = F.fciqmc_batch_slot_estimators(h, s)
+        for k in ("iteration", "n_walkers", "n_dets", "total_attempts", "total_spawns", "n_samples"):
+            assert e[k] == before[s][k], (s, k)
+        assert e["shift"] == before[s]["shift"]
+    F.fciqmc_batch_iterate(h, 20)
+    for slot, (ham, prm) in enumerate(sy):
+        d, p, _ = F.fciqmc_batch_slot_walkers(h, slot)
+        do, po, eo = _oracle_lists(ham, prm, 45)
+        assert np.array_equal(d, do) and np.array_equal(p, po), slot
+        e = F.fciqmc_batch_slot_estimators(h, slot)
+        assert e["shift"] == eo["shift"] and e["n_walkers"] == eo["n_walkers"]
+    F.fciqmc_free(h)
+
+
+def test_history_matches_the_estimates_of_each_iteration():
+    ham, prm = _systems()[2]
+    print("[gpu] iteration log", flush=True)
+    sv = F.Solver(ham, prm, F.current_stream())
+    seen = []
+    for _ in range(12):
+        sv.iterate(1)
+        seen.append(sv.estimates())
+    sv.iterate(30)
+    log = F.fciqmc_history(sv.h, 0, 1, 12)
+    for r, e in zip(log, seen):
+        assert r["iteration"] == e["iteration"]
+        for k in ("n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged", "aborted",
+                  "born"):
+            assert r[k] == e[k], k
+        assert r["shift"] == e["shift"] and r["proj_num"] == e["proj_num"]
+    with pytest.raises(F.FciqmcError):
+        F.fciqmc_history(sv.h, 0, 40, 5)     # beyond the last iteration
+    sv.close()

@@ -31,7 +31,7 @@ def _same_lists(gpu, ref, tag):
 
 def _same_estimates(eg, eo, tag):
     for k in ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
-              "aborted", "total_attempts", "total_spawns", "shift_varying", "n_samples"):
+              "aborted", "born", "total_attempts", "total_spawns", "shift_varying", "n_samples"):
         assert eg[k] == eo[k], (tag, k, eg[k], eo[k])
     assert eg["shift"] == eo["shift"], (tag, eg["shift"], eo["shift"])
     assert eg["e_ref"] == eo["e_ref"] and eg["p_double"] == eo["p_double"]

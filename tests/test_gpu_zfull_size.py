@@ -56,7 +56,7 @@ def test_full_size_iteration_matches_oracle():
 
     eg, eo = sv.estimates(), ref.estimates()
     for k in ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
-              "aborted", "shift_varying", "n_prev", "n_var"):
+              "aborted", "born", "shift_varying", "n_prev", "n_var"):
         assert eg[k] == eo[k], (k, eg[k], eo[k])
     assert eg["shift"] == eo["shift"]
     assert abs(eg["proj_num"] - eo["proj_num"]) <= 1e-10 * abs(eo["proj_num"])

@@ -14,7 +14,7 @@ from oracle import oracle as O
 from paper_1305_6981_amd import systems as S
 
 INT_KEYS = ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
-            "aborted", "total_attempts", "total_spawns", "n_samples", "n_var", "n_prev",
+            "aborted", "born", "total_attempts", "total_spawns", "n_samples", "n_var", "n_prev",
             "shift_varying")
 
 
