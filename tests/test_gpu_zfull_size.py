@@ -1,12 +1,17 @@
-"""Parity at the benchmark's full size and launch shape.
+"""Parity at full size, in the launch configuration the benchmark times.
 
-The 24e/30o band system (initiator n_a = 3, tau = 5e-4) is grown on the GPU to
-1e8 walkers exactly as bench.py grows it, with the default launch shape. From
-that snapshot the GPU and the oracle each run one iteration; the oracle spreads
-the determinants over one virtual process per host thread (Sec. 4.1; the
-result does not depend on the process count, see test_oracle_processes.py).
-Walker lists must be bit-identical, the integer statistics and the shift
-identical, and the projected-energy numerator equal to 1e-10 relative."""
+Config 3: the 24e/30o band system (initiator n_a = 3, tau = 5e-4) is grown on the
+GPU to 1e8 walkers and warmed up exactly as bench.py does it (shift set to the
+projected-energy estimate, damping 0.5, 300 iterations), with the default launch
+shape. Config 2: the 10e/20o system (n_a = 3, tau = 1e-3) is grown to 1e7
+walkers. From each snapshot the GPU runs three iterations in one call (one graph
+launch plus the sampled last iteration, so the chunk sums that the annihilation
+pass writes for the next iteration are used twice) and the oracle runs the same
+three iterations with the determinants spread over one virtual process per host
+thread (Sec. 4.1; the result does not depend on the process count, see
+test_oracle_processes.py). Walker lists must be bit-identical, the integer
+statistics and the shift identical, and the projected-energy numerator equal
+to 1e-10 relative."""
 import os
 import time
 
@@ -19,8 +24,57 @@ from paper_1305_6981_amd import systems as S
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
+K = 3
 
-def test_full_size_iteration_matches_oracle():
+
+def _grow(sv, target, limit):
+    while True:
+        e = sv.estimates()
+        if e["n_walkers"] >= target:
+            return e
+        sv.iterate(20 if e["n_walkers"] * 4 < target else 2)
+        assert e["iteration"] < limit, "growth stage did not reach the walker target"
+
+
+def _compare_k_iterations(ham, prm, sv, tag):
+    e = sv.estimates()
+    det, pop, _ = sv.walkers()
+    print(f"[gpu] {tag}: snapshot of {e['n_walkers']} walkers on {len(det)} determinants at "
+          f"iteration {e['iteration']}", flush=True)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    ref = O.Oracle(ham, prm, n_procs=threads, n_threads=threads)
+    ref.load_walkers(det, pop, iteration=e["iteration"], shift=e["shift"], n_prev=e["n_prev"],
+                     varying=e["shift_varying"], n_var=e["n_var"])
+    del det, pop
+    t1 = time.perf_counter()
+    sv.iterate(K)
+    hist = F.fciqmc_history(sv.h, 0, e["iteration"] + 1, K)
+    for k in range(K):
+        ref.iterate(1)
+        eo = ref.estimates()
+        r = hist[k]
+        for f in ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
+                  "aborted", "born"):
+            assert r[f] == eo[f], (tag, k, f, r[f], eo[f])
+        assert r["shift"] == eo["shift"], (tag, k)
+        assert abs(r["proj_num"] - eo["proj_num"]) <= 1e-10 * abs(eo["proj_num"]), (tag, k)
+        print(f"[gpu] {tag}: iteration {r['iteration']} statistics identical "
+              f"({r['spawns']} spawns, {r['born']} new determinants)", flush=True)
+    print(f"[gpu] {tag}: oracle {K} iterations on {threads} threads in "
+          f"{time.perf_counter() - t1:.1f} s", flush=True)
+    eg = sv.estimates()
+    assert eg["shift_varying"] == eo["shift_varying"] and eg["n_prev"] == eo["n_prev"]
+    dg, pg, fg = sv.walkers()
+    do, po, fo = ref.walkers()
+    assert len(dg) == len(do)
+    assert np.array_equal(dg, do)
+    assert np.array_equal(pg, po)
+    assert np.array_equal(fg, fo)
+    print(f"[gpu] {tag}: {len(dg)} determinants identical after {K} iterations", flush=True)
+    ref.close()
+
+
+def test_full_size_config3_matches_oracle():
     import torch
     assert torch.cuda.is_available()
     ham, prm, _ = S.workload("synth24e30o")
@@ -28,45 +82,28 @@ def test_full_size_iteration_matches_oracle():
     prm.target_walkers = target
     prm.initial_walkers = 20000
     prm.initial_shift = 40.0
+    prm.shift_damping = 0.5
     t0 = time.perf_counter()
     sv = F.Solver(ham, prm, F.current_stream())
-    while True:
-        e = sv.estimates()
-        if e["n_walkers"] >= target:
-            break
-        sv.iterate(20 if e["n_walkers"] * 4 < target else 2)
-        assert e["iteration"] < 2000, "growth stage did not reach the walker target"
+    e = _grow(sv, target, 2000)
     sv.set_shift(e["proj_num"] / e["ref_pop"], 1)
-    e = sv.estimates()
-    det, pop, _ = sv.walkers()
-    print(f"[gpu] full size: {e['n_walkers']} walkers on {len(det)} determinants after "
-          f"{e['iteration']} iterations ({time.perf_counter() - t0:.1f} s)", flush=True)
-    assert e["n_walkers"] >= target and len(det) > 10_000_000
-
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    ref = O.Oracle(ham, prm, n_procs=threads, n_threads=threads)
-    ref.load_walkers(det, pop, iteration=e["iteration"], shift=e["shift"], n_prev=e["n_prev"],
-                     varying=e["shift_varying"], n_var=e["n_var"])
-    del det, pop
-    t1 = time.perf_counter()
-    ref.iterate(1)
-    print(f"[gpu] oracle iteration on {threads} threads: {time.perf_counter() - t1:.1f} s",
-          flush=True)
-    sv.iterate(1)
-
-    eg, eo = sv.estimates(), ref.estimates()
-    for k in ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
-              "aborted", "born", "shift_varying", "n_prev", "n_var"):
-        assert eg[k] == eo[k], (k, eg[k], eo[k])
-    assert eg["shift"] == eo["shift"]
-    assert abs(eg["proj_num"] - eo["proj_num"]) <= 1e-10 * abs(eo["proj_num"])
-    dg, pg, fg = sv.walkers()
-    do, po, fo = ref.walkers()
-    assert len(dg) == len(do)
-    assert np.array_equal(dg, do)
-    assert np.array_equal(pg, po)
-    assert np.array_equal(fg, fo)
-    print(f"[gpu] full size: {len(dg)} determinants identical; total {time.perf_counter() - t0:.1f} s",
-          flush=True)
+    sv.iterate(300)
+    print(f"[gpu] config 3 grown and warmed up in {time.perf_counter() - t0:.1f} s", flush=True)
+    assert sv.estimates()["n_walkers"] >= target
+    _compare_k_iterations(ham, prm, sv, "config 3")
     sv.close()
-    ref.close()
+
+
+def test_full_size_config2_matches_oracle():
+    ham, prm, _ = S.workload("synth10e20o")
+    prm.initial_walkers = 10000
+    prm.initial_shift = 5.0
+    t0 = time.perf_counter()
+    sv = F.Solver(ham, prm, F.current_stream())
+    e = _grow(sv, prm.target_walkers, 20000)
+    sv.set_shift(e["proj_num"] / e["ref_pop"], 1)
+    sv.iterate(20)
+    print(f"[gpu] config 2 grown in {time.perf_counter() - t0:.1f} s", flush=True)
+    assert sv.estimates()["n_walkers"] >= 0.5 * prm.target_walkers
+    _compare_k_iterations(ham, prm, sv, "config 2")
+    sv.close()
