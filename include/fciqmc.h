@@ -80,9 +80,12 @@ typedef struct {
                                    reference always is); 0 gives plain FCIQMC */
     int64_t target_walkers;     /* the shift starts to vary once N_w >= target */
     int64_t initial_walkers;    /* walkers placed on the reference at start (0: 10) */
-    int64_t det_capacity;       /* initial main-table slots per buffer (0: automatic); the
-                                   table grows by itself, results do not depend on it */
-    int64_t spawn_capacity;     /* reserved (spawns accumulate in the main table) */
+    int64_t det_capacity;       /* initial main-list capacity in entries (0: automatic; rounded
+                                   up to whole chunks of 1024); the list is re-bucketed as it
+                                   grows, and results do not depend on it */
+    int64_t spawn_capacity;     /* initial capacity of the handle's spawn-record buffer in
+                                   records (0: automatic); it grows by itself (an iteration
+                                   that overflows it is re-run bit-exactly) */
     uint64_t seed;              /* Philox key */
     int32_t avg_start;          /* iterations after the shift starts varying before samples
                                    enter the averages */
@@ -104,10 +107,10 @@ typedef struct {
     int64_t n_samples;          /* iterations in the averages */
     int64_t n_var;              /* iteration at which the shift started to vary */
     int64_t n_prev;             /* N_w at the last shift update */
-    int64_t table_slots;        /* slots per main-table buffer (layout only) */
-    int64_t table_used;         /* slots holding a key, occupied or vacated, after the last
-                                   iteration (layout only; the table is compacted or grown
-                                   before this passes 70 % of table_slots) */
+    int64_t table_slots;        /* main-list capacity in entries: buckets x 256 (layout only) */
+    int64_t table_used;         /* main-list entries after the last iteration: the occupied
+                                   determinants and the reference (layout only; the list is
+                                   re-bucketed before the mean bucket passes 5/8 full) */
     double shift;               /* S, relative to E0 */
     double e_ref;               /* E0 = H_00 */
     double p_double;
@@ -146,33 +149,47 @@ typedef struct {
     int32_t shift_varying, status;
 } fciqmc_iteration;
 
-/* Create a handle holding one system, place initial_walkers on the reference.
+/* Create a handle holding one system and place initial_walkers on the
+ * reference D0, whose diagonal element E0 = H_00 is the energy origin of the
+ * shift (Sec. 2). The integrals are copied to the device with the pair and
+ * single-excitation term tables derived from them (Sec. 5).
  * hip_stream: a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream),
  * or NULL. Errors: EINVAL, ENOMEM, EDEVICE. */
 int fciqmc_init(const fciqmc_hamiltonian *ham, const fciqmc_params *prm, void *hip_stream,
                 fciqmc_t **out);
 
 /* Advance every active system of the handle by n_iterations (>= 0) full
- * iterations (spawn, death, annihilation, estimators, shift), in graph-captured
- * launches of up to 64 iterations. Tables grow as needed; an iteration that
- * overflows a table is re-executed bit-exactly after the growth.
+ * iterations: spawning from every walker with an excitation drawn by the
+ * generator of Sec. 5 and accepted with probability tau |H_ij| / P_gen
+ * (Sec. 2, Eq. pspawn); death/cloning of every determinant (Eq. pdeath);
+ * merging of the spawned walkers per child (Sec. 4.1) and annihilation against
+ * the main list with the initiator rule for unoccupied children (Sec. 4.2);
+ * the estimators (Eq. ProjE) and the shift update (Sec. 2). Iterations run in
+ * graph-captured launches of up to 64; the main list is re-bucketed as it
+ * grows, and an iteration that overflows the spawn-record buffer is re-run
+ * bit-exactly after the buffer grows.
  * Errors: EINVAL, EDEVICE, ECAPACITY, EOVERFLOW. */
 int fciqmc_iterate(fciqmc_t *h, int32_t n_iterations);
 
-/* Estimators of system 0 of the handle. */
+/* Estimators of system 0 of the handle: N_w, N_d, C_0 and the projected-energy
+ * numerator of the last iteration (Eq. ProjE), the shift and its update state
+ * (Sec. 2), and the averages of E_proj and of the shift with blocking error
+ * bars kept online (the blocking of correlated ratios cited in Sec. 7). */
 int fciqmc_estimators(fciqmc_t *h, fciqmc_estimates *out);
 
 /* Release everything. NULL-safe. */
 int fciqmc_free(fciqmc_t *h);
 
-/* Copy the occupied determinants of system 0, sorted by determinant, into the
+/* Copy the main list of system 0 (Sec. 4.2) -- its occupied determinants as
+ * bit strings (Sec. 3), sorted, with their signed populations -- into the
  * caller's host arrays (each of length cap; any may be NULL). flags[i] is 1
- * when the determinant is an initiator for the next iteration. Returns the
- * number of occupied determinants (which may exceed cap: then only cap are
- * written), or a negative error code. */
+ * when the determinant is an initiator for the next iteration (|C| > n_a, or
+ * the reference; Sec. 4.2). Returns the number of occupied determinants
+ * (which may exceed cap: then only cap are written), or a negative error code. */
 int64_t fciqmc_walkers(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap);
 
-/* Replace the walker list of system 0 (checkpoint restart). Entries with
+/* Replace the main list of system 0 (Sec. 4.2; determinants as bit strings,
+ * Sec. 3) for a checkpoint restart. Entries with
  * pop == 0 are ignored; the reference is kept in the list even when absent.
  * iteration is the number of completed iterations, shift is S relative to E0,
  * varying / n_var / n_prev restore the shift-update state. The averages are
@@ -181,26 +198,29 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
                         int64_t iteration, double shift, int64_t n_prev, int32_t varying,
                         int64_t n_var);
 
-/* Set the shift of system 0 and start (varying = 1) or stop its variation;
- * when started, N_prev is set to the current N_w and n_var to the current
- * iteration. Used to end a growth stage run at a raised shift. */
+/* Set the shift S of system 0 (Sec. 2; relative to E0) and start (varying = 1)
+ * or stop its variation; when started, N_prev is set to the current N_w and
+ * n_var to the current iteration. Used to end a growth stage run at a raised
+ * shift. */
 int fciqmc_set_shift(fciqmc_t *h, double shift, int32_t varying);
 
-/* Grow the main table of every active system to at least `slots` slots
- * (rounded up to a multiple of 4096) now, rather than when the table fills;
- * the rehash drops vacated slots. A table already that large is left alone.
- * Results never depend on table sizes. Errors: EINVAL (slots < 0), ECAPACITY
- * (the device cannot hold the larger table; the old one stays). */
+/* Re-bucket the main list (Sec. 4.2) of every active system into at least
+ * `slots` entries of capacity (rounded up to a multiple of 4096) now, rather
+ * than when its buckets fill. A list already that large is left alone.
+ * Results never depend on the capacity. Errors: EINVAL (slots < 0),
+ * ECAPACITY (the device cannot hold the larger list; the old one stays). */
 int fciqmc_reserve(fciqmc_t *h, int64_t slots);
 
 /* Thread-local message of the last failure ("" when none). */
 const char *fciqmc_last_error(void);
 
 /* ---- batching and serving: many independent systems in one handle -------
- * The systems of a batch advance together: every iteration of every system
- * is one pass of the same kernels over a descriptor table, so one launch
- * serves all of them, and each system's walker list is bit-identical to the
- * list it would have alone. Slots are numbered 0 .. max_slots-1. */
+ * Not in the paper (its parallelism is one system over many processes); these
+ * calls run many independent systems at once. The systems of a batch advance
+ * together: every iteration of every system is one pass of the same kernels
+ * over a descriptor table, so one launch serves all of them, and each
+ * system's walker list is bit-identical to the list it would have alone.
+ * Slots are numbered 0 .. max_slots-1. */
 
 /* Create a handle with room for max_slots systems and admit n of them
  * (hams[i], prms[i] -> slot i). Errors: EINVAL, ENOMEM, EDEVICE. */
@@ -216,16 +236,18 @@ int fciqmc_batch_iterate(fciqmc_t *h, int32_t n_iterations);
 int fciqmc_batch_iterate_each(fciqmc_t *h, const int32_t *n_iter);
 
 /* Admit one system into a free slot while others may be mid-run. Fails with
- * ENOMEM when its tables (28 B per table slot: key 8, accumulator 8, population
- * 4, diagonal element 8; two slots per target walker, rounded up to a multiple
- * of 4096) do not fit in the free device
- * memory left after the reserve, with ESTATE when no slot is free. */
+ * ENOMEM when its footprint (fciqmc_footprint_bytes: a main list of twice the
+ * walker target in entries of 20 B -- key 8, population 4, diagonal element 8
+ * -- plus 4 B per bucket of 256 entries, and its integral tables) does not
+ * fit in the free device memory left after the reserve, with ESTATE when no
+ * slot is free. */
 int fciqmc_batch_admit(fciqmc_t *h, const fciqmc_hamiltonian *ham, const fciqmc_params *prm,
                        int32_t *slot);
 
 /* Retire a slot and free its device memory. */
 int fciqmc_batch_retire(fciqmc_t *h, int32_t slot);
 
+/* fciqmc_estimators and fciqmc_walkers for the system in `slot`. */
 int fciqmc_batch_slot_estimators(fciqmc_t *h, int32_t slot, fciqmc_estimates *out);
 int64_t fciqmc_batch_slot_walkers(fciqmc_t *h, int32_t slot, uint64_t *det, int32_t *pop,
                                   uint32_t *flags, int64_t cap);
@@ -236,13 +258,15 @@ int64_t fciqmc_footprint_bytes(const fciqmc_hamiltonian *ham, const fciqmc_param
 int32_t fciqmc_batch_active(fciqmc_t *h);
 
 /* ---- instrumentation -------------------------------------------------------
- * Per-kernel device time (ms) accumulated since the last reset, measured with
- * HIP events on the handle's stream around each kernel of non-graph launches
- * (enable with fciqmc_set_profiling(h, 1); graph launches are then disabled).
- * Kernel groups: 0 chunk sums, 1 chunk scans, 2 spawning (with the merge of
- * spawned walkers into the main table), 3 death + annihilation per slot,
- * 4 statistics reduction / shift. counts[k] is the number of launches
- * measured. */
+ * Per-kernel-group device time (ms) accumulated since the last reset, measured
+ * with HIP events on the handle's stream around each group of non-graph
+ * launches (enable with fciqmc_set_profiling(h, 1); graph launches are then
+ * disabled). Groups: 0 chunk sums of |C| (first iteration of a launch),
+ * 1 attempt mapping (chunk scans), 2 spawning (Sec. 2, 5: records of the
+ * accepted spawns), 3 annihilation (the records sorted by bucket, then death,
+ * merge and annihilation per bucket: Eq. pdeath, Sec. 4.1, 4.2),
+ * 4 statistics reduction / shift (Eq. ProjE, Sec. 2). counts[k] is the number
+ * of launches measured. */
 int fciqmc_set_profiling(fciqmc_t *h, int32_t on);
 int fciqmc_kernel_times(fciqmc_t *h, double ms[5], int64_t counts[5]);
 
@@ -300,8 +324,8 @@ int fciqmc_blocking(const double *num, const double *den, int64_t n, double *mea
  * an overflowing bucket completes the iteration through the spill list and is
  * re-bucketed (fciqmc_estimates.spills). record_capacity > 0 replaces the record
  * buffer by one of that many records now (0: leave it). tile_map_limit >= 0 caps
- * the map from spawn tiles to buckets at that many entries (0: no map), so tile
- * grabs beyond it search the bucket offsets instead; -1 restores the default.
+ * the map from spawn tiles to chunks at that many entries (0: no map), so tile
+ * grabs beyond it search the chunk offsets instead; -1 restores the default.
  * Results do not depend on any of these. Errors: EINVAL, ENOMEM. */
 int fciqmc_set_test_options(fciqmc_t *h, int32_t planner, int64_t tile_map_limit,
                             int64_t record_capacity);

@@ -1297,6 +1297,10 @@ int admit_full(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_p
     h->sys[s].last.nd = 1;
     h->sys[s].last.c0 = n0;
     h->sys[s].last.shift = prm->initial_shift;
+    if (prm->spawn_capacity > 0) {   // the record buffer is shared by the handle's systems
+        rc = ensure_records(h, prm->spawn_capacity);
+        if (rc) return rc;
+    }
     return upload_desc(h);
 }
 
