@@ -1094,6 +1094,27 @@ static int procs_init(orc_state *st, int64_t range)
     return 0;
 }
 
+/* Whether D lies in the restricted space of the run (Sec. 5: a child outside it is
+ * treated as a null excitation). The excitation level counts the electrons of D
+ * outside the reference's orbitals; the seniority counts the spatial orbitals that
+ * hold exactly one electron. */
+static int in_space(const orc_params *prm, uint64_t d0, uint64_t D)
+{
+    if ((prm->space & ORC_SPACE_EXCITATION) && popcount64(D & ~d0) > prm->max_excitation)
+        return 0;
+    if (prm->space & ORC_SPACE_SENIORITY) {
+        int single = 0;
+        for (int s = 0; s < 32; s++)
+            single += (int)(((D >> (2 * s)) & 1u) != ((D >> (2 * s + 1)) & 1u));
+        if (single > prm->max_seniority)
+            return 0;
+    }
+    if ((prm->space & ORC_SPACE_FROZEN) &&
+        ((D & prm->frozen_occupied) != prm->frozen_occupied || (D & prm->frozen_empty)))
+        return 0;
+    return 1;
+}
+
 int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
 {
     *out = NULL;
@@ -1107,6 +1128,12 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
         return fail("oracle: n_procs must be in 0..4096 and n_threads >= 0");
     if (prm->ref_own_proc && prm->n_procs < 2)
         return fail("oracle: a dedicated reference process needs n_procs >= 2");
+    if (prm->space & ~(ORC_SPACE_EXCITATION | ORC_SPACE_SENIORITY | ORC_SPACE_FROZEN))
+        return fail("oracle: unknown space restriction");
+    if (((prm->space & ORC_SPACE_EXCITATION) && prm->max_excitation < 0) ||
+        ((prm->space & ORC_SPACE_SENIORITY) && prm->max_seniority < 0) ||
+        ((prm->space & ORC_SPACE_FROZEN) && (prm->frozen_occupied & prm->frozen_empty)))
+        return fail("oracle: inconsistent space restriction");
     orc_state *st = calloc(1, sizeof *st);
     if (!st)
         return fail("oracle: out of host memory");
@@ -1117,6 +1144,12 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
         return -1;
     }
     st->prm = *prm;
+    if (!in_space(prm, st->sys.d0, st->sys.d0)) {
+        free(st->sys.h1);
+        free(st->sys.eri);
+        free(st);
+        return fail("oracle: the reference is outside the restricted space");
+    }
     st->n_procs = prm->n_procs > 0 ? prm->n_procs : 1;
     st->n_threads = prm->n_threads > 0 ? prm->n_threads : 1;
     make_map(st->pmap, prm->proc_seed ? prm->proc_seed : 0xD15781B7ull);
@@ -1190,7 +1223,7 @@ static int proc_spawn_death(orc_state *st, int p)
             excit_t ex;
             gen_excit(s, &di, w, &ex);
             attempts++;
-            if (!ex.det || ex.hel == 0.0)
+            if (!ex.det || ex.hel == 0.0 || !in_space(&st->prm, s->d0, ex.det))
                 continue;
             /* The acceptance uniform is the type word's uniform rescaled within the
              * chosen type's interval: given the type it is uniform on [0, 1) and

@@ -46,8 +46,21 @@ typedef struct {
     int32_t ref_own_proc;       /* 1: the reference alone on process 0 (needs n_procs >= 2) */
     uint64_t proc_seed;         /* seeds the random map of the process hash; 0 = default */
     int32_t n_threads;          /* host threads over which the processes run; 0 = 1 */
+    /* Restricted space (Sec. 5: children outside it are null excitations): a bitwise OR
+     * of ORC_SPACE_* selects the conditions a determinant of the space meets. */
+    int32_t space;
+    int32_t max_excitation;     /* ORC_SPACE_EXCITATION: at most this many electrons moved
+                                   away from the reference */
+    int32_t max_seniority;      /* ORC_SPACE_SENIORITY: at most this many singly occupied
+                                   spatial orbitals */
     int32_t pad1;
+    uint64_t frozen_occupied;   /* ORC_SPACE_FROZEN: spin orbitals occupied in every determinant */
+    uint64_t frozen_empty;      /* ORC_SPACE_FROZEN: spin orbitals empty in every determinant */
 } orc_params;
+
+#define ORC_SPACE_EXCITATION 1
+#define ORC_SPACE_SENIORITY  2
+#define ORC_SPACE_FROZEN     4
 
 typedef struct {
     int64_t iteration, n_walkers, n_dets, ref_pop;

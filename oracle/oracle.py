@@ -25,7 +25,10 @@ class OrcParams(C.Structure):
                 ("avg_start", C.c_int32), ("pad0", C.c_int32),
                 ("hash_seed", C.c_uint64), ("hash_range", C.c_int64),
                 ("n_procs", C.c_int32), ("ref_own_proc", C.c_int32),
-                ("proc_seed", C.c_uint64), ("n_threads", C.c_int32), ("pad1", C.c_int32)]
+                ("proc_seed", C.c_uint64), ("n_threads", C.c_int32),
+                ("space", C.c_int32), ("max_excitation", C.c_int32), ("max_seniority", C.c_int32),
+                ("pad1", C.c_int32), ("frozen_occupied", C.c_uint64),
+                ("frozen_empty", C.c_uint64)]
 
 
 class OrcEst(C.Structure):
@@ -130,7 +133,9 @@ class Oracle:
                       params.shift_update_every, params.initiator_threshold,
                       params.target_walkers, params.initial_walkers, params.seed,
                       params.avg_start, 0, hash_seed, hash_range, n_procs,
-                      int(bool(ref_own_proc)), proc_seed, n_threads, 0)
+                      int(bool(ref_own_proc)), proc_seed, n_threads, params.space,
+                      params.max_excitation, params.max_seniority, 0, params.frozen_occupied,
+                      params.frozen_empty)
         self._h = C.c_void_p()
         if L.orc_create(C.byref(h), C.byref(p), C.byref(self._h)) != 0:
             raise RuntimeError(L.orc_last_error().decode())

@@ -40,7 +40,23 @@ __all__ = [
     "Hamiltonian", "Params", "hubbard_ring", "synthetic_molecule",
     "band_energies", "npair", "n_eri", "aufbau_det", "neel_det",
     "workload", "batch_workload", "serve_requests",
+    "SPACE_EXCITATION", "SPACE_SENIORITY", "SPACE_FROZEN", "cas_masks",
 ]
+
+# Restricted-space conditions (combined with a bitwise OR in Params.space).
+SPACE_EXCITATION = 1   # at most max_excitation electrons moved away from the reference
+SPACE_SENIORITY = 2    # at most max_seniority singly occupied spatial orbitals
+SPACE_FROZEN = 4       # frozen_occupied spin orbitals filled, frozen_empty ones empty
+
+
+def cas_masks(n_core: int, n_active: int, n_orb: int):
+    """(frozen_occupied, frozen_empty) spin-orbital masks of a complete active space:
+    the n_core lowest spatial orbitals doubly occupied, the next n_active free, the
+    rest empty (orbitals in the given order)."""
+    core = (1 << (2 * n_core)) - 1
+    used = (1 << (2 * (n_core + n_active))) - 1
+    full = (1 << (2 * n_orb)) - 1
+    return core, full & ~used
 
 
 def npair(m: int) -> int:
@@ -85,6 +101,12 @@ class Params:
     spawn_capacity: int = 0
     seed: int = 1
     avg_start: int = 0
+    # restricted space: a bitwise OR of SPACE_* (0: the full space) and its limits
+    space: int = 0
+    max_excitation: int = 0
+    max_seniority: int = 0
+    frozen_occupied: int = 0
+    frozen_empty: int = 0
     extra: dict = field(default_factory=dict)
 
 
