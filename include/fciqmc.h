@@ -89,8 +89,25 @@ typedef struct {
     uint64_t seed;              /* Philox key */
     int32_t avg_start;          /* iterations after the shift starts varying before samples
                                    enter the averages */
-    int32_t reserved0;
+    /* Restricted space (Sec. 5 and its note on truncated and active-space
+     * calculations): a child outside the space is a null excitation, so the run
+     * samples the ground state of H within the space. space = 0: the full space;
+     * else a bitwise OR of FCIQMC_SPACE_*; the reference must lie in the space
+     * (EINVAL otherwise). */
+    int32_t space;
+    int32_t max_excitation;     /* FCIQMC_SPACE_EXCITATION: at most this many electrons
+                                   outside the reference's orbitals (2: CISD) */
+    int32_t max_seniority;      /* FCIQMC_SPACE_SENIORITY: at most this many singly
+                                   occupied spatial orbitals */
+    uint64_t frozen_occupied;   /* FCIQMC_SPACE_FROZEN: spin orbitals occupied in every
+                                   determinant (a CAS core) */
+    uint64_t frozen_empty;      /* FCIQMC_SPACE_FROZEN: spin orbitals empty in every
+                                   determinant (CAS virtuals) */
 } fciqmc_params;
+
+#define FCIQMC_SPACE_EXCITATION 1
+#define FCIQMC_SPACE_SENIORITY  2
+#define FCIQMC_SPACE_FROZEN     4
 
 /* Estimators and counters of one system. Counts refer to the last completed
  * iteration unless marked total. */

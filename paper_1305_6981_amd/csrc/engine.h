@@ -93,6 +93,9 @@ struct SysDesc {
     int64_t nbuckets;                // nb
     int64_t nchunks, gchunk0;        // chunks (nb / BPC) of this system and the first global one
     int64_t stop_at;                 // iterate while iter < stop_at
+    // Restricted space (FCIQMC_SPACE_* bits; children outside it are null excitations).
+    int32_t space, max_ex, max_sen, pad2;
+    uint64_t frz_occ, frz_emp;
     // --- updated on the device
     int64_t iter;
     double shift;

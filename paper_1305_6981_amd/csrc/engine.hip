@@ -626,7 +626,26 @@ int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     if (ham->orb_irrep)
         for (int i = 0; i < ham->n_orb; ++i)
             if (ham->orb_irrep[i] > 7) return set_err(FCIQMC_EINVAL, "irrep labels must be 0..7");
+    if (prm->space & ~(FCIQMC_SPACE_EXCITATION | FCIQMC_SPACE_SENIORITY | FCIQMC_SPACE_FROZEN))
+        return set_err(FCIQMC_EINVAL, "unknown space restriction");
+    if (((prm->space & FCIQMC_SPACE_EXCITATION) && prm->max_excitation < 0) ||
+        ((prm->space & FCIQMC_SPACE_SENIORITY) && prm->max_seniority < 0) ||
+        ((prm->space & FCIQMC_SPACE_FROZEN) && (prm->frozen_occupied & prm->frozen_empty)))
+        return set_err(FCIQMC_EINVAL, "inconsistent space restriction");
     return 0;
+}
+
+// Whether det lies in the run's restricted space (host check of the reference).
+bool host_in_space(const fciqmc_params *prm, uint64_t d0, uint64_t det) {
+    if ((prm->space & FCIQMC_SPACE_EXCITATION) && __builtin_popcountll(det & ~d0) > prm->max_excitation)
+        return false;
+    if ((prm->space & FCIQMC_SPACE_SENIORITY) &&
+        __builtin_popcountll((det ^ (det >> 1)) & 0x5555555555555555ull) > prm->max_seniority)
+        return false;
+    if ((prm->space & FCIQMC_SPACE_FROZEN) &&
+        ((det & prm->frozen_occupied) != prm->frozen_occupied || (det & prm->frozen_empty)))
+        return false;
+    return true;
 }
 
 int64_t initial_capacity(const fciqmc_params *prm) {
@@ -672,6 +691,8 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     } else {
         S.d0 = aufbau(S.h1, S.M, S.na, S.nb);
     }
+    if (!host_in_space(prm, S.d0, S.d0))
+        return set_err(FCIQMC_EINVAL, "the reference lies outside the restricted space");
     if (ham->p_double >= 0.0) {
         S.p_double = ham->p_double;
     } else {
@@ -765,6 +786,11 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     d.target = prm->target_walkers;
     d.seed = prm->seed;
     d.d0 = S.d0;
+    d.space = prm->space;
+    d.max_ex = prm->max_excitation;
+    d.max_sen = prm->max_seniority;
+    d.frz_occ = prm->frozen_occupied;
+    d.frz_emp = prm->frozen_empty;
     d.valid = valid;
     for (int p = 0; p < nso; ++p) d.cmask[2 * S.irrep[p >> 1] + (p & 1)] |= 1ull << p;
     for (int i = 0; i < S.M; ++i) d.irr_packed[i >> 4] |= (uint64_t)S.irrep[i] << (4 * (i & 15));
@@ -1469,6 +1495,8 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
         if ((d & ~valid) || a != S.na || b != S.nb)
             return set_err(FCIQMC_EINVAL, "determinant with wrong electron counts in walker list");
         if (pop[i] == INT32_MIN) return set_err(FCIQMC_EINVAL, "population out of range");
+        if (!host_in_space(&S.prm, S.d0, d))
+            return set_err(FCIQMC_EINVAL, "determinant outside the restricted space in walker list");
         if (d == S.d0) have_ref = true;
         v.emplace_back(d, pop[i]);
     }

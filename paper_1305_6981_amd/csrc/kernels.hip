@@ -299,6 +299,17 @@ __device__ double hel_double(const SysDesc &d, uint64_t det, int p, int q, int a
     return par ? -v : v;
 }
 
+// Whether a child lies in the system's restricted space (Sec. 5: outside it the
+// excitation is null). Excitation level: electrons outside the reference's
+// orbitals; seniority: spatial orbitals holding exactly one electron.
+__device__ __forceinline__ bool in_space(const SysDesc &d, uint64_t det) {
+    const int sp = d.space;
+    if ((sp & 1) && __popcll(det & ~d.d0) > d.max_ex) return false;
+    if ((sp & 2) && __popcll((det ^ (det >> 1)) & 0x5555555555555555ull) > d.max_sen) return false;
+    if ((sp & 4) && ((det & d.frz_occ) != d.frz_occ || (det & d.frz_emp) != 0ull)) return false;
+    return true;
+}
+
 // <det|H|d0> for det != d0 within two excitations of d0 (d0 is the source).
 __device__ double hel_to_ref(const SysDesc &d, uint64_t det) {
     const uint64_t from = d.d0 & ~det, to = det & ~d.d0;
@@ -818,7 +829,7 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         const bool ok = d.n_class == 2
                             ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.w1, it.w2, sel8, ex)
                             : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.w1, it.w2, sel8, ex);
-        if (!ok) continue;
+        if (!ok || (d.space && !in_space(d, ex.det))) continue;
         const double hel = hel_single(d, it.D, ex.p, ex.a);
         if (hel == 0.0) continue;
         const int32_t v = accept(d, hel, ex.pgen, accept_uniform(d, it.w0), it.C, status);
@@ -1010,6 +1021,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         const bool stopped = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)status) != 0;
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
         const bool c1 = d.n_class == 2;          // no point group: classes are the spins
+        const bool restricted = d.space != 0;    // children outside the space are null
         ClassView<true> cv1{d.valid, nullptr};
         ClassView<false> cvg{d.valid, s_cm};
         if (at < at_end && !stopped) {
@@ -1043,6 +1055,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                         if (ok) ex.hel = hel_single(d, D, ex.p, ex.a);
                     }
                 }
+                if (r == EX_OK && restricted && !in_space(d, ex.det)) r = EX_NULL;
                 if (r == EX_OK) {
                     if (ex.hel != 0.0) {
                         const int32_t v = accept(d, ex.hel, ex.pgen, accept_uniform(d, w.x), C, status);

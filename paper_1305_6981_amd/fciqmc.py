@@ -37,7 +37,9 @@ class Params(C.Structure):
                 ("initiator_threshold", C.c_int32), ("target_walkers", C.c_int64),
                 ("initial_walkers", C.c_int64), ("det_capacity", C.c_int64),
                 ("spawn_capacity", C.c_int64), ("seed", C.c_uint64),
-                ("avg_start", C.c_int32), ("reserved0", C.c_int32)]
+                ("avg_start", C.c_int32), ("space", C.c_int32),
+                ("max_excitation", C.c_int32), ("max_seniority", C.c_int32),
+                ("frozen_occupied", C.c_uint64), ("frozen_empty", C.c_uint64)]
 
 
 _EST_INT = ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
@@ -149,7 +151,8 @@ def marshal_hamiltonian(ham):
 def marshal_params(p):
     return Params(p.tau, p.shift_damping, p.initial_shift, p.shift_update_every,
                   p.initiator_threshold, p.target_walkers, p.initial_walkers, p.det_capacity,
-                  p.spawn_capacity, p.seed, p.avg_start, 0)
+                  p.spawn_capacity, p.seed, p.avg_start, p.space, p.max_excitation,
+                  p.max_seniority, p.frozen_occupied, p.frozen_empty)
 
 
 def current_stream():
