@@ -237,6 +237,9 @@ typedef struct {
     double inv_p_double, inv_p_single;   /* 1/P_double, 1/P_single (0 when the type is impossible) */
     uint64_t d0;
     double e0;
+    int hphf;                 /* 0, or the spin parity (+1 even S, -1 odd S) of the
+                                 spin-coupled functions (Sec. 5.3) */
+    int lam;                  /* their relative sign (-1)^S (-1)^{N/2} (see hphf_rep) */
 } sys_t;
 
 static int64_t pair_index(int i, int j)
@@ -524,6 +527,123 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint32_t w[4], 
     out->pgen = (2.0 * s->p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
                 (double)((int64_t)N * (N - 1) * (int64_t)(n_a_set - delta_d));
     out->hel = hel_double(s, det, p, q, a, b);
+}
+
+/* The probability that gen_excit produces T from the determinant of di: the
+ * single-excitation probability of Sec. 5.1 or the double-excitation formula of
+ * Sec. 5.2 for the excitation that turns the determinant into T, 0 when T is not
+ * a single or double excitation the generator can draw. */
+static double pgen_of(const sys_t *s, const detinfo_t *di, uint64_t T)
+{
+    const uint64_t det = di->det;
+    const int N = di->n;
+    if (popcount64(T) != popcount64(det))
+        return 0.0;
+    const uint64_t from = det & ~T, to = T & ~det;
+    const int nf = popcount64(from);
+    int f[2], t[2], k = 0, m = 0;
+    for (int r = 0; r < s->n_so; r++) {
+        if ((from >> r) & 1u && k < 2)
+            f[k++] = r;
+        if ((to >> r) & 1u && m < 2)
+            t[m++] = r;
+    }
+    if (nf == 1) {
+        const int p = f[0], a = t[0];
+        if (s->class_of[a] != s->class_of[p])
+            return 0.0;
+        int delta_s = 0;
+        for (int e = 0; e < N; e++)
+            if (di->n_unocc[s->class_of[di->occ[e]]] == 0)
+                delta_s++;
+        const int nal = di->n_unocc[s->class_of[p]];
+        return s->p_single / (double)((int64_t)nal * (int64_t)(N - delta_s));
+    }
+    if (nf != 2)
+        return 0.0;
+    const int p = f[0], q = f[1], a = t[0], b = t[1];
+    const int same = (p & 1) == (q & 1);
+    if (same && ((a & 1) != (p & 1) || (b & 1) != (p & 1)))
+        return 0.0;
+    if (!partner_ok(s, p, q, a, b))
+        return 0.0;
+    int n_a_set = 0, delta_d = 0;
+    for (int r = 0; r < s->n_so; r++) {
+        if ((det >> r) & 1u)
+            continue;
+        if (same && (r & 1) != (p & 1))
+            continue;
+        n_a_set++;
+        if (n_partner(s, di, p, q, r) == 0)
+            delta_d++;
+    }
+    const int nba = n_partner(s, di, p, q, a), nbb = n_partner(s, di, p, q, b);
+    return (2.0 * s->p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
+           (double)((int64_t)N * (N - 1) * (int64_t)(n_a_set - delta_d));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spin-coupled functions (Sec. 5.3, Eqs. EqualCoeffs and SpinCoup). With the */
+/* spin orbitals interleaved (p = 2s + sigma), exchanging the alpha and beta  */
+/* occupations of every spatial orbital maps |D> to (-1)^{n2(D)} |D~>, n2 the */
+/* number of doubly occupied orbitals (each such pair of creation operators   */
+/* swaps order) and D~ the exchanged bit string. The function of the pair    */
+/* {D, D~} with spin parity (-1)^S is (|D> + lam (-1)^{n2(D)} |D~>) / sqrt 2, */
+/* lam = (-1)^S (-1)^{N/2}; a closed pair (D = D~: every orbital empty or      */
+/* doubly occupied) is |D> itself and belongs to even S only. A function is    */
+/* stored as min(D, D~).                                                        */
+/* ------------------------------------------------------------------------ */
+#define EVEN_BITS 0x5555555555555555ull
+
+static uint64_t spin_flip(uint64_t D) { return ((D & EVEN_BITS) << 1) | ((D >> 1) & EVEN_BITS); }
+
+static int n_doubly(uint64_t D) { return popcount64(D & (D >> 1) & EVEN_BITS); }
+
+static uint64_t hphf_rep(uint64_t D)
+{
+    uint64_t f = spin_flip(D);
+    return f < D ? f : D;
+}
+
+/* <Phi_j|H|Phi_i> for the functions stored as Dj and Di (Di the source of the
+ * excitation, Dj != Di). Both open: <Dj|H|Di> + lam (-1)^{n2(Dj)} <Dj~|H|Di>; one
+ * closed: sqrt2 <Dj|H|Di> (the other term equals the first); both closed:
+ * <Dj|H|Di>. Every element is evaluated with Di as the source. */
+static double hphf_hel(const sys_t *s, uint64_t Di, uint64_t Dj)
+{
+    const uint64_t fi = spin_flip(Di), fj = spin_flip(Dj);
+    const double h = hel_general(s, Dj, Di);
+    if (fi != Di && fj != Dj) {
+        const int sg = (n_doubly(Dj) & 1) ? -s->lam : s->lam;
+        return h + (double)sg * hel_general(s, fj, Di);
+    }
+    if (fi != Di || fj != Dj)
+        return 1.4142135623730951 * h;
+    return h;
+}
+
+/* Diagonal element of the stored function D (of the determinant D without
+ * spin-coupled functions). */
+static double fdiag(const sys_t *s, uint64_t D)
+{
+    const double h = hdiag_of(s, D);
+    if (!s->hphf)
+        return h;
+    const uint64_t f = spin_flip(D);
+    if (f == D)
+        return h;
+    const int sg = (n_doubly(D) & 1) ? -s->lam : s->lam;
+    return h + (double)sg * hel_general(s, f, D);
+}
+
+/* <Phi_0|H|Phi_D> for the projected energy, 0 beyond double excitations. */
+static double ref_hel(const sys_t *s, uint64_t D)
+{
+    if (!s->hphf)
+        return popcount64(D ^ s->d0) <= 4 ? hel_general(s, D, s->d0) : 0.0;
+    if (popcount64(D ^ s->d0) > 4 && popcount64(spin_flip(D) ^ s->d0) > 4)
+        return 0.0;
+    return hphf_hel(s, s->d0, D);
 }
 
 /* Counts of symmetry-allowed single and double excitations from a determinant,
@@ -1144,11 +1264,30 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
         return -1;
     }
     st->prm = *prm;
-    if (!in_space(prm, st->sys.d0, st->sys.d0)) {
+    const char *why = NULL;
+    if (!in_space(prm, st->sys.d0, st->sys.d0))
+        why = "oracle: the reference is outside the restricted space";
+    if (prm->hphf) {
+        /* spin-coupled functions of spin parity hphf (Sec. 5.3) */
+        sys_t *s = &st->sys;
+        if (prm->hphf != 1 && prm->hphf != -1)
+            why = "oracle: hphf must be 0, 1 or -1";
+        else if (s->n_alpha != s->n_beta)
+            why = "oracle: spin-coupled functions need n_alpha = n_beta";
+        else if (prm->space)
+            why = "oracle: spin-coupled functions with a restricted space are not supported";
+        s->hphf = prm->hphf;
+        s->lam = ((s->N / 2) & 1) ? -prm->hphf : prm->hphf;
+        s->d0 = hphf_rep(s->d0);
+        if (!why && spin_flip(s->d0) == s->d0 && prm->hphf < 0)
+            why = "oracle: a closed-shell reference has no odd-spin function";
+        s->e0 = fdiag(s, s->d0);
+    }
+    if (why) {
         free(st->sys.h1);
         free(st->sys.eri);
         free(st);
-        return fail("oracle: the reference is outside the restricted space");
+        return fail(why);
     }
     st->n_procs = prm->n_procs > 0 ? prm->n_procs : 1;
     st->n_threads = prm->n_threads > 0 ? prm->n_threads : 1;
@@ -1223,6 +1362,21 @@ static int proc_spawn_death(orc_state *st, int p)
             excit_t ex;
             gen_excit(s, &di, w, &ex);
             attempts++;
+            if (s->hphf && ex.det) {
+                /* The target is the function holding the child (Sec. 5.3): generated
+                 * from D only, it is reached through the child or through its
+                 * spin-exchanged partner, so its generation probability is the sum
+                 * of the two. The pair of D itself is part of the diagonal. */
+                const uint64_t Dj = hphf_rep(ex.det), fx = spin_flip(ex.det);
+                if (Dj == D || (spin_flip(Dj) == Dj && s->hphf < 0)) {
+                    ex.det = 0;
+                } else {
+                    if (fx != ex.det)
+                        ex.pgen = ex.pgen + pgen_of(s, &di, fx);
+                    ex.hel = hphf_hel(s, D, Dj);
+                    ex.det = Dj;
+                }
+            }
             if (!ex.det || ex.hel == 0.0 || !in_space(&st->prm, s->d0, ex.det))
                 continue;
             /* The acceptance uniform is the type word's uniform rescaled within the
@@ -1283,8 +1437,8 @@ static void proc_stats(orc_state *st, int q)
             continue;
         nw += C < 0 ? -(int64_t)C : C;
         nd++;
-        if (D != s->d0 && popcount64(D ^ s->d0) <= 4)
-            num = num + hel_general(s, D, s->d0) * (double)C;
+        if (D != s->d0)
+            num = num + ref_hel(s, D) * (double)C;
     }
     pr->nw = nw;
     pr->nd = nd;
@@ -1353,7 +1507,7 @@ static int proc_annihilate(orc_state *st, int q)
         } else if (f) {
             if (c > 2147483647 || c < -2147483647)
                 return fail("oracle: population overflow");
-            if (ml_insert(ml, D, (int32_t)c, hdiag_of(s, D)) < 0)
+            if (ml_insert(ml, D, (int32_t)c, fdiag(s, D)) < 0)
                 return -1;
             born++;
         } else {
@@ -1384,7 +1538,7 @@ static int proc_load(orc_state *st, int q)
         const uint64_t D = st->load_det[t];
         if (ml_find(ml, D) >= 0)
             return fail("oracle: duplicate determinant in walker list");
-        if (ml_insert(ml, D, st->load_pop[t], hdiag_of(&st->sys, D)) < 0)
+        if (ml_insert(ml, D, st->load_pop[t], fdiag(&st->sys, D)) < 0)
             return -1;
     }
     proc_stats(st, q);
@@ -1603,6 +1757,12 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
 {
     if (!st)
         return fail("oracle: null state");
+    if (st->sys.hphf)
+        for (int64_t t = 0; t < n; t++)
+            if (pop[t] != 0 && (hphf_rep(det[t]) != det[t] ||
+                                (spin_flip(det[t]) == det[t] && st->sys.hphf < 0)))
+                return fail("oracle: a walker list of spin-coupled functions holds each "
+                            "function as the smaller determinant of its pair");
     int64_t range = st->proc[0].ml.range;
     procs_free(st);
     if (procs_init(st, range) != 0)
@@ -1683,12 +1843,28 @@ double orc_hel(const orc_state *st, uint64_t bra, uint64_t ket)
 
 double orc_hdiag(const orc_state *st, uint64_t det) { return hdiag_of(&st->sys, det); }
 
+double orc_fn_hel(const orc_state *st, uint64_t bra, uint64_t ket)
+{
+    if (bra == ket)
+        return fdiag(&st->sys, ket);
+    return st->sys.hphf ? hphf_hel(&st->sys, ket, bra) : hel_general(&st->sys, bra, ket);
+}
+
+double orc_fn_diag(const orc_state *st, uint64_t fn) { return fdiag(&st->sys, fn); }
+
+double orc_pgen(const orc_state *st, uint64_t det, uint64_t target)
+{
+    detinfo_t di;
+    det_setup(&st->sys, det, &di);
+    return pgen_of(&st->sys, &di, target);
+}
+
 double orc_proj_num(const orc_state *st, const uint64_t *det, const double *c, int64_t n)
 {
     double num = 0.0;
     for (int64_t t = 0; t < n; t++)
-        if (det[t] != st->sys.d0 && popcount64(det[t] ^ st->sys.d0) <= 4)
-            num = num + hel_general(&st->sys, det[t], st->sys.d0) * c[t];
+        if (det[t] != st->sys.d0)
+            num = num + ref_hel(&st->sys, det[t]) * c[t];
     return num;
 }
 

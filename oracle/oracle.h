@@ -53,7 +53,9 @@ typedef struct {
                                    away from the reference */
     int32_t max_seniority;      /* ORC_SPACE_SENIORITY: at most this many singly occupied
                                    spatial orbitals */
-    int32_t pad1;
+    int32_t hphf;               /* 0: determinants; +1 / -1: spin-coupled functions
+                                   (Sec. 5.3) of even / odd total spin S (needs
+                                   n_alpha = n_beta; no restricted space) */
     uint64_t frozen_occupied;   /* ORC_SPACE_FROZEN: spin orbitals occupied in every determinant */
     uint64_t frozen_empty;      /* ORC_SPACE_FROZEN: spin orbitals empty in every determinant */
 } orc_params;
@@ -94,6 +96,12 @@ int     orc_decode(uint64_t det, int32_t *occ);          /* byte-table decode; r
 int64_t orc_hash(const orc_state *st, uint64_t det, int64_t range);   /* Algorithm 1 */
 double  orc_hel(const orc_state *st, uint64_t bra, uint64_t ket);      /* <bra|H|ket> */
 double  orc_hdiag(const orc_state *st, uint64_t det);
+double  orc_pgen(const orc_state *st, uint64_t det, uint64_t target);  /* generator's probability */
+/* Elements between the stored functions of the run (determinants, or spin-coupled
+ * functions held as their smaller determinant): <bra|H|ket> with ket the source,
+ * and the diagonal element. */
+double  orc_fn_hel(const orc_state *st, uint64_t bra, uint64_t ket);
+double  orc_fn_diag(const orc_state *st, uint64_t fn);
 double  orc_proj_num(const orc_state *st, const uint64_t *det, const double *c, int64_t n);
 int     orc_sample_excitations(const orc_state *st, uint64_t det, int64_t iteration,
                                int64_t n_samples, uint64_t *out_det, double *out_pgen,

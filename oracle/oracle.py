@@ -27,7 +27,7 @@ class OrcParams(C.Structure):
                 ("n_procs", C.c_int32), ("ref_own_proc", C.c_int32),
                 ("proc_seed", C.c_uint64), ("n_threads", C.c_int32),
                 ("space", C.c_int32), ("max_excitation", C.c_int32), ("max_seniority", C.c_int32),
-                ("pad1", C.c_int32), ("frozen_occupied", C.c_uint64),
+                ("hphf", C.c_int32), ("frozen_occupied", C.c_uint64),
                 ("frozen_empty", C.c_uint64)]
 
 
@@ -75,6 +75,12 @@ def lib():
         L.orc_proj_num.argtypes = [vp, vp, vp, C.c_int64]
         L.orc_proj_num.restype = C.c_double
         L.orc_sample_excitations.argtypes = [vp, C.c_uint64, C.c_int64, C.c_int64, vp, vp, vp]
+        L.orc_pgen.argtypes = [vp, C.c_uint64, C.c_uint64]
+        L.orc_pgen.restype = C.c_double
+        L.orc_fn_hel.argtypes = [vp, C.c_uint64, C.c_uint64]
+        L.orc_fn_hel.restype = C.c_double
+        L.orc_fn_diag.argtypes = [vp, C.c_uint64]
+        L.orc_fn_diag.restype = C.c_double
         L.orc_blocking.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         _LIB = L
@@ -134,8 +140,8 @@ class Oracle:
                       params.target_walkers, params.initial_walkers, params.seed,
                       params.avg_start, 0, hash_seed, hash_range, n_procs,
                       int(bool(ref_own_proc)), proc_seed, n_threads, params.space,
-                      params.max_excitation, params.max_seniority, 0, params.frozen_occupied,
-                      params.frozen_empty)
+                      params.max_excitation, params.max_seniority, params.hphf,
+                      params.frozen_occupied, params.frozen_empty)
         self._h = C.c_void_p()
         if L.orc_create(C.byref(h), C.byref(p), C.byref(self._h)) != 0:
             raise RuntimeError(L.orc_last_error().decode())
@@ -202,6 +208,17 @@ class Oracle:
         det = np.ascontiguousarray(det, dtype=np.uint64)
         c = np.ascontiguousarray(c, dtype=np.float64)
         return lib().orc_proj_num(self._h, _ptr(det), _ptr(c), len(det))
+
+    def fn_hel(self, bra: int, ket: int) -> float:
+        """<bra|H|ket> between stored functions of the run, ket the source."""
+        return lib().orc_fn_hel(self._h, C.c_uint64(bra), C.c_uint64(ket))
+
+    def fn_diag(self, fn: int) -> float:
+        return lib().orc_fn_diag(self._h, C.c_uint64(fn))
+
+    def pgen(self, det: int, target: int) -> float:
+        """Probability that the excitation generator produces target from det."""
+        return lib().orc_pgen(self._h, C.c_uint64(det), C.c_uint64(target))
 
     def sample_excitations(self, det: int, n: int, iteration: int = 0):
         od = np.zeros(n, dtype=np.uint64)

@@ -107,6 +107,8 @@ class Params:
     max_seniority: int = 0
     frozen_occupied: int = 0
     frozen_empty: int = 0
+    # spin-coupled functions: 0 off, +1 / -1 for even / odd total spin
+    hphf: int = 0
     extra: dict = field(default_factory=dict)
 
 

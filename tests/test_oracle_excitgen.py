@@ -103,6 +103,12 @@ def test_pgen_equals_enumerated_probability(name, mk, _):
         # Every element returned is <D'|H|D>.
         for d, h in list(zip(out[~nulls], hel[~nulls]))[:300]:
             assert h == o.hel(int(d), det)
+        # The probability of a given target (used for spin-coupled functions) equals the
+        # enumerated one for every determinant of the sector.
+        for t in dets:
+            ref = probs.get(int(t), 0.0)
+            got = o.pgen(det, int(t))
+            assert abs(got - ref) <= 1e-14 * ref if ref > 0 else got == 0.0, (name, det, int(t))
 
 
 def _combinatorial_p_double(m, na, nb):
