@@ -103,6 +103,16 @@ typedef struct {
                                    determinant (a CAS core) */
     uint64_t frozen_empty;      /* FCIQMC_SPACE_FROZEN: spin orbitals empty in every
                                    determinant (CAS virtuals) */
+    /* Spin-coupled functions (Sec. 5.3, Eqs. EqualCoeffs and SpinCoup): 0 samples
+     * determinants; +1 / -1 samples the pairs {D, D~} (alpha and beta exchanged)
+     * symmetric under the exchange with the sign of even / odd total spin S.
+     * Needs n_alpha = n_beta and no restricted space (EINVAL otherwise). A function
+     * is held as the smaller determinant of its pair (walker lists in and out);
+     * excitations are drawn from that determinant, the target's generation
+     * probability sums over its two determinants. Closed pairs (every orbital
+     * empty or doubly occupied) exist for even S only. */
+    int32_t hphf;
+    int32_t reserved1;
 } fciqmc_params;
 
 #define FCIQMC_SPACE_EXCITATION 1

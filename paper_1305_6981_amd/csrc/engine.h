@@ -96,6 +96,9 @@ struct SysDesc {
     // Restricted space (FCIQMC_SPACE_* bits; children outside it are null excitations).
     int32_t space, max_ex, max_sen, pad2;
     uint64_t frz_occ, frz_emp;
+    // Spin-coupled functions (Sec. 5.3): hphf = 0 (determinants), +1 / -1 (even / odd
+    // total spin); lam = hphf (-1)^{N/2}, the relative sign of a pair's determinants.
+    int32_t hphf, lam;
     // --- updated on the device
     int64_t iter;
     double shift;

@@ -632,7 +632,17 @@ int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
         ((prm->space & FCIQMC_SPACE_SENIORITY) && prm->max_seniority < 0) ||
         ((prm->space & FCIQMC_SPACE_FROZEN) && (prm->frozen_occupied & prm->frozen_empty)))
         return set_err(FCIQMC_EINVAL, "inconsistent space restriction");
+    if (prm->hphf != 0 && prm->hphf != 1 && prm->hphf != -1)
+        return set_err(FCIQMC_EINVAL, "hphf must be 0, 1 or -1");
+    if (prm->hphf && ham->n_alpha != ham->n_beta)
+        return set_err(FCIQMC_EINVAL, "spin-coupled functions need n_alpha = n_beta");
+    if (prm->hphf && prm->space)
+        return set_err(FCIQMC_EINVAL, "spin-coupled functions with a restricted space are not supported");
     return 0;
+}
+
+uint64_t host_spin_flip(uint64_t D) {
+    return ((D & 0x5555555555555555ull) << 1) | ((D >> 1) & 0x5555555555555555ull);
 }
 
 // Whether det lies in the run's restricted space (host check of the reference).
@@ -699,6 +709,12 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
         int64_t ns, nd;
         excitation_counts(S, S.d0, ns, nd);
         S.p_double = (ns + nd) > 0 ? (double)nd / (double)(ns + nd) : 0.0;
+    }
+    if (prm->hphf) {   // the reference function, stored as the smaller determinant of its pair
+        const uint64_t f = host_spin_flip(S.d0);
+        if (f == S.d0 && prm->hphf < 0)
+            return set_err(FCIQMC_EINVAL, "a closed-shell reference has no odd-spin function");
+        S.d0 = std::min(S.d0, f);
     }
     S.reserve_bytes = target_footprint(ham, prm);
     // free-memory admission
@@ -791,6 +807,8 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     d.max_sen = prm->max_seniority;
     d.frz_occ = prm->frozen_occupied;
     d.frz_emp = prm->frozen_empty;
+    d.hphf = prm->hphf;
+    d.lam = ((S.N / 2) & 1) ? -prm->hphf : prm->hphf;
     d.valid = valid;
     for (int p = 0; p < nso; ++p) d.cmask[2 * S.irrep[p >> 1] + (p & 1)] |= 1ull << p;
     for (int i = 0; i < S.M; ++i) d.irr_packed[i >> 4] |= (uint64_t)S.irrep[i] << (4 * (i & 15));
@@ -1497,6 +1515,9 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
         if (pop[i] == INT32_MIN) return set_err(FCIQMC_EINVAL, "population out of range");
         if (!host_in_space(&S.prm, S.d0, d))
             return set_err(FCIQMC_EINVAL, "determinant outside the restricted space in walker list");
+        if (S.prm.hphf && (host_spin_flip(d) < d || (host_spin_flip(d) == d && S.prm.hphf < 0)))
+            return set_err(FCIQMC_EINVAL, "a list of spin-coupled functions holds each as the "
+                                          "smaller determinant of its pair");
         if (d == S.d0) have_ref = true;
         v.emplace_back(d, pop[i]);
     }

@@ -475,6 +475,132 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
     return EX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Spin-coupled functions (Sec. 5.3, Eqs. EqualCoeffs and SpinCoup). With spin
+// orbitals interleaved, exchanging alpha and beta in every spatial orbital maps
+// |D> to (-1)^{n2(D)} |D~> (n2: doubly occupied orbitals); the function of the
+// pair {D, D~} is (|D> + lam (-1)^{n2(D)} |D~>)/sqrt2, lam = (-1)^S (-1)^{N/2}
+// (SysDesc::lam), or |D> for a closed pair D = D~ (even S only). A function is
+// stored as min(D, D~); excitations are drawn from that determinant only.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spin_flip(uint64_t D) {
+    return ((D & EVEN_BITS) << 1) | ((D >> 1) & EVEN_BITS);
+}
+__device__ __forceinline__ uint64_t fn_rep(uint64_t D) {
+    const uint64_t f = spin_flip(D);
+    return f < D ? f : D;
+}
+__device__ __forceinline__ int pair_sign(const SysDesc &d, uint64_t D) {
+    return (__popcll(D & (D >> 1) & EVEN_BITS) & 1) ? -d.lam : d.lam;
+}
+
+// <bra|H|ket> for a single or double excitation with ket the source (0 beyond).
+__device__ double hel_between(const SysDesc &d, uint64_t bra, uint64_t ket) {
+    const uint64_t from = ket & ~bra, to = bra & ~ket;
+    const int n = __popcll(from);
+    if (n == 1) return hel_single(d, ket, __builtin_ctzll(from), __builtin_ctzll(to));
+    if (n == 2)
+        return hel_double(d, ket, __builtin_ctzll(from), 63 - __builtin_clzll(from),
+                          __builtin_ctzll(to), 63 - __builtin_clzll(to));
+    return 0.0;
+}
+
+// <Phi_j|H|Phi_i> for the stored functions Dj != Di, Di the source: both open,
+// <Dj|H|Di> + lam (-1)^{n2(Dj)} <Dj~|H|Di>; one closed, sqrt2 <Dj|H|Di>; both
+// closed, <Dj|H|Di>.
+__device__ double fn_hel(const SysDesc &d, uint64_t Di, uint64_t Dj) {
+    const uint64_t fi = spin_flip(Di), fj = spin_flip(Dj);
+    const double h = hel_between(d, Dj, Di);
+    if (fi != Di && fj != Dj) return h + (double)pair_sign(d, Dj) * hel_between(d, fj, Di);
+    if (fi != Di || fj != Dj) return 1.4142135623730951 * h;
+    return h;
+}
+
+// Diagonal element of a stored function from its determinant's diagonal hd.
+__device__ __forceinline__ double fn_diag_from(const SysDesc &d, uint64_t D, double hd) {
+    if (!d.hphf) return hd;
+    const uint64_t f = spin_flip(D);
+    if (f == D) return hd;
+    return hd + (double)pair_sign(d, D) * hel_between(d, f, D);
+}
+__device__ double fn_diag(const SysDesc &d, uint64_t D) { return fn_diag_from(d, D, hdiag_of(d, D)); }
+
+// Projected-energy element <Phi_0|H|Phi_D> (Eq. ProjE) and whether it can be
+// nonzero (D within a double excitation of the reference, or its partner).
+__device__ __forceinline__ bool near_ref(const SysDesc &d, uint64_t D) {
+    return __popcll(D ^ d.d0) <= 4 || (d.hphf && __popcll(spin_flip(D) ^ d.d0) <= 4);
+}
+__device__ double ref_hel(const SysDesc &d, uint64_t D) {
+    return d.hphf ? fn_hel(d, d.d0, D) : hel_to_ref(d, D);
+}
+
+// The probability that excite() draws T from det (Secs. 5.1, 5.2) by the same
+// operations as the draw, 0 when it cannot draw T. recip[k] = 1/k.
+__device__ double pgen_target(const SysDesc &d, const uint64_t *cm, const double *recip,
+                              uint64_t det, uint64_t T) {
+    const uint64_t from = det & ~T, to = T & ~det;
+    const int nf = __popcll(from);
+    if (nf != __popcll(to)) return 0.0;
+    const uint64_t emp = ~det & d.valid;
+    const bool c1 = d.n_class == 2;
+    auto mask = [&](int c) -> uint64_t {
+        return c1 ? (d.valid & ((c & 1) ? ODD_BITS : EVEN_BITS)) : cm[c];
+    };
+    auto cls = [&](int p) -> int { return c1 ? (p & 1) : class_of(d, p); };
+    if (nf == 1) {
+        const int p = __builtin_ctzll(from), a = __builtin_ctzll(to);
+        if (cls(a) != cls(p)) return 0.0;
+        uint64_t movable = 0;
+        for (int c = 0; c < (c1 ? 2 : d.n_class); ++c) {
+            const uint64_t m = mask(c);
+            if (emp & m) movable |= det & m;
+        }
+        const uint32_t nmov = (uint32_t)__popcll(movable);
+        const uint32_t nal = (uint32_t)__popcll(emp & mask(cls(p)));
+        return d.p_single / (double)((int64_t)nal * (int64_t)nmov);
+    }
+    if (nf != 2) return 0.0;
+    const int p = __builtin_ctzll(from), q = 63 - __builtin_clzll(from);
+    const int a = __builtin_ctzll(to), b = 63 - __builtin_clzll(to);
+    const bool same = ((p ^ q) & 1) == 0;
+    if (same ? (((a ^ p) & 1) || ((b ^ p) & 1)) : (((a ^ b) & 1) == 0)) return 0.0;
+    if (c1) return same ? d.pgen_c1[p & 1] : d.pgen_c1[2 + (a & 1)];
+    const int gpq = irrep_of(d, p >> 1) ^ irrep_of(d, q >> 1);
+    const int ca = class_of(d, a), cb = class_of(d, b);
+    const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
+    if (cb != pca) return 0.0;
+    const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
+    uint64_t allowed = 0;
+    for (int c = 0; c < d.n_class; ++c) {
+        const uint64_t memb = A & cm[c];
+        if (!memb) continue;
+        const int sb = same ? (p & 1) : 1 - (c & 1);
+        const int pc = 2 * (gpq ^ (c >> 1)) + sb;
+        const int nb = __popcll(emp & cm[pc]) - (pc == c ? 1 : 0);
+        if (nb > 0) allowed |= memb;
+    }
+    const uint32_t nal = (uint32_t)__popcll(allowed);
+    const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
+    const uint32_t nba = (uint32_t)__popcll(emp & cm[pca] & ~(1ull << a));
+    const int nbb = __popcll(emp & cm[pcb]) - (pcb == cb ? 1 : 0);
+    return (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
+           (double)((int64_t)d.N * (int64_t)(d.N - 1) * (int64_t)nal);
+}
+
+// A drawn excitation as a spawn between stored functions: the target is the
+// function holding the child, reached through the child or its partner (their
+// probabilities add); the pair of the source itself is diagonal (null), and so is a
+// closed pair in an odd-spin run. Returns false for a null excitation.
+__device__ bool to_function(const SysDesc &d, const uint64_t *cm, const double *recip,
+                            uint64_t D, Excit &ex) {
+    const uint64_t Dj = fn_rep(ex.det), fx = spin_flip(ex.det);
+    if (Dj == D || (d.hphf < 0 && spin_flip(Dj) == Dj)) return false;
+    if (fx != ex.det) ex.pgen = ex.pgen + pgen_target(d, cm, recip, D, fx);
+    ex.hel = fn_hel(d, D, Dj);
+    ex.det = Dj;
+    return true;
+}
+
 // Natural log for the shift update: x = m 2^e with m in (1/sqrt2, sqrt2],
 // ln x = e ln2 + 2 atanh((m-1)/(m+1)), the atanh series summed by Horner's
 // rule through the z^25 term. Fixed operation order (no contraction), so any
@@ -814,7 +940,8 @@ __device__ __forceinline__ void flush_spawn_count(unsigned long long *counter,
 
 // Drain both queues of system s with the whole workgroup (call uniformly).
 __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc &d, int s,
-                             const uint32_t *sel8, unsigned long long &spawned) {
+                             const uint32_t *sel8, const double *recip,
+                             unsigned long long &spawned) {
     const int t = threadIdx.x;
     uint32_t *status = &a.status[s];
     // a system whose record buffer overflowed re-runs the iteration: drop its queued work
@@ -830,7 +957,12 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
                             ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.w1, it.w2, sel8, ex)
                             : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.w1, it.w2, sel8, ex);
         if (!ok || (d.space && !in_space(d, ex.det))) continue;
-        const double hel = hel_single(d, it.D, ex.p, ex.a);
+        if (d.hphf) {
+            if (!to_function(d, d.cmask, recip, it.D, ex)) continue;
+        } else {
+            ex.hel = hel_single(d, it.D, ex.p, ex.a);
+        }
+        const double hel = ex.hel;
         if (hel == 0.0) continue;
         const int32_t v = accept(d, hel, ex.pgen, accept_uniform(d, it.w0), it.C, status);
         if (v == 0) continue;
@@ -948,7 +1080,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             // queued work and tallies belong to another system: finish them first
             if (Q.sys >= 0) {
                 const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, spawned);
+                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, spawned);
                 flush_spawn_count(&a.spawns[qs], spawned);
             }
             __syncthreads();
@@ -1022,6 +1154,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
         const bool c1 = d.n_class == 2;          // no point group: classes are the spins
         const bool restricted = d.space != 0;    // children outside the space are null
+        const bool coupled = d.hphf != 0;        // walkers on spin-coupled functions
         ClassView<true> cv1{d.valid, nullptr};
         ClassView<false> cvg{d.valid, s_cm};
         if (at < at_end && !stopped) {
@@ -1056,6 +1189,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                     }
                 }
                 if (r == EX_OK && restricted && !in_space(d, ex.det)) r = EX_NULL;
+                if (r == EX_OK && coupled && !to_function(d, s_cm, s_recip, D, ex)) r = EX_NULL;
                 if (r == EX_OK) {
                     if (ex.hel != 0.0) {
                         const int32_t v = accept(d, ex.hel, ex.pgen, accept_uniform(d, w.x), C, status);
@@ -1083,12 +1217,12 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             }
         }
         __syncthreads();
-        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, s_sel8, spawned);
+        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, s_sel8, s_recip, spawned);
     }
     __syncthreads();
     if (Q.sys >= 0) {
         const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, spawned);
+        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, spawned);
         flush_spawn_count(&a.spawns[qs], spawned);
     }
 }
@@ -1332,9 +1466,10 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
         const bool two = j + (int)blockDim.x < n;
         const uint32_t i1 = two ? queue[j + blockDim.x] : i0;
         double h0, h1;
-        hdiag_lds2(d.e_core, *gp(d.key + i0), *gp(d.key + i1), hpp, jk, d.n_so, h0, h1);
-        *gp(d.hdiag + i0) = h0;
-        if (two) *gp(d.hdiag + i1) = h1;
+        const uint64_t k0 = *gp(d.key + i0), k1 = *gp(d.key + i1);
+        hdiag_lds2(d.e_core, k0, k1, hpp, jk, d.n_so, h0, h1);
+        *gp(d.hdiag + i0) = fn_diag_from(d, k0, h0);
+        if (two) *gp(d.hdiag + i1) = fn_diag_from(d, k1, h1);
     }
 }
 
@@ -1664,7 +1799,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         nw += an;
                         nwb += (unsigned long long)an;
                         cnt += 1ull << CNT_SHIFT_ND;
-                        if (!is_ref && __popcll(D ^ d.d0) <= 4) nearm |= 1u << u;
+                        if (!is_ref && near_ref(d, D)) nearm |= 1u << u;
                     }
                     if (np != 0 || is_ref) keepm |= 1u << u;   // the reference keeps its entry at 0
                 }
@@ -1698,7 +1833,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     const int64_t an = sp < 0 ? -sp : sp;
                     nw += an;
                     cnt += 1ull << CNT_SHIFT_ND;
-                    if (call < 32 && __popcll(D ^ d.d0) <= 4) nearn |= 1u << call;
+                    if (call < 32 && near_ref(d, D)) nearn |= 1u << call;
                     const int pos = k < H ? (int)W.free_[k] : n + (k - H);
                     if (pos < BQ) {
                         nwb += (unsigned long long)an;
@@ -1708,7 +1843,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         if (q < POST_QUEUE) {
                             s_queue[q] = (uint32_t)(base + pos);
                         } else {   // (another system's window, or many new determinants)
-                            *gp(d.hdiag + base + pos) = hdiag_of(d, D);
+                            *gp(d.hdiag + base + pos) = fn_diag(d, D);
                         }
                     } else {
                         // the bucket is full: completed in the spill list, re-bucketed by the host
@@ -1716,7 +1851,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         if (j < (unsigned long long)a.sp_cap) {
                             a.sp_det[j] = D;
                             a.sp_pop[j] = (int32_t)sp;
-                            a.sp_hd[j] = hdiag_of(d, D);
+                            a.sp_hd[j] = fn_diag(d, D);
                             a.sp_sys[j] = s;
                             a.spilled[s] = 1u;
                         } else {
@@ -1777,17 +1912,17 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 // double excitation of the reference, taken last, when few values are live.
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    if ((nearm >> u) & 1u) num = num + hel_to_ref(d, kin[u]) * (double)npv[u];
+                    if ((nearm >> u) & 1u) num = num + ref_hel(d, kin[u]) * (double)npv[u];
                 if (nr <= (uint32_t)NREC) {
                     for (int i = 0; i < 2; ++i)
                         if ((nearn >> i) & 1u)
-                            num = num + hel_to_ref(d, W.key[lane + 64 * i]) * (double)W.acc[lane + 64 * i];
+                            num = num + ref_hel(d, W.key[lane + 64 * i]) * (double)W.acc[lane + 64 * i];
                 } else {
                     for (int i = lane; i < kc; i += 64) {
                         const uint64_t D = a.recs[r0 + i].det;
                         const int32_t sp = a.recs[r0 + i].w;
-                        if (sp != 0 && (a.recs[r0 + i].tag & F_INIT) && __popcll(D ^ d.d0) <= 4)
-                            num = num + hel_to_ref(d, D) * (double)sp;
+                        if (sp != 0 && (a.recs[r0 + i].tag & F_INIT) && near_ref(d, D))
+                            num = num + ref_hel(d, D) * (double)sp;
                     }
                 }
             }
@@ -1975,7 +2110,7 @@ __global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const in
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t D = det[i];
-        if (!bucket_put(d, D, pop[i], hdiag_of(d, D))) atomicOr(err, 1u);
+        if (!bucket_put(d, D, pop[i], fn_diag(d, D))) atomicOr(err, 1u);
     }
 }
 
@@ -2155,7 +2290,7 @@ hipError_t launch_stage_sort(void *stage, int64_t n, hipStream_t s) {
 }
 
 __global__ void k_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = hdiag_of(desc[sys], det);
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = fn_diag(desc[sys], det);
 }
 
 hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s) {

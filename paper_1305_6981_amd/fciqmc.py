@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("spawn_capacity", C.c_int64), ("seed", C.c_uint64),
                 ("avg_start", C.c_int32), ("space", C.c_int32),
                 ("max_excitation", C.c_int32), ("max_seniority", C.c_int32),
-                ("frozen_occupied", C.c_uint64), ("frozen_empty", C.c_uint64)]
+                ("frozen_occupied", C.c_uint64), ("frozen_empty", C.c_uint64),
+                ("hphf", C.c_int32), ("reserved1", C.c_int32)]
 
 
 _EST_INT = ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
@@ -152,7 +153,7 @@ def marshal_params(p):
     return Params(p.tau, p.shift_damping, p.initial_shift, p.shift_update_every,
                   p.initiator_threshold, p.target_walkers, p.initial_walkers, p.det_capacity,
                   p.spawn_capacity, p.seed, p.avg_start, p.space, p.max_excitation,
-                  p.max_seniority, p.frozen_occupied, p.frozen_empty)
+                  p.max_seniority, p.frozen_occupied, p.frozen_empty, p.hphf, 0)
 
 
 def current_stream():
