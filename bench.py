@@ -68,7 +68,7 @@ def log(*a):
 
 
 class Roctx:
-    """roctxProfilerResume/Pause, so rocprofv3 --selected-regions covers the timed region."""
+    """roctxProfilerResume/Pause, so rocprofv3 --selected-regions covers the profiling window."""
 
     def __init__(self):
         self.mod = None
@@ -347,6 +347,40 @@ def served(F, S, n_requests, scale, max_iters, plain_every, seed=5):
     return out
 
 
+def variant(F, S, name, walkers, warmup, steps, **mods):
+    """The 24e/30o system at the benchmark's walker target in another sampling mode
+    (spin-coupled functions, a restricted space): grown and warmed up like the
+    headline run, then `steps` iterations timed on the graph path."""
+    ham, prm, _ = S.workload("synth24e30o")
+    prm.target_walkers = int(walkers)
+    prm.initial_walkers = 20000
+    prm.initial_shift = 40.0
+    prm.shift_damping = 0.5
+    for k, v in mods.items():
+        setattr(prm, k, v)
+    sv = F.Solver(ham, prm, F.current_stream())
+    e = grow(sv, prm.target_walkers)
+    sv.set_shift(e["proj_num"] / e["ref_pop"] if e["ref_pop"] else 0.0, 1)
+    sv.iterate(warmup)
+    ew = sv.estimates()
+    sv.reserve(int(ew["table_used"] * 1.3 * 8 / 5) + 1)
+    e0 = sv.estimates()
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sv.iterate(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e1 = sv.estimates()
+    sv.close()
+    att = e1["total_attempts"] - e0["total_attempts"]
+    log(f"[variant] {name}: {steps} iterations in {dt:.3f} s at N_w {e1['n_walkers']}, "
+        f"N_d {e1['n_dets']}")
+    return {"mode": mods, "walkers": e1["n_walkers"], "dets": e1["n_dets"],
+            "spawn_attempts_per_s": att / dt, "ms_per_step": dt * 1e3 / steps,
+            "annihilated_dets_per_s": (e1["total_spawns"] - e0["total_spawns"]) / dt}
+
+
 def copy_calibration(roctx, nbytes=1 << 30):
     """One plain streaming kernel of known traffic inside a profiled region: an elementwise
     multiply reading nbytes and writing nbytes (caches evicted first by a 2x larger fill).
@@ -490,7 +524,28 @@ def pmc_summary(path, last=0):
         print(f"{name:44s} {ctr:22s} dispatches {n:5d} mean {v:.6g}")
 
 
+def trace_summary(path):
+    """Per-kernel launches, mean and total duration from a rocprofv3 --kernel-trace
+    --stats CSV tree (its *kernel_stats.csv)."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no kernel_stats.csv under {path}")
+    rows = list(csv.DictReader(open(files[0])))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print(f"# kernel statistics of {files[0]}")
+    print(f"{'kernel':34s} {'calls':>6s} {'mean_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+    for r in rows:
+        name = r["Name"].split("(")[0].replace("fq::", "")[:34]
+        print(f"{name:34s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
+              f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
+
+
 def main():
+    if len(sys.argv) >= 3 and sys.argv[1] == "--trace-summary":
+        trace_summary(sys.argv[2])
+        return
     if len(sys.argv) >= 3 and sys.argv[1] == "--pmc-summary":
         pmc_summary(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 0)
         return
@@ -528,6 +583,8 @@ def main():
                     help="run only the serving leg and print its summary")
     ap.add_argument("--served-plain-every", type=int, default=25,
                     help="run every n-th served request alone for comparison")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the spin-coupled and restricted-space runs of the workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="add a 1 GiB elementwise multiply in its own profiled region")
     args = ap.parse_args()
@@ -585,12 +642,10 @@ def main():
 
     # timed window: the production path (graph launches)
     torch.cuda.synchronize()
-    roctx.resume()
     t0 = time.perf_counter()
     sv.iterate(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    roctx.pause()
     e1 = sv.estimates()
     dt = t1 - t0
     attempts = e1["total_attempts"] - e0["total_attempts"]
@@ -602,10 +657,15 @@ def main():
         f"N_d {e1['n_dets']}, attempts {attempts}, spawns {spawns}"
         + (" (re-bucketed inside the window)" if rebucketed else ""))
 
-    # profiling window: direct launches bracketed by events, per-kernel-group times
+    # profiling window: direct launches bracketed by events, per-kernel-group times (and
+    # the region a rocprofv3 kernel trace with --selected-regions records)
     F.fciqmc_set_profiling(sv.h, 1)
     ep0 = sv.estimates()
+    torch.cuda.synchronize()
+    roctx.resume()
     sv.iterate(args.profile_steps)
+    torch.cuda.synchronize()
+    roctx.pause()
     ep1 = sv.estimates()
     kms, kcnt = F.fciqmc_kernel_times(sv.h)
     F.fciqmc_set_profiling(sv.h, 0)
@@ -669,6 +729,14 @@ def main():
         out["gpu_over_oracle"] = out["value"] / out["cpu_baseline"]["value"]
         del det, pop
     sv.close()
+    if not args.no_variants:
+        log("[bench] sampling variants of the workload")
+        out["variants"] = {
+            "spin_coupled_even_S": variant(F, S, "spin-coupled functions", args.walkers, 150, 50,
+                                           hphf=1),
+            "cisdtq": variant(F, S, "excitation level <= 4", args.walkers, 150, 50,
+                              space=S.SPACE_EXCITATION, max_excitation=4),
+        }
     if not args.no_batched:
         log("[bench] batched vs plain (64 systems)")
         out["batched"] = batched_vs_plain(F, S, args.batched_iters, args.batched_scale,
