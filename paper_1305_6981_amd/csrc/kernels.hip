@@ -1475,13 +1475,7 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
-// Exclusive prefix over the wavefront's lanes of a per-lane count v < 8, and its
-// total, from ballots of its bits.
-__device__ __forceinline__ int wave_prefix8(int v, int lane) {
-    const uint64_t lt = lanes_below(lane);
-    return __popcll(__ballot(v & 1) & lt) + 2 * __popcll(__ballot(v & 2) & lt) +
-           4 * __popcll(__ballot(v & 4) & lt);
-}
+// Sum over the wavefront's lanes of a per-lane count v < 8, from ballots of its bits.
 __device__ __forceinline__ int wave_total8(int v) {
     return __popcll(__ballot(v & 1)) + 2 * __popcll(__ballot(v & 2)) + 4 * __popcll(__ballot(v & 4));
 }
@@ -1580,6 +1574,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
             s_bn[t] = sc >= 0 ? (int16_t)desc[sc].bcnt[(int64_t)s_cloc[t / BPC] * BPC + t % BPC] : 0;
         }
         __syncthreads();
+        // this wavefront's statistics over consecutive buckets of one system (per lane;
+        // reduced when the system changes and at the end of the window)
+        int64_t a_nw = 0, a_ab = 0, a_born = 0;
+        uint64_t a_cnt = 0;
+        double a_num = 0.0;
         for (int ci = 0; ci < nwin; ++ci) {
             const int64_t c = c0 + ci;
             const int s = s_csys[ci];
@@ -1599,19 +1598,19 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 const uint32_t nr = s_boff[ci * BPC + wid + 1] - r0;
                 // the H_DD queue serves one system at a time: the first to use it in a window
                 if (lane == 0 && s_qsys < 0) atomicCAS(&s_qsys, -1, s);
-                const int e0 = 4 * lane;
+                // entry u * 64 + lane is this lane's u-th; R rounds cover the n entries
+                const int R = (n + 63) >> 6;
                 uint64_t kin[4] = {0ull, 0ull, 0ull, 0ull};
                 int32_t pin[4] = {0, 0, 0, 0};
                 double hin[4] = {0.0, 0.0, 0.0, 0.0};
-                if (e0 < n) {
-                    const ulonglong2 k01 = gload_u2(d.key + base + e0);
-                    const ulonglong2 k23 = gload_u2(d.key + base + e0 + 2);
-                    const int4 pv = gload_i4(d.pop + base + e0);
-                    const double2 h01 = gload_d2(d.hdiag + base + e0);
-                    const double2 h23 = gload_d2(d.hdiag + base + e0 + 2);
-                    kin[0] = k01.x; kin[1] = k01.y; kin[2] = k23.x; kin[3] = k23.y;
-                    pin[0] = pv.x; pin[1] = pv.y; pin[2] = pv.z; pin[3] = pv.w;
-                    hin[0] = h01.x; hin[1] = h01.y; hin[2] = h23.x; hin[3] = h23.y;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u >= R) break;
+                    if ((u << 6) + lane < n) {
+                        kin[u] = *gp(d.key + base + (u << 6) + lane);
+                        pin[u] = *gp(d.pop + base + (u << 6) + lane);
+                        hin[u] = *gp(d.hdiag + base + (u << 6) + lane);
+                    }
                 }
                 uint64_t rd = 0ull;   // this lane's record (fast path)
                 int32_t rw = 0;
@@ -1633,8 +1632,9 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 int32_t pdv[4] = {0, 0, 0, 0};
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
+                    if (u >= R) break;
                     const int32_t p = pin[u];
-                    if (e0 + u >= n || p == 0) continue;
+                    if ((u << 6) + lane >= n || p == 0) continue;
                     uint64_t xd, xu;
                     draw2(d.seed, kin[u], 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
                     const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
@@ -1669,7 +1669,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     if (nr > 0) {
     #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            if (e0 + u >= n) continue;
+                            if (u >= R) break;
+                            if ((u << 6) + lane >= n) continue;
                             const int h = wh_find(kin[u], W.key);
                             if (h < 0) continue;
                             spv[u] = W.acc[h];
@@ -1731,7 +1732,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         }
     #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            if (e0 + u >= n) continue;
+                            if (u >= R) break;
+                            if ((u << 6) + lane >= n) continue;
                             const int h = wh_find(kin[u], W.key);
                             if (h < 0) continue;
                             spv[u] += W.acc[h];
@@ -1768,7 +1770,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                                        // spawns (new determinants kept in place)
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    if (e0 + u >= n) continue;
+                    if (u >= R) break;
+                    if ((u << 6) + lane >= n) continue;
                     const uint64_t D = kin[u];
                     const bool is_ref = D == d.d0;
                     const int64_t pd = pdv[u];
@@ -1803,15 +1806,16 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     }
                     if (np != 0 || is_ref) keepm |= 1u << u;   // the reference keeps its entry at 0
                 }
-                const int nin = e0 < n ? (n - e0 < 4 ? n - e0 : 4) : 0;
-                const int nkeep = __popc(keepm), nhole = nin - nkeep;
-                {   // positions emptied this iteration, ascending
-                    int k = wave_prefix8(nhole, lane);
+                // positions emptied this iteration, ascending (round by round, lanes in order)
+                int H = 0;
     #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (u < nin && !((keepm >> u) & 1u)) W.free_[k++] = (uint16_t)(e0 + u);
+                for (int u = 0; u < 4; ++u) {
+                    if (u >= R) break;
+                    const bool hole = (u << 6) + lane < n && !((keepm >> u) & 1u);
+                    const uint64_t m = __ballot(hole);
+                    if (hole) W.free_[H + __popcll(m & lanes_below(lane))] = (uint16_t)((u << 6) + lane);
+                    H += __popcll(m);
                 }
-                const int H = wave_total8(nhole);
                 const int Lk = n - H;
                 wave_sync();
                 // New determinants: children outside the bucket with an initiator parent go
@@ -1886,23 +1890,26 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 const int np_ = Lk + K < BQ ? Lk + K : BQ;
                 uint32_t movedm = 0u;
                 if (K < H) {   // uniform
-    #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (((keepm >> u) & 1u) && e0 + u >= np_) movedm |= 1u << u;
-                    int r = K + wave_prefix8(__popc(movedm), lane);
+                    int r = K;
     #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        if (!((movedm >> u) & 1u)) continue;
-                        const int64_t dst = base + W.free_[r++];
-                        *gp(d.key + dst) = kin[u];
-                        *gp(d.pop + dst) = npv[u];
-                        *gp(d.hdiag + dst) = hin[u];
+                        if (u >= R) break;
+                        const bool mv = ((keepm >> u) & 1u) && (u << 6) + lane >= np_;
+                        const uint64_t m = __ballot(mv);
+                        if (mv) {
+                            const int64_t dst = base + W.free_[r + __popcll(m & lanes_below(lane))];
+                            *gp(d.key + dst) = kin[u];
+                            *gp(d.pop + dst) = npv[u];
+                            *gp(d.hdiag + dst) = hin[u];
+                            movedm |= 1u << u;
+                        }
+                        r += __popcll(m);
                     }
                 }
     #pragma unroll
                 for (int u = 0; u < 4; ++u)
                     if (((keepm & ~movedm) >> u) & 1u && npv[u] != pin[u])
-                        *gp(d.pop + base + e0 + u) = npv[u];
+                        *gp(d.pop + base + (u << 6) + lane) = npv[u];
                 if (lane == 0) {
                     d.bcnt[lb] = np_;
                     cnt += (uint64_t)np_;
@@ -1926,14 +1933,26 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     }
                 }
             }
-            // fixed-order reduction per wavefront; each wavefront writes its bucket's share
-            nw = wave_sum((long long)nw);
-            aborted = wave_sum((long long)aborted);
-            cnt = wave_sum((unsigned long long)cnt);
-            num = wave_sum(num);
+            a_nw += nw;
+            a_ab += aborted;
+            a_cnt += cnt;
+            a_num = a_num + num;
+            a_born += born;
+            // the statistics share of this wavefront: its accumulated buckets when the
+            // system changes after this chunk or the window ends (fixed-order reduction),
+            // nothing otherwise
+            const bool last = ci + 1 == nwin || s_csys[ci + 1] != s;
+            ChunkStat cs{0, 0, 0ull, 0.0, 0};
+            if (last) {
+                cs = ChunkStat{(int64_t)wave_sum((long long)a_nw), (int64_t)wave_sum((long long)a_ab),
+                               (uint64_t)wave_sum((unsigned long long)a_cnt), wave_sum(a_num), a_born};
+                a_nw = a_ab = a_born = 0;
+                a_cnt = 0ull;
+                a_num = 0.0;
+            }
             nwb = wave_sum(nwb);
             if (lane == 0) {
-                a.chunk_stat[c * POST_WAVES + wid] = ChunkStat{nw, aborted, cnt, num, born};
+                a.chunk_stat[c * POST_WAVES + wid] = cs;
                 // walkers that spawn next iteration: none if the system stops after this one
                 if (s_cnext[ci] && nwb) atomicAdd(&s_cnws[ci], nwb);
                 if (atomicAdd(&s_cdone[ci], 1) == POST_WAVES - 1) {
