@@ -1369,8 +1369,11 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Home slot: a multiplicative hash of the two folded words (the determinants of one
+// bucket agree in the bits of mix64 that chose the bucket, not in these).
+static_assert(WHASH == 128, "wh_home takes the top 7 bits of the product");
 __device__ __forceinline__ uint32_t wh_home(uint64_t D) {
-    return (uint32_t)mix64(D) & (uint32_t)(WHASH - 1);
+    return (((uint32_t)D ^ (uint32_t)(D >> 32)) * 0x9E3779B1u) >> 25;
 }
 
 // Slot of D in a wavefront's hash (-1: absent). Call when no lane inserts.
@@ -1387,15 +1390,17 @@ __device__ __forceinline__ int wh_find(uint64_t D, const uint64_t *hk) {
 
 // Slot of D, claimed when absent. Lanes that race for an empty slot with the same D
 // agree on it; with different D the losers probe on. For at most WHASH - 1
-// distinct children (no limit needed).
-__device__ __forceinline__ int wh_claim(uint64_t D, uint64_t *hk) {
+// distinct children (no limit needed). *own: this lane entered D (one lane per D).
+__device__ __forceinline__ int wh_claim(uint64_t D, uint64_t *hk, bool *own) {
     uint32_t h = wh_home(D);
+    *own = false;
     for (;;) {
         const uint64_t x = hk[h];
         if (x == D) return (int)h;
         if (x == 0ull) {
             const unsigned long long old =
                 atomicCAS((unsigned long long *)&hk[h], 0ull, (unsigned long long)D);
+            *own = old == 0ull;
             if (old == 0ull || old == D) return (int)h;
         }
         h = (h + 1u) & (uint32_t)(WHASH - 1);
@@ -1612,9 +1617,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         hin[u] = *gp(d.hdiag + base + (u << 6) + lane);
                     }
                 }
-                uint64_t rd = 0ull;   // this lane's record (fast path)
-                int32_t rw = 0;
+                uint64_t rd = 0ull;   // this lane's record (fast path), its hash slot, and
+                int32_t rw = 0;       // whether this lane entered the child there
                 uint32_t rf = 0u;
+                int rh = 0;
+                bool rown = false;
                 if ((uint32_t)lane < nr && nr <= (uint32_t)NREC) {
                     const SpawnRec r = get_rec(a.srt + r0 + lane);
                     rd = r.det;
@@ -1637,7 +1644,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     if ((u << 6) + lane >= n || p == 0) continue;
                     uint64_t xd, xu;
                     draw2(d.seed, kin[u], 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
-                    const int64_t absC = p < 0 ? -(int64_t)p : (int64_t)p;
+                    const uint32_t absC = (uint32_t)(p < 0 ? -p : p);   // |p| <= 2^31 - 1
                     const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
                     const double ad = fabs(dv);
                     const double fl = floor(ad);
@@ -1645,8 +1652,9 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     if (fl > 1073741824.0) {
                         atomicOr(status, ST_POP_OVERFLOW);
                     } else {
-                        const int64_t m = (int64_t)fl + (u01(xd) < ad - fl ? 1 : 0);
-                        pd = (int64_t)p - (p > 0 ? 1 : -1) * (dv > 0.0 ? 1 : -1) * m;
+                        // m <= 2^30 + 1; C - sign(C) sign(d) m
+                        const int32_t m = (int32_t)fl + (u01(xd) < ad - fl ? 1 : 0);
+                        pd = (int64_t)p + (((p > 0) == (dv > 0.0)) ? -(int64_t)m : (int64_t)m);
                         if (pd > 2147483647ll || pd < -2147483647ll) {
                             atomicOr(status, ST_POP_OVERFLOW);
                             pd = 0;
@@ -1661,9 +1669,9 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (nr <= (uint32_t)NREC) {
                     // Fast path: at most NREC records, so at most NREC distinct children.
                     if ((uint32_t)lane < nr) {
-                        const int h = wh_claim(rd, W.key);
-                        atomicAdd((unsigned long long *)&W.acc[h], (unsigned long long)(long long)rw);
-                        if (rf & F_INIT) atomicOr(&W.flg[h], F_INIT);
+                        rh = wh_claim(rd, W.key, &rown);
+                        atomicAdd((unsigned long long *)&W.acc[rh], (unsigned long long)(long long)rw);
+                        if (rf & F_INIT) atomicOr(&W.flg[rh], F_INIT);
                     }
                     wave_sync();
                     if (nr > 0) {
@@ -1822,7 +1830,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 // to the emptied positions first, then past the end; the others are discarded.
                 int K = 0;
                 int calls = 0;
-                uint32_t nearn = 0u;   // fast path: bit i, the new determinant of slot lane + 64 i
+                uint32_t nearn = 0u;   // fast path: bit 0, this lane's new determinant
                                        // contributes to the projected energy
                 auto place = [&](uint64_t D, long long sp, bool init) {   // (all lanes; D = 0: none)
                     const bool real = D != 0ull && sp != 0;
@@ -1863,18 +1871,18 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         }
                     }
                 };
+                long long rsp = 0ll;   // fast path: walkers that arrived for this lane's child
                 if (nr <= (uint32_t)NREC) {
-                    for (int h = lane; h < WHASH; h += 64) {
-                        const uint64_t D = W.key[h];
-                        const uint32_t f = W.flg[h];
-                        const bool cand = D != 0ull && !(f & F_MATCHED);
-                        const long long sp = cand ? W.acc[h] : 0ll;
-                        if (sp > 2147483647ll || sp < -2147483647ll) {
-                            atomicOr(status, ST_POP_OVERFLOW);
-                            place(0ull, 0ll, false);
-                        } else {
-                            place(cand ? D : 0ull, sp, (f & F_INIT) != 0u);
-                        }
+                    // one lane per distinct child: the lane that entered it into the hash
+                    const uint32_t f = rown ? W.flg[rh] : F_MATCHED;
+                    const bool cand = !(f & F_MATCHED);
+                    rsp = cand ? W.acc[rh] : 0ll;
+                    if (rsp > 2147483647ll || rsp < -2147483647ll) {
+                        atomicOr(status, ST_POP_OVERFLOW);
+                        rsp = 0ll;
+                        place(0ull, 0ll, false);
+                    } else {
+                        place(cand ? rd : 0ull, rsp, (f & F_INIT) != 0u);
                     }
                 } else {
                     for (int i0 = 0; i0 < kc; i0 += 64) {
@@ -1921,9 +1929,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 for (int u = 0; u < 4; ++u)
                     if ((nearm >> u) & 1u) num = num + ref_hel(d, kin[u]) * (double)npv[u];
                 if (nr <= (uint32_t)NREC) {
-                    for (int i = 0; i < 2; ++i)
-                        if ((nearn >> i) & 1u)
-                            num = num + ref_hel(d, W.key[lane + 64 * i]) * (double)W.acc[lane + 64 * i];
+                    if (nearn & 1u) num = num + ref_hel(d, rd) * (double)rsp;
                 } else {
                     for (int i = lane; i < kc; i += 64) {
                         const uint64_t D = a.recs[r0 + i].det;
