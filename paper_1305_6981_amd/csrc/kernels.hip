@@ -1636,31 +1636,26 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 W.flg[lane + 64] = 0u;
                 // death of every entry (Eq. pdeath, one stochastic rounding for the whole
                 // determinant); it depends on nothing that arrives
+                // (branch-free over the lanes: p = 0 past the bucket's entries gives pd = 0)
                 int32_t pdv[4] = {0, 0, 0, 0};
+                bool ovf = false;   // a population left int32 (reported once for the bucket)
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (u >= R) break;
                     const int32_t p = pin[u];
-                    if ((u << 6) + lane >= n || p == 0) continue;
                     uint64_t xd, xu;
                     draw2(d.seed, kin[u], 0xFFFFFFFFu, d.iter, 0x80u, xd, xu);
                     const uint32_t absC = (uint32_t)(p < 0 ? -p : p);   // |p| <= 2^31 - 1
                     const double dv = ((hin[u] - d.e0) - d.shift) * d.tau * (double)absC;
                     const double ad = fabs(dv);
                     const double fl = floor(ad);
-                    int64_t pd = p;
-                    if (fl > 1073741824.0) {
-                        atomicOr(status, ST_POP_OVERFLOW);
-                    } else {
-                        // m <= 2^30 + 1; C - sign(C) sign(d) m
-                        const int32_t m = (int32_t)fl + (u01(xd) < ad - fl ? 1 : 0);
-                        pd = (int64_t)p + (((p > 0) == (dv > 0.0)) ? -(int64_t)m : (int64_t)m);
-                        if (pd > 2147483647ll || pd < -2147483647ll) {
-                            atomicOr(status, ST_POP_OVERFLOW);
-                            pd = 0;
-                        }
-                    }
-                    pdv[u] = (int32_t)pd;
+                    const bool big = fl > 1073741824.0;   // the entry is left as it is
+                    // m <= 2^30 + 1; C - sign(C) sign(d) m
+                    const int32_t m = (int32_t)(big ? 0.0 : fl) + (u01(xd) < ad - fl ? 1 : 0);
+                    const int64_t pm = (int64_t)p + (((p > 0) == (dv > 0.0)) ? -(int64_t)m : (int64_t)m);
+                    const bool range = pm > 2147483647ll || pm < -2147483647ll;
+                    ovf |= p != 0 && (big || range);
+                    pdv[u] = p == 0 ? 0 : big ? p : range ? 0 : (int32_t)pm;
                 }
                 wave_sync();
                 long long spv[4] = {0ll, 0ll, 0ll, 0ll};   // walkers arrived per entry
@@ -1776,44 +1771,40 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 uint32_t nearm = 0u;   // bit u: entry u contributes to the projected energy
                 int reborn = 0;        // entries emptied by death and re-entered by initiator
                                        // spawns (new determinants kept in place)
+                // (branch-free over the lanes: past the bucket's entries D = 0, and nothing
+                // arrives, so np = 0 and nothing is counted)
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (u >= R) break;
-                    if ((u << 6) + lane >= n) continue;
                     const uint64_t D = kin[u];
                     const bool is_ref = D == d.d0;
                     const int64_t pd = pdv[u];
                     // (walkers spawned onto the reference arrive in their own sum)
-                    const long long sp = spv[u] + (is_ref ? a.d0acc[s] : 0ll);
-                    int64_t np;
-                    if (pd != 0 || is_ref) {
-                        np = pd + sp;
-                    } else if (sp != 0 && ((flv >> u) & 1u)) {
-                        np = sp;
-                        ++reborn;
-                    } else {
-                        np = 0;
-                        if (sp != 0) aborted += sp < 0 ? -sp : sp;
-                    }
-                    if (sp != 0) cnt += 1ull << CNT_SHIFT_MERGED;
-                    if (np > 2147483647ll || np < -2147483647ll) {
-                        atomicOr(status, ST_POP_OVERFLOW);
-                        np = 0;
-                    }
+                    long long sp = spv[u];
+                    if (is_ref) sp += a.d0acc[s];
+                    const bool alive = pd != 0 || is_ref;
+                    const bool reb = !alive && sp != 0 && ((flv >> u) & 1u);
+                    const long long asp = sp < 0 ? -sp : sp;
+                    int64_t np = alive ? pd + sp : (reb ? sp : 0ll);
+                    reborn += reb ? 1 : 0;
+                    aborted += (!alive && !reb) ? asp : 0ll;
+                    cnt += sp != 0 ? 1ull << CNT_SHIFT_MERGED : 0ull;
+                    const bool range = np > 2147483647ll || np < -2147483647ll;
+                    ovf |= range;
+                    np = range ? 0ll : np;
                     npv[u] = (int32_t)np;
                     if (is_ref) {
                         a.c0[s] = np;
                         a.d0acc[s] = 0ll;   // consumed
                     }
-                    if (np != 0) {
-                        const int64_t an = np < 0 ? -np : np;
-                        nw += an;
-                        nwb += (unsigned long long)an;
-                        cnt += 1ull << CNT_SHIFT_ND;
-                        if (!is_ref && near_ref(d, D)) nearm |= 1u << u;
-                    }
-                    if (np != 0 || is_ref) keepm |= 1u << u;   // the reference keeps its entry at 0
+                    const int64_t an = np < 0 ? -np : np;
+                    nw += an;
+                    nwb += (unsigned long long)an;
+                    cnt += np != 0 ? 1ull << CNT_SHIFT_ND : 0ull;
+                    nearm |= (np != 0 && !is_ref && near_ref(d, D)) ? 1u << u : 0u;
+                    keepm |= (np != 0 || is_ref) ? 1u << u : 0u;   // the reference keeps its entry at 0
                 }
+                if (ovf) atomicOr(status, ST_POP_OVERFLOW);
                 // positions emptied this iteration, ascending (round by round, lanes in order)
                 int H = 0;
     #pragma unroll
