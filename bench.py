@@ -180,12 +180,12 @@ def measured_traffic(kernels):
         return None
 
 
-def issued_ops_per_attempt():
-    v = read_profile("k_spawn_valu_synth24e30o.txt")
+def issued_ops_per(kern, unit):
+    v = read_profile(f"{kern}_valu_synth24e30o.txt")
     if v is None:
         return None
     try:
-        return float(v["issued_lane_ops_per_attempt"])
+        return float(v[f"issued_lane_ops_per_{unit}"])
     except KeyError:
         return None
 
@@ -487,31 +487,36 @@ def write_traffic(fetch_dir, write_dir, last, command):
             out.write(ln)
 
 
-def write_valu(counter_dir, last, attempts_per_launch, command):
-    """profiles/k_spawn_valu_synth24e30o.txt: issued VALU lane-operations per attempt of
-    k_spawn (SQ_INSTS_VALU x 64 / attempts) and its LDS bank-conflict share."""
+def write_valu(counter_dir, last, attempts_per_launch, dets_per_launch, command):
+    """profiles/k_spawn_valu_synth24e30o.txt and profiles/k_post_valu_synth24e30o.txt:
+    issued VALU lane-operations (SQ_INSTS_VALU x 64) per attempt of k_spawn and per
+    determinant of k_post, with the other instruction counters and the LDS
+    bank-conflict share."""
     m = pmc_means(counter_dir, last)
-
-    def get(c):
-        v = [x for (k, cc), x in m.items() if k.endswith("::k_spawn") and cc == c]
-        return v[0][0] if v else float("nan")
-    valu = get("SQ_INSTS_VALU")
-    with open(os.path.join(PROFILES, "k_spawn_valu_synth24e30o.txt"), "w") as out:
-        out.write("# k_spawn instruction counters (rocprofv3 --pmc, per dispatch, mean of the last\n"
-                  f"# {last} dispatches = the profiling window's iterations).\n"
-                  "# Commands (repository root, one MI355X):\n")
-        for c in command:
-            out.write(f"#   {c}\n")
-        out.write(f"kernels_sha256: {kernel_source_hash()}\n"
-                  f"attempts_per_launch: {attempts_per_launch:.6g}\n")
-        for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
-                  "SQ_INSTS_VMEM_WR", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT",
-                  "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"):
-            out.write(f"{c}: {get(c):.6g}\n")
-        out.write(f"issued_lane_ops_per_attempt: {valu * 64.0 / attempts_per_launch:.4g}\n"
-                  f"lds_bank_conflict_share: "
-                  f"{get('SQ_LDS_BANK_CONFLICT') / max(get('SQ_ACTIVE_INST_LDS'), 1.0):.4g}\n")
-    print(f"k_spawn: {valu * 64.0 / attempts_per_launch:.1f} issued lane-ops per attempt")
+    for kern, unit, units in (("k_spawn", "attempt", attempts_per_launch),
+                              ("k_post", "det", dets_per_launch)):
+        def get(c):
+            v = [x for (k, cc), x in m.items() if k.endswith("::" + kern) and cc == c]
+            return v[0][0] if v else float("nan")
+        valu = get("SQ_INSTS_VALU")
+        with open(os.path.join(PROFILES, f"{kern}_valu_synth24e30o.txt"), "w") as out:
+            out.write(f"# {kern} instruction counters (rocprofv3 --pmc, per dispatch, mean of the\n"
+                      f"# last {last} dispatches = the profiling window's iterations); per {unit}:\n"
+                      f"# SQ_INSTS_VALU x 64 / {unit}s per launch.\n"
+                      "# Commands (repository root, one MI355X):\n")
+            for c in command:
+                out.write(f"#   {c}\n")
+            out.write(f"kernels_sha256: {kernel_source_hash()}\n"
+                      f"{unit}s_per_launch: {units:.6g}\n")
+            for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+                      "SQ_INSTS_VMEM_WR", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT",
+                      "SQ_WAVE_CYCLES"):
+                out.write(f"{c}: {get(c):.6g}\n")
+            out.write(f"issued_lane_ops_per_{unit}: {valu * 64.0 / units:.4g}\n"
+                      f"salu_per_{unit}: {get('SQ_INSTS_SALU') * 64.0 / units:.4g}\n"
+                      f"lds_bank_conflict_share: "
+                      f"{get('SQ_LDS_BANK_CONFLICT') / max(get('SQ_ACTIVE_INST_LDS'), 1.0):.4g}\n")
+        print(f"{kern}: {valu * 64.0 / units:.1f} issued lane-ops per {unit}")
 
 
 def pmc_summary(path, last=0):
@@ -553,9 +558,10 @@ def main():
         # --write-traffic FETCH_DIR WRITE_DIR LAST [command lines ...]
         write_traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5:])
         return
-    if len(sys.argv) >= 5 and sys.argv[1] == "--write-valu":
-        # --write-valu COUNTER_DIR LAST ATTEMPTS_PER_LAUNCH [command lines ...]
-        write_valu(sys.argv[2], int(sys.argv[3]), float(sys.argv[4]), sys.argv[5:])
+    if len(sys.argv) >= 6 and sys.argv[1] == "--write-valu":
+        # --write-valu COUNTER_DIR LAST ATTEMPTS_PER_LAUNCH DETS_PER_LAUNCH [command lines ...]
+        write_valu(sys.argv[2], int(sys.argv[3]), float(sys.argv[4]), float(sys.argv[5]),
+                   sys.argv[6:])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -680,7 +686,7 @@ def main():
 
     spawn_ms = grp_ms["spawn"]
     achieved_ops = OPS_PER_ATTEMPT * att_launch / (spawn_ms * 1e-3) / 1e12
-    issued = issued_ops_per_attempt()
+    issued = issued_ops_per("k_spawn", "attempt")
     roofline = {"bound": "alu", "kernel": "k_spawn", "achieved": achieved_ops,
                 "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved_ops / ALU_PEAK_TOPS,
                 "traffic": measured_traffic(GROUP_KERNELS["spawn"]),
@@ -697,7 +703,8 @@ def main():
                     "traffic": measured_traffic(GROUP_KERNELS["annihilation"]),
                     "algorithmic_bytes": b_group, "k_post_algorithmic_bytes": b_post,
                     "avg_ms": ann_ms, "measured_copy_gbs": copy_gbs,
-                    "frac_of_measured_copy": ach / copy_gbs}
+                    "frac_of_measured_copy": ach / copy_gbs,
+                    "k_post_issued_lane_ops_per_det": issued_ops_per("k_post", "det")}
 
     mean = lambda k: float(np.mean([r[k] for r in win]))  # noqa: E731
     out = {
