@@ -1,10 +1,11 @@
 // HIP kernels of the FCIQMC iteration (Booth, Smart & Alavi, arXiv:1305.6981)
 // for gfx950.
 //
-// The main list of a system is hash-partitioned into buckets of at most 1024
+// The main list of a system is hash-partitioned into buckets of at most 256
 // densely packed entries (determinant, population, stored H_DD): the paper's
 // distribution of determinants over processes by a hash (Sec. 4.1), with a
-// workgroup in the role of a process. One iteration of every active system is
+// wavefront in the role of a process. Four consecutive buckets form a chunk,
+// the unit of attempt mapping. One iteration of every active system is
 // eleven launches (twelve in the first iteration of a launch sequence):
 //
 //   k_chunk_sum   sum |C| over each bucket and over fixed contiguous ranges of
@@ -21,7 +22,7 @@
 //   k_bscan_*     exclusive scan of the records per bucket (range totals, their
 //                 scan, then the scan inside each range)
 //   k_scatter     the records grouped by bucket (a counting sort)
-//   k_post        per bucket, by one workgroup: the records merged per child in
+//   k_post        per bucket, by one wavefront: the records merged per child in
 //                 an LDS hash (the sort and compress of Sec. 4.1); death/cloning
 //                 of every entry (Eq. pdeath); annihilation with the initiator
 //                 test for children that are unoccupied after death (Sec. 4.2);
