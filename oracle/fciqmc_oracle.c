@@ -68,6 +68,20 @@ static int fail(const char *msg)
 const char *orc_last_error(void) { return g_err; }
 
 /* ------------------------------------------------------------------------ */
+/* Determinants (Sec. 3): bit p set when spin orbital p is occupied, in as   */
+/* many 64-bit words as the spin orbitals need (one up to 64, two up to 128). */
+/* Held here as one 128-bit integer; in the API as 1 or 2 words, low first.  */
+/* ------------------------------------------------------------------------ */
+typedef unsigned __int128 det_t;
+#define MAX_SO 128
+#define MAX_ORB 64
+#define DBIT(p) ((det_t)1 << (p))
+
+static uint64_t det_lo(det_t d) { return (uint64_t)d; }
+static uint64_t det_hi(det_t d) { return (uint64_t)(d >> 64); }
+static det_t det_make(uint64_t lo, uint64_t hi) { return ((det_t)hi << 64) | (det_t)lo; }
+
+/* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).                       */
 /* Each round: two 32x32->64 products of counter words 0 and 2 with the      */
 /* round multipliers; the new counter is (hi1^c1^k0, lo1, hi0^c3^k1, lo0).   */
@@ -98,23 +112,26 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 /* Random-number contract (a reading: the paper uses a Mersenne Twister).
- * key = (lo32(seed), hi32(seed)); counter = (lo32(D), hi32(D), k, ((n mod 2^24) << 8) | block).
+ * key = (lo32(K), hi32(K)) with K = seed XOR (bits 64..127 of D);
+ * counter = (bits 0..31 of D, bits 32..63 of D, k, ((n mod 2^24) << 8) | block).
+ * (For determinants of at most 64 spin orbitals K is the seed.)
  * Spawn attempt k on D at iteration n:
  *   block 0 -> x0 (excitation type), x1 (electron or electron pair)
  *   block 1 -> x2 (orbital a), x3 (orbital b)
  *   block 2 -> x4 (acceptance)
  * Death on D: k = 0xFFFFFFFF, block 0x80 -> x0.
  * A 64-bit draw is (w[2j+1] << 32) | w[2j]. */
-static void draw_block(uint64_t seed, uint64_t det, uint32_t k, int64_t iter, uint32_t block,
+static void draw_block(uint64_t seed, det_t det, uint32_t k, int64_t iter, uint32_t block,
                        uint64_t x[2])
 {
     uint32_t ctr[4], key[2], w[4];
-    ctr[0] = (uint32_t)det;
-    ctr[1] = (uint32_t)(det >> 32);
+    const uint64_t lo = det_lo(det), kk = seed ^ det_hi(det);
+    ctr[0] = (uint32_t)lo;
+    ctr[1] = (uint32_t)(lo >> 32);
     ctr[2] = k;
     ctr[3] = ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block;
-    key[0] = (uint32_t)seed;
-    key[1] = (uint32_t)(seed >> 32);
+    key[0] = (uint32_t)kk;
+    key[1] = (uint32_t)(kk >> 32);
     orc_philox4x32_10(ctr, key, w);
     x[0] = ((uint64_t)w[1] << 32) | (uint64_t)w[0];
     x[1] = ((uint64_t)w[3] << 32) | (uint64_t)w[2];
@@ -128,16 +145,17 @@ static double unit_uniform(uint64_t x)
 
 /* The four 32-bit words of one Philox block, for a spawning attempt: word 0
  * decides the type (and, rescaled, the acceptance), words 1-3 the orbitals. */
-static void draw_words(uint64_t seed, uint64_t det, uint32_t k, int64_t iter, uint32_t block,
+static void draw_words(uint64_t seed, det_t det, uint32_t k, int64_t iter, uint32_t block,
                        uint32_t w[4])
 {
     uint32_t ctr[4], key[2];
-    ctr[0] = (uint32_t)det;
-    ctr[1] = (uint32_t)(det >> 32);
+    const uint64_t lo = det_lo(det), kk = seed ^ det_hi(det);
+    ctr[0] = (uint32_t)lo;
+    ctr[1] = (uint32_t)(lo >> 32);
     ctr[2] = k;
     ctr[3] = ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block;
-    key[0] = (uint32_t)seed;
-    key[1] = (uint32_t)(seed >> 32);
+    key[0] = (uint32_t)kk;
+    key[1] = (uint32_t)(kk >> 32);
     orc_philox4x32_10(ctr, key, w);
 }
 
@@ -199,11 +217,11 @@ static void build_lut(void)
     g_lut_ready = 1;
 }
 
-int orc_decode(uint64_t det, int32_t *occ)
+static int decode_det(det_t det, int32_t *occ)
 {
     build_lut();
     int n = 0;
-    for (int byte = 0; byte < 8; byte++) {
+    for (int byte = 0; byte < 16; byte++) {
         unsigned v = (unsigned)((det >> (8 * byte)) & 0xFFu);
         if (!v)
             continue;
@@ -213,7 +231,12 @@ int orc_decode(uint64_t det, int32_t *occ)
     return n;
 }
 
-static int popcount64(uint64_t x)
+int orc_decode(const uint64_t *det, int32_t words, int32_t *occ)
+{
+    return decode_det(det_make(det[0], words > 1 ? det[1] : 0), occ);
+}
+
+static int popcount64(det_t x)
 {
     int c = 0;
     while (x) {
@@ -230,12 +253,12 @@ typedef struct {
     int M, N, n_alpha, n_beta, n_so;
     double e_core;
     double *h1, *eri;
-    int irrep[32];
+    int irrep[MAX_ORB];
     int n_class;
-    int class_of[64];
+    int class_of[MAX_SO];
     double p_double, p_single;
     double inv_p_double, inv_p_single;   /* 1/P_double, 1/P_single (0 when the type is impossible) */
-    uint64_t d0;
+    det_t d0;
     double e0;
     int hphf;                 /* 0, or the spin parity (+1 even S, -1 odd S) of the
                                  spin-coupled functions (Sec. 5.3) */
@@ -279,7 +302,7 @@ static double h_so(const sys_t *s, int p, int q)
 }
 
 /* Number of occupied orbitals strictly between p and a. */
-static int n_between(uint64_t det, int p, int a)
+static int n_between(det_t det, int p, int a)
 {
     int lo = p < a ? p : a, hi = p < a ? a : p;
     int c = 0;
@@ -290,10 +313,10 @@ static int n_between(uint64_t det, int p, int a)
 }
 
 /* Diagonal element: E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)]. */
-static double hdiag_of(const sys_t *s, uint64_t det)
+static double hdiag_of(const sys_t *s, det_t det)
 {
-    int32_t occ[64];
-    int n = orc_decode(det, occ);
+    int32_t occ[MAX_SO];
+    int n = decode_det(det, occ);
     double acc = s->e_core;
     for (int i = 0; i < n; i++)
         acc = acc + h_so(s, occ[i], occ[i]);
@@ -305,10 +328,10 @@ static double hdiag_of(const sys_t *s, uint64_t det)
 }
 
 /* Single excitation p -> a from det: sign * (h_pa + sum_{q occ, q != p} [(pa|qq) - (pq|qa)]). */
-static double hel_single(const sys_t *s, uint64_t det, int p, int a)
+static double hel_single(const sys_t *s, det_t det, int p, int a)
 {
-    int32_t occ[64];
-    int n = orc_decode(det, occ);
+    int32_t occ[MAX_SO];
+    int n = decode_det(det, occ);
     double acc = h_so(s, p, a);
     for (int i = 0; i < n; i++) {
         int q = occ[i];
@@ -324,7 +347,7 @@ static double hel_single(const sys_t *s, uint64_t det, int p, int a)
 /* Double excitation p,q -> a,b (p<q occupied; a,b empty).
  * Pairing: for unlike spins a' carries the spin of p; for like spins a' = min(a, b).
  * Sign: parity of q -> b' on det, times parity of p -> a' on the result. */
-static double hel_double(const sys_t *s, uint64_t det, int p, int q, int a, int b)
+static double hel_double(const sys_t *s, det_t det, int p, int q, int a, int b)
 {
     int ap, bp;
     if ((p & 1) != (q & 1)) {
@@ -340,18 +363,18 @@ static double hel_double(const sys_t *s, uint64_t det, int p, int q, int a, int 
         bp = a < b ? b : a;
     }
     int nsw = n_between(det, q, bp);
-    uint64_t d1 = (det & ~(1ull << q)) | (1ull << bp);
+    det_t d1 = (det & ~DBIT(q)) | DBIT(bp);
     nsw += n_between(d1, p, ap);
     double v = eri_so(s, p, ap, q, bp) - eri_so(s, p, bp, q, ap);
     return (nsw & 1) ? -v : v;
 }
 
 /* <bra|H|ket>, ket taken as the source of the excitation. */
-static double hel_general(const sys_t *s, uint64_t bra, uint64_t ket)
+static double hel_general(const sys_t *s, det_t bra, det_t ket)
 {
     if (popcount64(bra) != popcount64(ket))
         return 0.0;
-    uint64_t diff = bra ^ ket;
+    det_t diff = bra ^ ket;
     int nd = popcount64(diff);
     if (nd == 0)
         return hdiag_of(s, ket);
@@ -376,16 +399,16 @@ static double hel_general(const sys_t *s, uint64_t bra, uint64_t ket)
 /* Symmetry classes: (irrep, spin); class id = 2*irrep + spin.               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    uint64_t det;
+    det_t det;
     int n;
-    int32_t occ[64];
+    int32_t occ[MAX_SO];
     int n_unocc[16];
 } detinfo_t;
 
-static void det_setup(const sys_t *s, uint64_t det, detinfo_t *di)
+static void det_setup(const sys_t *s, det_t det, detinfo_t *di)
 {
     di->det = det;
-    di->n = orc_decode(det, di->occ);
+    di->n = decode_det(det, di->occ);
     for (int c = 0; c < 16; c++)
         di->n_unocc[c] = 0;
     for (int r = 0; r < s->n_so; r++)
@@ -416,7 +439,7 @@ static int partner_ok(const sys_t *s, int p, int q, int x, int y)
 }
 
 typedef struct {
-    uint64_t det;   /* 0 = null excitation */
+    det_t det;      /* 0 = null excitation */
     double pgen;
     double hel;
 } excit_t;
@@ -425,14 +448,14 @@ typedef struct {
 static void gen_excit(const sys_t *s, const detinfo_t *di, const uint32_t w[4], excit_t *out)
 {
     const int N = di->n;
-    const uint64_t det = di->det;
+    const det_t det = di->det;
     out->det = 0;
     out->pgen = 0.0;
     out->hel = 0.0;
     int is_double = unit_uniform32(w[0]) < s->p_double;
     if (!is_double) {
         /* Sec. 5.1: renormalise over the electrons that have an allowed a. */
-        int n_allow[64], delta_s = 0;
+        int n_allow[MAX_SO], delta_s = 0;
         for (int e = 0; e < N; e++) {
             n_allow[e] = di->n_unocc[s->class_of[di->occ[e]]];
             if (n_allow[e] == 0)
@@ -464,7 +487,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint32_t w[4], 
             }
             ka--;
         }
-        out->det = det ^ (1ull << p) ^ (1ull << a);
+        out->det = det ^ DBIT(p) ^ DBIT(a);
         out->pgen = s->p_single / (double)((int64_t)n_allow[esel] * (int64_t)(N - delta_s));
         out->hel = hel_single(s, det, p, a);
         return;
@@ -523,7 +546,7 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint32_t w[4], 
         kb--;
     }
     int nbb = n_partner(s, di, p, q, b);
-    out->det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
+    out->det = det ^ DBIT(p) ^ DBIT(q) ^ DBIT(a) ^ DBIT(b);
     out->pgen = (2.0 * s->p_double * (1.0 / (double)nba + 1.0 / (double)nbb)) /
                 (double)((int64_t)N * (N - 1) * (int64_t)(n_a_set - delta_d));
     out->hel = hel_double(s, det, p, q, a, b);
@@ -533,13 +556,13 @@ static void gen_excit(const sys_t *s, const detinfo_t *di, const uint32_t w[4], 
  * single-excitation probability of Sec. 5.1 or the double-excitation formula of
  * Sec. 5.2 for the excitation that turns the determinant into T, 0 when T is not
  * a single or double excitation the generator can draw. */
-static double pgen_of(const sys_t *s, const detinfo_t *di, uint64_t T)
+static double pgen_of(const sys_t *s, const detinfo_t *di, det_t T)
 {
-    const uint64_t det = di->det;
+    const det_t det = di->det;
     const int N = di->n;
     if (popcount64(T) != popcount64(det))
         return 0.0;
-    const uint64_t from = det & ~T, to = T & ~det;
+    const det_t from = det & ~T, to = T & ~det;
     const int nf = popcount64(from);
     int f[2], t[2], k = 0, m = 0;
     for (int r = 0; r < s->n_so; r++) {
@@ -593,15 +616,15 @@ static double pgen_of(const sys_t *s, const detinfo_t *di, uint64_t T)
 /* doubly occupied) is |D> itself and belongs to even S only. A function is    */
 /* stored as min(D, D~).                                                        */
 /* ------------------------------------------------------------------------ */
-#define EVEN_BITS 0x5555555555555555ull
+#define EVEN_BITS det_make(0x5555555555555555ull, 0x5555555555555555ull)
 
-static uint64_t spin_flip(uint64_t D) { return ((D & EVEN_BITS) << 1) | ((D >> 1) & EVEN_BITS); }
+static det_t spin_flip(det_t D) { return ((D & EVEN_BITS) << 1) | ((D >> 1) & EVEN_BITS); }
 
-static int n_doubly(uint64_t D) { return popcount64(D & (D >> 1) & EVEN_BITS); }
+static int n_doubly(det_t D) { return popcount64(D & (D >> 1) & EVEN_BITS); }
 
-static uint64_t hphf_rep(uint64_t D)
+static det_t hphf_rep(det_t D)
 {
-    uint64_t f = spin_flip(D);
+    det_t f = spin_flip(D);
     return f < D ? f : D;
 }
 
@@ -609,9 +632,9 @@ static uint64_t hphf_rep(uint64_t D)
  * excitation, Dj != Di). Both open: <Dj|H|Di> + lam (-1)^{n2(Dj)} <Dj~|H|Di>; one
  * closed: sqrt2 <Dj|H|Di> (the other term equals the first); both closed:
  * <Dj|H|Di>. Every element is evaluated with Di as the source. */
-static double hphf_hel(const sys_t *s, uint64_t Di, uint64_t Dj)
+static double hphf_hel(const sys_t *s, det_t Di, det_t Dj)
 {
-    const uint64_t fi = spin_flip(Di), fj = spin_flip(Dj);
+    const det_t fi = spin_flip(Di), fj = spin_flip(Dj);
     const double h = hel_general(s, Dj, Di);
     if (fi != Di && fj != Dj) {
         const int sg = (n_doubly(Dj) & 1) ? -s->lam : s->lam;
@@ -624,12 +647,12 @@ static double hphf_hel(const sys_t *s, uint64_t Di, uint64_t Dj)
 
 /* Diagonal element of the stored function D (of the determinant D without
  * spin-coupled functions). */
-static double fdiag(const sys_t *s, uint64_t D)
+static double fdiag(const sys_t *s, det_t D)
 {
     const double h = hdiag_of(s, D);
     if (!s->hphf)
         return h;
-    const uint64_t f = spin_flip(D);
+    const det_t f = spin_flip(D);
     if (f == D)
         return h;
     const int sg = (n_doubly(D) & 1) ? -s->lam : s->lam;
@@ -637,7 +660,7 @@ static double fdiag(const sys_t *s, uint64_t D)
 }
 
 /* <Phi_0|H|Phi_D> for the projected energy, 0 beyond double excitations. */
-static double ref_hel(const sys_t *s, uint64_t D)
+static double ref_hel(const sys_t *s, det_t D)
 {
     if (!s->hphf)
         return popcount64(D ^ s->d0) <= 4 ? hel_general(s, D, s->d0) : 0.0;
@@ -648,10 +671,10 @@ static double ref_hel(const sys_t *s, uint64_t D)
 
 /* Counts of symmetry-allowed single and double excitations from a determinant,
  * by enumeration (used to fix P_double from the reference, Sec. 5). */
-static void count_excitations(const sys_t *s, uint64_t det, int64_t *n_single, int64_t *n_double)
+static void count_excitations(const sys_t *s, det_t det, int64_t *n_single, int64_t *n_double)
 {
-    int32_t occ[64];
-    int n = orc_decode(det, occ);
+    int32_t occ[MAX_SO];
+    int n = decode_det(det, occ);
     int64_t ns = 0, nd = 0;
     for (int e = 0; e < n; e++)
         for (int r = 0; r < s->n_so; r++)
@@ -685,7 +708,7 @@ static void count_excitations(const sys_t *s, uint64_t det, int64_t *n_single, i
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int64_t cap, high;        /* storage size; one past the highest slot ever used */
-    uint64_t *det;            /* 0 = vacant */
+    det_t *det;               /* 0 = vacant */
     int32_t *pop;
     double *hdiag;
     int64_t *next;            /* chain link */
@@ -694,7 +717,7 @@ typedef struct {
     int64_t *ring;            /* circular list of vacant slots */
     int64_t ring_head, ring_count;
     int64_t n_entries;
-    int64_t map[64];          /* Algorithm 1 random orbital map */
+    int64_t map[MAX_SO];      /* Algorithm 1 random orbital map */
 } mainlist_t;
 
 static int64_t hash_alg1(const int64_t *map, const int32_t *occ, int n, int64_t range)
@@ -706,10 +729,10 @@ static int64_t hash_alg1(const int64_t *map, const int32_t *occ, int n, int64_t 
     return r < 0 ? -r : r;
 }
 
-static int64_t ml_hash(const mainlist_t *ml, uint64_t det)
+static int64_t ml_hash(const mainlist_t *ml, det_t det)
 {
-    int32_t occ[64];
-    int n = orc_decode(det, occ);
+    int32_t occ[MAX_SO];
+    int n = decode_det(det, occ);
     return hash_alg1(ml->map, occ, n, ml->range);
 }
 
@@ -722,10 +745,10 @@ static uint64_t splitmix64(uint64_t *state)
 }
 
 /* A 1-to-1 map from spin orbitals to distinct random integers (Algorithm 1). */
-static void make_map(int64_t map[64], uint64_t seed)
+static void make_map(int64_t map[MAX_SO], uint64_t seed)
 {
     uint64_t st = seed;
-    for (int r = 0; r < 64; r++) {
+    for (int r = 0; r < MAX_SO; r++) {
         for (;;) {
             int64_t v = (int64_t)(splitmix64(&st) >> 2);
             int dup = 0;
@@ -745,7 +768,7 @@ static int ml_init(mainlist_t *ml, int64_t cap, int64_t range, uint64_t hash_see
     memset(ml, 0, sizeof *ml);
     ml->cap = cap;
     ml->range = range;
-    ml->det = calloc((size_t)cap, sizeof(uint64_t));
+    ml->det = calloc((size_t)cap, sizeof(det_t));
     ml->pop = calloc((size_t)cap, sizeof(int32_t));
     ml->hdiag = calloc((size_t)cap, sizeof(double));
     ml->next = malloc((size_t)cap * sizeof(int64_t));
@@ -770,7 +793,7 @@ static void ml_free(mainlist_t *ml)
     memset(ml, 0, sizeof *ml);
 }
 
-static int64_t ml_find(const mainlist_t *ml, uint64_t det)
+static int64_t ml_find(const mainlist_t *ml, det_t det)
 {
     int64_t h = ml_hash(ml, det);
     for (int64_t i = ml->head[h]; i >= 0; i = ml->next[i])
@@ -805,7 +828,7 @@ static int ml_rehash(mainlist_t *ml, int64_t new_range)
 static int ml_grow(mainlist_t *ml)
 {
     int64_t nc = ml->cap * 2;
-    uint64_t *d = realloc(ml->det, (size_t)nc * sizeof(uint64_t));
+    det_t *d = realloc(ml->det, (size_t)nc * sizeof(det_t));
     if (!d)
         return fail("oracle: out of host memory");
     ml->det = d;
@@ -840,7 +863,7 @@ static int ml_grow(mainlist_t *ml)
 }
 
 /* Insert into the earliest vacancy recorded in the circular list, else past the end. */
-static int64_t ml_insert(mainlist_t *ml, uint64_t det, int32_t pop, double hd)
+static int64_t ml_insert(mainlist_t *ml, det_t det, int32_t pop, double hd)
 {
     int64_t slot;
     if (ml->ring_count > 0) {
@@ -880,7 +903,7 @@ static void ml_remove(mainlist_t *ml, int64_t slot)
 /* Whole state.                                                              */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    uint64_t det;
+    det_t det;
     int64_t pop;
     uint32_t flag;
 } spawn_t;
@@ -910,7 +933,8 @@ struct orc_state {
     proc_t *proc;
     const uint64_t *load_det;     /* walker list being loaded (during orc_load_walkers) */
     const int32_t *load_pop;
-    int64_t pmap[64];         /* Algorithm 1 map of the process hash */
+    int64_t pmap[MAX_SO];     /* Algorithm 1 map of the process hash */
+    int W;                    /* 64-bit words per determinant in the API (1 or 2) */
     /* dynamics */
     int64_t iter;
     double shift;
@@ -924,13 +948,29 @@ struct orc_state {
     int64_t n_series, cap_series;
 };
 
+/* A determinant given in the API's W words (low word first), and back. */
+static det_t det_in(const orc_state *st, const uint64_t *w)
+{
+    return det_make(w[0], st->W > 1 ? w[1] : 0);
+}
+static void det_out(const orc_state *st, det_t d, uint64_t *w)
+{
+    w[0] = det_lo(d);
+    if (st->W > 1)
+        w[1] = det_hi(d);
+}
+static det_t load_det_at(const orc_state *st, int64_t t)
+{
+    return det_in(st, st->load_det + t * st->W);
+}
+
 static int cmp_spawn(const void *a, const void *b)
 {
-    uint64_t x = ((const spawn_t *)a)->det, y = ((const spawn_t *)b)->det;
+    det_t x = ((const spawn_t *)a)->det, y = ((const spawn_t *)b)->det;
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
-static int push_rec(spawn_t **buf, int64_t *n, int64_t *cap, uint64_t det, int64_t pop,
+static int push_rec(spawn_t **buf, int64_t *n, int64_t *cap, det_t det, int64_t pop,
                     uint32_t flag)
 {
     if (*n == *cap) {
@@ -951,7 +991,7 @@ static int push_rec(spawn_t **buf, int64_t *n, int64_t *cap, uint64_t det, int64
 /* Owning process of a determinant: the process hash of Sec. 4.1 (Algorithm 1
  * with its own map, over the range of processes); with a dedicated reference
  * process, the reference sits on process 0 and the rest hash over 1..P-1. */
-static int owner_of(const orc_state *st, uint64_t det)
+static int owner_of(const orc_state *st, det_t det)
 {
     if (st->n_procs == 1)
         return 0;
@@ -961,8 +1001,8 @@ static int owner_of(const orc_state *st, uint64_t det)
             return 0;
         lo = 1;
     }
-    int32_t occ[64];
-    int n = orc_decode(det, occ);
+    int32_t occ[MAX_SO];
+    int n = decode_det(det, occ);
     return lo + (int)hash_alg1(st->pmap, occ, n, st->n_procs - lo);
 }
 
@@ -993,8 +1033,8 @@ static int push_series(orc_state *st, double num, double den, double shift)
 static int sys_init(sys_t *s, const orc_ham *h)
 {
     memset(s, 0, sizeof *s);
-    if (h->n_orb <= 0 || 2 * h->n_orb > 64)
-        return fail("oracle: need 1 <= n_orb <= 32");
+    if (h->n_orb <= 0 || 2 * h->n_orb > MAX_SO)
+        return fail("oracle: need 1 <= n_orb <= 64");
     if (h->n_alpha < 0 || h->n_beta < 0 || h->n_alpha > h->n_orb || h->n_beta > h->n_orb ||
         h->n_alpha + h->n_beta == 0)
         return fail("oracle: bad electron counts");
@@ -1027,7 +1067,7 @@ static int sys_init(sys_t *s, const orc_ham *h)
         s->class_of[r] = class_id(s->irrep[r >> 1], r & 1);
     /* Reference determinant. */
     if (h->ref_det) {
-        s->d0 = *h->ref_det;
+        s->d0 = det_make(h->ref_det[0], s->n_so > 64 ? h->ref_det[1] : 0);
         uint64_t a = 0, b = 0;
         for (int r = 0; r < s->n_so; r++)
             if ((s->d0 >> r) & 1u) {
@@ -1036,11 +1076,11 @@ static int sys_init(sys_t *s, const orc_ham *h)
                 else
                     a++;
             }
-        if ((s->n_so < 64 && (s->d0 >> s->n_so) != 0) || (int)a != s->n_alpha ||
+        if ((s->n_so < MAX_SO && (s->d0 >> s->n_so) != 0) || (int)a != s->n_alpha ||
             (int)b != s->n_beta)
             return fail("oracle: reference determinant does not match the electron counts");
     } else {
-        int order[32];
+        int order[MAX_ORB];
         for (int r = 0; r < s->M; r++)
             order[r] = r;
         for (int r = 1; r < s->M; r++) {          /* insertion sort by (h_pp, index) */
@@ -1053,9 +1093,9 @@ static int sys_init(sys_t *s, const orc_ham *h)
         }
         s->d0 = 0;
         for (int r = 0; r < s->n_alpha; r++)
-            s->d0 |= 1ull << (2 * order[r]);
+            s->d0 |= DBIT(2 * order[r]);
         for (int r = 0; r < s->n_beta; r++)
-            s->d0 |= 1ull << (2 * order[r] + 1);
+            s->d0 |= DBIT(2 * order[r] + 1);
     }
     s->e0 = hdiag_of(s, s->d0);
     if (h->p_double >= 0.0) {
@@ -1218,19 +1258,28 @@ static int procs_init(orc_state *st, int64_t range)
  * treated as a null excitation). The excitation level counts the electrons of D
  * outside the reference's orbitals; the seniority counts the spatial orbitals that
  * hold exactly one electron. */
-static int in_space(const orc_params *prm, uint64_t d0, uint64_t D)
+static det_t frozen_occ(const orc_params *prm)
+{
+    return det_make(prm->frozen_occupied, prm->frozen_occupied_hi);
+}
+static det_t frozen_emp(const orc_params *prm)
+{
+    return det_make(prm->frozen_empty, prm->frozen_empty_hi);
+}
+
+static int in_space(const orc_params *prm, det_t d0, det_t D)
 {
     if ((prm->space & ORC_SPACE_EXCITATION) && popcount64(D & ~d0) > prm->max_excitation)
         return 0;
     if (prm->space & ORC_SPACE_SENIORITY) {
         int single = 0;
-        for (int s = 0; s < 32; s++)
+        for (int s = 0; s < MAX_ORB; s++)
             single += (int)(((D >> (2 * s)) & 1u) != ((D >> (2 * s + 1)) & 1u));
         if (single > prm->max_seniority)
             return 0;
     }
     if ((prm->space & ORC_SPACE_FROZEN) &&
-        ((D & prm->frozen_occupied) != prm->frozen_occupied || (D & prm->frozen_empty)))
+        ((D & frozen_occ(prm)) != frozen_occ(prm) || (D & frozen_emp(prm))))
         return 0;
     return 1;
 }
@@ -1252,7 +1301,7 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
         return fail("oracle: unknown space restriction");
     if (((prm->space & ORC_SPACE_EXCITATION) && prm->max_excitation < 0) ||
         ((prm->space & ORC_SPACE_SENIORITY) && prm->max_seniority < 0) ||
-        ((prm->space & ORC_SPACE_FROZEN) && (prm->frozen_occupied & prm->frozen_empty)))
+        ((prm->space & ORC_SPACE_FROZEN) && (frozen_occ(prm) & frozen_emp(prm))))
         return fail("oracle: inconsistent space restriction");
     orc_state *st = calloc(1, sizeof *st);
     if (!st)
@@ -1265,6 +1314,11 @@ int orc_create(const orc_ham *ham, const orc_params *prm, orc_state **out)
     }
     st->prm = *prm;
     const char *why = NULL;
+    st->W = st->sys.n_so > 64 ? 2 : 1;
+    if (prm->det_words == 2)
+        st->W = 2;
+    else if (prm->det_words != 0 && !(prm->det_words == 1 && st->W == 1))
+        why = "oracle: det_words must be 0, 1 (at most 64 spin orbitals) or 2";
     if (!in_space(prm, st->sys.d0, st->sys.d0))
         why = "oracle: the reference is outside the restricted space";
     if (prm->hphf) {
@@ -1324,7 +1378,7 @@ void orc_free(orc_state *st)
     free(st);
 }
 
-static int is_initiator(const orc_state *st, uint64_t det, int32_t pop)
+static int is_initiator(const orc_state *st, det_t det, int32_t pop)
 {
     int64_t a = pop < 0 ? -(int64_t)pop : pop;
     return a > st->prm.n_a || det == st->sys.d0;
@@ -1347,7 +1401,7 @@ static int proc_spawn_death(orc_state *st, int p)
 
     int64_t high = ml->high;
     for (int64_t slot = 0; slot < high; slot++) {
-        uint64_t D = ml->det[slot];
+        det_t D = ml->det[slot];
         if (!D)
             continue;
         int32_t C = ml->pop[slot];
@@ -1367,7 +1421,7 @@ static int proc_spawn_death(orc_state *st, int p)
                  * from D only, it is reached through the child or through its
                  * spin-exchanged partner, so its generation probability is the sum
                  * of the two. The pair of D itself is part of the diagonal. */
-                const uint64_t Dj = hphf_rep(ex.det), fx = spin_flip(ex.det);
+                const det_t Dj = hphf_rep(ex.det), fx = spin_flip(ex.det);
                 if (Dj == D || (spin_flip(Dj) == Dj && s->hphf < 0)) {
                     ex.det = 0;
                 } else {
@@ -1427,7 +1481,7 @@ static void proc_stats(orc_state *st, int q)
     int64_t nw = 0, nd = 0, c0 = 0;
     double num = 0.0;
     for (int64_t slot = 0; slot < ml->high; slot++) {
-        uint64_t D = ml->det[slot];
+        det_t D = ml->det[slot];
         if (!D)
             continue;
         int32_t C = ml->pop[slot];
@@ -1483,7 +1537,7 @@ static int proc_annihilate(orc_state *st, int q)
     int64_t merged = 0, aborted = 0, born = 0;
     int64_t i = 0;
     while (i < pr->n_in) {
-        uint64_t D = pr->in[i].det;
+        det_t D = pr->in[i].det;
         int64_t c = 0;
         uint32_t f = 0;
         while (i < pr->n_in && pr->in[i].det == D) {
@@ -1535,7 +1589,7 @@ static int proc_load(orc_state *st, int q)
     mainlist_t *ml = &pr->ml;
     for (int64_t u = 0; u < pr->n_load; u++) {
         const int64_t t = pr->load_idx[u];
-        const uint64_t D = st->load_det[t];
+        const det_t D = load_det_at(st, t);
         if (ml_find(ml, D) >= 0)
             return fail("oracle: duplicate determinant in walker list");
         if (ml_insert(ml, D, st->load_pop[t], fdiag(&st->sys, D)) < 0)
@@ -1703,6 +1757,8 @@ int orc_estimates(orc_state *st, orc_est *out)
     return 0;
 }
 
+int32_t orc_det_words(const orc_state *st) { return st ? st->W : -1; }
+
 int64_t orc_walkers(orc_state *st, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap)
 {
     if (!st)
@@ -1732,7 +1788,7 @@ int64_t orc_walkers(orc_state *st, uint64_t *det, int32_t *pop, uint32_t *flags,
     }
     qsort(tmp, (size_t)n, sizeof(spawn_t), cmp_spawn);
     for (int64_t t = 0; t < n && t < cap; t++) {
-        det[t] = tmp[t].det;
+        det_out(st, tmp[t].det, det + t * st->W);
         if (pop)
             pop[t] = (int32_t)tmp[t].pop;
         if (flags)
@@ -1749,7 +1805,7 @@ int64_t orc_proc_dets(orc_state *st, int32_t p)
     return st->proc[p].ml.n_entries;
 }
 
-int32_t orc_owner(const orc_state *st, uint64_t det) { return owner_of(st, det); }
+int32_t orc_owner(const orc_state *st, const uint64_t *det) { return owner_of(st, det_in(st, det)); }
 
 int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int64_t n,
                      int64_t iteration, double shift, int64_t n_prev, int32_t varying,
@@ -1758,11 +1814,12 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
     if (!st)
         return fail("oracle: null state");
     if (st->sys.hphf)
-        for (int64_t t = 0; t < n; t++)
-            if (pop[t] != 0 && (hphf_rep(det[t]) != det[t] ||
-                                (spin_flip(det[t]) == det[t] && st->sys.hphf < 0)))
+        for (int64_t t = 0; t < n; t++) {
+            const det_t D = det_in(st, det + t * st->W);
+            if (pop[t] != 0 && (hphf_rep(D) != D || (spin_flip(D) == D && st->sys.hphf < 0)))
                 return fail("oracle: a walker list of spin-coupled functions holds each "
                             "function as the smaller determinant of its pair");
+        }
     int64_t range = st->proc[0].ml.range;
     procs_free(st);
     if (procs_init(st, range) != 0)
@@ -1778,9 +1835,10 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
         own[t] = -1;
         if (pop[t] == 0)
             continue;
-        if (det[t] == st->sys.d0)
+        const det_t D = det_in(st, det + t * st->W);
+        if (D == st->sys.d0)
             have_ref = 1;
-        own[t] = owner_of(st, det[t]);
+        own[t] = owner_of(st, D);
         st->proc[own[t]].n_load++;
     }
     int rc = 0;
@@ -1829,56 +1887,67 @@ int orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop, int
 /* ------------------------------------------------------------------------ */
 /* Unit-level entry points.                                                  */
 /* ------------------------------------------------------------------------ */
-int64_t orc_hash(const orc_state *st, uint64_t det, int64_t range)
+int64_t orc_hash(const orc_state *st, const uint64_t *det, int64_t range)
 {
-    int32_t occ[64];
-    int n = orc_decode(det, occ);
+    int32_t occ[MAX_SO];
+    int n = decode_det(det_in(st, det), occ);
     return hash_alg1(st->proc[0].ml.map, occ, n, range);
 }
 
-double orc_hel(const orc_state *st, uint64_t bra, uint64_t ket)
+double orc_hel(const orc_state *st, const uint64_t *bra, const uint64_t *ket)
 {
-    return hel_general(&st->sys, bra, ket);
+    return hel_general(&st->sys, det_in(st, bra), det_in(st, ket));
 }
 
-double orc_hdiag(const orc_state *st, uint64_t det) { return hdiag_of(&st->sys, det); }
-
-double orc_fn_hel(const orc_state *st, uint64_t bra, uint64_t ket)
+double orc_hdiag(const orc_state *st, const uint64_t *det)
 {
+    return hdiag_of(&st->sys, det_in(st, det));
+}
+
+double orc_fn_hel(const orc_state *st, const uint64_t *bra_w, const uint64_t *ket_w)
+{
+    const det_t bra = det_in(st, bra_w), ket = det_in(st, ket_w);
     if (bra == ket)
         return fdiag(&st->sys, ket);
     return st->sys.hphf ? hphf_hel(&st->sys, ket, bra) : hel_general(&st->sys, bra, ket);
 }
 
-double orc_fn_diag(const orc_state *st, uint64_t fn) { return fdiag(&st->sys, fn); }
+double orc_fn_diag(const orc_state *st, const uint64_t *fn)
+{
+    return fdiag(&st->sys, det_in(st, fn));
+}
 
-double orc_pgen(const orc_state *st, uint64_t det, uint64_t target)
+double orc_pgen(const orc_state *st, const uint64_t *det, const uint64_t *target)
 {
     detinfo_t di;
-    det_setup(&st->sys, det, &di);
-    return pgen_of(&st->sys, &di, target);
+    det_setup(&st->sys, det_in(st, det), &di);
+    return pgen_of(&st->sys, &di, det_in(st, target));
 }
 
 double orc_proj_num(const orc_state *st, const uint64_t *det, const double *c, int64_t n)
 {
     double num = 0.0;
-    for (int64_t t = 0; t < n; t++)
-        if (det[t] != st->sys.d0)
-            num = num + ref_hel(&st->sys, det[t]) * c[t];
+    for (int64_t t = 0; t < n; t++) {
+        const det_t D = det_in(st, det + t * st->W);
+        if (D != st->sys.d0)
+            num = num + ref_hel(&st->sys, D) * c[t];
+    }
     return num;
 }
 
-int orc_sample_excitations(const orc_state *st, uint64_t det, int64_t iteration, int64_t n_samples,
-                           uint64_t *out_det, double *out_pgen, double *out_hel)
+int orc_sample_excitations(const orc_state *st, const uint64_t *det_w, int64_t iteration,
+                           int64_t n_samples, uint64_t *out_det, double *out_pgen,
+                           double *out_hel)
 {
     detinfo_t di;
+    const det_t det = det_in(st, det_w);
     det_setup(&st->sys, det, &di);
     for (int64_t k = 0; k < n_samples; k++) {
         uint32_t w[4];
         draw_words(st->prm.seed, det, (uint32_t)k, iteration, 0, w);
         excit_t ex;
         gen_excit(&st->sys, &di, w, &ex);
-        out_det[k] = ex.det;
+        det_out(st, ex.det, out_det + k * st->W);
         out_pgen[k] = ex.pgen;
         out_hel[k] = ex.hel;
     }

@@ -11,7 +11,11 @@
  *
  * Conventions (shared only as a *data format* with the product ABI):
  *   spin orbital p = 2*s + sigma (s spatial, sigma 0 = alpha, 1 = beta);
- *   a determinant is a uint64 with bit p set when p is occupied;
+ *   a determinant has bit p set when p is occupied and is passed as W 64-bit
+ *   words, low word first (Sec. 3: as many words as the spin orbitals need):
+ *   W = 1 up to 64 spin orbitals, W = 2 up to 128 (orc_det_words; W = 2 can
+ *   also be forced for fewer with orc_params.det_words). Arrays of
+ *   determinants hold W words per entry;
  *   h1 is M*M row-major; eri is the eight-fold packed (pq|rs) array with pair
  *   index ij = i(i+1)/2 + j (i >= j) and element IJ(IJ+1)/2 + KL (IJ >= KL).
  */
@@ -30,7 +34,7 @@ typedef struct {
     const double *eri;
     const uint8_t *orb_irrep;   /* NULL: every orbital in the totally symmetric irrep */
     double p_double;            /* < 0: ratio of double to all excitations from D0 */
-    const uint64_t *ref_det;    /* NULL: aufbau by h_pp */
+    const uint64_t *ref_det;    /* NULL: aufbau by h_pp; else W words */
 } orc_ham;
 
 typedef struct {
@@ -58,6 +62,9 @@ typedef struct {
                                    n_alpha = n_beta; no restricted space) */
     uint64_t frozen_occupied;   /* ORC_SPACE_FROZEN: spin orbitals occupied in every determinant */
     uint64_t frozen_empty;      /* ORC_SPACE_FROZEN: spin orbitals empty in every determinant */
+    uint64_t frozen_occupied_hi, frozen_empty_hi;   /* the same for spin orbitals 64..127 */
+    int32_t det_words;          /* 0: as the spin orbitals need; 2: two words even for <= 64 */
+    int32_t pad1;
 } orc_params;
 
 #define ORC_SPACE_EXCITATION 1
@@ -87,23 +94,25 @@ int     orc_load_walkers(orc_state *st, const uint64_t *det, const int32_t *pop,
                          int64_t n_var);
 void    orc_free(orc_state *st);
 int64_t orc_proc_dets(orc_state *st, int32_t p);           /* main-list entries on process p */
-int32_t orc_owner(const orc_state *st, uint64_t det);     /* process that owns det */
+int32_t orc_owner(const orc_state *st, const uint64_t *det);   /* process that owns det */
+int32_t orc_det_words(const orc_state *st);                     /* W */
 const char *orc_last_error(void);
 
 /* Unit-level entry points used by the pins. */
 void    orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
-int     orc_decode(uint64_t det, int32_t *occ);          /* byte-table decode; returns count */
-int64_t orc_hash(const orc_state *st, uint64_t det, int64_t range);   /* Algorithm 1 */
-double  orc_hel(const orc_state *st, uint64_t bra, uint64_t ket);      /* <bra|H|ket> */
-double  orc_hdiag(const orc_state *st, uint64_t det);
-double  orc_pgen(const orc_state *st, uint64_t det, uint64_t target);  /* generator's probability */
+/* (Determinant arguments below: W words each, W = orc_det_words of the state.) */
+int     orc_decode(const uint64_t *det, int32_t words, int32_t *occ);   /* byte-table decode */
+int64_t orc_hash(const orc_state *st, const uint64_t *det, int64_t range);   /* Algorithm 1 */
+double  orc_hel(const orc_state *st, const uint64_t *bra, const uint64_t *ket);   /* <bra|H|ket> */
+double  orc_hdiag(const orc_state *st, const uint64_t *det);
+double  orc_pgen(const orc_state *st, const uint64_t *det, const uint64_t *target);
 /* Elements between the stored functions of the run (determinants, or spin-coupled
  * functions held as their smaller determinant): <bra|H|ket> with ket the source,
  * and the diagonal element. */
-double  orc_fn_hel(const orc_state *st, uint64_t bra, uint64_t ket);
-double  orc_fn_diag(const orc_state *st, uint64_t fn);
+double  orc_fn_hel(const orc_state *st, const uint64_t *bra, const uint64_t *ket);
+double  orc_fn_diag(const orc_state *st, const uint64_t *fn);
 double  orc_proj_num(const orc_state *st, const uint64_t *det, const double *c, int64_t n);
-int     orc_sample_excitations(const orc_state *st, uint64_t det, int64_t iteration,
+int     orc_sample_excitations(const orc_state *st, const uint64_t *det, int64_t iteration,
                                int64_t n_samples, uint64_t *out_det, double *out_pgen,
                                double *out_hel);
 double  orc_log(double x);                              /* shift-update logarithm */

@@ -28,7 +28,8 @@ class OrcParams(C.Structure):
                 ("proc_seed", C.c_uint64), ("n_threads", C.c_int32),
                 ("space", C.c_int32), ("max_excitation", C.c_int32), ("max_seniority", C.c_int32),
                 ("hphf", C.c_int32), ("frozen_occupied", C.c_uint64),
-                ("frozen_empty", C.c_uint64)]
+                ("frozen_empty", C.c_uint64), ("frozen_occupied_hi", C.c_uint64),
+                ("frozen_empty_hi", C.c_uint64), ("det_words", C.c_int32), ("pad1", C.c_int32)]
 
 
 class OrcEst(C.Structure):
@@ -61,25 +62,27 @@ def lib():
         L.orc_free.argtypes = [vp]
         L.orc_last_error.restype = C.c_char_p
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
-        L.orc_decode.argtypes = [C.c_uint64, vp]
-        L.orc_hash.argtypes = [vp, C.c_uint64, C.c_int64]
+        L.orc_decode.argtypes = [vp, C.c_int32, vp]
+        L.orc_hash.argtypes = [vp, vp, C.c_int64]
         L.orc_hash.restype = C.c_int64
         L.orc_proc_dets.argtypes = [vp, C.c_int32]
         L.orc_proc_dets.restype = C.c_int64
-        L.orc_owner.argtypes = [vp, C.c_uint64]
+        L.orc_owner.argtypes = [vp, vp]
         L.orc_owner.restype = C.c_int32
-        L.orc_hel.argtypes = [vp, C.c_uint64, C.c_uint64]
+        L.orc_det_words.argtypes = [vp]
+        L.orc_det_words.restype = C.c_int32
+        L.orc_hel.argtypes = [vp, vp, vp]
         L.orc_hel.restype = C.c_double
-        L.orc_hdiag.argtypes = [vp, C.c_uint64]
+        L.orc_hdiag.argtypes = [vp, vp]
         L.orc_hdiag.restype = C.c_double
         L.orc_proj_num.argtypes = [vp, vp, vp, C.c_int64]
         L.orc_proj_num.restype = C.c_double
-        L.orc_sample_excitations.argtypes = [vp, C.c_uint64, C.c_int64, C.c_int64, vp, vp, vp]
-        L.orc_pgen.argtypes = [vp, C.c_uint64, C.c_uint64]
+        L.orc_sample_excitations.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp, vp]
+        L.orc_pgen.argtypes = [vp, vp, vp]
         L.orc_pgen.restype = C.c_double
-        L.orc_fn_hel.argtypes = [vp, C.c_uint64, C.c_uint64]
+        L.orc_fn_hel.argtypes = [vp, vp, vp]
         L.orc_fn_hel.restype = C.c_double
-        L.orc_fn_diag.argtypes = [vp, C.c_uint64]
+        L.orc_fn_diag.argtypes = [vp, vp]
         L.orc_fn_diag.restype = C.c_double
         L.orc_blocking.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_double),
                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]
@@ -99,9 +102,37 @@ def philox4x32_10(ctr, key):
     return out
 
 
+MASK64 = (1 << 64) - 1
+
+
+def words_of(det: int, w: int) -> np.ndarray:
+    """A determinant (Python int) as w 64-bit words, low word first."""
+    return np.array([(int(det) >> (64 * i)) & MASK64 for i in range(w)], dtype=np.uint64)
+
+
+def det_array(dets, w: int) -> np.ndarray:
+    """Determinants as the API's array: shape (n,) for one word, (n, 2) for two
+    (columns: low word, high word). Accepts ints or an array already in shape."""
+    a = np.asarray(dets)
+    if w == 1:
+        return np.ascontiguousarray(a, dtype=np.uint64).reshape(-1)
+    if a.ndim == 2:
+        return np.ascontiguousarray(a, dtype=np.uint64)
+    return np.array([[int(d) & MASK64, int(d) >> 64] for d in a.reshape(-1)],
+                    dtype=np.uint64).reshape(-1, 2)
+
+
+def det_ints(arr) -> list:
+    """Python ints from the API's determinant array (either shape)."""
+    a = np.asarray(arr)
+    if a.ndim == 1:
+        return [int(x) for x in a]
+    return [int(lo) | (int(hi) << 64) for lo, hi in a]
+
+
 def decode(det: int):
-    occ = np.zeros(64, dtype=np.int32)
-    n = lib().orc_decode(C.c_uint64(det), _ptr(occ))
+    occ = np.zeros(128, dtype=np.int32)
+    n = lib().orc_decode(_ptr(words_of(det, 2)), 2, _ptr(occ))
     return occ[:n].tolist()
 
 
@@ -128,7 +159,7 @@ class Oracle:
         self._h1 = np.ascontiguousarray(ham.h1, dtype=np.float64)
         self._eri = np.ascontiguousarray(ham.eri, dtype=np.float64)
         self._irr = None if ham.orb_irrep is None else np.ascontiguousarray(ham.orb_irrep, np.uint8)
-        self._ref = None if ham.ref_det is None else np.array([ham.ref_det], dtype=np.uint64)
+        self._ref = None if ham.ref_det is None else words_of(ham.ref_det, 2)
         h = OrcHam(ham.n_orb, ham.n_alpha, ham.n_beta, 0, ham.e_core,
                    self._h1.ctypes.data_as(C.POINTER(C.c_double)),
                    self._eri.ctypes.data_as(C.POINTER(C.c_double)),
@@ -141,11 +172,14 @@ class Oracle:
                       params.avg_start, 0, hash_seed, hash_range, n_procs,
                       int(bool(ref_own_proc)), proc_seed, n_threads, params.space,
                       params.max_excitation, params.max_seniority, params.hphf,
-                      params.frozen_occupied, params.frozen_empty)
+                      int(params.frozen_occupied) & MASK64, int(params.frozen_empty) & MASK64,
+                      int(params.frozen_occupied) >> 64, int(params.frozen_empty) >> 64,
+                      getattr(params, "det_words", 0), 0)
         self._h = C.c_void_p()
         if L.orc_create(C.byref(h), C.byref(p), C.byref(self._h)) != 0:
             raise RuntimeError(L.orc_last_error().decode())
         self.n_elec = ham.n_alpha + ham.n_beta
+        self.W = L.orc_det_words(self._h)
 
     def close(self):
         if self._h:
@@ -170,27 +204,33 @@ class Oracle:
         self._check(lib().orc_estimates(self._h, C.byref(e)))
         return {f[0]: getattr(e, f[0]) for f in OrcEst._fields_ if f[0] != "pad0"}
 
+    def _w(self, det: int) -> np.ndarray:
+        return words_of(det, self.W)
+
     def walkers(self):
+        """(det, pop, flags) sorted by determinant; det has shape (n,) with one word
+        per determinant, (n, 2) with two."""
         n = lib().orc_walkers(self._h, None, None, None, 0)
-        det = np.zeros(max(n, 1), dtype=np.uint64)
+        det = np.zeros(max(n, 1) * self.W, dtype=np.uint64)
         pop = np.zeros(max(n, 1), dtype=np.int32)
         flg = np.zeros(max(n, 1), dtype=np.uint32)
         m = lib().orc_walkers(self._h, _ptr(det), _ptr(pop), _ptr(flg), n)
         if m < 0:
             raise RuntimeError(lib().orc_last_error().decode())
-        return det[:n], pop[:n], flg[:n]
+        det = det[:n * self.W]
+        return (det if self.W == 1 else det.reshape(-1, 2)), pop[:n], flg[:n]
 
     def load_walkers(self, det, pop, iteration=0, shift=0.0, n_prev=0, varying=0, n_var=0):
-        det = np.ascontiguousarray(det, dtype=np.uint64)
+        det = det_array(det, self.W)
         pop = np.ascontiguousarray(pop, dtype=np.int32)
-        self._check(lib().orc_load_walkers(self._h, _ptr(det), _ptr(pop), len(det), iteration,
+        self._check(lib().orc_load_walkers(self._h, _ptr(det), _ptr(pop), len(pop), iteration,
                                            shift, n_prev, varying, n_var))
 
     def hel(self, bra: int, ket: int) -> float:
-        return lib().orc_hel(self._h, C.c_uint64(bra), C.c_uint64(ket))
+        return lib().orc_hel(self._h, _ptr(self._w(bra)), _ptr(self._w(ket)))
 
     def hdiag(self, det: int) -> float:
-        return lib().orc_hdiag(self._h, C.c_uint64(det))
+        return lib().orc_hdiag(self._h, _ptr(self._w(det)))
 
     def proc_dets(self, p: int) -> int:
         n = lib().orc_proc_dets(self._h, p)
@@ -199,31 +239,33 @@ class Oracle:
         return n
 
     def owner(self, det: int) -> int:
-        return lib().orc_owner(self._h, C.c_uint64(det))
+        return lib().orc_owner(self._h, _ptr(self._w(det)))
 
     def hash(self, det: int, rng: int) -> int:
-        return lib().orc_hash(self._h, C.c_uint64(det), rng)
+        return lib().orc_hash(self._h, _ptr(self._w(det)), rng)
 
     def proj_num(self, det, c) -> float:
-        det = np.ascontiguousarray(det, dtype=np.uint64)
+        det = det_array(det, self.W)
         c = np.ascontiguousarray(c, dtype=np.float64)
-        return lib().orc_proj_num(self._h, _ptr(det), _ptr(c), len(det))
+        return lib().orc_proj_num(self._h, _ptr(det), _ptr(c), len(c))
 
     def fn_hel(self, bra: int, ket: int) -> float:
         """<bra|H|ket> between stored functions of the run, ket the source."""
-        return lib().orc_fn_hel(self._h, C.c_uint64(bra), C.c_uint64(ket))
+        return lib().orc_fn_hel(self._h, _ptr(self._w(bra)), _ptr(self._w(ket)))
 
     def fn_diag(self, fn: int) -> float:
-        return lib().orc_fn_diag(self._h, C.c_uint64(fn))
+        return lib().orc_fn_diag(self._h, _ptr(self._w(fn)))
 
     def pgen(self, det: int, target: int) -> float:
         """Probability that the excitation generator produces target from det."""
-        return lib().orc_pgen(self._h, C.c_uint64(det), C.c_uint64(target))
+        return lib().orc_pgen(self._h, _ptr(self._w(det)), _ptr(self._w(target)))
 
     def sample_excitations(self, det: int, n: int, iteration: int = 0):
-        od = np.zeros(n, dtype=np.uint64)
+        """(children, pgen, element) of n attempts; children as Python ints when the
+        determinants take two words."""
+        od = np.zeros(n * self.W, dtype=np.uint64)
         pg = np.zeros(n)
         he = np.zeros(n)
-        self._check(lib().orc_sample_excitations(self._h, C.c_uint64(det), iteration, n,
+        self._check(lib().orc_sample_excitations(self._h, _ptr(self._w(det)), iteration, n,
                                                  _ptr(od), _ptr(pg), _ptr(he)))
-        return od, pg, he
+        return (od if self.W == 1 else det_ints(od.reshape(-1, 2))), pg, he

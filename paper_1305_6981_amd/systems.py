@@ -109,6 +109,9 @@ class Params:
     frozen_empty: int = 0
     # spin-coupled functions: 0 off, +1 / -1 for even / odd total spin
     hphf: int = 0
+    # 64-bit words per determinant: 0 as the spin orbitals need (1 up to 64, 2 up to
+    # 128); 2 forces two words for fewer
+    det_words: int = 0
     extra: dict = field(default_factory=dict)
 
 
