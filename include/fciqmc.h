@@ -19,8 +19,13 @@
  *
  * Conventions
  *   - spin orbital p = 2*s + sigma (s spatial orbital, sigma 0 = alpha,
- *     1 = beta); a determinant is a uint64 with bit p set when p is occupied
- *     (the bit-string representation of Sec. 3). 2*n_orb <= 64.
+ *     1 = beta); a determinant has bit p set when p is occupied (the
+ *     bit-string representation of Sec. 3) and takes as many 64-bit words as
+ *     its spin orbitals need, low word first: W = 1 up to 64 spin orbitals,
+ *     W = 2 up to 128 (2*n_orb <= 128; fciqmc_det_words; W = 2 can be forced
+ *     for fewer with fciqmc_params.det_words). Every determinant argument and
+ *     array below holds W words per determinant, and all systems of a handle
+ *     share one W (the first system's).
  *   - all pointers in this header are HOST pointers; the library copies what
  *     it needs at the call and never keeps a caller's pointer.
  *   - return value: 0 on success, a negative FCIQMC_E* code on failure; the
@@ -42,7 +47,7 @@ extern "C" {
 #endif
 
 #define FCIQMC_OK            0
-#define FCIQMC_EINVAL       -1   /* bad argument: sizes, tau <= 0, 2*n_orb > 64, ... */
+#define FCIQMC_EINVAL       -1   /* bad argument: sizes, tau <= 0, 2*n_orb > 128, ... */
 #define FCIQMC_ENOMEM       -2   /* device or host allocation failed / does not fit */
 #define FCIQMC_EDEVICE      -3   /* a HIP call failed (message kept) */
 #define FCIQMC_ECAPACITY    -4   /* a table could not be grown */
@@ -54,7 +59,7 @@ typedef struct fciqmc_t fciqmc_t;   /* opaque; owned by the library */
 /* The Hamiltonian in an M-orbital determinant basis with N = n_alpha + n_beta
  * electrons (Sec. 2). */
 typedef struct {
-    int32_t n_orb;              /* M spatial orbitals, 1 <= M <= 32 */
+    int32_t n_orb;              /* M spatial orbitals, 1 <= M <= 64 */
     int32_t n_alpha, n_beta;    /* electrons per spin */
     int32_t reserved0;
     double e_core;              /* constant energy */
@@ -66,7 +71,8 @@ typedef struct {
     double p_double;            /* >= 0: probability of drawing a double excitation; < 0: the
                                    ratio of double to all symmetry-allowed excitations of the
                                    reference (Sec. 5) */
-    const uint64_t *ref_det;    /* NULL: aufbau (lowest n_alpha / n_beta orbitals by h_pp) */
+    const uint64_t *ref_det;    /* NULL: aufbau (lowest n_alpha / n_beta orbitals by h_pp);
+                                   else W words */
 } fciqmc_hamiltonian;
 
 /* Run parameters. */
@@ -99,9 +105,9 @@ typedef struct {
                                    outside the reference's orbitals (2: CISD) */
     int32_t max_seniority;      /* FCIQMC_SPACE_SENIORITY: at most this many singly
                                    occupied spatial orbitals */
-    uint64_t frozen_occupied;   /* FCIQMC_SPACE_FROZEN: spin orbitals occupied in every
-                                   determinant (a CAS core) */
-    uint64_t frozen_empty;      /* FCIQMC_SPACE_FROZEN: spin orbitals empty in every
+    uint64_t frozen_occupied;   /* FCIQMC_SPACE_FROZEN: spin orbitals (0-63) occupied in
+                                   every determinant (a CAS core) */
+    uint64_t frozen_empty;      /* FCIQMC_SPACE_FROZEN: spin orbitals (0-63) empty in every
                                    determinant (CAS virtuals) */
     /* Spin-coupled functions (Sec. 5.3, Eqs. EqualCoeffs and SpinCoup): 0 samples
      * determinants; +1 / -1 samples the pairs {D, D~} (alpha and beta exchanged)
@@ -113,6 +119,12 @@ typedef struct {
      * empty or doubly occupied) exist for even S only. */
     int32_t hphf;
     int32_t reserved1;
+    uint64_t frozen_occupied_hi;/* as frozen_occupied, for spin orbitals 64-127 */
+    uint64_t frozen_empty_hi;   /* as frozen_empty, for spin orbitals 64-127 */
+    int32_t det_words;          /* 64-bit words per determinant: 0 as the spin orbitals need
+                                   (Sec. 3); 2 forces two words for at most 64 (EINVAL: other
+                                   values, or 1 for more than 64 spin orbitals) */
+    int32_t reserved2;
 } fciqmc_params;
 
 #define FCIQMC_SPACE_EXCITATION 1
@@ -208,15 +220,16 @@ int fciqmc_estimators(fciqmc_t *h, fciqmc_estimates *out);
 int fciqmc_free(fciqmc_t *h);
 
 /* Copy the main list of system 0 (Sec. 4.2) -- its occupied determinants as
- * bit strings (Sec. 3), sorted, with their signed populations -- into the
- * caller's host arrays (each of length cap; any may be NULL). flags[i] is 1
+ * bit strings (Sec. 3; W words each, det has room for cap * W words), sorted
+ * as unsigned integers, with their signed populations -- into the caller's
+ * host arrays (each of length cap; any may be NULL). flags[i] is 1
  * when the determinant is an initiator for the next iteration (|C| > n_a, or
  * the reference; Sec. 4.2). Returns the number of occupied determinants
  * (which may exceed cap: then only cap are written), or a negative error code. */
 int64_t fciqmc_walkers(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap);
 
-/* Replace the main list of system 0 (Sec. 4.2; determinants as bit strings,
- * Sec. 3) for a checkpoint restart. Entries with
+/* Replace the main list of system 0 (Sec. 4.2; determinants as bit strings of
+ * W words each, Sec. 3) for a checkpoint restart. Entries with
  * pop == 0 are ignored; the reference is kept in the list even when absent.
  * iteration is the number of completed iterations, shift is S relative to E0,
  * varying / n_var / n_prev restore the shift-update state. The averages are
@@ -224,6 +237,10 @@ int64_t fciqmc_walkers(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags
 int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, int64_t n,
                         int64_t iteration, double shift, int64_t n_prev, int32_t varying,
                         int64_t n_var);
+
+/* 64-bit words per determinant of the handle's systems (Sec. 3): 1 or 2, or a
+ * negative error code. */
+int32_t fciqmc_det_words(const fciqmc_t *h);
 
 /* Set the shift S of system 0 (Sec. 2; relative to E0) and start (varying = 1)
  * or stop its variation; when started, N_prev is set to the current N_w and
@@ -330,7 +347,8 @@ int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial);
  * threads or handles) race and must be serialised by the caller. Returns the
  * number of occupied determinants (only min(n, cap) entries are written), or
  * ECAPACITY when the list exceeds 2^21 determinants (nothing written),
- * EINVAL, ESTATE, EDEVICE. */
+ * EINVAL, ESTATE (also for two-word determinants, which the area does not
+ * hold), EDEVICE. */
 int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags,
                                int64_t cap);
 

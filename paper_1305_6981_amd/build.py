@@ -17,7 +17,8 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "engine.hip")]
+    # kernels_w2.hip: the same kernels for two-word determinants (namespace fq::w2)
+    srcs = [os.path.join(CSRC, f) for f in ("kernels.hip", "kernels_w2.hip", "engine.hip")]
     cmd = ["hipcc", *HIPCC_FLAGS, "-o", LIB + ".tmp", *srcs]
     if verbose:
         print(" ".join(cmd))

@@ -104,6 +104,14 @@ struct SysDesc {
     double shift;
     int32_t varying, pad3;
     int64_t n_prev, n_var;
+    // --- set by the host: determinants of more than 64 spin orbitals (two words,
+    // Sec. 3): the high words of d0, valid, cmask, frz_occ and frz_emp, and the irreps
+    // of spatial orbitals 32-63 (4 bits each); det_words = 1 or 2 selects the width.
+    uint64_t d0_hi, valid_hi;
+    uint64_t cmask_hi[NCLASS];
+    uint64_t irr_packed_hi[2];
+    uint64_t frz_occ_hi, frz_emp_hi;
+    int32_t det_words, pad5;
 };
 
 // A spawn record (16 B, written and read with one vector access): child
@@ -173,25 +181,36 @@ constexpr size_t NOALLOC_VALS_OFF = NOALLOC_KEYS_OFF + 8 * (size_t)NOALLOC_MAX_D
 constexpr size_t NOALLOC_FLAGS_OFF = NOALLOC_VALS_OFF + 4 * (size_t)NOALLOC_MAX_DETS;
 constexpr size_t NOALLOC_BYTES = NOALLOC_FLAGS_OFF + 4 * (size_t)NOALLOC_MAX_DETS;
 
-// Kernel launchers (kernels.hip).
+// Kernel launchers (kernels.hip, compiled once per determinant width: one word in fq,
+// two words in fq::w2). Determinant arrays hold the width's words per entry.
 constexpr int NKERN = 5;   // profiled kernel groups: chunk sums, scans, spawn, annihilation
                            // (record sort + death/annihilation pass), statistics/shift
-// first: the chunk sums are taken from the tables (the first iteration of a launch, after
-// any host-side change); later iterations use the sums the previous iteration's k_post wrote.
-void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool first,
-                      hipStream_t s, hipEvent_t *ev /* NKERN + 1 events or nullptr */);
-hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const int32_t *pop,
-                       int64_t n, uint32_t *d_err, hipStream_t s);
-// Move every entry of the buckets (src_*, src_nb buckets, counts src_cnt) and the spill
-// entries of system sys into the descriptor's (empty) buckets.
-hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,
-                           const int32_t *src_pop, const double *src_hd, const int32_t *src_cnt,
-                           int64_t src_nb, const uint64_t *sp_det, const int32_t *sp_pop,
-                           const double *sp_hd, const int32_t *sp_sys, int64_t n_sp,
-                           uint32_t *d_err, hipStream_t s);
-hipError_t launch_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt, int64_t nb,
-                          uint64_t *out_det, int32_t *out_pop, unsigned long long *count,
-                          hipStream_t s);
+#define FQ_WIDTH_LAUNCHERS                                                                     \
+    /* first: the chunk sums are taken from the tables (the first iteration of a launch,     \
+       after any host-side change); later iterations use the sums the previous iteration's   \
+       k_post wrote. */                                                                       \
+    void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool first,      \
+                          hipStream_t s, hipEvent_t *ev /* NKERN + 1 events or nullptr */);     \
+    hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det,                 \
+                           const int32_t *pop, int64_t n, uint32_t *d_err, hipStream_t s);      \
+    /* Move every entry of the buckets (src_*, src_nb buckets, counts src_cnt) and the spill  \
+       entries of system sys into the descriptor's (empty) buckets. */                        \
+    hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key,         \
+                               const int32_t *src_pop, const double *src_hd,                  \
+                               const int32_t *src_cnt, int64_t src_nb, const uint64_t *sp_det, \
+                               const int32_t *sp_pop, const double *sp_hd,                    \
+                               const int32_t *sp_sys, int64_t n_sp, uint32_t *d_err,          \
+                               hipStream_t s);                                                 \
+    hipError_t launch_compact(const uint64_t *key, const int32_t *pop, const int32_t *cnt,    \
+                              int64_t nb, uint64_t *out_det, int32_t *out_pop,                \
+                              unsigned long long *count, hipStream_t s);                      \
+    /* H_DD (or the function's diagonal) of one determinant, words lo and hi. */              \
+    hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t lo, uint64_t hi,          \
+                         double *out, hipStream_t s);
+FQ_WIDTH_LAUNCHERS
+namespace w2 {
+FQ_WIDTH_LAUNCHERS
+}  // namespace w2
 // Export into the staging area `stage` (NOALLOC layout): compaction of the occupied
 // slots (entries past NOALLOC_MAX_DETS are counted, not written), then a bitonic
 // sort by determinant of the first n entries padded to a power of two.
@@ -200,7 +219,6 @@ hipError_t launch_stage_compact(const uint64_t *key, const int32_t *pop, const i
 hipError_t launch_stage_sort(void *stage, int64_t n, hipStream_t s);
 // Initiator flag of each of the n sorted entries: |pop| > n_a, or the reference.
 hipError_t launch_stage_flags(void *stage, int64_t n, int32_t n_a, uint64_t d0, hipStream_t s);
-hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s);
 int spawn_grid_size();
 int post_grid_size();
 

@@ -30,6 +30,32 @@
 
 using namespace fq;
 
+// Determinants on the host: one 128-bit integer (bit p: spin orbital p occupied).
+// The API and the device hold W = 1 or 2 64-bit words per determinant, low word
+// first (Sec. 3: as many words as the spin orbitals need).
+typedef unsigned __int128 hdet_t;
+static inline int hpopc(hdet_t x) {
+    return __builtin_popcountll((uint64_t)x) + __builtin_popcountll((uint64_t)(x >> 64));
+}
+static inline hdet_t hbit(int p) { return (hdet_t)1 << p; }
+static inline uint64_t hlo(hdet_t x) { return (uint64_t)x; }
+static inline uint64_t hhi(hdet_t x) { return (uint64_t)(x >> 64); }
+static inline hdet_t hdet_in(const uint64_t *w, int W) {
+    return W > 1 ? (((hdet_t)w[1] << 64) | (hdet_t)w[0]) : (hdet_t)w[0];
+}
+static inline void hdet_out(hdet_t d, uint64_t *w, int W) {
+    w[0] = hlo(d);
+    if (W > 1) w[1] = hhi(d);
+}
+static const hdet_t HEVEN = ((hdet_t)0x5555555555555555ull << 64) | (hdet_t)0x5555555555555555ull;
+// Words per determinant for a system of n_orb spatial orbitals (det_words: 0 as needed,
+// 2 forced).
+static inline int words_for(int n_orb, int det_words) {
+    return (2 * n_orb > 64 || det_words == 2) ? 2 : 1;
+}
+// The kernels' launchers of the handle's width.
+#define FQ_LAUNCH(W, fn, ...) ((W) == 2 ? fq::w2::fn(__VA_ARGS__) : fq::fn(__VA_ARGS__))
+
 // Device staging area of fciqmc_walkers_noalloc (every call on a GPU shares
 // that GPU's copy). Host code never uses this name as an address: the address
 // of each device's copy is taken once per device with hipGetSymbolAddress when
@@ -172,16 +198,17 @@ struct SysHost {
     std::vector<double> h1, eri;
     std::vector<uint8_t> irrep;
     double e_core = 0.0, p_double = 0.0, e0 = 0.0;
-    uint64_t d0 = 0;
+    hdet_t d0 = 0;
+    int W = 1;                 // 64-bit words per determinant
     int64_t cap = 0;           // main-list capacity: buckets * BQ
     void *block = nullptr;     // one device allocation for the main list + integrals
-    uint64_t *key = nullptr;
+    uint64_t *key = nullptr;   // W words per entry
     int32_t *pop = nullptr;
     double *hd = nullptr;
     int32_t *bcnt = nullptr;
     double *d_h1 = nullptr, *d_eri = nullptr, *d_jk = nullptr;
-    std::vector<double> jk;    // [n_so][64] pair table
-    std::vector<double> t3;    // [n_so][64][64] single-excitation term table
+    std::vector<double> jk;    // [n_so][64 W] pair table
+    std::vector<double> t3;    // [n_so][64 W][64 W] single-excitation term table
     double *d_t3 = nullptr;
     int64_t growth = 0;        // expected per-iteration increase of the entries
     int64_t spawn_peak = 0;    // most spawn records of one iteration in the last launch
@@ -200,6 +227,7 @@ struct SysHost {
 
 struct fciqmc_t {
     int dev = 0;
+    int W = 1;                              // words per determinant of every system here
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int max_sys = 0;
@@ -288,9 +316,10 @@ EngineArgs make_args(fciqmc_t *h) {
     a.tile_cap = h->tile_cap;
     char *r = (char *)h->d_recs;
     const size_t rc = (size_t)h->rec_cap;
+    const size_t rb = 16 * (size_t)h->W;     // bytes per record
     a.recs = (SpawnRec *)r;
-    a.srt = (SpawnRec *)(r + 16 * rc);
-    a.rec_rank = (uint32_t *)(r + 32 * rc);
+    a.srt = (SpawnRec *)(r + rb * rc);
+    a.rec_rank = (uint32_t *)(r + 2 * rb * rc);
     a.rec_count = h->d_rec_count;
     a.rec_cap = h->rec_cap;
     a.bhist = h->d_bhist;
@@ -299,17 +328,18 @@ EngineArgs make_args(fciqmc_t *h) {
     a.boff_rg = h->d_boff_rg;
     char *q = (char *)h->d_spill;
     const size_t sc = (size_t)h->sp_cap;
+    const size_t kb = 8 * (size_t)h->W;      // bytes per determinant
     a.sp_det = (uint64_t *)q;
-    a.sp_hd = (double *)(q + 8 * sc);
-    a.sp_pop = (int32_t *)(q + 16 * sc);
-    a.sp_sys = (int32_t *)(q + 20 * sc);
+    a.sp_hd = (double *)(q + kb * sc);
+    a.sp_pop = (int32_t *)(q + (kb + 8) * sc);
+    a.sp_sys = (int32_t *)(q + (kb + 12) * sc);
     a.sp_count = h->d_sp_count;
     a.sp_cap = h->sp_cap;
     a.spilled = h->d_spilled;
     return a;
 }
 
-// The spawn-record buffer for `cap` records (36 B each: unsorted with rank, and sorted).
+// The spawn-record buffer for `cap` records (32 W + 4 B each: unsorted, sorted, rank).
 int ensure_records(fciqmc_t *h, int64_t cap) {
     if (cap <= h->rec_cap) return 0;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -317,7 +347,7 @@ int ensure_records(fciqmc_t *h, int64_t cap) {
     h->d_recs = nullptr;
     h->rec_cap = 0;
     drop_graphs(h);
-    if (hipMalloc(&h->d_recs, (size_t)cap * 36) != hipSuccess) {
+    if (hipMalloc(&h->d_recs, (size_t)cap * (32 * h->W + 4)) != hipSuccess) {
         (void)hipGetLastError();
         return set_err(FCIQMC_ENOMEM, "spawn-record buffer of " + std::to_string(cap) +
                                           " records does not fit in device memory");
@@ -441,24 +471,26 @@ int ensure_tile_map(fciqmc_t *h) {
     return 0;
 }
 
-// Device bytes of a main list of cap entries: determinant, population, H_DD
-// per entry, and one count per bucket.
-int64_t table_bytes(int64_t cap) {
-    return cap * (int64_t)(sizeof(uint64_t) + sizeof(int32_t) + sizeof(double)) +
+// Device bytes of a main list of cap entries: determinant (W words), population,
+// H_DD per entry, and one count per bucket.
+int64_t table_bytes(int64_t cap, int W) {
+    return cap * (int64_t)(8 * W + sizeof(int32_t) + sizeof(double)) +
            (cap / BQ) * (int64_t)sizeof(int32_t) + 256;
 }
 
-int64_t integral_doubles(int M) {
-    const int64_t np = (int64_t)M * (M + 1) / 2;
-    return (int64_t)M * M + np * (np + 1) / 2 + 64 * 64 + (int64_t)2 * M * 64 * 64;
+// h1, the packed ERI, the pair table and the single-excitation term table, with
+// rows of 64 W spin orbitals.
+int64_t integral_doubles(int M, int W) {
+    const int64_t np = (int64_t)M * (M + 1) / 2, ns = 64 * (int64_t)W;
+    return (int64_t)M * M + np * (np + 1) / 2 + ns * ns + (int64_t)2 * M * ns * ns;
 }
 
-int64_t integral_bytes(int M) { return integral_doubles(M) * 8 + 256; }
+int64_t integral_bytes(int M, int W) { return integral_doubles(M, W) * 8 + 256; }
 
 void carve(SysHost &S, void *blk, int64_t cap) {
     char *p = (char *)blk;
     S.key = (uint64_t *)p;
-    p += cap * sizeof(uint64_t);
+    p += cap * 8 * S.W;
     S.hd = (double *)p;
     p += cap * sizeof(double);
     S.pop = (int32_t *)p;
@@ -471,7 +503,7 @@ void carve(SysHost &S, void *blk, int64_t cap) {
     S.d_eri = (double *)p;
     p += (size_t)S.eri.size() * sizeof(double);
     S.d_jk = (double *)p;
-    p += 64 * 64 * sizeof(double);
+    p += (size_t)64 * S.W * 64 * S.W * sizeof(double);
     S.d_t3 = (double *)p;
     S.block = blk;
     S.cap = cap;
@@ -480,7 +512,7 @@ void carve(SysHost &S, void *blk, int64_t cap) {
 // Allocate the main list of a system with cap entries (every bucket empty) and
 // room for its integrals. Old storage is released by the caller.
 int alloc_tables(fciqmc_t *h, SysHost &S, int64_t cap, void **block_out) {
-    const int64_t tb = table_bytes(cap), ib = integral_bytes(S.M);
+    const int64_t tb = table_bytes(cap, S.W), ib = integral_bytes(S.M, S.W);
     void *blk = nullptr;
     hipError_t e = hipMalloc(&blk, (size_t)(tb + ib));
     if (e != hipSuccess) {
@@ -543,9 +575,9 @@ int rebucket_system(fciqmc_t *h, int s, int64_t new_cap, int64_t n_spill) {
         if (rc) return rc;
         HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
         const EngineArgs a = make_args(h);
-        HIP_TRY(launch_rebucket(h->d_desc, s, S_old.key, S_old.pop, S_old.hd, S_old.bcnt,
-                                S_old.cap / BQ, a.sp_det, a.sp_pop, a.sp_hd, a.sp_sys, n_spill,
-                                h->d_err, h->stream));
+        HIP_TRY(FQ_LAUNCH(h->W, launch_rebucket, h->d_desc, s, S_old.key, S_old.pop, S_old.hd,
+                          S_old.bcnt, S_old.cap / BQ, a.sp_det, a.sp_pop, a.sp_hd, a.sp_sys,
+                          n_spill, h->d_err, h->stream));
         uint32_t err = 0;
         HIP_TRY(hipMemcpyAsync(&err, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -568,19 +600,19 @@ int rebucket_system(fciqmc_t *h, int s, int64_t new_cap, int64_t n_spill) {
     }
 }
 
-uint64_t aufbau(const std::vector<double> &h1, int M, int na, int nb) {
+hdet_t aufbau(const std::vector<double> &h1, int M, int na, int nb) {
     std::vector<int> order(M);
     for (int i = 0; i < M; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return h1[a * M + a] < h1[b * M + b]; });
-    uint64_t d = 0;
-    for (int i = 0; i < na; ++i) d |= 1ull << (2 * order[i]);
-    for (int i = 0; i < nb; ++i) d |= 1ull << (2 * order[i] + 1);
+    hdet_t d = 0;
+    for (int i = 0; i < na; ++i) d |= hbit(2 * order[i]);
+    for (int i = 0; i < nb; ++i) d |= hbit(2 * order[i] + 1);
     return d;
 }
 
 // Numbers of symmetry-allowed singles and doubles from det, counted per class.
-void excitation_counts(const SysHost &S, uint64_t det, int64_t &ns, int64_t &nd) {
+void excitation_counts(const SysHost &S, hdet_t det, int64_t &ns, int64_t &nd) {
     const int nso = 2 * S.M;
     int n_occ[NCLASS] = {0}, n_emp[NCLASS] = {0};
     auto cls = [&](int p) { return 2 * (int)S.irrep[p >> 1] + (p & 1); };
@@ -612,8 +644,10 @@ void excitation_counts(const SysHost &S, uint64_t det, int64_t &ns, int64_t &nd)
 
 int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     if (!ham || !prm) return set_err(FCIQMC_EINVAL, "null hamiltonian or params");
-    if (ham->n_orb < 1 || ham->n_orb > 32)
-        return set_err(FCIQMC_EINVAL, "n_orb must be in 1..32 (2*n_orb <= 64)");
+    if (ham->n_orb < 1 || ham->n_orb > 64)
+        return set_err(FCIQMC_EINVAL, "n_orb must be in 1..64 (2*n_orb <= 128)");
+    if (prm->det_words < 0 || prm->det_words > 2 || (prm->det_words == 1 && 2 * ham->n_orb > 64))
+        return set_err(FCIQMC_EINVAL, "det_words must be 0, 1 (at most 64 spin orbitals) or 2");
     if (ham->n_alpha < 0 || ham->n_beta < 0 || ham->n_alpha > ham->n_orb ||
         ham->n_beta > ham->n_orb || ham->n_alpha + ham->n_beta == 0)
         return set_err(FCIQMC_EINVAL, "bad electron counts");
@@ -630,7 +664,9 @@ int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
         return set_err(FCIQMC_EINVAL, "unknown space restriction");
     if (((prm->space & FCIQMC_SPACE_EXCITATION) && prm->max_excitation < 0) ||
         ((prm->space & FCIQMC_SPACE_SENIORITY) && prm->max_seniority < 0) ||
-        ((prm->space & FCIQMC_SPACE_FROZEN) && (prm->frozen_occupied & prm->frozen_empty)))
+        ((prm->space & FCIQMC_SPACE_FROZEN) &&
+         ((prm->frozen_occupied & prm->frozen_empty) ||
+          (prm->frozen_occupied_hi & prm->frozen_empty_hi))))
         return set_err(FCIQMC_EINVAL, "inconsistent space restriction");
     if (prm->hphf != 0 && prm->hphf != 1 && prm->hphf != -1)
         return set_err(FCIQMC_EINVAL, "hphf must be 0, 1 or -1");
@@ -641,20 +677,17 @@ int validate(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     return 0;
 }
 
-uint64_t host_spin_flip(uint64_t D) {
-    return ((D & 0x5555555555555555ull) << 1) | ((D >> 1) & 0x5555555555555555ull);
-}
+hdet_t host_spin_flip(hdet_t D) { return ((D & HEVEN) << 1) | ((D >> 1) & HEVEN); }
 
 // Whether det lies in the run's restricted space (host check of the reference).
-bool host_in_space(const fciqmc_params *prm, uint64_t d0, uint64_t det) {
-    if ((prm->space & FCIQMC_SPACE_EXCITATION) && __builtin_popcountll(det & ~d0) > prm->max_excitation)
+bool host_in_space(const fciqmc_params *prm, hdet_t d0, hdet_t det) {
+    if ((prm->space & FCIQMC_SPACE_EXCITATION) && hpopc(det & ~d0) > prm->max_excitation)
         return false;
-    if ((prm->space & FCIQMC_SPACE_SENIORITY) &&
-        __builtin_popcountll((det ^ (det >> 1)) & 0x5555555555555555ull) > prm->max_seniority)
+    if ((prm->space & FCIQMC_SPACE_SENIORITY) && hpopc((det ^ (det >> 1)) & HEVEN) > prm->max_seniority)
         return false;
-    if ((prm->space & FCIQMC_SPACE_FROZEN) &&
-        ((det & prm->frozen_occupied) != prm->frozen_occupied || (det & prm->frozen_empty)))
-        return false;
+    const hdet_t fo = ((hdet_t)prm->frozen_occupied_hi << 64) | (hdet_t)prm->frozen_occupied;
+    const hdet_t fe = ((hdet_t)prm->frozen_empty_hi << 64) | (hdet_t)prm->frozen_empty;
+    if ((prm->space & FCIQMC_SPACE_FROZEN) && ((det & fo) != fo || (det & fe))) return false;
     return true;
 }
 
@@ -667,10 +700,11 @@ int64_t initial_capacity(const fciqmc_params *prm) {
 // the target in entries, and its integrals.
 int64_t target_footprint(const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
     const int64_t cap = round_cap(2 * std::max<int64_t>(prm->target_walkers, 1));
-    return table_bytes(cap) + integral_bytes(ham->n_orb);
+    const int W = words_for(ham->n_orb, prm->det_words);
+    return table_bytes(cap, W) + integral_bytes(ham->n_orb, W);
 }
 
-int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop);
+int load_list(fciqmc_t *h, int s, const std::vector<hdet_t> &det, const std::vector<int32_t> &pop);
 
 // Admit a system into slot s (slot must be free).
 int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params *prm) {
@@ -690,11 +724,16 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     S.irrep.assign(S.M, 0);
     if (ham->orb_irrep) S.irrep.assign(ham->orb_irrep, ham->orb_irrep + S.M);
     const int nso = 2 * S.M;
-    const uint64_t valid = nso == 64 ? ~0ull : ((1ull << nso) - 1ull);
+    S.W = words_for(S.M, prm->det_words);
+    if (S.W != h->W)
+        return set_err(FCIQMC_EINVAL, "a batch holds determinants of one width: this system takes " +
+                                          std::to_string(S.W) + " 64-bit words, the batch " +
+                                          std::to_string(h->W));
+    const hdet_t valid = nso == 128 ? ~(hdet_t)0 : (hbit(nso) - 1);
     if (ham->ref_det) {
-        S.d0 = *ham->ref_det;
+        S.d0 = hdet_in(ham->ref_det, S.W);
         int a = 0, b = 0;
-        for (int p = 0; p < 64; ++p)
+        for (int p = 0; p < 128; ++p)
             if ((S.d0 >> p) & 1) (p & 1 ? b : a)++;
         if ((S.d0 & ~valid) || a != S.na || b != S.nb)
             return set_err(FCIQMC_EINVAL, "reference determinant does not match the electron counts");
@@ -711,7 +750,7 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
         S.p_double = (ns + nd) > 0 ? (double)nd / (double)(ns + nd) : 0.0;
     }
     if (prm->hphf) {   // the reference function, stored as the smaller determinant of its pair
-        const uint64_t f = host_spin_flip(S.d0);
+        const hdet_t f = host_spin_flip(S.d0);
         if (f == S.d0 && prm->hphf < 0)
             return set_err(FCIQMC_EINVAL, "a closed-shell reference has no odd-spin function");
         S.d0 = std::min(S.d0, f);
@@ -722,13 +761,16 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     HIP_TRY(hipMemGetInfo(&fr, &tot));
     int64_t reserved = 0;
     for (int t = 0; t < h->max_sys; ++t)
-        if (t != s && h->sys[t].active) reserved += std::max<int64_t>(0, h->sys[t].reserve_bytes - table_bytes(h->sys[t].cap));
+        if (t != s && h->sys[t].active)
+            reserved += std::max<int64_t>(0, h->sys[t].reserve_bytes - table_bytes(h->sys[t].cap, h->W));
     const int64_t need = S.reserve_bytes;
     if ((int64_t)fr - reserved < need + (int64_t)(1ull << 30))
         return set_err(FCIQMC_ENOMEM, "system footprint " + std::to_string(need) +
                                           " B does not fit in free device memory");
-    // Pair table for the diagonal elements: (pp|qq) - (pq|qp) over spin orbitals p < q.
-    S.jk.assign(64 * 64, 0.0);
+    // Pair table for the diagonal elements: (pp|qq) - (pq|qp) over spin orbitals p < q,
+    // rows of ns = 64 W entries.
+    const int ns = 64 * S.W;
+    S.jk.assign((size_t)ns * ns, 0.0);
     auto eri_sp = [&](int i, int j, int k, int l) {
         auto tri = [](int x, int y) { return x >= y ? (int64_t)x * (x + 1) / 2 + y : (int64_t)y * (y + 1) / 2 + x; };
         const int64_t a = tri(i, j), b = tri(k, l);
@@ -738,18 +780,18 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
         for (int q = p + 1; q < nso; ++q) {
             const double coul = eri_sp(p >> 1, p >> 1, q >> 1, q >> 1);
             const double exch = ((p ^ q) & 1) ? 0.0 : eri_sp(p >> 1, q >> 1, q >> 1, p >> 1);
-            S.jk[p * 64 + q] = coul - exch;
+            S.jk[(size_t)p * ns + q] = coul - exch;
         }
     // Single-excitation terms: for p -> a (same spin) and each spectator q,
     // (pa|qq) - [same spin](pq|qa), the difference the Slater-Condon sum adds.
-    S.t3.assign((size_t)nso * 64 * 64, 0.0);
+    S.t3.assign((size_t)nso * ns * ns, 0.0);
     for (int p = 0; p < nso; ++p)
         for (int a = 0; a < nso; ++a) {
             if ((p ^ a) & 1) continue;
             for (int q = 0; q < nso; ++q) {
                 const double coul = eri_sp(p >> 1, a >> 1, q >> 1, q >> 1);
                 const double exch = ((p ^ q) & 1) ? 0.0 : eri_sp(p >> 1, q >> 1, q >> 1, a >> 1);
-                S.t3[((size_t)p * 64 + a) * 64 + q] = coul - exch;
+                S.t3[((size_t)p * ns + a) * ns + q] = coul - exch;
             }
         }
     const int64_t cap = initial_capacity(prm);
@@ -784,8 +826,7 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     {
         // pgen of a double excitation without a point group, by the same operations
         // as the general branch of the kernels' excitation generator
-        const int ne[2] = {S.M - __builtin_popcountll(S.d0 & 0x5555555555555555ull),
-                           S.M - __builtin_popcountll(S.d0 & 0xAAAAAAAAAAAAAAAAull)};
+        const int ne[2] = {S.M - hpopc(S.d0 & HEVEN), S.M - hpopc(S.d0 & (HEVEN << 1))};
         d.n_emp[0] = ne[0];
         d.n_emp[1] = ne[1];
         auto pg = [&](int nba, int nbb, int nal) {
@@ -801,17 +842,31 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
     }
     d.target = prm->target_walkers;
     d.seed = prm->seed;
-    d.d0 = S.d0;
+    d.d0 = hlo(S.d0);
+    d.d0_hi = hhi(S.d0);
+    d.det_words = S.W;
     d.space = prm->space;
     d.max_ex = prm->max_excitation;
     d.max_sen = prm->max_seniority;
     d.frz_occ = prm->frozen_occupied;
     d.frz_emp = prm->frozen_empty;
+    d.frz_occ_hi = prm->frozen_occupied_hi;
+    d.frz_emp_hi = prm->frozen_empty_hi;
     d.hphf = prm->hphf;
     d.lam = ((S.N / 2) & 1) ? -prm->hphf : prm->hphf;
-    d.valid = valid;
-    for (int p = 0; p < nso; ++p) d.cmask[2 * S.irrep[p >> 1] + (p & 1)] |= 1ull << p;
-    for (int i = 0; i < S.M; ++i) d.irr_packed[i >> 4] |= (uint64_t)S.irrep[i] << (4 * (i & 15));
+    d.valid = hlo(valid);
+    d.valid_hi = hhi(valid);
+    for (int p = 0; p < nso; ++p) {
+        const int c = 2 * S.irrep[p >> 1] + (p & 1);
+        if (p < 64)
+            d.cmask[c] |= 1ull << p;
+        else
+            d.cmask_hi[c] |= 1ull << (p - 64);
+    }
+    for (int i = 0; i < S.M; ++i) {
+        uint64_t *w = i < 32 ? d.irr_packed : d.irr_packed_hi;
+        w[(i >> 4) & 1] |= (uint64_t)S.irrep[i] << (4 * (i & 15));
+    }
     d.shift = prm->initial_shift;
     fill_desc_tables(h, s);
     rc = relayout(h);
@@ -824,14 +879,16 @@ int admit(fciqmc_t *h, int s, const fciqmc_hamiltonian *ham, const fciqmc_params
 }
 
 // Replace the list of system s by (det, pop).
-int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::vector<int32_t> &pop) {
+int load_list(fciqmc_t *h, int s, const std::vector<hdet_t> &det, const std::vector<int32_t> &pop) {
     SysHost &S = h->sys[s];
     const int64_t n = (int64_t)det.size();
+    std::vector<uint64_t> words((size_t)n * S.W);
+    for (int64_t i = 0; i < n; ++i) hdet_out(det[i], &words[(size_t)i * S.W], S.W);
     uint64_t *dd = nullptr;
     int32_t *dp = nullptr;
-    HIP_TRY(hipMalloc(&dd, std::max<int64_t>(n, 1) * 8));
+    HIP_TRY(hipMalloc(&dd, std::max<int64_t>(n, 1) * 8 * S.W));
     HIP_TRY(hipMalloc(&dp, std::max<int64_t>(n, 1) * 4));
-    HIP_TRY(hipMemcpyAsync(dd, det.data(), n * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(dd, words.data(), n * 8 * S.W, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(dp, pop.data(), n * 4, hipMemcpyHostToDevice, h->stream));
     int64_t need = std::max<int64_t>(S.cap, cap_for_entries(n));
     int rc = 0;
@@ -858,7 +915,7 @@ int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::v
         rc = upload_desc(h);
         if (rc) break;
         HIP_TRY(hipMemsetAsync(h->d_err, 0, sizeof(uint32_t), h->stream));
-        HIP_TRY(launch_load(h->d_desc, s, dd, dp, n, h->d_err, h->stream));
+        HIP_TRY(FQ_LAUNCH(h->W, launch_load, h->d_desc, s, dd, dp, n, h->d_err, h->stream));
         uint32_t err = 0;
         HIP_TRY(hipMemcpyAsync(&err, h->d_err, 4, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -879,7 +936,7 @@ int load_list(fciqmc_t *h, int s, const std::vector<uint64_t> &det, const std::v
 int compute_e0(fciqmc_t *h, int s);
 
 struct Walkers {
-    std::vector<uint64_t> det;
+    std::vector<hdet_t> det;
     std::vector<int32_t> pop;
 };
 
@@ -888,24 +945,26 @@ int export_walkers(fciqmc_t *h, int s, Walkers &w) {
     uint64_t *od = nullptr;
     int32_t *op = nullptr;
     unsigned long long *cnt = nullptr;
-    HIP_TRY(hipMalloc(&od, S.cap * 8));
+    HIP_TRY(hipMalloc(&od, S.cap * 8 * S.W));
     HIP_TRY(hipMalloc(&op, S.cap * 4));
     HIP_TRY(hipMalloc(&cnt, 8));
     HIP_TRY(hipMemsetAsync(cnt, 0, 8, h->stream));
-    HIP_TRY(launch_compact(S.key, S.pop, S.bcnt, S.cap / BQ, od, op, cnt, h->stream));
+    HIP_TRY(FQ_LAUNCH(h->W, launch_compact, S.key, S.pop, S.bcnt, S.cap / BQ, od, op, cnt, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, cnt, 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    std::vector<uint64_t> dv(n);
+    std::vector<uint64_t> words(n * S.W);
+    std::vector<hdet_t> dv(n);
     std::vector<int32_t> pv(n);
     if (n) {
-        HIP_TRY(hipMemcpyAsync(dv.data(), od, n * 8, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(words.data(), od, n * 8 * S.W, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipMemcpyAsync(pv.data(), op, n * 4, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
     hipFree(od);
     hipFree(op);
     hipFree(cnt);
+    for (size_t i = 0; i < n; ++i) dv[i] = hdet_in(&words[i * S.W], S.W);
     std::vector<size_t> idx(n);
     for (size_t i = 0; i < n; ++i) idx[i] = i;
     std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return dv[a] < dv[b]; });
@@ -964,7 +1023,7 @@ int fill_estimates(fciqmc_t *h, int s, fciqmc_estimates *o) {
 }
 
 // Statistics of the list as loaded (before any iteration): N_w, N_d, C_0, num.
-int refresh_stats_after_load(fciqmc_t *h, int s, const std::vector<uint64_t> &det,
+int refresh_stats_after_load(fciqmc_t *h, int s, const std::vector<hdet_t> &det,
                              const std::vector<int32_t> &pop, double num) {
     SysHost &S = h->sys[s];
     IterRecord r{};
@@ -992,7 +1051,7 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
     for (int i = 0; i < L; ++i)
-        launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
+        FQ_LAUNCH(h->W, launch_iteration, a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
     HIP_TRY(hipStreamEndCapture(h->stream, &g));
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
@@ -1070,7 +1129,7 @@ int run_iterations(fciqmc_t *h, int L, bool sample) {
     EngineArgs a = make_args(h);
     if (h->profiling) {
         for (int i = 0; i < L; ++i) {
-            launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, h->ev);
+            FQ_LAUNCH(h->W, launch_iteration, a, h->post_grid, h->spawn_grid, i == 0, h->stream, h->ev);
             HIP_TRY(hipEventSynchronize(h->ev[NKERN]));
             for (int k = 0; k < NKERN; ++k) {
                 float ms = 0.f;
@@ -1089,7 +1148,7 @@ int run_iterations(fciqmc_t *h, int L, bool sample) {
             HIP_TRY(hipGraphLaunch(ex, h->stream));
         }
         if (sample) {
-            launch_iteration(a, h->post_grid, h->spawn_grid, true, h->stream, h->ev);
+            FQ_LAUNCH(h->W, launch_iteration, a, h->post_grid, h->spawn_grid, true, h->stream, h->ev);
             HIP_TRY(hipGetLastError());
             HIP_TRY(hipEventSynchronize(h->ev[NKERN]));
             for (int k = 0; k < NKERN; ++k) {
@@ -1100,7 +1159,7 @@ int run_iterations(fciqmc_t *h, int L, bool sample) {
         }
     } else {
         for (int i = 0; i < L; ++i)
-        launch_iteration(a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
+        FQ_LAUNCH(h->W, launch_iteration, a, h->post_grid, h->spawn_grid, i == 0, h->stream, nullptr);
         HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1239,9 +1298,10 @@ int resolve_stage(int dev, void **out) {
     return 0;
 }
 
-int create_handle(int max_slots, void *stream, fciqmc_t **out) {
+int create_handle(int max_slots, void *stream, int W, fciqmc_t **out) {
     fciqmc_t *h = new (std::nothrow) fciqmc_t();
     if (!h) return set_err(FCIQMC_ENOMEM, "host allocation failed");
+    h->W = W;
     HIP_TRY(hipGetDevice(&h->dev));
     {
         const int rc = resolve_stage(h->dev, &h->d_stage);
@@ -1288,7 +1348,7 @@ int create_handle(int max_slots, void *stream, fciqmc_t **out) {
         if (rc) return rc;
     }
     h->sp_cap = SPILL_CAP;
-    HIP_TRY(hipMalloc(&h->d_spill, (size_t)h->sp_cap * 24));
+    HIP_TRY(hipMalloc(&h->d_spill, (size_t)h->sp_cap * (16 + 8 * h->W)));
     HIP_TRY(hipMalloc(&h->d_sp_count, sizeof(unsigned long long)));
     HIP_TRY(hipMemsetAsync(h->d_sp_count, 0, sizeof(unsigned long long), h->stream));
     HIP_TRY(hipMalloc(&h->d_spilled, sizeof(uint32_t) * max_slots));
@@ -1312,7 +1372,8 @@ int compute_e0(fciqmc_t *h, int s) {
     HIP_TRY(hipMalloc(&d_out, 8));
     int rc = upload_desc(h);
     if (rc) return rc;
-    HIP_TRY(launch_e0(h->d_desc, s, h->sys[s].d0, d_out, h->stream));
+    HIP_TRY(FQ_LAUNCH(h->W, launch_e0, h->d_desc, s, hlo(h->sys[s].d0), hhi(h->sys[s].d0), d_out,
+                      h->stream));
     double e0 = 0;
     HIP_TRY(hipMemcpyAsync(&e0, d_out, 8, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1397,7 +1458,7 @@ int64_t walkers_out(fciqmc_t *h, int s, uint64_t *det, int32_t *pop, uint32_t *f
     const SysHost &S = h->sys[s];
     const int64_t n = (int64_t)w.det.size();
     for (int64_t i = 0; i < n && i < cap; ++i) {
-        if (det) det[i] = w.det[i];
+        if (det) hdet_out(w.det[i], det + i * S.W, S.W);
         if (pop) pop[i] = w.pop[i];
         if (flags) {
             const int64_t a = w.pop[i] < 0 ? -(int64_t)w.pop[i] : w.pop[i];
@@ -1425,8 +1486,13 @@ int fciqmc_batch_create(int32_t max_slots, int32_t n, const fciqmc_hamiltonian *
         int rc = validate(&hams[i], &prms[i]);
         if (rc) return rc;
     }
+    // one determinant width for the batch: the first system's (one word when empty)
+    const int W = n > 0 ? words_for(hams[0].n_orb, prms[0].det_words) : 1;
+    for (int i = 1; i < n; ++i)
+        if (words_for(hams[i].n_orb, prms[i].det_words) != W)
+            return set_err(FCIQMC_EINVAL, "a batch holds determinants of one width (64-bit words)");
     fciqmc_t *h = nullptr;
-    int rc = create_handle(max_slots, hip_stream, &h);
+    int rc = create_handle(max_slots, hip_stream, W, &h);
     if (rc) {
         release(h);
         return rc;
@@ -1480,6 +1546,11 @@ int fciqmc_batch_slot_estimators(fciqmc_t *h, int32_t slot, fciqmc_estimates *ou
     return fill_estimates(h, slot, out);
 }
 
+int32_t fciqmc_det_words(const fciqmc_t *h) {
+    if (!h) return set_err(FCIQMC_EINVAL, "null handle");
+    return h->W;
+}
+
 int64_t fciqmc_walkers(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_t *flags, int64_t cap) {
     if (!h) return set_err(FCIQMC_EINVAL, "null handle");
     return walkers_out(h, 0, det, pop, flags, cap);
@@ -1500,15 +1571,15 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
     const int s = 0;
     SysHost &S = h->sys[s];
     if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
-    const uint64_t valid = 2 * S.M == 64 ? ~0ull : ((1ull << (2 * S.M)) - 1ull);
-    std::vector<std::pair<uint64_t, int32_t>> v;
+    const hdet_t valid = 2 * S.M == 128 ? ~(hdet_t)0 : (hbit(2 * S.M) - 1);
+    std::vector<std::pair<hdet_t, int32_t>> v;
     v.reserve(n + 1);
     bool have_ref = false;
     for (int64_t i = 0; i < n; ++i) {
         if (pop[i] == 0) continue;
-        const uint64_t d = det[i];
+        const hdet_t d = hdet_in(det + i * S.W, S.W);
         int a = 0, b = 0;
-        for (int p = 0; p < 64; ++p)
+        for (int p = 0; p < 128; ++p)
             if ((d >> p) & 1) (p & 1 ? b : a)++;
         if ((d & ~valid) || a != S.na || b != S.nb)
             return set_err(FCIQMC_EINVAL, "determinant with wrong electron counts in walker list");
@@ -1526,7 +1597,7 @@ int fciqmc_load_walkers(fciqmc_t *h, const uint64_t *det, const int32_t *pop, in
     for (size_t i = 1; i < v.size(); ++i)
         if (v[i].first == v[i - 1].first)
             return set_err(FCIQMC_EINVAL, "duplicate determinant in walker list");
-    std::vector<uint64_t> dv(v.size());
+    std::vector<hdet_t> dv(v.size());
     std::vector<int32_t> pv(v.size());
     for (size_t i = 0; i < v.size(); ++i) {
         dv[i] = v[i].first;
@@ -1649,7 +1720,7 @@ int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *
 // walker list, the dynamics, the statistics and the per-iteration records.
 struct SysSnapshot {
     int s = 0;
-    std::vector<uint64_t> det;
+    std::vector<hdet_t> det;
     std::vector<int32_t> pop;
     SysDesc desc{};
     IterRecord last{};
@@ -1862,6 +1933,8 @@ int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_
     const int s = 0;
     const SysHost &S = h->sys[s];
     if (!S.active) return set_err(FCIQMC_ESTATE, "slot is not active");
+    if (h->W != 1)
+        return set_err(FCIQMC_ESTATE, "the staging export holds one-word determinants only");
     HIP_TRY(launch_stage_compact(S.key, S.pop, S.bcnt, S.cap / BQ, h->d_stage, h->stream));
     unsigned long long n = 0;
     HIP_TRY(hipMemcpyAsync(&n, h->d_stage, sizeof n, hipMemcpyDeviceToHost, h->stream));
@@ -1874,7 +1947,7 @@ int64_t fciqmc_walkers_noalloc(fciqmc_t *h, uint64_t *det, int32_t *pop, uint32_
     if (m > 0 && (det || pop || flags)) {
         HIP_TRY(launch_stage_sort(h->d_stage, (int64_t)n, h->stream));
         if (flags)
-            HIP_TRY(launch_stage_flags(h->d_stage, m, S.prm.initiator_threshold, S.d0, h->stream));
+            HIP_TRY(launch_stage_flags(h->d_stage, m, S.prm.initiator_threshold, hlo(S.d0), h->stream));
         const char *p = (const char *)h->d_stage;
         if (det)
             HIP_TRY(hipMemcpyAsync(det, p + NOALLOC_KEYS_OFF, (size_t)m * 8, hipMemcpyDeviceToHost,

@@ -39,11 +39,90 @@
 // oracle and are compiled with -ffp-contract=off.
 #include "engine.h"
 
+#ifndef FQ_DET_WORDS
+#define FQ_DET_WORDS 1
+#endif
+
 namespace fq {
+#if FQ_DET_WORDS == 2
+namespace w2 {
+#endif
+
+// ---------------------------------------------------------------------------
+// Determinants (Sec. 3): bit p set when spin orbital p is occupied, in as many
+// 64-bit words as the spin orbitals need. This file is compiled once per width:
+// one word (up to 64 spin orbitals, det_t = uint64_t) into namespace fq, two
+// words (up to 128, det_t = a 128-bit integer with the operations used here)
+// into fq::w2.
+// ---------------------------------------------------------------------------
+#if FQ_DET_WORDS == 1
+typedef uint64_t det_t;
+__device__ __forceinline__ uint64_t lo64(det_t x) { return x; }
+__device__ __forceinline__ uint64_t hi64(det_t) { return 0ull; }
+__device__ __forceinline__ det_t make_det(uint64_t lo, uint64_t) { return lo; }
+__device__ __forceinline__ int dpopc(det_t x) { return __popcll(x); }
+__device__ __forceinline__ int dctz(det_t x) { return __builtin_ctzll(x); }      // lowest set bit
+__device__ __forceinline__ int dhib(det_t x) { return 63 - __builtin_clzll(x); } // highest set bit
+#else
+struct det_t {
+    unsigned __int128 v;
+    det_t() = default;
+    __device__ constexpr explicit det_t(unsigned long long x) : v(x) {}
+    __device__ explicit operator bool() const { return v != 0; }
+};
+__device__ __forceinline__ det_t det_raw(unsigned __int128 v) {
+    det_t r;
+    r.v = v;
+    return r;
+}
+__device__ __forceinline__ det_t operator&(det_t a, det_t b) { return det_raw(a.v & b.v); }
+__device__ __forceinline__ det_t operator|(det_t a, det_t b) { return det_raw(a.v | b.v); }
+__device__ __forceinline__ det_t operator^(det_t a, det_t b) { return det_raw(a.v ^ b.v); }
+__device__ __forceinline__ det_t operator~(det_t a) { return det_raw(~a.v); }
+__device__ __forceinline__ det_t operator<<(det_t a, int k) { return det_raw(a.v << k); }
+__device__ __forceinline__ det_t operator>>(det_t a, int k) { return det_raw(a.v >> k); }
+__device__ __forceinline__ det_t operator-(det_t a, unsigned long long b) { return det_raw(a.v - b); }
+__device__ __forceinline__ det_t &operator&=(det_t &a, det_t b) { a.v &= b.v; return a; }
+__device__ __forceinline__ det_t &operator|=(det_t &a, det_t b) { a.v |= b.v; return a; }
+__device__ __forceinline__ det_t &operator^=(det_t &a, det_t b) { a.v ^= b.v; return a; }
+__device__ __forceinline__ bool operator==(det_t a, det_t b) { return a.v == b.v; }
+__device__ __forceinline__ bool operator!=(det_t a, det_t b) { return a.v != b.v; }
+__device__ __forceinline__ bool operator<(det_t a, det_t b) { return a.v < b.v; }
+__device__ __forceinline__ uint64_t lo64(det_t x) { return (uint64_t)x.v; }
+__device__ __forceinline__ uint64_t hi64(det_t x) { return (uint64_t)(x.v >> 64); }
+__device__ __forceinline__ det_t make_det(uint64_t lo, uint64_t hi) {
+    return det_raw(((unsigned __int128)hi << 64) | (unsigned __int128)lo);
+}
+__device__ __forceinline__ int dpopc(det_t x) { return __popcll(lo64(x)) + __popcll(hi64(x)); }
+__device__ __forceinline__ int dctz(det_t x) {
+    const uint64_t l = lo64(x);
+    return l ? __builtin_ctzll(l) : 64 + __builtin_ctzll(hi64(x));
+}
+__device__ __forceinline__ int dhib(det_t x) {
+    const uint64_t h = hi64(x);
+    return h ? 127 - __builtin_clzll(h) : 63 - __builtin_clzll(lo64(x));
+}
+#endif
+constexpr int NSO_MAX = 64 * FQ_DET_WORDS;   // spin orbitals a determinant holds
+#define DBIT(p) (det_t(1ull) << (p))
+__device__ __forceinline__ det_t even_bits() {
+    return make_det(0x5555555555555555ull, 0x5555555555555555ull);
+}
+__device__ __forceinline__ det_t odd_bits() {
+    return make_det(0xAAAAAAAAAAAAAAAAull, 0xAAAAAAAAAAAAAAAAull);
+}
+// The determinant-valued fields of a system's descriptor.
+__device__ __forceinline__ det_t ref_of(const SysDesc &d) { return make_det(d.d0, d.d0_hi); }
+__device__ __forceinline__ det_t valid_of(const SysDesc &d) { return make_det(d.valid, d.valid_hi); }
+__device__ __forceinline__ det_t cmask_of(const SysDesc &d, int c) {
+    return make_det(d.cmask[c], d.cmask_hi[c]);
+}
+__device__ __forceinline__ det_t *keys_of(const SysDesc &d) { return (det_t *)d.key; }
 
 // ---------------------------------------------------------------------------
 // Random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
-// Counter (lo32(D), hi32(D), k, ((iter mod 2^24) << 8) | block), key = seed.
+// Counter (bits 0-31 of D, bits 32-63 of D, k, ((iter mod 2^24) << 8) | block),
+// key = seed XOR (bits 64-127 of D), i.e. the seed up to 64 spin orbitals.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -62,11 +141,12 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
-__device__ __forceinline__ void draw2(uint64_t seed, uint64_t det, uint32_t k, int64_t iter,
+__device__ __forceinline__ void draw2(uint64_t seed, det_t det, uint32_t k, int64_t iter,
                                       uint32_t block, uint64_t &x0, uint64_t &x1) {
-    const uint4 ctr = make_uint4((uint32_t)det, (uint32_t)(det >> 32), k,
+    const uint64_t lo = lo64(det), key = seed ^ hi64(det);
+    const uint4 ctr = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), k,
                                  ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block);
-    const uint4 w = philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint4 w = philox10(ctr, (uint32_t)key, (uint32_t)(key >> 32));
     x0 = ((uint64_t)w.y << 32) | (uint64_t)w.x;
     x1 = ((uint64_t)w.w << 32) | (uint64_t)w.z;
 }
@@ -78,11 +158,12 @@ __device__ __forceinline__ double u01(uint64_t x) {
 // The four words of one Philox block of a spawning attempt: word 0 picks the
 // type and, rescaled within the chosen type's interval, is the acceptance
 // uniform; words 1-3 pick the orbitals.
-__device__ __forceinline__ uint4 draw_words(uint64_t seed, uint64_t det, uint32_t k, int64_t iter,
+__device__ __forceinline__ uint4 draw_words(uint64_t seed, det_t det, uint32_t k, int64_t iter,
                                             uint32_t block) {
-    const uint4 ctr = make_uint4((uint32_t)det, (uint32_t)(det >> 32), k,
+    const uint64_t lo = lo64(det), key = seed ^ hi64(det);
+    const uint4 ctr = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), k,
                                  ((uint32_t)((uint64_t)iter & 0xFFFFFFu) << 8) | block);
-    return philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return philox10(ctr, (uint32_t)key, (uint32_t)(key >> 32));
 }
 
 // w / 2^32, exact in double.
@@ -128,6 +209,12 @@ __device__ __forceinline__ int select_bit(uint64_t x, uint32_t k, const uint32_t
     if (k >= c) { k -= c; w >>= 8; pos += 8; }
     return pos + (int)((sel8[w & 0xFFu] >> (3u * k)) & 7u);
 }
+#if FQ_DET_WORDS == 2
+__device__ __forceinline__ int select_bit(det_t x, uint32_t k, const uint32_t *sel8) {
+    const uint32_t c = (uint32_t)__popcll(lo64(x));
+    return k < c ? select_bit(lo64(x), k, sel8) : 64 + select_bit(hi64(x), k - c, sel8);
+}
+#endif
 
 // 64-bit finaliser of MurmurHash3 (public domain): table placement only.
 __device__ __forceinline__ uint64_t mix64(uint64_t h) {
@@ -142,8 +229,12 @@ __device__ __forceinline__ uint64_t mix64(uint64_t h) {
 // Bucket of a determinant among nb buckets: the high word of mix64(D) * nb, i.e.
 // the hash scaled onto [0, nb) (the placement of Sec. 4.1's process hash; the
 // paper's Algorithm 1 is kept in the CPU oracle, results do not depend on it).
-__device__ __forceinline__ uint32_t bucket_of(uint64_t D, uint64_t nb) {
+__device__ __forceinline__ uint32_t bucket_of(det_t D, uint64_t nb) {
+#if FQ_DET_WORDS == 1
     return (uint32_t)__umul64hi(mix64(D), nb);
+#else
+    return (uint32_t)__umul64hi(mix64(lo64(D) ^ mix64(hi64(D) ^ 0x9E3779B97F4A7C15ull)), nb);
+#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -196,18 +287,67 @@ __device__ __forceinline__ void gstore_i4(void *p, int x, int y, int z, int w) {
     *gp(reinterpret_cast<v4i32 *>(p)) = v;
 }
 
-// Spawn records, one 16-byte access each.
-__device__ __forceinline__ void put_rec(SpawnRec *p, uint64_t D, int32_t w, uint32_t tag) {
+// Main-list keys in global memory (one 16-byte access for two words).
+#if FQ_DET_WORDS == 1
+__device__ __forceinline__ det_t ldk(const det_t *p) { return *gp(p); }
+__device__ __forceinline__ void stk(det_t *p, det_t v) { *gp(p) = v; }
+#else
+__device__ __forceinline__ det_t ldk(const det_t *p) {
+    const ulonglong2 w = gload_u2((const uint64_t *)p);
+    return make_det(w.x, w.y);
+}
+__device__ __forceinline__ void stk(det_t *p, det_t v) {
+    v2u64 w;
+    w.x = lo64(v);
+    w.y = hi64(v);
+    *gp(reinterpret_cast<v2u64 *>(p)) = w;
+}
+#endif
+
+// Spawn records: one 16-byte access each (two for two-word determinants, whose
+// records take 32 bytes).
+#if FQ_DET_WORDS == 1
+typedef SpawnRec rec_t;
+__device__ __forceinline__ void put_rec(rec_t *p, det_t D, int32_t w, uint32_t tag) {
     gstore_i4(p, (int)(uint32_t)D, (int)(uint32_t)(D >> 32), w, (int)tag);
 }
-__device__ __forceinline__ SpawnRec get_rec(const SpawnRec *p) {
+__device__ __forceinline__ rec_t get_rec(const rec_t *p) {
     const int4 x = gload_i4((const int32_t *)p);
-    SpawnRec r;
+    rec_t r;
     r.det = (uint64_t)(uint32_t)x.x | ((uint64_t)(uint32_t)x.y << 32);
     r.w = x.z;
     r.tag = (uint32_t)x.w;
     return r;
 }
+#else
+struct __attribute__((aligned(16))) rec_t {
+    det_t det;
+    int32_t w;
+    uint32_t tag;
+    uint64_t pad;
+};
+static_assert(sizeof(rec_t) == 32, "two-word spawn records take 32 bytes");
+__device__ __forceinline__ void put_rec(rec_t *p, det_t D, int32_t w, uint32_t tag) {
+    const uint64_t lo = lo64(D), hi = hi64(D);
+    gstore_i4(p, (int)(uint32_t)lo, (int)(uint32_t)(lo >> 32), (int)(uint32_t)hi,
+              (int)(uint32_t)(hi >> 32));
+    gstore_i4((char *)p + 16, w, (int)tag, 0, 0);
+}
+__device__ __forceinline__ rec_t get_rec(const rec_t *p) {
+    const int4 x = gload_i4((const int32_t *)p);
+    const int4 y = gload_i4((const int32_t *)p + 4);
+    rec_t r;
+    r.det = make_det((uint64_t)(uint32_t)x.x | ((uint64_t)(uint32_t)x.y << 32),
+                     (uint64_t)(uint32_t)x.z | ((uint64_t)(uint32_t)x.w << 32));
+    r.w = y.x;
+    r.tag = (uint32_t)y.y;
+    return r;
+}
+#endif
+static_assert(sizeof(rec_t) == 16 * FQ_DET_WORDS, "record size");
+__device__ __forceinline__ rec_t *recs_of(const EngineArgs &a) { return (rec_t *)a.recs; }
+__device__ __forceinline__ rec_t *srt_of(const EngineArgs &a) { return (rec_t *)a.srt; }
+__device__ __forceinline__ det_t *spill_dets(const EngineArgs &a) { return (det_t *)a.sp_det; }
 
 __device__ __forceinline__ double eri_so(const SysDesc &d, int p, int q, int r, int s) {
     if (((p ^ q) | (r ^ s)) & 1) return 0.0;
@@ -222,7 +362,12 @@ __device__ __forceinline__ double h_so(const SysDesc &d, int p, int q) {
 // Both words are read at uniform addresses (scalar loads); the lane's label is
 // then picked out with ALU operations only.
 __device__ __forceinline__ int irrep_of(const SysDesc &d, int s) {
+#if FQ_DET_WORDS == 1
     const uint64_t w0 = d.irr_packed[0], w1 = d.irr_packed[1];
+#else
+    const uint64_t w0 = (s & 32) ? d.irr_packed_hi[0] : d.irr_packed[0];
+    const uint64_t w1 = (s & 32) ? d.irr_packed_hi[1] : d.irr_packed[1];
+#endif
     return (int)((((s & 16) ? w1 : w0) >> (4 * (s & 15))) & 0xFull);
 }
 
@@ -231,24 +376,24 @@ __device__ __forceinline__ int class_of(const SysDesc &d, int p) {
 }
 
 // The orbitals strictly between p and a, and the parity of the occupied ones.
-__device__ __forceinline__ uint64_t between_mask(int p, int a) {
+__device__ __forceinline__ det_t between_mask(int p, int a) {
     const int lo = p < a ? p : a, hi = p < a ? a : p;
-    return ((1ull << hi) - 1ull) & ~((2ull << lo) - 1ull);
+    return (DBIT(hi) - 1ull) & ~((det_t(2ull) << lo) - 1ull);
 }
-__device__ __forceinline__ int between_parity(uint64_t det, int p, int a) {
-    return __popcll(det & between_mask(p, a)) & 1;
+__device__ __forceinline__ int between_parity(det_t det, int p, int a) {
+    return dpopc(det & between_mask(p, a)) & 1;
 }
 
-__device__ double hdiag_of(const SysDesc &d, uint64_t det) {
+__device__ double hdiag_of(const SysDesc &d, det_t det) {
     double acc = d.e_core;
-    for (uint64_t m = det; m; m &= m - 1) {
-        const int p = __builtin_ctzll(m);
+    for (det_t m = det; m; m &= m - 1ull) {
+        const int p = dctz(m);
         acc = acc + h_so(d, p, p);
     }
-    for (uint64_t m1 = det; m1; m1 &= m1 - 1) {
-        const int p = __builtin_ctzll(m1);
-        for (uint64_t m2 = m1 & (m1 - 1); m2; m2 &= m2 - 1) {
-            const int q = __builtin_ctzll(m2);
+    for (det_t m1 = det; m1; m1 &= m1 - 1ull) {
+        const int p = dctz(m1);
+        for (det_t m2 = m1 & (m1 - 1ull); m2; m2 &= m2 - 1ull) {
+            const int q = dctz(m2);
             acc = acc + (eri_so(d, p, p, q, q) - eri_so(d, p, q, q, p));
         }
     }
@@ -258,20 +403,20 @@ __device__ double hdiag_of(const SysDesc &d, uint64_t det) {
 // Single excitation p -> a: h_pa + sum over occupied q != p (ascending) of
 // (pa|qq) - [same spin](pq|qa), each term read from the precomputed row
 // t3[p][a][*]; four loads are issued before they are added, in order.
-__device__ double hel_single(const SysDesc &d, uint64_t det, int p, int a) {
+__device__ double hel_single(const SysDesc &d, det_t det, int p, int a) {
     double acc = h_so(d, p, a);
-    const gdouble *row = gptr(d.t3) + ((p * 64 + a) << 6);
-    uint64_t m = det & ~(1ull << p);
+    const gdouble *row = gptr(d.t3) + ((p * NSO_MAX + a) * NSO_MAX);
+    det_t m = det & ~DBIT(p);
     while (m) {
-        const int q0 = __builtin_ctzll(m);
-        m &= m - 1;
-        const int q1 = m ? __builtin_ctzll(m) : q0;
-        m &= m - 1;
-        const int q2 = m ? __builtin_ctzll(m) : q0;
-        m &= m - 1;
-        const int q3 = m ? __builtin_ctzll(m) : q0;
+        const int q0 = dctz(m);
+        m &= m - 1ull;
+        const int q1 = m ? dctz(m) : q0;
+        m &= m - 1ull;
+        const int q2 = m ? dctz(m) : q0;
+        m &= m - 1ull;
+        const int q3 = m ? dctz(m) : q0;
         const int n = 1 + (q1 != q0) + (q2 != q0) + (q3 != q0);
-        m &= m - 1;
+        m &= m - 1ull;
         const double v0 = row[q0], v1 = row[q1], v2 = row[q2], v3 = row[q3];
         acc = acc + v0;
         if (n > 1) acc = acc + v1;
@@ -283,7 +428,7 @@ __device__ double hel_single(const SysDesc &d, uint64_t det, int p, int a) {
 
 // p < q occupied, a, b empty. Pairing: unlike spins -> a' carries p's spin;
 // like spins -> a' = min(a, b). Sign: q -> b' on det, then p -> a'.
-__device__ double hel_double(const SysDesc &d, uint64_t det, int p, int q, int a, int b) {
+__device__ double hel_double(const SysDesc &d, det_t det, int p, int q, int a, int b) {
     int ap, bp;
     if ((p ^ q) & 1) {
         const bool a_with_p = ((a ^ p) & 1) == 0;
@@ -294,8 +439,8 @@ __device__ double hel_double(const SysDesc &d, uint64_t det, int p, int q, int a
         bp = a < b ? b : a;
     }
     // the two parities at once: parity(x) ^ parity(y) = parity(x ^ y)
-    const uint64_t d1 = (det & ~(1ull << q)) | (1ull << bp);
-    const int par = __popcll((det & between_mask(q, bp)) ^ (d1 & between_mask(p, ap))) & 1;
+    const det_t d1 = (det & ~DBIT(q)) | DBIT(bp);
+    const int par = dpopc((det & between_mask(q, bp)) ^ (d1 & between_mask(p, ap))) & 1;
     const double v = eri_so(d, p, ap, q, bp) - eri_so(d, p, bp, q, ap);
     return par ? -v : v;
 }
@@ -303,22 +448,24 @@ __device__ double hel_double(const SysDesc &d, uint64_t det, int p, int q, int a
 // Whether a child lies in the system's restricted space (Sec. 5: outside it the
 // excitation is null). Excitation level: electrons outside the reference's
 // orbitals; seniority: spatial orbitals holding exactly one electron.
-__device__ __forceinline__ bool in_space(const SysDesc &d, uint64_t det) {
+__device__ __forceinline__ bool in_space(const SysDesc &d, det_t det) {
     const int sp = d.space;
-    if ((sp & 1) && __popcll(det & ~d.d0) > d.max_ex) return false;
-    if ((sp & 2) && __popcll((det ^ (det >> 1)) & 0x5555555555555555ull) > d.max_sen) return false;
-    if ((sp & 4) && ((det & d.frz_occ) != d.frz_occ || (det & d.frz_emp) != 0ull)) return false;
+    if ((sp & 1) && dpopc(det & ~ref_of(d)) > d.max_ex) return false;
+    if ((sp & 2) && dpopc((det ^ (det >> 1)) & even_bits()) > d.max_sen) return false;
+    const det_t fo = make_det(d.frz_occ, d.frz_occ_hi), fe = make_det(d.frz_emp, d.frz_emp_hi);
+    if ((sp & 4) && ((det & fo) != fo || (det & fe))) return false;
     return true;
 }
 
 // <det|H|d0> for det != d0 within two excitations of d0 (d0 is the source).
-__device__ double hel_to_ref(const SysDesc &d, uint64_t det) {
-    const uint64_t from = d.d0 & ~det, to = det & ~d.d0;
-    const int nd = __popcll(from);
-    if (nd == 1) return hel_single(d, d.d0, __builtin_ctzll(from), __builtin_ctzll(to));
-    const int p = __builtin_ctzll(from), q = 63 - __builtin_clzll(from);
-    const int a = __builtin_ctzll(to), b = 63 - __builtin_clzll(to);
-    return hel_double(d, d.d0, p, q, a, b);
+__device__ double hel_to_ref(const SysDesc &d, det_t det) {
+    const det_t d0 = ref_of(d);
+    const det_t from = d0 & ~det, to = det & ~d0;
+    const int nd = dpopc(from);
+    if (nd == 1) return hel_single(d, d0, dctz(from), dctz(to));
+    const int p = dctz(from), q = dhib(from);
+    const int a = dctz(to), b = dhib(to);
+    return hel_double(d, d0, p, q, a, b);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,14 +474,12 @@ __device__ double hel_to_ref(const SysDesc &d, uint64_t det) {
 // Returns false for a null excitation.
 // ---------------------------------------------------------------------------
 struct Excit {
-    uint64_t det;
+    det_t det;
     double pgen;
     double hel;
     int p, a;
 };
 
-constexpr uint64_t EVEN_BITS = 0x5555555555555555ull;
-constexpr uint64_t ODD_BITS = 0xAAAAAAAAAAAAAAAAull;
 
 // Symmetry classes seen from the excitation generator. With no point group
 // (every orbital in irrep 0, two classes: the spins) everything is bit
@@ -342,10 +487,10 @@ constexpr uint64_t ODD_BITS = 0xAAAAAAAAAAAAAAAAull;
 // class index differs between lanes.
 template <bool C1>
 struct ClassView {
-    uint64_t valid;
-    const uint64_t *cm;   // LDS copy of SysDesc::cmask (unused when C1)
-    __device__ __forceinline__ uint64_t mask(int c) const {
-        if (C1) return valid & ((c & 1) ? ODD_BITS : EVEN_BITS);
+    det_t valid;
+    const det_t *cm;      // LDS copy of SysDesc::cmask (unused when C1)
+    __device__ __forceinline__ det_t mask(int c) const {
+        if (C1) return valid & ((c & 1) ? odd_bits() : even_bits());
         return cm[c];
     }
     __device__ __forceinline__ int irrep(const SysDesc &d, int s) const {
@@ -361,22 +506,22 @@ struct ClassView {
 // for a null excitation; otherwise the child, pgen and the orbitals p -> a.
 template <bool C1>
 __device__ __forceinline__ bool excite_single(const SysDesc &d, const ClassView<C1> &cv,
-                                              uint64_t det, uint32_t w1, uint32_t w2,
+                                              det_t det, uint32_t w1, uint32_t w2,
                                               const uint32_t *sel8, Excit &ex) {
-    const uint64_t emp = ~det & d.valid;
+    const det_t emp = ~det & valid_of(d);
     const int n_class = C1 ? 2 : d.n_class;
-    uint64_t movable = 0;
+    det_t movable = det_t(0ull);
     for (int c = 0; c < n_class; ++c) {
-        const uint64_t cm = C1 ? cv.mask(c) : d.cmask[c];
+        const det_t cm = C1 ? cv.mask(c) : cmask_of(d, c);
         if (emp & cm) movable |= det & cm;
     }
-    const uint32_t nmov = (uint32_t)__popcll(movable);
+    const uint32_t nmov = (uint32_t)dpopc(movable);
     if (nmov == 0) return false;
     const int p = select_bit(movable, pick(w1, nmov), sel8);
-    const uint64_t tg = emp & cv.mask(cv.cls(d, p));
-    const uint32_t nal = (uint32_t)__popcll(tg);
+    const det_t tg = emp & cv.mask(cv.cls(d, p));
+    const uint32_t nal = (uint32_t)dpopc(tg);
     const int a = select_bit(tg, pick(w2, nal), sel8);
-    ex.det = det ^ (1ull << p) ^ (1ull << a);
+    ex.det = det ^ DBIT(p) ^ DBIT(a);
     ex.pgen = d.p_single / (double)((int64_t)nal * (int64_t)nmov);
     ex.p = p;
     ex.a = a;
@@ -392,10 +537,10 @@ constexpr int EX_NULL = 0, EX_OK = 1, EX_SINGLE_DEFERRED = 2;
 // words and generates it later, so the rare singles do not make whole
 // wavefronts run the single path.
 template <bool C1>
-__device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv, uint64_t det,
+__device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv, det_t det,
                                       uint4 w, const double *recip, const uint32_t *sel8,
                                       bool defer_single, Excit &ex) {
-    const uint64_t emp = ~det & d.valid;
+    const det_t emp = ~det & valid_of(d);
     const int N = d.N;
     const int n_class = C1 ? 2 : d.n_class;
     if (!(u01_32(w.x) < d.p_double)) {
@@ -425,53 +570,53 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
         // spins alone, and pgen is one of four per-system values (the general branch
         // below gives the same sets, counts and pgen).
         const int sp = p & 1;
-        const uint64_t e0 = emp & EVEN_BITS, e1 = emp & ODD_BITS;
+        const det_t e0 = emp & even_bits(), e1 = emp & odd_bits();
         const uint32_t n0 = (uint32_t)d.n_emp[0], n1 = (uint32_t)d.n_emp[1];
-        uint64_t allowed;
+        det_t allowed;
         uint32_t nal;
         if (same) {
             allowed = sp ? e1 : e0;
             const uint32_t ne = sp ? n1 : n0;
             nal = ne >= 2 ? ne : 0;
         } else {
-            allowed = (n1 > 0 ? e0 : 0ull) | (n0 > 0 ? e1 : 0ull);
+            allowed = (n1 > 0 ? e0 : det_t(0ull)) | (n0 > 0 ? e1 : det_t(0ull));
             nal = (n1 > 0 ? n0 : 0u) + (n0 > 0 ? n1 : 0u);
         }
         if (nal == 0) return EX_NULL;
         a = select_bit(allowed, pick(w.z, nal), sel8);
         const int sa = a & 1;
-        const uint64_t bset = same ? (allowed & ~(1ull << a)) : (sa ? e0 : e1);
+        const det_t bset = same ? (allowed & ~DBIT(a)) : (sa ? e0 : e1);
         const uint32_t nba = same ? nal - 1 : (sa ? n0 : n1);
         b = select_bit(bset, pick(w.w, nba), sel8);
         ex.pgen = same ? (sp ? d.pgen_c1[1] : d.pgen_c1[0]) : (sa ? d.pgen_c1[3] : d.pgen_c1[2]);
     } else {
-        const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
+        const det_t A = same ? (emp & ((p & 1) ? odd_bits() : even_bits())) : emp;
         const int gpq = cv.irrep(d, p >> 1) ^ cv.irrep(d, q >> 1);
         // a orbitals whose partner class (Eq. sym1 plus spin) has an empty orbital besides a.
-        uint64_t allowed = 0;
+        det_t allowed = det_t(0ull);
         for (int c = 0; c < n_class; ++c) {
-            const uint64_t memb = A & d.cmask[c];
+            const det_t memb = A & cmask_of(d, c);
             if (!memb) continue;
             const int sb = same ? (p & 1) : 1 - (c & 1);
             const int pc = 2 * (gpq ^ (c >> 1)) + sb;
-            const int nb = __popcll(emp & cv.mask(pc)) - (pc == c ? 1 : 0);
+            const int nb = dpopc(emp & cv.mask(pc)) - (pc == c ? 1 : 0);
             if (nb > 0) allowed |= memb;
         }
-        const uint32_t nal = (uint32_t)__popcll(allowed);
+        const uint32_t nal = (uint32_t)dpopc(allowed);
         if (nal == 0) return EX_NULL;
         a = select_bit(allowed, pick(w.z, nal), sel8);
         const int ca = cv.cls(d, a);
         const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
-        const uint64_t bset = emp & cv.mask(pca) & ~(1ull << a);
-        const uint32_t nba = (uint32_t)__popcll(bset);
+        const det_t bset = emp & cv.mask(pca) & ~DBIT(a);
+        const uint32_t nba = (uint32_t)dpopc(bset);
         b = select_bit(bset, pick(w.w, nba), sel8);
         const int cb = cv.cls(d, b);
         const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
-        const int nbb = __popcll(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
+        const int nbb = dpopc(emp & cv.mask(pcb)) - (pcb == cb ? 1 : 0);
         ex.pgen = (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
                   (double)((int64_t)N * (int64_t)(N - 1) * (int64_t)nal);
     }
-    ex.det = det ^ (1ull << p) ^ (1ull << q) ^ (1ull << a) ^ (1ull << b);
+    ex.det = det ^ DBIT(p) ^ DBIT(q) ^ DBIT(a) ^ DBIT(b);
     ex.hel = hel_double(d, det, p, q, a, b);
     return EX_OK;
 }
@@ -484,33 +629,31 @@ __device__ __forceinline__ int excite(const SysDesc &d, const ClassView<C1> &cv,
 // (SysDesc::lam), or |D> for a closed pair D = D~ (even S only). A function is
 // stored as min(D, D~); excitations are drawn from that determinant only.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t spin_flip(uint64_t D) {
-    return ((D & EVEN_BITS) << 1) | ((D >> 1) & EVEN_BITS);
+__device__ __forceinline__ det_t spin_flip(det_t D) {
+    return ((D & even_bits()) << 1) | ((D >> 1) & even_bits());
 }
-__device__ __forceinline__ uint64_t fn_rep(uint64_t D) {
-    const uint64_t f = spin_flip(D);
+__device__ __forceinline__ det_t fn_rep(det_t D) {
+    const det_t f = spin_flip(D);
     return f < D ? f : D;
 }
-__device__ __forceinline__ int pair_sign(const SysDesc &d, uint64_t D) {
-    return (__popcll(D & (D >> 1) & EVEN_BITS) & 1) ? -d.lam : d.lam;
+__device__ __forceinline__ int pair_sign(const SysDesc &d, det_t D) {
+    return (dpopc(D & (D >> 1) & even_bits()) & 1) ? -d.lam : d.lam;
 }
 
 // <bra|H|ket> for a single or double excitation with ket the source (0 beyond).
-__device__ double hel_between(const SysDesc &d, uint64_t bra, uint64_t ket) {
-    const uint64_t from = ket & ~bra, to = bra & ~ket;
-    const int n = __popcll(from);
-    if (n == 1) return hel_single(d, ket, __builtin_ctzll(from), __builtin_ctzll(to));
-    if (n == 2)
-        return hel_double(d, ket, __builtin_ctzll(from), 63 - __builtin_clzll(from),
-                          __builtin_ctzll(to), 63 - __builtin_clzll(to));
+__device__ double hel_between(const SysDesc &d, det_t bra, det_t ket) {
+    const det_t from = ket & ~bra, to = bra & ~ket;
+    const int n = dpopc(from);
+    if (n == 1) return hel_single(d, ket, dctz(from), dctz(to));
+    if (n == 2) return hel_double(d, ket, dctz(from), dhib(from), dctz(to), dhib(to));
     return 0.0;
 }
 
 // <Phi_j|H|Phi_i> for the stored functions Dj != Di, Di the source: both open,
 // <Dj|H|Di> + lam (-1)^{n2(Dj)} <Dj~|H|Di>; one closed, sqrt2 <Dj|H|Di>; both
 // closed, <Dj|H|Di>.
-__device__ double fn_hel(const SysDesc &d, uint64_t Di, uint64_t Dj) {
-    const uint64_t fi = spin_flip(Di), fj = spin_flip(Dj);
+__device__ double fn_hel(const SysDesc &d, det_t Di, det_t Dj) {
+    const det_t fi = spin_flip(Di), fj = spin_flip(Dj);
     const double h = hel_between(d, Dj, Di);
     if (fi != Di && fj != Dj) return h + (double)pair_sign(d, Dj) * hel_between(d, fj, Di);
     if (fi != Di || fj != Dj) return 1.4142135623730951 * h;
@@ -518,51 +661,51 @@ __device__ double fn_hel(const SysDesc &d, uint64_t Di, uint64_t Dj) {
 }
 
 // Diagonal element of a stored function from its determinant's diagonal hd.
-__device__ __forceinline__ double fn_diag_from(const SysDesc &d, uint64_t D, double hd) {
+__device__ __forceinline__ double fn_diag_from(const SysDesc &d, det_t D, double hd) {
     if (!d.hphf) return hd;
-    const uint64_t f = spin_flip(D);
+    const det_t f = spin_flip(D);
     if (f == D) return hd;
     return hd + (double)pair_sign(d, D) * hel_between(d, f, D);
 }
-__device__ double fn_diag(const SysDesc &d, uint64_t D) { return fn_diag_from(d, D, hdiag_of(d, D)); }
+__device__ double fn_diag(const SysDesc &d, det_t D) { return fn_diag_from(d, D, hdiag_of(d, D)); }
 
 // Projected-energy element <Phi_0|H|Phi_D> (Eq. ProjE) and whether it can be
 // nonzero (D within a double excitation of the reference, or its partner).
-__device__ __forceinline__ bool near_ref(const SysDesc &d, uint64_t D) {
-    return __popcll(D ^ d.d0) <= 4 || (d.hphf && __popcll(spin_flip(D) ^ d.d0) <= 4);
+__device__ __forceinline__ bool near_ref(const SysDesc &d, det_t D) {
+    return dpopc(D ^ ref_of(d)) <= 4 || (d.hphf && dpopc(spin_flip(D) ^ ref_of(d)) <= 4);
 }
-__device__ double ref_hel(const SysDesc &d, uint64_t D) {
-    return d.hphf ? fn_hel(d, d.d0, D) : hel_to_ref(d, D);
+__device__ double ref_hel(const SysDesc &d, det_t D) {
+    return d.hphf ? fn_hel(d, ref_of(d), D) : hel_to_ref(d, D);
 }
 
 // The probability that excite() draws T from det (Secs. 5.1, 5.2) by the same
 // operations as the draw, 0 when it cannot draw T. recip[k] = 1/k.
-__device__ double pgen_target(const SysDesc &d, const uint64_t *cm, const double *recip,
-                              uint64_t det, uint64_t T) {
-    const uint64_t from = det & ~T, to = T & ~det;
-    const int nf = __popcll(from);
-    if (nf != __popcll(to)) return 0.0;
-    const uint64_t emp = ~det & d.valid;
+__device__ double pgen_target(const SysDesc &d, const det_t *cm, const double *recip,
+                              det_t det, det_t T) {
+    const det_t from = det & ~T, to = T & ~det;
+    const int nf = dpopc(from);
+    if (nf != dpopc(to)) return 0.0;
+    const det_t emp = ~det & valid_of(d);
     const bool c1 = d.n_class == 2;
-    auto mask = [&](int c) -> uint64_t {
-        return c1 ? (d.valid & ((c & 1) ? ODD_BITS : EVEN_BITS)) : cm[c];
+    auto mask = [&](int c) -> det_t {
+        return c1 ? (valid_of(d) & ((c & 1) ? odd_bits() : even_bits())) : cm[c];
     };
     auto cls = [&](int p) -> int { return c1 ? (p & 1) : class_of(d, p); };
     if (nf == 1) {
-        const int p = __builtin_ctzll(from), a = __builtin_ctzll(to);
+        const int p = dctz(from), a = dctz(to);
         if (cls(a) != cls(p)) return 0.0;
-        uint64_t movable = 0;
+        det_t movable = det_t(0ull);
         for (int c = 0; c < (c1 ? 2 : d.n_class); ++c) {
-            const uint64_t m = mask(c);
+            const det_t m = mask(c);
             if (emp & m) movable |= det & m;
         }
-        const uint32_t nmov = (uint32_t)__popcll(movable);
-        const uint32_t nal = (uint32_t)__popcll(emp & mask(cls(p)));
+        const uint32_t nmov = (uint32_t)dpopc(movable);
+        const uint32_t nal = (uint32_t)dpopc(emp & mask(cls(p)));
         return d.p_single / (double)((int64_t)nal * (int64_t)nmov);
     }
     if (nf != 2) return 0.0;
-    const int p = __builtin_ctzll(from), q = 63 - __builtin_clzll(from);
-    const int a = __builtin_ctzll(to), b = 63 - __builtin_clzll(to);
+    const int p = dctz(from), q = dhib(from);
+    const int a = dctz(to), b = dhib(to);
     const bool same = ((p ^ q) & 1) == 0;
     if (same ? (((a ^ p) & 1) || ((b ^ p) & 1)) : (((a ^ b) & 1) == 0)) return 0.0;
     if (c1) return same ? d.pgen_c1[p & 1] : d.pgen_c1[2 + (a & 1)];
@@ -570,20 +713,20 @@ __device__ double pgen_target(const SysDesc &d, const uint64_t *cm, const double
     const int ca = class_of(d, a), cb = class_of(d, b);
     const int pca = 2 * (gpq ^ (ca >> 1)) + (same ? (p & 1) : 1 - (ca & 1));
     if (cb != pca) return 0.0;
-    const uint64_t A = same ? (emp & ((p & 1) ? ODD_BITS : EVEN_BITS)) : emp;
-    uint64_t allowed = 0;
+    const det_t A = same ? (emp & ((p & 1) ? odd_bits() : even_bits())) : emp;
+    det_t allowed = det_t(0ull);
     for (int c = 0; c < d.n_class; ++c) {
-        const uint64_t memb = A & cm[c];
+        const det_t memb = A & cm[c];
         if (!memb) continue;
         const int sb = same ? (p & 1) : 1 - (c & 1);
         const int pc = 2 * (gpq ^ (c >> 1)) + sb;
-        const int nb = __popcll(emp & cm[pc]) - (pc == c ? 1 : 0);
+        const int nb = dpopc(emp & cm[pc]) - (pc == c ? 1 : 0);
         if (nb > 0) allowed |= memb;
     }
-    const uint32_t nal = (uint32_t)__popcll(allowed);
+    const uint32_t nal = (uint32_t)dpopc(allowed);
     const int pcb = 2 * (gpq ^ (cb >> 1)) + (same ? (p & 1) : 1 - (cb & 1));
-    const uint32_t nba = (uint32_t)__popcll(emp & cm[pca] & ~(1ull << a));
-    const int nbb = __popcll(emp & cm[pcb]) - (pcb == cb ? 1 : 0);
+    const uint32_t nba = (uint32_t)dpopc(emp & cm[pca] & ~DBIT(a));
+    const int nbb = dpopc(emp & cm[pcb]) - (pcb == cb ? 1 : 0);
     return (2.0 * d.p_double * (recip[nba] + recip[nbb])) /
            (double)((int64_t)d.N * (int64_t)(d.N - 1) * (int64_t)nal);
 }
@@ -592,9 +735,9 @@ __device__ double pgen_target(const SysDesc &d, const uint64_t *cm, const double
 // function holding the child, reached through the child or its partner (their
 // probabilities add); the pair of the source itself is diagonal (null), and so is a
 // closed pair in an odd-spin run. Returns false for a null excitation.
-__device__ bool to_function(const SysDesc &d, const uint64_t *cm, const double *recip,
-                            uint64_t D, Excit &ex) {
-    const uint64_t Dj = fn_rep(ex.det), fx = spin_flip(ex.det);
+__device__ bool to_function(const SysDesc &d, const det_t *cm, const double *recip,
+                            det_t D, Excit &ex) {
+    const det_t Dj = fn_rep(ex.det), fx = spin_flip(ex.det);
     if (Dj == D || (d.hphf < 0 && spin_flip(Dj) == Dj)) return false;
     if (fx != ex.det) ex.pgen = ex.pgen + pgen_target(d, cm, recip, D, fx);
     ex.hel = fn_hel(d, D, Dj);
@@ -850,7 +993,7 @@ __global__ __launch_bounds__(256) void k_scan_down(EngineArgs a) {
 // iteration sends it many: the reference is the hot spot of Sec. 4.1).
 constexpr uint32_t REC_UNRANKED = 0x40000000u;
 __device__ __forceinline__ void put_record(const EngineArgs &a, const SysDesc &d, int s,
-                                           unsigned long long j, uint64_t D, int32_t v, bool init,
+                                           unsigned long long j, det_t D, int32_t v, bool init,
                                            uint32_t *status) {
     if (j >= (unsigned long long)a.rec_cap) {
         atomicOr(status, ST_TABLE_FULL);
@@ -859,13 +1002,13 @@ __device__ __forceinline__ void put_record(const EngineArgs &a, const SysDesc &d
     const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(D, (uint64_t)d.nbuckets);
     a.rec_rank[j] = __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-    put_rec(a.recs + j, D, v, gb | (init ? 0x80000000u : 0u));
+    put_rec(recs_of(a) + j, D, v, gb | (init ? 0x80000000u : 0u));
 }
 
 // One record per active lane, with one buffer reservation for the wavefront
 // (callable from divergent code). Its bucket and rank are left to k_fix, which
 // keeps this path short in the spawning loop.
-__device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint64_t D, int32_t v,
+__device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, det_t D, int32_t v,
                                                 bool init, uint32_t *status) {
     const uint64_t m = __ballot(1);
     const int lane = threadIdx.x & 63;
@@ -878,7 +1021,7 @@ __device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint
         atomicOr(status, ST_TABLE_FULL);
         return;
     }
-    put_rec(a.recs + j, D, v, (uint32_t)s | REC_UNRANKED | (init ? 0x80000000u : 0u));
+    put_rec(recs_of(a) + j, D, v, (uint32_t)s | REC_UNRANKED | (init ? 0x80000000u : 0u));
 }
 
 // Work queued in LDS by the attempt loop and drained by the whole workgroup:
@@ -887,7 +1030,7 @@ __device__ __forceinline__ void put_record_wave(const EngineArgs &a, int s, uint
 // table is a chain of HBM round trips, overlapped with the other workgroups'
 // spawning).
 struct SingleItem {
-    uint64_t D;          // source determinant
+    det_t D;             // source determinant
     uint32_t w0, w1, w2; // type/acceptance, electron and hole words
     int32_t C;           // source population (sign)
     uint32_t init;       // initiator flag of the source
@@ -922,7 +1065,7 @@ __device__ __forceinline__ int32_t accept(const SysDesc &d, double hel, double p
 
 struct SpawnQueues {
     SingleItem sgl[SGL_QUEUE];
-    uint64_t spd[SPW_QUEUE];
+    det_t spd[SPW_QUEUE];
     int2 spv[SPW_QUEUE];   // (signed walkers, initiator flag)
     int nsgl, nspw, sys;
     unsigned long long base;   // first record of a drain
@@ -940,10 +1083,17 @@ __device__ __forceinline__ void flush_spawn_count(unsigned long long *counter,
 }
 
 // Drain both queues of system s with the whole workgroup (call uniformly).
+// cm_lds: the LDS copy of the system's class masks (the descriptor's own copy is
+// read instead for one-word determinants).
 __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc &d, int s,
-                             const uint32_t *sel8, const double *recip,
+                             const uint32_t *sel8, const double *recip, const det_t *cm_lds,
                              unsigned long long &spawned) {
     const int t = threadIdx.x;
+#if FQ_DET_WORDS == 1
+    const det_t *const cmk = d.cmask;
+#else
+    const det_t *const cmk = cm_lds;
+#endif
     uint32_t *status = &a.status[s];
     // a system whose record buffer overflowed re-runs the iteration: drop its queued work
     // (decided once for the workgroup: other workgroups may set the status meanwhile)
@@ -955,11 +1105,11 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         const SingleItem it = Q.sgl[j];
         Excit ex;
         const bool ok = d.n_class == 2
-                            ? excite_single(d, ClassView<true>{d.valid, nullptr}, it.D, it.w1, it.w2, sel8, ex)
-                            : excite_single(d, ClassView<false>{d.valid, d.cmask}, it.D, it.w1, it.w2, sel8, ex);
+                            ? excite_single(d, ClassView<true>{valid_of(d), nullptr}, it.D, it.w1, it.w2, sel8, ex)
+                            : excite_single(d, ClassView<false>{valid_of(d), cmk}, it.D, it.w1, it.w2, sel8, ex);
         if (!ok || (d.space && !in_space(d, ex.det))) continue;
         if (d.hphf) {
-            if (!to_function(d, d.cmask, recip, it.D, ex)) continue;
+            if (!to_function(d, cmk, recip, it.D, ex)) continue;
         } else {
             ex.hel = hel_single(d, it.D, ex.p, ex.a);
         }
@@ -968,9 +1118,9 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
         const int32_t v = accept(d, hel, ex.pgen, accept_uniform(d, it.w0), it.C, status);
         if (v == 0) continue;
         ++spawned;
-        const uint64_t Dn = ex.det;
+        const det_t Dn = ex.det;
         const bool init = it.init != 0;
-        if (Dn == d.d0) {
+        if (Dn == ref_of(d)) {
             __hip_atomic_fetch_add(&a.d0acc[s], (long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             continue;
         }
@@ -1022,7 +1172,7 @@ __device__ __forceinline__ int64_t last_le(const unsigned long long *v, int64_t 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5)))
 void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long s_incl[CHUNK];
-    __shared__ uint64_t s_det[CHUNK];
+    __shared__ det_t s_det[CHUNK];
     __shared__ int32_t s_pop[CHUNK];
     __shared__ unsigned long long s_wsum[4];
     __shared__ int s_wcnt[4];
@@ -1030,7 +1180,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned int s_tile;
     __shared__ double s_recip[65];
     __shared__ uint32_t s_sel8[256];
-    __shared__ uint64_t s_cm[NCLASS];
+    __shared__ det_t s_cm[NCLASS];
     __shared__ SpawnQueues Q;
     const unsigned long long n_tiles = a.total[1];
     const int64_t nch = *a.nchunks;
@@ -1081,13 +1231,13 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             // queued work and tallies belong to another system: finish them first
             if (Q.sys >= 0) {
                 const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, spawned);
+                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, s_cm, spawned);
                 flush_spawn_count(&a.spawns[qs], spawned);
             }
             __syncthreads();
             if (t == 0) Q.sys = s;
         }
-        if (t < NCLASS) s_cm[t] = d.cmask[t];   // ordered before use by the barrier below
+        if (t < NCLASS) s_cm[t] = cmask_of(d, t);   // ordered before use by the barrier below
         // Stage the chunk's entries that hold walkers (its four buckets, one per
         // wavefront, four entries per lane), compacted, with the inclusive prefix sum
         // of |C|. Only the lanes over a bucket's entries read (the entries are packed
@@ -1096,15 +1246,27 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         const int64_t base = lb * BQ + 4 * lane;
         const int n_b = d.bcnt[lb] - 4 * lane;
         int4 pv = make_int4(0, 0, 0, 0);
+#if FQ_DET_WORDS == 1
         ulonglong2 k01 = make_ulonglong2(0ull, 0ull), k23 = make_ulonglong2(0ull, 0ull);
         if (n_b > 0) {
             pv = gload_i4(d.pop + base);
             k01 = gload_u2(d.key + base);
             k23 = gload_u2(d.key + base + 2);
         }
+#else
+        det_t kk[4] = {det_t(0ull), det_t(0ull), det_t(0ull), det_t(0ull)};
+        if (n_b > 0) {
+            pv = gload_i4(d.pop + base);
+            for (int u = 0; u < 4; ++u) kk[u] = ldk(keys_of(d) + base + u);
+        }
+#endif
         const int32_t pa[4] = {0 < n_b ? pv.x : 0, 1 < n_b ? pv.y : 0, 2 < n_b ? pv.z : 0,
                                3 < n_b ? pv.w : 0};
+#if FQ_DET_WORDS == 1
         const uint64_t ka[4] = {k01.x, k01.y, k23.x, k23.y};
+#else
+        const det_t ka[4] = {kk[0], kk[1], kk[2], kk[3]};
+#endif
         const int nocc = (pa[0] != 0) + (pa[1] != 0) + (pa[2] != 0) + (pa[3] != 0);
         unsigned long long run = 0;
 #pragma unroll
@@ -1156,8 +1318,8 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         const bool c1 = d.n_class == 2;          // no point group: classes are the spins
         const bool restricted = d.space != 0;    // children outside the space are null
         const bool coupled = d.hphf != 0;        // walkers on spin-coupled functions
-        ClassView<true> cv1{d.valid, nullptr};
-        ClassView<false> cvg{d.valid, s_cm};
+        ClassView<true> cv1{valid_of(d), nullptr};
+        ClassView<false> cvg{valid_of(d), s_cm};
         if (at < at_end && !stopped) {
             const unsigned long long local = at - off_c;
             int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
@@ -1169,9 +1331,9 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             uint32_t k = (uint32_t)(local - (sl ? s_incl[sl - 1] : 0ull));
             for (;;) {
                 const int32_t C = s_pop[sl];
-                const uint64_t D = s_det[sl];
+                const det_t D = s_det[sl];
                 const int64_t absC = C < 0 ? -(int64_t)C : (int64_t)C;
-                const bool init = absC > d.n_a || D == d.d0;
+                const bool init = absC > d.n_a || D == ref_of(d);
                 const uint4 w = draw_words(d.seed, D, k, d.iter, 0u);
                 Excit ex;
                 int r = c1 ? excite(d, cv1, D, w, s_recip, s_sel8, defer, ex)
@@ -1194,7 +1356,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (r == EX_OK) {
                     if (ex.hel != 0.0) {
                         const int32_t v = accept(d, ex.hel, ex.pgen, accept_uniform(d, w.x), C, status);
-                        if (v != 0 && ex.det == d.d0) {
+                        if (v != 0 && ex.det == ref_of(d)) {
                             ++spawned;
                             __hip_atomic_fetch_add(&a.d0acc[s], (long long)v, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
@@ -1218,12 +1380,12 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             }
         }
         __syncthreads();
-        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, s_sel8, s_recip, spawned);
+        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, s_sel8, s_recip, s_cm, spawned);
     }
     __syncthreads();
     if (Q.sys >= 0) {
         const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, spawned);
+        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, s_cm, spawned);
         flush_spawn_count(&a.spawns[qs], spawned);
     }
 }
@@ -1237,13 +1399,13 @@ __global__ __launch_bounds__(256) void k_fix(EngineArgs a, const SysDesc *__rest
     const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t gf = a.recs[i].tag;
+        const uint32_t gf = recs_of(a)[i].tag;
         if (!(gf & REC_UNRANKED)) continue;
         const SysDesc &d = desc[gf & 0x3FFFFFFFu];
-        const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(a.recs[i].det, (uint64_t)d.nbuckets);
+        const uint32_t gb = (uint32_t)(d.gchunk0 * BPC) + bucket_of(recs_of(a)[i].det, (uint64_t)d.nbuckets);
         a.rec_rank[i] = __hip_atomic_fetch_add(&a.bhist[gb], 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-        a.recs[i].tag = gb | (gf & 0x80000000u);
+        recs_of(a)[i].tag = gb | (gf & 0x80000000u);
     }
 }
 
@@ -1330,10 +1492,10 @@ __global__ __launch_bounds__(256) void k_scatter(EngineArgs a) {
     const int64_t n = cnt < (unsigned long long)a.rec_cap ? (int64_t)cnt : a.rec_cap;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const SpawnRec r = get_rec(a.recs + i);
+        const rec_t r = get_rec(recs_of(a) + i);
         const uint32_t gb = r.tag & 0x7FFFFFFFu;
         const uint32_t pos = a.boff[gb] + a.rec_rank[i];
-        put_rec(a.srt + pos, r.det, r.w, r.tag >> 31);
+        put_rec(srt_of(a) + pos, r.det, r.w, r.tag >> 31);
     }
 }
 
@@ -1370,13 +1532,30 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Home slot: a multiplicative hash of the two folded words (the determinants of one
+// Home slot: a multiplicative hash of the folded words (the determinants of one
 // bucket agree in the bits of mix64 that chose the bucket, not in these).
 static_assert(WHASH == 128, "wh_home takes the top 7 bits of the product");
-__device__ __forceinline__ uint32_t wh_home(uint64_t D) {
-    return (((uint32_t)D ^ (uint32_t)(D >> 32)) * 0x9E3779B1u) >> 25;
+__device__ __forceinline__ uint32_t wh_home(det_t D) {
+    const uint64_t f = lo64(D) ^ hi64(D);
+    return (((uint32_t)f ^ (uint32_t)(f >> 32)) * 0x9E3779B1u) >> 25;
 }
 
+// A wavefront's working set in k_post: its merge hash (children, walkers arrived,
+// flags) and the positions emptied in its bucket. One-word children mark an empty
+// slot by 0 and are claimed by a 64-bit compare-and-swap; two-word children have no
+// such atomic, so a 32-bit owner word (0: empty, else the claiming lane + 1) is
+// claimed and the owner then writes the child.
+struct WaveLds {
+    det_t key[WHASH];          // child (one word: 0 when empty)
+    long long acc[WHASH];      // walkers arrived for it
+    uint32_t flg[WHASH];       // F_INIT | F_MATCHED
+#if FQ_DET_WORDS == 2
+    uint32_t own[WHASH];       // 0: empty; else the lane that entered the child, + 1
+#endif
+    uint16_t free_[BQ];        // positions emptied this iteration, ascending
+};
+
+#if FQ_DET_WORDS == 1
 // Slot of D in a wavefront's hash (-1: absent). Call when no lane inserts.
 __device__ __forceinline__ int wh_find(uint64_t D, const uint64_t *hk) {
     uint32_t h = wh_home(D);
@@ -1432,6 +1611,71 @@ __device__ __forceinline__ int wh_claim_limited(uint64_t D, uint64_t *hk, int *n
     return -1;
 }
 
+__device__ __forceinline__ int wl_find(det_t D, const WaveLds &W) { return wh_find(D, W.key); }
+__device__ __forceinline__ int wl_claim(det_t D, WaveLds &W, bool *own, int) {
+    return wh_claim(D, W.key, own);
+}
+__device__ __forceinline__ int wl_claim_limited(det_t D, WaveLds &W, int *ncl, int) {
+    return wh_claim_limited(D, W.key, ncl);
+}
+__device__ __forceinline__ bool wl_used(const WaveLds &W, int h) { return W.key[h] != 0ull; }
+__device__ __forceinline__ void wl_clear(WaveLds &W, int h) { W.key[h] = 0ull; }
+#else
+__device__ __forceinline__ bool wl_used(const WaveLds &W, int h) { return W.own[h] != 0u; }
+__device__ __forceinline__ void wl_clear(WaveLds &W, int h) { W.own[h] = 0u; }
+__device__ __forceinline__ int wl_find(det_t D, const WaveLds &W) {
+    uint32_t h = wh_home(D);
+    for (int k = 0; k < WHASH; ++k) {
+        if (W.own[h] == 0u) return -1;
+        if (W.key[h] == D) return (int)h;
+        h = (h + 1u) & (uint32_t)(WHASH - 1);
+    }
+    return -1;
+}
+// Claim of a slot: lanes that find it empty race for its owner word; the winner
+// writes the child, and after the wave-level ordering point every lane still
+// probing compares the (now written) child with its own. A lane whose probe ends
+// early leaves the loop masked off; the others stay in step.
+__device__ __forceinline__ int wl_claim(det_t D, WaveLds &W, bool *own, int lane) {
+    uint32_t h = wh_home(D);
+    *own = false;
+    for (;;) {
+        bool won = false;
+        if (W.own[h] == 0u) won = atomicCAS(&W.own[h], 0u, (uint32_t)lane + 1u) == 0u;
+        if (won) W.key[h] = D;
+        wave_sync();
+        if (won) {
+            *own = true;
+            return (int)h;
+        }
+        if (W.key[h] == D) return (int)h;
+        h = (h + 1u) & (uint32_t)(WHASH - 1);
+    }
+}
+__device__ __forceinline__ int wl_claim_limited(det_t D, WaveLds &W, int *ncl, int lane) {
+    uint32_t h = wh_home(D);
+    for (int k = 0; k < WHASH; ++k) {
+        bool won = false, full = false;
+        if (W.own[h] == 0u) {
+            if (atomicAdd(ncl, 1) >= NREC) {
+                atomicSub(ncl, 1);
+                full = true;
+            } else {
+                won = atomicCAS(&W.own[h], 0u, (uint32_t)lane + 1u) == 0u;
+                if (!won) atomicSub(ncl, 1);   // the slot went to another lane's claim
+            }
+        }
+        if (won) W.key[h] = D;
+        wave_sync();
+        if (won) return (int)h;
+        if (full) return -1;
+        if (W.key[h] == D) return (int)h;
+        h = (h + 1u) & (uint32_t)(WHASH - 1);
+    }
+    return -1;
+}
+#endif
+
 // H_DD = E_core + sum_p h_pp + sum_{p<q} [(pp|qq) - (pq|qp)], accumulated in
 // ascending (p, q) order from the LDS copies of h_pp and of the pair table (its
 // upper triangle, row after row: entry (p, q) at pair_row(p, n) + q), for two
@@ -1440,21 +1684,21 @@ __device__ __forceinline__ int wh_claim_limited(uint64_t D, uint64_t *hk, int *n
 // order of a single sum.
 __device__ __forceinline__ int pair_row(int p, int n) { return p * (2 * n - p - 3) / 2 - 1; }
 
-__device__ __forceinline__ void hdiag_lds2(double e_core, uint64_t da, uint64_t db,
+__device__ __forceinline__ void hdiag_lds2(double e_core, det_t da, det_t db,
                                            const double *hpp, const double *jk, int n,
                                            double &ra, double &rb) {
     double xa = e_core, xb = e_core;
-    for (uint64_t ma = da, mb = db; ma; ma &= ma - 1, mb &= mb - 1) {
-        xa = xa + hpp[__builtin_ctzll(ma)];
-        xb = xb + hpp[__builtin_ctzll(mb)];
+    for (det_t ma = da, mb = db; ma; ma &= ma - 1ull, mb &= mb - 1ull) {
+        xa = xa + hpp[dctz(ma)];
+        xb = xb + hpp[dctz(mb)];
     }
-    for (uint64_t m1a = da, m1b = db; m1a; m1a &= m1a - 1, m1b &= m1b - 1) {
-        const int ba = pair_row(__builtin_ctzll(m1a), n);
-        const int bb = pair_row(__builtin_ctzll(m1b), n);
-        for (uint64_t m2a = m1a & (m1a - 1), m2b = m1b & (m1b - 1); m2a;
-             m2a &= m2a - 1, m2b &= m2b - 1) {
-            xa = xa + jk[ba + __builtin_ctzll(m2a)];
-            xb = xb + jk[bb + __builtin_ctzll(m2b)];
+    for (det_t m1a = da, m1b = db; m1a; m1a &= m1a - 1ull, m1b &= m1b - 1ull) {
+        const int ba = pair_row(dctz(m1a), n);
+        const int bb = pair_row(dctz(m1b), n);
+        for (det_t m2a = m1a & (m1a - 1ull), m2b = m1b & (m1b - 1ull); m2a;
+             m2a &= m2a - 1ull, m2b &= m2b - 1ull) {
+            xa = xa + jk[ba + dctz(m2a)];
+            xb = xb + jk[bb + dctz(m2b)];
         }
     }
     ra = xa;
@@ -1472,7 +1716,7 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
         const bool two = j + (int)blockDim.x < n;
         const uint32_t i1 = two ? queue[j + blockDim.x] : i0;
         double h0, h1;
-        const uint64_t k0 = *gp(d.key + i0), k1 = *gp(d.key + i1);
+        const det_t k0 = ldk(keys_of(d) + i0), k1 = ldk(keys_of(d) + i1);
         hdiag_lds2(d.e_core, k0, k1, hpp, jk, d.n_so, h0, h1);
         *gp(d.hdiag + i0) = fn_diag_from(d, k0, h0);
         if (two) *gp(d.hdiag + i1) = fn_diag_from(d, k1, h1);
@@ -1490,12 +1734,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     // Each wavefront's working set, and (between chunks only) the pair table from
     // which the diagonal elements of new determinants are computed.
-    struct WaveLds {
-        uint64_t key[WHASH];       // child (0: empty)
-        long long acc[WHASH];      // walkers arrived for it
-        uint32_t flg[WHASH];       // F_INIT | F_MATCHED
-        uint16_t free_[BQ];        // positions emptied this iteration, ascending
-    };
     union PostLds {
         WaveLds w[POST_WAVES];
         struct {
@@ -1606,31 +1844,31 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (lane == 0 && s_qsys < 0) atomicCAS(&s_qsys, -1, s);
                 // entry u * 64 + lane is this lane's u-th; R rounds cover the n entries
                 const int R = (n + 63) >> 6;
-                uint64_t kin[4] = {0ull, 0ull, 0ull, 0ull};
+                det_t kin[4] = {det_t(0ull), det_t(0ull), det_t(0ull), det_t(0ull)};
                 int32_t pin[4] = {0, 0, 0, 0};
                 double hin[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (u >= R) break;
                     if ((u << 6) + lane < n) {
-                        kin[u] = *gp(d.key + base + (u << 6) + lane);
+                        kin[u] = ldk(keys_of(d) + base + (u << 6) + lane);
                         pin[u] = *gp(d.pop + base + (u << 6) + lane);
                         hin[u] = *gp(d.hdiag + base + (u << 6) + lane);
                     }
                 }
-                uint64_t rd = 0ull;   // this lane's record (fast path), its hash slot, and
+                det_t rd = det_t(0ull);   // this lane's record (fast path), its hash slot, and
                 int32_t rw = 0;       // whether this lane entered the child there
                 uint32_t rf = 0u;
                 int rh = 0;
                 bool rown = false;
                 if ((uint32_t)lane < nr && nr <= (uint32_t)NREC) {
-                    const SpawnRec r = get_rec(a.srt + r0 + lane);
+                    const rec_t r = get_rec(srt_of(a) + r0 + lane);
                     rd = r.det;
                     rw = r.w;
                     rf = r.tag;
                 }
-                W.key[lane] = 0ull;
-                W.key[lane + 64] = 0ull;
+                wl_clear(W, lane);
+                wl_clear(W, lane + 64);
                 W.acc[lane] = 0ll;
                 W.acc[lane + 64] = 0ll;
                 W.flg[lane] = 0u;
@@ -1665,7 +1903,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 if (nr <= (uint32_t)NREC) {
                     // Fast path: at most NREC records, so at most NREC distinct children.
                     if ((uint32_t)lane < nr) {
-                        rh = wh_claim(rd, W.key, &rown);
+                        rh = wl_claim(rd, W, &rown, lane);
                         atomicAdd((unsigned long long *)&W.acc[rh], (unsigned long long)(long long)rw);
                         if (rf & F_INIT) atomicOr(&W.flg[rh], F_INIT);
                     }
@@ -1675,7 +1913,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         for (int u = 0; u < 4; ++u) {
                             if (u >= R) break;
                             if ((u << 6) + lane >= n) continue;
-                            const int h = wh_find(kin[u], W.key);
+                            const int h = wl_find(kin[u], W);
                             if (h < 0) continue;
                             spv[u] = W.acc[h];
                             flv |= (W.flg[h] & F_INIT) << u;
@@ -1690,8 +1928,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     // of the unsorted record buffer.
                     for (int round = 0;; ++round) {
                         if (round > 0) {
-                            W.key[lane] = 0ull;
-                            W.key[lane + 64] = 0ull;
+                            wl_clear(W, lane);
+                            wl_clear(W, lane + 64);
                             W.acc[lane] = 0ll;
                             W.acc[lane + 64] = 0ll;
                             W.flg[lane] = 0u;
@@ -1701,35 +1939,37 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         wave_sync();
                         bool maybe = false;
                         for (uint32_t j = lane; j < nr; j += 64) {   // (a record stays with its lane)
-                            const uint32_t f = a.srt[r0 + j].tag;
+                            rec_t *const srt = srt_of(a);
+                            const uint32_t f = srt[r0 + j].tag;
                             if (round > 0 && !(f & F_DEFER)) continue;
-                            const uint64_t D = a.srt[r0 + j].det;
-                            const int h = wh_claim_limited(D, W.key, &s_ncl[wid]);
+                            const det_t D = srt[r0 + j].det;
+                            const int h = wl_claim_limited(D, W, &s_ncl[wid], lane);
                             if (h < 0) {
-                                a.srt[r0 + j].tag = (f & F_INIT) | F_MAYBE;
+                                srt[r0 + j].tag = (f & F_INIT) | F_MAYBE;
                                 maybe = true;
                                 continue;
                             }
-                            if (f & F_DEFER) a.srt[r0 + j].tag = f & F_INIT;
+                            if (f & F_DEFER) srt[r0 + j].tag = f & F_INIT;
                             atomicAdd((unsigned long long *)&W.acc[h],
-                                      (unsigned long long)(long long)a.srt[r0 + j].w);
+                                      (unsigned long long)(long long)srt[r0 + j].w);
                             if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
                         }
                         wave_sync();
                         bool defer = false;
                         if (__ballot(maybe)) {
                             for (uint32_t j = lane; j < nr; j += 64) {
-                                const uint32_t f = a.srt[r0 + j].tag;
+                                rec_t *const srt = srt_of(a);
+                                const uint32_t f = srt[r0 + j].tag;
                                 if (!(f & F_MAYBE)) continue;
-                                const int h = wh_find(a.srt[r0 + j].det, W.key);
+                                const int h = wl_find(srt[r0 + j].det, W);
                                 if (h < 0) {
-                                    a.srt[r0 + j].tag = (f & F_INIT) | F_DEFER;
+                                    srt[r0 + j].tag = (f & F_INIT) | F_DEFER;
                                     defer = true;
                                     continue;
                                 }
-                                a.srt[r0 + j].tag = f & F_INIT;
+                                srt[r0 + j].tag = f & F_INIT;
                                 atomicAdd((unsigned long long *)&W.acc[h],
-                                          (unsigned long long)(long long)a.srt[r0 + j].w);
+                                          (unsigned long long)(long long)srt[r0 + j].w);
                                 if (f & F_INIT) atomicOr(&W.flg[h], F_INIT);
                             }
                             wave_sync();
@@ -1738,7 +1978,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         for (int u = 0; u < 4; ++u) {
                             if (u >= R) break;
                             if ((u << 6) + lane >= n) continue;
-                            const int h = wh_find(kin[u], W.key);
+                            const int h = wl_find(kin[u], W);
                             if (h < 0) continue;
                             spv[u] += W.acc[h];
                             flv |= (W.flg[h] & F_INIT) << u;
@@ -1747,8 +1987,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         wave_sync();
                         // stage this round's children outside the bucket (one per slot)
                         for (int h = lane; h < WHASH; h += 64) {
-                            const uint64_t D = W.key[h];
-                            const bool cand = D != 0ull && !(W.flg[h] & F_MATCHED);
+                            const det_t D = W.key[h];
+                            const bool cand = wl_used(W, h) && !(W.flg[h] & F_MATCHED);
                             const uint64_t m = __ballot(cand);
                             if (cand) {
                                 const uint32_t j = r0 + (uint32_t)kc + (uint32_t)__popcll(m & lanes_below(lane));
@@ -1757,7 +1997,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                                     atomicOr(status, ST_POP_OVERFLOW);
                                     sp = 0;
                                 }
-                                put_rec(a.recs + j, D, (int32_t)sp, W.flg[h] & F_INIT);
+                                put_rec(recs_of(a) + j, D, (int32_t)sp, W.flg[h] & F_INIT);
                             }
                             kc += __popcll(m);
                         }
@@ -1777,8 +2017,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (u >= R) break;
-                    const uint64_t D = kin[u];
-                    const bool is_ref = D == d.d0;
+                    const det_t D = kin[u];
+                    const bool is_ref = D == ref_of(d);
                     const int64_t pd = pdv[u];
                     // (walkers spawned onto the reference arrive in their own sum)
                     long long sp = spv[u];
@@ -1824,8 +2064,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 int calls = 0;
                 uint32_t nearn = 0u;   // fast path: bit 0, this lane's new determinant
                                        // contributes to the projected energy
-                auto place = [&](uint64_t D, long long sp, bool init) {   // (all lanes; D = 0: none)
-                    const bool real = D != 0ull && sp != 0;
+                auto place = [&](det_t D, long long sp, bool init) {   // (all lanes; D = 0: none)
+                    const bool real = D != det_t(0ull) && sp != 0;
                     if (real) cnt += 1ull << CNT_SHIFT_MERGED;
                     if (real && !init) aborted += sp < 0 ? -sp : sp;
                     const bool nd = real && init;
@@ -1841,9 +2081,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     const int pos = k < H ? (int)W.free_[k] : n + (k - H);
                     if (pos < BQ) {
                         nwb += (unsigned long long)an;
-                        *gp(d.key + base + pos) = D;
+                        stk(keys_of(d) + base + pos, D);
                         *gp(d.pop + base + pos) = (int32_t)sp;
-                        const int q = s_qsys == s ? atomicAdd(&s_qn, 1) : POST_QUEUE;
+                        // (two-word determinants: no LDS pair table; H_DD computed here)
+                        const int q = (FQ_DET_WORDS == 1 && s_qsys == s) ? atomicAdd(&s_qn, 1)
+                                                                         : POST_QUEUE;
                         if (q < POST_QUEUE) {
                             s_queue[q] = (uint32_t)(base + pos);
                         } else {   // (another system's window, or many new determinants)
@@ -1853,7 +2095,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         // the bucket is full: completed in the spill list, re-bucketed by the host
                         const unsigned long long j = atomicAdd(a.sp_count, 1ull);
                         if (j < (unsigned long long)a.sp_cap) {
-                            a.sp_det[j] = D;
+                            spill_dets(a)[j] = D;
                             a.sp_pop[j] = (int32_t)sp;
                             a.sp_hd[j] = fn_diag(d, D);
                             a.sp_sys[j] = s;
@@ -1872,16 +2114,17 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     if (rsp > 2147483647ll || rsp < -2147483647ll) {
                         atomicOr(status, ST_POP_OVERFLOW);
                         rsp = 0ll;
-                        place(0ull, 0ll, false);
+                        place(det_t(0ull), 0ll, false);
                     } else {
-                        place(cand ? rd : 0ull, rsp, (f & F_INIT) != 0u);
+                        place(cand ? rd : det_t(0ull), rsp, (f & F_INIT) != 0u);
                     }
                 } else {
                     for (int i0 = 0; i0 < kc; i0 += 64) {
                         const int i = i0 + lane;
                         const bool in = i < kc;
-                        place(in ? a.recs[r0 + i].det : 0ull, in ? (long long)a.recs[r0 + i].w : 0ll,
-                              in && (a.recs[r0 + i].tag & F_INIT));
+                        const rec_t *const st = recs_of(a);
+                        place(in ? st[r0 + i].det : det_t(0ull), in ? (long long)st[r0 + i].w : 0ll,
+                              in && (st[r0 + i].tag & F_INIT));
                     }
                 }
                 // Re-pack: n' = (kept entries) + (new determinants); when fewer new
@@ -1898,7 +2141,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         const uint64_t m = __ballot(mv);
                         if (mv) {
                             const int64_t dst = base + W.free_[r + __popcll(m & lanes_below(lane))];
-                            *gp(d.key + dst) = kin[u];
+                            stk(keys_of(d) + dst, kin[u]);
                             *gp(d.pop + dst) = npv[u];
                             *gp(d.hdiag + dst) = hin[u];
                             movedm |= 1u << u;
@@ -1924,9 +2167,10 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                     if (nearn & 1u) num = num + ref_hel(d, rd) * (double)rsp;
                 } else {
                     for (int i = lane; i < kc; i += 64) {
-                        const uint64_t D = a.recs[r0 + i].det;
-                        const int32_t sp = a.recs[r0 + i].w;
-                        if (sp != 0 && (a.recs[r0 + i].tag & F_INIT) && near_ref(d, D))
+                        const rec_t *const st = recs_of(a);
+                        const det_t D = st[r0 + i].det;
+                        const int32_t sp = st[r0 + i].w;
+                        if (sp != 0 && (st[r0 + i].tag & F_INIT) && near_ref(d, D))
                             num = num + ref_hel(d, D) * (double)sp;
                     }
                 }
@@ -2110,36 +2354,36 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool f
 // Loading a walker list, re-bucketing into more (or fewer) buckets, exporting.
 // ---------------------------------------------------------------------------
 // Append determinant D (population p, diagonal element hd) to its bucket.
-__device__ __forceinline__ bool bucket_put(const SysDesc &d, uint64_t D, int32_t p, double hd) {
+__device__ __forceinline__ bool bucket_put(const SysDesc &d, det_t D, int32_t p, double hd) {
     const uint32_t b = bucket_of(D, (uint64_t)d.nbuckets);
     const int pos = atomicAdd(&d.bcnt[b], 1);
     if (pos >= BQ) return false;
     const int64_t j = (int64_t)b * BQ + pos;
-    d.key[j] = D;
+    keys_of(d)[j] = D;
     d.pop[j] = p;
     d.hdiag[j] = hd;
     return true;
 }
 
-__global__ void k_load(SysDesc *desc, int32_t sys, const uint64_t *det, const int32_t *pop,
+__global__ void k_load(SysDesc *desc, int32_t sys, const det_t *det, const int32_t *pop,
                        int64_t n, uint32_t *err) {
     const SysDesc &d = desc[sys];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t D = det[i];
+        const det_t D = det[i];
         if (!bucket_put(d, D, pop[i], fn_diag(d, D))) atomicOr(err, 1u);
     }
 }
 
-__global__ void k_rebucket(SysDesc *desc, int32_t sys, const uint64_t *skey, const int32_t *spop,
+__global__ void k_rebucket(SysDesc *desc, int32_t sys, const det_t *skey, const int32_t *spop,
                            const double *shd, const int32_t *scnt, int64_t snb,
-                           const uint64_t *xdet, const int32_t *xpop, const double *xhd,
+                           const det_t *xdet, const int32_t *xpop, const double *xhd,
                            const int32_t *xsys, int64_t nx, uint32_t *err) {
     const SysDesc &d = desc[sys];
     const int64_t ns = snb * BQ;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ns + nx;
          i += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t D;
+        det_t D;
         int32_t p;
         double hd;
         if (i < ns) {
@@ -2154,15 +2398,15 @@ __global__ void k_rebucket(SysDesc *desc, int32_t sys, const uint64_t *skey, con
             p = xpop[k];
             hd = xhd[k];
         }
-        if (p == 0 && D != d.d0) continue;
+        if (p == 0 && D != ref_of(d)) continue;
         if (!bucket_put(d, D, p, hd)) atomicOr(err, 1u);
     }
 }
 
 // Occupied entries (population != 0) of nb buckets, in any order, into odet/opop
 // (at most `limit` written; *count gets the total). One counter atomic per wavefront.
-__global__ __launch_bounds__(256) void k_compact(const uint64_t *kv, const int32_t *pop,
-                                                 const int32_t *cnt, int64_t nb, uint64_t *odet,
+__global__ __launch_bounds__(256) void k_compact(const det_t *kv, const int32_t *pop,
+                                                 const int32_t *cnt, int64_t nb, det_t *odet,
                                                  int32_t *opop, unsigned long long *count,
                                                  int64_t limit) {
     const int lane = threadIdx.x & 63;
@@ -2171,7 +2415,7 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *kv, const int32
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = base + threadIdx.x;
         bool take = false;
-        uint64_t D = 0;
+        det_t D = det_t(0ull);
         int32_t p = 0;
         if (i < ns && (int)(i % BQ) < cnt[i / BQ]) {
             D = kv[i];
@@ -2199,7 +2443,7 @@ hipError_t launch_load(SysDesc *d_desc, int32_t sys, const uint64_t *det, const 
     if (n <= 0) return hipSuccess;
     const int64_t g = (n + 255) / 256;
     hipLaunchKernelGGL(k_load, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, d_desc,
-                       sys, det, pop, n, d_err);
+                       sys, (const det_t *)det, pop, n, d_err);
     return hipGetLastError();
 }
 
@@ -2211,8 +2455,8 @@ hipError_t launch_rebucket(SysDesc *d_desc, int32_t sys, const uint64_t *src_key
     const int64_t g = (src_nb * BQ + n_sp + 255) / 256;
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rebucket, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
-                       d_desc, sys, src_key, src_pop, src_hd, src_cnt, src_nb, sp_det, sp_pop,
-                       sp_hd, sp_sys, n_sp, d_err);
+                       d_desc, sys, (const det_t *)src_key, src_pop, src_hd, src_cnt, src_nb,
+                       (const det_t *)sp_det, sp_pop, sp_hd, sp_sys, n_sp, d_err);
     return hipGetLastError();
 }
 
@@ -2220,11 +2464,12 @@ hipError_t launch_compact(const uint64_t *key, const int32_t *pop, const int32_t
                           uint64_t *out_det, int32_t *out_pop, unsigned long long *count,
                           hipStream_t s) {
     const int64_t g = (nb * BQ + 255) / 256;
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s, key,
-                       pop, cnt, nb, out_det, out_pop, count, nb * BQ);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)(g < 65536 ? g : 65536)), dim3(256), 0, s,
+                       (const det_t *)key, pop, cnt, nb, (det_t *)out_det, out_pop, count, nb * BQ);
     return hipGetLastError();
 }
 
+#if FQ_DET_WORDS == 1
 // ---------------------------------------------------------------------------
 // Export through a fixed staging area (no allocation): the counter is cleared by
 // a kernel (no memset node), the occupied slots are compacted with one counter
@@ -2306,14 +2551,19 @@ hipError_t launch_stage_sort(void *stage, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *out = fn_diag(desc[sys], det);
+#endif   // the staging export (one-word determinants only)
+
+__global__ void k_e0(const SysDesc *desc, int32_t sys, uint64_t lo, uint64_t hi, double *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = fn_diag(desc[sys], make_det(lo, hi));
 }
 
-hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t det, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_e0, dim3(1), dim3(64), 0, s, desc, sys, det, out);
+hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t lo, uint64_t hi, double *out,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_e0, dim3(1), dim3(64), 0, s, desc, sys, lo, hi, out);
     return hipGetLastError();
 }
+
+#if FQ_DET_WORDS == 1
 
 int post_grid_size() { return spawn_grid_size() / 8 * 4; }   // four workgroups per CU
 
@@ -2326,5 +2576,9 @@ int spawn_grid_size() {
     }
     return cus * 8;
 }
+#endif
 
+#if FQ_DET_WORDS == 2
+}  // namespace w2
+#endif
 }  // namespace fq

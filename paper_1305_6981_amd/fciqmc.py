@@ -40,7 +40,9 @@ class Params(C.Structure):
                 ("avg_start", C.c_int32), ("space", C.c_int32),
                 ("max_excitation", C.c_int32), ("max_seniority", C.c_int32),
                 ("frozen_occupied", C.c_uint64), ("frozen_empty", C.c_uint64),
-                ("hphf", C.c_int32), ("reserved1", C.c_int32)]
+                ("hphf", C.c_int32), ("reserved1", C.c_int32),
+                ("frozen_occupied_hi", C.c_uint64), ("frozen_empty_hi", C.c_uint64),
+                ("det_words", C.c_int32), ("reserved2", C.c_int32)]
 
 
 _EST_INT = ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns", "merged",
@@ -74,7 +76,8 @@ EXPORTED = ["fciqmc_init", "fciqmc_iterate", "fciqmc_estimators", "fciqmc_free",
             "fciqmc_batch_slot_walkers", "fciqmc_footprint_bytes", "fciqmc_batch_active",
             "fciqmc_set_profiling", "fciqmc_kernel_times", "fciqmc_set_launch",
             "fciqmc_get_launch", "fciqmc_autotune", "fciqmc_blocking",
-            "fciqmc_set_test_options", "fciqmc_walkers_noalloc", "fciqmc_history"]
+            "fciqmc_set_test_options", "fciqmc_walkers_noalloc", "fciqmc_history",
+            "fciqmc_det_words"]
 
 
 def lib():
@@ -115,6 +118,7 @@ def lib():
             "fciqmc_set_test_options": ([vp, i32, i64, i64], C.c_int),
             "fciqmc_walkers_noalloc": ([vp, vp, vp, vp, i64], i64),
             "fciqmc_history": ([vp, i32, i64, i64, C.POINTER(Iteration)], i64),
+            "fciqmc_det_words": ([vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -139,7 +143,7 @@ def marshal_hamiltonian(ham):
     k.h1 = np.ascontiguousarray(ham.h1, dtype=np.float64)
     k.eri = np.ascontiguousarray(ham.eri, dtype=np.float64)
     k.irr = None if ham.orb_irrep is None else np.ascontiguousarray(ham.orb_irrep, dtype=np.uint8)
-    k.ref = None if ham.ref_det is None else np.array([ham.ref_det], dtype=np.uint64)
+    k.ref = None if ham.ref_det is None else det_words_of(ham.ref_det)
     h = Hamiltonian(ham.n_orb, ham.n_alpha, ham.n_beta, 0, ham.e_core,
                     k.h1.ctypes.data_as(C.POINTER(C.c_double)),
                     k.eri.ctypes.data_as(C.POINTER(C.c_double)),
@@ -149,11 +153,33 @@ def marshal_hamiltonian(ham):
     return h, k
 
 
+MASK64 = (1 << 64) - 1
+
+
+def det_words_of(det: int) -> np.ndarray:
+    """A determinant (Python int, up to 128 bits) as two 64-bit words, low first."""
+    return np.array([int(det) & MASK64, int(det) >> 64], dtype=np.uint64)
+
+
+def det_array(dets, w: int) -> np.ndarray:
+    """Determinants as the ABI's array of w words each: shape (n,) for one word,
+    (n, 2) for two (columns low, high); accepts ints or an array in either shape."""
+    a = np.asarray(dets)
+    if w == 1:
+        return np.ascontiguousarray(a, dtype=np.uint64).reshape(-1)
+    if a.ndim == 2:
+        return np.ascontiguousarray(a, dtype=np.uint64)
+    return np.array([[int(d) & MASK64, int(d) >> 64] for d in a.reshape(-1)],
+                    dtype=np.uint64).reshape(-1, 2)
+
+
 def marshal_params(p):
+    fo, fe = int(p.frozen_occupied), int(p.frozen_empty)
     return Params(p.tau, p.shift_damping, p.initial_shift, p.shift_update_every,
                   p.initiator_threshold, p.target_walkers, p.initial_walkers, p.det_capacity,
                   p.spawn_capacity, p.seed, p.avg_start, p.space, p.max_excitation,
-                  p.max_seniority, p.frozen_occupied, p.frozen_empty, p.hphf, 0)
+                  p.max_seniority, fo & MASK64, fe & MASK64, p.hphf, 0, fo >> 64, fe >> 64,
+                  getattr(p, "det_words", 0), 0)
 
 
 def current_stream():
@@ -200,18 +226,25 @@ def fciqmc_free(handle):
         lib().fciqmc_free(handle)
 
 
-def _walkers(fn, *lead):
+def fciqmc_det_words(handle):
+    return _check(lib().fciqmc_det_words(handle))
+
+
+def _walkers(fn, w, *lead):
     n = _check(fn(*lead, None, None, None, 0))
-    det = np.zeros(max(n, 1), np.uint64)
+    det = np.zeros(max(n, 1) * w, np.uint64)
     pop = np.zeros(max(n, 1), np.int32)
     flg = np.zeros(max(n, 1), np.uint32)
     m = _check(fn(*lead, _ptr(det), _ptr(pop), _ptr(flg), n))
     assert m == n
-    return det[:n], pop[:n], flg[:n]
+    det = det[:n * w]
+    return (det if w == 1 else det.reshape(-1, 2)), pop[:n], flg[:n]
 
 
 def fciqmc_walkers(handle):
-    return _walkers(lib().fciqmc_walkers, handle)
+    """(det, pop, flags): det of shape (n,) with one word per determinant, (n, 2)
+    with two (low, high)."""
+    return _walkers(lib().fciqmc_walkers, fciqmc_det_words(handle), handle)
 
 
 def fciqmc_walkers_noalloc(handle, det, pop, flags):
@@ -226,9 +259,9 @@ def fciqmc_walkers_noalloc(handle, det, pop, flags):
 
 
 def fciqmc_load_walkers(handle, det, pop, iteration=0, shift=0.0, n_prev=0, varying=0, n_var=0):
-    det = np.ascontiguousarray(det, dtype=np.uint64)
+    det = det_array(det, fciqmc_det_words(handle))
     pop = np.ascontiguousarray(pop, dtype=np.int32)
-    _check(lib().fciqmc_load_walkers(handle, _ptr(det), _ptr(pop), len(det), iteration, shift,
+    _check(lib().fciqmc_load_walkers(handle, _ptr(det), _ptr(pop), len(pop), iteration, shift,
                                      n_prev, varying, n_var))
 
 
@@ -287,7 +320,8 @@ def fciqmc_batch_slot_estimators(handle, slot):
 
 
 def fciqmc_batch_slot_walkers(handle, slot):
-    return _walkers(lib().fciqmc_batch_slot_walkers, handle, C.c_int32(slot))
+    return _walkers(lib().fciqmc_batch_slot_walkers, fciqmc_det_words(handle), handle,
+                    C.c_int32(slot))
 
 
 def fciqmc_footprint_bytes(ham, params):
