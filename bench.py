@@ -349,8 +349,8 @@ def served(F, S, n_requests, scale, max_iters, plain_every, seed=5):
 
 def variant(F, S, name, walkers, warmup, steps, **mods):
     """The 24e/30o system at the benchmark's walker target in another sampling mode
-    (spin-coupled functions, a restricted space): grown and warmed up like the
-    headline run, then `steps` iterations timed on the graph path."""
+    (spin-coupled functions, a restricted space, two-word determinants): grown and
+    warmed up like the headline run, then `steps` iterations timed on the graph path."""
     ham, prm, _ = S.workload("synth24e30o")
     prm.target_walkers = int(walkers)
     prm.initial_walkers = 20000
@@ -743,6 +743,10 @@ def main():
                                            hphf=1),
             "cisdtq": variant(F, S, "excitation level <= 4", args.walkers, 150, 50,
                               space=S.SPACE_EXCITATION, max_excitation=4),
+            # the two-word kernels (determinants of 65-128 spin orbitals) on the same
+            # system and trajectory: the cost of the second word
+            "two_word_determinants": variant(F, S, "two-word determinants", args.walkers, 150,
+                                             50, det_words=2),
         }
     if not args.no_batched:
         log("[bench] batched vs plain (64 systems)")

@@ -32,8 +32,9 @@
  *     except the rounding order of the projected-energy numerator sum.
  *
  * Readings where the paper is silent:
- *   RNG = Philox4x32-10 (Salmon et al., SC'11) keyed by the seed, with a
- *   counter built from (determinant, walker ordinal, iteration, block); a
+ *   RNG = Philox4x32-10 (Salmon et al., SC'11) keyed by the seed (XOR the
+ *   determinant's second word beyond 64 spin orbitals), with a counter built
+ *   from (determinant, walker ordinal, iteration, block); a
  *   spawning attempt uses one block: word 0 picks the type and, rescaled
  *   within the chosen type's probability interval, is the acceptance uniform;
  *   words 1-3 pick the orbitals (index = floor(w n / 2^32));

@@ -1038,7 +1038,7 @@ struct SingleItem {
 };
 
 constexpr int SPAWN_GRAB = 4;    // spawn tiles per dynamic grab (one counter serves the chip)
-constexpr int SGL_QUEUE = 128;
+constexpr int SGL_QUEUE = 128 / FQ_DET_WORDS;   // (two words: the spawn kernel's LDS in 40 KB)
 constexpr int SPW_QUEUE = 256;
 constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
 constexpr int SPW_DRAIN = 192;     // (a tile adds about 30 spawns; a fuller queue is merged inline)
@@ -1168,8 +1168,9 @@ __device__ __forceinline__ int64_t last_le(const unsigned long long *v, int64_t 
     return lo + __popcll(__ballot(le)) - 1;
 }
 
-// At most 96 VGPRs: five wavefronts per SIMD (the LDS use allows five workgroups per CU).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 5)))
+// At most 96 VGPRs: five wavefronts per SIMD (the LDS use allows five workgroups per CU);
+// four with two-word determinants (more registers and LDS per attempt).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6 - FQ_DET_WORDS, 6 - FQ_DET_WORDS)))
 void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long s_incl[CHUNK];
     __shared__ det_t s_det[CHUNK];
@@ -1705,9 +1706,35 @@ __device__ __forceinline__ void hdiag_lds2(double e_core, det_t da, det_t db,
     rb = xb;
 }
 
+#if FQ_DET_WORDS == 2
+// As hdiag_lds2, with the pair table read from global memory ([n_so][NSO_MAX],
+// entry (p, q) at p NSO_MAX + q): for more than 64 spin orbitals, whose upper
+// triangle would take 65 KB of LDS.
+__device__ __forceinline__ void hdiag_glb2(double e_core, det_t da, det_t db, const double *hpp,
+                                           const double *jk, double &ra, double &rb) {
+    double xa = e_core, xb = e_core;
+    for (det_t ma = da, mb = db; ma; ma &= ma - 1ull, mb &= mb - 1ull) {
+        xa = xa + hpp[dctz(ma)];
+        xb = xb + hpp[dctz(mb)];
+    }
+    const gdouble *t = gptr(jk);
+    for (det_t m1a = da, m1b = db; m1a; m1a &= m1a - 1ull, m1b &= m1b - 1ull) {
+        const gdouble *ra_ = t + dctz(m1a) * NSO_MAX, *rb_ = t + dctz(m1b) * NSO_MAX;
+        for (det_t m2a = m1a & (m1a - 1ull), m2b = m1b & (m1b - 1ull); m2a;
+             m2a &= m2a - 1ull, m2b &= m2b - 1ull) {
+            xa = xa + ra_[dctz(m2a)];
+            xb = xb + rb_[dctz(m2b)];
+        }
+    }
+    ra = xa;
+    rb = xb;
+}
+#endif
+
 // Diagonal elements of the queued new determinants (positions in the system's
 // arrays, all of one system, so all with the same electron count), two per
-// thread at a time.
+// thread at a time; the pair table from LDS (jk), or from global memory when jk is
+// null (two-word determinants of more than 64 spin orbitals).
 __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t *queue, int n,
                                                const double *hpp, const double *jk) {
     const int step = 2 * (int)blockDim.x;
@@ -1717,7 +1744,14 @@ __device__ __forceinline__ void flush_new_dets(const SysDesc &d, const uint32_t 
         const uint32_t i1 = two ? queue[j + blockDim.x] : i0;
         double h0, h1;
         const det_t k0 = ldk(keys_of(d) + i0), k1 = ldk(keys_of(d) + i1);
+#if FQ_DET_WORDS == 1
         hdiag_lds2(d.e_core, k0, k1, hpp, jk, d.n_so, h0, h1);
+#else
+        if (jk)
+            hdiag_lds2(d.e_core, k0, k1, hpp, jk, d.n_so, h0, h1);
+        else
+            hdiag_glb2(d.e_core, k0, k1, hpp, d.jk, h0, h1);
+#endif
         *gp(d.hdiag + i0) = fn_diag_from(d, k0, h0);
         if (two) *gp(d.hdiag + i1) = fn_diag_from(d, k1, h1);
     }
@@ -1737,8 +1771,8 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     union PostLds {
         WaveLds w[POST_WAVES];
         struct {
-            double jk[64 * 63 / 2];
-            double hpp[64];
+            double jk[64 * 63 / 2];   // (up to 64 spin orbitals)
+            double hpp[NSO_MAX];
         } tab;
     };
     __shared__ PostLds L;
@@ -1772,13 +1806,17 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     }
     auto flush = [&]() {   // (uniform) H_DD of the queued new determinants
         const SysDesc &dq = desc[s_qsys];
-        for (int i = t; i < dq.n_so * 64; i += 256) {
-            const int p = i >> 6, q = i & 63;
-            if (q > p && q < dq.n_so) L.tab.jk[pair_row(p, dq.n_so) + q] = gptr(dq.jk)[i];
-        }
+        const bool in_lds = dq.n_so <= 64;   // the pair table's upper triangle fits in LDS
+        if (in_lds)
+            for (int i = t; i < dq.n_so * 64; i += 256) {
+                const int p = i >> 6, q = i & 63;
+                if (q > p && q < dq.n_so)
+                    L.tab.jk[pair_row(p, dq.n_so) + q] = gptr(dq.jk)[p * NSO_MAX + q];
+            }
         for (int i = t; i < dq.n_so; i += 256) L.tab.hpp[i] = h_so(dq, i, i);
         __syncthreads();
-        flush_new_dets(dq, s_queue, s_qn < POST_QUEUE ? s_qn : POST_QUEUE, L.tab.hpp, L.tab.jk);
+        flush_new_dets(dq, s_queue, s_qn < POST_QUEUE ? s_qn : POST_QUEUE, L.tab.hpp,
+                       in_lds ? L.tab.jk : nullptr);
         __syncthreads();
     };
     // Each workgroup takes a contiguous range of chunks, in windows of POST_WIN; inside
@@ -2083,9 +2121,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                         nwb += (unsigned long long)an;
                         stk(keys_of(d) + base + pos, D);
                         *gp(d.pop + base + pos) = (int32_t)sp;
-                        // (two-word determinants: no LDS pair table; H_DD computed here)
-                        const int q = (FQ_DET_WORDS == 1 && s_qsys == s) ? atomicAdd(&s_qn, 1)
-                                                                         : POST_QUEUE;
+                        const int q = s_qsys == s ? atomicAdd(&s_qn, 1) : POST_QUEUE;
                         if (q < POST_QUEUE) {
                             s_queue[q] = (uint32_t)(base + pos);
                         } else {   // (another system's window, or many new determinants)
