@@ -591,6 +591,9 @@ def main():
                     help="run every n-th served request alone for comparison")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the spin-coupled and restricted-space runs of the workload")
+    ap.add_argument("--det-words", type=int, default=0,
+                    help="64-bit words per determinant for the headline run: 0 as needed (one "
+                         "for this system), 2 to time the two-word kernels on it")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="add a 1 GiB elementwise multiply in its own profiled region")
     args = ap.parse_args()
@@ -616,6 +619,7 @@ def main():
     prm.initial_walkers = args.initial_walkers
     prm.initial_shift = args.growth_shift
     prm.shift_damping = args.shift_damping
+    prm.det_words = args.det_words
     log(f"[bench] growth stage to {target} walkers at shift +{args.growth_shift}")
     t_g = time.perf_counter()
     sv = F.Solver(ham, prm, F.current_stream())
@@ -706,6 +710,9 @@ def main():
                     "frac_of_measured_copy": ach / copy_gbs,
                     "k_post_issued_lane_ops_per_det": issued_ops_per("k_post", "det")}
 
+    if F.fciqmc_det_words(sv.h) != 1:   # the committed counters describe the one-word kernels
+        roofline.update(traffic=None, issued_lane_ops_per_attempt=None, issue_frac=None)
+        roofline_ann.update(traffic=None, k_post_issued_lane_ops_per_det=None)
     mean = lambda k: float(np.mean([r[k] for r in win]))  # noqa: E731
     out = {
         "metric": "spawn attempts/s + annihilated dets/s at 1e8 walkers; batched vs plain",
@@ -723,7 +730,8 @@ def main():
                    "dets_mean": mean("n_dets"), "spawns_per_iteration": mean("spawns"),
                    "merged_per_iteration": mean("merged"), "born_per_iteration": mean("born"),
                    "table_slots": e1["table_slots"], "rebucketed_in_window": rebucketed,
-                   "path": "graph launches (production path)", "parallelism": "1 GPU"},
+                   "path": "graph launches (production path)", "parallelism": "1 GPU",
+                   "det_words": F.fciqmc_det_words(sv.h)},
         "profiling_window": {"iterations": args.profile_steps, "ms_per_step": prof_ms,
                              "group_ms": grp_ms},
         "roofline": roofline,

@@ -169,6 +169,8 @@ def det_array(dets, w: int) -> np.ndarray:
         return np.ascontiguousarray(a, dtype=np.uint64).reshape(-1)
     if a.ndim == 2:
         return np.ascontiguousarray(a, dtype=np.uint64)
+    if a.dtype == np.uint64:     # one-word values: a zero high word
+        return np.ascontiguousarray(np.stack([a.reshape(-1), np.zeros(a.size, np.uint64)], axis=1))
     return np.array([[int(d) & MASK64, int(d) >> 64] for d in a.reshape(-1)],
                     dtype=np.uint64).reshape(-1, 2)
 

@@ -11,7 +11,9 @@ three iterations with the determinants spread over one virtual process per host
 thread (Sec. 4.1; the result does not depend on the process count, see
 test_oracle_processes.py). Walker lists must be bit-identical, the integer
 statistics and the shift identical, and the projected-energy numerator equal
-to 1e-10 relative."""
+to 1e-10 relative. For config 3 the same snapshot also runs through the
+two-word kernels (determinants of more than 64 spin orbitals, forced here),
+which must give the one-word run's lists and statistics exactly."""
 import os
 import time
 
@@ -36,9 +38,19 @@ def _grow(sv, target, limit):
         assert e["iteration"] < limit, "growth stage did not reach the walker target"
 
 
-def _compare_k_iterations(ham, prm, sv, tag):
+def _compare_k_iterations(ham, prm, sv, tag, two_words=False):
     e = sv.estimates()
     det, pop, _ = sv.walkers()
+    sv2 = None
+    if two_words:
+        import copy
+        p2 = copy.copy(prm)
+        p2.det_words = 2
+        sv2 = F.Solver(ham, p2, F.current_stream())
+        sv2.reserve(e["table_slots"])
+        sv2.load_walkers(det, pop, iteration=e["iteration"], shift=e["shift"],
+                         n_prev=e["n_prev"], varying=e["shift_varying"], n_var=e["n_var"])
+        print(f"[gpu] {tag}: snapshot loaded into the two-word kernels", flush=True)
     print(f"[gpu] {tag}: snapshot of {e['n_walkers']} walkers on {len(det)} determinants at "
           f"iteration {e['iteration']}", flush=True)
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -72,6 +84,18 @@ def _compare_k_iterations(ham, prm, sv, tag):
     assert np.array_equal(fg, fo)
     print(f"[gpu] {tag}: {len(dg)} determinants identical after {K} iterations", flush=True)
     ref.close()
+    if sv2 is not None:
+        sv2.iterate(K)
+        h2 = F.fciqmc_history(sv2.h, 0, e["iteration"] + 1, K)
+        for k in range(K):
+            for f in ("iteration", "n_walkers", "n_dets", "ref_pop", "attempts", "spawns",
+                      "merged", "aborted", "born", "shift"):
+                assert h2[k][f] == hist[k][f], (tag, "two words", k, f)
+        d2, p2_, f2 = sv2.walkers()
+        assert d2.shape == (len(dg), 2) and np.array_equal(d2[:, 0], dg) and not d2[:, 1].any()
+        assert np.array_equal(p2_, pg) and np.array_equal(f2, fg)
+        print(f"[gpu] {tag}: two-word kernels identical after {K} iterations", flush=True)
+        sv2.close()
 
 
 def test_full_size_config3_matches_oracle():
@@ -90,7 +114,7 @@ def test_full_size_config3_matches_oracle():
     sv.iterate(300)
     print(f"[gpu] config 3 grown and warmed up in {time.perf_counter() - t0:.1f} s", flush=True)
     assert sv.estimates()["n_walkers"] >= target
-    _compare_k_iterations(ham, prm, sv, "config 3")
+    _compare_k_iterations(ham, prm, sv, "config 3", two_words=True)
     sv.close()
 
 
