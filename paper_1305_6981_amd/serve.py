@@ -135,7 +135,17 @@ class SolveServer:
                     except F.FciqmcError as e:
                         if e.code == -2 and active:      # ENOMEM: wait for a retirement
                             break
-                        raise
+                        if e.code != -1:
+                            raise
+                        # EINVAL: a request this batch cannot hold (bad parameters, or
+                        # determinants of another width than the batch's one word)
+                        pending.pop(0)
+                        stats.results.append(Result(req.tag, req.arrival, now, now, 0, float("nan"),
+                                                    float("nan"), float("nan"), 0, False, True, {},
+                                                    None))
+                        if self.on_result is not None:
+                            self.on_result(stats.results[-1])
+                        continue
                     pending.pop(0)
                     active[slot] = [req, now, 0, {}]
                 stats.peak_active = max(stats.peak_active, len(active))

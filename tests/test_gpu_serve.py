@@ -52,3 +52,20 @@ def test_served_results_equal_solo_runs():
     assert late
     summ = stats.summary()
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
+
+
+def test_request_the_batch_cannot_hold_fails_alone():
+    """A request of another determinant width (72 spin orbitals: two words) than the
+    server's one-word batch is recorded as failed; the others are served."""
+    reqs = _requests()[:2]
+    big = S.synthetic_molecule(36, 2, 2, 7, orb_energy=np.linspace(-4.0, 4.0, 36))
+    reqs.insert(1, serve.Request(big, S.Params(tau=0.01, seed=9), arrival=0.0, max_iters=20,
+                                 tag="two-word"))
+    print(f"[gpu] serving {len(reqs)} requests, one of two-word determinants", flush=True)
+    stats = serve.SolveServer(max_slots=3, chunk_iters=16, tol=0.0).run(reqs)
+    by_tag = {r.tag: r for r in stats.results}
+    assert len(by_tag) == 3
+    assert by_tag["two-word"].failed and by_tag["two-word"].iterations == 0
+    for req in reqs:
+        if req.tag != "two-word":
+            assert not by_tag[req.tag].failed and by_tag[req.tag].iterations == req.max_iters
