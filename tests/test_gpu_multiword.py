@@ -61,6 +61,15 @@ def test_hubbard_ring_of_40_sites():
     _pair(ham, prm, 3, 40, "hubbard40")
 
 
+def test_largest_width_128_spin_orbitals():
+    # 64 spatial orbitals, the reference in the four highest spin orbitals (124..127)
+    ham = S.synthetic_molecule(64, 2, 2, 67, orb_energy=np.linspace(3.0, -3.0, 64))
+    assert int(ham.ref_det) == (15 << 124)
+    prm = S.Params(tau=0.01, shift_damping=0.5, shift_update_every=5, target_walkers=4000,
+                   initial_walkers=400, seed=38, initiator_threshold=1)
+    _pair(ham, prm, 3, 40, "mol64")
+
+
 def test_point_group_labels_beyond_orbital_32():
     irr = np.array([(i * 5) % 4 for i in range(40)], np.uint8)
     ham = S.synthetic_molecule(40, 3, 3, 63, irreps=irr, orb_energy=np.linspace(-4.0, 4.0, 40))

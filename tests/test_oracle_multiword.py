@@ -237,3 +237,28 @@ def test_walker_list_round_trip_with_two_words():
     assert got == {d0: 7, dets[1]: -3, dets[2]: 2}
     assert O.det_ints(det) == sorted(got)
     o.close()
+
+
+def test_largest_width_128_spin_orbitals():
+    """64 spatial orbitals, electrons up to spin orbital 127: elements against the
+    operator action and pgen against the enumeration."""
+    ham = S.synthetic_molecule(64, 2, 2, 67, orb_energy=np.linspace(3.0, -3.0, 64))
+    assert int(ham.ref_det) == (15 << 124)          # the four highest spin orbitals
+    g = _unpack(ham)
+    o = O.Oracle(ham, S.Params(tau=0.01, seed=12))
+    assert o.W == 2
+    kets = [int(ham.ref_det), _det([0, 63], [31, 32]), _det([1, 62], [63, 0])]
+    for ket in kets:
+        col = apply_h(ham, g, ket)
+        for bra, ref in col.items():
+            got = o.hel(bra, ket)
+            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (ket, bra, got, ref)
+    p_double = o.estimates()["p_double"]
+    for det in kets[:2]:
+        probs, p_null = enumerate_generation(ham, det, p_double)
+        assert abs(sum(probs.values()) + p_null - 1.0) < 1e-12
+        out, pgen, _ = o.sample_excitations(det, 20000, iteration=2)
+        for d, pg in zip(out, pgen):
+            if d:
+                assert abs(pg - probs[d]) <= 1e-14 * probs[d]
+    o.close()
