@@ -170,6 +170,10 @@ struct EngineArgs {
     unsigned long long *sp_count;
     int64_t sp_cap;
     uint32_t *spilled;               // [max_sys] set by k_post when a bucket spilled
+    // Every system of the launch draws plain determinants with no point group and no
+    // restricted space: the spawning kernel is then launched in its variant that
+    // leaves those cases out.
+    int32_t plain;
 };
 
 // Staging area of the export that allocates nothing (fciqmc_walkers_noalloc): a

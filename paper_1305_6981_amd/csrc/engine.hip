@@ -271,7 +271,7 @@ struct fciqmc_t {
     int spawn_grid = 2048;
     int post_grid = 1024;
     int tile = 2048;
-    std::map<int, hipGraphExec_t> graphs;
+    std::map<int, hipGraphExec_t> graphs;   // by 2 L + plain (L iterations, kernel variant)
     bool use_graph = true;
     bool profiling = false;
     hipEvent_t ev[NKERN + 1] = {};
@@ -336,6 +336,11 @@ EngineArgs make_args(fciqmc_t *h) {
     a.sp_count = h->d_sp_count;
     a.sp_cap = h->sp_cap;
     a.spilled = h->d_spilled;
+    a.plain = 1;
+    for (int s = 0; s < h->max_sys; ++s) {
+        const SysDesc &d = h->hdesc[s];
+        if (h->sys[s].active && (d.n_class != 2 || d.hphf || d.space)) a.plain = 0;
+    }
     return a;
 }
 
@@ -1042,12 +1047,14 @@ int refresh_stats_after_load(fciqmc_t *h, int s, const std::vector<hdet_t> &det,
 int run_iterations(fciqmc_t *h, int L, bool sample);
 
 int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
-    auto it = h->graphs.find(L);
+    // a graph holds the spawning kernel's variant: one graph per length and variant
+    EngineArgs a = make_args(h);
+    const int key = 2 * L + a.plain;
+    auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         *out = it->second;
         return 0;
     }
-    EngineArgs a = make_args(h);
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeRelaxed));
     for (int i = 0; i < L; ++i)
@@ -1056,7 +1063,7 @@ int capture_or_get(fciqmc_t *h, int L, hipGraphExec_t *out) {
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
     HIP_TRY(hipGraphDestroy(g));
-    h->graphs[L] = ex;
+    h->graphs[key] = ex;
     *out = ex;
     return 0;
 }

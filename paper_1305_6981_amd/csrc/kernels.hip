@@ -793,6 +793,31 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront by data-parallel primitives
+// (DPP): shifts within rows of 16 lanes, then row broadcasts (no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_move(unsigned long long v) {
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return (unsigned long long)(uint32_t)lo | ((unsigned long long)(uint32_t)hi << 32);
+}
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long x) {
+    const int lane = threadIdx.x & 63, r = lane & 15;
+    unsigned long long y = dpp_move<0x111>(x);   // row_shr:1
+    if (r >= 1) x += y;
+    y = dpp_move<0x112>(x);                      // row_shr:2
+    if (r >= 2) x += y;
+    y = dpp_move<0x114>(x);                      // row_shr:4
+    if (r >= 4) x += y;
+    y = dpp_move<0x118>(x);                      // row_shr:8
+    if (r >= 8) x += y;
+    y = dpp_move<0x142>(x);                      // row_bcast:15 (last lane of the row below)
+    if (lane & 16) x += y;
+    y = dpp_move<0x143>(x);                      // row_bcast:31 (lane 31, to the upper half)
+    if (lane >= 32) x += y;
+    return x;
+}
+
 // Halves of the chunk sums and range sums: this iteration's in (step & 1).
 __device__ __forceinline__ unsigned cur_half(const EngineArgs &a) { return (unsigned)(*a.step & 1ull); }
 __device__ __forceinline__ unsigned long long *sums(const EngineArgs &a, unsigned h) {
@@ -1084,7 +1109,8 @@ __device__ __forceinline__ void flush_spawn_count(unsigned long long *counter,
 
 // Drain both queues of system s with the whole workgroup (call uniformly).
 // cm_lds: the LDS copy of the system's class masks (the descriptor's own copy is
-// read instead for one-word determinants).
+// read instead for one-word determinants). PLAIN: as for k_spawn.
+template <bool PLAIN>
 __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc &d, int s,
                              const uint32_t *sel8, const double *recip, const det_t *cm_lds,
                              unsigned long long &spawned) {
@@ -1104,11 +1130,11 @@ __device__ void drain_queues(SpawnQueues &Q, const EngineArgs &a, const SysDesc 
     for (int j = t; j < nsgl; j += blockDim.x) {
         const SingleItem it = Q.sgl[j];
         Excit ex;
-        const bool ok = d.n_class == 2
+        const bool ok = PLAIN || d.n_class == 2
                             ? excite_single(d, ClassView<true>{valid_of(d), nullptr}, it.D, it.w1, it.w2, sel8, ex)
                             : excite_single(d, ClassView<false>{valid_of(d), cmk}, it.D, it.w1, it.w2, sel8, ex);
-        if (!ok || (d.space && !in_space(d, ex.det))) continue;
-        if (d.hphf) {
+        if (!ok || (!PLAIN && d.space && !in_space(d, ex.det))) continue;
+        if (!PLAIN && d.hphf) {
             if (!to_function(d, cmk, recip, it.D, ex)) continue;
         } else {
             ex.hel = hel_single(d, it.D, ex.p, ex.a);
@@ -1170,13 +1196,15 @@ __device__ __forceinline__ int64_t last_le(const unsigned long long *v, int64_t 
 
 // At most 96 VGPRs: five wavefronts per SIMD (the LDS use allows five workgroups per CU);
 // four with two-word determinants (more registers and LDS per attempt).
+// PLAIN: every system of the launch has no point group, no restricted space and plain
+// determinants (EngineArgs::plain), so those branches are compiled out.
+template <bool PLAIN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6 - FQ_DET_WORDS, 6 - FQ_DET_WORDS)))
 void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long s_incl[CHUNK];
     __shared__ det_t s_det[CHUNK];
     __shared__ int32_t s_pop[CHUNK];
-    __shared__ unsigned long long s_wsum[4];
-    __shared__ int s_wcnt[4];
+    __shared__ unsigned long long s_wsum[4];   // per wavefront: walkers | entries << 48
     __shared__ long long s_c;
     __shared__ unsigned int s_tile;
     __shared__ double s_recip[65];
@@ -1232,7 +1260,7 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             // queued work and tallies belong to another system: finish them first
             if (Q.sys >= 0) {
                 const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, s_cm, spawned);
+                if (Q.nsgl > 0 || Q.nspw > 0) drain_queues<PLAIN>(Q, a, desc[qs], qs, s_sel8, s_recip, s_cm, spawned);
                 flush_spawn_count(&a.spawns[qs], spawned);
             }
             __syncthreads();
@@ -1273,27 +1301,17 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             run += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
-        unsigned long long xw = run, xc = (unsigned long long)nocc;
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long yw = __shfl_up(xw, o, 64);
-            const unsigned long long yc = __shfl_up(xc, o, 64);
-            if (lane >= o) {
-                xw += yw;
-                xc += yc;
-            }
-        }
-        if (lane == 63) {
-            s_wsum[wid] = xw;
-            s_wcnt[wid] = (int)xc;
-        }
+        // one scan of both: a lane's walkers (< 2^33) with its entry count (<= 4) above
+        // bit 48; over the workgroup the sums stay below 2^41 and 2^10
+        const unsigned long long mine = run | ((unsigned long long)nocc << 48);
+        const unsigned long long xs = wave_incl_scan(mine);
+        if (lane == 63) s_wsum[wid] = xs;
         __syncthreads();
-        unsigned long long wbefore = xw - run;
-        int pos = (int)xc - nocc;
-        for (int w = 0; w < wid; ++w) {
-            wbefore += s_wsum[w];
-            pos += s_wcnt[w];
-        }
-        const int n_occ = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+        unsigned long long before = xs - mine;
+        for (int w = 0; w < wid; ++w) before += s_wsum[w];
+        unsigned long long wbefore = before & ((1ull << 48) - 1ull);
+        int pos = (int)(before >> 48);
+        const int n_occ = (int)((s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3]) >> 48);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (pa[u] == 0) continue;
@@ -1316,9 +1334,9 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         // no attempts for a system that has stopped this iteration (its record buffer overflowed)
         const bool stopped = __builtin_amdgcn_readfirstlane(*(volatile uint32_t *)status) != 0;
         const bool defer = d.p_double >= 0.5;   // singles are rare: queue them
-        const bool c1 = d.n_class == 2;          // no point group: classes are the spins
-        const bool restricted = d.space != 0;    // children outside the space are null
-        const bool coupled = d.hphf != 0;        // walkers on spin-coupled functions
+        const bool c1 = PLAIN || d.n_class == 2;           // no point group: classes are the spins
+        const bool restricted = !PLAIN && d.space != 0;    // children outside the space are null
+        const bool coupled = !PLAIN && d.hphf != 0;        // walkers on spin-coupled functions
         ClassView<true> cv1{valid_of(d), nullptr};
         ClassView<false> cvg{valid_of(d), s_cm};
         if (at < at_end && !stopped) {
@@ -1381,12 +1399,12 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             }
         }
         __syncthreads();
-        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues(Q, a, d, s, s_sel8, s_recip, s_cm, spawned);
+        if (Q.nsgl >= SGL_DRAIN || Q.nspw >= SPW_DRAIN) drain_queues<PLAIN>(Q, a, d, s, s_sel8, s_recip, s_cm, spawned);
     }
     __syncthreads();
     if (Q.sys >= 0) {
         const int qs = __builtin_amdgcn_readfirstlane(Q.sys);
-        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues(Q, a, desc[qs], qs, s_sel8, s_recip, s_cm, spawned);
+        if (Q.nsgl > 0 || Q.nspw > 0) drain_queues<PLAIN>(Q, a, desc[qs], qs, s_sel8, s_recip, s_cm, spawned);
         flush_spawn_count(&a.spawns[qs], spawned);
     }
 }
@@ -2369,8 +2387,12 @@ void launch_iteration(const EngineArgs &a, int post_grid, int spawn_grid, bool f
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_scan_down, dim3(SCAN_G), dim3(256), 0, s, a);
     if (ev) (void)hipEventRecord(ev[2], s);
-    hipLaunchKernelGGL(k_spawn, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
-                       (const SysDesc *)a.desc);
+    if (a.plain)
+        hipLaunchKernelGGL(k_spawn<true>, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
+                           (const SysDesc *)a.desc);
+    else
+        hipLaunchKernelGGL(k_spawn<false>, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
+                           (const SysDesc *)a.desc);
     if (ev) (void)hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(k_fix, dim3((unsigned)spawn_grid), dim3(256), 0, s, a,
                        (const SysDesc *)a.desc);
