@@ -2246,7 +2246,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 a_cnt = 0ull;
                 a_num = 0.0;
             }
-            nwb = wave_sum(nwb);
+            {   // the wavefront's total, by DPP (all lanes active here)
+                const unsigned long long x = wave_incl_scan(nwb);
+                nwb = (unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63) |
+                      ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63) << 32);
+            }
             if (lane == 0) {
                 a.chunk_stat[c * POST_WAVES + wid] = cs;
                 // walkers that spawn next iteration: none if the system stops after this one

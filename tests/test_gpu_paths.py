@@ -1,7 +1,8 @@
 """Rarely taken paths of the HIP implementation, forced and checked bit for bit
 against the oracle through the C ABI: the grow-and-redo path of a table that
 overflows inside an iteration, spawn tiles located by search instead of the
-tile map, a reference population of zero, death that crosses zero."""
+tile map, large tiles, a reference population of zero, death that crosses
+zero."""
 import numpy as np
 import pytest
 
@@ -56,6 +57,25 @@ def test_tile_search_without_map(limit):
         ref.iterate(15)
         _same_lists(gpu, ref, f"tiles{limit}/{b}")
         _same_estimates(gpu.estimates(), ref.estimates(), f"tiles{limit}/{b}")
+    gpu.close()
+
+
+@pytest.mark.parametrize("tile", [4096, 65536])
+def test_large_tiles(tile):
+    """A reference holding 20000 walkers fills whole tiles of 4096 attempts, or
+    a large part of one tile of 65536 (the per-thread runs of the tile split are
+    then long, and cross from the reference to the entries after it)."""
+    ham, prm, _ = S.workload("hubbard8")
+    prm.initial_walkers, prm.target_walkers = 20000, 40000
+    print(f"[gpu] large tiles: {tile}", flush=True)
+    gpu = F.Solver(ham, prm, _stream())
+    F.fciqmc_set_launch(gpu.h, 512, tile, 256)
+    ref = O.Oracle(ham, prm)
+    for b in range(3):
+        gpu.iterate(30)
+        ref.iterate(30)
+        _same_lists(gpu, ref, f"tile{tile}/{b}")
+        _same_estimates(gpu.estimates(), ref.estimates(), f"tile{tile}/{b}")
     gpu.close()
 
 
