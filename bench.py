@@ -426,6 +426,8 @@ def pmc_means(path, last=0):
         with open(f) as fh:
             for r in csv.DictReader(fh):
                 name = (r.get("Kernel_Name") or r.get("Kernel-Name") or "?").split("(")[0]
+                if "fq::" in name:   # void fq::k_spawn<true> -> fq::k_spawn
+                    name = name.split("<")[0].replace("void ", "")
                 ctr = r.get("Counter_Name") or r.get("Counter-Name") or "?"
                 v = float(r.get("Counter_Value") or r.get("Counter-Value") or "nan")
                 disp = int(r.get("Dispatch_Id") or r.get("Dispatch-Id") or 0)
@@ -542,7 +544,7 @@ def trace_summary(path):
     print(f"# kernel statistics of {files[0]}")
     print(f"{'kernel':34s} {'calls':>6s} {'mean_us':>10s} {'total_ms':>10s} {'pct':>6s}")
     for r in rows:
-        name = r["Name"].split("(")[0].replace("fq::", "")[:34]
+        name = r["Name"].split("(")[0].replace("fq::", "").replace("void ", "")[:34]
         print(f"{name:34s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
               f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
 

@@ -1194,14 +1194,17 @@ __device__ __forceinline__ int64_t last_le(const unsigned long long *v, int64_t 
     return lo + __popcll(__ballot(le)) - 1;
 }
 
-// At most 96 VGPRs: five wavefronts per SIMD (the LDS use allows five workgroups per CU);
+// At most 80 VGPRs: six wavefronts per SIMD (the LDS use allows six workgroups per CU);
 // four with two-word determinants (more registers and LDS per attempt).
 // PLAIN: every system of the launch has no point group, no restricted space and plain
 // determinants (EngineArgs::plain), so those branches are compiled out.
 template <bool PLAIN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6 - FQ_DET_WORDS, 6 - FQ_DET_WORDS)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FQ_DET_WORDS == 1 ? 6 : 4, FQ_DET_WORDS == 1 ? 6 : 4)))
 void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
-    __shared__ unsigned long long s_incl[CHUNK];
+    // inclusive sums of |C| over the staged entries, relative to the tile's first attempt
+    // and clamped to 32 bits (the entries a thread can start in stay exact: a tile has at
+    // most 2^20 attempts and |C| < 2^31)
+    __shared__ int32_t s_rel[CHUNK];
     __shared__ det_t s_det[CHUNK];
     __shared__ int32_t s_pop[CHUNK];
     __shared__ unsigned long long s_wsum[4];   // per wavefront: walkers | entries << 48
@@ -1318,7 +1321,8 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             wbefore += (unsigned long long)(pa[u] < 0 ? -(int64_t)pa[u] : (int64_t)pa[u]);
             s_pop[pos] = pa[u];
             s_det[pos] = ka[u];
-            s_incl[pos] = wbefore;
+            const long long rel = (long long)wbefore - (long long)(j * tile);
+            s_rel[pos] = (int32_t)(rel < INT32_MIN ? INT32_MIN : rel > INT32_MAX ? INT32_MAX : rel);
             ++pos;
         }
         __syncthreads();
@@ -1340,14 +1344,14 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         ClassView<true> cv1{valid_of(d), nullptr};
         ClassView<false> cvg{valid_of(d), s_cm};
         if (at < at_end && !stopped) {
-            const unsigned long long local = at - off_c;
-            int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum > local
+            const int32_t xr = (int32_t)(at - lo_t);   // this thread's first attempt in the tile
+            int sl = 0, hi = n_occ - 1;  // first occupied entry with inclusive sum past it
             while (sl < hi) {
                 const int mid = (sl + hi) >> 1;
-                if (s_incl[mid] > local) hi = mid;
+                if (s_rel[mid] > xr) hi = mid;
                 else sl = mid + 1;
             }
-            uint32_t k = (uint32_t)(local - (sl ? s_incl[sl - 1] : 0ull));
+            uint32_t k = sl ? (uint32_t)(xr - s_rel[sl - 1]) : (uint32_t)(at - off_c);
             for (;;) {
                 const int32_t C = s_pop[sl];
                 const det_t D = s_det[sl];
