@@ -1268,8 +1268,10 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
             }
             __syncthreads();
             if (t == 0) Q.sys = s;
+            // the class masks of the new system (not read by the plain variant), ordered
+            // before use by the barrier below
+            if (!PLAIN && t < NCLASS) s_cm[t] = cmask_of(d, t);
         }
-        if (t < NCLASS) s_cm[t] = cmask_of(d, t);   // ordered before use by the barrier below
         // Stage the chunk's entries that hold walkers (its four buckets, one per
         // wavefront, four entries per lane), compacted, with the inclusive prefix sum
         // of |C|. Only the lanes over a bucket's entries read (the entries are packed
