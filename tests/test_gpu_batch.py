@@ -123,3 +123,40 @@ def test_history_matches_the_estimates_of_each_iteration():
     with pytest.raises(F.FciqmcError):
         F.fciqmc_history(sv.h, 0, 40, 5)     # beyond the last iteration
     sv.close()
+
+
+def test_mixed_batch_switches_the_spawning_kernel():
+    """A batch of plain systems runs the spawning kernel's plain variant; admitting
+    systems with a point group, spin-coupled functions and a restricted space moves
+    the whole batch to the general variant (new graphs), and retiring them moves it
+    back. Every system follows the oracle's trajectory exactly throughout."""
+    plain = _systems()[:2]
+    irr = np.array([(i * 3) % 4 for i in range(10)], np.uint8)
+    general = [
+        (S.synthetic_molecule(10, 3, 3, 207, irreps=irr),
+         S.Params(tau=0.01, initiator_threshold=2, target_walkers=5000, initial_walkers=500,
+                  initial_shift=1.0, seed=106)),
+        (S.synthetic_molecule(6, 3, 3, 76, orb_energy=np.linspace(-0.8, 0.8, 6)),
+         S.Params(tau=0.01, shift_update_every=10, target_walkers=5000, initial_walkers=500,
+                  initial_shift=1.0, seed=107, hphf=1)),
+        (S.synthetic_molecule(12, 3, 3, 208),
+         S.Params(tau=0.01, target_walkers=5000, initial_walkers=500, initial_shift=1.0,
+                  seed=108, space=S.SPACE_EXCITATION, max_excitation=2)),
+    ]
+    print("[gpu] mixed batch", flush=True)
+    h = F.fciqmc_batch_create(5, [a for a, _ in plain], [b for _, b in plain], F.current_stream())
+    F.fciqmc_batch_iterate(h, 20)
+    slots = [F.fciqmc_batch_admit(h, *sy) for sy in general]
+    assert slots == [2, 3, 4]
+    F.fciqmc_batch_iterate(h, 30)
+    for slot, (ham, prm) in zip(slots, general):
+        d, p, _ = F.fciqmc_batch_slot_walkers(h, slot)
+        do, po, _ = _oracle_lists(ham, prm, 30)
+        assert np.array_equal(d, do) and np.array_equal(p, po), slot
+        F.fciqmc_batch_retire(h, slot)
+    F.fciqmc_batch_iterate(h, 10)
+    for slot, (ham, prm) in enumerate(plain):
+        d, p, _ = F.fciqmc_batch_slot_walkers(h, slot)
+        do, po, _ = _oracle_lists(ham, prm, 60)
+        assert np.array_equal(d, do) and np.array_equal(p, po), slot
+    F.fciqmc_free(h)
