@@ -160,3 +160,24 @@ def test_mixed_batch_switches_the_spawning_kernel():
         do, po, _ = _oracle_lists(ham, prm, 60)
         assert np.array_equal(d, do) and np.array_equal(p, po), slot
     F.fciqmc_free(h)
+
+
+def test_config4_batch_of_64_systems_matches_the_oracle():
+    """The batched workload's 64 systems (32 Hubbard rings of 10-16 sites, 32
+    molecules from 10e/16o to 14e/26o, ragged walker targets), at 1/200 of its
+    walker targets, advanced together for 50 iterations: each system's list,
+    counters and shift equal the oracle's."""
+    sy = S.batch_workload(scale=0.005)
+    for _, prm in sy:
+        prm.initial_walkers = max(prm.target_walkers // 2, 10)
+    print(f"[gpu] batch of {len(sy)} (the batched workload)", flush=True)
+    h = F.fciqmc_batch_create(len(sy), [a for a, _ in sy], [b for _, b in sy], F.current_stream())
+    F.fciqmc_batch_iterate(h, 50)
+    for slot, (ham, prm) in enumerate(sy):
+        d, p, _ = F.fciqmc_batch_slot_walkers(h, slot)
+        do, po, eo = _oracle_lists(ham, prm, 50)
+        assert np.array_equal(d, do) and np.array_equal(p, po), slot
+        e = F.fciqmc_batch_slot_estimators(h, slot)
+        for k in ("n_walkers", "n_dets", "attempts", "spawns", "merged", "aborted", "shift"):
+            assert e[k] == eo[k], (slot, k)
+    F.fciqmc_free(h)
