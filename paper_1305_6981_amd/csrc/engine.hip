@@ -1794,7 +1794,7 @@ int restore_snapshot(fciqmc_t *h, const SysSnapshot &o) {
 
 int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial) {
     if (!h || iters_per_trial < 1) return set_err(FCIQMC_EINVAL, "bad argument");
-    int cus = fq::spawn_grid_size() / 8;
+    int cus = fq::post_grid_size() / 4;   // (four post workgroups per CU)
     // The trials run on the live systems; their state is saved first and restored
     // afterwards, so tuning leaves every trajectory where it was.
     std::vector<SysSnapshot> snaps;

@@ -1062,7 +1062,7 @@ struct SingleItem {
     uint32_t pad;
 };
 
-constexpr int SPAWN_GRAB = 4;    // spawn tiles per dynamic grab (one counter serves the chip)
+constexpr int SPAWN_GRAB = 8;    // spawn tiles per dynamic grab (one counter serves the chip)
 constexpr int SGL_QUEUE = 128 / FQ_DET_WORDS;   // (two words: the spawn kernel's LDS in 40 KB)
 constexpr int SPW_QUEUE = 256;
 constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
@@ -2633,17 +2633,17 @@ hipError_t launch_e0(const SysDesc *desc, int32_t sys, uint64_t lo, uint64_t hi,
 
 #if FQ_DET_WORDS == 1
 
-int post_grid_size() { return spawn_grid_size() / 8 * 4; }   // four workgroups per CU
-
-int spawn_grid_size() {
+static int cu_count() {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
             cus = prop.multiProcessorCount;
     }
-    return cus * 8;
+    return cus;
 }
+int post_grid_size() { return cu_count() * 4; }    // four workgroups per CU
+int spawn_grid_size() { return cu_count() * 6; }   // six resident workgroups per CU
 #endif
 
 #if FQ_DET_WORDS == 2
