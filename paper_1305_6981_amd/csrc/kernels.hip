@@ -1812,6 +1812,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ int s_cdone[POST_WIN];                // wavefronts done with the chunk
     __shared__ int s_qn, s_qsys;
     __shared__ int s_ncl[POST_WAVES];
+    __shared__ int64_t s_win;                        // first chunk of the window taken
     const int64_t nch = *a.nchunks;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     WaveLds &W = L.w[wid];
@@ -1843,14 +1844,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                        in_lds ? L.tab.jk : nullptr);
         __syncthreads();
     };
-    // Each workgroup takes a contiguous range of chunks, in windows of POST_WIN; inside
-    // a window the wavefronts run through the chunks independently, and the last one
-    // done with a chunk writes the chunk's sum for the next iteration.
-    const int64_t per = (nch + gridDim.x - 1) / gridDim.x;
-    const int64_t c_lo = (int64_t)blockIdx.x * per;
-    const int64_t c_hi = c_lo + per < nch ? c_lo + per : nch;
-    for (int64_t c0 = c_lo; c0 < c_hi; c0 += POST_WIN) {
-        const int nwin = (int)(c_hi - c0 < POST_WIN ? c_hi - c0 : POST_WIN);
+    // The workgroups take windows of POST_WIN consecutive chunks from a shared counter
+    // (so the faster ones take more); inside a window the wavefronts run through the
+    // chunks independently, and the last one done with a chunk writes the chunk's sum
+    // for the next iteration.
+    for (;;) {
         __syncthreads();   // the previous window is done
         if (s_qn > 0) {    // (uniform)
             flush();
@@ -1859,6 +1857,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 s_qsys = -1;
             }
         }
+        if (t == 0) s_win = (int64_t)atomicAdd(&a.work[1], 1u) * POST_WIN;
+        __syncthreads();
+        const int64_t c0 = s_win;
+        if (c0 >= nch) break;
+        const int nwin = (int)(nch - c0 < POST_WIN ? nch - c0 : POST_WIN);
         if (t < nwin) {
             const int sc = a.chunk_sys[c0 + t];
             bool live = false, next = false;
