@@ -1545,6 +1545,8 @@ constexpr int WHASH = 128;              // hash slots per wavefront (load <= 0.5
 constexpr int POST_QUEUE = 1024;        // new determinants whose H_DD is still to be computed
 constexpr int POST_MAX_SYS = 256;       // systems whose status k_post snapshots in LDS
 constexpr int POST_WIN = 32;            // chunks per window of bucket metadata in LDS
+// the window's POST_WIN BPC + 1 record offsets are loaded by one thread each
+static_assert(POST_WIN * BPC + 1 <= 256, "one k_post thread per record offset of a window");
 constexpr uint32_t F_INIT = 1u;         // from an initiator parent (records and hash slots)
 constexpr uint32_t F_MATCHED = 2u;      // hash slot: the child is an entry of the bucket
 constexpr uint32_t F_MAYBE = 2u;        // record: found the hash full in this round,
