@@ -1062,7 +1062,7 @@ struct SingleItem {
     uint32_t pad;
 };
 
-constexpr int SPAWN_GRAB = 8;    // spawn tiles per dynamic grab (one counter serves the chip)
+constexpr int SPAWN_GRAB = 8;    // spawn tiles per dynamic grab at most (one counter serves the chip)
 constexpr int SGL_QUEUE = 128 / FQ_DET_WORDS;   // (two words: the spawn kernel's LDS in 40 KB)
 constexpr int SPW_QUEUE = 256;
 constexpr int SGL_DRAIN = 48;     // drain the queues once they hold this many items
@@ -1228,6 +1228,11 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
     }
     __syncthreads();
     unsigned int next_tile = 0, grab_end = 0;   // wavefront 0's current grab of tiles
+    // tiles per grab: SPAWN_GRAB when every workgroup gets many, fewer for small launches
+    // (so that the tiles still spread over the workgroups)
+    const unsigned long long per_wg = n_tiles / (4ull * gridDim.x);
+    const unsigned int grab = per_wg >= (unsigned long long)SPAWN_GRAB ? (unsigned int)SPAWN_GRAB
+                              : per_wg > 0ull ? (unsigned int)per_wg : 1u;
     unsigned long long spawned = 0;             // this thread's spawning events of system Q.sys
     for (;;) {
         // Tiles never cross a chunk: chunk c owns ceil(N_c / tile) consecutive tiles.
@@ -1235,9 +1240,9 @@ void k_spawn(EngineArgs a, const SysDesc *__restrict__ desc) {
         if (wid == 0) {
             if (next_tile >= grab_end) {
                 unsigned int g = 0;
-                if (lane == 0) g = atomicAdd(&a.work[0], (unsigned int)SPAWN_GRAB);
+                if (lane == 0) g = atomicAdd(&a.work[0], grab);
                 next_tile = __shfl(g, 0, 64);
-                grab_end = next_tile + SPAWN_GRAB;
+                grab_end = next_tile + grab;
             }
             const unsigned int tix = next_tile++;
             if (lane == 0) s_tile = tix;
@@ -1846,10 +1851,13 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                        in_lds ? L.tab.jk : nullptr);
         __syncthreads();
     };
-    // The workgroups take windows of POST_WIN consecutive chunks from a shared counter
-    // (so the faster ones take more); inside a window the wavefronts run through the
-    // chunks independently, and the last one done with a chunk writes the chunk's sum
-    // for the next iteration.
+    // The workgroups take windows of consecutive chunks from a shared counter (so the
+    // faster ones take more): POST_WIN chunks when every workgroup gets many, fewer for
+    // small launches; inside a window the wavefronts run through the chunks
+    // independently, and the last one done with a chunk writes the chunk's sum for the
+    // next iteration.
+    const int64_t per_wg = nch / (4 * (int64_t)gridDim.x);
+    const int gwin = per_wg >= POST_WIN ? POST_WIN : per_wg > 0 ? (int)per_wg : 1;
     for (;;) {
         __syncthreads();   // the previous window is done
         if (s_qn > 0) {    // (uniform)
@@ -1859,11 +1867,11 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
                 s_qsys = -1;
             }
         }
-        if (t == 0) s_win = (int64_t)atomicAdd(&a.work[1], 1u) * POST_WIN;
+        if (t == 0) s_win = (int64_t)atomicAdd(&a.work[1], 1u) * gwin;
         __syncthreads();
         const int64_t c0 = s_win;
         if (c0 >= nch) break;
-        const int nwin = (int)(nch - c0 < POST_WIN ? nch - c0 : POST_WIN);
+        const int nwin = (int)(nch - c0 < gwin ? nch - c0 : gwin);
         if (t < nwin) {
             const int sc = a.chunk_sys[c0 + t];
             bool live = false, next = false;
