@@ -1530,8 +1530,9 @@ __global__ __launch_bounds__(256) void k_scatter(EngineArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// K4d: annihilation. A workgroup takes a contiguous range of chunks and, in each,
-// every wavefront one bucket, with no workgroup barrier inside a bucket:
+// K4d: annihilation. A workgroup takes windows of consecutive chunks from a shared
+// counter and, in each chunk, every wavefront one bucket, with no workgroup barrier
+// inside a bucket:
 //   - the bucket's records are merged per child in the wavefront's LDS hash
 //     (the sort and compress of Sec. 4.1, by hashing);
 //   - every entry dies first (Eq. pdeath); then the walkers that arrived for it
