@@ -1800,13 +1800,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     // Each wavefront's working set, and (between chunks only) the pair table from
     // which the diagonal elements of new determinants are computed.
-    union PostLds {
-        WaveLds w[POST_WAVES];
-        struct {
-            double jk[64 * 63 / 2];   // (up to 64 spin orbitals)
-            double hpp[NSO_MAX];
-        } tab;
+    struct PairTable {
+        double jk[64 * 63 / 2];   // (up to 64 spin orbitals)
+        double hpp[NSO_MAX];
     };
+#if FQ_DET_WORDS == 1
+    // side by side: the staged pair table stays valid while the wavefronts use theirs
+    struct PostLds {
+        WaveLds w[POST_WAVES];
+        PairTable tab;
+    };
+#else
+    union PostLds {   // (two words: no room for both at four workgroups per CU)
+        WaveLds w[POST_WAVES];
+        PairTable tab;
+    };
+#endif
     __shared__ PostLds L;
     __shared__ uint32_t s_queue[POST_QUEUE];
     __shared__ uint32_t s_stat[POST_MAX_SYS];   // the systems' status at the kernel's start
@@ -1819,6 +1828,7 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     __shared__ unsigned long long s_cnws[POST_WIN];  // the chunk's sum of |C| after the iteration
     __shared__ int s_cdone[POST_WIN];                // wavefronts done with the chunk
     __shared__ int s_qn, s_qsys;
+    __shared__ int s_tabsys;                         // system whose pair table is staged (-1: none)
     __shared__ int s_ncl[POST_WAVES];
     __shared__ int64_t s_win;                        // first chunk of the window taken
     const int64_t nch = *a.nchunks;
@@ -1836,18 +1846,22 @@ void k_post(EngineArgs a, const SysDesc *__restrict__ desc) {
     if (t == 0) {
         s_qn = 0;
         s_qsys = -1;
+        s_tabsys = -1;
     }
     auto flush = [&]() {   // (uniform) H_DD of the queued new determinants
         const SysDesc &dq = desc[s_qsys];
         const bool in_lds = dq.n_so <= 64;   // the pair table's upper triangle fits in LDS
-        if (in_lds)
-            for (int i = t; i < dq.n_so * 64; i += 256) {
-                const int p = i >> 6, q = i & 63;
-                if (q > p && q < dq.n_so)
-                    L.tab.jk[pair_row(p, dq.n_so) + q] = gptr(dq.jk)[p * NSO_MAX + q];
-            }
-        for (int i = t; i < dq.n_so; i += 256) L.tab.hpp[i] = h_so(dq, i, i);
-        __syncthreads();
+        if (FQ_DET_WORDS == 2 || s_tabsys != s_qsys) {   // (uniform) stage the system's tables
+            if (in_lds)
+                for (int i = t; i < dq.n_so * 64; i += 256) {
+                    const int p = i >> 6, q = i & 63;
+                    if (q > p && q < dq.n_so)
+                        L.tab.jk[pair_row(p, dq.n_so) + q] = gptr(dq.jk)[p * NSO_MAX + q];
+                }
+            for (int i = t; i < dq.n_so; i += 256) L.tab.hpp[i] = h_so(dq, i, i);
+            __syncthreads();
+            if (t == 0) s_tabsys = s_qsys;   // (read again only after the barrier below)
+        }
         flush_new_dets(dq, s_queue, s_qn < POST_QUEUE ? s_qn : POST_QUEUE, L.tab.hpp,
                        in_lds ? L.tab.jk : nullptr);
         __syncthreads();
