@@ -331,7 +331,7 @@ int64_t fciqmc_history(fciqmc_t *h, int32_t slot, int64_t first, int64_t n, fciq
  * lowest spawning time per attempt and annihilation time per iteration, and
  * restores the systems: their walker lists continue exactly as if no trial
  * had run (the projected-energy numerator may differ in its last bits, since
- * its partial sums follow the table layout). */
+ * its partial sums follow the table layout and the launch shape). */
 int fciqmc_set_launch(fciqmc_t *h, int32_t spawn_grid, int32_t tile, int32_t post_grid);
 int fciqmc_get_launch(fciqmc_t *h, int32_t *spawn_grid, int32_t *tile, int32_t *post_grid);
 int fciqmc_autotune(fciqmc_t *h, int32_t iters_per_trial);
